@@ -1,0 +1,278 @@
+"""Pins for the CPU oracle: it is checked against things fixed independently
+of its own code (closed forms, brute force, library routines, the paper's
+worked example), so that a dropped term, wrong sign/index or a transposed
+operand in it fails here before it is trusted as the parity reference."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import acr, bcr, direct, hodlr, refine
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- generators
+def test_stencils_symmetric_and_signs():
+    for st in (W.poisson(9, 7), W.varkappa(12)):
+        A = direct.assemble(st)
+        assert abs(A - A.T).max() == 0.0
+        assert np.all(st.west <= 0) and np.all(st.north <= 0)
+    st = W.convdiff(16)
+    A = direct.assemble(st).toarray()
+    off = A - np.diag(np.diag(A))
+    assert np.all(off <= 0.0)                                  # M-matrix signs
+    assert np.all(np.diag(A) >= -off.sum(axis=1) - 1e-12)       # diagonal dominance
+
+
+def test_varkappa_contrast_exact():
+    st = W.varkappa(32)
+    kw = -st.west.reshape(32, 32)[:, 1:]
+    kn = -st.north.reshape(32, 32)[:-1, :]
+    vals = np.concatenate([kw.ravel(), kn.ravel()])
+    # contrast is defined over all face samples; interior faces cannot exceed it
+    assert vals.max() / vals.min() <= 1e4 * (1 + 1e-12)
+    assert vals.max() / vals.min() > 1e2
+
+
+def test_blocks_structure():
+    """D_i tridiagonal, E_i and F_i diagonal (Section 3, remark after Eq. system)."""
+    st = W.varkappa(10)
+    D, E, F = direct.blocks(st)
+    for Di, Ei, Fi in zip(D, E, F):
+        assert np.count_nonzero(np.triu(Di, 2)) == 0 and np.count_nonzero(np.tril(Di, -2)) == 0
+        assert np.count_nonzero(Ei - np.diag(np.diag(Ei))) == 0
+        assert np.count_nonzero(Fi - np.diag(np.diag(Fi))) == 0
+    assert np.count_nonzero(E[0]) == 0 and np.count_nonzero(F[-1]) == 0
+
+
+# ------------------------------------------------------------- O1 closed forms
+@pytest.mark.parametrize("n,p,q", [(15, 1, 1), (31, 3, 5), (20, 7, 2)])
+def test_direct_discrete_eigenfunction(n, p, q):
+    """h^2-scaled 5-point Laplacian: A phi = lambda phi, lambda = 4 sin^2(p pi h/2) + 4 sin^2(q pi h/2)."""
+    st = W.poisson(n)
+    x, y = W.node_coords(n, n)
+    h = 1.0 / (n + 1)
+    phi = np.sin(p * math.pi * x) * np.sin(q * math.pi * y)
+    lam = 4 * math.sin(p * math.pi * h / 2) ** 2 + 4 * math.sin(q * math.pi * h / 2) ** 2
+    u = direct.solve(st, phi)
+    assert np.linalg.norm(u - phi / lam) / np.linalg.norm(phi / lam) < 1e-12
+    ub = bcr.bcr_solve(st, phi)
+    assert np.linalg.norm(ub - phi / lam) / np.linalg.norm(phi / lam) < 1e-12
+
+
+@pytest.mark.parametrize("n", [7, 24])
+def test_direct_manufactured_variable_kappa(n):
+    """u = x(1-x)y(1-y), kappa = 1+x+y at face midpoints: the flux-form 5-point
+    scheme is exact for this pair, so the discrete solution equals u at nodes."""
+    kx, ky = W.kappa_faces_from_function(lambda X, Y: 1.0 + X + Y, n, n)
+    st = W.flux_form(kx, ky, n, n)
+    x, y = W.node_coords(n, n)
+    kap = 1 + x + y
+    f = -((1 - 2 * x) * y * (1 - y) - 2 * kap * y * (1 - y)
+          + x * (1 - x) * (1 - 2 * y) - 2 * kap * x * (1 - x))
+    h = 1.0 / (n + 1)
+    u_exact = x * (1 - x) * y * (1 - y)
+    u = direct.solve(st, h * h * f)
+    assert np.linalg.norm(u - u_exact) / np.linalg.norm(u_exact) < 1e-12
+    ub = bcr.bcr_solve(st, h * h * f)
+    assert np.linalg.norm(ub - u_exact) / np.linalg.norm(u_exact) < 1e-12
+
+
+# ------------------------------------------------------------- O2 brute force
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 2), (3, 3), (4, 4), (5, 5), (7, 7), (8, 8),
+                                   (16, 16), (33, 33), (6, 11), (9, 2), (5, 12)])
+def test_bcr_equals_lu(nx, ny):
+    st = W.convdiff(nx, ny) if nx != ny else W.varkappa(nx) if nx > 2 else W.poisson(nx)
+    b = W.rhs(st.n, 3, seed=W.seed_for(0, nx * 100 + ny))
+    A = direct.assemble(st).toarray()
+    x_lu = np.linalg.solve(A, b)
+    x_bcr = bcr.bcr_solve(st, b)
+    cond = np.linalg.cond(A)
+    assert np.linalg.norm(x_bcr - x_lu) / np.linalg.norm(x_lu) < 1e-15 * cond * 10 + 1e-14
+
+
+def test_level_sizes():
+    assert bcr.level_sizes(8) == [8, 4, 2, 1]
+    assert bcr.level_sizes(1024) == [2 ** k for k in range(10, -1, -1)]
+    assert bcr.level_sizes(96) == [96, 48, 24, 12, 6, 3, 1]
+    assert bcr.level_sizes(5) == [5, 2, 1]
+
+
+def _read_patterns():
+    pats, cur = {}, None
+    with open(os.path.join(GOLDEN, "n8_block_patterns.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            tok = line.split()
+            if tok[0] == "level":
+                cur = int(tok[1])
+                pats[cur] = {"order": [int(t) for t in tok[3:]], "rows": []}
+            else:
+                pats[cur]["rows"].append(tok)
+    return pats
+
+
+def _assemble_blocks(D, E, F):
+    m, s = len(D), D[0].shape[0]
+    A = np.zeros((m * s, m * s))
+    for i in range(m):
+        A[i * s:(i + 1) * s, i * s:(i + 1) * s] = D[i]
+        if i > 0:
+            A[i * s:(i + 1) * s, (i - 1) * s:i * s] = E[i]
+        if i + 1 < m:
+            A[i * s:(i + 1) * s, (i + 1) * s:(i + 2) * s] = F[i]
+    return A
+
+
+def test_worked_example_n8_patterns_and_schur():
+    """The paper's 8-block example: permuted block patterns at each level, and
+    each reduced system equals the Schur complement H22 - H21 H11^-1 H12 of the
+    permuted system (Eq. "sche", Eq. "fund"), computed here by brute force."""
+    pats = _read_patterns()
+    rng = np.random.default_rng(5)
+    s, m = 3, 8
+    D = [np.eye(s) * 8 + rng.standard_normal((s, s)) for _ in range(m)]
+    E = [np.zeros((s, s))] + [rng.standard_normal((s, s)) for _ in range(m - 1)]
+    F = [rng.standard_normal((s, s)) for _ in range(m - 1)] + [np.zeros((s, s))]
+    level = 0
+    while True:
+        m = len(D)
+        order = list(range(0, m, 2)) + list(range(1, m, 2))
+        assert pats[level]["order"] == order
+        A = _assemble_blocks(D, E, F)
+        perm = np.concatenate([np.arange(k * s, (k + 1) * s) for k in order])
+        H = A[np.ix_(perm, perm)]
+        for r, bi in enumerate(order):
+            for c, bj in enumerate(order):
+                blk = H[r * s:(r + 1) * s, c * s:(c + 1) * s]
+                tok = pats[level]["rows"][r][c]
+                if tok == ".":
+                    assert np.count_nonzero(blk) == 0
+                else:
+                    assert np.count_nonzero(blk) > 0
+                    assert tok == {0: "D", -1: "E", 1: "F"}[bj - bi]
+        if m == 1:
+            break
+        ne = (m + 1) // 2
+        H11, H12 = H[:ne * s, :ne * s], H[:ne * s, ne * s:]
+        H21, H22 = H[ne * s:, :ne * s], H[ne * s:, ne * s:]
+        S = H22 - H21 @ np.linalg.solve(H11, H12)
+        X, D, E, F = bcr.reduce_level(D, E, F)
+        assert np.allclose(_assemble_blocks(D, E, F), S, rtol=0, atol=1e-12)
+        level += 1
+    assert level == 3
+
+
+# ------------------------------------------------------------------ HODLR T_eps
+def test_truncation_rule_prescribed_spectrum():
+    rng = np.random.default_rng(0)
+    p, q = 40, 30
+    Uo, _ = np.linalg.qr(rng.standard_normal((p, q)))
+    Vo, _ = np.linalg.qr(rng.standard_normal((q, q)))
+    sig = 10.0 ** -np.arange(q, dtype=float)          # 1, 1e-1, ..., 1e-29
+    B = (Uo * sig) @ Vo.T
+    for eps, t in ((1e-3 * 0.9999, 4), (1e-6 * 0.9999, 7), (1e-3 * 1.0001, 3), (0.5, 1)):
+        U, V = hodlr.truncate(B, eps)
+        assert U.shape[1] == t
+        err = np.linalg.norm(B - U @ V.T, 2)
+        assert err <= eps * sig[0]
+        assert abs(err - sig[t]) <= 1e-12
+    # relative to s1 of the block itself: s = (2, 1, 0.5)
+    B2 = (Uo[:, :3] * np.array([2.0, 1.0, 0.5])) @ Vo[:, :3].T
+    assert hodlr.truncate(B2, 0.2501)[0].shape[1] == 2
+    assert hodlr.truncate(B2, 0.2499)[0].shape[1] == 3
+    U, V = hodlr.truncate(np.zeros((5, 4)), 1e-8)
+    assert U.shape == (5, 0) and V.shape == (4, 0)
+
+
+def test_hodlr_roundtrip_matvec_and_tree():
+    rng = np.random.default_rng(1)
+    M = rng.standard_normal((96, 96))
+    H = hodlr.compress(M, 24, 0.0)
+    assert np.allclose(hodlr.densify(H), M, atol=1e-12)
+    x = rng.standard_normal((96, 3))
+    assert np.allclose(hodlr.matvec(H, x), M @ x, atol=1e-11)
+    assert hodlr.cluster_sizes(96, 32) == [24, 24, 24, 24]
+    assert hodlr.cluster_sizes(1024, 64) == [64] * 16
+    assert hodlr.depth(H) == 2
+    # smooth kernel: error of every block bounded by eps * its own s1
+    xs = np.linspace(0, 1, 128)
+    K = 1.0 / (1.0 + 40 * np.abs(xs[:, None] - xs[None, :]))
+    Hk = hodlr.compress(K, 16, 1e-6)
+    assert np.linalg.norm(hodlr.densify(Hk) - K, 2) <= 1e-6 * np.linalg.norm(K, 2) * 4
+
+
+def test_level0_ranks_exactly_one():
+    """Tridiagonal D_i: every off-diagonal HODLR block is exactly rank 1 (Section 3)."""
+    st = W.varkappa(64)
+    D, E, F = direct.blocks(st)
+    for Di in D[:5]:
+        H = hodlr.compress(Di, 16, 1e-14)
+        for d, rs in hodlr.ranks(H).items():
+            assert all(r == 1 for r in rs)
+        assert np.abs(hodlr.densify(H) - Di).max() <= 1e-15 * np.abs(Di).max()
+    for Ei in E[1:4]:
+        H = hodlr.compress(Ei, 16, 1e-14)
+        assert all(r == 0 for rs in hodlr.ranks(H).values() for r in rs)
+
+
+# -------------------------------------------------------------------- O3 ACR
+def test_acr_eps0_reproduces_bcr():
+    st = W.varkappa(33)
+    b = W.rhs(st.n, 2, seed=3)
+    fac = acr.factor(st, 8, 0.0)
+    x = acr.solve(fac, st, b)
+    xb = bcr.bcr_solve(st, b)
+    assert np.linalg.norm(x - xb) / np.linalg.norm(xb) < 1e-12
+
+
+def test_acr_error_decreases_with_eps():
+    st = W.varkappa(64, seed=W.seed_for(1, 2))
+    b = W.rhs(st.n, 1)
+    x0 = direct.solve(st, b)
+    errs = []
+    for eps in (1e-2, 1e-4, 1e-6, 1e-8, 1e-10):
+        x = acr.solve(acr.factor(st, 16, eps), st, b)
+        errs.append(np.linalg.norm(x - x0) / np.linalg.norm(x0))
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1))
+    assert errs[-1] < 1e-8
+
+
+def test_acr_symmetry_preserved():
+    """Symmetric operator: T_eps(B^T) = T_eps(B)^T, so the reduced blocks stay
+    symmetric (D') and E'_{j+1} = F'_j^T, to rounding."""
+    st = W.poisson(32)
+    D, E, F = direct.blocks(st)
+    fac = acr.factor_blocks(D, E, F, 8, 1e-8)
+    for lev in range(1, len(fac.levels)):
+        X, El, Fl = fac.levels[lev]
+        for k, Xk in X.items():
+            Xd = hodlr.densify(Xk)
+            assert np.allclose(Xd, Xd.T, atol=1e-10 * np.abs(Xd).max())
+        for j in range(len(El) - 1):
+            Ed = hodlr.densify(El[j + 1])
+            Fd = hodlr.densify(Fl[j])
+            assert np.allclose(Ed, Fd.T, atol=1e-10 * np.abs(Fd).max())
+
+
+def test_acr_ranks_bounded_and_memory_below_dense():
+    st = W.poisson(64)
+    fac = acr.factor(st, 16, 1e-8)
+    assert max(acr.level_ranks(fac)) <= 16
+    dense_entries = sum(64 * 64 * (len(X) + len(E) + len(F)) for X, E, F in fac.levels)
+    assert acr.stored_entries(fac) < dense_entries
+
+
+def test_refinement_with_acr_preconditioner():
+    st = W.convdiff(48)
+    b = W.rhs(st.n, 2, seed=11)
+    fac = acr.factor(st, 12, 1e-4)
+    x, hist = refine.refine(st, b, lambda r: acr.solve(fac, st, r), tol=1e-10, maxit=30)
+    assert hist[-1] <= 1e-10
+    assert direct.residual(st, x, b) <= 1e-10
+    assert len(hist) - 1 <= 8
