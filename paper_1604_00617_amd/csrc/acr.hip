@@ -1,0 +1,540 @@
+// Accelerated Cyclic Reduction driver and the extern "C" entry points.
+//
+// Factor (Section 3): level by level over the current m blocks, with the
+// even block indices k eliminated and the odd ones i = 2j+1 kept,
+//   X_k = T(D_k^{-1}), P_k = T(X_k E_k), Q_k = T(X_k F_k),
+//   D'_j = T(D_i - E_i Q_{i-1} - F_i P_{i+1}), E'_j = T(-E_i P_{i-1}),
+//   F'_j = T(-F_i Q_{i+1}),
+// until one block remains (its inverse is stored too).  At level 0 the E_i
+// and F_i are diagonal and the products are scalings.  All blocks of one
+// level are processed together by each batched launch.
+// Solve: forward reduction g_k = X_k f_k, f'_j = f_i - E_i g_{i-1} - F_i g_{i+1};
+// final u = X f; back-substitution u_k = X_k (f_k - E_k u_{k-1} - F_k u_{k+1}).
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hodlr.hpp"
+#include "kernels.hpp"
+
+namespace acr {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct FactorBase {
+  virtual ~FactorBase() = default;
+  virtual void solve(const double* B, double* X, int nrhs, hipStream_t st) = 0;
+  virtual void info(acr_info* out) const = 0;
+  virtual void block(int level, int which, int k, double* dense, hipStream_t st) const = 0;
+};
+
+template <typename T>
+struct Level {
+  int m = 0;        // blocks at this level
+  int nreal = 0;    // even blocks (ceil(m/2))
+  int ne = 0;       // even slots incl. a zero dummy when m is even (floor(m/2)+1)
+  HSet<T> X;        // nreal inverses
+  bool diag = false;
+  DBuf<T> e0, f0;   // level 0: diagonals of E_i, F_i ([m][s])
+  HSet<T> E, F;     // level >= 1: m HODLR blocks each
+};
+
+template <typename T>
+struct Factor final : FactorBase {
+  int nx = 0, ny = 0, leaf = 0, b = 0, L = 0, precision = 0;
+  double eps = 0;
+  std::vector<Level<T>> lev;
+  HSet<T> Xlast;
+  Work work_done;
+  std::vector<int> lev_rank;
+
+  size_t bytes() const {
+    size_t t = Xlast.bytes();
+    for (const auto& l : lev) {
+      t += l.X.bytes() + l.E.bytes() + l.F.bytes() + l.e0.bytes() + l.f0.bytes();
+    }
+    return t;
+  }
+
+  void info(acr_info* o) const override {
+    std::memset(o, 0, sizeof(*o));
+    o->nx = nx; o->ny = ny; o->leaf = leaf; o->depth = L; o->levels = (int)lev.size();
+    o->precision = precision; o->eps = eps;
+    o->factor_bytes = (int64_t)bytes();
+    int mr = Xlast.max_rank();
+    for (size_t i = 0; i < lev.size() && i < 40; ++i) {
+      o->level_max_rank[i] = lev_rank[i];
+      mr = std::max(mr, lev_rank[i]);
+    }
+    o->max_rank = mr;
+    o->factor_flops = work_done.total();
+    // one solve pass reads every stored X twice (forward and back) and every
+    // stored E/F once
+    double sb = 2.0 * Xlast.bytes();
+    double fl = 0;
+    for (const auto& l : lev) {
+      sb += 2.0 * l.X.bytes() + l.E.bytes() + l.F.bytes() + l.e0.bytes() + l.f0.bytes();
+    }
+    o->solve_bytes = sb;
+    // two flops per stored multiply-add entry read
+    fl = 2.0 * sb / sizeof(T);
+    o->solve_flops_per_rhs = fl;
+  }
+
+  void block(int level, int which, int k, double* dense, hipStream_t st) const override {
+    const int s = nx;
+    if (level == (int)lev.size()) {
+      if (which != 0 || k != 0) fail(ACR_ERR_INVALID_ARG, "last level holds only X_0");
+      densify_to_host(st, Xlast, 0, dense);
+      return;
+    }
+    if (level < 0 || level > (int)lev.size()) fail(ACR_ERR_INVALID_ARG, "level out of range");
+    const Level<T>& l = lev[level];
+    if (which == 0) {
+      if (k < 0 || k >= l.m || (k & 1)) fail(ACR_ERR_INVALID_ARG, "X_k needs an even k < m");
+      densify_to_host(st, l.X, k / 2, dense);
+      return;
+    }
+    if (which != 1 && which != 2) fail(ACR_ERR_INVALID_ARG, "which must be 0, 1 or 2");
+    if (k < 0 || k >= l.m) fail(ACR_ERR_INVALID_ARG, "block index out of range");
+    if (l.diag) {
+      std::vector<T> d(s);
+      const DBuf<T>& src = which == 1 ? l.e0 : l.f0;
+      ACR_HIP(hipMemcpyAsync(d.data(), src.get() + (size_t)k * s, s * sizeof(T), hipMemcpyDeviceToHost, st));
+      ACR_HIP(hipStreamSynchronize(st));
+      for (size_t e = 0; e < (size_t)s * s; ++e) dense[e] = 0.0;
+      for (int r = 0; r < s; ++r) dense[(size_t)r * (s + 1)] = (double)d[r];
+    } else {
+      densify_to_host(st, which == 1 ? l.E : l.F, k, dense);
+    }
+  }
+
+  void solve(const double* B, double* Xout, int nrhs, hipStream_t st) override;
+};
+
+template <typename T>
+Flat<T> vflat(T* p, int s, int nrhs, int mmul = 1, int moff = 0) {
+  Flat<T> f;
+  f.p = p; f.ld = s; f.sm = (long long)s * nrhs; f.mmul = mmul; f.moff = moff;
+  return f;
+}
+
+template <typename T>
+void Factor<T>::solve(const double* B, double* Xout, int nrhs, hipStream_t st) {
+  const int s = nx;
+  const int nl = (int)lev.size();
+  const size_t blk = (size_t)s * nrhs;
+  std::vector<DBuf<T>> F(nl + 1), G(nl), U(nl + 1);
+  F[0].resize((size_t)ny * blk);
+  to_blocks<T>(st, s, ny, nrhs, B, (long long)nx * ny, F[0].get());
+  for (int l = 0; l < nl; ++l) {
+    const Level<T>& L_ = lev[l];
+    const int m = L_.m, nodd = m / 2;
+    G[l].resize((size_t)L_.ne * blk);
+    // g_k = X_k f_(2k)
+    hmul<T>(st, HV<T>{&L_.X, 1, 0}, L_.nreal, 0, false, nrhs, T(1), vflat(F[l].get(), s, nrhs, 2, 0),
+            T(0), vflat(G[l].get(), s, nrhs));
+    if (L_.ne > L_.nreal) fill<T>(st, G[l].get() + (size_t)L_.nreal * blk, blk, T(0));
+    // f'_j = f_(2j+1) - E_(2j+1) g_j - F_(2j+1) g_(j+1)
+    F[l + 1].resize((size_t)nodd * blk);
+    bcopy<T>(st, (int)blk, 1, nodd, T(1), with_map(bop(F[l].get(), 1, (long long)blk), 2, 1),
+             bop(F[l + 1].get(), 1, (long long)blk));
+    if (L_.diag) {
+      bdiag_axpy<T>(st, s, nrhs, nodd, T(-1), L_.e0.get(), 2, 1, G[l].get(), 1, 0, F[l + 1].get(), 1, 0);
+      bdiag_axpy<T>(st, s, nrhs, nodd, T(-1), L_.f0.get(), 2, 1, G[l].get(), 1, 1, F[l + 1].get(), 1, 0);
+    } else {
+      hmul<T>(st, HV<T>{&L_.E, 2, 1}, nodd, 0, false, nrhs, T(-1), vflat(G[l].get(), s, nrhs, 1, 0), T(1),
+              vflat(F[l + 1].get(), s, nrhs));
+      hmul<T>(st, HV<T>{&L_.F, 2, 1}, nodd, 0, false, nrhs, T(-1), vflat(G[l].get(), s, nrhs, 1, 1), T(1),
+              vflat(F[l + 1].get(), s, nrhs));
+    }
+  }
+  // final block; U[l] holds level-l unknowns with one zero pad block at each end
+  U[nl].resize(3 * blk);
+  fill<T>(st, U[nl].get(), 3 * blk, T(0));
+  hmul<T>(st, HV<T>{&Xlast, 1, 0}, 1, 0, false, nrhs, T(1), vflat(F[nl].get(), s, nrhs), T(0),
+          vflat(U[nl].get() + blk, s, nrhs));
+  for (int l = nl - 1; l >= 0; --l) {
+    const Level<T>& L_ = lev[l];
+    const int m = L_.m, nodd = m / 2;
+    U[l].resize((size_t)(m + 2) * blk);
+    fill<T>(st, U[l].get(), blk, T(0));
+    fill<T>(st, U[l].get() + (size_t)(m + 1) * blk, blk, T(0));
+    bcopy<T>(st, (int)blk, 1, nodd, T(1), with_map(bop(U[l + 1].get(), 1, (long long)blk), 1, 1),
+             with_map(bop(U[l].get(), 1, (long long)blk), 2, 2));
+    DBuf<T> tmp((size_t)L_.nreal * blk);
+    // tmp_k = E_(2k) u_(2k-1) + F_(2k) u_(2k+1)   (padded indices 2k and 2k+2)
+    if (L_.diag) {
+      fill<T>(st, tmp.get(), tmp.size(), T(0));
+      bdiag_axpy<T>(st, s, nrhs, L_.nreal, T(1), L_.e0.get(), 2, 0, U[l].get(), 2, 0, tmp.get(), 1, 0);
+      bdiag_axpy<T>(st, s, nrhs, L_.nreal, T(1), L_.f0.get(), 2, 0, U[l].get(), 2, 2, tmp.get(), 1, 0);
+    } else {
+      hmul<T>(st, HV<T>{&L_.E, 2, 0}, L_.nreal, 0, false, nrhs, T(1), vflat(U[l].get(), s, nrhs, 2, 0), T(0),
+              vflat(tmp.get(), s, nrhs));
+      hmul<T>(st, HV<T>{&L_.F, 2, 0}, L_.nreal, 0, false, nrhs, T(1), vflat(U[l].get(), s, nrhs, 2, 2), T(1),
+              vflat(tmp.get(), s, nrhs));
+    }
+    // u_(2k) = g_k - X_k tmp_k   (padded index 2k+1)
+    bcopy<T>(st, (int)blk, 1, L_.nreal, T(1), bop(G[l].get(), 1, (long long)blk),
+             with_map(bop(U[l].get(), 1, (long long)blk), 2, 1));
+    hmul<T>(st, HV<T>{&L_.X, 1, 0}, L_.nreal, 0, false, nrhs, T(-1), vflat(tmp.get(), s, nrhs), T(1),
+            vflat(U[l].get(), s, nrhs, 2, 1));
+  }
+  from_blocks<T>(st, s, ny, nrhs, U[0].get() + blk, Xout, (long long)nx * ny);
+}
+
+int hodlr_depth(int s, int leaf) {
+  int L = 0;
+  while (s > leaf) {
+    if (s & 1) return -1;
+    s >>= 1;
+    ++L;
+  }
+  return L;
+}
+
+// Opt-in stage checks (environment ACR_DEBUG_CHECKS=1): after each stage of
+// the factorisation, synchronise and fail with the stage name if a pivot was
+// bad or a stored value is not finite.
+bool debug_checks() {
+  static const bool on = [] {
+    const char* e = std::getenv("ACR_DEBUG_CHECKS");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
+template <typename T>
+void stage_check(hipStream_t st, const HSet<T>& H, const int* status, const char* what, int level) {
+  if (!debug_checks()) return;
+  int bad = 0;
+  ACR_HIP(hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, st));
+  ACR_HIP(hipStreamSynchronize(st));
+  std::string msg;
+  bool nf = false;
+  double mx = 0, m1 = 0;
+  scan_values<T>(st, (long long)H.cnt * H.leaf_stride(), H.lv.get(), &nf, &m1);
+  if (nf) msg += " leaves";
+  mx = m1;
+  for (int d = 1; d <= H.L; ++d) {
+    bool b1 = false, b2 = false;
+    double a1 = 0, a2 = 0;
+    scan_values<T>(st, (long long)H.cnt * H.k[d] * H.s, H.U[d].get(), &b1, &a1);
+    scan_values<T>(st, (long long)H.cnt * H.k[d] * H.s, H.V[d].get(), &b2, &a2);
+    if (b1) msg += " U" + std::to_string(d);
+    if (b2) msg += " V" + std::to_string(d);
+    mx = std::max(mx, std::max(a1, a2));
+  }
+  std::fprintf(stderr, "[acr check] level %d %-10s cnt %d ranks", level, what, H.cnt);
+  for (int d = 1; d <= H.L; ++d) std::fprintf(stderr, " %d", H.kc[d]);
+  std::fprintf(stderr, " max|.| %.3e%s%s\n", mx, bad ? " BAD-PIVOT" : "", msg.empty() ? "" : (" NONFINITE:" + msg).c_str());
+  if (bad || !msg.empty())
+    fail(bad ? ACR_ERR_SINGULAR : ACR_ERR_INTERNAL,
+         std::string("stage check failed at level ") + std::to_string(level) + " " + what + msg);
+}
+
+template <typename T>
+std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_options& opt, hipStream_t st) {
+  auto f = std::make_unique<Factor<T>>();
+  const int s = op.nx, ny = op.ny;
+  f->nx = s; f->ny = ny; f->leaf = opt.leaf; f->eps = opt.eps; f->precision = opt.precision;
+  const int L = hodlr_depth(s, opt.leaf);
+  f->L = L;
+  const int b = s >> L;
+  f->b = b;
+  const double eps = opt.eps;
+  const double ieps = opt.inner_eps;
+  const int mr = opt.max_rank;
+  work() = Work();
+  DBuf<int> status(1);
+  ACR_HIP(hipMemsetAsync(status.get(), 0, sizeof(int), st));
+  {
+    DBuf<int> nonfin(1);
+    ACR_HIP(hipMemsetAsync(nonfin.get(), 0, sizeof(int), st));
+    const long long n = (long long)s * ny;
+    for (const double* a : {op.diag, op.west, op.east, op.south, op.north}) flag_nonfinite(st, n, a, nonfin.get());
+    int bad = 0;
+    ACR_HIP(hipMemcpyAsync(&bad, nonfin.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    ACR_HIP(hipStreamSynchronize(st));
+    if (bad) fail(ACR_ERR_INVALID_ARG, "the operator holds a NaN or infinite coefficient");
+  }
+
+  // level-0 operator: D_i as exact rank-1 HODLR, E_i/F_i diagonal
+  HSet<T> D;
+  {
+    std::vector<int> k1(L + 1, 1);
+    D.alloc(st, ny, s, b, L, k1, false);
+    build_leaves_tridiag<T>(st, s, b, ny, 1, 0, op.diag, op.west, op.east, D.lv.get());
+    for (int d = 1; d <= L; ++d) {
+      build_rank1_factors<T>(st, s, s >> d, ny, 1, 0, op.west, op.east, D.U[d].get(), D.V[d].get());
+      D.kc[d] = 1;
+    }
+  }
+  HSet<T> E, F;
+  DBuf<T> e0((size_t)ny * s), f0((size_t)ny * s);
+  gather_diag<T>(st, s, ny, 1, 0, op.south, e0.get());
+  gather_diag<T>(st, s, ny, 1, 0, op.north, f0.get());
+  // E_0 and F_(ny-1) are outside the grid: exact zeros
+  fill<T>(st, e0.get(), s, T(0));
+  fill<T>(st, f0.get() + (size_t)(ny - 1) * s, s, T(0));
+
+  int m = ny;
+  bool diag = true;
+  while (m > 1) {
+    Level<T> lv;
+    lv.m = m;
+    lv.nreal = (m + 1) / 2;
+    lv.ne = m / 2 + 1;
+    lv.diag = diag;
+    const int nodd = m / 2;
+    // X_k = T(D_k^{-1}) for even k
+    stage_check(st, D, status.get(), "D", (int)f->lev.size());
+    hinv<T>(st, lv.X, HV<T>{&D, 2, 0}, lv.nreal, status.get());
+    stage_check(st, lv.X, status.get(), "inv", (int)f->lev.size());
+    recompress<T>(st, lv.X, eps, mr);
+    stage_check(st, lv.X, status.get(), "X", (int)f->lev.size());
+    HSet<T> P, Q;
+    HSet<T> Dn, En, Fn;
+    if (diag) {
+      hscale_cols<T>(st, P, lv.ne, HV<T>{&lv.X, 1, 0}, e0.get(), 2, 0, lv.nreal);
+      hscale_cols<T>(st, Q, lv.ne, HV<T>{&lv.X, 1, 0}, f0.get(), 2, 0, lv.nreal);
+      recompress<T>(st, P, eps, mr);
+      recompress<T>(st, Q, eps, mr);
+      // D'_j = D_i - diag(e_i) Q_j - diag(f_i) P_(j+1)
+      std::vector<STerm<T>> terms(3);
+      terms[0].h = HV<T>{&D, 2, 1};
+      terms[1].h = HV<T>{&Q, 1, 0}; terms[1].coef = T(-1); terms[1].rows = e0.get(); terms[1].rmul = 2; terms[1].roff = 1;
+      terms[2].h = HV<T>{&P, 1, 1}; terms[2].coef = T(-1); terms[2].rows = f0.get(); terms[2].rmul = 2; terms[2].roff = 1;
+      hstack<T>(st, Dn, nodd, terms, nodd);
+      std::vector<STerm<T>> te(1), tf(1);
+      te[0].h = HV<T>{&P, 1, 0}; te[0].coef = T(-1); te[0].rows = e0.get(); te[0].rmul = 2; te[0].roff = 1;
+      tf[0].h = HV<T>{&Q, 1, 1}; tf[0].coef = T(-1); tf[0].rows = f0.get(); tf[0].rmul = 2; tf[0].roff = 1;
+      hstack<T>(st, En, nodd, te, nodd);
+      hstack<T>(st, Fn, nodd, tf, nodd);
+      lv.e0 = std::move(e0);
+      lv.f0 = std::move(f0);
+    } else {
+      hprod<T>(st, P, lv.ne, HV<T>{&lv.X, 1, 0}, HV<T>{&E, 2, 0}, lv.nreal, T(1));
+      hprod<T>(st, Q, lv.ne, HV<T>{&lv.X, 1, 0}, HV<T>{&F, 2, 0}, lv.nreal, T(1));
+      recompress<T>(st, P, eps, mr);
+      recompress<T>(st, Q, eps, mr);
+      HSet<T> EQ, FP;
+      hprod<T>(st, EQ, nodd, HV<T>{&E, 2, 1}, HV<T>{&Q, 1, 0}, nodd, T(1));
+      hprod<T>(st, FP, nodd, HV<T>{&F, 2, 1}, HV<T>{&P, 1, 1}, nodd, T(1));
+      if (ieps > 0) {
+        recompress<T>(st, EQ, ieps, 0);
+        recompress<T>(st, FP, ieps, 0);
+      }
+      std::vector<STerm<T>> terms(3);
+      terms[0].h = HV<T>{&D, 2, 1};
+      terms[1].h = HV<T>{&EQ, 1, 0}; terms[1].coef = T(-1);
+      terms[2].h = HV<T>{&FP, 1, 0}; terms[2].coef = T(-1);
+      hstack<T>(st, Dn, nodd, terms, nodd);
+      hprod<T>(st, En, nodd, HV<T>{&E, 2, 1}, HV<T>{&P, 1, 0}, nodd, T(-1));
+      hprod<T>(st, Fn, nodd, HV<T>{&F, 2, 1}, HV<T>{&Q, 1, 1}, nodd, T(-1));
+      lv.E = std::move(E);
+      lv.F = std::move(F);
+    }
+    stage_check(st, P, status.get(), "P", (int)f->lev.size());
+    stage_check(st, Q, status.get(), "Q", (int)f->lev.size());
+    stage_check(st, Dn, status.get(), "D'-exact", (int)f->lev.size());
+    recompress<T>(st, Dn, eps, mr);
+    recompress<T>(st, En, eps, mr);
+    recompress<T>(st, Fn, eps, mr);
+    stage_check(st, Dn, status.get(), "D'", (int)f->lev.size());
+    stage_check(st, En, status.get(), "E'", (int)f->lev.size());
+    stage_check(st, Fn, status.get(), "F'", (int)f->lev.size());
+    int r = lv.X.max_rank();
+    r = std::max(r, lv.E.max_rank());
+    r = std::max(r, lv.F.max_rank());
+    f->lev_rank.push_back(r);
+    f->lev.push_back(std::move(lv));
+    D = std::move(Dn);
+    E = std::move(En);
+    F = std::move(Fn);
+    m = nodd;
+    diag = false;
+  }
+  hinv<T>(st, f->Xlast, HV<T>{&D, 1, 0}, 1, status.get());
+  recompress<T>(st, f->Xlast, eps, mr);
+  int bad = 0;
+  ACR_HIP(hipMemcpyAsync(&bad, status.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+  ACR_HIP(hipStreamSynchronize(st));
+  if (bad) fail(ACR_ERR_SINGULAR, "zero or non-finite pivot in a dense leaf or capacitance inverse");
+  f->work_done = work();
+  return f;
+}
+
+}  // namespace
+}  // namespace acr
+
+struct acr_handle_s {
+  std::unique_ptr<acr::FactorBase> f;
+  int precision = 0;
+  int nx = 0, ny = 0;
+};
+
+using namespace acr;
+
+namespace {
+
+acr_status guard(const std::function<void()>& fn) {
+  try {
+    g_last_error.clear();
+    fn();
+    return ACR_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc& e) {
+    g_last_error = "host allocation failed";
+    return ACR_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return ACR_ERR_INTERNAL;
+  }
+}
+
+void check_op(const acr_operator* op) {
+  if (!op) fail(ACR_ERR_INVALID_ARG, "operator is NULL");
+  if (op->nx < 1 || op->ny < 1) fail(ACR_ERR_INVALID_ARG, "nx and ny must be >= 1");
+  if ((long long)op->nx * op->ny > (1LL << 31)) fail(ACR_ERR_INVALID_ARG, "N too large");
+  if (!op->diag || !op->west || !op->east || !op->south || !op->north)
+    fail(ACR_ERR_INVALID_ARG, "a stencil array is NULL");
+}
+
+}  // namespace
+
+extern "C" {
+
+acr_status acr_factor(const acr_operator* op, const acr_options* opt, void* stream, acr_handle* out) {
+  return guard([&] {
+    check_op(op);
+    if (!opt || !out) fail(ACR_ERR_INVALID_ARG, "options or output handle is NULL");
+    if (opt->leaf < 1 || opt->leaf > 128) fail(ACR_ERR_INVALID_ARG, "leaf must be in 1..128");
+    if (!(opt->eps >= 0.0) || !std::isfinite(opt->eps)) fail(ACR_ERR_INVALID_ARG, "eps must be finite and >= 0");
+    if (!(opt->inner_eps >= 0.0)) fail(ACR_ERR_INVALID_ARG, "inner_eps must be >= 0");
+    if (opt->precision != ACR_FP64 && opt->precision != ACR_MIXED_FP32)
+      fail(ACR_ERR_INVALID_ARG, "unknown precision");
+    if (opt->max_rank < 0) fail(ACR_ERR_INVALID_ARG, "max_rank must be >= 0");
+    if (hodlr_depth(op->nx, opt->leaf) < 0)
+      fail(ACR_ERR_INVALID_ARG, "block size must be leaf' * 2^L (halving exact down to the leaf)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto h = std::make_unique<acr_handle_s>();
+    h->precision = opt->precision;
+    h->nx = op->nx; h->ny = op->ny;
+    if (opt->precision == ACR_FP64) h->f = factor_impl<double>(*op, *opt, st);
+    else h->f = factor_impl<float>(*op, *opt, st);
+    *out = h.release();
+  });
+}
+
+acr_status acr_solve(acr_handle h, const double* B, double* X, int32_t nrhs, void* stream) {
+  return guard([&] {
+    if (!h || !B || !X) fail(ACR_ERR_INVALID_ARG, "NULL argument");
+    if (nrhs < 1) fail(ACR_ERR_INVALID_ARG, "nrhs must be >= 1");
+    h->f->solve(B, X, nrhs, static_cast<hipStream_t>(stream));
+  });
+}
+
+acr_status acr_residual(const acr_operator* op, const double* X, const double* B, double* R,
+                        int32_t nrhs, void* stream) {
+  return guard([&] {
+    check_op(op);
+    if (!X || !B || !R || nrhs < 1) fail(ACR_ERR_INVALID_ARG, "bad vector arguments");
+    stencil_residual(static_cast<hipStream_t>(stream), op->nx, op->ny, nrhs, op->diag, op->west, op->east,
+                     op->south, op->north, X, B, R);
+  });
+}
+
+acr_status acr_solve_refined(acr_handle h, const acr_operator* op, const double* B, double* X,
+                             int32_t nrhs, double tol, int32_t maxit, int32_t* iters, double* relres,
+                             void* stream) {
+  int its = 0;
+  double rel = INFINITY;
+  acr_status st0 = guard([&] {
+    check_op(op);
+    if (!h || !B || !X || nrhs < 1 || maxit < 0) fail(ACR_ERR_INVALID_ARG, "bad arguments");
+    if (op->nx != h->nx || op->ny != h->ny) fail(ACR_ERR_INVALID_ARG, "operator shape differs from the factor");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long n = (long long)op->nx * op->ny;
+    DBuf<double> R((size_t)n * nrhs), D((size_t)n * nrhs), nb(nrhs), nr(nrhs);
+    std::vector<double> hb(nrhs), hr(nrhs);
+    col_sumsq(st, n, nrhs, B, nb.get());
+    ACR_HIP(hipMemcpyAsync(hb.data(), nb.get(), nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    ACR_HIP(hipMemsetAsync(X, 0, (size_t)n * nrhs * sizeof(double), st));
+    ACR_HIP(hipMemcpyAsync(R.get(), B, (size_t)n * nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
+    ACR_HIP(hipStreamSynchronize(st));
+    for (its = 0;; ++its) {
+      if (its > 0) {
+        stencil_residual(st, op->nx, op->ny, nrhs, op->diag, op->west, op->east, op->south, op->north, X, B,
+                         R.get());
+      }
+      col_sumsq(st, n, nrhs, R.get(), nr.get());
+      ACR_HIP(hipMemcpyAsync(hr.data(), nr.get(), nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      ACR_HIP(hipStreamSynchronize(st));
+      rel = 0.0;
+      for (int q = 0; q < nrhs; ++q) {
+        const double v = hb[q] > 0 ? std::sqrt(hr[q] / hb[q]) : std::sqrt(hr[q]);
+        rel = std::max(rel, v);
+      }
+      if (!(rel > tol) || its >= maxit || !std::isfinite(rel)) break;
+      h->f->solve(R.get(), D.get(), nrhs, st);
+      axpy_d(st, n * nrhs, D.get(), X);
+    }
+    if (!(rel <= tol)) fail(ACR_ERR_NOT_CONVERGED, "refinement stopped at relative residual " + std::to_string(rel));
+  });
+  if (iters) *iters = its;
+  if (relres) *relres = rel;
+  return st0;
+}
+
+acr_status acr_get_info(acr_handle h, acr_info* out) {
+  return guard([&] {
+    if (!h || !out) fail(ACR_ERR_INVALID_ARG, "NULL argument");
+    h->f->info(out);
+  });
+}
+
+acr_status acr_get_block(acr_handle h, int32_t level, int32_t which, int32_t k, double* dense, void* stream) {
+  return guard([&] {
+    if (!h || !dense) fail(ACR_ERR_INVALID_ARG, "NULL argument");
+    h->f->block(level, which, k, dense, static_cast<hipStream_t>(stream));
+  });
+}
+
+acr_status acr_destroy(acr_handle h) {
+  return guard([&] {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    delete h;
+  });
+}
+
+const char* acr_status_string(acr_status s) {
+  switch (s) {
+    case ACR_OK: return "ok";
+    case ACR_ERR_INVALID_ARG: return "invalid argument";
+    case ACR_ERR_OOM: return "out of device memory";
+    case ACR_ERR_SINGULAR: return "singular pivot";
+    case ACR_ERR_NOT_CONVERGED: return "refinement did not converge";
+    case ACR_ERR_DEVICE: return "HIP runtime error";
+    case ACR_ERR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* acr_last_error(void) { return g_last_error.c_str(); }
+
+acr_status acr_trim_pool(void) {
+  return guard([&] { Pool::get().trim(); });
+}
+
+}  // extern "C"

@@ -1,0 +1,171 @@
+// Shared host-side plumbing of the ACR library: error handling, the device
+// memory pool, device buffers and the descriptors of batched operands.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/acr.h"
+
+namespace acr {
+
+// ----------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  acr_status code;
+  Error(acr_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(acr_status c, const std::string& m) { throw Error(c, m); }
+
+#define ACR_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      ::acr::fail(e_ == hipErrorOutOfMemory ? ACR_ERR_OOM : ACR_ERR_DEVICE,            \
+                  std::string(#call) + ": " + hipGetErrorString(e_) + " (" __FILE__ ":" + \
+                      std::to_string(__LINE__) + ")");                                 \
+  } while (0)
+
+#define ACR_CHECK_LAUNCH() ACR_HIP(hipGetLastError())
+
+// ------------------------------------------------------------ memory pool
+// Caching allocator: freed blocks are kept per rounded size and reused by
+// later requests on the same stream order (every library call uses one
+// stream, so a block released after enqueued work can be handed out to work
+// enqueued later on that stream without a synchronisation).
+class Pool {
+ public:
+  static Pool& get() {
+    static Pool p;
+    return p;
+  }
+  void* alloc(size_t bytes) {
+    if (bytes == 0) return nullptr;
+    size_t r = round(bytes);
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      auto it = free_.lower_bound(r);
+      if (it != free_.end() && it->first <= r + r / 4) {
+        void* p = it->second;
+        size_t sz = it->first;
+        free_.erase(it);
+        live_[p] = sz;
+        return p;
+      }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, r);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      e = hipMalloc(&p, r);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(ACR_ERR_OOM, "hipMalloc of " + std::to_string(r) + " bytes failed");
+      }
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    live_[p] = r;
+    total_ += r;
+    return p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    free_.emplace(it->second, p);
+    live_.erase(it);
+  }
+  void trim() {
+    std::lock_guard<std::mutex> g(mu_);
+    if (!free_.empty()) (void)hipDeviceSynchronize();
+    for (auto& kv : free_) {
+      (void)hipFree(kv.second);
+      total_ -= kv.first;
+    }
+    free_.clear();
+  }
+  size_t total() const { return total_; }
+
+ private:
+  static size_t round(size_t b) {
+    if (b <= 4096) return 4096;
+    size_t g = 1;
+    while (g * 16 < b) g <<= 1;           // granularity ~ b/16, power of two
+    return (b + g - 1) / g * g;
+  }
+  std::mutex mu_;
+  std::multimap<size_t, void*> free_;
+  std::map<void*, size_t> live_;
+  size_t total_ = 0;
+};
+
+// Owning device buffer of n elements of T (from the pool).
+template <typename T>
+class DBuf {
+ public:
+  DBuf() = default;
+  explicit DBuf(size_t n) { resize(n); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { reset(); p_ = o.p_; n_ = o.n_; o.p_ = nullptr; o.n_ = 0; }
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void resize(size_t n) {
+    reset();
+    if (n) p_ = static_cast<T*>(Pool::get().alloc(n * sizeof(T)));
+    n_ = n;
+  }
+  void reset() {
+    if (p_) Pool::get().release(p_);
+    p_ = nullptr;
+    n_ = 0;
+  }
+  T* get() const { return p_; }
+  size_t size() const { return n_; }
+  size_t bytes() const { return n_ * sizeof(T); }
+
+ private:
+  T* p_ = nullptr;
+  size_t n_ = 0;
+};
+
+// -------------------------------------------------- batched operand views
+// One operand of a batched operation over problems p = (m, c): matrix index
+// m (0..nmat-1) and cluster index c (0..ncl-1).  The operand of problem p
+// starts at
+//   base + (mmul*m + moff)*sm + ((c^cxor) >> 1)*sc_pair + ((c^cxor) & 1)*sc_odd
+// and is column-major with leading dimension ld (transposed if trans).
+struct BOp {
+  const void* p = nullptr;
+  int ld = 1;
+  int trans = 0;
+  int mmul = 1, moff = 0;
+  long long sm = 0;
+  long long sc_pair = 0, sc_odd = 0;
+  int cxor = 0;
+};
+
+// Uniform cluster stride helper: operand of cluster c at base + c*sc.
+inline BOp bop(const void* p, int ld, long long sm, long long sc = 0, int trans = 0) {
+  BOp o;
+  o.p = p; o.ld = ld; o.sm = sm; o.sc_pair = 2 * sc; o.sc_odd = sc; o.trans = trans;
+  return o;
+}
+inline BOp with_map(BOp o, int mmul, int moff) { o.mmul = mmul; o.moff = moff; return o; }
+inline BOp swapped(BOp o) { o.cxor = 1; return o; }
+inline BOp transposed(BOp o) { o.trans = 1; return o; }
+
+}  // namespace acr

@@ -1,0 +1,129 @@
+// Host launchers of the ACR device kernels (gfx950).  Every launcher enqueues
+// on `st` and checks the launch.  Problems of a batched call are indexed
+// p = m*ncl + c (matrix m, cluster c) unless stated otherwise.
+#pragma once
+
+#include "common.hpp"
+
+namespace acr {
+
+// C_p = alpha * op(A_p) op(B_p) + beta * C_p, all problems M x N x K.
+// beta == 0 overwrites C without reading it.
+template <typename T>
+void bgemm(hipStream_t st, int M, int N, int K, int nmat, int ncl, T alpha, const BOp& A,
+           const BOp& B, T beta, const BOp& C);
+
+// X_p = A_p^{-1} (n x n, Gauss-Jordan with partial pivoting, computed in FP64).
+// A_p at A + p*sA (ld n), X_p at X + p*sX (ld n).  *status set to 1 on a zero
+// or non-finite pivot.
+template <typename Tin, typename Tout>
+void binverse(hipStream_t st, int n, int nprob, const Tin* A, long long sA, Tout* X,
+              long long sX, int* status);
+
+// R factor of the Householder QR of each p x k operand A_(m,c):
+// R_p = c x k upper trapezoidal, c = min(p, k), column-major ld = c, at R + p*c*k.
+// If Vref is given, the reflectors are kept: v_j (p values, zero above row j,
+// v_j[j] = 1) at Vref + (p_idx*c + j)*p and tau_j at tau + p_idx*c + j, so that
+// Q = H_0 H_1 ... H_(c-1), H_j = I - tau_j v_j v_j^T.
+template <typename T>
+void bqr_r(hipStream_t st, int p, int k, int nmat, int ncl, const BOp& A, T* R, T* Vref = nullptr,
+           T* tau = nullptr);
+
+// Y_(m,c) = Q_(m,c) [Z; 0] with the reflectors of a bqr_r call (same p, c
+// and problem order); Z of problem (m, c) is the c x t block at
+// Z + (m*ncl + (c ^ zxor)) * sZ (ld c).
+template <typename T>
+void bapply_q(hipStream_t st, int p, int c, int t, int nmat, int ncl, const T* Vref, const T* tau,
+              const T* Z, long long sZ, int zxor, const BOp& Y);
+
+// One-sided Jacobi SVD of each c x c matrix K_p (at K + p*c*c, ld c):
+// K_p J_p = Usc_p, columns sorted by decreasing norm sig.  Outputs (per
+// problem, contiguous): sig[c], Usc[c*c], J[c*c]; rank_p = #{sig > eps*sig_1}
+// capped by maxrank (> 0).  K is overwritten.
+template <typename T>
+void bsvd(hipStream_t st, int c, int nprob, T* K, T* sig, T* Usc, T* J, int* rank, double eps,
+          int maxrank);
+
+// Truncation: Jt = J[:, :kout] with columns >= rank_p zeroed (c x kout per problem).
+template <typename T>
+void btrunc_coef(hipStream_t st, int c, int kout, int nprob, const T* J, const int* rank, T* Jt);
+
+// max over rank[0..n) into *out (device int).
+void bmax_int(hipStream_t st, const int* rank, int n, int* out);
+
+// dst_m = alpha * src_m (rows x cols each; ld / stride per matrix / maps in
+// the BOps; cluster fields ignored).
+template <typename T>
+void bcopy(hipStream_t st, int rows, int cols, int nmat, T alpha, const BOp& src, const BOp& dst);
+// dst_m += alpha * src_m
+template <typename T>
+void badd(hipStream_t st, int rows, int cols, int nmat, T alpha, const BOp& src, const BOp& dst);
+
+// Fill n values with v.
+template <typename T>
+void fill(hipStream_t st, T* p, size_t n, T v);
+
+// Scale rows (side 0) or columns (side 1) of per-matrix / per-cluster blocks:
+// X_(m,c)[r, q] *= alpha * vec[(vmul*m+voff)*vstride + c*vcl + (side ? q : r)].
+// The operand uses the cluster fields of X (sc_pair/sc_odd).
+template <typename T>
+void bscale(hipStream_t st, int rows, int cols, int nmat, int ncl, const BOp& X, const T* vec,
+            int vmul, int voff, long long vstride, long long vcl, int side, T alpha);
+
+// Capacitance matrices of the HODLR inverse: for each parent q of a pair of
+// clusters (2q, 2q+1) with cores c_(2q), c_(2q+1) (k x k each, contiguous per
+// cluster), G_q = [[I, c_(2q+1)], [c_(2q), I]] (2k x 2k, ld 2k).
+template <typename T>
+void build_capacitance(hipStream_t st, int k, int npairs, const T* cores, T* G);
+
+// Level-0 diagonal blocks D_i of the stencil as HODLR matrices (Section 3:
+// tridiagonal D_i has exact rank-1 off-diagonal blocks).  Block index of
+// matrix m is i = bmul*m + boff.  Leaves: the tridiagonal band restricted to
+// each b x b diagonal leaf.
+template <typename T>
+void build_leaves_tridiag(hipStream_t st, int s, int b, int nmat, int bmul, int boff,
+                          const double* diag, const double* west, const double* east, T* leaves);
+// Depth-d factors (cluster size sd, one column each, flat length s): the
+// upper-right block of a first child couples its last row to the sibling's
+// first column (value east), the lower-left block of a second child couples
+// its first row to the sibling's last column (value west).
+template <typename T>
+void build_rank1_factors(hipStream_t st, int s, int sd, int nmat, int bmul, int boff,
+                         const double* west, const double* east, T* U, T* V);
+
+// Copy a diagonal (per block, contiguous s values) of the stencil into T.
+template <typename T>
+void gather_diag(hipStream_t st, int s, int nmat, int bmul, int boff, const double* src, T* dst);
+
+// Block-major <-> column-major vector layouts.  V[i][q][j] = B[(i*s + j) + q*ld].
+template <typename T>
+void to_blocks(hipStream_t st, int s, int nblk, int nrhs, const double* B, long long ld, T* V);
+template <typename T>
+void from_blocks(hipStream_t st, int s, int nblk, int nrhs, const T* V, double* B, long long ld);
+
+// y = y + alpha * diag(d_(bmul*j+boff)) * x_j  for vectors in block-major form
+// (nmat blocks of s x nrhs).  Rows scaled by d.
+template <typename T>
+void bdiag_axpy(hipStream_t st, int s, int nrhs, int nmat, T alpha, const T* d, int dmul, int doff,
+                const T* x, int xmul, int xoff, T* y, int ymul, int yoff);
+
+// R = B - A X (FP64 5-point stencil); N = nx*ny, columns nrhs, ld N.
+void stencil_residual(hipStream_t st, int nx, int ny, int nrhs, const double* diag,
+                      const double* west, const double* east, const double* south,
+                      const double* north, const double* X, const double* B, double* R);
+
+// out[q] = sum_i A[i + q*n]^2  (n rows, ncol columns), FP64.
+void col_sumsq(hipStream_t st, long long n, int ncol, const double* A, double* out);
+
+// *flag = 1 if any of a[0..n) is NaN or infinite (flag untouched otherwise).
+void flag_nonfinite(hipStream_t st, long long n, const double* a, int* flag);
+
+// Diagnostics: whether a[0..n) holds a NaN/Inf and the largest finite |a|.
+// Synchronises st.
+template <typename T>
+void scan_values(hipStream_t st, long long n, const T* a, bool* bad, double* amax);
+
+// X += D (both N x nrhs FP64).
+void axpy_d(hipStream_t st, long long n, const double* D, double* X);
+
+}  // namespace acr

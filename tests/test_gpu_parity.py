@@ -1,0 +1,188 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Forward-error gate (FP64): ||x_gpu - x_oracle|| / ||x_oracle|| <= 10 eps at the
+same eps and leaf, on the same seeded inputs.  Stored blocks are compared
+element-wise (after densifying both).  Mixed precision is gated on the FP64
+relative residual after refinement (<= 1e-10) computed on the CPU.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import acr as OA
+from oracle import direct, hodlr
+
+pytestmark = pytest.mark.gpu
+
+
+def _op(acr, st):
+    return acr.Operator.from_arrays(st.nx, st.ny, *st.arrays())
+
+
+def _solve(acr, st, leaf, eps, prec="fp64", nrhs=2, seed=7, **kw):
+    import torch
+    h = acr.acr_factor(_op(acr, st), leaf, eps, prec, **kw)
+    b = W.rhs(st.n, nrhs, seed=seed)
+    x = acr.acr_solve(h, torch.from_numpy(b).cuda()).cpu().numpy()
+    return h, b, x
+
+
+def _relerr(x, y):
+    return float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
+
+CASES = [
+    # (stencil builder, leaf, eps): several tiles, odd block counts, ragged levels
+    (lambda: W.poisson(64), 16, 1e-10),                    # 64x64 Poisson, leaf 16 (the small config)
+    (lambda: W.varkappa(128), 32, 1e-8),
+    (lambda: W.convdiff(96, 37), 24, 1e-7),               # leaf 24 after two halvings, 37 blocks
+    (lambda: W.varkappa(64), 64, 1e-9),                    # one dense leaf per block: exact BCR
+    (lambda: W.poisson(48, 5), 6, 1e-6),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_fp64_solution_vs_oracle(gpu, case):
+    build, leaf, eps = CASES[case]
+    st = build()
+    h, b, x = _solve(gpu, st, leaf, eps)
+    fac = OA.factor(st, leaf, eps)
+    xo = OA.solve(fac, st, b)
+    e = _relerr(x, xo)
+    print(f"{st.name} {st.nx}x{st.ny} leaf {leaf} eps {eps}: |x-x_oracle|/|x_oracle| = {e:.3e}")
+    assert e <= 10 * eps
+    info = gpu.acr_get_info(h)
+    assert info["levels"] == len(fac.levels)
+    assert info["level_max_rank"] == [max(r, 0) for r in info["level_max_rank"]]
+
+
+def test_fp64_blocks_vs_oracle(gpu):
+    """Stored X_k, E_k, F_k of the first levels, element-wise after densifying."""
+    st = W.varkappa(64, seed=W.seed_for(1, 5))
+    leaf, eps = 16, 1e-9
+    h = gpu.acr_factor(_op(gpu, st), leaf, eps, "fp64")
+    fac = OA.factor(st, leaf, eps)
+    for lev in range(3):
+        X, E, F = fac.levels[lev]
+        for k in (0, 2, len(E) - 2 - (len(E) % 2)):
+            ref = hodlr.densify(X[k])
+            got = gpu.acr_get_block(h, lev, 0, k)
+            assert np.abs(got - ref).max() <= 10 * eps * np.abs(ref).max()
+        for k in (1, len(E) // 2, len(E) - 1):
+            for which, L in ((1, E), (2, F)):
+                ref = hodlr.densify(L[k])
+                got = gpu.acr_get_block(h, lev, which, k)
+                scale = max(np.abs(ref).max(), 1e-300)
+                assert np.abs(got - ref).max() <= 10 * eps * scale
+    # level-0 off-diagonal ranks of D are exactly one: the first stored X has
+    # exact ranks 1, 2, ... by depth, so its truncated ranks are bounded by the depth
+    assert gpu.acr_get_info(h)["level_max_rank"][0] <= 2
+
+
+def test_mixed_refined_residual(gpu):
+    import torch
+    st = W.varkappa(128)
+    op = _op(gpu, st)
+    h = gpu.acr_factor(op, 32, 1e-6, "mixed")
+    b = W.rhs(st.n, 3, seed=3)
+    x, its, rel = gpu.acr_solve_refined(h, op, torch.from_numpy(b).cuda(), tol=1e-10, maxit=30)
+    r = direct.residual(st, x.cpu().numpy(), b)
+    print(f"mixed IR: {its} iterations, device relres {rel:.2e}, CPU relres {r:.2e}")
+    assert r <= 1e-10
+    assert its <= 30
+
+
+def test_fp64_refined_residual(gpu):
+    import torch
+    st = W.convdiff(128)
+    op = _op(gpu, st)
+    h = gpu.acr_factor(op, 32, 1e-6, "fp64")
+    b = W.rhs(st.n, 2, seed=4)
+    x, its, rel = gpu.acr_solve_refined(h, op, torch.from_numpy(b).cuda(), tol=1e-10, maxit=30)
+    assert direct.residual(st, x.cpu().numpy(), b) <= 1e-10
+
+
+def test_mixed_forward_error_reported(gpu):
+    """Mixed-precision solve before refinement, against the FP64 oracle at the
+    same eps (reported; the binding gate for FP32 is the refined residual)."""
+    st = W.varkappa(64)
+    h, b, x = _solve(gpu, st, 16, 1e-6, "mixed")
+    xo = OA.solve(OA.factor(st, 16, 1e-6), st, b)
+    e = _relerr(x, xo)
+    print(f"mixed pre-refinement forward error vs oracle: {e:.3e} (10*eps = 1e-5)")
+    assert e < 1e-2
+
+
+def test_edge_cases(gpu):
+    # one block: no reduction level, just the HODLR inverse
+    st = W.poisson(64, 1)
+    h, b, x = _solve(gpu, st, 16, 1e-12)
+    assert _relerr(x, direct.solve(st, b)) < 1e-9
+    assert gpu.acr_get_info(h)["levels"] == 0
+    # block size 1 (tridiagonal system of scalars), odd block count
+    st = W.poisson(1, 9)
+    h, b, x = _solve(gpu, st, 4, 0.0)
+    assert _relerr(x, direct.solve(st, b)) < 1e-13
+    # block size below the leaf: dense BCR
+    st = W.varkappa(20)
+    h, b, x = _solve(gpu, st, 32, 1e-8)
+    assert _relerr(x, direct.solve(st, b)) < 1e-11
+    # eps = 0: nothing truncated, exact to rounding
+    st = W.varkappa(32)
+    h, b, x = _solve(gpu, st, 8, 0.0)
+    assert _relerr(x, direct.solve(st, b)) < 1e-11
+
+
+def test_deterministic_fp64(gpu):
+    st = W.varkappa(64)
+    _, _, x1 = _solve(gpu, st, 16, 1e-8)
+    _, _, x2 = _solve(gpu, st, 16, 1e-8)
+    assert np.array_equal(x1, x2)
+
+
+def test_errors(gpu):
+    st = W.poisson(50)                       # 50 -> 25: odd cluster above the leaf
+    with pytest.raises(gpu.ACRError) as ei:
+        gpu.acr_factor(_op(gpu, st), 16, 1e-6)
+    assert ei.value.name == "ACR_ERR_INVALID_ARG"
+    st = W.poisson(32)
+    for leaf, eps in ((0, 1e-6), (16, -1.0), (16, float("nan"))):
+        with pytest.raises(gpu.ACRError) as ei:
+            gpu.acr_factor(_op(gpu, st), leaf, eps)
+        assert ei.value.name == "ACR_ERR_INVALID_ARG"
+    # zero operator: every leaf pivot is zero
+    z = np.zeros(32 * 32)
+    op = gpu.Operator.from_arrays(32, 32, z, z, z, z, z)
+    with pytest.raises(gpu.ACRError) as ei:
+        gpu.acr_factor(op, 16, 1e-6)
+    assert ei.value.name == "ACR_ERR_SINGULAR"
+    # non-finite input is rejected before any arithmetic
+    st = W.poisson(32)
+    d = st.diag.copy()
+    d[5] = np.nan
+    op = gpu.Operator.from_arrays(32, 32, d, st.west, st.east, st.south, st.north)
+    with pytest.raises(gpu.ACRError) as ei:
+        gpu.acr_factor(op, 16, 1e-6)
+    assert ei.value.name == "ACR_ERR_INVALID_ARG"
+    # refinement that cannot reach the tolerance reports NOT_CONVERGED
+    import torch
+    st = W.varkappa(64)
+    op = _op(gpu, st)
+    h = gpu.acr_factor(op, 16, 1e-6, "mixed")
+    b = torch.from_numpy(W.rhs(st.n, 1)).cuda()
+    with pytest.raises(gpu.ACRError) as ei:
+        gpu.acr_solve_refined(h, op, b, tol=1e-30, maxit=2)
+    assert ei.value.name == "ACR_ERR_NOT_CONVERGED"
+
+
+def test_mixed_denormal_columns_regression(gpu):
+    """256x256 variable kappa, leaf 64, FP32 factor: columns of the block
+    inverses decay below 1/FLT_MAX inside far clusters; the Householder
+    vectors must stay finite (they once overflowed to inf in FP32)."""
+    import torch
+    st = W.varkappa(256)
+    op = _op(gpu, st)
+    h = gpu.acr_factor(op, 64, 1e-6, "mixed")
+    b = W.rhs(st.n, 1, seed=5)
+    x, its, rel = gpu.acr_solve_refined(h, op, torch.from_numpy(b).cuda(), tol=1e-10, maxit=30)
+    assert direct.residual(st, x.cpu().numpy(), b) <= 1e-10
