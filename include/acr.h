@@ -152,6 +152,31 @@ const char* acr_status_string(acr_status s);
 /* Text of the last error raised on the calling thread ("" if none). */
 const char* acr_last_error(void);
 
+/* Kernel classes of the event profiler. */
+typedef enum {
+  ACR_KC_GEMM = 0,     /* batched GEMM over (matrix, cluster) problems */
+  ACR_KC_INVERSE = 1,  /* dense leaf / capacitance inverses (FP64) */
+  ACR_KC_QR = 2,       /* Householder R factors (recompression) */
+  ACR_KC_APPLYQ = 3,   /* Q [J; 0] products (recompression) */
+  ACR_KC_SVD = 4,      /* one-sided Jacobi SVD of the recompression cores */
+  ACR_KC_MATVEC = 5,   /* HODLR multi-vector products of the solve */
+  ACR_KC_COPY = 6,     /* stacking copies, scalings */
+  ACR_KC_OTHER = 7,    /* layout, residual, reductions */
+  ACR_KC_COUNT = 8
+} acr_kernel_class;
+
+/* Start timing every launch of the classes in class_mask (bit c = class c)
+ * with HIP events recorded on each launch's stream; clears earlier records.
+ * A mask of 0 stops recording.  For benchmarking and diagnostics. */
+acr_status acr_profile_start(uint32_t class_mask);
+
+/* Totals for one class since acr_profile_start (host outputs, any may be
+ * NULL): launches, summed event time in ms, algorithmic flops and bytes of
+ * those launches (counted from their shapes; for the Jacobi SVD the pair
+ * inner products of the sweeps actually run).  Waits for the recorded events. */
+acr_status acr_profile_read(int32_t cls, int64_t* launches, double* total_ms, double* flops,
+                            double* bytes);
+
 /* Release the library's cached (unused) device memory. */
 acr_status acr_trim_pool(void);
 

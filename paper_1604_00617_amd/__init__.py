@@ -220,3 +220,32 @@ def acr_destroy(h: Handle):
 
 def acr_trim_pool():
     _check(load().acr_trim_pool())
+
+
+KERNEL_CLASSES = ["gemm", "inverse", "qr", "applyq", "svd", "matvec", "copy", "other"]
+
+
+def acr_profile_start(classes=None):
+    """Time every launch of the given kernel classes (names or indices; None = all)."""
+    lib = load()
+    lib.acr_profile_start.argtypes = [ctypes.c_uint32]
+    lib.acr_profile_start.restype = ctypes.c_int
+    if classes is None:
+        mask = (1 << len(KERNEL_CLASSES)) - 1
+    else:
+        mask = 0
+        for c in classes:
+            mask |= 1 << (KERNEL_CLASSES.index(c) if isinstance(c, str) else int(c))
+    _check(lib.acr_profile_start(mask))
+
+
+def acr_profile_read(cls) -> dict:
+    lib = load()
+    lib.acr_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.acr_profile_read.restype = ctypes.c_int
+    idx = KERNEL_CLASSES.index(cls) if isinstance(cls, str) else int(cls)
+    n, ms, fl, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib.acr_profile_read(idx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)))
+    return {"class": KERNEL_CLASSES[idx], "launches": n.value, "total_ms": ms.value, "flops": fl.value,
+            "bytes": by.value}

@@ -533,6 +533,41 @@ const char* acr_status_string(acr_status s) {
 
 const char* acr_last_error(void) { return g_last_error.c_str(); }
 
+acr_status acr_profile_start(uint32_t class_mask) {
+  return guard([&] { Profiler::get().start(class_mask); });
+}
+
+acr_status acr_profile_read(int32_t cls, int64_t* launches, double* total_ms, double* flops,
+                            double* bytes) {
+  return guard([&] {
+    if (cls < 0 || cls >= KC_COUNT) fail(ACR_ERR_INVALID_ARG, "unknown kernel class");
+    Profiler& P = Profiler::get();
+    std::lock_guard<std::mutex> g(P.mu());
+    int64_t n = 0;
+    double ms = 0, fl = 0, by = 0;
+    for (auto& r : P.recs()) {
+      if (r.cls != cls) continue;
+      ACR_HIP(hipEventSynchronize(r.b));
+      float e = 0;
+      ACR_HIP(hipEventElapsedTime(&e, r.a, r.b));
+      ++n;
+      ms += e;
+      by += r.bytes;
+      fl += r.flops;
+      if (r.dev_sweeps) {
+        std::vector<int> sw(r.nprob);
+        ACR_HIP(hipMemcpy(sw.data(), r.dev_sweeps, r.nprob * sizeof(int), hipMemcpyDeviceToHost));
+        const double per = 3.0 * (double)r.c * r.c * (r.c - 1);   // pair dot products per sweep
+        for (int v : sw) fl += per * v;
+      }
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms;
+    if (flops) *flops = fl;
+    if (bytes) *bytes = by;
+  });
+}
+
 acr_status acr_trim_pool(void) {
   return guard([&] { Pool::get().trim(); });
 }

@@ -142,6 +142,73 @@ class DBuf {
   size_t n_ = 0;
 };
 
+// --------------------------------------------------------- event profiler
+// Opt-in timing of every launch of selected kernel classes with HIP events
+// recorded on the launch stream, plus the algorithmic flops and bytes of each
+// launch (counted from its shapes).
+enum KClass { KC_GEMM = 0, KC_INVERSE, KC_QR, KC_APPLYQ, KC_SVD, KC_MATVEC, KC_COPY, KC_OTHER, KC_COUNT };
+
+class Profiler {
+ public:
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+    double flops, bytes;
+    const int* dev_sweeps;   // SVD: per-problem sweep counts (flops filled at read time)
+    int nprob, c;
+  };
+  static Profiler& get() {
+    static Profiler p;
+    return p;
+  }
+  bool on(int cls) const { return (mask_ >> cls) & 1u; }
+  void start(unsigned mask) {
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto& r : recs_) { pool_.push_back(r.a); pool_.push_back(r.b); }
+    recs_.clear();
+    owned_.clear();
+    mask_ = mask;
+  }
+  hipEvent_t event() {
+    if (!pool_.empty()) { hipEvent_t e = pool_.back(); pool_.pop_back(); return e; }
+    hipEvent_t e;
+    ACR_HIP(hipEventCreate(&e));
+    return e;
+  }
+  void push(const Rec& r) { std::lock_guard<std::mutex> g(mu_); recs_.push_back(r); }
+  std::mutex& mu() { return mu_; }
+  std::vector<Rec>& recs() { return recs_; }
+  std::vector<DBuf<int>>& owned() { return owned_; }
+
+ private:
+  unsigned mask_ = 0;
+  std::mutex mu_;
+  std::vector<Rec> recs_;
+  std::vector<hipEvent_t> pool_;
+  std::vector<DBuf<int>> owned_;
+};
+
+struct ProfScope {
+  bool act = false;
+  Profiler::Rec r{};
+  hipStream_t st = nullptr;
+  ProfScope(int cls, hipStream_t s, double flops, double bytes) {
+    Profiler& P = Profiler::get();
+    if (!P.on(cls)) return;
+    act = true;
+    st = s;
+    std::lock_guard<std::mutex> g(P.mu());
+    r.cls = cls; r.flops = flops; r.bytes = bytes; r.dev_sweeps = nullptr;
+    r.a = P.event(); r.b = P.event();
+    ACR_HIP(hipEventRecord(r.a, st));
+  }
+  ~ProfScope() {
+    if (!act) return;
+    (void)hipEventRecord(r.b, st);
+    Profiler::get().push(r);
+  }
+};
+
 // -------------------------------------------------- batched operand views
 // One operand of a batched operation over problems p = (m, c): matrix index
 // m (0..nmat-1) and cluster index c (0..ncl-1).  The operand of problem p

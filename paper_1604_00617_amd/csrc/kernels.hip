@@ -212,6 +212,88 @@ __global__ __launch_bounds__(256) void k_inverse(int n, const Tin* A, long long 
   if (tid == 0 && bad) status[0] = 1;
 }
 
+// In-place Gauss-Jordan with partial pivoting, n x n row-major in LDS (FP64):
+// pivot j: a_jj <- 1/p, row j scaled, column j <- -a_rj/p, rank-1 update of the
+// rest; the row swaps are undone as column swaps in reverse order at the end.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_inverse_lds(int n, const Tin* A, long long sA, Tout* X,
+                                                     long long sX, int* status) {
+  extern __shared__ double W[];
+  __shared__ int perm[128];
+  __shared__ double colj[128];
+  __shared__ int piv;
+  __shared__ double pinv;
+  __shared__ int bad;
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const Tin* Ap = A + (long long)p * sA;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < n * n; e += 256) {
+    const int r = e % n, c = e / n;
+    W[r * n + c] = (double)Ap[e];
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid < WAVE) {
+      double best = -1.0;
+      int bi = j;
+      for (int r = j + tid; r < n; r += WAVE) {
+        const double v = fabs(W[r * n + j]);
+        if (v > best) { best = v; bi = r; }
+      }
+      for (int off = WAVE / 2; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, WAVE);
+        const int oi = __shfl_xor(bi, off, WAVE);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) {
+        piv = bi;
+        perm[j] = bi;
+        if (!(best > 0.0) || !isfinite(best)) bad = 1;
+      }
+    }
+    __syncthreads();
+    const int pr = piv;
+    if (pr != j)
+      for (int c = tid; c < n; c += 256) {
+        const double a = W[j * n + c];
+        W[j * n + c] = W[pr * n + c];
+        W[pr * n + c] = a;
+      }
+    __syncthreads();
+    for (int r = tid; r < n; r += 256) colj[r] = W[r * n + j];
+    if (tid == 0) {
+      const double pv = W[j * n + j];
+      pinv = pv != 0.0 ? 1.0 / pv : 0.0;
+    }
+    __syncthreads();
+    const double inv = pinv;
+    for (int c = tid; c < n; c += 256) W[j * n + c] = (c == j) ? inv : W[j * n + c] * inv;
+    __syncthreads();
+    for (int e = tid; e < n * n; e += 256) {
+      const int r = e / n, c = e % n;
+      if (r == j) continue;
+      W[r * n + c] = (c == j) ? -colj[r] * inv : fma(-colj[r], W[j * n + c], W[r * n + c]);
+    }
+    __syncthreads();
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    const int pc = perm[j];
+    if (pc != j)
+      for (int r = tid; r < n; r += 256) {
+        const double a = W[r * n + j];
+        W[r * n + j] = W[r * n + pc];
+        W[r * n + pc] = a;
+      }
+    __syncthreads();
+  }
+  Tout* Xp = X + (long long)p * sX;
+  for (int e = tid; e < n * n; e += 256) {
+    const int r = e % n, c = e / n;
+    Xp[e] = (Tout)W[r * n + c];
+  }
+  if (tid == 0 && bad) status[0] = 1;
+}
+
 // ------------------------------------------------------------ QR (R only)
 // Householder QR of a p x k panel; one workgroup of 256 threads per problem.
 // The panel is copied to LDS when it fits, else to a global scratch copy.
@@ -333,7 +415,7 @@ __global__ __launch_bounds__(256) void k_apply_q(int p, int c, int t, int ncl, c
 // ------------------------------------------------------- one-sided Jacobi
 template <typename T>
 __global__ __launch_bounds__(256) void k_svd(int c, T* Kall, T* Jall, T* sig, T* Usc, T* Jout,
-                                             int* rank, double eps, int maxrank) {
+                                             int* rank, double eps, int maxrank, int* sweeps) {
   __shared__ int nrot;
   __shared__ double red[4];
   __shared__ T snorm[512];
@@ -407,6 +489,7 @@ __global__ __launch_bounds__(256) void k_svd(int c, T* Kall, T* Jall, T* sig, T*
     __syncthreads();
     const int done = (nrot == 0);
     __syncthreads();
+    if (sweeps && tid == 0) sweeps[prob] = sweep + 1;
     if (done) break;
   }
   // column norms, sort descending (ties by index), emit
@@ -634,14 +717,25 @@ __global__ void k_residual(int nx, int ny, const double* diag, const double* wes
   }
 }
 
-__global__ void k_col_sumsq(long long n, const double* A, double* out) {
+// Partial sums of squares: block (x, q) covers a contiguous chunk of column q.
+__global__ void k_col_sumsq_part(long long n, long long chunk, const double* A, double* part) {
   __shared__ double red[4];
-  const int q = blockIdx.x;
+  const int q = blockIdx.y;
+  const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
   double s = 0.0;
-  for (long long i = threadIdx.x; i < n; i += 256) {
+  for (long long i = lo + threadIdx.x; i < hi; i += 256) {
     const double v = A[i + q * n];
     s += v * v;
   }
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) part[(size_t)q * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void k_col_sumsq_final(int nparts, const double* part, double* out) {
+  __shared__ double red[4];
+  const int q = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 256) s += part[(size_t)q * nparts + i];
   s = block_sum256(s, red);
   if (threadIdx.x == 0) out[q] = s;
 }
@@ -694,6 +788,8 @@ void bgemm(hipStream_t st, int M, int N, int K, int nmat, int ncl, T alpha, cons
            const BOp& B, T beta, const BOp& C) {
   if (M <= 0 || N <= 0 || nmat <= 0 || ncl <= 0) return;
   const int nprob = nmat * ncl;
+  ProfScope ps(KC_GEMM, st, 2.0 * M * N * K * nprob,
+               (double)sizeof(T) * nprob * ((double)M * K + (double)K * N + (double)M * N * (beta != T(0) ? 2 : 1)));
   // pick the tile shape with the least padded area (bigger tiles preferred)
   struct Cfg { int tm, tn; double eff; };
   const Cfg cfgs[] = {{64, 64, 1.0}, {64, 16, 0.8}, {16, 64, 0.8}, {32, 32, 0.8}, {16, 16, 0.55}};
@@ -718,6 +814,13 @@ template <typename Tin, typename Tout>
 void binverse(hipStream_t st, int n, int nprob, const Tin* A, long long sA, Tout* X, long long sX,
               int* status) {
   if (n <= 0 || nprob <= 0) return;
+  ProfScope ps(KC_INVERSE, st, 2.0 * n * n * n * nprob, 2.0 * n * n * nprob * sizeof(Tin));
+  if (n <= 88) {   // in place: n*n doubles of LDS (+1.6 KB static) within 64 KB
+    hipLaunchKernelGGL((k_inverse_lds<Tin, Tout>), dim3(nprob), dim3(256), (size_t)n * n * sizeof(double),
+                       st, n, A, sA, X, sX, status);
+    ACR_CHECK_LAUNCH();
+    return;
+  }
   const size_t lds = (size_t)n * 2 * n * sizeof(double);
   const bool use_lds = lds + 2048 <= kMaxLds;
   DBuf<double> ws;
@@ -731,6 +834,10 @@ template <typename T>
 void bqr_r(hipStream_t st, int p, int k, int nmat, int ncl, const BOp& A, T* R, T* Vref, T* tau) {
   if (p <= 0 || k <= 0 || nmat <= 0) return;
   const int nprob = nmat * ncl;
+  const double kr = std::min(p, k);
+  ProfScope ps(KC_QR, st,
+               nprob * (p >= k ? 2.0 * k * k * (p - k / 3.0) : 2.0 * p * p * (k - p / 3.0)),
+               (double)sizeof(T) * nprob * ((double)p * k + kr * k + (Vref ? (double)p * kr : 0.0)));
   const size_t panel = (size_t)p * k * sizeof(T);
   const size_t vbytes = (size_t)p * sizeof(T);
   const bool use_lds = panel + vbytes + 1024 <= kMaxLds;
@@ -745,6 +852,8 @@ template <typename T>
 void bapply_q(hipStream_t st, int p, int c, int t, int nmat, int ncl, const T* Vref, const T* tau,
               const T* Z, long long sZ, int zxor, const BOp& Y) {
   if (p <= 0 || t <= 0 || nmat <= 0) return;
+  ProfScope ps(KC_APPLYQ, st, 4.0 * nmat * ncl * t * ((double)p * c - 0.5 * c * c),
+               (double)sizeof(T) * nmat * ncl * ((double)p * c + (double)c * t + (double)p * t));
   hipLaunchKernelGGL((k_apply_q<T>), dim3(nmat * ncl), dim3(256), 0, st, p, c, t, ncl, Vref, tau, Z,
                      sZ, zxor, Y);
   ACR_CHECK_LAUNCH();
@@ -756,8 +865,17 @@ void bsvd(hipStream_t st, int c, int nprob, T* K, T* sig, T* Usc, T* J, int* ran
   if (c <= 0 || nprob <= 0) return;
   if (c > 512) fail(ACR_ERR_INVALID_ARG, "bsvd: core larger than 512");
   DBuf<T> Jw((size_t)nprob * c * c);
+  int* sweeps = nullptr;
+  Profiler& P = Profiler::get();
+  if (P.on(KC_SVD)) {
+    std::lock_guard<std::mutex> g(P.mu());
+    P.owned().emplace_back((size_t)nprob);
+    sweeps = P.owned().back().get();
+  }
+  ProfScope ps(KC_SVD, st, 0.0, 3.0 * (double)c * c * nprob * sizeof(T));
+  ps.r.dev_sweeps = sweeps; ps.r.nprob = nprob; ps.r.c = c;
   hipLaunchKernelGGL((k_svd<T>), dim3(nprob), dim3(256), 0, st, c, K, Jw.get(), sig, Usc, J, rank,
-                     eps, maxrank);
+                     eps, maxrank, sweeps);
   ACR_CHECK_LAUNCH();
 }
 
@@ -777,6 +895,7 @@ void bmax_int(hipStream_t st, const int* rank, int n, int* out) {
 template <typename T>
 void bcopy(hipStream_t st, int rows, int cols, int nmat, T alpha, const BOp& src, const BOp& dst) {
   if (rows <= 0 || cols <= 0 || nmat <= 0) return;
+  ProfScope ps(KC_COPY, st, 0.0, 2.0 * rows * cols * nmat * sizeof(T));
   dim3 g(grid1((long long)rows * cols, 256, 1024), nmat);
   hipLaunchKernelGGL((k_bcopy<T>), g, dim3(256), 0, st, rows, cols, alpha, src, dst, 0);
   ACR_CHECK_LAUNCH();
@@ -785,6 +904,7 @@ void bcopy(hipStream_t st, int rows, int cols, int nmat, T alpha, const BOp& src
 template <typename T>
 void badd(hipStream_t st, int rows, int cols, int nmat, T alpha, const BOp& src, const BOp& dst) {
   if (rows <= 0 || cols <= 0 || nmat <= 0) return;
+  ProfScope ps(KC_COPY, st, (double)rows * cols * nmat, 3.0 * rows * cols * nmat * sizeof(T));
   dim3 g(grid1((long long)rows * cols, 256, 1024), nmat);
   hipLaunchKernelGGL((k_bcopy<T>), g, dim3(256), 0, st, rows, cols, alpha, src, dst, 1);
   ACR_CHECK_LAUNCH();
@@ -801,6 +921,7 @@ template <typename T>
 void bscale(hipStream_t st, int rows, int cols, int nmat, int ncl, const BOp& X, const T* vec,
             int vmul, int voff, long long vstride, long long vcl, int side, T alpha) {
   if (rows <= 0 || cols <= 0 || nmat <= 0) return;
+  ProfScope ps(KC_COPY, st, (double)rows * cols * nmat * ncl, 2.0 * rows * cols * nmat * ncl * sizeof(T));
   dim3 g(grid1((long long)rows * cols, 256, 256), nmat * ncl);
   hipLaunchKernelGGL((k_bscale<T>), g, dim3(256), 0, st, rows, cols, ncl, X, vec, vmul, voff,
                      vstride, vcl, side, alpha);
@@ -846,6 +967,7 @@ template <typename T>
 void to_blocks(hipStream_t st, int s, int nblk, int nrhs, const double* B, long long ld, T* V) {
   const long long n = (long long)s * nblk * nrhs;
   if (n <= 0) return;
+  ProfScope ps(KC_OTHER, st, 0.0, (double)n * (8 + sizeof(T)));
   hipLaunchKernelGGL((k_to_blocks<T>), dim3(grid1(n, 256, 16384)), dim3(256), 0, st, s, nblk, nrhs,
                      B, ld, V);
   ACR_CHECK_LAUNCH();
@@ -855,6 +977,7 @@ template <typename T>
 void from_blocks(hipStream_t st, int s, int nblk, int nrhs, const T* V, double* B, long long ld) {
   const long long n = (long long)s * nblk * nrhs;
   if (n <= 0) return;
+  ProfScope ps(KC_OTHER, st, 0.0, (double)n * (8 + sizeof(T)));
   hipLaunchKernelGGL((k_from_blocks<T>), dim3(grid1(n, 256, 16384)), dim3(256), 0, st, s, nblk,
                      nrhs, V, B, ld);
   ACR_CHECK_LAUNCH();
@@ -864,6 +987,7 @@ template <typename T>
 void bdiag_axpy(hipStream_t st, int s, int nrhs, int nmat, T alpha, const T* d, int dmul, int doff,
                 const T* x, int xmul, int xoff, T* y, int ymul, int yoff) {
   if (nmat <= 0) return;
+  ProfScope ps(KC_MATVEC, st, 2.0 * s * nrhs * nmat, (double)sizeof(T) * nmat * (3.0 * s * nrhs + s));
   dim3 g(grid1((long long)s * nrhs, 256, 256), nmat);
   hipLaunchKernelGGL((k_bdiag_axpy<T>), g, dim3(256), 0, st, s, nrhs, alpha, d, dmul, doff, x, xmul,
                      xoff, y, ymul, yoff);
@@ -874,6 +998,7 @@ void stencil_residual(hipStream_t st, int nx, int ny, int nrhs, const double* di
                       const double* west, const double* east, const double* south,
                       const double* north, const double* X, const double* B, double* R) {
   const long long N = (long long)nx * ny;
+  ProfScope ps(KC_OTHER, st, 10.0 * N * nrhs, 8.0 * N * (5.0 + 3.0 * nrhs));
   dim3 g(grid1(N, 256, 8192), nrhs);
   hipLaunchKernelGGL(k_residual, g, dim3(256), 0, st, nx, ny, diag, west, east, south, north, X, B,
                      R);
@@ -881,7 +1006,12 @@ void stencil_residual(hipStream_t st, int nx, int ny, int nrhs, const double* di
 }
 
 void col_sumsq(hipStream_t st, long long n, int ncol, const double* A, double* out) {
-  hipLaunchKernelGGL(k_col_sumsq, dim3(ncol), dim3(256), 0, st, n, A, out);
+  const int nparts = (int)std::min<long long>(512, std::max<long long>(1, (n + 4095) / 4096));
+  const long long chunk = (n + nparts - 1) / nparts;
+  DBuf<double> part((size_t)nparts * ncol);
+  hipLaunchKernelGGL(k_col_sumsq_part, dim3(nparts, ncol), dim3(256), 0, st, n, chunk, A, part.get());
+  ACR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_col_sumsq_final, dim3(ncol), dim3(256), 0, st, nparts, part.get(), out);
   ACR_CHECK_LAUNCH();
 }
 
