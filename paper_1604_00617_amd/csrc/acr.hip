@@ -298,56 +298,76 @@ std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_option
     stage_check(st, D, status.get(), "D", (int)f->lev.size());
     hinv<T>(st, lv.X, HV<T>{&D, 2, 0}, lv.nreal, status.get());
     stage_check(st, lv.X, status.get(), "inv", (int)f->lev.size());
-    recompress<T>(st, lv.X, eps, mr);
+    recompress_multi<T>(st, {&lv.X}, eps, mr);
     stage_check(st, lv.X, status.get(), "X", (int)f->lev.size());
     HSet<T> P, Q;
     HSet<T> Dn, En, Fn;
     if (diag) {
-      hscale_cols<T>(st, P, lv.ne, HV<T>{&lv.X, 1, 0}, e0.get(), 2, 0, lv.nreal);
-      hscale_cols<T>(st, Q, lv.ne, HV<T>{&lv.X, 1, 0}, f0.get(), 2, 0, lv.nreal);
-      recompress<T>(st, P, eps, mr);
-      recompress<T>(st, Q, eps, mr);
-      // D'_j = D_i - diag(e_i) Q_j - diag(f_i) P_(j+1)
-      std::vector<STerm<T>> terms(3);
+      // P_k = X_k diag(e_2k), Q_k = X_k diag(f_2k)
+      std::vector<ColScale<T>> cs(2);
+      cs[0].C = &P; cs[0].cnt_alloc = lv.ne; cs[0].nmat = lv.nreal; cs[0].H = HV<T>{&lv.X, 1, 0};
+      cs[0].cols = e0.get(); cs[0].cmul = 2; cs[0].coff = 0;
+      cs[1] = cs[0];
+      cs[1].C = &Q; cs[1].cols = f0.get();
+      hscale_cols_multi<T>(st, cs);
+      recompress_multi<T>(st, {&P, &Q}, eps, mr);
+      // D'_j = D_i - diag(e_i) Q_j - diag(f_i) P_(j+1);  E'_j = -diag(e_i) P_j;  F'_j = -diag(f_i) Q_(j+1)
+      std::vector<ScaleTerm<T>> terms(3);
       terms[0].h = HV<T>{&D, 2, 1};
-      terms[1].h = HV<T>{&Q, 1, 0}; terms[1].coef = T(-1); terms[1].rows = e0.get(); terms[1].rmul = 2; terms[1].roff = 1;
-      terms[2].h = HV<T>{&P, 1, 1}; terms[2].coef = T(-1); terms[2].rows = f0.get(); terms[2].rmul = 2; terms[2].roff = 1;
+      terms[1].h = HV<T>{&Q, 1, 0}; terms[1].coef = -1.0; terms[1].rows = e0.get(); terms[1].rmul = 2; terms[1].roff = 1;
+      terms[2].h = HV<T>{&P, 1, 1}; terms[2].coef = -1.0; terms[2].rows = f0.get(); terms[2].rmul = 2; terms[2].roff = 1;
       hstack<T>(st, Dn, nodd, terms, nodd);
-      std::vector<STerm<T>> te(1), tf(1);
-      te[0].h = HV<T>{&P, 1, 0}; te[0].coef = T(-1); te[0].rows = e0.get(); te[0].rmul = 2; te[0].roff = 1;
-      tf[0].h = HV<T>{&Q, 1, 1}; tf[0].coef = T(-1); tf[0].rows = f0.get(); tf[0].rmul = 2; tf[0].roff = 1;
+      std::vector<ScaleTerm<T>> te(1), tf(1);
+      te[0].h = HV<T>{&P, 1, 0}; te[0].coef = -1.0; te[0].rows = e0.get(); te[0].rmul = 2; te[0].roff = 1;
+      tf[0].h = HV<T>{&Q, 1, 1}; tf[0].coef = -1.0; tf[0].rows = f0.get(); tf[0].rmul = 2; tf[0].roff = 1;
       hstack<T>(st, En, nodd, te, nodd);
       hstack<T>(st, Fn, nodd, tf, nodd);
       lv.e0 = std::move(e0);
       lv.f0 = std::move(f0);
     } else {
-      hprod<T>(st, P, lv.ne, HV<T>{&lv.X, 1, 0}, HV<T>{&E, 2, 0}, lv.nreal, T(1));
-      hprod<T>(st, Q, lv.ne, HV<T>{&lv.X, 1, 0}, HV<T>{&F, 2, 0}, lv.nreal, T(1));
-      recompress<T>(st, P, eps, mr);
-      recompress<T>(st, Q, eps, mr);
+      // P_k = X_k E_2k, Q_k = X_k F_2k
+      std::vector<POut<T>> pq(2);
+      pq[0].C = &P; pq[0].cnt_alloc = lv.ne; pq[0].nmat = lv.nreal;
+      pq[0].terms = {PTerm<T>{1.0, HV<T>{&lv.X, 1, 0}, HV<T>{&E, 2, 0}}};
+      pq[1].C = &Q; pq[1].cnt_alloc = lv.ne; pq[1].nmat = lv.nreal;
+      pq[1].terms = {PTerm<T>{1.0, HV<T>{&lv.X, 1, 0}, HV<T>{&F, 2, 0}}};
+      hprod_multi<T>(st, pq);
+      recompress_multi<T>(st, {&P, &Q}, eps, mr);
+      std::vector<POut<T>> up(3);
+      up[1].C = &En; up[1].cnt_alloc = nodd; up[1].nmat = nodd;
+      up[1].terms = {PTerm<T>{-1.0, HV<T>{&E, 2, 1}, HV<T>{&P, 1, 0}}};
+      up[2].C = &Fn; up[2].cnt_alloc = nodd; up[2].nmat = nodd;
+      up[2].terms = {PTerm<T>{-1.0, HV<T>{&F, 2, 1}, HV<T>{&Q, 1, 1}}};
       HSet<T> EQ, FP;
-      hprod<T>(st, EQ, nodd, HV<T>{&E, 2, 1}, HV<T>{&Q, 1, 0}, nodd, T(1));
-      hprod<T>(st, FP, nodd, HV<T>{&F, 2, 1}, HV<T>{&P, 1, 1}, nodd, T(1));
       if (ieps > 0) {
-        recompress<T>(st, EQ, ieps, 0);
-        recompress<T>(st, FP, ieps, 0);
+        // intermediate truncation of the two Schur products, then the sum
+        up[0].C = &EQ; up[0].cnt_alloc = nodd; up[0].nmat = nodd;
+        up[0].terms = {PTerm<T>{1.0, HV<T>{&E, 2, 1}, HV<T>{&Q, 1, 0}}};
+        up.push_back(POut<T>());
+        up[3].C = &FP; up[3].cnt_alloc = nodd; up[3].nmat = nodd;
+        up[3].terms = {PTerm<T>{1.0, HV<T>{&F, 2, 1}, HV<T>{&P, 1, 1}}};
+        hprod_multi<T>(st, up);
+        recompress_multi<T>(st, {&EQ, &FP}, ieps, 0);
+        std::vector<ScaleTerm<T>> terms(3);
+        terms[0].h = HV<T>{&D, 2, 1};
+        terms[1].h = HV<T>{&EQ, 1, 0}; terms[1].coef = -1.0;
+        terms[2].h = HV<T>{&FP, 1, 0}; terms[2].coef = -1.0;
+        hstack<T>(st, Dn, nodd, terms, nodd);
+      } else {
+        // D'_j = D_i - E_i Q_j - F_i P_(j+1), accumulated exactly, one truncation
+        up[0].C = &Dn; up[0].cnt_alloc = nodd; up[0].nmat = nodd;
+        up[0].has_d = true; up[0].D = HV<T>{&D, 2, 1};
+        up[0].terms = {PTerm<T>{-1.0, HV<T>{&E, 2, 1}, HV<T>{&Q, 1, 0}},
+                       PTerm<T>{-1.0, HV<T>{&F, 2, 1}, HV<T>{&P, 1, 1}}};
+        hprod_multi<T>(st, up);
       }
-      std::vector<STerm<T>> terms(3);
-      terms[0].h = HV<T>{&D, 2, 1};
-      terms[1].h = HV<T>{&EQ, 1, 0}; terms[1].coef = T(-1);
-      terms[2].h = HV<T>{&FP, 1, 0}; terms[2].coef = T(-1);
-      hstack<T>(st, Dn, nodd, terms, nodd);
-      hprod<T>(st, En, nodd, HV<T>{&E, 2, 1}, HV<T>{&P, 1, 0}, nodd, T(-1));
-      hprod<T>(st, Fn, nodd, HV<T>{&F, 2, 1}, HV<T>{&Q, 1, 1}, nodd, T(-1));
       lv.E = std::move(E);
       lv.F = std::move(F);
     }
     stage_check(st, P, status.get(), "P", (int)f->lev.size());
     stage_check(st, Q, status.get(), "Q", (int)f->lev.size());
     stage_check(st, Dn, status.get(), "D'-exact", (int)f->lev.size());
-    recompress<T>(st, Dn, eps, mr);
-    recompress<T>(st, En, eps, mr);
-    recompress<T>(st, Fn, eps, mr);
+    recompress_multi<T>(st, {&Dn, &En, &Fn}, eps, mr);
     stage_check(st, Dn, status.get(), "D'", (int)f->lev.size());
     stage_check(st, En, status.get(), "E'", (int)f->lev.size());
     stage_check(st, Fn, status.get(), "F'", (int)f->lev.size());
@@ -363,7 +383,7 @@ std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_option
     diag = false;
   }
   hinv<T>(st, f->Xlast, HV<T>{&D, 1, 0}, 1, status.get());
-  recompress<T>(st, f->Xlast, eps, mr);
+  recompress_multi<T>(st, {&f->Xlast}, eps, mr);
   int bad = 0;
   ACR_HIP(hipMemcpyAsync(&bad, status.get(), sizeof(int), hipMemcpyDeviceToHost, st));
   ACR_HIP(hipStreamSynchronize(st));
@@ -554,6 +574,11 @@ acr_status acr_profile_read(int32_t cls, int64_t* launches, double* total_ms, do
       ms += e;
       by += r.bytes;
       fl += r.flops;
+      if (r.dev_flops) {
+        std::vector<double> f(r.nprob);
+        ACR_HIP(hipMemcpy(f.data(), r.dev_flops, r.nprob * sizeof(double), hipMemcpyDeviceToHost));
+        for (double v : f) fl += v;
+      }
       if (r.dev_sweeps) {
         std::vector<int> sw(r.nprob);
         ACR_HIP(hipMemcpy(sw.data(), r.dev_sweeps, r.nprob * sizeof(int), hipMemcpyDeviceToHost));

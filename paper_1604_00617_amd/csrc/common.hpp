@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <stdexcept>
@@ -156,6 +157,7 @@ class Profiler {
     double flops, bytes;
     const int* dev_sweeps;   // SVD: per-problem sweep counts (flops filled at read time)
     int nprob, c;
+    const double* dev_flops; // per-problem flops counted on the device
   };
   static Profiler& get() {
     static Profiler p;
@@ -167,6 +169,7 @@ class Profiler {
     for (auto& r : recs_) { pool_.push_back(r.a); pool_.push_back(r.b); }
     recs_.clear();
     owned_.clear();
+    owned_d_.clear();
     mask_ = mask;
   }
   hipEvent_t event() {
@@ -179,6 +182,7 @@ class Profiler {
   std::mutex& mu() { return mu_; }
   std::vector<Rec>& recs() { return recs_; }
   std::vector<DBuf<int>>& owned() { return owned_; }
+  std::vector<DBuf<double>>& owned_d() { return owned_d_; }
 
  private:
   unsigned mask_ = 0;
@@ -186,6 +190,7 @@ class Profiler {
   std::vector<Rec> recs_;
   std::vector<hipEvent_t> pool_;
   std::vector<DBuf<int>> owned_;
+  std::vector<DBuf<double>> owned_d_;
 };
 
 struct ProfScope {
@@ -198,7 +203,7 @@ struct ProfScope {
     act = true;
     st = s;
     std::lock_guard<std::mutex> g(P.mu());
-    r.cls = cls; r.flops = flops; r.bytes = bytes; r.dev_sweeps = nullptr;
+    r.cls = cls; r.flops = flops; r.bytes = bytes; r.dev_sweeps = nullptr; r.dev_flops = nullptr;
     r.a = P.event(); r.b = P.event();
     ACR_HIP(hipEventRecord(r.a, st));
   }
@@ -211,9 +216,9 @@ struct ProfScope {
 
 // -------------------------------------------------- batched operand views
 // One operand of a batched operation over problems p = (m, c): matrix index
-// m (0..nmat-1) and cluster index c (0..ncl-1).  The operand of problem p
-// starts at
-//   base + (mmul*m + moff)*sm + ((c^cxor) >> 1)*sc_pair + ((c^cxor) & 1)*sc_odd
+// m (0..nmat-1) and cluster index c (0..ncl-1).  With cc = (c >> cshift) ^ cxor
+// the operand of problem p starts at
+//   base + (mmul*m + moff)*sm + (cc >> 1)*sc_pair + (cc & 1)*sc_odd
 // and is column-major with leading dimension ld (transposed if trans).
 struct BOp {
   const void* p = nullptr;
@@ -223,6 +228,7 @@ struct BOp {
   long long sm = 0;
   long long sc_pair = 0, sc_odd = 0;
   int cxor = 0;
+  int cshift = 0;   // cluster used = ((c >> cshift) ^ cxor)
 };
 
 // Uniform cluster stride helper: operand of cluster c at base + c*sc.
@@ -233,6 +239,49 @@ inline BOp bop(const void* p, int ld, long long sm, long long sc = 0, int trans 
 }
 inline BOp with_map(BOp o, int mmul, int moff) { o.mmul = mmul; o.moff = moff; return o; }
 inline BOp swapped(BOp o) { o.cxor = 1; return o; }
+inline BOp ancestor(BOp o, int shift, int x) { o.cshift = shift; o.cxor = x; return o; }
 inline BOp transposed(BOp o) { o.trans = 1; return o; }
+
+// ------------------------------------------------------- descriptor arena
+// Job descriptors of grouped launches: written to pinned host memory and
+// copied to a device buffer on the launch stream just before the kernel that
+// reads them.  The arena is recycled only after the stream has been
+// synchronised (reset() is called at those points).
+class DescArena {
+ public:
+  static DescArena& get() {
+    static DescArena a;
+    return a;
+  }
+  // Copy `bytes` of host data into the arena and enqueue its upload on st;
+  // returns the device address.
+  void* put(const void* data, size_t bytes, hipStream_t st) {
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (off_ + need > cap_) {
+      ACR_HIP(hipStreamSynchronize(st));
+      off_ = 0;
+      if (need > cap_) grow(need * 2);
+    }
+    std::memcpy(host_ + off_, data, bytes);
+    ACR_HIP(hipMemcpyAsync(dev_ + off_, host_ + off_, bytes, hipMemcpyHostToDevice, st));
+    void* d = dev_ + off_;
+    off_ += need;
+    return d;
+  }
+  void reset() { off_ = 0; }   // only after the stream that used it is synchronised
+
+ private:
+  DescArena() { grow(size_t(8) << 20); }
+  void grow(size_t cap) {
+    if (host_) { (void)hipHostFree(host_); (void)hipFree(dev_); }
+    ACR_HIP(hipHostMalloc((void**)&host_, cap, hipHostMallocDefault));
+    ACR_HIP(hipMalloc((void**)&dev_, cap));
+    cap_ = cap;
+    off_ = 0;
+  }
+  char* host_ = nullptr;
+  char* dev_ = nullptr;
+  size_t cap_ = 0, off_ = 0;
+};
 
 }  // namespace acr

@@ -1,10 +1,10 @@
-// H-arithmetic on batched HODLR sets: every operation is a short sequence of
-// batched launches over (matrix, cluster) problems of one depth.
+// H-arithmetic on batched HODLR sets, planned as grouped launches: every
+// operation below collects the independent batched problems of all clusters,
+// depths and operands it needs into a few job lists and launches each list
+// once (see kernels.hpp for the job kinds).
 #include "hodlr.hpp"
 
 #include <algorithm>
-
-#include "kernels.hpp"
 
 namespace acr {
 
@@ -51,6 +51,7 @@ int HSet<T>::max_rank() const {
   return r;
 }
 
+// ------------------------------------------------------------- operands
 namespace {
 
 template <typename T>
@@ -67,146 +68,224 @@ BOp factor_op(HV<T> H, const DBuf<T>& F, int d, long long sc) {
 }
 
 template <typename T>
-BOp flat_op(const Flat<T>& f, long long sc, int col0 = 0) {
-  BOp o = bop(f.p + (long long)col0 * f.ld, f.ld, f.sm, sc);
-  return with_map(o, f.mmul, f.moff);
-}
-
-template <typename T>
-Flat<T> flat_of(const HSet<T>& H, const DBuf<T>& F, int d, int col0 = 0) {
+Flat<T> flat_set(HV<T> H, const DBuf<T>& F, int d) {
   Flat<T> f;
-  f.p = F.get() + (size_t)col0 * H.s;
-  f.ld = H.s;
-  f.sm = (long long)H.k[d] * H.s;
+  f.p = F.get();
+  f.ld = H.h->s;
+  f.sm = (long long)H.h->k[d] * H.h->s;
+  f.mmul = H.mmul;
+  f.moff = H.moff;
   return f;
 }
 
-template <typename T>
-void count_gemm(long long M, long long N, long long K, long long nprob) {
-  work().gemm_flops += 2.0 * M * N * K * nprob;
+GSeg seg(const BOp& A, const BOp& B, int K, double scale = 1.0) {
+  GSeg g;
+  g.A = A; g.B = B; g.K = K; g.scale = scale;
+  return g;
+}
+
+CJob copy_job(int rows, int cols, int nmat, double alpha, const BOp& src, const BOp& dst,
+              int ncl = 1, int accumulate = 0) {
+  CJob J;
+  J.rows = rows; J.cols = cols; J.nmat = nmat; J.ncl = ncl; J.alpha = alpha;
+  J.src = src; J.dst = dst; J.accumulate = accumulate;
+  return J;
 }
 
 }  // namespace
 
+template <typename T>
+BOp flat_op(const Flat<T>& f, long long sc, int col0) {
+  BOp o = bop(f.p + (long long)col0 * f.ld, f.ld, f.sm, sc);
+  return with_map(o, f.mmul, f.moff);
+}
+
+// ------------------------------------------------------------- GemmPlan
+void GemmPlan::add(int M, int N, int nmat, int ncl, double alpha, double beta, const BOp& C,
+                   const std::vector<GSeg>& sg) {
+  if (M <= 0 || N <= 0 || nmat <= 0 || ncl <= 0 || sg.empty()) return;
+  if ((int)sg.size() > kMaxSeg) fail(ACR_ERR_INTERNAL, "too many GEMM segments");
+  GJob J;
+  J.M = M; J.N = N; J.nmat = nmat; J.ncl = ncl; J.alpha = alpha; J.beta = beta; J.C = C;
+  J.seg0 = (int)segs.size();
+  J.nseg = (int)sg.size();
+  double K = 0;
+  for (const auto& g : sg) {
+    segs.push_back(g);
+    K += g.K;
+  }
+  work().gemm_flops += 2.0 * M * N * K * nmat * ncl;
+  jobs.push_back(J);
+}
+
+template <typename T>
+void GemmPlan::run(hipStream_t st) {
+  if (!jobs.empty()) ggemm<T>(st, jobs, segs);
+  jobs.clear();
+  segs.clear();
+}
+
 // ------------------------------------------------------------------- hmul
 template <typename T>
-void hmul(hipStream_t st, HV<T> H, int nmat, int dfrom, bool trans, int ncol, T alpha, Flat<T> Y,
-          T beta, Flat<T> out) {
+std::vector<GSeg> plan_hmul(GemmPlan& red, std::vector<DBuf<T>>& keep, HV<T> H, int nmat,
+                            int dfrom, bool trans, int ncol, double alpha, Flat<T> Y) {
   const HSet<T>& h = *H.h;
-  if (nmat <= 0 || ncol <= 0) return;
-  const int b = h.b;
-  // dense leaves
+  const int b = h.b, L = h.L;
+  std::vector<GSeg> out;
   BOp A = leaves_op(H);
   A.trans = trans ? 1 : 0;
-  bgemm<T>(st, b, ncol, b, nmat, h.nleaf(), alpha, A, flat_op(Y, b), beta, flat_op(out, b));
-  count_gemm<T>(b, ncol, b, (long long)nmat * h.nleaf());
-  for (int d = std::max(dfrom + 1, 1); d <= h.L; ++d) {
+  out.push_back(seg(A, flat_op(Y, b), b, alpha));
+  for (int d = std::max(dfrom + 1, 1); d <= L; ++d) {
     const int w = h.kc[d];
     if (w == 0) continue;
     const int ncl = 1 << d, sd = h.sd(d);
-    DBuf<T> tmp((size_t)nmat * ncl * w * ncol);
-    // tmp_c = (V or U)[rows c]^T Y[rows c]
-    BOp Ain = factor_op(H, trans ? h.U[d] : h.V[d], d, sd);
-    Ain.trans = 1;
-    BOp Tc = bop(tmp.get(), w, (long long)ncl * w * ncol, (long long)w * ncol);
-    bgemm<T>(st, w, ncol, sd, nmat, ncl, T(1), Ain, flat_op(Y, sd), T(0), Tc);
-    // out[rows c] += alpha * (U or V)[rows c] tmp_(sib c)
-    BOp Aout = factor_op(H, trans ? h.V[d] : h.U[d], d, sd);
-    bgemm<T>(st, sd, ncol, w, nmat, ncl, alpha, Aout, swapped(Tc), T(1), flat_op(out, sd));
-    count_gemm<T>(2LL * sd, ncol, w, (long long)nmat * ncl);
+    keep.emplace_back((size_t)nmat * ncl * w * ncol);
+    // T_d[c] = F_d[rows c]^T Y[rows c]   (F = V, or U for the transpose)
+    BOp Tc = bop(keep.back().get(), w, (long long)ncl * w * ncol, (long long)w * ncol);
+    red.add(w, ncol, nmat, ncl, 1.0, 0.0, Tc,
+            {seg(transposed(factor_op(H, trans ? h.U[d] : h.V[d], d, sd)), flat_op(Y, sd), sd)});
+    // rows of leaf l: G_d[rows l] T_d[sibling of the depth-d ancestor of l]
+    out.push_back(seg(factor_op(H, trans ? h.V[d] : h.U[d], d, b), ancestor(Tc, L - d, 1), w, alpha));
   }
+  return out;
 }
 
-// ------------------------------------------------------------------ hprod
 template <typename T>
-void hprod(hipStream_t st, HSet<T>& C, int cnt_alloc, HV<T> A, HV<T> B, int nmat, T alpha) {
-  const HSet<T>& a = *A.h;
-  const HSet<T>& bb = *B.h;
-  const int L = a.L, s = a.s, b = a.b;
-  const int nleaf = a.nleaf();
-  // Ancestor terms: for depth d'' the block A[p, q] B[q, p] (q = sib p) is
-  // U^A_p (V^A_p^T U^B_q) V^B_q^T; it restricts to every block below p.
-  // Stored as (Upart, Vpart) flat pairs of width min(kA, kB).
-  std::vector<int> wanc(L + 1, 0);
-  std::vector<DBuf<T>> Up(L + 1), Vp(L + 1);
-  std::vector<const T*> Upp(L + 1, nullptr), Vpp(L + 1, nullptr);
-  std::vector<long long> Ups(L + 1, 0), Vps(L + 1, 0);
-  std::vector<int> Upm(L + 1, 1), Upo(L + 1, 0), Vpm(L + 1, 1), Vpo(L + 1, 0);
-  for (int d = 1; d <= L; ++d) {
-    const int kA = a.kc[d], kB = bb.kc[d];
-    if (kA == 0 || kB == 0) continue;
-    const int ncl = 1 << d, sd = a.sd(d);
-    DBuf<T> W((size_t)nmat * ncl * kA * kB);
-    BOp Wc = bop(W.get(), kA, (long long)ncl * kA * kB, (long long)kA * kB);
-    bgemm<T>(st, kA, kB, sd, nmat, ncl, T(1), transposed(factor_op(A, a.V[d], d, sd)),
-             factor_op(B, bb.U[d], d, sd), T(0), Wc);
-    count_gemm<T>(kA, kB, sd, (long long)nmat * ncl);
-    if (kB <= kA) {
-      // Upart = U^A (.) W_(sib), Vpart = V^B
-      wanc[d] = kB;
-      Up[d].resize((size_t)nmat * kB * s);
-      BOp Z = bop(Up[d].get(), s, (long long)kB * s, sd);
-      bgemm<T>(st, sd, kB, kA, nmat, ncl, T(1), factor_op(A, a.U[d], d, sd), swapped(Wc), T(0), Z);
-      count_gemm<T>(sd, kB, kA, (long long)nmat * ncl);
-      Upp[d] = Up[d].get(); Ups[d] = (long long)kB * s; Upm[d] = 1; Upo[d] = 0;
-      Vpp[d] = bb.V[d].get(); Vps[d] = (long long)bb.k[d] * s; Vpm[d] = B.mmul; Vpo[d] = B.moff;
-    } else {
-      // Upart = U^A, Vpart = V^B (.) W_(sib)^T
-      wanc[d] = kA;
-      Vp[d].resize((size_t)nmat * kA * s);
-      BOp Z = bop(Vp[d].get(), s, (long long)kA * s, sd);
-      bgemm<T>(st, sd, kA, kB, nmat, ncl, T(1), factor_op(B, bb.V[d], d, sd),
-               transposed(swapped(Wc)), T(0), Z);
-      count_gemm<T>(sd, kA, kB, (long long)nmat * ncl);
-      Upp[d] = a.U[d].get(); Ups[d] = (long long)a.k[d] * s; Upm[d] = A.mmul; Upo[d] = A.moff;
-      Vpp[d] = Vp[d].get(); Vps[d] = (long long)kA * s; Vpm[d] = 1; Vpo[d] = 0;
+void hmul(hipStream_t st, HV<T> H, int nmat, int dfrom, bool trans, int ncol, T alpha, Flat<T> Y,
+          T beta, Flat<T> out) {
+  if (nmat <= 0 || ncol <= 0) return;
+  GemmPlan red, exp;
+  std::vector<DBuf<T>> keep;
+  auto sg = plan_hmul<T>(red, keep, H, nmat, dfrom, trans, ncol, (double)alpha, Y);
+  exp.add(H.h->b, ncol, nmat, H.h->nleaf(), 1.0, (double)beta, flat_op(out, H.h->b), sg);
+  red.run<T>(st);
+  exp.run<T>(st);
+}
+
+// ------------------------------------------------------------ hprod_multi
+template <typename T>
+void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
+  GemmPlan s1, s2, s3;
+  std::vector<CJob> copies;
+  std::vector<DBuf<T>> keep;
+  struct Anc {
+    int w = 0;
+    const T* up = nullptr;
+    long long ups = 0;
+    int upm = 1, upo = 0;
+    const T* vp = nullptr;
+    long long vps = 0;
+    int vpm = 1, vpo = 0;
+  };
+  for (auto& O : outs) {
+    const int nmat = O.nmat;
+    const HSet<T>& g = O.terms.empty() ? *O.D.h : *O.terms[0].A.h;
+    const int L = g.L, s = g.s, b = g.b, nleaf = g.nleaf();
+    // Ancestor terms of each product: for depth e the block A[p, q] B[q, p]
+    // (q = sib p) is U^A_p (V^A_p^T U^B_q) V^B_q^T, restricted to every block
+    // below p; stored as a flat (Upart, Vpart) pair of width min(kA, kB).
+    std::vector<std::vector<Anc>> anc(O.terms.size(), std::vector<Anc>(L + 1));
+    for (size_t t = 0; t < O.terms.size(); ++t) {
+      const HV<T> A = O.terms[t].A, B = O.terms[t].B;
+      const HSet<T>& a = *A.h;
+      const HSet<T>& bb = *B.h;
+      for (int d = 1; d <= L; ++d) {
+        const int kA = a.kc[d], kB = bb.kc[d];
+        if (kA == 0 || kB == 0) continue;
+        const int ncl = 1 << d, sd = g.sd(d);
+        keep.emplace_back((size_t)nmat * ncl * kA * kB);
+        BOp Wc = bop(keep.back().get(), kA, (long long)ncl * kA * kB, (long long)kA * kB);
+        s1.add(kA, kB, nmat, ncl, 1.0, 0.0, Wc,
+               {seg(transposed(factor_op(A, a.V[d], d, sd)), factor_op(B, bb.U[d], d, sd), sd)});
+        Anc& an = anc[t][d];
+        if (kB <= kA) {
+          keep.emplace_back((size_t)nmat * kB * s);
+          s2.add(sd, kB, nmat, ncl, 1.0, 0.0, bop(keep.back().get(), s, (long long)kB * s, sd),
+                 {seg(factor_op(A, a.U[d], d, sd), swapped(Wc), kA)});
+          an.w = kB;
+          an.up = keep.back().get(); an.ups = (long long)kB * s; an.upm = 1; an.upo = 0;
+          an.vp = bb.V[d].get(); an.vps = (long long)bb.k[d] * s; an.vpm = B.mmul; an.vpo = B.moff;
+        } else {
+          keep.emplace_back((size_t)nmat * kA * s);
+          s2.add(sd, kA, nmat, ncl, 1.0, 0.0, bop(keep.back().get(), s, (long long)kA * s, sd),
+                 {seg(factor_op(B, bb.V[d], d, sd), transposed(swapped(Wc)), kB)});
+          an.w = kA;
+          an.up = a.U[d].get(); an.ups = (long long)a.k[d] * s; an.upm = A.mmul; an.upo = A.moff;
+          an.vp = keep.back().get(); an.vps = (long long)kA * s; an.vpm = 1; an.vpo = 0;
+        }
+      }
     }
-  }
-  std::vector<int> kC(L + 1, 0);
-  for (int d = 1; d <= L; ++d) {
-    kC[d] = a.kc[d] + bb.kc[d];
-    for (int e = 1; e < d; ++e) kC[d] += wanc[e];
-  }
-  C.alloc(st, cnt_alloc, s, b, L, kC, cnt_alloc > nmat);
-  // leaves: C_l = A_l B_l + sum over ancestors of Upart[l] Vpart[l]^T
-  bgemm<T>(st, b, b, b, nmat, nleaf, alpha, leaves_op(A), leaves_op(B), T(0),
-           bop(C.lv.get(), b, C.leaf_stride(), (long long)b * b));
-  count_gemm<T>(b, b, b, (long long)nmat * nleaf);
-  for (int e = 1; e <= L; ++e) {
-    if (!wanc[e]) continue;
-    BOp Ua = with_map(bop(Upp[e], s, Ups[e], b), Upm[e], Upo[e]);
-    BOp Va = with_map(bop(Vpp[e], s, Vps[e], b, 1), Vpm[e], Vpo[e]);
-    bgemm<T>(st, b, b, wanc[e], nmat, nleaf, alpha, Ua, Va, T(1),
-             bop(C.lv.get(), b, C.leaf_stride(), (long long)b * b));
-    count_gemm<T>(b, b, wanc[e], (long long)nmat * nleaf);
-  }
-  for (int d = 1; d <= L; ++d) {
-    int col = 0;
-    const int kA = a.kc[d], kB = bb.kc[d];
-    if (kB > 0) {   // A[t,t] B[t,s] = (Adiag U^B) V^B^T
-      Flat<T> Y; Y.p = bb.U[d].get(); Y.ld = s; Y.sm = (long long)bb.k[d] * s; Y.mmul = B.mmul; Y.moff = B.moff;
-      hmul<T>(st, A, nmat, d, false, kB, alpha, Y, T(0), flat_of(C, C.U[d], d, col));
-      bcopy<T>(st, s, kB, nmat, T(1), with_map(bop(bb.V[d].get(), s, (long long)bb.k[d] * s), B.mmul, B.moff),
-               bop(C.V[d].get() + (size_t)col * s, s, (long long)C.k[d] * s));
-      col += kB;
+    std::vector<int> kC(L + 1, 0);
+    for (int d = 1; d <= L; ++d) {
+      if (O.has_d) kC[d] += O.D.h->kc[d];
+      for (size_t t = 0; t < O.terms.size(); ++t) {
+        kC[d] += O.terms[t].A.h->kc[d] + O.terms[t].B.h->kc[d];
+        for (int e = 1; e < d; ++e) kC[d] += anc[t][e].w;
+      }
     }
-    if (kA > 0) {   // A[t,s] B[s,s] = U^A (Bdiag^T V^A)^T
-      bcopy<T>(st, s, kA, nmat, alpha, with_map(bop(a.U[d].get(), s, (long long)a.k[d] * s), A.mmul, A.moff),
-               bop(C.U[d].get() + (size_t)col * s, s, (long long)C.k[d] * s));
-      Flat<T> Y; Y.p = a.V[d].get(); Y.ld = s; Y.sm = (long long)a.k[d] * s; Y.mmul = A.mmul; Y.moff = A.moff;
-      hmul<T>(st, B, nmat, d, true, kA, T(1), Y, T(0), flat_of(C, C.V[d], d, col));
-      col += kA;
+    HSet<T>& C = *O.C;
+    C.alloc(st, O.cnt_alloc, s, b, L, kC, O.cnt_alloc > nmat);
+    for (int d = 1; d <= L; ++d) {
+      int col = 0;
+      auto cu = [&](int c0, long long sc) { return bop(C.U[d].get() + (size_t)c0 * s, s, (long long)C.k[d] * s, sc); };
+      auto cv = [&](int c0, long long sc) { return bop(C.V[d].get() + (size_t)c0 * s, s, (long long)C.k[d] * s, sc); };
+      if (O.has_d && O.D.h->kc[d]) {
+        const int w = O.D.h->kc[d];
+        copies.push_back(copy_job(s, w, nmat, 1.0, factor_op(O.D, O.D.h->U[d], d, 0), cu(col, 0)));
+        copies.push_back(copy_job(s, w, nmat, 1.0, factor_op(O.D, O.D.h->V[d], d, 0), cv(col, 0)));
+        col += w;
+      }
+      for (size_t t = 0; t < O.terms.size(); ++t) {
+        const double coef = O.terms[t].coef;
+        const HV<T> A = O.terms[t].A, B = O.terms[t].B;
+        const HSet<T>& a = *A.h;
+        const HSet<T>& bb = *B.h;
+        const int kA = a.kc[d], kB = bb.kc[d];
+        if (kB > 0) {   // A[t,t] B[t,s] = (Adiag U^B) V^B^T
+          auto sg = plan_hmul<T>(s1, keep, A, nmat, d, false, kB, coef, flat_set(B, bb.U[d], d));
+          s3.add(b, kB, nmat, nleaf, 1.0, 0.0, cu(col, b), sg);
+          copies.push_back(copy_job(s, kB, nmat, 1.0, factor_op(B, bb.V[d], d, 0), cv(col, 0)));
+          col += kB;
+        }
+        if (kA > 0) {   // A[t,s] B[s,s] = U^A (Bdiag^T V^A)^T
+          copies.push_back(copy_job(s, kA, nmat, coef, factor_op(A, a.U[d], d, 0), cu(col, 0)));
+          auto sg = plan_hmul<T>(s1, keep, B, nmat, d, true, kA, 1.0, flat_set(A, a.V[d], d));
+          s3.add(b, kA, nmat, nleaf, 1.0, 0.0, cv(col, b), sg);
+          col += kA;
+        }
+        for (int e = 1; e < d; ++e) {
+          const Anc& an = anc[t][e];
+          if (!an.w) continue;
+          copies.push_back(copy_job(s, an.w, nmat, coef, with_map(bop(an.up, s, an.ups), an.upm, an.upo), cu(col, 0)));
+          copies.push_back(copy_job(s, an.w, nmat, 1.0, with_map(bop(an.vp, s, an.vps), an.vpm, an.vpo), cv(col, 0)));
+          col += an.w;
+        }
+      }
+      C.kc[d] = col;
     }
-    for (int e = 1; e < d; ++e) {
-      if (!wanc[e]) continue;
-      bcopy<T>(st, s, wanc[e], nmat, alpha, with_map(bop(Upp[e], s, Ups[e]), Upm[e], Upo[e]),
-               bop(C.U[d].get() + (size_t)col * s, s, (long long)C.k[d] * s));
-      bcopy<T>(st, s, wanc[e], nmat, T(1), with_map(bop(Vpp[e], s, Vps[e]), Vpm[e], Vpo[e]),
-               bop(C.V[d].get() + (size_t)col * s, s, (long long)C.k[d] * s));
-      col += wanc[e];
+    // leaves: C_l = D_l + sum_t coef_t (A_l B_l + sum_e Upart_e[l] Vpart_e[l]^T)
+    std::vector<GSeg> ls;
+    for (size_t t = 0; t < O.terms.size(); ++t) {
+      const double coef = O.terms[t].coef;
+      ls.push_back(seg(leaves_op(O.terms[t].A), leaves_op(O.terms[t].B), b, coef));
+      for (int e = 1; e <= L; ++e) {
+        const Anc& an = anc[t][e];
+        if (!an.w) continue;
+        ls.push_back(seg(with_map(bop(an.up, s, an.ups, b), an.upm, an.upo),
+                         with_map(bop(an.vp, s, an.vps, b, 1), an.vpm, an.vpo), an.w, coef));
+      }
     }
-    C.kc[d] = col;
+    const BOp CL = bop(C.lv.get(), b, C.leaf_stride(), (long long)b * b);
+    if (O.has_d)
+      copies.push_back(copy_job((int)O.D.h->leaf_stride(), 1, nmat, 1.0,
+                                with_map(bop(O.D.h->lv.get(), 1, O.D.h->leaf_stride()), O.D.mmul, O.D.moff),
+                                bop(C.lv.get(), 1, C.leaf_stride())));
+    if (!ls.empty()) s3.add(b, b, nmat, nleaf, 1.0, O.has_d ? 1.0 : 0.0, CL, ls);
   }
+  s1.run<T>(st);
+  s2.run<T>(st);
+  gcopy<T>(st, copies);
+  s3.run<T>(st);
 }
 
 // ------------------------------------------------------------------- hinv
@@ -219,8 +298,9 @@ void hinv(hipStream_t st, HSet<T>& X, HV<T> M, int nmat, int* status) {
     for (int e = 1; e <= d; ++e) kX[d] += mm.kc[e];
   X.alloc(st, nmat, s, b, L, kX, false);
   // leaves: X_l = M_l^{-1}
-  bcopy<T>(st, b * nleaf * b, 1, nmat, T(1), with_map(bop(mm.lv.get(), 1, mm.leaf_stride()), M.mmul, M.moff),
-           bop(X.lv.get(), 1, X.leaf_stride()));
+  gcopy<T>(st, {copy_job((int)mm.leaf_stride(), 1, nmat, 1.0,
+                         with_map(bop(mm.lv.get(), 1, mm.leaf_stride()), M.mmul, M.moff),
+                         bop(X.lv.get(), 1, X.leaf_stride()))});
   binverse<T, T>(st, b, nmat * nleaf, X.lv.get(), (long long)b * b, X.lv.get(), (long long)b * b,
                  status);
   work().inv_flops += 2.0 * b * b * b * nmat * nleaf;
@@ -229,20 +309,25 @@ void hinv(hipStream_t st, HSet<T>& X, HV<T> M, int nmat, int* status) {
     const int k = mm.kc[d];
     if (k == 0) continue;
     const int ncl = 1 << d, sd = mm.sd(d);
+    std::vector<DBuf<T>> keep;
     DBuf<T> abuf((size_t)nmat * k * s), bbuf((size_t)nmat * k * s), wbuf((size_t)nmat * k * s);
     Flat<T> fa; fa.p = abuf.get(); fa.ld = s; fa.sm = (long long)k * s;
     Flat<T> fb; fb.p = bbuf.get(); fb.ld = s; fb.sm = (long long)k * s;
     Flat<T> fw; fw.p = wbuf.get(); fw.ld = s; fw.sm = (long long)k * s;
-    Flat<T> Um; Um.p = mm.U[d].get(); Um.ld = s; Um.sm = (long long)mm.k[d] * s; Um.mmul = M.mmul; Um.moff = M.moff;
-    Flat<T> Vm = Um; Vm.p = mm.V[d].get();
     // a = Xdiag U^M (children inverses applied), bb = Xdiag^T V^M
-    hmul<T>(st, XV, nmat, d, false, k, T(1), Um, T(0), fa);
-    hmul<T>(st, XV, nmat, d, true, k, T(1), Vm, T(0), fb);
+    GemmPlan red, exp;
+    auto sa = plan_hmul<T>(red, keep, XV, nmat, d, false, k, 1.0, flat_set(M, mm.U[d], d));
+    auto sb = plan_hmul<T>(red, keep, XV, nmat, d, true, k, 1.0, flat_set(M, mm.V[d], d));
+    exp.add(b, k, nmat, nleaf, 1.0, 0.0, flat_op(fa, b), sa);
+    exp.add(b, k, nmat, nleaf, 1.0, 0.0, flat_op(fb, b), sb);
+    red.run<T>(st);
+    exp.run<T>(st);
     // cores c_sigma = V^M[sigma]^T a[sigma]
     DBuf<T> cores((size_t)nmat * ncl * k * k);
-    bgemm<T>(st, k, k, sd, nmat, ncl, T(1), transposed(factor_op(M, mm.V[d], d, sd)), flat_op(fa, sd),
-             T(0), bop(cores.get(), k, (long long)ncl * k * k, (long long)k * k));
-    count_gemm<T>(k, k, sd, (long long)nmat * ncl);
+    GemmPlan cp;
+    cp.add(k, k, nmat, ncl, 1.0, 0.0, bop(cores.get(), k, (long long)ncl * k * k, (long long)k * k),
+           {seg(transposed(factor_op(M, mm.V[d], d, sd)), flat_op(fa, sd), sd)});
+    cp.run<T>(st);
     const int npairs = nmat * ncl / 2, n2 = 2 * k;
     DBuf<T> G((size_t)npairs * n2 * n2);
     build_capacitance<T>(st, k, npairs, cores.get(), G.get());
@@ -255,32 +340,33 @@ void hinv(hipStream_t st, HSet<T>& X, HV<T> M, int nmat, int* status) {
     BOp Go = Gd;
     Go.p = G.get() + (size_t)k * n2;              // (0,1) block for a first child
     Go.sc_odd = (long long)k - (long long)k * n2;  // (1,0) block for a second child
-    // U^X_d = -a[t] Gdiag(t), V^X_d = bb
-    bgemm<T>(st, sd, k, k, nmat, ncl, T(-1), flat_op(fa, sd), Gd, T(0),
-             bop(X.U[d].get(), s, (long long)X.k[d] * s, sd));
-    bcopy<T>(st, s, k, nmat, T(1), bop(bbuf.get(), s, (long long)k * s),
-             bop(X.V[d].get(), s, (long long)X.k[d] * s));
+    // U^X_d = -a[t] Gdiag(t);  W = a[t] Goff(t)
+    GemmPlan gp;
+    gp.add(sd, k, nmat, ncl, -1.0, 0.0, bop(X.U[d].get(), s, (long long)X.k[d] * s, sd), {seg(flat_op(fa, sd), Gd, k)});
+    gp.add(sd, k, nmat, ncl, 1.0, 0.0, flat_op(fw, sd), {seg(flat_op(fa, sd), Go, k)});
+    gp.run<T>(st);
+    // V^X_d = bb; X[t,t] -= W[t] bb[t]^T pushed to every depth below d
+    std::vector<CJob> cj;
+    cj.push_back(copy_job(s, k, nmat, 1.0, bop(bbuf.get(), s, (long long)k * s), bop(X.V[d].get(), s, (long long)X.k[d] * s)));
     X.kc[d] = k;
-    // W = a[t] Goff(t): X[t,t] -= W[t] bb[t]^T pushed below depth d
-    bgemm<T>(st, sd, k, k, nmat, ncl, T(1), flat_op(fa, sd), Go, T(0), flat_op(fw, sd));
-    count_gemm<T>(2LL * sd, k, k, (long long)nmat * ncl);
     for (int e = d + 1; e <= L; ++e) {
-      bcopy<T>(st, s, k, nmat, T(-1), bop(wbuf.get(), s, (long long)k * s),
-               bop(X.U[e].get() + (size_t)X.kc[e] * s, s, (long long)X.k[e] * s));
-      bcopy<T>(st, s, k, nmat, T(1), bop(bbuf.get(), s, (long long)k * s),
-               bop(X.V[e].get() + (size_t)X.kc[e] * s, s, (long long)X.k[e] * s));
+      cj.push_back(copy_job(s, k, nmat, -1.0, bop(wbuf.get(), s, (long long)k * s),
+                            bop(X.U[e].get() + (size_t)X.kc[e] * s, s, (long long)X.k[e] * s)));
+      cj.push_back(copy_job(s, k, nmat, 1.0, bop(bbuf.get(), s, (long long)k * s),
+                            bop(X.V[e].get() + (size_t)X.kc[e] * s, s, (long long)X.k[e] * s)));
       X.kc[e] += k;
     }
-    bgemm<T>(st, b, b, k, nmat, nleaf, T(-1), bop(wbuf.get(), s, (long long)k * s, b),
-             bop(bbuf.get(), s, (long long)k * s, b, 1), T(1),
-             bop(X.lv.get(), b, X.leaf_stride(), (long long)b * b));
-    count_gemm<T>(b, b, k, (long long)nmat * nleaf);
+    gcopy<T>(st, cj);
+    GemmPlan lp;
+    lp.add(b, b, nmat, nleaf, 1.0, 1.0, bop(X.lv.get(), b, X.leaf_stride(), (long long)b * b),
+           {seg(bop(wbuf.get(), s, (long long)k * s, b), bop(bbuf.get(), s, (long long)k * s, b, 1), k, -1.0)});
+    lp.run<T>(st);
   }
 }
 
-// ----------------------------------------------------------------- hstack
+// ------------------------------------------------------------- level 0
 template <typename T>
-void hstack(hipStream_t st, HSet<T>& C, int cnt_alloc, const std::vector<STerm<T>>& terms, int nmat) {
+void hstack(hipStream_t st, HSet<T>& C, int cnt_alloc, const std::vector<ScaleTerm<T>>& terms, int nmat) {
   const HSet<T>& h0 = *terms[0].h.h;
   const int L = h0.L, s = h0.s, b = h0.b;
   std::vector<int> kC(L + 1, 0);
@@ -288,130 +374,171 @@ void hstack(hipStream_t st, HSet<T>& C, int cnt_alloc, const std::vector<STerm<T
     for (int d = 1; d <= L; ++d) kC[d] += t.h.h->kc[d];
   C.alloc(st, cnt_alloc, s, b, L, kC, cnt_alloc > nmat);
   const long long ls = C.leaf_stride();
-  bool first = true;
+  std::vector<CJob> first;
+  std::vector<std::vector<CJob>> rest;
   std::vector<int> col(L + 1, 0);
-  for (const auto& t : terms) {
+  for (size_t ti = 0; ti < terms.size(); ++ti) {
+    const auto& t = terms[ti];
     const HSet<T>& h = *t.h.h;
-    // leaves: C += coef * diag(rows) * H_leaves
-    DBuf<T> tmp;
-    const T* src = h.lv.get();
-    int smul = t.h.mmul, soff = t.h.moff;
-    long long sstr = h.leaf_stride();
-    if (t.rows) {
-      tmp.resize((size_t)nmat * ls);
-      bcopy<T>(st, (int)ls, 1, nmat, T(1), with_map(bop(h.lv.get(), 1, h.leaf_stride()), t.h.mmul, t.h.moff),
-               bop(tmp.get(), 1, ls));
-      bscale<T>(st, b, b, nmat, h.nleaf(), bop(tmp.get(), b, ls, (long long)b * b), t.rows, t.rmul,
-                t.roff, s, b, 0, T(1));
-      src = tmp.get(); smul = 1; soff = 0; sstr = ls;
-    }
-    if (first)
-      bcopy<T>(st, (int)ls, 1, nmat, t.coef, with_map(bop(src, 1, sstr), smul, soff), bop(C.lv.get(), 1, ls));
-    else
-      badd<T>(st, (int)ls, 1, nmat, t.coef, with_map(bop(src, 1, sstr), smul, soff), bop(C.lv.get(), 1, ls));
-    first = false;
+    // leaves (rows of leaf c are rows c*b.. of the scale vector)
+    CJob lj = copy_job(b, b, nmat, t.coef, leaves_op(t.h), bop(C.lv.get(), b, ls, (long long)b * b), h.nleaf(),
+                       ti > 0 ? 1 : 0);
+    if (t.rows) { lj.scale = t.rows; lj.smul = t.rmul; lj.soff = t.roff; lj.sstride = s; lj.scl = b; lj.sside = 0; }
+    if (ti == 0) first.push_back(lj);
+    else rest.push_back({lj});
     for (int d = 1; d <= L; ++d) {
       const int w = h.kc[d];
       if (!w) continue;
-      T* ud = C.U[d].get() + (size_t)col[d] * s;
-      T* vd = C.V[d].get() + (size_t)col[d] * s;
-      bcopy<T>(st, s, w, nmat, t.coef, with_map(bop(h.U[d].get(), s, (long long)h.k[d] * s), t.h.mmul, t.h.moff),
-               bop(ud, s, (long long)C.k[d] * s));
-      if (t.rows)
-        bscale<T>(st, s, w, nmat, 1, bop(ud, s, (long long)C.k[d] * s), t.rows, t.rmul, t.roff, s, 0, 0, T(1));
-      bcopy<T>(st, s, w, nmat, T(1), with_map(bop(h.V[d].get(), s, (long long)h.k[d] * s), t.h.mmul, t.h.moff),
-               bop(vd, s, (long long)C.k[d] * s));
+      CJob uj = copy_job(s, w, nmat, t.coef, factor_op(t.h, h.U[d], d, 0),
+                         bop(C.U[d].get() + (size_t)col[d] * s, s, (long long)C.k[d] * s));
+      if (t.rows) { uj.scale = t.rows; uj.smul = t.rmul; uj.soff = t.roff; uj.sstride = s; uj.scl = 0; uj.sside = 0; }
+      first.push_back(uj);
+      first.push_back(copy_job(s, w, nmat, 1.0, factor_op(t.h, h.V[d], d, 0),
+                               bop(C.V[d].get() + (size_t)col[d] * s, s, (long long)C.k[d] * s)));
       col[d] += w;
     }
   }
+  gcopy<T>(st, first);
+  for (auto& r : rest) gcopy<T>(st, r);
   for (int d = 1; d <= L; ++d) C.kc[d] = col[d];
 }
 
 template <typename T>
-void hscale_cols(hipStream_t st, HSet<T>& C, int cnt_alloc, HV<T> H, const T* cols, int cmul, int coff,
-                 int nmat) {
-  const HSet<T>& h = *H.h;
-  const int L = h.L, s = h.s, b = h.b;
-  std::vector<int> kC(L + 1, 0);
-  for (int d = 1; d <= L; ++d) kC[d] = h.kc[d];
-  C.alloc(st, cnt_alloc, s, b, L, kC, cnt_alloc > nmat);
-  const long long ls = C.leaf_stride();
-  bcopy<T>(st, (int)ls, 1, nmat, T(1), with_map(bop(h.lv.get(), 1, h.leaf_stride()), H.mmul, H.moff),
-           bop(C.lv.get(), 1, ls));
-  bscale<T>(st, b, b, nmat, h.nleaf(), bop(C.lv.get(), b, ls, (long long)b * b), cols, cmul, coff, s, b, 1,
-            T(1));
-  for (int d = 1; d <= L; ++d) {
-    const int w = h.kc[d];
-    if (!w) continue;
-    bcopy<T>(st, s, w, nmat, T(1), with_map(bop(h.U[d].get(), s, (long long)h.k[d] * s), H.mmul, H.moff),
-             bop(C.U[d].get(), s, (long long)C.k[d] * s));
-    bcopy<T>(st, s, w, nmat, T(1), with_map(bop(h.V[d].get(), s, (long long)h.k[d] * s), H.mmul, H.moff),
-             bop(C.V[d].get(), s, (long long)C.k[d] * s));
-    // (H diag(c))[t, sib t] = U_t (diag(c_sib) V_t)^T: scale V rows
-    bscale<T>(st, s, w, nmat, 1, bop(C.V[d].get(), s, (long long)C.k[d] * s), cols, cmul, coff, s, 0, 0, T(1));
-    C.kc[d] = w;
+void hscale_cols_multi(hipStream_t st, std::vector<ColScale<T>>& outs) {
+  std::vector<CJob> cj;
+  for (auto& O : outs) {
+    const HSet<T>& h = *O.H.h;
+    const int L = h.L, s = h.s, b = h.b, nmat = O.nmat;
+    std::vector<int> kC(L + 1, 0);
+    for (int d = 1; d <= L; ++d) kC[d] = h.kc[d];
+    HSet<T>& C = *O.C;
+    C.alloc(st, O.cnt_alloc, s, b, L, kC, O.cnt_alloc > nmat);
+    const long long ls = C.leaf_stride();
+    CJob lj = copy_job(b, b, nmat, 1.0, leaves_op(O.H), bop(C.lv.get(), b, ls, (long long)b * b), h.nleaf());
+    lj.scale = O.cols; lj.smul = O.cmul; lj.soff = O.coff; lj.sstride = s; lj.scl = b; lj.sside = 1;
+    cj.push_back(lj);
+    for (int d = 1; d <= L; ++d) {
+      const int w = h.kc[d];
+      if (!w) continue;
+      cj.push_back(copy_job(s, w, nmat, 1.0, factor_op(O.H, h.U[d], d, 0), bop(C.U[d].get(), s, (long long)C.k[d] * s)));
+      // (H diag(c))[t, sib t] = U_t (diag(c_sib) V_t)^T: scale V rows
+      CJob vj = copy_job(s, w, nmat, 1.0, factor_op(O.H, h.V[d], d, 0), bop(C.V[d].get(), s, (long long)C.k[d] * s));
+      vj.scale = O.cols; vj.smul = O.cmul; vj.soff = O.coff; vj.sstride = s; vj.scl = 0; vj.sside = 0;
+      cj.push_back(vj);
+      C.kc[d] = w;
+    }
   }
+  gcopy<T>(st, cj);
 }
 
 // ------------------------------------------------------------- recompress
 template <typename T>
-void recompress(hipStream_t st, HSet<T>& H, double eps, int maxrank) {
-  const int s = H.s, cnt = H.cnt;
-  if (cnt <= 0) return;
-  DBuf<int> dmax(1);
-  for (int d = 1; d <= H.L; ++d) {
-    const int kcol = H.kc[d];
-    if (kcol == 0) continue;
-    const int ncl = 1 << d, sd = H.sd(d), c = std::min(sd, kcol);
-    const int nprob = cnt * ncl;
-    HV<T> HH{&H, 1, 0};
-    DBuf<T> Ru((size_t)nprob * c * kcol), Rv((size_t)nprob * c * kcol);
-    DBuf<T> Vref((size_t)nprob * sd * c), tau((size_t)nprob * c);
-    bqr_r<T>(st, sd, kcol, cnt, ncl, factor_op(HH, H.U[d], d, sd), Ru.get());
-    bqr_r<T>(st, sd, kcol, cnt, ncl, factor_op(HH, H.V[d], d, sd), Rv.get(), Vref.get(), tau.get());
+void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double eps, int maxrank) {
+  struct Item {
+    HSet<T>* H = nullptr;
+    int d = 0, sd = 0, kcol = 0, c = 0, ncl = 0, nprob = 0, kout = 0;
+    DBuf<T> Ru, Rv, Uref, Utau, K, sig, UK, Ut, Un, Vn, Cv;
+    DBuf<int> rank;
+  };
+  std::vector<Item> items;
+  for (HSet<T>* H : sets)
+    for (int d = 1; d <= H->L; ++d) {
+      if (H->kc[d] == 0 || H->cnt == 0) continue;
+      Item it;
+      it.H = H; it.d = d; it.sd = H->sd(d); it.kcol = H->kc[d];
+      it.c = std::min(it.sd, it.kcol); it.ncl = 1 << d; it.nprob = H->cnt * it.ncl;
+      items.push_back(std::move(it));
+    }
+  if (items.empty()) return;
+  // QR of the stacked U (reflectors kept) and V (R only) of every block,
+  // cores K_t = Ru_t Rv_(sib t)^T, their rank-revealing SVDs and ranks
+  std::vector<QJob> qj;
+  GemmPlan kp;
+  std::vector<SJob> sj;
+  std::vector<MJob> mj;
+  DBuf<int> dmax(items.size());
+  for (size_t i = 0; i < items.size(); ++i) {
+    Item& it = items[i];
+    HV<T> HH{it.H, 1, 0};
+    const size_t np = it.nprob, c = it.c, kc = it.kcol;
+    it.Ru.resize(np * c * kc); it.Rv.resize(np * c * kc);
+    it.Uref.resize(np * it.sd * c); it.Utau.resize(np * c);
+    QJob qu;
+    qu.p = it.sd; qu.k = it.kcol; qu.nmat = it.H->cnt; qu.ncl = it.ncl;
+    qu.A = factor_op(HH, it.H->U[it.d], it.d, it.sd);
+    qu.R = it.Ru.get(); qu.Vref = it.Uref.get(); qu.tau = it.Utau.get();
+    QJob qv = qu;
+    qv.A = factor_op(HH, it.H->V[it.d], it.d, it.sd);
+    qv.R = it.Rv.get(); qv.Vref = nullptr; qv.tau = nullptr;
+    qj.push_back(qu);
+    qj.push_back(qv);
     {
-      const double p = sd, k = kcol, r = c;
-      work().qr_flops += 2.0 * nprob * (2.0 * p * k * r - (p + k) * r * r + 2.0 / 3.0 * r * r * r);
+      const double p = it.sd, k = it.kcol, r = it.c;
+      work().qr_flops += 2.0 * np * (2.0 * p * k * r - (p + k) * r * r + 2.0 / 3.0 * r * r * r);
     }
-    BOp Rub = bop(Ru.get(), c, (long long)ncl * c * kcol, (long long)c * kcol);
-    BOp Rvb = bop(Rv.get(), c, (long long)ncl * c * kcol, (long long)c * kcol);
-    DBuf<T> K((size_t)nprob * c * c);
-    bgemm<T>(st, c, c, kcol, cnt, ncl, T(1), Rub, transposed(swapped(Rvb)), T(0),
-             bop(K.get(), c, (long long)ncl * c * c, (long long)c * c));
-    count_gemm<T>(c, c, kcol, nprob);
-    DBuf<T> sig((size_t)nprob * c), Usc((size_t)nprob * c * c), J((size_t)nprob * c * c);
-    DBuf<int> rank(nprob);
-    bsvd<T>(st, c, nprob, K.get(), sig.get(), Usc.get(), J.get(), rank.get(), eps, maxrank);
-    work().svd_flops += 8.0 * 6.0 * (double)c * c * c / 2.0 * nprob;   // nominal 8 sweeps
-    bmax_int(st, rank.get(), nprob, dmax.get());
-    int kout = 0;
-    ACR_HIP(hipMemcpyAsync(&kout, dmax.get(), sizeof(int), hipMemcpyDeviceToHost, st));
-    ACR_HIP(hipStreamSynchronize(st));
-    DBuf<T> Un, Vn;
-    if (kout > 0) {
-      // K = Ru Rv^T = Usc J^T with Usc = Ut S.  Kept part:
-      //   U_new = Q_U Usc_t = U Rv^T J_t   (no inverse: U Rv^T = Q_U K)
-      //   V_new = Q_V J_t                  (reflectors of the V factor)
-      DBuf<T> Jt((size_t)nprob * c * kout);
-      btrunc_coef<T>(st, c, kout, nprob, J.get(), rank.get(), Jt.get());
-      DBuf<T> Cu((size_t)nprob * kcol * kout);
-      BOp Cub = bop(Cu.get(), kcol, (long long)ncl * kcol * kout, (long long)kcol * kout);
-      bgemm<T>(st, kcol, kout, c, cnt, ncl, T(1), transposed(swapped(Rvb)),
-               bop(Jt.get(), c, (long long)ncl * c * kout, (long long)c * kout), T(0), Cub);
-      count_gemm<T>(kcol, kout, c, nprob);
-      Un.resize((size_t)cnt * kout * s);
-      Vn.resize((size_t)cnt * kout * s);
-      bgemm<T>(st, sd, kout, kcol, cnt, ncl, T(1), factor_op(HH, H.U[d], d, sd), Cub, T(0),
-               bop(Un.get(), s, (long long)kout * s, sd));
-      count_gemm<T>(sd, kout, kcol, nprob);
-      // V_new[rows sig] = Q_V(sig) [Jt_(sib sig); 0]
-      bapply_q<T>(st, sd, c, kout, cnt, ncl, Vref.get(), tau.get(), Jt.get(), (long long)c * kout, 1,
-                  bop(Vn.get(), s, (long long)kout * s, sd));
-      work().qr_flops += 4.0 * sd * c * kout * nprob;
-    }
-    H.U[d] = std::move(Un);
-    H.V[d] = std::move(Vn);
-    H.k[d] = H.kc[d] = kout;
+    it.K.resize(np * c * c);
+    BOp Rub = bop(it.Ru.get(), it.c, (long long)it.ncl * c * kc, (long long)c * kc);
+    BOp Rvb = bop(it.Rv.get(), it.c, (long long)it.ncl * c * kc, (long long)c * kc);
+    kp.add(it.c, it.c, it.H->cnt, it.ncl, 1.0, 0.0, bop(it.K.get(), it.c, (long long)it.ncl * c * c, (long long)c * c),
+           {seg(Rub, transposed(swapped(Rvb)), it.kcol)});
+    it.sig.resize(np * c); it.UK.resize(np * c * c); it.rank.resize(np);
+    SJob sv;
+    sv.c = it.c; sv.nprob = it.nprob; sv.K = it.K.get(); sv.sig = it.sig.get(); sv.UK = it.UK.get();
+    sv.rank = it.rank.get(); sv.eps = eps; sv.maxrank = maxrank;
+    sj.push_back(sv);
+    work().svd_flops += 6.0 * (double)c * c * c * np;
+    MJob m;
+    m.rank = it.rank.get(); m.n = it.nprob; m.out = dmax.get() + i;
+    mj.push_back(m);
+  }
+  gqr<T>(st, qj);
+  kp.run<T>(st);
+  grsvd<T>(st, sj);
+  gmax(st, mj);
+  std::vector<int> kout(items.size());
+  ACR_HIP(hipMemcpyAsync(kout.data(), dmax.get(), items.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+  ACR_HIP(hipStreamSynchronize(st));
+  // Keep s_t > eps s_1:  K = U_K S J^T,
+  //   U_new = Q_U [U_K,t; 0]          (orthonormal columns)
+  //   V_new = V Ru^T U_K,t            (= Q_V J_t S_t, no inverse)
+  std::vector<TJob> tj;
+  std::vector<AJob> aj;
+  GemmPlan cvp, vnp;
+  for (size_t i = 0; i < items.size(); ++i) {
+    Item& it = items[i];
+    it.kout = kout[i];
+    if (it.kout == 0) continue;
+    HV<T> HH{it.H, 1, 0};
+    const int s = it.H->s, c = it.c, ko = it.kout, kc = it.kcol;
+    const size_t np = it.nprob;
+    it.Ut.resize(np * c * ko);
+    TJob t;
+    t.c = c; t.kout = ko; t.nprob = it.nprob; t.UK = it.UK.get(); t.rank = it.rank.get(); t.Ut = it.Ut.get();
+    tj.push_back(t);
+    it.Un.resize((size_t)it.H->cnt * ko * s);
+    it.Vn.resize((size_t)it.H->cnt * ko * s);
+    AJob a;
+    a.p = it.sd; a.c = c; a.t = ko; a.nmat = it.H->cnt; a.ncl = it.ncl; a.zxor = 0;
+    a.Vref = it.Uref.get(); a.tau = it.Utau.get(); a.Z = it.Ut.get(); a.sZ = (long long)c * ko;
+    a.Y = bop(it.Un.get(), s, (long long)ko * s, it.sd);
+    aj.push_back(a);
+    work().qr_flops += 4.0 * it.sd * c * ko * np;
+    it.Cv.resize(np * kc * ko);
+    BOp Rub = bop(it.Ru.get(), c, (long long)it.ncl * c * kc, (long long)c * kc);
+    BOp Cvb = bop(it.Cv.get(), kc, (long long)it.ncl * kc * ko, (long long)kc * ko);
+    cvp.add(kc, ko, it.H->cnt, it.ncl, 1.0, 0.0, Cvb,
+            {seg(transposed(Rub), bop(it.Ut.get(), c, (long long)it.ncl * c * ko, (long long)c * ko), c)});
+    vnp.add(it.sd, ko, it.H->cnt, it.ncl, 1.0, 0.0, bop(it.Vn.get(), s, (long long)ko * s, it.sd),
+            {seg(factor_op(HH, it.H->V[it.d], it.d, it.sd), swapped(Cvb), kc)});
+  }
+  gtrunc<T>(st, tj);
+  gapply_q<T>(st, aj);
+  cvp.run<T>(st);
+  vnp.run<T>(st);
+  for (auto& it : items) {
+    it.H->U[it.d] = std::move(it.Un);
+    it.H->V[it.d] = std::move(it.Vn);
+    it.H->k[it.d] = it.H->kc[it.d] = it.kout;
   }
 }
 
@@ -455,12 +582,16 @@ void densify_to_host(hipStream_t st, const HSet<T>& H, int m, double* out) {
 
 #define INST(T)                                                                                    \
   template struct HSet<T>;                                                                         \
+  template void GemmPlan::run<T>(hipStream_t);                                                     \
+  template BOp flat_op<T>(const Flat<T>&, long long, int);                                         \
+  template std::vector<GSeg> plan_hmul<T>(GemmPlan&, std::vector<DBuf<T>>&, HV<T>, int, int, bool, \
+                                          int, double, Flat<T>);                                   \
   template void hmul<T>(hipStream_t, HV<T>, int, int, bool, int, T, Flat<T>, T, Flat<T>);          \
-  template void hprod<T>(hipStream_t, HSet<T>&, int, HV<T>, HV<T>, int, T);                        \
+  template void hprod_multi<T>(hipStream_t, std::vector<POut<T>>&);                                \
   template void hinv<T>(hipStream_t, HSet<T>&, HV<T>, int, int*);                                  \
-  template void hstack<T>(hipStream_t, HSet<T>&, int, const std::vector<STerm<T>>&, int);          \
-  template void hscale_cols<T>(hipStream_t, HSet<T>&, int, HV<T>, const T*, int, int, int);        \
-  template void recompress<T>(hipStream_t, HSet<T>&, double, int);                                 \
+  template void hstack<T>(hipStream_t, HSet<T>&, int, const std::vector<ScaleTerm<T>>&, int);      \
+  template void hscale_cols_multi<T>(hipStream_t, std::vector<ColScale<T>>&);                      \
+  template void recompress_multi<T>(hipStream_t, const std::vector<HSet<T>*>&, double, int);       \
   template void densify_to_host<T>(hipStream_t, const HSet<T>&, int, double*);
 
 INST(float)

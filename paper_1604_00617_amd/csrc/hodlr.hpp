@@ -8,14 +8,16 @@
 //   U[d]   : [cnt][k[d]][s]     depth d = 1..L: rows of cluster tau (size s/2^d)
 //                               hold U_tau of the block A[tau, sib(tau)] = U_tau V_tau^T
 //   V[d]   : [cnt][k[d]][s]     rows of cluster sib(tau) hold V_tau
-// so every depth is one s x k[d] matrix per HODLR, and all clusters of a depth
-// are processed by one batched launch.  Ranks are padded to the set maximum
-// per depth (padding columns are zero).
+// so every depth is one s x k[d] matrix per HODLR, and all clusters of all
+// depths and of several independent operations are processed by a few
+// grouped launches.  Ranks are padded to the set maximum per depth (padding
+// columns are zero).
 #pragma once
 
 #include <vector>
 
 #include "common.hpp"
+#include "kernels.hpp"
 
 namespace acr {
 
@@ -40,7 +42,7 @@ struct HSet {
 // entry mmul*m + moff of the set).
 template <typename T>
 struct HV {
-  const HSet<T>* h;
+  const HSet<T>* h = nullptr;
   int mmul = 1, moff = 0;
 };
 
@@ -53,54 +55,104 @@ struct Flat {
   int mmul = 1, moff = 0;
 };
 
-// out_m = alpha * op(Hdiag_m) Y_m + beta * out_m, where Hdiag_m is the
-// block-diagonal part of H_m at depth dfrom (leaves plus off-diagonal blocks
-// of depth > dfrom; dfrom = 0 is the whole matrix) and op = transpose if trans.
+// Jobs of one grouped GEMM launch.
+struct GemmPlan {
+  std::vector<GJob> jobs;
+  std::vector<GSeg> segs;
+  void add(int M, int N, int nmat, int ncl, double alpha, double beta, const BOp& C,
+           const std::vector<GSeg>& sg);
+  template <typename T>
+  void run(hipStream_t st);
+  bool empty() const { return jobs.empty(); }
+};
+
+// HODLR multi-vector product alpha * op(Hdiag) Y with Hdiag the block-diagonal
+// part of H at depth dfrom (leaves + off-diagonal blocks of depth > dfrom;
+// dfrom = 0 is the whole matrix).  Adds the per-depth reductions
+// T_d = F_d[cl]^T Y[cl] to `red` and returns the K-segments whose sum, per
+// leaf row block, is the product (leaf block times Y, then every depth's
+// U_d[rows] T_d[sibling ancestor]).  Temporaries are appended to `keep`.
+template <typename T>
+std::vector<GSeg> plan_hmul(GemmPlan& red, std::vector<DBuf<T>>& keep, HV<T> H, int nmat,
+                            int dfrom, bool trans, int ncol, double alpha, Flat<T> Y);
+
+// Operand of rows (cluster c of size sc) of a flat matrix.
+template <typename T>
+BOp flat_op(const Flat<T>& f, long long sc, int col0 = 0);
+
+// out_m = alpha op(Hdiag_m) Y_m + beta out_m (two grouped launches).
 template <typename T>
 void hmul(hipStream_t st, HV<T> H, int nmat, int dfrom, bool trans, int ncol, T alpha, Flat<T> Y,
           T beta, Flat<T> out);
 
-// C_m = alpha * A_m B_m with exact low-rank accumulation (no truncation).
-// C is allocated with cnt_alloc >= nmat entries (extra entries zero).
+// One product term coef * A_m B_m of a sum of products.
 template <typename T>
-void hprod(hipStream_t st, HSet<T>& C, int cnt_alloc, HV<T> A, HV<T> B, int nmat, T alpha);
+struct PTerm {
+  double coef = 1.0;
+  HV<T> A, B;
+};
+
+// C_m = D_m (optional) + sum_t coef_t A_t,m B_t,m, accumulated exactly in
+// low-rank form (ranks add, no truncation).  C gets cnt_alloc >= nmat
+// entries (extra entries zero).
+template <typename T>
+struct POut {
+  HSet<T>* C = nullptr;
+  int cnt_alloc = 0, nmat = 0;
+  bool has_d = false;
+  HV<T> D;
+  std::vector<PTerm<T>> terms;
+};
+
+// All outputs are planned together: four grouped GEMM launches plus one
+// grouped copy, whatever the number of outputs, terms and depths.
+template <typename T>
+void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs);
 
 // X_m = M_m^{-1}, exact in exact arithmetic (bottom-up Sherman-Morrison-
 // Woodbury over the depths; the capacitance and leaf inverses in FP64).
 template <typename T>
 void hinv(hipStream_t st, HSet<T>& X, HV<T> M, int nmat, int* status);
 
-// One term of a stacked sum: coef * diag(rows)? * H_m; `rows` (optional) is a
-// per-matrix vector of s values at rows + (rmul*m + roff)*s.
+// Level-0 operations with diagonal E/F (scalings): see acr.hip.
+// C_m = diag(rows_(rmul*m+roff))? * coef * H_m  (copy with optional row scale)
+// or, with cols set, H_m diag(cols_(cmul*m+coff)).
 template <typename T>
-struct STerm {
+struct ScaleTerm {
   HV<T> h;
-  T coef = T(1);
+  double coef = 1.0;
   const T* rows = nullptr;
   int rmul = 1, roff = 0;
 };
 
-// C_m = sum_t terms: factors stacked side by side (ranks add), leaves summed.
+// C_m = sum_t coef_t diag(rows_t) H_t,m (stack of scaled sets).
 template <typename T>
-void hstack(hipStream_t st, HSet<T>& C, int cnt_alloc, const std::vector<STerm<T>>& terms,
+void hstack(hipStream_t st, HSet<T>& C, int cnt_alloc, const std::vector<ScaleTerm<T>>& terms,
             int nmat);
 
-// C_m = H_m diag(cols_(cmul*m+coff)) (column scaling: leaves' columns and V rows).
+// C_m = H_m diag(cols_(cmul*m+coff)) for several outputs at once.
 template <typename T>
-void hscale_cols(hipStream_t st, HSet<T>& C, int cnt_alloc, HV<T> H, const T* cols, int cmul,
-                 int coff, int nmat);
+struct ColScale {
+  HSet<T>* C = nullptr;
+  int cnt_alloc = 0, nmat = 0;
+  HV<T> H;
+  const T* cols = nullptr;
+  int cmul = 1, coff = 0;
+};
+template <typename T>
+void hscale_cols_multi(hipStream_t st, std::vector<ColScale<T>>& outs);
 
-// T_eps of every off-diagonal block of every matrix in the set (in place):
-// QR of the stacked U and V, SVD of R_U R_V^T, keep s_t > eps * s_1.
+// T_eps of every off-diagonal block of every matrix of every set (in place):
+// QR of the stacked U and V, rank-revealing SVD of R_U R_V^T, keep
+// s_t > eps * s_1.  One synchronisation for all sets and depths.
 template <typename T>
-void recompress(hipStream_t st, HSet<T>& H, double eps, int maxrank);
+void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double eps, int maxrank);
 
 // Dense copy of matrix m (host, column-major s x s, FP64).  Synchronises st.
 template <typename T>
 void densify_to_host(hipStream_t st, const HSet<T>& H, int m, double* out);
 
-// Algorithmic work counters of the batched primitives (host side, from the
-// shapes launched): flops and the name of the calling phase.
+// Algorithmic work counters of the factorisation (host side, from shapes).
 struct Work {
   double gemm_flops = 0, qr_flops = 0, svd_flops = 0, inv_flops = 0;
   double total() const { return gemm_flops + qr_flops + svd_flops + inv_flops; }

@@ -21,9 +21,21 @@ constexpr size_t kMaxLds = 65536;   // dynamic + static LDS budget per workgroup
 
 template <typename T>
 __device__ __forceinline__ const T* optr(const BOp& o, int m, int c) {
-  const int cc = c ^ o.cxor;
+  const int cc = (c >> o.cshift) ^ o.cxor;
   return static_cast<const T*>(o.p) + (long long)(o.mmul * m + o.moff) * o.sm +
          (long long)(cc >> 1) * o.sc_pair + (long long)(cc & 1) * o.sc_odd;
+}
+
+// Job owning workgroup `bid` in a grouped launch (jobs sorted by block0).
+template <typename J>
+__device__ __forceinline__ int job_of(const J* jobs, int n, long long bid) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block0 <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 template <typename T>
@@ -56,23 +68,27 @@ template <> struct Eps<float> { static constexpr double v = 5.9604644775390625e-
 template <> struct Eps<double> { static constexpr double v = 1.1102230246251565e-16; };
 
 // ------------------------------------------------------------------ GEMM
-// Tile TM x TN per workgroup, TK deep, each thread RM x RN outputs.
+// Grouped, K-segmented batched GEMM.  A workgroup computes one TM x TN tile
+// of one problem of one job, accumulating over every segment of the job;
+// each thread holds RM x RN outputs, operands are staged through LDS in TK
+// slices.
 template <typename T, int TM, int TN, int TK, int RM, int RN>
-__global__ __launch_bounds__((TM / RM) * (TN / RN)) void k_bgemm(int M, int N, int K, int ncl,
-                                                                int tilesM, int tilesN, T alpha,
-                                                                BOp A, BOp B, T beta, BOp C) {
+__global__ __launch_bounds__((TM / RM) * (TN / RN)) void k_ggemm(const GJob* __restrict__ jobs,
+                                                                int njobs,
+                                                                const GSeg* __restrict__ segs) {
   constexpr int TX = TM / RM, TY = TN / RN, NT = TX * TY;
   __shared__ T As[TK][TM + 1];
   __shared__ T Bs[TK][TN + 1];
-  const int tiles = tilesM * tilesN;
   const long long bid = blockIdx.x;
-  const int prob = (int)(bid / tiles);
-  const int t = (int)(bid % tiles);
+  const GJob& J = jobs[job_of(jobs, njobs, bid)];
+  const int tilesM = J.tilesM;
+  const int tiles = tilesM * J.tilesN;
+  const long long local = bid - J.block0;
+  const int prob = (int)(local / tiles);
+  const int t = (int)(local % tiles);
   const int tm = t % tilesM, tn = t / tilesM;
-  const int m = prob / ncl, c = prob % ncl;
-  const T* Ap = optr<T>(A, m, c);
-  const T* Bp = optr<T>(B, m, c);
-  T* Cp = const_cast<T*>(optr<T>(C, m, c));
+  const int m = prob / J.ncl, c = prob % J.ncl;
+  const int M = J.M, N = J.N;
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
   const int i0 = tm * TM, j0 = tn * TN;
@@ -81,39 +97,49 @@ __global__ __launch_bounds__((TM / RM) * (TN / RN)) void k_bgemm(int M, int N, i
   for (int r = 0; r < RM; ++r)
 #pragma unroll
     for (int q = 0; q < RN; ++q) acc[r][q] = T(0);
-
-  for (int k0 = 0; k0 < K; k0 += TK) {
-    for (int e = tid; e < TM * TK; e += NT) {
-      int i, kk;
-      if (!A.trans) { i = e % TM; kk = e / TM; } else { kk = e % TK; i = e / TK; }
-      const int gi = i0 + i, gk = k0 + kk;
-      T v = T(0);
-      if (gi < M && gk < K) v = A.trans ? Ap[gk + (long long)gi * A.ld] : Ap[gi + (long long)gk * A.ld];
-      As[kk][i] = v;
+  for (int sg = 0; sg < J.nseg; ++sg) {
+    const GSeg& S = segs[J.seg0 + sg];
+    const int K = S.K;
+    const int lda = S.A.ld, ldb = S.B.ld, ta = S.A.trans, tb = S.B.trans;
+    const T sscale = (T)S.scale;
+    const T* Ap = optr<T>(S.A, m, c);
+    const T* Bp = optr<T>(S.B, m, c);
+    for (int k0 = 0; k0 < K; k0 += TK) {
+      for (int e = tid; e < TM * TK; e += NT) {
+        int i, kk;
+        if (!ta) { i = e % TM; kk = e / TM; } else { kk = e % TK; i = e / TK; }
+        const int gi = i0 + i, gk = k0 + kk;
+        T v = T(0);
+        if (gi < M && gk < K) v = ta ? Ap[gk + (long long)gi * lda] : Ap[gi + (long long)gk * lda];
+        As[kk][i] = v * sscale;
+      }
+      for (int e = tid; e < TK * TN; e += NT) {
+        int kk, jj;
+        if (!tb) { kk = e % TK; jj = e / TK; } else { jj = e % TN; kk = e / TN; }
+        const int gk = k0 + kk, gj = j0 + jj;
+        T v = T(0);
+        if (gk < K && gj < N) v = tb ? Bp[gj + (long long)gk * ldb] : Bp[gk + (long long)gj * ldb];
+        Bs[kk][jj] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < TK; ++kk) {
+        T a[RM], b[RN];
+#pragma unroll
+        for (int r = 0; r < RM; ++r) a[r] = As[kk][tx + r * TX];
+#pragma unroll
+        for (int q = 0; q < RN; ++q) b[q] = Bs[kk][ty + q * TY];
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+#pragma unroll
+          for (int q = 0; q < RN; ++q) acc[r][q] = fma(a[r], b[q], acc[r][q]);
+      }
+      __syncthreads();
     }
-    for (int e = tid; e < TK * TN; e += NT) {
-      int kk, j;
-      if (!B.trans) { kk = e % TK; j = e / TK; } else { j = e % TN; kk = e / TN; }
-      const int gk = k0 + kk, gj = j0 + j;
-      T v = T(0);
-      if (gk < K && gj < N) v = B.trans ? Bp[gj + (long long)gk * B.ld] : Bp[gk + (long long)gj * B.ld];
-      Bs[kk][j] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      T a[RM], b[RN];
-#pragma unroll
-      for (int r = 0; r < RM; ++r) a[r] = As[kk][tx + r * TX];
-#pragma unroll
-      for (int q = 0; q < RN; ++q) b[q] = Bs[kk][ty + q * TY];
-#pragma unroll
-      for (int r = 0; r < RM; ++r)
-#pragma unroll
-        for (int q = 0; q < RN; ++q) acc[r][q] = fma(a[r], b[q], acc[r][q]);
-    }
-    __syncthreads();
   }
+  T* Cp = const_cast<T*>(optr<T>(J.C, m, c));
+  const int ldc = J.C.ld;
+  const T alpha = (T)J.alpha, beta = (T)J.beta;
 #pragma unroll
   for (int r = 0; r < RM; ++r) {
     const int gi = i0 + tx + r * TX;
@@ -122,25 +148,12 @@ __global__ __launch_bounds__((TM / RM) * (TN / RN)) void k_bgemm(int M, int N, i
     for (int q = 0; q < RN; ++q) {
       const int gj = j0 + ty + q * TY;
       if (gj >= N) continue;
-      T* cp = Cp + gi + (long long)gj * C.ld;
+      T* cp = Cp + gi + (long long)gj * ldc;
       T v = alpha * acc[r][q];
       if (beta != T(0)) v = fma(beta, *cp, v);
       *cp = v;
     }
   }
-}
-
-template <typename T, int TM, int TN, int RM, int RN>
-void launch_gemm(hipStream_t st, int M, int N, int K, int nprob, int ncl, T alpha, const BOp& A,
-                 const BOp& B, T beta, const BOp& C) {
-  const int tilesM = (M + TM - 1) / TM, tilesN = (N + TN - 1) / TN;
-  const long long blocks = (long long)nprob * tilesM * tilesN;
-  constexpr int NT = (TM / RM) * (TN / RN);
-  if (blocks <= 0) return;
-  if (blocks > 0x7fffffffLL) fail(ACR_ERR_INVALID_ARG, "bgemm: grid too large");
-  hipLaunchKernelGGL((k_bgemm<T, TM, TN, 16, RM, RN>), dim3((unsigned)blocks), dim3(NT), 0, st, M,
-                     N, K, ncl, tilesM, tilesN, alpha, A, B, beta, C);
-  ACR_CHECK_LAUNCH();
 }
 
 // ---------------------------------------------------------------- inverse
@@ -298,18 +311,24 @@ __global__ __launch_bounds__(256) void k_inverse_lds(int n, const Tin* A, long l
 // Householder QR of a p x k panel; one workgroup of 256 threads per problem.
 // The panel is copied to LDS when it fits, else to a global scratch copy.
 template <typename T>
-__global__ __launch_bounds__(256) void k_qr_r(int p, int k, int ncl, BOp A, T* R, T* ws,
-                                              int use_lds, T* Vref, T* taus) {
+__global__ __launch_bounds__(256) void k_gqr(const QJob* __restrict__ jobs, int njobs) {
   extern __shared__ unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   __shared__ double red[4];
   __shared__ T s_beta, s_tau;
   __shared__ double s_v0;
-  const int prob = blockIdx.x;
+  const QJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int prob = (int)(blockIdx.x - Jb.block0);
+  const int p = Jb.p, k = Jb.k, ncl = Jb.ncl;
   const int m = prob / ncl, c = prob % ncl;
+  const BOp A = Jb.A;
   const T* Ap = optr<T>(A, m, c);
+  const int krr = min(p, k);
+  T* const R = static_cast<T*>(Jb.R);
+  T* const Vref = Jb.Vref ? static_cast<T*>(Jb.Vref) + (size_t)prob * p * krr : nullptr;
+  T* const taus = Jb.tau ? static_cast<T*>(Jb.tau) + (size_t)prob * krr : nullptr;
   T* v = sm;                                  // Householder vector, p entries
-  T* W = use_lds ? sm + p : ws + (size_t)prob * p * k;
+  T* W = Jb.lds ? sm + p : static_cast<T*>(Jb.ws) + (size_t)prob * p * k;
   const int tid = threadIdx.x, wv = tid / WAVE, lane = tid % WAVE;
   for (int e = tid; e < p * k; e += 256) {
     const int r = e % p, q = e / p;
@@ -349,7 +368,7 @@ __global__ __launch_bounds__(256) void k_qr_r(int p, int k, int ncl, BOp A, T* R
         v[r] = (r == j) ? T(1) : (T)((double)W[r + (size_t)j * p] / v0);
       __syncthreads();
       if (Vref) {
-        T* vo = Vref + (size_t)prob * p * kr + (size_t)j * p;
+        T* vo = Vref + (size_t)j * p;
         for (int r = tid; r < p; r += 256) vo[r] = r < j ? T(0) : v[r];
       }
       // apply (I - tau v v^T) to columns j+1..k-1: one wave per column
@@ -362,10 +381,10 @@ __global__ __launch_bounds__(256) void k_qr_r(int p, int k, int ncl, BOp A, T* R
       }
     }
     if (Vref && tau == T(0)) {
-      T* vo = Vref + (size_t)prob * p * kr + (size_t)j * p;
+      T* vo = Vref + (size_t)j * p;
       for (int r = tid; r < p; r += 256) vo[r] = T(0);
     }
-    if (Vref && tid == 0) taus[(size_t)prob * kr + j] = tau;
+    if (Vref && tid == 0) taus[j] = tau;
     __syncthreads();
     if (tid == 0) W[j + (size_t)j * p] = s_beta;
     __syncthreads();
@@ -381,15 +400,16 @@ __global__ __launch_bounds__(256) void k_qr_r(int p, int k, int ncl, BOp A, T* R
 // Y = Q [Z; 0] for the Householder Q of a QR with reflectors (v_j, tau_j):
 // Y is p x t (column-major, ld = Y.ld, in place), Z is c x t (ld c).
 template <typename T>
-__global__ __launch_bounds__(256) void k_apply_q(int p, int c, int t, int ncl, const T* Vref,
-                                                 const T* taus, const T* Z, long long sZ, int zxor,
-                                                 BOp Y) {
-  const int prob = blockIdx.x;
+__global__ __launch_bounds__(256) void k_gapply_q(const AJob* __restrict__ jobs, int njobs) {
+  const AJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int prob = (int)(blockIdx.x - Jb.block0);
+  const int p = Jb.p, c = Jb.c, t = Jb.t, ncl = Jb.ncl;
   const int m = prob / ncl, cl = prob % ncl;
+  const BOp Y = Jb.Y;
   T* y = const_cast<T*>(optr<T>(Y, m, cl));
-  const T* z = Z + (size_t)(m * ncl + (cl ^ zxor)) * sZ;
-  const T* vr = Vref + (size_t)prob * p * c;
-  const T* ta = taus + (size_t)prob * c;
+  const T* z = static_cast<const T*>(Jb.Z) + (size_t)(m * ncl + (cl ^ Jb.zxor)) * Jb.sZ;
+  const T* vr = static_cast<const T*>(Jb.Vref) + (size_t)prob * p * c;
+  const T* ta = static_cast<const T*>(Jb.tau) + (size_t)prob * c;
   const int tid = threadIdx.x, wv = tid / WAVE, lane = tid % WAVE;
   for (int e = tid; e < p * t; e += 256) {
     const int r = e % p, q = e / p;
@@ -412,53 +432,160 @@ __global__ __launch_bounds__(256) void k_apply_q(int p, int c, int t, int ncl, c
   }
 }
 
-// ------------------------------------------------------- one-sided Jacobi
+// ------------------------------------------------ rank-revealing SVD
+// Rank-revealing SVD of a recompression core K (c x c, column-major, used as
+// scratch in place), preconditioned one-sided Jacobi:
+//  1. column-pivoted Householder QR  K P = Q_K [R_top; R22], stopped once every
+//     remaining column norm is <= delta = 0.1 eps nu_1 / sqrt(c) (nu_1 = largest
+//     column norm <= s_1), so ||R22||_2 <= 0.1 eps s_1;
+//  2. one-sided Jacobi on the thin X = R_top^T (c x t'): X J_X = Usc_X, so
+//     R_top = J_X S Utilde^T and the left singular vectors of K are
+//     U_K = Q_K [J_X; 0] (J_X is accumulated from plane rotations, hence
+//     orthogonal to working precision);
+//  3. sort by s, rank_p = #{s_i > eps s_1} (capped by maxrank > 0).
+// Outputs per problem: sig[c] (sorted, zero past t'), UK (c x c, column k the
+// k-th left singular vector, zero past t').
 template <typename T>
-__global__ __launch_bounds__(256) void k_svd(int c, T* Kall, T* Jall, T* sig, T* Usc, T* Jout,
-                                             int* rank, double eps, int maxrank, int* sweeps) {
-  __shared__ int nrot;
-  __shared__ double red[4];
+__global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, int njobs) {
+  __shared__ double nrm[512];
+  __shared__ double taus[512];
   __shared__ T snorm[512];
   __shared__ int spos[512];
-  const int prob = blockIdx.x;
-  T* Ak = Kall + (size_t)prob * c * c;
+  __shared__ double red[4];
+  __shared__ int s_piv, s_stop, nrot;
+  __shared__ double s_delta2, s_v0;
+  __shared__ T s_beta;
+  const SJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int prob = (int)(blockIdx.x - Jb.block0);
+  const int c = Jb.c, maxrank = Jb.maxrank;
+  const double eps = Jb.eps;
+  T* const Xall = static_cast<T*>(Jb.X);
+  T* const Jall = static_cast<T*>(Jb.J);
+  T* const sig = static_cast<T*>(Jb.sig);
+  T* const UK = static_cast<T*>(Jb.UK);
+  int* const rank = Jb.rank;
+  double* const flops = Jb.flops;
+  const int tid = threadIdx.x, wv = tid / WAVE, lane = tid % WAVE;
+  T* W = static_cast<T*>(Jb.K) + (size_t)prob * c * c;
+  double fl = 0.0;
+  int tp = 0;
+  for (int j = 0; j < c; ++j) {
+    for (int q = j + wv; q < c; q += 4) {
+      const T* col = W + (size_t)q * c;
+      double ss = 0.0;
+      for (int r = j + lane; r < c; r += WAVE) ss += (double)col[r] * (double)col[r];
+      ss = wave_sum(ss);
+      if (lane == 0) nrm[q] = ss;
+    }
+    __syncthreads();
+    if (tid < WAVE) {
+      double best = -1.0;
+      int bi = j;
+      for (int q = j + tid; q < c; q += WAVE)
+        if (nrm[q] > best) { best = nrm[q]; bi = q; }
+      for (int off = WAVE / 2; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, WAVE);
+        const int oi = __shfl_xor(bi, off, WAVE);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) {
+        if (j == 0) s_delta2 = eps > 0.0 ? (0.01 * eps * eps) * best / c : 0.0;
+        s_piv = bi;
+        s_stop = (best <= s_delta2) || !(best > 0.0);
+      }
+    }
+    __syncthreads();
+    if (s_stop) break;
+    const int pc = s_piv;
+    if (pc != j)
+      for (int r = tid; r < c; r += 256) {
+        const T a = W[r + (size_t)j * c];
+        W[r + (size_t)j * c] = W[r + (size_t)pc * c];
+        W[r + (size_t)pc * c] = a;
+      }
+    __syncthreads();
+    double ss = 0.0;
+    for (int r = j + 1 + tid; r < c; r += 256) ss += (double)W[r + (size_t)j * c] * (double)W[r + (size_t)j * c];
+    const double tail = block_sum256(ss, red);
+    if (tid == 0) {
+      const double alpha = (double)W[j + (size_t)j * c];
+      const double nr = sqrt(alpha * alpha + tail);
+      const double beta = alpha >= 0.0 ? -nr : nr;
+      if (tail == 0.0 || nr == 0.0) {
+        taus[j] = 0.0;
+        s_beta = (T)alpha;
+      } else {
+        taus[j] = (beta - alpha) / beta;
+        s_v0 = alpha - beta;
+        s_beta = (T)beta;
+      }
+    }
+    __syncthreads();
+    const T tau = (T)taus[j];
+    if (tau != T(0)) {
+      const double v0 = s_v0;
+      for (int r = j + 1 + tid; r < c; r += 256) W[r + (size_t)j * c] = (T)((double)W[r + (size_t)j * c] / v0);
+      __syncthreads();
+      const T* v = W + (size_t)j * c;
+      for (int q = j + 1 + wv; q < c; q += 4) {
+        T* col = W + (size_t)q * c;
+        T d = lane == 0 ? col[j] : T(0);
+        for (int r = j + 1 + lane; r < c; r += WAVE) d = fma(v[r], col[r], d);
+        d = wave_sum(d) * tau;
+        if (lane == 0) col[j] -= d;
+        for (int r = j + 1 + lane; r < c; r += WAVE) col[r] = fma(-d, v[r], col[r]);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) W[j + (size_t)j * c] = s_beta;
+    __syncthreads();
+    tp = j + 1;
+    fl += 6.0 * (double)(c - j) * (c - j);
+  }
+  // X = R_top^T (c x tp), J_X = I (tp x tp), both with leading dimension c
+  T* X = Xall + (size_t)prob * c * c;
   T* J = Jall + (size_t)prob * c * c;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < c * c; e += 256) J[e] = (e % c == e / c) ? T(1) : T(0);
-  // Frobenius norm for the negligible-column test
-  double ss = 0.0;
-  for (int e = tid; e < c * c; e += 256) ss += (double)Ak[e] * (double)Ak[e];
-  const double fro2 = block_sum256(ss, red);
-  const double negl2 = fro2 * Eps<T>::v * Eps<T>::v;
-  const double tol = Eps<T>::v * 4.0;
-  const int cp = (c + 1) & ~1;          // players (one bye if c is odd)
+  for (int e = tid; e < c * tp; e += 256) {
+    const int q = e % c, i = e / c;
+    X[q + (size_t)i * c] = q >= i ? W[i + (size_t)q * c] : T(0);
+  }
+  for (int e = tid; e < tp * tp; e += 256) {
+    const int r = e % tp, i = e / tp;
+    J[r + (size_t)i * c] = r == i ? T(1) : T(0);
+  }
+  __syncthreads();
+  double ssf = 0.0;
+  for (int e = tid; e < c * tp; e += 256) {
+    const double x = X[(e % c) + (size_t)(e / c) * c];
+    ssf += x * x;
+  }
+  const double negl2 = block_sum256(ssf, red) * Eps<T>::v * Eps<T>::v;
+  const double tol = 4.0 * Eps<T>::v;
+  const int cp = (tp + 1) & ~1;
   const int npairs = cp / 2;
-  int g = 256 / max(npairs, 1);         // threads per pair (power of two, <= 64)
-  int gp = 1;
+  int g = 256 / max(npairs, 1), gp = 1;
   while (gp * 2 <= g && gp * 2 <= WAVE) gp *= 2;
   g = gp;
-  const int slots = 256 / g;            // pairs processed concurrently
-  const int gl = tid % g;
-  __syncthreads();
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  const int slots = 256 / g, gl = tid % g;
+  for (int sweep = 0; sweep < 60 && tp > 1; ++sweep) {
     if (tid == 0) nrot = 0;
     __syncthreads();
     for (int rnd = 0; rnd < cp - 1; ++rnd) {
       for (int pb = 0; pb < npairs; pb += slots) {
         const int pk = pb + tid / g;
-        int i = -1, j = -1;
+        int i = -1, jj = -1;
         if (pk < npairs) {
           const int a = (pk == 0) ? 0 : ((rnd + pk - 1) % (cp - 1)) + 1;
           const int b = ((rnd + (cp - 1 - pk) - 1) % (cp - 1)) + 1;
-          i = min(a, b); j = max(a, b);
-          if (j >= c) { i = -1; j = -1; }
+          i = min(a, b); jj = max(a, b);
+          if (jj >= tp) { i = -1; jj = -1; }
         }
         double al = 0.0, be = 0.0, ga = 0.0;
         if (i >= 0) {
-          const T* ai = Ak + (size_t)i * c;
-          const T* aj = Ak + (size_t)j * c;
+          const T* xi = X + (size_t)i * c;
+          const T* xj = X + (size_t)jj * c;
           for (int r = gl; r < c; r += g) {
-            const double x = ai[r], y = aj[r];
+            const double x = xi[r], y = xj[r];
             al += x * x; be += y * y; ga += x * y;
           }
         }
@@ -469,17 +596,19 @@ __global__ __launch_bounds__(256) void k_svd(int c, T* Kall, T* Jall, T* sig, T*
           double t = (az > 1e15) ? 0.5 / az : 1.0 / (az + sqrt(1.0 + az * az));
           t = copysign(t, zeta);
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          T* ai = Ak + (size_t)i * c;
-          T* aj = Ak + (size_t)j * c;
-          T* ji = J + (size_t)i * c;
-          T* jj = J + (size_t)j * c;
+          T* xi = X + (size_t)i * c;
+          T* xj = X + (size_t)jj * c;
           for (int r = gl; r < c; r += g) {
-            const double x = ai[r], y = aj[r];
-            ai[r] = (T)(cs * x - sn * y);
-            aj[r] = (T)(sn * x + cs * y);
-            const double u = ji[r], w = jj[r];
-            ji[r] = (T)(cs * u - sn * w);
-            jj[r] = (T)(sn * u + cs * w);
+            const double x = xi[r], y = xj[r];
+            xi[r] = (T)(cs * x - sn * y);
+            xj[r] = (T)(sn * x + cs * y);
+          }
+          T* ji = J + (size_t)i * c;
+          T* jjp = J + (size_t)jj * c;
+          for (int r = gl; r < tp; r += g) {
+            const double x = ji[r], y = jjp[r];
+            ji[r] = (T)(cs * x - sn * y);
+            jjp[r] = (T)(sn * x + cs * y);
           }
           if (gl == 0) atomicAdd(&nrot, 1);
         }
@@ -487,16 +616,18 @@ __global__ __launch_bounds__(256) void k_svd(int c, T* Kall, T* Jall, T* sig, T*
       }
     }
     __syncthreads();
-    const int done = (nrot == 0);
+    const int nr = nrot;
+    fl += 3.0 * (double)tp * (tp - 1) * c + (double)nr * (6.0 * c + 6.0 * tp);
     __syncthreads();
-    if (sweeps && tid == 0) sweeps[prob] = sweep + 1;
-    if (done) break;
+    if (nr == 0) break;
   }
-  // column norms, sort descending (ties by index), emit
+  // singular values, sort (descending, ties by index)
   for (int q = tid; q < c; q += 256) {
     double s2 = 0.0;
-    const T* aq = Ak + (size_t)q * c;
-    for (int r = 0; r < c; ++r) s2 += (double)aq[r] * (double)aq[r];
+    if (q < tp) {
+      const T* xq = X + (size_t)q * c;
+      for (int r = 0; r < c; ++r) s2 += (double)xq[r] * (double)xq[r];
+    }
     snorm[q] = (T)sqrt(s2);
   }
   __syncthreads();
@@ -507,17 +638,33 @@ __global__ __launch_bounds__(256) void k_svd(int c, T* Kall, T* Jall, T* sig, T*
     spos[q] = pos;
   }
   __syncthreads();
-  T* so = sig + (size_t)prob * c;
-  T* uo = Usc + (size_t)prob * c * c;
-  T* jo = Jout + (size_t)prob * c * c;
+  // U_K = Q_K [J_X; 0] with columns in sorted order; written to UK
+  T* Y = UK + (size_t)prob * c * c;
   for (int e = tid; e < c * c; e += 256) {
-    const int r = e % c, q = e / c;
-    const int d = spos[q];
-    uo[r + (size_t)d * c] = Ak[e];
-    jo[r + (size_t)d * c] = J[e];
+    const int r = e % c, q = e / c;    // q = source column (unsorted)
+    T v = T(0);
+    if (q < tp && r < tp) v = J[r + (size_t)q * c];
+    if (q < tp) Y[r + (size_t)spos[q] * c] = v;
+    else Y[r + (size_t)q * c] = T(0);   // columns past tp stay zero (spos[q] == q there)
   }
-  for (int q = tid; q < c; q += 256) so[spos[q]] = snorm[q];
   __syncthreads();
+  for (int j = tp - 1; j >= 0; --j) {
+    const T tau = (T)taus[j];
+    if (tau != T(0)) {
+      const T* v = W + (size_t)j * c;
+      for (int q = wv; q < tp; q += 4) {
+        T* col = Y + (size_t)q * c;
+        T d = lane == 0 ? col[j] : T(0);
+        for (int r = j + 1 + lane; r < c; r += WAVE) d = fma(v[r], col[r], d);
+        d = wave_sum(d) * tau;
+        if (lane == 0) col[j] -= d;
+        for (int r = j + 1 + lane; r < c; r += WAVE) col[r] = fma(-d, v[r], col[r]);
+      }
+    }
+    __syncthreads();
+  }
+  T* so = sig + (size_t)prob * c;
+  for (int q = tid; q < c; q += 256) so[spos[q]] = snorm[q];
   if (tid == 0) {
     T smax = T(0);
     for (int q = 0; q < c; ++q) smax = snorm[q] > smax ? snorm[q] : smax;
@@ -528,46 +675,64 @@ __global__ __launch_bounds__(256) void k_svd(int c, T* Kall, T* Jall, T* sig, T*
     }
     if (maxrank > 0 && t > maxrank) t = maxrank;
     rank[prob] = t;
+    fl += 4.0 * (double)c * tp * tp;
+    if (flops) flops[prob] = fl;
   }
 }
 
 template <typename T>
-__global__ void k_trunc_coef(int c, int kout, const T* J, const int* rank, T* Jt) {
-  const int prob = blockIdx.y;
-  const long long n = (long long)c * kout;
-  const int t = rank[prob];
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int r = (int)(e % c), q = (int)(e / c);
-    Jt[(size_t)prob * n + e] = (q < t && q < c) ? J[(size_t)prob * c * c + r + (size_t)q * c] : T(0);
+__global__ void k_gtrunc(const TJob* __restrict__ jobs, int njobs) {
+  const TJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int prob = (int)(blockIdx.x - Jb.block0);
+  const int c = Jb.c, kout = Jb.kout;
+  const int t = Jb.rank[prob];
+  const T* J = static_cast<const T*>(Jb.UK) + (size_t)prob * c * c;
+  T* Jt = static_cast<T*>(Jb.Ut) + (size_t)prob * c * kout;
+  for (int e = threadIdx.x; e < c * kout; e += blockDim.x) {
+    const int r = e % c, q = e / c;
+    Jt[e] = (q < t && q < c) ? J[r + (size_t)q * c] : T(0);
   }
 }
 
-__global__ void k_max_int(const int* v, int n, int* out) {
+__global__ void k_gmax(const MJob* __restrict__ jobs) {
   __shared__ int sm[256];
+  const MJob& Jb = jobs[blockIdx.x];
   int mx = 0;
-  for (int i = threadIdx.x; i < n; i += 256) mx = max(mx, v[i]);
+  for (int i = threadIdx.x; i < Jb.n; i += 256) mx = max(mx, Jb.rank[i]);
   sm[threadIdx.x] = mx;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + s]);
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + s2]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sm[0];
+  if (threadIdx.x == 0) Jb.out[0] = sm[0];
 }
 
+constexpr int kCopyChunk = 2048;
+
 template <typename T>
-__global__ void k_bcopy(int rows, int cols, T alpha, BOp src, BOp dst, int accumulate) {
-  const int m = blockIdx.y;
-  const T* s = optr<T>(src, m, 0);
-  T* d = const_cast<T*>(optr<T>(dst, m, 0));
-  const long long n = (long long)rows * cols;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x) {
+__global__ void k_gcopy(const CJob* __restrict__ jobs, int njobs) {
+  const CJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long local = blockIdx.x - Jb.block0;
+  const int chunk = (int)(local % Jb.chunks);
+  const long long pc = local / Jb.chunks;
+  const int m = (int)(pc / Jb.ncl), c = (int)(pc % Jb.ncl);
+  const BOp src = Jb.src, dst = Jb.dst;
+  const T* sp = optr<T>(src, m, c);
+  T* dp = const_cast<T*>(optr<T>(dst, m, c));
+  const T* sc = Jb.scale ? static_cast<const T*>(Jb.scale) + (long long)(Jb.smul * m + Jb.soff) * Jb.sstride +
+                               (long long)c * Jb.scl
+                         : nullptr;
+  const int rows = Jb.rows;
+  const long long n = (long long)rows * Jb.cols;
+  const long long e0 = (long long)chunk * kCopyChunk, e1 = min(n, e0 + kCopyChunk);
+  const T alpha = (T)Jb.alpha;
+  for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int r = (int)(e % rows), q = (int)(e / rows);
-    T* dp = d + r + (long long)q * dst.ld;
-    const T v = alpha * s[r + (long long)q * src.ld];
-    *dp = accumulate ? *dp + v : v;
+    T v = alpha * sp[r + (long long)q * src.ld];
+    if (sc) v *= sc[Jb.sside ? q : r];
+    T* d = dp + r + (long long)q * dst.ld;
+    *d = Jb.accumulate ? *d + v : v;
   }
 }
 
@@ -576,21 +741,6 @@ __global__ void k_fill(T* p, size_t n, T v) {
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
        e += (size_t)gridDim.x * blockDim.x)
     p[e] = v;
-}
-
-template <typename T>
-__global__ void k_bscale(int rows, int cols, int ncl, BOp X, const T* vec, int vmul, int voff,
-                         long long vstride, long long vcl, int side, T alpha) {
-  const int prob = blockIdx.y;
-  const int m = prob / ncl, c = prob % ncl;
-  T* x = const_cast<T*>(optr<T>(X, m, c));
-  const T* v = vec + (long long)(vmul * m + voff) * vstride + (long long)c * vcl;
-  const long long n = (long long)rows * cols;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int r = (int)(e % rows), q = (int)(e / rows);
-    x[r + (long long)q * X.ld] *= alpha * v[side ? q : r];
-  }
 }
 
 template <typename T>
@@ -783,31 +933,81 @@ inline unsigned grid1(long long n, int bs = 256, long long cap = 65535) {
 }  // namespace
 
 // ================================================================ launchers
+namespace {
+
+struct TileCfg { int tm, tn; double eff; };
+constexpr TileCfg kTiles[5] = {{64, 64, 1.0}, {64, 16, 0.8}, {16, 64, 0.8}, {32, 32, 0.8}, {16, 16, 0.55}};
+
+int pick_tile(int M, int N) {
+  int best = 0;
+  double bc = 1e300;
+  for (int i = 0; i < 5; ++i) {
+    const double pm = (double)((M + kTiles[i].tm - 1) / kTiles[i].tm) * kTiles[i].tm;
+    const double pn = (double)((N + kTiles[i].tn - 1) / kTiles[i].tn) * kTiles[i].tn;
+    const double cost = pm * pn / kTiles[i].eff;
+    if (cost < bc) { bc = cost; best = i; }
+  }
+  return best;
+}
+
+template <typename J>
+const J* upload(const std::vector<J>& v, hipStream_t st) {
+  return static_cast<const J*>(DescArena::get().put(v.data(), v.size() * sizeof(J), st));
+}
+
+}  // namespace
+
+template <typename T>
+void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs) {
+  std::vector<GJob> by[5];
+  double fl[5] = {0, 0, 0, 0, 0}, bytes[5] = {0, 0, 0, 0, 0};
+  for (auto& J : jobs) {
+    if (J.M <= 0 || J.N <= 0 || J.nmat <= 0 || J.ncl <= 0 || J.nseg <= 0) continue;
+    const int cfg = pick_tile(J.M, J.N);
+    J.tilesM = (J.M + kTiles[cfg].tm - 1) / kTiles[cfg].tm;
+    J.tilesN = (J.N + kTiles[cfg].tn - 1) / kTiles[cfg].tn;
+    double K = 0;
+    for (int sg = 0; sg < J.nseg; ++sg) K += segs[J.seg0 + sg].K;
+    const double np = (double)J.nmat * J.ncl;
+    fl[cfg] += 2.0 * J.M * J.N * K * np;
+    bytes[cfg] += sizeof(T) * np * ((double)J.M * K + K * J.N + (double)J.M * J.N * (J.beta != 0.0 ? 2 : 1));
+    by[cfg].push_back(J);
+  }
+  const GSeg* dsegs = nullptr;
+  for (int cfg = 0; cfg < 5; ++cfg) {
+    if (by[cfg].empty()) continue;
+    if (!dsegs) dsegs = upload(segs, st);
+    long long b0 = 0;
+    for (auto& J : by[cfg]) {
+      J.block0 = b0;
+      b0 += (long long)J.nmat * J.ncl * J.tilesM * J.tilesN;
+    }
+    if (b0 > 0x7fffffffLL) fail(ACR_ERR_INVALID_ARG, "grouped GEMM grid too large");
+    const GJob* dj = upload(by[cfg], st);
+    const int nj = (int)by[cfg].size();
+    ProfScope ps(KC_GEMM, st, fl[cfg], bytes[cfg]);
+    switch (cfg) {
+      case 0: hipLaunchKernelGGL((k_ggemm<T, 64, 64, 16, 4, 4>), dim3((unsigned)b0), dim3(256), 0, st, dj, nj, dsegs); break;
+      case 1: hipLaunchKernelGGL((k_ggemm<T, 64, 16, 16, 4, 4>), dim3((unsigned)b0), dim3(64), 0, st, dj, nj, dsegs); break;
+      case 2: hipLaunchKernelGGL((k_ggemm<T, 16, 64, 16, 4, 4>), dim3((unsigned)b0), dim3(64), 0, st, dj, nj, dsegs); break;
+      case 3: hipLaunchKernelGGL((k_ggemm<T, 32, 32, 16, 4, 4>), dim3((unsigned)b0), dim3(64), 0, st, dj, nj, dsegs); break;
+      default: hipLaunchKernelGGL((k_ggemm<T, 16, 16, 16, 2, 2>), dim3((unsigned)b0), dim3(64), 0, st, dj, nj, dsegs); break;
+    }
+    ACR_CHECK_LAUNCH();
+  }
+}
+
 template <typename T>
 void bgemm(hipStream_t st, int M, int N, int K, int nmat, int ncl, T alpha, const BOp& A,
            const BOp& B, T beta, const BOp& C) {
   if (M <= 0 || N <= 0 || nmat <= 0 || ncl <= 0) return;
-  const int nprob = nmat * ncl;
-  ProfScope ps(KC_GEMM, st, 2.0 * M * N * K * nprob,
-               (double)sizeof(T) * nprob * ((double)M * K + (double)K * N + (double)M * N * (beta != T(0) ? 2 : 1)));
-  // pick the tile shape with the least padded area (bigger tiles preferred)
-  struct Cfg { int tm, tn; double eff; };
-  const Cfg cfgs[] = {{64, 64, 1.0}, {64, 16, 0.8}, {16, 64, 0.8}, {32, 32, 0.8}, {16, 16, 0.55}};
-  int best = 0;
-  double bc = 1e300;
-  for (int i = 0; i < 5; ++i) {
-    const double pm = (double)((M + cfgs[i].tm - 1) / cfgs[i].tm) * cfgs[i].tm;
-    const double pn = (double)((N + cfgs[i].tn - 1) / cfgs[i].tn) * cfgs[i].tn;
-    const double cost = pm * pn / cfgs[i].eff;
-    if (cost < bc) { bc = cost; best = i; }
-  }
-  switch (best) {
-    case 0: launch_gemm<T, 64, 64, 4, 4>(st, M, N, K, nprob, ncl, alpha, A, B, beta, C); break;
-    case 1: launch_gemm<T, 64, 16, 4, 4>(st, M, N, K, nprob, ncl, alpha, A, B, beta, C); break;
-    case 2: launch_gemm<T, 16, 64, 4, 4>(st, M, N, K, nprob, ncl, alpha, A, B, beta, C); break;
-    case 3: launch_gemm<T, 32, 32, 4, 4>(st, M, N, K, nprob, ncl, alpha, A, B, beta, C); break;
-    default: launch_gemm<T, 16, 16, 2, 2>(st, M, N, K, nprob, ncl, alpha, A, B, beta, C); break;
-  }
+  std::vector<GSeg> segs(1);
+  segs[0].A = A; segs[0].B = B; segs[0].K = K;
+  std::vector<GJob> jobs(1);
+  GJob& J = jobs[0];
+  J.M = M; J.N = N; J.nmat = nmat; J.ncl = ncl; J.seg0 = 0; J.nseg = 1;
+  J.alpha = (double)alpha; J.beta = (double)beta; J.C = C;
+  ggemm<T>(st, std::move(jobs), segs);
 }
 
 template <typename Tin, typename Tout>
@@ -831,83 +1031,198 @@ void binverse(hipStream_t st, int n, int nprob, const Tin* A, long long sA, Tout
 }
 
 template <typename T>
+void gqr(hipStream_t st, std::vector<QJob> jobs) {
+  std::vector<DBuf<T>> scratch;
+  std::vector<QJob> use;
+  size_t dyn = 0;
+  double fl = 0, by = 0;
+  long long b0 = 0;
+  for (auto& J : jobs) {
+    if (J.p <= 0 || J.k <= 0 || J.nmat <= 0 || J.ncl <= 0) continue;
+    const size_t np = (size_t)J.nmat * J.ncl;
+    const size_t panel = (size_t)J.p * J.k * sizeof(T), vb = (size_t)J.p * sizeof(T);
+    J.lds = panel + vb + 1024 <= kMaxLds;
+    if (J.lds) {
+      dyn = std::max(dyn, panel + vb);
+    } else {
+      scratch.emplace_back(np * J.p * J.k);
+      J.ws = scratch.back().get();
+      dyn = std::max(dyn, vb);
+    }
+    J.block0 = b0;
+    b0 += (long long)np;
+    const double p = J.p, k = J.k, kr = std::min(J.p, J.k);
+    fl += np * (p >= k ? 2.0 * k * k * (p - k / 3.0) : 2.0 * p * p * (k - p / 3.0));
+    by += (double)sizeof(T) * np * (p * k + kr * k + (J.Vref ? p * kr : 0.0));
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  const QJob* dj = upload(use, st);
+  ProfScope ps(KC_QR, st, fl, by);
+  hipLaunchKernelGGL((k_gqr<T>), dim3((unsigned)b0), dim3(256), dyn, st, dj, (int)use.size());
+  ACR_CHECK_LAUNCH();
+}
+
+template <typename T>
 void bqr_r(hipStream_t st, int p, int k, int nmat, int ncl, const BOp& A, T* R, T* Vref, T* tau) {
-  if (p <= 0 || k <= 0 || nmat <= 0) return;
-  const int nprob = nmat * ncl;
-  const double kr = std::min(p, k);
-  ProfScope ps(KC_QR, st,
-               nprob * (p >= k ? 2.0 * k * k * (p - k / 3.0) : 2.0 * p * p * (k - p / 3.0)),
-               (double)sizeof(T) * nprob * ((double)p * k + kr * k + (Vref ? (double)p * kr : 0.0)));
-  const size_t panel = (size_t)p * k * sizeof(T);
-  const size_t vbytes = (size_t)p * sizeof(T);
-  const bool use_lds = panel + vbytes + 1024 <= kMaxLds;
-  DBuf<T> ws;
-  if (!use_lds) ws.resize((size_t)nprob * p * k);
-  hipLaunchKernelGGL((k_qr_r<T>), dim3(nprob), dim3(256), use_lds ? panel + vbytes : vbytes, st, p,
-                     k, ncl, A, R, ws.get(), use_lds ? 1 : 0, Vref, tau);
+  std::vector<QJob> jobs(1);
+  QJob& J = jobs[0];
+  J.p = p; J.k = k; J.nmat = nmat; J.ncl = ncl; J.A = A; J.R = R; J.Vref = Vref; J.tau = tau;
+  gqr<T>(st, std::move(jobs));
+}
+
+template <typename T>
+void gapply_q(hipStream_t st, std::vector<AJob> jobs) {
+  std::vector<AJob> use;
+  double fl = 0, by = 0;
+  long long b0 = 0;
+  for (auto& J : jobs) {
+    if (J.p <= 0 || J.t <= 0 || J.nmat <= 0 || J.ncl <= 0) continue;
+    J.block0 = b0;
+    const double np = (double)J.nmat * J.ncl;
+    b0 += (long long)np;
+    fl += 4.0 * np * J.t * ((double)J.p * J.c - 0.5 * J.c * J.c);
+    by += (double)sizeof(T) * np * ((double)J.p * J.c + (double)J.c * J.t + (double)J.p * J.t);
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  const AJob* dj = upload(use, st);
+  ProfScope ps(KC_APPLYQ, st, fl, by);
+  hipLaunchKernelGGL((k_gapply_q<T>), dim3((unsigned)b0), dim3(256), 0, st, dj, (int)use.size());
   ACR_CHECK_LAUNCH();
 }
 
 template <typename T>
 void bapply_q(hipStream_t st, int p, int c, int t, int nmat, int ncl, const T* Vref, const T* tau,
               const T* Z, long long sZ, int zxor, const BOp& Y) {
-  if (p <= 0 || t <= 0 || nmat <= 0) return;
-  ProfScope ps(KC_APPLYQ, st, 4.0 * nmat * ncl * t * ((double)p * c - 0.5 * c * c),
-               (double)sizeof(T) * nmat * ncl * ((double)p * c + (double)c * t + (double)p * t));
-  hipLaunchKernelGGL((k_apply_q<T>), dim3(nmat * ncl), dim3(256), 0, st, p, c, t, ncl, Vref, tau, Z,
-                     sZ, zxor, Y);
+  std::vector<AJob> jobs(1);
+  AJob& J = jobs[0];
+  J.p = p; J.c = c; J.t = t; J.nmat = nmat; J.ncl = ncl; J.zxor = zxor;
+  J.Vref = Vref; J.tau = tau; J.Z = Z; J.sZ = sZ; J.Y = Y;
+  gapply_q<T>(st, std::move(jobs));
+}
+
+template <typename T>
+void grsvd(hipStream_t st, std::vector<SJob> jobs) {
+  std::vector<DBuf<T>> scratch;
+  std::vector<SJob> use;
+  Profiler& P = Profiler::get();
+  const bool prof = P.on(KC_SVD);
+  double* fl = nullptr;
+  long long b0 = 0, total = 0;
+  double by = 0;
+  for (auto& J : jobs) {
+    if (J.c <= 0 || J.nprob <= 0) continue;
+    if (J.c > 512) fail(ACR_ERR_INVALID_ARG, "rank-revealing SVD core larger than 512");
+    total += J.nprob;
+  }
+  if (total == 0) return;
+  if (prof) {
+    std::lock_guard<std::mutex> g(P.mu());
+    P.owned_d().emplace_back((size_t)total);
+    fl = P.owned_d().back().get();
+  }
+  for (auto& J : jobs) {
+    if (J.c <= 0 || J.nprob <= 0) continue;
+    scratch.emplace_back((size_t)J.nprob * J.c * J.c);
+    J.X = scratch.back().get();
+    scratch.emplace_back((size_t)J.nprob * J.c * J.c);
+    J.J = scratch.back().get();
+    J.flops = fl ? fl + b0 : nullptr;
+    J.block0 = b0;
+    b0 += J.nprob;
+    by += 4.0 * (double)J.c * J.c * J.nprob * sizeof(T);
+    use.push_back(J);
+  }
+  const SJob* dj = upload(use, st);
+  ProfScope ps(KC_SVD, st, 0.0, by);
+  ps.r.dev_flops = fl; ps.r.nprob = (int)total;
+  hipLaunchKernelGGL((k_grsvd<T>), dim3((unsigned)b0), dim3(256), 0, st, dj, (int)use.size());
   ACR_CHECK_LAUNCH();
 }
 
 template <typename T>
-void bsvd(hipStream_t st, int c, int nprob, T* K, T* sig, T* Usc, T* J, int* rank, double eps,
-          int maxrank) {
-  if (c <= 0 || nprob <= 0) return;
-  if (c > 512) fail(ACR_ERR_INVALID_ARG, "bsvd: core larger than 512");
-  DBuf<T> Jw((size_t)nprob * c * c);
-  int* sweeps = nullptr;
-  Profiler& P = Profiler::get();
-  if (P.on(KC_SVD)) {
-    std::lock_guard<std::mutex> g(P.mu());
-    P.owned().emplace_back((size_t)nprob);
-    sweeps = P.owned().back().get();
+void brsvd(hipStream_t st, int c, int nprob, T* K, T* sig, T* UK, int* rank, double eps, int maxrank) {
+  std::vector<SJob> jobs(1);
+  SJob& J = jobs[0];
+  J.c = c; J.nprob = nprob; J.K = K; J.sig = sig; J.UK = UK; J.rank = rank; J.eps = eps; J.maxrank = maxrank;
+  grsvd<T>(st, std::move(jobs));
+}
+
+template <typename T>
+void gtrunc(hipStream_t st, std::vector<TJob> jobs) {
+  std::vector<TJob> use;
+  long long b0 = 0;
+  for (auto& J : jobs) {
+    if (J.c <= 0 || J.kout <= 0 || J.nprob <= 0) continue;
+    J.block0 = b0;
+    b0 += J.nprob;
+    use.push_back(J);
   }
-  ProfScope ps(KC_SVD, st, 0.0, 3.0 * (double)c * c * nprob * sizeof(T));
-  ps.r.dev_sweeps = sweeps; ps.r.nprob = nprob; ps.r.c = c;
-  hipLaunchKernelGGL((k_svd<T>), dim3(nprob), dim3(256), 0, st, c, K, Jw.get(), sig, Usc, J, rank,
-                     eps, maxrank, sweeps);
+  if (use.empty()) return;
+  const TJob* dj = upload(use, st);
+  ProfScope ps(KC_COPY, st, 0.0, 0.0);
+  hipLaunchKernelGGL((k_gtrunc<T>), dim3((unsigned)b0), dim3(256), 0, st, dj, (int)use.size());
   ACR_CHECK_LAUNCH();
 }
 
 template <typename T>
 void btrunc_coef(hipStream_t st, int c, int kout, int nprob, const T* J, const int* rank, T* Jt) {
-  if (c <= 0 || kout <= 0 || nprob <= 0) return;
-  dim3 g(grid1((long long)c * kout, 256, 64), nprob);
-  hipLaunchKernelGGL((k_trunc_coef<T>), g, dim3(256), 0, st, c, kout, J, rank, Jt);
+  std::vector<TJob> jobs(1);
+  jobs[0].c = c; jobs[0].kout = kout; jobs[0].nprob = nprob; jobs[0].UK = J; jobs[0].rank = rank; jobs[0].Ut = Jt;
+  gtrunc<T>(st, std::move(jobs));
+}
+
+void gmax(hipStream_t st, const std::vector<MJob>& jobs) {
+  if (jobs.empty()) return;
+  const MJob* dj = upload(jobs, st);
+  hipLaunchKernelGGL(k_gmax, dim3((unsigned)jobs.size()), dim3(256), 0, st, dj);
   ACR_CHECK_LAUNCH();
 }
 
 void bmax_int(hipStream_t st, const int* rank, int n, int* out) {
-  hipLaunchKernelGGL(k_max_int, dim3(1), dim3(256), 0, st, rank, n, out);
+  std::vector<MJob> jobs(1);
+  jobs[0].rank = rank; jobs[0].n = n; jobs[0].out = out;
+  gmax(st, jobs);
+}
+
+template <typename T>
+void gcopy(hipStream_t st, std::vector<CJob> jobs) {
+  std::vector<CJob> use;
+  long long b0 = 0;
+  double by = 0;
+  for (auto& J : jobs) {
+    if (J.rows <= 0 || J.cols <= 0 || J.nmat <= 0 || J.ncl <= 0) continue;
+    const long long n = (long long)J.rows * J.cols;
+    J.chunks = (int)((n + kCopyChunk - 1) / kCopyChunk);
+    J.block0 = b0;
+    b0 += (long long)J.nmat * J.ncl * J.chunks;
+    by += (2.0 + J.accumulate) * n * J.nmat * J.ncl * sizeof(T);
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  if (b0 > 0x7fffffffLL) fail(ACR_ERR_INVALID_ARG, "grouped copy grid too large");
+  const CJob* dj = upload(use, st);
+  ProfScope ps(KC_COPY, st, 0.0, by);
+  hipLaunchKernelGGL((k_gcopy<T>), dim3((unsigned)b0), dim3(256), 0, st, dj, (int)use.size());
   ACR_CHECK_LAUNCH();
 }
 
 template <typename T>
 void bcopy(hipStream_t st, int rows, int cols, int nmat, T alpha, const BOp& src, const BOp& dst) {
-  if (rows <= 0 || cols <= 0 || nmat <= 0) return;
-  ProfScope ps(KC_COPY, st, 0.0, 2.0 * rows * cols * nmat * sizeof(T));
-  dim3 g(grid1((long long)rows * cols, 256, 1024), nmat);
-  hipLaunchKernelGGL((k_bcopy<T>), g, dim3(256), 0, st, rows, cols, alpha, src, dst, 0);
-  ACR_CHECK_LAUNCH();
+  std::vector<CJob> jobs(1);
+  CJob& J = jobs[0];
+  J.rows = rows; J.cols = cols; J.nmat = nmat; J.ncl = 1; J.alpha = (double)alpha; J.src = src; J.dst = dst;
+  gcopy<T>(st, std::move(jobs));
 }
 
 template <typename T>
 void badd(hipStream_t st, int rows, int cols, int nmat, T alpha, const BOp& src, const BOp& dst) {
-  if (rows <= 0 || cols <= 0 || nmat <= 0) return;
-  ProfScope ps(KC_COPY, st, (double)rows * cols * nmat, 3.0 * rows * cols * nmat * sizeof(T));
-  dim3 g(grid1((long long)rows * cols, 256, 1024), nmat);
-  hipLaunchKernelGGL((k_bcopy<T>), g, dim3(256), 0, st, rows, cols, alpha, src, dst, 1);
-  ACR_CHECK_LAUNCH();
+  std::vector<CJob> jobs(1);
+  CJob& J = jobs[0];
+  J.rows = rows; J.cols = cols; J.nmat = nmat; J.ncl = 1; J.alpha = (double)alpha; J.src = src; J.dst = dst;
+  J.accumulate = 1;
+  gcopy<T>(st, std::move(jobs));
 }
 
 template <typename T>
@@ -920,12 +1235,11 @@ void fill(hipStream_t st, T* p, size_t n, T v) {
 template <typename T>
 void bscale(hipStream_t st, int rows, int cols, int nmat, int ncl, const BOp& X, const T* vec,
             int vmul, int voff, long long vstride, long long vcl, int side, T alpha) {
-  if (rows <= 0 || cols <= 0 || nmat <= 0) return;
-  ProfScope ps(KC_COPY, st, (double)rows * cols * nmat * ncl, 2.0 * rows * cols * nmat * ncl * sizeof(T));
-  dim3 g(grid1((long long)rows * cols, 256, 256), nmat * ncl);
-  hipLaunchKernelGGL((k_bscale<T>), g, dim3(256), 0, st, rows, cols, ncl, X, vec, vmul, voff,
-                     vstride, vcl, side, alpha);
-  ACR_CHECK_LAUNCH();
+  std::vector<CJob> jobs(1);
+  CJob& J = jobs[0];
+  J.rows = rows; J.cols = cols; J.nmat = nmat; J.ncl = ncl; J.alpha = (double)alpha; J.src = X; J.dst = X;
+  J.scale = vec; J.smul = vmul; J.soff = voff; J.sstride = vstride; J.scl = vcl; J.sside = side;
+  gcopy<T>(st, std::move(jobs));
 }
 
 template <typename T>
@@ -1049,12 +1363,18 @@ void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
 }
 
 #define INST(T)                                                                                   \
+  template void ggemm<T>(hipStream_t, std::vector<GJob>, const std::vector<GSeg>&);               \
+  template void gqr<T>(hipStream_t, std::vector<QJob>);                                           \
+  template void grsvd<T>(hipStream_t, std::vector<SJob>);                                         \
+  template void gapply_q<T>(hipStream_t, std::vector<AJob>);                                      \
+  template void gtrunc<T>(hipStream_t, std::vector<TJob>);                                        \
+  template void gcopy<T>(hipStream_t, std::vector<CJob>);                                         \
   template void bgemm<T>(hipStream_t, int, int, int, int, int, T, const BOp&, const BOp&, T,      \
                          const BOp&);                                                             \
   template void bqr_r<T>(hipStream_t, int, int, int, int, const BOp&, T*, T*, T*);                \
   template void bapply_q<T>(hipStream_t, int, int, int, int, int, const T*, const T*, const T*,   \
                             long long, int, const BOp&);                                          \
-  template void bsvd<T>(hipStream_t, int, int, T*, T*, T*, T*, int*, double, int);                \
+  template void brsvd<T>(hipStream_t, int, int, T*, T*, T*, int*, double, int);                   \
   template void btrunc_coef<T>(hipStream_t, int, int, int, const T*, const int*, T*);             \
   template void bcopy<T>(hipStream_t, int, int, int, T, const BOp&, const BOp&);                  \
   template void badd<T>(hipStream_t, int, int, int, T, const BOp&, const BOp&);                   \

@@ -3,9 +3,115 @@
 // p = m*ncl + c (matrix m, cluster c) unless stated otherwise.
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace acr {
+
+// ------------------------------------------------------------ grouped jobs
+// A grouped launch runs a list of independent jobs (each a batch of uniform
+// problems) in one kernel; workgroups [block0, next block0) belong to a job.
+constexpr int kMaxSeg = 16;
+
+// C = alpha * sum_s op(A_s) op(B_s) + beta * C over the problems (m, c) of a
+// job; segment s contributes a K_s-deep product (a K-concatenated GEMM).
+struct GSeg {
+  BOp A, B;
+  int K = 0, pad = 0;
+  double scale = 1.0;   // multiplies this segment's product
+};
+struct GJob {
+  long long block0 = 0;
+  int M = 0, N = 0, nmat = 0, ncl = 0;
+  int tilesM = 0, tilesN = 0, seg0 = 0, nseg = 0;
+  double alpha = 1.0, beta = 0.0;
+  BOp C;
+};
+
+// Householder R (and optionally reflectors) of p x k panels, one workgroup
+// per problem; R at R + prob*c*k (c = min(p, k), ld c), reflectors at
+// Vref + prob*p*c, tau + prob*c; ws = global scratch when the panel does not
+// fit in LDS (p*k per problem).
+struct QJob {
+  long long block0 = 0;
+  int p = 0, k = 0, nmat = 0, ncl = 0;
+  BOp A;
+  void* R = nullptr;
+  void* Vref = nullptr;
+  void* tau = nullptr;
+  void* ws = nullptr;
+  int lds = 0, pad = 0;
+};
+
+// Rank-revealing SVD of c x c cores (see brsvd).
+struct SJob {
+  long long block0 = 0;
+  int c = 0, nprob = 0;
+  void* K = nullptr;
+  void* X = nullptr;
+  void* J = nullptr;
+  void* sig = nullptr;
+  void* UK = nullptr;
+  int* rank = nullptr;
+  double* flops = nullptr;
+  double eps = 0.0;
+  int maxrank = 0, pad = 0;
+};
+
+// Y_(m,c) = Q_(m,c) [Z_(m, c^zxor); 0] with reflectors of a QJob.
+struct AJob {
+  long long block0 = 0;
+  int p = 0, c = 0, t = 0, nmat = 0, ncl = 0, zxor = 0;
+  const void* Vref = nullptr;
+  const void* tau = nullptr;
+  const void* Z = nullptr;
+  long long sZ = 0;
+  BOp Y;
+};
+
+// Ut_p = UK_p[:, :kout] with columns >= rank_p zeroed (c x kout).
+struct TJob {
+  long long block0 = 0;
+  int c = 0, kout = 0, nprob = 0, pad = 0;
+  const void* UK = nullptr;
+  const int* rank = nullptr;
+  void* Ut = nullptr;
+};
+
+// *out = max(rank[0..n)).
+struct MJob {
+  const int* rank = nullptr;
+  int* out = nullptr;
+  int n = 0, pad = 0;
+};
+
+// dst_(m,c) (= or +=) alpha * diag? * src_(m,c), rows x cols each; optional
+// scale vector: element (r, q) is multiplied by
+// scale[(smul*m + soff)*sstride + c*scl + (sside ? q : r)].
+struct CJob {
+  long long block0 = 0;
+  int rows = 0, cols = 0, nmat = 0, ncl = 0, chunks = 0, accumulate = 0;
+  double alpha = 1.0;
+  BOp src, dst;
+  const void* scale = nullptr;
+  int smul = 1, soff = 0, sside = 0, pad = 0;
+  long long sstride = 0, scl = 0;
+};
+
+template <typename T>
+void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs);
+template <typename T>
+void gqr(hipStream_t st, std::vector<QJob> jobs);
+template <typename T>
+void grsvd(hipStream_t st, std::vector<SJob> jobs);
+template <typename T>
+void gapply_q(hipStream_t st, std::vector<AJob> jobs);
+template <typename T>
+void gtrunc(hipStream_t st, std::vector<TJob> jobs);
+void gmax(hipStream_t st, const std::vector<MJob>& jobs);
+template <typename T>
+void gcopy(hipStream_t st, std::vector<CJob> jobs);
 
 // C_p = alpha * op(A_p) op(B_p) + beta * C_p, all problems M x N x K.
 // beta == 0 overwrites C without reading it.
@@ -36,13 +142,14 @@ template <typename T>
 void bapply_q(hipStream_t st, int p, int c, int t, int nmat, int ncl, const T* Vref, const T* tau,
               const T* Z, long long sZ, int zxor, const BOp& Y);
 
-// One-sided Jacobi SVD of each c x c matrix K_p (at K + p*c*c, ld c):
-// K_p J_p = Usc_p, columns sorted by decreasing norm sig.  Outputs (per
-// problem, contiguous): sig[c], Usc[c*c], J[c*c]; rank_p = #{sig > eps*sig_1}
-// capped by maxrank (> 0).  K is overwritten.
+// Rank-revealing SVD of each c x c core K_p (at K + p*c*c, ld c; overwritten):
+// column-pivoted QR stopped at 0.1*eps of the largest column, one-sided Jacobi
+// on the thin transposed triangle, left singular vectors U_K = Q_K [J; 0].
+// Outputs per problem: sig[c] sorted decreasing, UK (c x c, columns = left
+// singular vectors in that order, zero past the numerical rank), rank_p =
+// #{sig > eps*sig_1} capped by maxrank (> 0).
 template <typename T>
-void bsvd(hipStream_t st, int c, int nprob, T* K, T* sig, T* Usc, T* J, int* rank, double eps,
-          int maxrank);
+void brsvd(hipStream_t st, int c, int nprob, T* K, T* sig, T* UK, int* rank, double eps, int maxrank);
 
 // Truncation: Jt = J[:, :kout] with columns >= rank_p zeroed (c x kout per problem).
 template <typename T>
