@@ -163,10 +163,20 @@ void hmul(hipStream_t st, HV<T> H, int nmat, int dfrom, bool trans, int ncol, T 
 }
 
 // ------------------------------------------------------------ hprod_multi
+// For every output C = D + sum_t coef_t A_t B_t (exact low-rank accumulation):
+//   depth-d block of A B = A[t,t] B[t,s] + A[t,s] B[s,s] + ancestor terms
+//                        = (Adiag_{>d} U^B_d) V^B_d^T + U^A_d (Bdiag_{>d}^T V^A_d)^T + ...
+// The products Adiag_{>d} U^B_d of all depths d are one pass over A's leaves:
+// with Y = [U^B_1 | ... | U^B_L] (column block d), the depth-e reduction
+// T_e = V^A_e[cl]^T Y[cl] is kept only for the column blocks d < e (the rest
+// stays zero), and out = leaves(A) Y + sum_e U^A_e[rows] T_e[sibling ancestor]
+// holds every Adiag_{>d} U^B_d in its column block d.  Same for the
+// transposed side.  Stages: copies in, reductions + cores, ancestor parts,
+// copies, expansions + leaves, copies out.
 template <typename T>
 void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
   GemmPlan s1, s2, s3;
-  std::vector<CJob> copies;
+  std::vector<CJob> cin, cmid, cout;
   std::vector<DBuf<T>> keep;
   struct Anc {
     int w = 0;
@@ -177,18 +187,33 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
     long long vps = 0;
     int vpm = 1, vpo = 0;
   };
+  // reduction outputs of all terms live in one zero-initialised buffer
+  size_t tsize = 0;
+  for (auto& O : outs) {
+    const HSet<T>& g = O.terms.empty() ? *O.D.h : *O.terms[0].A.h;
+    for (auto& tm : O.terms) {
+      int NA = 0, NB = 0;
+      for (int d = 1; d <= g.L; ++d) { NA += tm.A.h->kc[d]; NB += tm.B.h->kc[d]; }
+      for (int e = 1; e <= g.L; ++e)
+        tsize += (size_t)O.nmat * ((size_t)1 << e) * ((size_t)tm.A.h->kc[e] * NB + (size_t)tm.B.h->kc[e] * NA);
+    }
+  }
+  DBuf<T> tbuf(tsize);
+  if (tsize) ACR_HIP(hipMemsetAsync(tbuf.get(), 0, tsize * sizeof(T), st));
+  size_t toff = 0;
   for (auto& O : outs) {
     const int nmat = O.nmat;
     const HSet<T>& g = O.terms.empty() ? *O.D.h : *O.terms[0].A.h;
     const int L = g.L, s = g.s, b = g.b, nleaf = g.nleaf();
-    // Ancestor terms of each product: for depth e the block A[p, q] B[q, p]
-    // (q = sib p) is U^A_p (V^A_p^T U^B_q) V^B_q^T, restricted to every block
-    // below p; stored as a flat (Upart, Vpart) pair of width min(kA, kB).
     std::vector<std::vector<Anc>> anc(O.terms.size(), std::vector<Anc>(L + 1));
+    std::vector<const T*> outA(O.terms.size(), nullptr), outB(O.terms.size(), nullptr);
+    std::vector<std::vector<int>> cAo(O.terms.size()), cBo(O.terms.size());
     for (size_t t = 0; t < O.terms.size(); ++t) {
+      const double coef = O.terms[t].coef;
       const HV<T> A = O.terms[t].A, B = O.terms[t].B;
       const HSet<T>& a = *A.h;
       const HSet<T>& bb = *B.h;
+      // ancestor terms (see the block comment above)
       for (int d = 1; d <= L; ++d) {
         const int kA = a.kc[d], kB = bb.kc[d];
         if (kA == 0 || kB == 0) continue;
@@ -214,6 +239,67 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
           an.vp = keep.back().get(); an.vps = (long long)kA * s; an.vpm = 1; an.vpo = 0;
         }
       }
+      // stacked inputs Y = [U^B_1 | ... | U^B_L], Y' = [V^A_1 | ... | V^A_L]
+      std::vector<int>& cB = cBo[t];
+      std::vector<int>& cA = cAo[t];
+      cB.assign(L + 2, 0);
+      cA.assign(L + 2, 0);
+      for (int d = 1; d <= L; ++d) { cB[d + 1] = cB[d] + bb.kc[d]; cA[d + 1] = cA[d] + a.kc[d]; }
+      const int NB = cB[L + 1], NA = cA[L + 1];
+      if (NB > 0) {
+        keep.emplace_back((size_t)nmat * NB * s);
+        T* Y = keep.back().get();
+        for (int d = 1; d <= L; ++d)
+          if (bb.kc[d])
+            cin.push_back(copy_job(s, bb.kc[d], nmat, 1.0, factor_op(B, bb.U[d], d, 0),
+                                   bop(Y + (size_t)cB[d] * s, s, (long long)NB * s)));
+        keep.emplace_back((size_t)nmat * NB * s);
+        T* Oa = keep.back().get();
+        outA[t] = Oa;
+        // reductions: T_e = V^A_e[cl]^T Y[cl] on the column blocks d < e
+        BOp leafA = leaves_op(A);
+        std::vector<GSeg> ex{seg(leafA, bop(Y, s, (long long)NB * s, b), b, coef)};
+        for (int e = 1; e <= L; ++e) {
+          const int w = a.kc[e];
+          const int ncl = 1 << e, sd = g.sd(e);
+          if (w == 0) continue;
+          T* Te = tbuf.get() + toff;
+          toff += (size_t)nmat * ncl * w * NB;
+          BOp Tc = bop(Te, w, (long long)ncl * w * NB, (long long)w * NB);
+          if (cB[e] > 0)
+            s1.add(w, cB[e], nmat, ncl, 1.0, 0.0, Tc,
+                   {seg(transposed(factor_op(A, a.V[e], e, sd)), bop(Y, s, (long long)NB * s, sd), sd)});
+          ex.push_back(seg(factor_op(A, a.U[e], e, b), ancestor(Tc, L - e, 1), w, coef));
+        }
+        s3.add(b, NB, nmat, nleaf, 1.0, 0.0, bop(Oa, s, (long long)NB * s, b), ex);
+      }
+      if (NA > 0) {
+        keep.emplace_back((size_t)nmat * NA * s);
+        T* Y = keep.back().get();
+        for (int d = 1; d <= L; ++d)
+          if (a.kc[d])
+            cin.push_back(copy_job(s, a.kc[d], nmat, 1.0, factor_op(A, a.V[d], d, 0),
+                                   bop(Y + (size_t)cA[d] * s, s, (long long)NA * s)));
+        keep.emplace_back((size_t)nmat * NA * s);
+        T* Ob = keep.back().get();
+        outB[t] = Ob;
+        BOp leafB = leaves_op(B);
+        leafB.trans = 1;
+        std::vector<GSeg> ex{seg(leafB, bop(Y, s, (long long)NA * s, b), b, 1.0)};
+        for (int e = 1; e <= L; ++e) {
+          const int w = bb.kc[e];
+          const int ncl = 1 << e, sd = g.sd(e);
+          if (w == 0) continue;
+          T* Te = tbuf.get() + toff;
+          toff += (size_t)nmat * ncl * w * NA;
+          BOp Tc = bop(Te, w, (long long)ncl * w * NA, (long long)w * NA);
+          if (cA[e] > 0)
+            s1.add(w, cA[e], nmat, ncl, 1.0, 0.0, Tc,
+                   {seg(transposed(factor_op(B, bb.U[e], e, sd)), bop(Y, s, (long long)NA * s, sd), sd)});
+          ex.push_back(seg(factor_op(B, bb.V[e], e, b), ancestor(Tc, L - e, 1), w, 1.0));
+        }
+        s3.add(b, NA, nmat, nleaf, 1.0, 0.0, bop(Ob, s, (long long)NA * s, b), ex);
+      }
     }
     std::vector<int> kC(L + 1, 0);
     for (int d = 1; d <= L; ++d) {
@@ -227,12 +313,12 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
     C.alloc(st, O.cnt_alloc, s, b, L, kC, O.cnt_alloc > nmat);
     for (int d = 1; d <= L; ++d) {
       int col = 0;
-      auto cu = [&](int c0, long long sc) { return bop(C.U[d].get() + (size_t)c0 * s, s, (long long)C.k[d] * s, sc); };
-      auto cv = [&](int c0, long long sc) { return bop(C.V[d].get() + (size_t)c0 * s, s, (long long)C.k[d] * s, sc); };
+      auto cu = [&](int c0) { return bop(C.U[d].get() + (size_t)c0 * s, s, (long long)C.k[d] * s); };
+      auto cv = [&](int c0) { return bop(C.V[d].get() + (size_t)c0 * s, s, (long long)C.k[d] * s); };
       if (O.has_d && O.D.h->kc[d]) {
         const int w = O.D.h->kc[d];
-        copies.push_back(copy_job(s, w, nmat, 1.0, factor_op(O.D, O.D.h->U[d], d, 0), cu(col, 0)));
-        copies.push_back(copy_job(s, w, nmat, 1.0, factor_op(O.D, O.D.h->V[d], d, 0), cv(col, 0)));
+        cmid.push_back(copy_job(s, w, nmat, 1.0, factor_op(O.D, O.D.h->U[d], d, 0), cu(col)));
+        cmid.push_back(copy_job(s, w, nmat, 1.0, factor_op(O.D, O.D.h->V[d], d, 0), cv(col)));
         col += w;
       }
       for (size_t t = 0; t < O.terms.size(); ++t) {
@@ -241,23 +327,23 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
         const HSet<T>& a = *A.h;
         const HSet<T>& bb = *B.h;
         const int kA = a.kc[d], kB = bb.kc[d];
-        if (kB > 0) {   // A[t,t] B[t,s] = (Adiag U^B) V^B^T
-          auto sg = plan_hmul<T>(s1, keep, A, nmat, d, false, kB, coef, flat_set(B, bb.U[d], d));
-          s3.add(b, kB, nmat, nleaf, 1.0, 0.0, cu(col, b), sg);
-          copies.push_back(copy_job(s, kB, nmat, 1.0, factor_op(B, bb.V[d], d, 0), cv(col, 0)));
+        if (kB > 0) {   // (Adiag U^B) V^B^T: column block d of the A-side pass
+          const int NB = cBo[t][L + 1];
+          cout.push_back(copy_job(s, kB, nmat, 1.0, bop(outA[t] + (size_t)cBo[t][d] * s, s, (long long)NB * s), cu(col)));
+          cmid.push_back(copy_job(s, kB, nmat, 1.0, factor_op(B, bb.V[d], d, 0), cv(col)));
           col += kB;
         }
-        if (kA > 0) {   // A[t,s] B[s,s] = U^A (Bdiag^T V^A)^T
-          copies.push_back(copy_job(s, kA, nmat, coef, factor_op(A, a.U[d], d, 0), cu(col, 0)));
-          auto sg = plan_hmul<T>(s1, keep, B, nmat, d, true, kA, 1.0, flat_set(A, a.V[d], d));
-          s3.add(b, kA, nmat, nleaf, 1.0, 0.0, cv(col, b), sg);
+        if (kA > 0) {   // U^A (Bdiag^T V^A)^T: column block d of the transposed pass
+          const int NA = cAo[t][L + 1];
+          cmid.push_back(copy_job(s, kA, nmat, coef, factor_op(A, a.U[d], d, 0), cu(col)));
+          cout.push_back(copy_job(s, kA, nmat, 1.0, bop(outB[t] + (size_t)cAo[t][d] * s, s, (long long)NA * s), cv(col)));
           col += kA;
         }
         for (int e = 1; e < d; ++e) {
           const Anc& an = anc[t][e];
           if (!an.w) continue;
-          copies.push_back(copy_job(s, an.w, nmat, coef, with_map(bop(an.up, s, an.ups), an.upm, an.upo), cu(col, 0)));
-          copies.push_back(copy_job(s, an.w, nmat, 1.0, with_map(bop(an.vp, s, an.vps), an.vpm, an.vpo), cv(col, 0)));
+          cmid.push_back(copy_job(s, an.w, nmat, coef, with_map(bop(an.up, s, an.ups), an.upm, an.upo), cu(col)));
+          cmid.push_back(copy_job(s, an.w, nmat, 1.0, with_map(bop(an.vp, s, an.vps), an.vpm, an.vpo), cv(col)));
           col += an.w;
         }
       }
@@ -277,15 +363,17 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
     }
     const BOp CL = bop(C.lv.get(), b, C.leaf_stride(), (long long)b * b);
     if (O.has_d)
-      copies.push_back(copy_job((int)O.D.h->leaf_stride(), 1, nmat, 1.0,
-                                with_map(bop(O.D.h->lv.get(), 1, O.D.h->leaf_stride()), O.D.mmul, O.D.moff),
-                                bop(C.lv.get(), 1, C.leaf_stride())));
+      cmid.push_back(copy_job((int)O.D.h->leaf_stride(), 1, nmat, 1.0,
+                              with_map(bop(O.D.h->lv.get(), 1, O.D.h->leaf_stride()), O.D.mmul, O.D.moff),
+                              bop(C.lv.get(), 1, C.leaf_stride())));
     if (!ls.empty()) s3.add(b, b, nmat, nleaf, 1.0, O.has_d ? 1.0 : 0.0, CL, ls);
   }
+  gcopy<T>(st, cin);
   s1.run<T>(st);
   s2.run<T>(st);
-  gcopy<T>(st, copies);
+  gcopy<T>(st, cmid);
   s3.run<T>(st);
+  gcopy<T>(st, cout);
 }
 
 // ------------------------------------------------------------------- hinv

@@ -156,6 +156,206 @@ __global__ __launch_bounds__((TM / RM) * (TN / RN)) void k_ggemm(const GJob* __r
   }
 }
 
+// Reduction GEMM C = sum_s scale_s A_s^T B_s with long K (A_s: K x M, B_s:
+// K x N, both column-major).  A workgroup owns an 8 x 8 output tile; its four
+// waves split K (wave w takes k = 64 w + lane, step 256), every lane keeps the
+// 64 partial sums of the tile (coalesced loads, each element read once), a
+// butterfly transpose-reduction leaves lane l with output l of its wave, and
+// the four waves are summed through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_dot(const GJob* __restrict__ jobs, int njobs,
+                                                 const GSeg* __restrict__ segs) {
+  __shared__ T red[4][64];
+  const long long bid = blockIdx.x;
+  const GJob& J = jobs[job_of(jobs, njobs, bid)];
+  const int tilesM = J.tilesM;
+  const int tiles = tilesM * J.tilesN;
+  const long long local = bid - J.block0;
+  const int prob = (int)(local / tiles);
+  const int t = (int)(local % tiles);
+  const int tm = t % tilesM, tn = t / tilesM;
+  const int m = prob / J.ncl, c = prob % J.ncl;
+  const int M = J.M, N = J.N;
+  const int lane = threadIdx.x % WAVE;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int i0 = tm * 8, j0 = tn * 8;
+  T acc[64];
+#pragma unroll
+  for (int q = 0; q < 64; ++q) acc[q] = T(0);
+  for (int sg = 0; sg < J.nseg; ++sg) {
+    const GSeg& S = segs[J.seg0 + sg];
+    const int K = S.K, lda = S.A.ld, ldb = S.B.ld;
+    const T sc = (T)S.scale;
+    const T* Ap = optr<T>(S.A, m, c);
+    const T* Bp = optr<T>(S.B, m, c);
+    for (int k = wv * WAVE + lane; k < K; k += 4 * WAVE) {
+      T a[8], bv[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) a[r] = (i0 + r < M) ? Ap[k + (long long)(i0 + r) * lda] * sc : T(0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) bv[q] = (j0 + q < N) ? Bp[k + (long long)(j0 + q) * ldb] : T(0);
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[r * 8 + q] = fma(a[r], bv[q], acc[r * 8 + q]);
+    }
+  }
+  // butterfly transpose-reduction: after step h (partner lane ^ (32 >> h)) a
+  // lane keeps the half of its values selected by that lane bit; at the end
+  // lane l holds the wave's sum for output l
+#pragma unroll
+  for (int h = 0; h < 6; ++h) {
+    const int half = 32 >> h;
+    const bool hi = (lane & half) != 0;
+#pragma unroll
+    for (int q = 0; q < half; ++q) {
+      const T send = hi ? acc[q] : acc[q + half];
+      const T keep = hi ? acc[q + half] : acc[q];
+      acc[q] = keep + __shfl_xor(send, half, WAVE);
+    }
+  }
+  red[wv][lane] = acc[0];
+  __syncthreads();
+  if (wv == 0) {
+    const T v0 = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    const int gi = i0 + lane / 8, gj = j0 + lane % 8;
+    if (gi < M && gj < N) {
+      T* cp = const_cast<T*>(optr<T>(J.C, m, c)) + gi + (long long)gj * J.C.ld;
+      T v = (T)J.alpha * v0;
+      if (J.beta != 0.0) v = fma((T)J.beta, *cp, v);
+      *cp = v;
+    }
+  }
+}
+
+// Short-K reduction GEMM C = sum_s scale_s A_s^T B_s with outputs up to
+// 16 x 16 per workgroup: 64-deep K slices of A^T and B are staged through LDS
+// with loads coalesced along K, then thread t accumulates output
+// (t % 16, t / 16) of the tile.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_small(const GJob* __restrict__ jobs, int njobs,
+                                                   const GSeg* __restrict__ segs) {
+  constexpr int KS = 64;
+  __shared__ T As[KS][17];
+  __shared__ T Bs[KS][17];
+  const long long bid = blockIdx.x;
+  const GJob& J = jobs[job_of(jobs, njobs, bid)];
+  const int tilesM = J.tilesM;
+  const int tiles = tilesM * J.tilesN;
+  const long long local = bid - J.block0;
+  const int prob = (int)(local / tiles);
+  const int t = (int)(local % tiles);
+  const int tm = t % tilesM, tn = t / tilesM;
+  const int m = prob / J.ncl, c = prob % J.ncl;
+  const int M = J.M, N = J.N;
+  const int tid = threadIdx.x;
+  const int i0 = tm * 16, j0 = tn * 16;
+  const int oi = tid % 16, oj = tid / 16;
+  T acc = T(0);
+  for (int sg = 0; sg < J.nseg; ++sg) {
+    const GSeg& S = segs[J.seg0 + sg];
+    const int K = S.K, lda = S.A.ld, ldb = S.B.ld;
+    const T sc = (T)S.scale;
+    const T* Ap = optr<T>(S.A, m, c);
+    const T* Bp = optr<T>(S.B, m, c);
+    for (int k0 = 0; k0 < K; k0 += KS) {
+      for (int e = tid; e < KS * 16; e += 256) {
+        const int kk = e % KS, q = e / KS;
+        const int k = k0 + kk;
+        As[kk][q] = (k < K && i0 + q < M) ? Ap[k + (long long)(i0 + q) * lda] * sc : T(0);
+        Bs[kk][q] = (k < K && j0 + q < N) ? Bp[k + (long long)(j0 + q) * ldb] : T(0);
+      }
+      __syncthreads();
+#pragma unroll 16
+      for (int kk = 0; kk < KS; ++kk) acc = fma(As[kk][oi], Bs[kk][oj], acc);
+      __syncthreads();
+    }
+  }
+  const int gi = i0 + oi, gj = j0 + oj;
+  if (gi < M && gj < N) {
+    T* cp = const_cast<T*>(optr<T>(J.C, m, c)) + gi + (long long)gj * J.C.ld;
+    T v = (T)J.alpha * acc;
+    if (J.beta != 0.0) v = fma((T)J.beta, *cp, v);
+    *cp = v;
+  }
+}
+
+// Row GEMM C = sum_s scale_s op(A_s) B_s for tall outputs with few columns
+// (N <= NMAX): a workgroup owns 64 output rows (one per lane) and its four
+// waves split K in groups of 8 (wave w takes groups w, w+4, ...).  B(k, :) is
+// the same for every lane of a wave (a broadcast read), A is read per lane;
+// no LDS staging or barriers in the main loop.  The waves' partial sums are
+// combined through LDS at the end.
+template <typename T, int NMAX>
+__global__ __launch_bounds__(256) void k_gemm_rows(const GJob* __restrict__ jobs, int njobs,
+                                                  const GSeg* __restrict__ segs) {
+  __shared__ T red[3][64][16];
+  const long long bid = blockIdx.x;
+  const GJob& J = jobs[job_of(jobs, njobs, bid)];
+  const int tilesM = J.tilesM;
+  const long long local = bid - J.block0;
+  const int prob = (int)(local / tilesM);
+  const int tm = (int)(local % tilesM);
+  const int m = prob / J.ncl, c = prob % J.ncl;
+  const int M = J.M, N = J.N;
+  const int lane = threadIdx.x % WAVE;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wave-uniform
+  const int i = tm * 64 + lane;
+  const bool live = i < M;
+  T acc[NMAX];
+#pragma unroll
+  for (int q = 0; q < NMAX; ++q) acc[q] = T(0);
+  for (int sg = 0; sg < J.nseg; ++sg) {
+    const GSeg& S = segs[J.seg0 + sg];
+    const int K = S.K, lda = S.A.ld, ldb = S.B.ld, ta = S.A.trans;
+    const T sc = (T)S.scale;
+    const T* Ap = optr<T>(S.A, m, c);
+    const T* Bp = optr<T>(S.B, m, c);
+    for (int k0 = wv * 8; k0 < K; k0 += 32) {
+      T a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + u;
+        a[u] = (live && k < K) ? (ta ? Ap[k + (long long)i * lda] : Ap[i + (long long)k * lda]) * sc : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + u;
+        if (k < K) {
+          const T* bk = Bp + k;
+#pragma unroll
+          for (int q = 0; q < NMAX; ++q)
+            if (q < N) acc[q] = fma(a[u], bk[(long long)q * ldb], acc[q]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q0 = 0; q0 < NMAX; q0 += 16) {
+    if (wv > 0)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) red[wv - 1][lane][q] = acc[q0 + q];
+    __syncthreads();
+    if (wv == 0)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q0 + q] += red[0][lane][q] + red[1][lane][q] + red[2][lane][q];
+    __syncthreads();
+  }
+  if (wv == 0 && live) {
+    T* Cp = const_cast<T*>(optr<T>(J.C, m, c));
+    const int ldc = J.C.ld;
+    const T alpha = (T)J.alpha, beta = (T)J.beta;
+#pragma unroll
+    for (int q = 0; q < NMAX; ++q) {
+      if (q >= N) break;
+      T* cp = Cp + i + (long long)q * ldc;
+      T v = alpha * acc[q];
+      if (beta != T(0)) v = fma(beta, *cp, v);
+      *cp = v;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- inverse
 // Gauss-Jordan on the augmented matrix [A | I] (row-major n x 2n) in FP64.
 template <typename Tin, typename Tout>
@@ -957,41 +1157,84 @@ const J* upload(const std::vector<J>& v, hipStream_t st) {
 
 }  // namespace
 
+// Kernel kinds of the grouped GEMM: 0..4 = tile shapes of k_ggemm,
+// 5 = k_gemm_dot (long-K reductions A^T B with small outputs), 6..7 =
+// k_gemm_rows with 16 / 32 columns, 9 = k_gemm_small (short-K reductions).
 template <typename T>
 void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs) {
-  std::vector<GJob> by[5];
-  double fl[5] = {0, 0, 0, 0, 0}, bytes[5] = {0, 0, 0, 0, 0};
+  constexpr int NK = 10;
+  std::vector<GJob> by[NK];
+  double fl[NK] = {}, bytes[NK] = {};
   for (auto& J : jobs) {
     if (J.M <= 0 || J.N <= 0 || J.nmat <= 0 || J.ncl <= 0 || J.nseg <= 0) continue;
-    const int cfg = pick_tile(J.M, J.N);
-    J.tilesM = (J.M + kTiles[cfg].tm - 1) / kTiles[cfg].tm;
-    J.tilesN = (J.N + kTiles[cfg].tn - 1) / kTiles[cfg].tn;
     double K = 0;
-    for (int sg = 0; sg < J.nseg; ++sg) K += segs[J.seg0 + sg].K;
+    bool dotok = true, rowok = true;
+    for (int sg = 0; sg < J.nseg; ++sg) {
+      const GSeg& g = segs[J.seg0 + sg];
+      K += g.K;
+      if (!(g.A.trans && !g.B.trans)) dotok = false;
+      if (g.B.trans) rowok = false;
+    }
+    int kind;
+    if (dotok && J.M <= 64 && J.N <= 64 && K >= 256) {
+      kind = 5;
+      J.tilesM = (J.M + 7) / 8;
+      J.tilesN = (J.N + 7) / 8;
+    } else if (dotok && J.M <= 64 && J.N <= 64) {
+      kind = 9;
+      J.tilesM = (J.M + 15) / 16;
+      J.tilesN = (J.N + 15) / 16;
+    } else if (rowok && J.M >= 48 && J.N <= 32) {
+      kind = J.N <= 16 ? 6 : 7;
+      J.tilesM = (J.M + 63) / 64;
+      J.tilesN = 1;
+    } else {
+      kind = pick_tile(J.M, J.N);
+      J.tilesM = (J.M + kTiles[kind].tm - 1) / kTiles[kind].tm;
+      J.tilesN = (J.N + kTiles[kind].tn - 1) / kTiles[kind].tn;
+    }
     const double np = (double)J.nmat * J.ncl;
-    fl[cfg] += 2.0 * J.M * J.N * K * np;
-    bytes[cfg] += sizeof(T) * np * ((double)J.M * K + K * J.N + (double)J.M * J.N * (J.beta != 0.0 ? 2 : 1));
-    by[cfg].push_back(J);
+    fl[kind] += 2.0 * J.M * J.N * K * np;
+    bytes[kind] += sizeof(T) * np * ((double)J.M * K + K * J.N + (double)J.M * J.N * (J.beta != 0.0 ? 2 : 1));
+    by[kind].push_back(J);
   }
-  const GSeg* dsegs = nullptr;
-  for (int cfg = 0; cfg < 5; ++cfg) {
-    if (by[cfg].empty()) continue;
-    if (!dsegs) dsegs = upload(segs, st);
+  // one upload: segments, then the job lists of every kind
+  std::vector<char> blob(segs.size() * sizeof(GSeg));
+  if (!segs.empty()) std::memcpy(blob.data(), segs.data(), blob.size());
+  size_t off[NK];
+  long long nblk[NK] = {};
+  for (int kd = 0; kd < NK; ++kd) {
     long long b0 = 0;
-    for (auto& J : by[cfg]) {
+    for (auto& J : by[kd]) {
       J.block0 = b0;
       b0 += (long long)J.nmat * J.ncl * J.tilesM * J.tilesN;
     }
     if (b0 > 0x7fffffffLL) fail(ACR_ERR_INVALID_ARG, "grouped GEMM grid too large");
-    const GJob* dj = upload(by[cfg], st);
-    const int nj = (int)by[cfg].size();
-    ProfScope ps(KC_GEMM, st, fl[cfg], bytes[cfg]);
-    switch (cfg) {
-      case 0: hipLaunchKernelGGL((k_ggemm<T, 64, 64, 16, 4, 4>), dim3((unsigned)b0), dim3(256), 0, st, dj, nj, dsegs); break;
-      case 1: hipLaunchKernelGGL((k_ggemm<T, 64, 16, 16, 4, 4>), dim3((unsigned)b0), dim3(64), 0, st, dj, nj, dsegs); break;
-      case 2: hipLaunchKernelGGL((k_ggemm<T, 16, 64, 16, 4, 4>), dim3((unsigned)b0), dim3(64), 0, st, dj, nj, dsegs); break;
-      case 3: hipLaunchKernelGGL((k_ggemm<T, 32, 32, 16, 4, 4>), dim3((unsigned)b0), dim3(64), 0, st, dj, nj, dsegs); break;
-      default: hipLaunchKernelGGL((k_ggemm<T, 16, 16, 16, 2, 2>), dim3((unsigned)b0), dim3(64), 0, st, dj, nj, dsegs); break;
+    nblk[kd] = b0;
+    off[kd] = (blob.size() + 255) & ~size_t(255);
+    blob.resize(off[kd] + by[kd].size() * sizeof(GJob));
+    if (!by[kd].empty()) std::memcpy(blob.data() + off[kd], by[kd].data(), by[kd].size() * sizeof(GJob));
+  }
+  if (blob.empty()) return;
+  char* dev = static_cast<char*>(DescArena::get().put(blob.data(), blob.size(), st));
+  const GSeg* dsegs = reinterpret_cast<const GSeg*>(dev);
+  for (int kd = 0; kd < NK; ++kd) {
+    if (by[kd].empty()) continue;
+    const GJob* dj = reinterpret_cast<const GJob*>(dev + off[kd]);
+    const int nj = (int)by[kd].size();
+    const dim3 grid((unsigned)nblk[kd]);
+    ProfScope ps(KC_GEMM, st, fl[kd], bytes[kd]);
+    switch (kd) {
+      case 0: hipLaunchKernelGGL((k_ggemm<T, 64, 64, 16, 4, 4>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
+      case 1: hipLaunchKernelGGL((k_ggemm<T, 64, 16, 16, 4, 4>), grid, dim3(64), 0, st, dj, nj, dsegs); break;
+      case 2: hipLaunchKernelGGL((k_ggemm<T, 16, 64, 16, 4, 4>), grid, dim3(64), 0, st, dj, nj, dsegs); break;
+      case 3: hipLaunchKernelGGL((k_ggemm<T, 32, 32, 16, 4, 4>), grid, dim3(64), 0, st, dj, nj, dsegs); break;
+      case 4: hipLaunchKernelGGL((k_ggemm<T, 16, 16, 16, 2, 2>), grid, dim3(64), 0, st, dj, nj, dsegs); break;
+      case 5: hipLaunchKernelGGL((k_gemm_dot<T>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
+      case 6: hipLaunchKernelGGL((k_gemm_rows<T, 16>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
+      case 7: hipLaunchKernelGGL((k_gemm_rows<T, 32>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
+      case 8: hipLaunchKernelGGL((k_gemm_rows<T, 64>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
+      default: hipLaunchKernelGGL((k_gemm_small<T>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
     }
     ACR_CHECK_LAUNCH();
   }
