@@ -281,15 +281,30 @@ __global__ __launch_bounds__(256) void k_gemm_small(const GJob* __restrict__ job
 }
 
 // Row GEMM C = sum_s scale_s op(A_s) B_s for tall outputs with few columns
-// (N <= NMAX): a workgroup owns 64 output rows (one per lane) and its four
-// waves split K in groups of 8 (wave w takes groups w, w+4, ...).  B(k, :) is
-// the same for every lane of a wave (a broadcast read), A is read per lane;
-// no LDS staging or barriers in the main loop.  The waves' partial sums are
+// (N <= NMAX): a workgroup owns 64 output rows (one per lane).  The K
+// columns of all segments are taken as one flattened list and processed in
+// blocks of KB: per block, a column table (A column base, row stride, scale,
+// B row) is built in LDS, each wave issues the loads of its KB/4 A columns at
+// once, the B rows of the block are staged in LDS meanwhile, and the FMAs read
+// B as LDS broadcasts.  A workgroup so needs one memory round trip per block
+// instead of one per segment and K step.  The waves' partial sums are
 // combined through LDS at the end.
 template <typename T, int NMAX>
 __global__ __launch_bounds__(256) void k_gemm_rows(const GJob* __restrict__ jobs, int njobs,
                                                   const GSeg* __restrict__ segs) {
-  __shared__ T red[3][64][16];
+  constexpr int UA = (sizeof(T) == 8 && NMAX >= 32) ? 16 : 32;   // A columns per wave and block
+  constexpr int KB = 4 * UA;
+  constexpr int BUF = (KB * NMAX > 3 * 64 * NMAX) ? KB * NMAX : 3 * 64 * NMAX;
+  __shared__ T buf[BUF];                 // B block [KB][NMAX], then the wave partial sums
+  __shared__ const T* cA[KB];
+  __shared__ const T* cB[KB];
+  __shared__ long long cRs[KB];
+  __shared__ int cLdb[KB];
+  __shared__ T cSc[KB];
+  __shared__ const T* sA[kMaxSeg];
+  __shared__ const T* sB[kMaxSeg];
+  __shared__ int sLda[kMaxSeg], sLdb[kMaxSeg], sTa[kMaxSeg], sK[kMaxSeg], sK0[kMaxSeg + 1];
+  __shared__ T sSc[kMaxSeg];
   const long long bid = blockIdx.x;
   const GJob& J = jobs[job_of(jobs, njobs, bid)];
   const int tilesM = J.tilesM;
@@ -297,50 +312,77 @@ __global__ __launch_bounds__(256) void k_gemm_rows(const GJob* __restrict__ jobs
   const int prob = (int)(local / tilesM);
   const int tm = (int)(local % tilesM);
   const int m = prob / J.ncl, c = prob % J.ncl;
-  const int M = J.M, N = J.N;
-  const int lane = threadIdx.x % WAVE;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wave-uniform
+  const int M = J.M, N = J.N, nseg = J.nseg;
+  const int tid = threadIdx.x;
+  const int lane = tid % WAVE;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
   const int i = tm * 64 + lane;
   const bool live = i < M;
+  if (tid < nseg) {
+    const GSeg& S = segs[J.seg0 + tid];
+    sA[tid] = optr<T>(S.A, m, c);
+    sB[tid] = optr<T>(S.B, m, c);
+    sLda[tid] = S.A.ld;
+    sLdb[tid] = S.B.ld;
+    sTa[tid] = S.A.trans;
+    sK[tid] = S.K;
+    sSc[tid] = (T)S.scale;
+  }
+  __syncthreads();
+  if (tid <= nseg) {
+    int k0 = 0;
+    for (int q = 0; q < tid; ++q) k0 += sK[q];
+    sK0[tid] = k0;
+  }
+  __syncthreads();
+  const int Ktot = sK0[nseg];
   T acc[NMAX];
 #pragma unroll
   for (int q = 0; q < NMAX; ++q) acc[q] = T(0);
-  for (int sg = 0; sg < J.nseg; ++sg) {
-    const GSeg& S = segs[J.seg0 + sg];
-    const int K = S.K, lda = S.A.ld, ldb = S.B.ld, ta = S.A.trans;
-    const T sc = (T)S.scale;
-    const T* Ap = optr<T>(S.A, m, c);
-    const T* Bp = optr<T>(S.B, m, c);
-    for (int k0 = wv * 8; k0 < K; k0 += 32) {
-      T a[8];
+  for (int kb = 0; kb < Ktot; kb += KB) {
+    const int kcnt = min(KB, Ktot - kb);
+    if (tid < kcnt) {
+      const int k = kb + tid;
+      int sg = 0;
+      while (sg + 1 < nseg && sK0[sg + 1] <= k) ++sg;
+      const int ko = k - sK0[sg];
+      const long long lda = sLda[sg];
+      cA[tid] = sA[sg] + (sTa[sg] ? (long long)ko : ko * lda);
+      cRs[tid] = sTa[sg] ? lda : 1;
+      cSc[tid] = sSc[sg];
+      cB[tid] = sB[sg] + ko;
+      cLdb[tid] = sLdb[sg];
+    }
+    __syncthreads();
+    // this wave's A columns (all loads in flight together)
+    const int u0 = wv * UA;
+    T a[UA];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = k0 + u;
-        a[u] = (live && k < K) ? (ta ? Ap[k + (long long)i * lda] : Ap[i + (long long)k * lda]) * sc : T(0);
-      }
+    for (int u = 0; u < UA; ++u) {
+      const int kk = u0 + u;
+      a[u] = (live && kk < kcnt) ? cA[kk][i * cRs[kk]] * cSc[kk] : T(0);
+    }
+    // B rows of the block
+    for (int e = tid; e < KB * N; e += 256) {
+      const int kk = e % KB, q = e / KB;
+      if (kk < kcnt) buf[kk * NMAX + q] = cB[kk][(long long)q * cLdb[kk]];
+    }
+    __syncthreads();
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = k0 + u;
-        if (k < K) {
-          const T* bk = Bp + k;
+    for (int u = 0; u < UA; ++u) {
+      const int kk = u0 + u;
+      if (kk < kcnt) {
+        const T* br = buf + kk * NMAX;
 #pragma unroll
-          for (int q = 0; q < NMAX; ++q)
-            if (q < N) acc[q] = fma(a[u], bk[(long long)q * ldb], acc[q]);
-        }
+        for (int q = 0; q < NMAX; ++q) acc[q] = fma(a[u], br[q], acc[q]);
       }
     }
-  }
-#pragma unroll
-  for (int q0 = 0; q0 < NMAX; q0 += 16) {
-    if (wv > 0)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) red[wv - 1][lane][q] = acc[q0 + q];
-    __syncthreads();
-    if (wv == 0)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q0 + q] += red[0][lane][q] + red[1][lane][q] + red[2][lane][q];
     __syncthreads();
   }
+  if (wv > 0)
+#pragma unroll
+    for (int q = 0; q < NMAX; ++q) buf[((wv - 1) * NMAX + q) * 64 + lane] = acc[q];
+  __syncthreads();
   if (wv == 0 && live) {
     T* Cp = const_cast<T*>(optr<T>(J.C, m, c));
     const int ldc = J.C.ld;
@@ -348,8 +390,10 @@ __global__ __launch_bounds__(256) void k_gemm_rows(const GJob* __restrict__ jobs
 #pragma unroll
     for (int q = 0; q < NMAX; ++q) {
       if (q >= N) break;
+      const T v0 = acc[q] + buf[(0 * NMAX + q) * 64 + lane] + buf[(1 * NMAX + q) * 64 + lane] +
+                   buf[(2 * NMAX + q) * 64 + lane];
       T* cp = Cp + i + (long long)q * ldc;
-      T v = alpha * acc[q];
+      T v = alpha * v0;
       if (beta != T(0)) v = fma(beta, *cp, v);
       *cp = v;
     }
@@ -357,6 +401,82 @@ __global__ __launch_bounds__(256) void k_gemm_rows(const GJob* __restrict__ jobs
 }
 
 // ---------------------------------------------------------------- inverse
+// Small inverses (n <= N <= 64): Gauss-Jordan with partial pivoting in FP64,
+// one row per lane.  A wave holds 64/N matrices (lane group g, row r = lane
+// mod N) with the working row in registers; the pivot row's entries are
+// broadcast with lane reads, so there is no LDS traffic and no barrier in the
+// elimination.  Rows are never swapped: the row chosen at step j is recorded,
+// and with the in-place storage (column j of the working matrix holds column
+// p_j of the accumulated transformation M, M A = P) the inverse is read back
+// as X[j, p_j'] = W[p_j, j'].
+template <int N>
+__device__ __forceinline__ double row_bcast(double v, int src) {
+  if constexpr (N == WAVE) {
+    const int sl = __builtin_amdgcn_readfirstlane(src);
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)x, sl);
+    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), sl);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  } else {
+    return __shfl(v, src, N);
+  }
+}
+
+template <typename Tin, typename Tout, int N>
+__global__ __launch_bounds__(256) void k_inverse_wave(int n, int nprob, const Tin* __restrict__ A,
+                                                     long long sA, Tout* __restrict__ X, long long sX,
+                                                     int* status) {
+  constexpr int G = WAVE / N;
+  __shared__ int piv_row[4][WAVE];
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  const int g = lane / N, r = lane % N;
+  const long long p = ((long long)blockIdx.x * 4 + wv) * G + g;
+  const bool valid = p < nprob;
+  const Tin* Ap = A + (valid ? p : 0) * sA;
+  double a[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c)
+    a[c] = (valid && r < n && c < n) ? (double)Ap[r + (long long)c * n] : (r == c ? 1.0 : 0.0);
+  bool used = false, bad = false;
+  int mystep = r;
+  for (int j = 0; j < n; ++j) {
+    double f = 0.0;
+#pragma unroll
+    for (int c = 0; c < N; ++c) f = (c == j) ? a[c] : f;
+    double best = used ? -1.0 : fabs(f);
+    int bi = r;
+#pragma unroll
+    for (int off = N / 2; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, N);
+      const int oi = __shfl_xor(bi, off, N);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const double pv = row_bcast<N>(f, bi);
+    if (!(best > 0.0) || !isfinite(best)) bad = true;
+    const double inv = 1.0 / pv;
+    const bool is_piv = r == bi;
+    if (is_piv) { used = true; mystep = j; }
+    if (r == 0) piv_row[wv][g * N + j] = bi;
+    const double qq = is_piv ? -inv : f * inv;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      const double pc = row_bcast<N>(a[c], bi);
+      const double base = is_piv ? 0.0 : a[c];
+      a[c] = (c == j) ? -qq : fma(-qq, pc, base);
+    }
+  }
+  __syncthreads();
+  if (valid && r < n) {
+    Tout* Xp = X + p * sX;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      const int pc = piv_row[wv][g * N + c];   // < n unless the matrix is singular (then flagged)
+      if (c < n && pc < n) Xp[mystep + (long long)pc * n] = (Tout)a[c];
+    }
+    if (r == 0 && bad) status[0] = 1;
+  }
+}
+
 // Gauss-Jordan on the augmented matrix [A | I] (row-major n x 2n) in FP64.
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(256) void k_inverse(int n, const Tin* A, long long sA, Tout* X,
@@ -1158,8 +1278,8 @@ const J* upload(const std::vector<J>& v, hipStream_t st) {
 }  // namespace
 
 // Kernel kinds of the grouped GEMM: 0..4 = tile shapes of k_ggemm,
-// 5 = k_gemm_dot (long-K reductions A^T B with small outputs), 6..7 =
-// k_gemm_rows with 16 / 32 columns, 9 = k_gemm_small (short-K reductions).
+// 5 = k_gemm_dot (long-K reductions A^T B with small outputs), 6..8 =
+// k_gemm_rows with 16 / 32 / 4 columns, 9 = k_gemm_small (short-K reductions).
 template <typename T>
 void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs) {
   constexpr int NK = 10;
@@ -1184,8 +1304,8 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
       kind = 9;
       J.tilesM = (J.M + 15) / 16;
       J.tilesN = (J.N + 15) / 16;
-    } else if (rowok && J.M >= 48 && J.N <= 32) {
-      kind = J.N <= 16 ? 6 : 7;
+    } else if (rowok && J.M >= 48 && J.N <= (sizeof(T) == 4 ? 32 : 16)) {
+      kind = J.N <= 4 ? 8 : J.N <= 16 ? 6 : 7;
       J.tilesM = (J.M + 63) / 64;
       J.tilesN = 1;
     } else {
@@ -1232,8 +1352,8 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
       case 4: hipLaunchKernelGGL((k_ggemm<T, 16, 16, 16, 2, 2>), grid, dim3(64), 0, st, dj, nj, dsegs); break;
       case 5: hipLaunchKernelGGL((k_gemm_dot<T>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
       case 6: hipLaunchKernelGGL((k_gemm_rows<T, 16>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
-      case 7: hipLaunchKernelGGL((k_gemm_rows<T, 32>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
-      case 8: hipLaunchKernelGGL((k_gemm_rows<T, 64>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
+      case 7: hipLaunchKernelGGL((k_gemm_rows<T, sizeof(T) == 4 ? 32 : 16>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
+      case 8: hipLaunchKernelGGL((k_gemm_rows<T, 4>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
       default: hipLaunchKernelGGL((k_gemm_small<T>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
     }
     ACR_CHECK_LAUNCH();
@@ -1258,6 +1378,19 @@ void binverse(hipStream_t st, int n, int nprob, const Tin* A, long long sA, Tout
               int* status) {
   if (n <= 0 || nprob <= 0) return;
   ProfScope ps(KC_INVERSE, st, 2.0 * n * n * n * nprob, 2.0 * n * n * nprob * sizeof(Tin));
+  if (n <= 64) {   // one row per lane, 64/N matrices per wave, four waves per workgroup
+    auto launch = [&](auto kern, int Nt) {
+      const long long per = 4LL * (WAVE / Nt);
+      hipLaunchKernelGGL(kern, dim3((unsigned)((nprob + per - 1) / per)), dim3(256), 0, st, n, nprob, A, sA,
+                         X, sX, status);
+    };
+    if (n <= 8) launch(k_inverse_wave<Tin, Tout, 8>, 8);
+    else if (n <= 16) launch(k_inverse_wave<Tin, Tout, 16>, 16);
+    else if (n <= 32) launch(k_inverse_wave<Tin, Tout, 32>, 32);
+    else launch(k_inverse_wave<Tin, Tout, 64>, 64);
+    ACR_CHECK_LAUNCH();
+    return;
+  }
   if (n <= 88) {   // in place: n*n doubles of LDS (+1.6 KB static) within 64 KB
     hipLaunchKernelGGL((k_inverse_lds<Tin, Tout>), dim3(nprob), dim3(256), (size_t)n * n * sizeof(double),
                        st, n, A, sA, X, sX, status);
