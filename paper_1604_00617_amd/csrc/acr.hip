@@ -107,8 +107,7 @@ struct Factor final : FactorBase {
     if (l.diag) {
       std::vector<T> d(s);
       const DBuf<T>& src = which == 1 ? l.e0 : l.f0;
-      ACR_HIP(hipMemcpyAsync(d.data(), src.get() + (size_t)k * s, s * sizeof(T), hipMemcpyDeviceToHost, st));
-      ACR_HIP(hipStreamSynchronize(st));
+      read_to_host(d.data(), src.get() + (size_t)k * s, s * sizeof(T), st);
       for (size_t e = 0; e < (size_t)s * s; ++e) dense[e] = 0.0;
       for (int r = 0; r < s; ++r) dense[(size_t)r * (s + 1)] = (double)d[r];
     } else {
@@ -215,8 +214,7 @@ template <typename T>
 void stage_check(hipStream_t st, const HSet<T>& H, const int* status, const char* what, int level) {
   if (!debug_checks()) return;
   int bad = 0;
-  ACR_HIP(hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, st));
-  ACR_HIP(hipStreamSynchronize(st));
+  read_to_host(&bad, status, sizeof(int), st);
   std::string msg;
   bool nf = false;
   double mx = 0, m1 = 0;
@@ -254,15 +252,14 @@ std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_option
   const int mr = opt.max_rank;
   work() = Work();
   DBuf<int> status(1);
-  ACR_HIP(hipMemsetAsync(status.get(), 0, sizeof(int), st));
+  memset_async(status.get(), 0, sizeof(int), st);
   {
     DBuf<int> nonfin(1);
-    ACR_HIP(hipMemsetAsync(nonfin.get(), 0, sizeof(int), st));
+    memset_async(nonfin.get(), 0, sizeof(int), st);
     const long long n = (long long)s * ny;
     for (const double* a : {op.diag, op.west, op.east, op.south, op.north}) flag_nonfinite(st, n, a, nonfin.get());
     int bad = 0;
-    ACR_HIP(hipMemcpyAsync(&bad, nonfin.get(), sizeof(int), hipMemcpyDeviceToHost, st));
-    ACR_HIP(hipStreamSynchronize(st));
+    read_to_host(&bad, nonfin.get(), sizeof(int), st);
     if (bad) fail(ACR_ERR_INVALID_ARG, "the operator holds a NaN or infinite coefficient");
   }
 
@@ -385,8 +382,7 @@ std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_option
   hinv<T>(st, f->Xlast, HV<T>{&D, 1, 0}, 1, status.get());
   recompress_multi<T>(st, {&f->Xlast}, eps, mr);
   int bad = 0;
-  ACR_HIP(hipMemcpyAsync(&bad, status.get(), sizeof(int), hipMemcpyDeviceToHost, st));
-  ACR_HIP(hipStreamSynchronize(st));
+  read_to_host(&bad, status.get(), sizeof(int), st);
   if (bad) fail(ACR_ERR_SINGULAR, "zero or non-finite pivot in a dense leaf or capacitance inverse");
   f->work_done = work();
   return f;
@@ -409,14 +405,18 @@ acr_status guard(const std::function<void()>& fn) {
   try {
     g_last_error.clear();
     fn();
+    Queue::get().flush();   // everything recorded by this call is on the caller's stream now
     return ACR_OK;
   } catch (const Error& e) {
+    Queue::get().discard();
     g_last_error = e.what();
     return e.code;
   } catch (const std::bad_alloc& e) {
+    Queue::get().discard();
     g_last_error = "host allocation failed";
     return ACR_ERR_OOM;
   } catch (const std::exception& e) {
+    Queue::get().discard();
     g_last_error = e.what();
     return ACR_ERR_INTERNAL;
   }
@@ -488,18 +488,16 @@ acr_status acr_solve_refined(acr_handle h, const acr_operator* op, const double*
     DBuf<double> R((size_t)n * nrhs), D((size_t)n * nrhs), nb(nrhs), nr(nrhs);
     std::vector<double> hb(nrhs), hr(nrhs);
     col_sumsq(st, n, nrhs, B, nb.get());
-    ACR_HIP(hipMemcpyAsync(hb.data(), nb.get(), nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-    ACR_HIP(hipMemsetAsync(X, 0, (size_t)n * nrhs * sizeof(double), st));
-    ACR_HIP(hipMemcpyAsync(R.get(), B, (size_t)n * nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
-    ACR_HIP(hipStreamSynchronize(st));
+    memset_async(X, 0, (size_t)n * nrhs * sizeof(double), st);
+    copy_d2d_async(R.get(), B, (size_t)n * nrhs * sizeof(double), st);
+    read_to_host(hb.data(), nb.get(), nrhs * sizeof(double), st);
     for (its = 0;; ++its) {
       if (its > 0) {
         stencil_residual(st, op->nx, op->ny, nrhs, op->diag, op->west, op->east, op->south, op->north, X, B,
                          R.get());
       }
       col_sumsq(st, n, nrhs, R.get(), nr.get());
-      ACR_HIP(hipMemcpyAsync(hr.data(), nr.get(), nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      ACR_HIP(hipStreamSynchronize(st));
+      read_to_host(hr.data(), nr.get(), nrhs * sizeof(double), st);
       rel = 0.0;
       for (int q = 0; q < nrhs; ++q) {
         const double v = hb[q] > 0 ? std::sqrt(hr[q] / hb[q]) : std::sqrt(hr[q]);

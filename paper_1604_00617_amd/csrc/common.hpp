@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <stdexcept>
@@ -36,6 +37,9 @@ struct Error : std::runtime_error {
   } while (0)
 
 #define ACR_CHECK_LAUNCH() ACR_HIP(hipGetLastError())
+
+// Issues every deferred stream operation (see Queue below).
+void queue_flush();
 
 // ------------------------------------------------------------ memory pool
 // Caching allocator: freed blocks are kept per rounded size and reused by
@@ -87,6 +91,7 @@ class Pool {
     live_.erase(it);
   }
   void trim() {
+    queue_flush();   // deferred work may still use the blocks freed below
     std::lock_guard<std::mutex> g(mu_);
     if (!free_.empty()) (void)hipDeviceSynchronize();
     for (auto& kv : free_) {
@@ -243,45 +248,126 @@ inline BOp ancestor(BOp o, int shift, int x) { o.cshift = shift; o.cxor = x; ret
 inline BOp transposed(BOp o) { o.trans = 1; return o; }
 
 // ------------------------------------------------------- descriptor arena
-// Job descriptors of grouped launches: written to pinned host memory and
-// copied to a device buffer on the launch stream just before the kernel that
-// reads them.  The arena is recycled only after the stream has been
-// synchronised (reset() is called at those points).
+// Job descriptors of grouped launches are written to pinned host memory;
+// the pending range is copied to the device in one transfer when the queue
+// below is flushed, just before the launches that read it.  The arena wraps
+// around only after a stream synchronisation.
 class DescArena {
  public:
   static DescArena& get() {
     static DescArena a;
     return a;
   }
-  // Copy `bytes` of host data into the arena and enqueue its upload on st;
-  // returns the device address.
-  void* put(const void* data, size_t bytes, hipStream_t st) {
-    const size_t need = (bytes + 255) & ~size_t(255);
-    if (off_ + need > cap_) {
-      ACR_HIP(hipStreamSynchronize(st));
-      off_ = 0;
-      if (need > cap_) grow(need * 2);
-    }
-    std::memcpy(host_ + off_, data, bytes);
-    ACR_HIP(hipMemcpyAsync(dev_ + off_, host_ + off_, bytes, hipMemcpyHostToDevice, st));
-    void* d = dev_ + off_;
-    off_ += need;
-    return d;
+  // Stage `bytes` of host data; returns the device address it will have.
+  void* put(const void* data, size_t bytes, hipStream_t st);
+  // Copy everything staged since the last upload (on st).
+  void upload_pending(hipStream_t st) {
+    if (off_ > pend_)
+      ACR_HIP(hipMemcpyAsync(dev_ + pend_, host_ + pend_, off_ - pend_, hipMemcpyHostToDevice, st));
+    pend_ = off_;
   }
-  void reset() { off_ = 0; }   // only after the stream that used it is synchronised
 
  private:
-  DescArena() { grow(size_t(8) << 20); }
+  DescArena() { grow(size_t(16) << 20); }
   void grow(size_t cap) {
     if (host_) { (void)hipHostFree(host_); (void)hipFree(dev_); }
     ACR_HIP(hipHostMalloc((void**)&host_, cap, hipHostMallocDefault));
     ACR_HIP(hipMalloc((void**)&dev_, cap));
     cap_ = cap;
-    off_ = 0;
+    off_ = pend_ = 0;
   }
   char* host_ = nullptr;
   char* dev_ = nullptr;
-  size_t cap_ = 0, off_ = 0;
+  size_t cap_ = 0, off_ = 0, pend_ = 0;
 };
+
+// ---------------------------------------------------------- deferred queue
+// Every stream operation of the library (kernel launches, fills, device
+// copies) is recorded here and issued in order by flush(), after a single
+// upload of the job descriptors staged meanwhile.  This turns the hundreds
+// of small descriptor copies of one factorisation into a few.  flush() is
+// called before any host read of device data, before memory is returned to
+// the system and at the end of every entry point; ops issued by flush() keep
+// stream order with everything enqueued before.  One stream at a time: a new
+// stream flushes the ops of the previous one first.
+class Queue {
+ public:
+  static Queue& get() {
+    static Queue q;
+    return q;
+  }
+  void op(hipStream_t st, std::function<void()> f) {
+    if (!ops_.empty() && st != st_) flush();
+    st_ = st;
+    ops_.push_back(std::move(f));
+    if (ops_.size() >= kMaxPending) flush();
+  }
+  void flush() {
+    if (flushing_) return;
+    flushing_ = true;
+    std::vector<std::function<void()>> ops;
+    ops.swap(ops_);
+    try {
+      DescArena::get().upload_pending(st_);
+      for (auto& f : ops) f();
+    } catch (...) {
+      flushing_ = false;
+      throw;
+    }
+    flushing_ = false;
+  }
+  // Drop recorded ops (after an error: their buffers may be gone).
+  void discard() { ops_.clear(); }
+  bool empty() const { return ops_.empty(); }
+
+ private:
+  static constexpr size_t kMaxPending = 24;   // keeps the device fed during long host planning
+  std::vector<std::function<void()>> ops_;
+  hipStream_t st_ = nullptr;
+  bool flushing_ = false;
+};
+
+inline void queue_flush() { Queue::get().flush(); }
+
+inline void* DescArena::put(const void* data, size_t bytes, hipStream_t st) {
+  const size_t need = (bytes + 255) & ~size_t(255);
+  if (off_ + need > cap_) {
+    Queue::get().flush();              // issues the ops reading the staged range
+    ACR_HIP(hipStreamSynchronize(st));
+    off_ = pend_ = 0;
+    if (need > cap_) grow(need * 2);
+  }
+  std::memcpy(host_ + off_, data, bytes);
+  void* d = dev_ + off_;
+  off_ += need;
+  return d;
+}
+
+// Record a kernel launch (timed by the profiler when its class is selected).
+template <typename... KArgs, typename... Args>
+void launch(hipStream_t st, int cls, double flops, double bytes, void (*kern)(KArgs...), dim3 grid,
+            dim3 block, size_t shmem, Args... args) {
+  Queue::get().op(st, [=]() {
+    ProfScope ps(cls, st, flops, bytes);
+    hipLaunchKernelGGL(kern, grid, block, shmem, st, args...);
+    ACR_HIP(hipGetLastError());
+  });
+}
+
+// Record a byte fill / a device-to-device copy.
+inline void memset_async(void* p, int v, size_t bytes, hipStream_t st) {
+  if (!bytes) return;
+  Queue::get().op(st, [=]() { ACR_HIP(hipMemsetAsync(p, v, bytes, st)); });
+}
+inline void copy_d2d_async(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (!bytes) return;
+  Queue::get().op(st, [=]() { ACR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st)); });
+}
+// Flush, copy device data to the host and wait for it.
+inline void read_to_host(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  Queue::get().flush();
+  if (bytes) ACR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+  ACR_HIP(hipStreamSynchronize(st));
+}
 
 }  // namespace acr

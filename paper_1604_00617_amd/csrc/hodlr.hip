@@ -29,10 +29,10 @@ void HSet<T>::alloc(hipStream_t st, int cnt_, int s_, int b_, int L_, const std:
     V[d].resize((size_t)cnt * k[d] * s);
   }
   if (zero) {
-    if (lv.bytes()) ACR_HIP(hipMemsetAsync(lv.get(), 0, lv.bytes(), st));
+    memset_async(lv.get(), 0, lv.bytes(), st);
     for (int d = 1; d <= L; ++d) {
-      if (U[d].bytes()) ACR_HIP(hipMemsetAsync(U[d].get(), 0, U[d].bytes(), st));
-      if (V[d].bytes()) ACR_HIP(hipMemsetAsync(V[d].get(), 0, V[d].bytes(), st));
+      memset_async(U[d].get(), 0, U[d].bytes(), st);
+      memset_async(V[d].get(), 0, V[d].bytes(), st);
     }
   }
 }
@@ -199,7 +199,7 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
     }
   }
   DBuf<T> tbuf(tsize);
-  if (tsize) ACR_HIP(hipMemsetAsync(tbuf.get(), 0, tsize * sizeof(T), st));
+  memset_async(tbuf.get(), 0, tsize * sizeof(T), st);
   size_t toff = 0;
   for (auto& O : outs) {
     const int nmat = O.nmat;
@@ -374,6 +374,7 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
   gcopy<T>(st, cmid);
   s3.run<T>(st);
   gcopy<T>(st, cout);
+  Queue::get().flush();   // let the device start while the host plans the next step
 }
 
 // ------------------------------------------------------------------- hinv
@@ -450,6 +451,7 @@ void hinv(hipStream_t st, HSet<T>& X, HV<T> M, int nmat, int* status) {
            {seg(bop(wbuf.get(), s, (long long)k * s, b), bop(bbuf.get(), s, (long long)k * s, b, 1), k, -1.0)});
     lp.run<T>(st);
   }
+  Queue::get().flush();   // let the device start while the host plans the next step
 }
 
 // ------------------------------------------------------------- level 0
@@ -489,6 +491,7 @@ void hstack(hipStream_t st, HSet<T>& C, int cnt_alloc, const std::vector<ScaleTe
   gcopy<T>(st, first);
   for (auto& r : rest) gcopy<T>(st, r);
   for (int d = 1; d <= L; ++d) C.kc[d] = col[d];
+  Queue::get().flush();   // let the device start while the host plans the next step
 }
 
 template <typename T>
@@ -517,6 +520,7 @@ void hscale_cols_multi(hipStream_t st, std::vector<ColScale<T>>& outs) {
     }
   }
   gcopy<T>(st, cj);
+  Queue::get().flush();   // let the device start while the host plans the next step
 }
 
 // ------------------------------------------------------------- recompress
@@ -584,8 +588,7 @@ void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double 
   grsvd<T>(st, sj);
   gmax(st, mj);
   std::vector<int> kout(items.size());
-  ACR_HIP(hipMemcpyAsync(kout.data(), dmax.get(), items.size() * sizeof(int), hipMemcpyDeviceToHost, st));
-  ACR_HIP(hipStreamSynchronize(st));
+  read_to_host(kout.data(), dmax.get(), items.size() * sizeof(int), st);
   // Keep s_t > eps s_1:  K = U_K S J^T,
   //   U_new = Q_U [U_K,t; 0]          (orthonormal columns)
   //   V_new = V Ru^T U_K,t            (= Q_V J_t S_t, no inverse)
@@ -628,12 +631,14 @@ void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double 
     it.H->V[it.d] = std::move(it.Vn);
     it.H->k[it.d] = it.H->kc[it.d] = it.kout;
   }
+  Queue::get().flush();   // let the device start while the host plans the next step
 }
 
 template <typename T>
 void densify_to_host(hipStream_t st, const HSet<T>& H, int m, double* out) {
   const int s = H.s, b = H.b;
   std::vector<T> lv((size_t)H.leaf_stride());
+  Queue::get().flush();
   ACR_HIP(hipMemcpyAsync(lv.data(), H.lv.get() + (size_t)m * H.leaf_stride(), lv.size() * sizeof(T),
                          hipMemcpyDeviceToHost, st));
   std::vector<std::vector<T>> U(H.L + 1), V(H.L + 1);

@@ -1343,20 +1343,21 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
     const GJob* dj = reinterpret_cast<const GJob*>(dev + off[kd]);
     const int nj = (int)by[kd].size();
     const dim3 grid((unsigned)nblk[kd]);
-    ProfScope ps(KC_GEMM, st, fl[kd], bytes[kd]);
+    auto go = [&](auto kern, int threads) {
+      launch(st, KC_GEMM, fl[kd], bytes[kd], kern, grid, dim3(threads), 0, dj, nj, dsegs);
+    };
     switch (kd) {
-      case 0: hipLaunchKernelGGL((k_ggemm<T, 64, 64, 16, 4, 4>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
-      case 1: hipLaunchKernelGGL((k_ggemm<T, 64, 16, 16, 4, 4>), grid, dim3(64), 0, st, dj, nj, dsegs); break;
-      case 2: hipLaunchKernelGGL((k_ggemm<T, 16, 64, 16, 4, 4>), grid, dim3(64), 0, st, dj, nj, dsegs); break;
-      case 3: hipLaunchKernelGGL((k_ggemm<T, 32, 32, 16, 4, 4>), grid, dim3(64), 0, st, dj, nj, dsegs); break;
-      case 4: hipLaunchKernelGGL((k_ggemm<T, 16, 16, 16, 2, 2>), grid, dim3(64), 0, st, dj, nj, dsegs); break;
-      case 5: hipLaunchKernelGGL((k_gemm_dot<T>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
-      case 6: hipLaunchKernelGGL((k_gemm_rows<T, 16>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
-      case 7: hipLaunchKernelGGL((k_gemm_rows<T, sizeof(T) == 4 ? 32 : 16>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
-      case 8: hipLaunchKernelGGL((k_gemm_rows<T, 4>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
-      default: hipLaunchKernelGGL((k_gemm_small<T>), grid, dim3(256), 0, st, dj, nj, dsegs); break;
+      case 0: go(k_ggemm<T, 64, 64, 16, 4, 4>, 256); break;
+      case 1: go(k_ggemm<T, 64, 16, 16, 4, 4>, 64); break;
+      case 2: go(k_ggemm<T, 16, 64, 16, 4, 4>, 64); break;
+      case 3: go(k_ggemm<T, 32, 32, 16, 4, 4>, 64); break;
+      case 4: go(k_ggemm<T, 16, 16, 16, 2, 2>, 64); break;
+      case 5: go(k_gemm_dot<T>, 256); break;
+      case 6: go(k_gemm_rows<T, 16>, 256); break;
+      case 7: go(k_gemm_rows<T, sizeof(T) == 4 ? 32 : 16>, 256); break;
+      case 8: go(k_gemm_rows<T, 4>, 256); break;
+      default: go(k_gemm_small<T>, 256); break;
     }
-    ACR_CHECK_LAUNCH();
   }
 }
 
@@ -1377,33 +1378,30 @@ template <typename Tin, typename Tout>
 void binverse(hipStream_t st, int n, int nprob, const Tin* A, long long sA, Tout* X, long long sX,
               int* status) {
   if (n <= 0 || nprob <= 0) return;
-  ProfScope ps(KC_INVERSE, st, 2.0 * n * n * n * nprob, 2.0 * n * n * nprob * sizeof(Tin));
+  const double fl = 2.0 * n * n * n * nprob, by = 2.0 * n * n * nprob * sizeof(Tin);
   if (n <= 64) {   // one row per lane, 64/N matrices per wave, four waves per workgroup
-    auto launch = [&](auto kern, int Nt) {
+    auto go = [&](auto kern, int Nt) {
       const long long per = 4LL * (WAVE / Nt);
-      hipLaunchKernelGGL(kern, dim3((unsigned)((nprob + per - 1) / per)), dim3(256), 0, st, n, nprob, A, sA,
-                         X, sX, status);
+      launch(st, KC_INVERSE, fl, by, kern, dim3((unsigned)((nprob + per - 1) / per)), dim3(256), 0, n, nprob,
+             A, sA, X, sX, status);
     };
-    if (n <= 8) launch(k_inverse_wave<Tin, Tout, 8>, 8);
-    else if (n <= 16) launch(k_inverse_wave<Tin, Tout, 16>, 16);
-    else if (n <= 32) launch(k_inverse_wave<Tin, Tout, 32>, 32);
-    else launch(k_inverse_wave<Tin, Tout, 64>, 64);
-    ACR_CHECK_LAUNCH();
+    if (n <= 8) go(k_inverse_wave<Tin, Tout, 8>, 8);
+    else if (n <= 16) go(k_inverse_wave<Tin, Tout, 16>, 16);
+    else if (n <= 32) go(k_inverse_wave<Tin, Tout, 32>, 32);
+    else go(k_inverse_wave<Tin, Tout, 64>, 64);
     return;
   }
   if (n <= 88) {   // in place: n*n doubles of LDS (+1.6 KB static) within 64 KB
-    hipLaunchKernelGGL((k_inverse_lds<Tin, Tout>), dim3(nprob), dim3(256), (size_t)n * n * sizeof(double),
-                       st, n, A, sA, X, sX, status);
-    ACR_CHECK_LAUNCH();
+    launch(st, KC_INVERSE, fl, by, k_inverse_lds<Tin, Tout>, dim3(nprob), dim3(256),
+           (size_t)n * n * sizeof(double), n, A, sA, X, sX, status);
     return;
   }
   const size_t lds = (size_t)n * 2 * n * sizeof(double);
   const bool use_lds = lds + 2048 <= kMaxLds;
   DBuf<double> ws;
   if (!use_lds || n > 128) ws.resize((size_t)nprob * n * (2 * n + 1));
-  hipLaunchKernelGGL((k_inverse<Tin, Tout>), dim3(nprob), dim3(256), use_lds ? lds : 0, st, n, A,
-                     sA, X, sX, ws.get(), use_lds ? 1 : 0, status);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_INVERSE, fl, by, k_inverse<Tin, Tout>, dim3(nprob), dim3(256), use_lds ? lds : 0, n, A, sA,
+         X, sX, ws.get(), use_lds ? 1 : 0, status);
 }
 
 template <typename T>
@@ -1434,9 +1432,7 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
   }
   if (use.empty()) return;
   const QJob* dj = upload(use, st);
-  ProfScope ps(KC_QR, st, fl, by);
-  hipLaunchKernelGGL((k_gqr<T>), dim3((unsigned)b0), dim3(256), dyn, st, dj, (int)use.size());
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_QR, fl, by, k_gqr<T>, dim3((unsigned)b0), dim3(256), dyn, dj, (int)use.size());
 }
 
 template <typename T>
@@ -1463,9 +1459,7 @@ void gapply_q(hipStream_t st, std::vector<AJob> jobs) {
   }
   if (use.empty()) return;
   const AJob* dj = upload(use, st);
-  ProfScope ps(KC_APPLYQ, st, fl, by);
-  hipLaunchKernelGGL((k_gapply_q<T>), dim3((unsigned)b0), dim3(256), 0, st, dj, (int)use.size());
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_APPLYQ, fl, by, k_gapply_q<T>, dim3((unsigned)b0), dim3(256), 0, dj, (int)use.size());
 }
 
 template <typename T>
@@ -1511,10 +1505,14 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     use.push_back(J);
   }
   const SJob* dj = upload(use, st);
-  ProfScope ps(KC_SVD, st, 0.0, by);
-  ps.r.dev_flops = fl; ps.r.nprob = (int)total;
-  hipLaunchKernelGGL((k_grsvd<T>), dim3((unsigned)b0), dim3(256), 0, st, dj, (int)use.size());
-  ACR_CHECK_LAUNCH();
+  const int nj = (int)use.size();
+  const int nprob = (int)total;
+  Queue::get().op(st, [=]() {
+    ProfScope ps(KC_SVD, st, 0.0, by);
+    ps.r.dev_flops = fl; ps.r.nprob = nprob;
+    hipLaunchKernelGGL((k_grsvd<T>), dim3((unsigned)b0), dim3(256), 0, st, dj, nj);
+    ACR_HIP(hipGetLastError());
+  });
 }
 
 template <typename T>
@@ -1537,9 +1535,7 @@ void gtrunc(hipStream_t st, std::vector<TJob> jobs) {
   }
   if (use.empty()) return;
   const TJob* dj = upload(use, st);
-  ProfScope ps(KC_COPY, st, 0.0, 0.0);
-  hipLaunchKernelGGL((k_gtrunc<T>), dim3((unsigned)b0), dim3(256), 0, st, dj, (int)use.size());
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_COPY, 0.0, 0.0, k_gtrunc<T>, dim3((unsigned)b0), dim3(256), 0, dj, (int)use.size());
 }
 
 template <typename T>
@@ -1552,8 +1548,7 @@ void btrunc_coef(hipStream_t st, int c, int kout, int nprob, const T* J, const i
 void gmax(hipStream_t st, const std::vector<MJob>& jobs) {
   if (jobs.empty()) return;
   const MJob* dj = upload(jobs, st);
-  hipLaunchKernelGGL(k_gmax, dim3((unsigned)jobs.size()), dim3(256), 0, st, dj);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_OTHER, 0.0, 0.0, k_gmax, dim3((unsigned)jobs.size()), dim3(256), 0, dj);
 }
 
 void bmax_int(hipStream_t st, const int* rank, int n, int* out) {
@@ -1579,9 +1574,7 @@ void gcopy(hipStream_t st, std::vector<CJob> jobs) {
   if (use.empty()) return;
   if (b0 > 0x7fffffffLL) fail(ACR_ERR_INVALID_ARG, "grouped copy grid too large");
   const CJob* dj = upload(use, st);
-  ProfScope ps(KC_COPY, st, 0.0, by);
-  hipLaunchKernelGGL((k_gcopy<T>), dim3((unsigned)b0), dim3(256), 0, st, dj, (int)use.size());
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_COPY, 0.0, by, k_gcopy<T>, dim3((unsigned)b0), dim3(256), 0, dj, (int)use.size());
 }
 
 template <typename T>
@@ -1604,8 +1597,8 @@ void badd(hipStream_t st, int rows, int cols, int nmat, T alpha, const BOp& src,
 template <typename T>
 void fill(hipStream_t st, T* p, size_t n, T v) {
   if (!n) return;
-  hipLaunchKernelGGL((k_fill<T>), dim3(grid1((long long)n, 256, 16384)), dim3(256), 0, st, p, n, v);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_OTHER, 0.0, (double)n * sizeof(T), k_fill<T>, dim3(grid1((long long)n, 256, 16384)),
+         dim3(256), 0, p, n, v);
 }
 
 template <typename T>
@@ -1622,8 +1615,7 @@ template <typename T>
 void build_capacitance(hipStream_t st, int k, int npairs, const T* cores, T* G) {
   if (k <= 0 || npairs <= 0) return;
   dim3 g(grid1(4LL * k * k, 256, 64), npairs);
-  hipLaunchKernelGGL((k_build_cap<T>), g, dim3(256), 0, st, k, npairs, cores, G);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_OTHER, 0.0, 0.0, k_build_cap<T>, g, dim3(256), 0, k, npairs, cores, G);
 }
 
 template <typename T>
@@ -1631,9 +1623,8 @@ void build_leaves_tridiag(hipStream_t st, int s, int b, int nmat, int bmul, int 
                           const double* diag, const double* west, const double* east, T* leaves) {
   if (nmat <= 0) return;
   dim3 g(grid1((long long)s * b, 256, 256), nmat);
-  hipLaunchKernelGGL((k_leaves_tridiag<T>), g, dim3(256), 0, st, s, b, bmul, boff, diag, west, east,
-                     leaves);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_OTHER, 0.0, 0.0, k_leaves_tridiag<T>, g, dim3(256), 0, s, b, bmul, boff, diag, west, east,
+         leaves);
 }
 
 template <typename T>
@@ -1641,74 +1632,63 @@ void build_rank1_factors(hipStream_t st, int s, int sd, int nmat, int bmul, int 
                          const double* west, const double* east, T* U, T* V) {
   if (nmat <= 0) return;
   dim3 g(grid1(s, 256, 64), nmat);
-  hipLaunchKernelGGL((k_rank1<T>), g, dim3(256), 0, st, s, sd, bmul, boff, west, east, U, V);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_OTHER, 0.0, 0.0, k_rank1<T>, g, dim3(256), 0, s, sd, bmul, boff, west, east, U, V);
 }
 
 template <typename T>
 void gather_diag(hipStream_t st, int s, int nmat, int bmul, int boff, const double* src, T* dst) {
   if (nmat <= 0) return;
   dim3 g(grid1(s, 256, 64), nmat);
-  hipLaunchKernelGGL((k_gather_diag<T>), g, dim3(256), 0, st, s, bmul, boff, src, dst);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_OTHER, 0.0, 0.0, k_gather_diag<T>, g, dim3(256), 0, s, bmul, boff, src, dst);
 }
 
 template <typename T>
 void to_blocks(hipStream_t st, int s, int nblk, int nrhs, const double* B, long long ld, T* V) {
   const long long n = (long long)s * nblk * nrhs;
   if (n <= 0) return;
-  ProfScope ps(KC_OTHER, st, 0.0, (double)n * (8 + sizeof(T)));
-  hipLaunchKernelGGL((k_to_blocks<T>), dim3(grid1(n, 256, 16384)), dim3(256), 0, st, s, nblk, nrhs,
-                     B, ld, V);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_OTHER, 0.0, (double)n * (8 + sizeof(T)), k_to_blocks<T>, dim3(grid1(n, 256, 16384)),
+         dim3(256), 0, s, nblk, nrhs, B, ld, V);
 }
 
 template <typename T>
 void from_blocks(hipStream_t st, int s, int nblk, int nrhs, const T* V, double* B, long long ld) {
   const long long n = (long long)s * nblk * nrhs;
   if (n <= 0) return;
-  ProfScope ps(KC_OTHER, st, 0.0, (double)n * (8 + sizeof(T)));
-  hipLaunchKernelGGL((k_from_blocks<T>), dim3(grid1(n, 256, 16384)), dim3(256), 0, st, s, nblk,
-                     nrhs, V, B, ld);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_OTHER, 0.0, (double)n * (8 + sizeof(T)), k_from_blocks<T>, dim3(grid1(n, 256, 16384)),
+         dim3(256), 0, s, nblk, nrhs, V, B, ld);
 }
 
 template <typename T>
 void bdiag_axpy(hipStream_t st, int s, int nrhs, int nmat, T alpha, const T* d, int dmul, int doff,
                 const T* x, int xmul, int xoff, T* y, int ymul, int yoff) {
   if (nmat <= 0) return;
-  ProfScope ps(KC_MATVEC, st, 2.0 * s * nrhs * nmat, (double)sizeof(T) * nmat * (3.0 * s * nrhs + s));
   dim3 g(grid1((long long)s * nrhs, 256, 256), nmat);
-  hipLaunchKernelGGL((k_bdiag_axpy<T>), g, dim3(256), 0, st, s, nrhs, alpha, d, dmul, doff, x, xmul,
-                     xoff, y, ymul, yoff);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_MATVEC, 2.0 * s * nrhs * nmat, (double)sizeof(T) * nmat * (3.0 * s * nrhs + s),
+         k_bdiag_axpy<T>, g, dim3(256), 0, s, nrhs, alpha, d, dmul, doff, x, xmul, xoff, y, ymul, yoff);
 }
 
 void stencil_residual(hipStream_t st, int nx, int ny, int nrhs, const double* diag,
                       const double* west, const double* east, const double* south,
                       const double* north, const double* X, const double* B, double* R) {
   const long long N = (long long)nx * ny;
-  ProfScope ps(KC_OTHER, st, 10.0 * N * nrhs, 8.0 * N * (5.0 + 3.0 * nrhs));
   dim3 g(grid1(N, 256, 8192), nrhs);
-  hipLaunchKernelGGL(k_residual, g, dim3(256), 0, st, nx, ny, diag, west, east, south, north, X, B,
-                     R);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_OTHER, 10.0 * N * nrhs, 8.0 * N * (5.0 + 3.0 * nrhs), k_residual, g, dim3(256), 0, nx, ny,
+         diag, west, east, south, north, X, B, R);
 }
 
 void col_sumsq(hipStream_t st, long long n, int ncol, const double* A, double* out) {
   const int nparts = (int)std::min<long long>(512, std::max<long long>(1, (n + 4095) / 4096));
   const long long chunk = (n + nparts - 1) / nparts;
   DBuf<double> part((size_t)nparts * ncol);
-  hipLaunchKernelGGL(k_col_sumsq_part, dim3(nparts, ncol), dim3(256), 0, st, n, chunk, A, part.get());
-  ACR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_col_sumsq_final, dim3(ncol), dim3(256), 0, st, nparts, part.get(), out);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_OTHER, 0.0, 8.0 * n * ncol, k_col_sumsq_part, dim3(nparts, ncol), dim3(256), 0, n, chunk, A,
+         part.get());
+  launch(st, KC_OTHER, 0.0, 0.0, k_col_sumsq_final, dim3(ncol), dim3(256), 0, nparts, (const double*)part.get(),
+         out);
 }
 
 void flag_nonfinite(hipStream_t st, long long n, const double* a, int* flag) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_count_nonfinite, dim3(grid1(n, 256, 4096)), dim3(256), 0, st, n, a, flag);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_OTHER, 0.0, 8.0 * n, k_count_nonfinite, dim3(grid1(n, 256, 4096)), dim3(256), 0, n, a, flag);
 }
 
 template <typename T>
@@ -1719,11 +1699,12 @@ void scan_values(hipStream_t st, long long n, const T* a, bool* bad, double* ama
   const unsigned g = grid1(n, 256, 1024);
   DBuf<int> flag(1);
   DBuf<double> mx(g);
-  ACR_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int), st));
-  hipLaunchKernelGGL((k_scan_values<T>), dim3(g), dim3(256), 0, st, n, a, flag.get(), mx.get());
-  ACR_CHECK_LAUNCH();
+  memset_async(flag.get(), 0, sizeof(int), st);
+  launch(st, KC_OTHER, 0.0, (double)n * sizeof(T), k_scan_values<T>, dim3(g), dim3(256), 0, n, a, flag.get(),
+         mx.get());
   int hb = 0;
   std::vector<double> hm(g);
+  Queue::get().flush();
   ACR_HIP(hipMemcpyAsync(&hb, flag.get(), sizeof(int), hipMemcpyDeviceToHost, st));
   ACR_HIP(hipMemcpyAsync(hm.data(), mx.get(), g * sizeof(double), hipMemcpyDeviceToHost, st));
   ACR_HIP(hipStreamSynchronize(st));
@@ -1734,8 +1715,7 @@ template void scan_values<float>(hipStream_t, long long, const float*, bool*, do
 template void scan_values<double>(hipStream_t, long long, const double*, bool*, double*);
 
 void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
-  hipLaunchKernelGGL(k_axpy_d, dim3(grid1(n, 256, 16384)), dim3(256), 0, st, n, D, X);
-  ACR_CHECK_LAUNCH();
+  launch(st, KC_OTHER, 0.0, 24.0 * n, k_axpy_d, dim3(grid1(n, 256, 16384)), dim3(256), 0, n, D, X);
 }
 
 #define INST(T)                                                                                   \
