@@ -38,11 +38,43 @@ __device__ __forceinline__ int job_of(const J* jobs, int n, long long bid) {
   return lo;
 }
 
+// Cross-lane moves with DPP (data-parallel primitives: register operand
+// modifiers of VALU instructions, no LDS round trip).  Lanes whose source is
+// out of range or masked off read 0.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWMASK, 0xf, false));
+}
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, ROWMASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane_read(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double lane_read(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)v, l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane: quad sums
+// (quad_perm), row-of-16 sums (row_shr 4, 8: the last lane of each row holds
+// its row's total), then row_bcast 15 / 31 carry the row totals into lane 63,
+// which is read back as a scalar.  Every lane of the wave must be active.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
+  v += dpp_mov<0xb1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4e>(v);        // quad_perm [2,3,0,1]
+  v += dpp_mov<0x114>(v);       // row_shr:4
+  v += dpp_mov<0x118>(v);       // row_shr:8
+  v += dpp_mov<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_mov<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return lane_read(v, 63);
 }
 
 template <typename T>
