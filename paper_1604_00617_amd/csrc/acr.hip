@@ -116,6 +116,9 @@ struct Factor final : FactorBase {
   }
 
   void solve(const double* B, double* Xout, int nrhs, hipStream_t st) override;
+  void solve_fused(const double* B, double* Xout, int nrhs, hipStream_t st);
+  void solve_gemm(const double* B, double* Xout, int nrhs, hipStream_t st);
+  bool fused_ok(int nrhs) const;
 };
 
 template <typename T>
@@ -126,7 +129,126 @@ Flat<T> vflat(T* p, int s, int nrhs, int mmul = 1, int moff = 0) {
 }
 
 template <typename T>
+MVTerm mv_hodlr(const HSet<T>& H, int mmul, int moff, const T* y, int ymul, int yoff, double alpha) {
+  MVTerm M;
+  M.type = 0;
+  M.mmul = mmul; M.moff = moff; M.ymul = ymul; M.yoff = yoff; M.alpha = alpha; M.y = y;
+  M.lv = H.lv.get();
+  for (int d = 1; d <= H.L; ++d) {
+    M.U[d] = H.U[d].get(); M.V[d] = H.V[d].get(); M.k[d] = H.k[d]; M.kc[d] = H.kc[d];
+  }
+  return M;
+}
+
+template <typename T>
+MVTerm mv_diag(const T* dg, int mmul, int moff, const T* y, int ymul, int yoff, double alpha) {
+  MVTerm M;
+  M.type = 1;
+  M.mmul = mmul; M.moff = moff; M.ymul = ymul; M.yoff = yoff; M.alpha = alpha; M.y = y; M.lv = dg;
+  return M;
+}
+
+template <typename T>
+MVJob mv_job(int nmat, T* out, int omul, int ooff, int term0, int nterm, const T* C0 = nullptr, int cmul = 1,
+             int coff = 0, double beta = 1.0) {
+  MVJob J;
+  J.nmat = nmat; J.out = out; J.omul = omul; J.ooff = ooff; J.term0 = term0; J.nterm = nterm;
+  J.C0 = C0; J.cmul = cmul; J.coff = coff; J.beta = beta;
+  return J;
+}
+
+template <typename T>
+bool Factor<T>::fused_ok(int nrhs) const {
+  if (nrhs > 8 || L > kMvMaxDepth) return false;
+  const int NR = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8;
+  auto fits = [&](const HSet<T>& H) {
+    int t = 0;
+    for (int d = 1; d <= H.L; ++d) t += H.kc[d] * NR;
+    return t <= 512;
+  };
+  if (!fits(Xlast)) return false;
+  for (const auto& l : lev)
+    if (!fits(l.X) || (!l.diag && (!fits(l.E) || !fits(l.F)))) return false;
+  return true;
+}
+
+template <typename T>
 void Factor<T>::solve(const double* B, double* Xout, int nrhs, hipStream_t st) {
+  if (fused_ok(nrhs)) solve_fused(B, Xout, nrhs, st);
+  else solve_gemm(B, Xout, nrhs, st);
+}
+
+// Few right-hand sides: every step of a level is one fused matvec launch.
+// U[l] holds the level-l unknowns with one zero pad block at each end.
+template <typename T>
+void Factor<T>::solve_fused(const double* B, double* Xout, int nrhs, hipStream_t st) {
+  const int s = nx;
+  const int nl = (int)lev.size();
+  const size_t blk = (size_t)s * nrhs;
+  std::vector<DBuf<T>> F(nl + 1), G(nl), U(nl + 1);
+  F[0].resize((size_t)ny * blk);
+  to_blocks<T>(st, s, ny, nrhs, B, (long long)nx * ny, F[0].get());
+  for (int l = 0; l < nl; ++l) {
+    const Level<T>& Lv = lev[l];
+    const int m = Lv.m, nodd = m / 2;
+    G[l].resize((size_t)Lv.ne * blk);
+    {  // g_k = X_k f_(2k); the dummy slot (m even) is zero
+      std::vector<MVTerm> tm{mv_hodlr<T>(Lv.X, 1, 0, F[l].get(), 2, 0, 1.0)};
+      std::vector<MVJob> jb{mv_job<T>(Lv.nreal, G[l].get(), 1, 0, 0, 1),
+                            mv_job<T>(Lv.ne - Lv.nreal, G[l].get(), 1, Lv.nreal, 0, 0)};
+      ghmv<T>(st, s, b, L, nrhs, jb, tm);
+    }
+    F[l + 1].resize((size_t)nodd * blk);
+    if (nodd > 0) {  // f'_j = f_(2j+1) - E_(2j+1) g_j - F_(2j+1) g_(j+1)
+      std::vector<MVTerm> tm;
+      if (Lv.diag) {
+        tm.push_back(mv_diag<T>(Lv.e0.get(), 2, 1, G[l].get(), 1, 0, -1.0));
+        tm.push_back(mv_diag<T>(Lv.f0.get(), 2, 1, G[l].get(), 1, 1, -1.0));
+      } else {
+        tm.push_back(mv_hodlr<T>(Lv.E, 2, 1, G[l].get(), 1, 0, -1.0));
+        tm.push_back(mv_hodlr<T>(Lv.F, 2, 1, G[l].get(), 1, 1, -1.0));
+      }
+      std::vector<MVJob> jb{mv_job<T>(nodd, F[l + 1].get(), 1, 0, 0, 2, F[l].get(), 2, 1, 1.0)};
+      ghmv<T>(st, s, b, L, nrhs, jb, tm);
+    }
+  }
+  U[nl].resize(3 * blk);
+  {
+    std::vector<MVTerm> tm{mv_hodlr<T>(Xlast, 1, 0, F[nl].get(), 1, 0, 1.0)};
+    std::vector<MVJob> jb{mv_job<T>(1, U[nl].get(), 1, 1, 0, 1), mv_job<T>(2, U[nl].get(), 2, 0, 0, 0)};
+    ghmv<T>(st, s, b, L, nrhs, jb, tm);
+  }
+  for (int l = nl - 1; l >= 0; --l) {
+    const Level<T>& Lv = lev[l];
+    const int m = Lv.m, nodd = m / 2;
+    U[l].resize((size_t)(m + 2) * blk);
+    DBuf<T> tmp((size_t)Lv.nreal * blk);
+    {  // tmp_k = E_(2k) u_(2k-1) + F_(2k) u_(2k+1): level-(l+1) unknowns k-1 and k (padded k, k+1)
+      std::vector<MVTerm> tm;
+      if (Lv.diag) {
+        tm.push_back(mv_diag<T>(Lv.e0.get(), 2, 0, U[l + 1].get(), 1, 0, 1.0));
+        tm.push_back(mv_diag<T>(Lv.f0.get(), 2, 0, U[l + 1].get(), 1, 1, 1.0));
+      } else {
+        tm.push_back(mv_hodlr<T>(Lv.E, 2, 0, U[l + 1].get(), 1, 0, 1.0));
+        tm.push_back(mv_hodlr<T>(Lv.F, 2, 0, U[l + 1].get(), 1, 1, 1.0));
+      }
+      std::vector<MVJob> jb{mv_job<T>(Lv.nreal, tmp.get(), 1, 0, 0, 2)};
+      ghmv<T>(st, s, b, L, nrhs, jb, tm);
+    }
+    {  // u_(2k) = g_k - X_k tmp_k; odd unknowns from level l+1; zero pads
+      std::vector<MVTerm> tm{mv_hodlr<T>(Lv.X, 1, 0, tmp.get(), 1, 0, -1.0)};
+      std::vector<MVJob> jb{mv_job<T>(Lv.nreal, U[l].get(), 2, 1, 0, 1, G[l].get(), 1, 0, 1.0),
+                            mv_job<T>(nodd, U[l].get(), 2, 2, 0, 0, U[l + 1].get(), 1, 1, 1.0),
+                            mv_job<T>(1, U[l].get(), 1, 0, 0, 0),
+                            mv_job<T>(1, U[l].get(), 1, m + 1, 0, 0)};
+      ghmv<T>(st, s, b, L, nrhs, jb, tm);
+    }
+  }
+  from_blocks<T>(st, s, ny, nrhs, U[0].get() + blk, Xout, (long long)nx * ny);
+}
+
+template <typename T>
+void Factor<T>::solve_gemm(const double* B, double* Xout, int nrhs, hipStream_t st) {
   const int s = nx;
   const int nl = (int)lev.size();
   const size_t blk = (size_t)s * nrhs;

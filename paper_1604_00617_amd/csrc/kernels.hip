@@ -18,6 +18,7 @@ namespace {
 
 constexpr int WAVE = 64;
 constexpr size_t kMaxLds = 65536;   // dynamic + static LDS budget per workgroup
+constexpr int kMvSlots = 512;        // reduced values per term in the fused matvec
 
 template <typename T>
 __device__ __forceinline__ const T* optr(const BOp& o, int m, int c) {
@@ -428,6 +429,142 @@ __global__ __launch_bounds__(256) void k_gemm_rows(const GJob* __restrict__ jobs
       T v = alpha * v0;
       if (beta != T(0)) v = fma(beta, *cp, v);
       *cp = v;
+    }
+  }
+}
+
+// ------------------------------------------------------ fused HODLR matvec
+// One workgroup per (job, matrix, leaf) computes the leaf's rows of
+//   beta * C0 + sum_t alpha_t op_t y_t.
+// A HODLR term adds the leaf block times y (leaf rows) and, for every depth
+// d, U_d[leaf rows] (V_d[sibling rows]^T y[sibling rows]) with the sibling of
+// the leaf's depth-d ancestor.  The small reductions are recomputed by each
+// leaf's workgroup; the sibling clusters of the depths are disjoint, so a
+// workgroup reads every V row of its matrix at most once, and the leaves of
+// one matrix are placed on one XCD (block b runs on XCD b mod 8) so that they
+// share its L2.
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_hmv(const MVJob* __restrict__ jobs, int njobs,
+                                             const MVTerm* __restrict__ terms, int s, int b, int L,
+                                             int nrhs, long long nblocks) {
+  constexpr int CH = 8;   // reduction columns per pass
+  __shared__ T tpart[4][kMvSlots];
+  __shared__ T lred[256 * NR];
+  const long long per = (nblocks + 7) / 8;
+  const long long lb = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (lb >= nblocks) return;   // uniform over the workgroup, before any barrier
+  const MVJob& J = jobs[job_of(jobs, njobs, lb)];
+  const int nleaf = 1 << L;
+  const long long local = lb - J.block0;
+  const int m = (int)(local / nleaf), l = (int)(local % nleaf);
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  const int nparts = 256 / b, r = tid % b, part = tid / b;
+  const bool rowt = part < nparts;
+  const int row0 = l * b;
+  const long long vs = (long long)s * nrhs;
+  T acc[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) acc[q] = T(0);
+  for (int t = 0; t < J.nterm; ++t) {
+    const MVTerm& M = terms[J.term0 + t];
+    const T alpha = (T)M.alpha;
+    const int mm = M.mmul * m + M.moff;
+    const T* y = static_cast<const T*>(M.y) + (long long)(M.ymul * m + M.yoff) * vs;
+    if (M.type == 1) {
+      if (rowt && part == 0) {
+        const T dv = alpha * static_cast<const T*>(M.lv)[(long long)mm * s + row0 + r];
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+          if (q < nrhs) acc[q] = fma(dv, y[row0 + r + (long long)q * s], acc[q]);
+      }
+      continue;
+    }
+    // reductions V_d[sibling]^T y[sibling] of all depths (per-wave partial sums)
+    int slot = 0;
+    for (int d = 1; d <= L; ++d) {
+      const int w = M.kc[d];
+      if (w == 0) continue;
+      const int sd = s >> d;
+      const int sib = (l >> (L - d)) ^ 1;
+      const T* V = static_cast<const T*>(M.V[d]) + (long long)mm * M.k[d] * s;
+      for (int q0 = 0; q0 < w; q0 += CH) {
+        T pr[CH][NR];
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+#pragma unroll
+          for (int q = 0; q < NR; ++q) pr[c][q] = T(0);
+        for (int i = sib * sd + tid; i < (sib + 1) * sd; i += 256) {
+          T yv[NR];
+#pragma unroll
+          for (int q = 0; q < NR; ++q) yv[q] = q < nrhs ? y[i + (long long)q * s] : T(0);
+#pragma unroll
+          for (int c = 0; c < CH; ++c) {
+            if (q0 + c < w) {
+              const T v = V[i + (long long)(q0 + c) * s];
+#pragma unroll
+              for (int q = 0; q < NR; ++q) pr[c][q] = fma(v, yv[q], pr[c][q]);
+            }
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          if (q0 + c < w) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+              if (q < nrhs) {
+                const T tot = wave_sum(pr[c][q]);
+                if (lane == 0) tpart[wv][slot + (q0 + c) * NR + q] = tot;
+              }
+            }
+          }
+        }
+      }
+      slot += w * NR;
+    }
+    __syncthreads();
+    if (rowt) {
+      // leaf block times y (this thread: row r, columns part, part + nparts, ...)
+      const T* lf = static_cast<const T*>(M.lv) + ((long long)mm * nleaf + l) * b * b;
+      for (int j = part; j < b; j += nparts) {
+        const T a = alpha * lf[r + (long long)j * b];
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+          if (q < nrhs) acc[q] = fma(a, y[row0 + j + (long long)q * s], acc[q]);
+      }
+      // U_d[leaf rows] times the reduced values
+      slot = 0;
+      for (int d = 1; d <= L; ++d) {
+        const int w = M.kc[d];
+        if (w == 0) continue;
+        const T* Ud = static_cast<const T*>(M.U[d]) + (long long)mm * M.k[d] * s + row0 + r;
+        for (int c = part; c < w; c += nparts) {
+          const T u = alpha * Ud[(long long)c * s];
+#pragma unroll
+          for (int q = 0; q < NR; ++q) {
+            if (q < nrhs) {
+              const int o = slot + c * NR + q;
+              acc[q] = fma(u, tpart[0][o] + tpart[1][o] + tpart[2][o] + tpart[3][o], acc[q]);
+            }
+          }
+        }
+        slot += w * NR;
+      }
+    }
+    __syncthreads();   // tpart is reused by the next term
+  }
+  if (rowt)
+#pragma unroll
+    for (int q = 0; q < NR; ++q) lred[(part * b + r) * NR + q] = acc[q];
+  __syncthreads();
+  if (rowt && part == 0) {
+    T* out = static_cast<T*>(J.out) + (long long)(J.omul * m + J.ooff) * vs;
+    const T* c0 = J.C0 ? static_cast<const T*>(J.C0) + (long long)(J.cmul * m + J.coff) * vs : nullptr;
+    const T beta = (T)J.beta;
+    for (int q = 0; q < nrhs; ++q) {
+      T v = T(0);
+      for (int pp = 0; pp < nparts; ++pp) v += lred[(pp * b + r) * NR + q];
+      if (c0) v = fma(beta, c0[row0 + r + (long long)q * s], v);
+      out[row0 + r + (long long)q * s] = v;
     }
   }
 }
@@ -1610,6 +1747,58 @@ void gcopy(hipStream_t st, std::vector<CJob> jobs) {
 }
 
 template <typename T>
+void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs,
+          const std::vector<MVTerm>& terms) {
+  if (nrhs < 1 || nrhs > 8) fail(ACR_ERR_INTERNAL, "fused matvec takes 1..8 right-hand sides");
+  if (b < 1 || b > 256 || L > kMvMaxDepth || (b << L) != s) fail(ACR_ERR_INTERNAL, "fused matvec shape");
+  const int NR = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8;
+  const int nleaf = 1 << L;
+  double fl = 0, by = 0;
+  for (const auto& M : terms) {
+    if (M.type != 0) continue;
+    int slots = 0;
+    for (int d = 1; d <= L; ++d) slots += M.kc[d] * NR;
+    if (slots > kMvSlots) fail(ACR_ERR_INTERNAL, "fused matvec: ranks too large");
+  }
+  std::vector<MVJob> use;
+  long long b0 = 0;
+  for (auto& J : jobs) {
+    if (J.nmat <= 0) continue;
+    J.block0 = b0;
+    b0 += (long long)J.nmat * nleaf;
+    for (int t = 0; t < J.nterm; ++t) {
+      const MVTerm& M = terms[J.term0 + t];
+      double e = 0;
+      if (M.type == 1) {
+        e = s;
+      } else {
+        e = (double)s * b;
+        for (int d = 1; d <= L; ++d) e += 2.0 * s * M.kc[d];
+      }
+      by += (double)J.nmat * (e + (double)s * nrhs) * sizeof(T);
+      fl += 2.0 * J.nmat * e * nrhs;
+    }
+    by += (double)J.nmat * s * nrhs * sizeof(T) * (J.C0 ? 2 : 1);
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  if (b0 > (1LL << 31) - 8) fail(ACR_ERR_INVALID_ARG, "fused matvec grid too large");
+  const MVJob* dj = upload(use, st);
+  const MVTerm* dt = terms.empty() ? nullptr : upload(terms, st);
+  const dim3 grid((unsigned)(8 * ((b0 + 7) / 8)));
+  const int nj = (int)use.size();
+  auto go = [&](auto kern) {
+    launch(st, KC_MATVEC, fl, by, kern, grid, dim3(256), 0, dj, nj, dt, s, b, L, nrhs, b0);
+  };
+  switch (NR) {
+    case 1: go(k_hmv<T, 1>); break;
+    case 2: go(k_hmv<T, 2>); break;
+    case 4: go(k_hmv<T, 4>); break;
+    default: go(k_hmv<T, 8>); break;
+  }
+}
+
+template <typename T>
 void bcopy(hipStream_t st, int rows, int cols, int nmat, T alpha, const BOp& src, const BOp& dst) {
   std::vector<CJob> jobs(1);
   CJob& J = jobs[0];
@@ -1752,6 +1941,7 @@ void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
 
 #define INST(T)                                                                                   \
   template void ggemm<T>(hipStream_t, std::vector<GJob>, const std::vector<GSeg>&);               \
+  template void ghmv<T>(hipStream_t, int, int, int, int, std::vector<MVJob>, const std::vector<MVTerm>&); \
   template void gqr<T>(hipStream_t, std::vector<QJob>);                                           \
   template void grsvd<T>(hipStream_t, std::vector<SJob>);                                         \
   template void gapply_q<T>(hipStream_t, std::vector<AJob>);                                      \

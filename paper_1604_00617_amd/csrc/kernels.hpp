@@ -99,6 +99,38 @@ struct CJob {
   long long sstride = 0, scl = 0;
 };
 
+// Fused multi-term HODLR matvec for a few right-hand sides (solve path):
+//   out_m = beta * C0_m + sum_t alpha_t op_t(m) y_t(m)
+// with op_t a HODLR matrix of a set (all of one launch share s, b, L) or a
+// diagonal.  Vector blocks are s x nrhs, column-major, block stride s*nrhs;
+// block index of matrix m is mul*m + off for every operand.
+constexpr int kMvMaxDepth = 15;
+struct MVTerm {
+  int type = 0;               // 0 HODLR, 1 diagonal
+  int mmul = 1, moff = 0;     // operator index
+  int ymul = 1, yoff = 0;     // y block index
+  int pad = 0;
+  double alpha = 1.0;
+  const void* y = nullptr;
+  const void* lv = nullptr;   // leaves [cnt][2^L][b][b] (HODLR) or diagonals [cnt][s]
+  const void* U[kMvMaxDepth + 1] = {};
+  const void* V[kMvMaxDepth + 1] = {};
+  int k[kMvMaxDepth + 1] = {};    // allocated columns per depth (matrix stride k*s)
+  int kc[kMvMaxDepth + 1] = {};   // used columns
+};
+struct MVJob {
+  long long block0 = 0;
+  int nmat = 0, nterm = 0, term0 = 0;
+  int omul = 1, ooff = 0, cmul = 1, coff = 0;
+  double beta = 0.0;
+  const void* C0 = nullptr;       // null: out = sum of terms
+  void* out = nullptr;
+};
+
+template <typename T>
+void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs,
+          const std::vector<MVTerm>& terms);
+
 template <typename T>
 void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs);
 template <typename T>
