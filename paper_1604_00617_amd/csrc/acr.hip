@@ -161,10 +161,12 @@ template <typename T>
 bool Factor<T>::fused_ok(int nrhs) const {
   if (nrhs > 8 || L > kMvMaxDepth) return false;
   const int NR = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8;
+  // a launch pairs at most two HODLR terms: their reduced values and row-block
+  // columns must fit the kernel's LDS tables (512 entries each)
   auto fits = [&](const HSet<T>& H) {
-    int t = 0;
-    for (int d = 1; d <= H.L; ++d) t += H.kc[d] * NR;
-    return t <= 512;
+    int w = 0;
+    for (int d = 1; d <= H.L; ++d) w += H.kc[d];
+    return 2 * w * NR <= 512 && 2 * (H.b + w) <= 512;
   };
   if (!fits(Xlast)) return false;
   for (const auto& l : lev)

@@ -18,7 +18,8 @@ namespace {
 
 constexpr int WAVE = 64;
 constexpr size_t kMaxLds = 65536;   // dynamic + static LDS budget per workgroup
-constexpr int kMvSlots = 512;        // reduced values per term in the fused matvec
+constexpr int kMvSlots = 512;        // reduced values per workgroup in the fused matvec
+constexpr int kMvCols = 512;         // row-block columns per workgroup in the fused matvec
 
 template <typename T>
 __device__ __forceinline__ const T* optr(const BOp& o, int m, int c) {
@@ -439,16 +440,24 @@ __global__ __launch_bounds__(256) void k_gemm_rows(const GJob* __restrict__ jobs
 // A HODLR term adds the leaf block times y (leaf rows) and, for every depth
 // d, U_d[leaf rows] (V_d[sibling rows]^T y[sibling rows]) with the sibling of
 // the leaf's depth-d ancestor.  The small reductions are recomputed by each
-// leaf's workgroup; the sibling clusters of the depths are disjoint, so a
-// workgroup reads every V row of its matrix at most once, and the leaves of
-// one matrix are placed on one XCD (block b runs on XCD b mod 8) so that they
-// share its L2.
+// leaf's workgroup (the sibling clusters of the depths are disjoint, so the
+// workgroup reads every V row of its matrix at most once); the leaves of one
+// matrix are placed on one XCD (block b runs on XCD b mod 8) to share its L2.
+// Phase 1: one wave per (term, depth) reduction, loads batched in registers;
+// meanwhile the other threads build a table of the row block's columns
+// (leaf columns and U columns of every term) and their multipliers.
+// Phase 2: every thread (row r, column slice) sums its columns, loads again
+// batched; the slices are combined through LDS.
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_hmv(const MVJob* __restrict__ jobs, int njobs,
                                              const MVTerm* __restrict__ terms, int s, int b, int L,
                                              int nrhs, long long nblocks) {
-  constexpr int CH = 8;   // reduction columns per pass
-  __shared__ T tpart[4][kMvSlots];
+  constexpr int CH = 16;                 // reduction columns per chunk
+  constexpr int RB = NR <= 1 ? 4 : NR <= 2 ? 2 : 1;   // rows per lane per batch
+  constexpr int CB = 32;                 // columns per thread per batch in phase 2
+  __shared__ T tv[kMvSlots];
+  __shared__ const T* ccol[kMvCols];
+  __shared__ T cval[kMvCols * NR];
   __shared__ T lred[256 * NR];
   const long long per = (nblocks + 7) / 8;
   const long long lb = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -457,7 +466,8 @@ __global__ __launch_bounds__(256) void k_hmv(const MVJob* __restrict__ jobs, int
   const int nleaf = 1 << L;
   const long long local = lb - J.block0;
   const int m = (int)(local / nleaf), l = (int)(local % nleaf);
-  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  const int tid = threadIdx.x, lane = tid % WAVE;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
   const int nparts = 256 / b, r = tid % b, part = tid / b;
   const bool rowt = part < nparts;
   const int row0 = l * b;
@@ -465,106 +475,140 @@ __global__ __launch_bounds__(256) void k_hmv(const MVJob* __restrict__ jobs, int
   T acc[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = T(0);
+  // C0 and the diagonal terms (loads issued first)
+  if (rowt && part == 0) {
+    if (J.C0) {
+      const T* c0 = static_cast<const T*>(J.C0) + (long long)(J.cmul * m + J.coff) * vs + row0 + r;
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (q < nrhs) acc[q] = (T)J.beta * c0[(long long)q * s];
+    }
+    for (int t = 0; t < J.nterm; ++t) {
+      const MVTerm& M = terms[J.term0 + t];
+      if (M.type != 1) continue;
+      const int mm = M.mmul * m + M.moff;
+      const T* y = static_cast<const T*>(M.y) + (long long)(M.ymul * m + M.yoff) * vs + row0 + r;
+      const T dv = (T)M.alpha * static_cast<const T*>(M.lv)[(long long)mm * s + row0 + r];
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (q < nrhs) acc[q] = fma(dv, y[(long long)q * s], acc[q]);
+    }
+  }
+  // ---- phase 1
+  int npair = 0, ncol = 0, nslot = 0;
   for (int t = 0; t < J.nterm; ++t) {
     const MVTerm& M = terms[J.term0 + t];
-    const T alpha = (T)M.alpha;
+    if (M.type != 0) continue;
     const int mm = M.mmul * m + M.moff;
+    const T alpha = (T)M.alpha;
     const T* y = static_cast<const T*>(M.y) + (long long)(M.ymul * m + M.yoff) * vs;
-    if (M.type == 1) {
-      if (rowt && part == 0) {
-        const T dv = alpha * static_cast<const T*>(M.lv)[(long long)mm * s + row0 + r];
-#pragma unroll
-        for (int q = 0; q < NR; ++q)
-          if (q < nrhs) acc[q] = fma(dv, y[row0 + r + (long long)q * s], acc[q]);
-      }
-      continue;
-    }
-    // reductions V_d[sibling]^T y[sibling] of all depths (per-wave partial sums)
-    int slot = 0;
+    int wsum = 0;
     for (int d = 1; d <= L; ++d) {
       const int w = M.kc[d];
       if (w == 0) continue;
       const int sd = s >> d;
       const int sib = (l >> (L - d)) ^ 1;
-      const T* V = static_cast<const T*>(M.V[d]) + (long long)mm * M.k[d] * s;
-      for (int q0 = 0; q0 < w; q0 += CH) {
-        T pr[CH][NR];
+      if ((npair++ & 3) == wv) {
+        // this wave: tv[slot + q*NR + k] = V_d[sibling]^T y[sibling]
+        const T* Vb = static_cast<const T*>(M.V[d]) + (long long)mm * M.k[d] * s + (long long)sib * sd;
+        const T* yb = y + (long long)sib * sd;
+        const int slot = nslot + wsum * NR;
+        for (int q0 = 0; q0 < w; q0 += CH) {
+          T pr[CH][NR];
 #pragma unroll
-        for (int c = 0; c < CH; ++c)
+          for (int c = 0; c < CH; ++c)
 #pragma unroll
-          for (int q = 0; q < NR; ++q) pr[c][q] = T(0);
-        for (int i = sib * sd + tid; i < (sib + 1) * sd; i += 256) {
-          T yv[NR];
+            for (int q = 0; q < NR; ++q) pr[c][q] = T(0);
+          for (int i0 = 0; i0 < sd; i0 += WAVE * RB) {
+            T vv[RB][CH], yv[RB][NR];
 #pragma unroll
-          for (int q = 0; q < NR; ++q) yv[q] = q < nrhs ? y[i + (long long)q * s] : T(0);
+            for (int u = 0; u < RB; ++u) {
+              const int i = i0 + u * WAVE + lane;
+              const bool ok = i < sd;
+#pragma unroll
+              for (int q = 0; q < NR; ++q) yv[u][q] = (ok && q < nrhs) ? yb[i + (long long)q * s] : T(0);
+#pragma unroll
+              for (int c = 0; c < CH; ++c) vv[u][c] = (ok && q0 + c < w) ? Vb[i + (long long)(q0 + c) * s] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u)
+#pragma unroll
+              for (int c = 0; c < CH; ++c)
+#pragma unroll
+                for (int q = 0; q < NR; ++q) pr[c][q] = fma(vv[u][c], yv[u][q], pr[c][q]);
+          }
 #pragma unroll
           for (int c = 0; c < CH; ++c) {
             if (q0 + c < w) {
-              const T v = V[i + (long long)(q0 + c) * s];
 #pragma unroll
-              for (int q = 0; q < NR; ++q) pr[c][q] = fma(v, yv[q], pr[c][q]);
-            }
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < CH; ++c) {
-          if (q0 + c < w) {
-#pragma unroll
-            for (int q = 0; q < NR; ++q) {
-              if (q < nrhs) {
+              for (int q = 0; q < NR; ++q) {
                 const T tot = wave_sum(pr[c][q]);
-                if (lane == 0) tpart[wv][slot + (q0 + c) * NR + q] = tot;
+                if (lane == 0) tv[slot + (q0 + c) * NR + q] = tot;
               }
             }
           }
         }
       }
-      slot += w * NR;
+      wsum += w;
     }
-    __syncthreads();
-    if (rowt) {
-      // leaf block times y (this thread: row r, columns part, part + nparts, ...)
-      const T* lf = static_cast<const T*>(M.lv) + ((long long)mm * nleaf + l) * b * b;
-      for (int j = part; j < b; j += nparts) {
-        const T a = alpha * lf[r + (long long)j * b];
-#pragma unroll
-        for (int q = 0; q < NR; ++q)
-          if (q < nrhs) acc[q] = fma(a, y[row0 + j + (long long)q * s], acc[q]);
-      }
-      // U_d[leaf rows] times the reduced values
-      slot = 0;
-      for (int d = 1; d <= L; ++d) {
-        const int w = M.kc[d];
-        if (w == 0) continue;
-        const T* Ud = static_cast<const T*>(M.U[d]) + (long long)mm * M.k[d] * s + row0 + r;
-        for (int c = part; c < w; c += nparts) {
-          const T u = alpha * Ud[(long long)c * s];
-#pragma unroll
-          for (int q = 0; q < NR; ++q) {
-            if (q < nrhs) {
-              const int o = slot + c * NR + q;
-              acc[q] = fma(u, tpart[0][o] + tpart[1][o] + tpart[2][o] + tpart[3][o], acc[q]);
-            }
-          }
-        }
-        slot += w * NR;
-      }
+    // column table: leaf columns, then the U columns of every depth
+    const T* lf = static_cast<const T*>(M.lv) + ((long long)mm * nleaf + l) * b * b;
+    for (int e = tid; e < b; e += 256) ccol[ncol + e] = lf + (long long)e * b;
+    for (int e = tid; e < b * NR; e += 256) {
+      const int jc = e / NR, q = e % NR;
+      cval[(ncol + jc) * NR + q] = q < nrhs ? alpha * y[row0 + jc + (long long)q * s] : T(0);
     }
-    __syncthreads();   // tpart is reused by the next term
+    for (int g = tid; g < wsum; g += 256) {
+      int d = 1, q = g;
+      while (q >= M.kc[d]) { q -= M.kc[d]; ++d; }
+      ccol[ncol + b + g] = static_cast<const T*>(M.U[d]) + (long long)mm * M.k[d] * s + (long long)q * s + row0;
+    }
+    ncol += b + wsum;
+    nslot += wsum * NR;
   }
-  if (rowt)
+  __syncthreads();
+  // multipliers of the U columns: alpha_t * reduced values
+  {
+    int c0 = 0, sl = 0;
+    for (int t = 0; t < J.nterm; ++t) {
+      const MVTerm& M = terms[J.term0 + t];
+      if (M.type != 0) continue;
+      int wsum = 0;
+      for (int d = 1; d <= L; ++d) wsum += M.kc[d];
+      const T alpha = (T)M.alpha;
+      for (int e = tid; e < wsum * NR; e += 256) cval[(c0 + b) * NR + e] = alpha * tv[sl + e];
+      c0 += b + wsum;
+      sl += wsum * NR;
+    }
+  }
+  __syncthreads();
+  // ---- phase 2: acc += sum over columns of column[r] * multiplier
+  if (rowt) {
+    for (int cb = part; cb < ncol; cb += nparts * CB) {
+      T a[CB];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        const int c = cb + u * nparts;
+        a[u] = c < ncol ? ccol[c][r] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        const int c = cb + u * nparts;
+        if (c < ncol)
+#pragma unroll
+          for (int q = 0; q < NR; ++q) acc[q] = fma(a[u], cval[c * NR + q], acc[q]);
+      }
+    }
 #pragma unroll
     for (int q = 0; q < NR; ++q) lred[(part * b + r) * NR + q] = acc[q];
+  }
   __syncthreads();
   if (rowt && part == 0) {
-    T* out = static_cast<T*>(J.out) + (long long)(J.omul * m + J.ooff) * vs;
-    const T* c0 = J.C0 ? static_cast<const T*>(J.C0) + (long long)(J.cmul * m + J.coff) * vs : nullptr;
-    const T beta = (T)J.beta;
+    T* out = static_cast<T*>(J.out) + (long long)(J.omul * m + J.ooff) * vs + row0 + r;
     for (int q = 0; q < nrhs; ++q) {
-      T v = T(0);
-      for (int pp = 0; pp < nparts; ++pp) v += lred[(pp * b + r) * NR + q];
-      if (c0) v = fma(beta, c0[row0 + r + (long long)q * s], v);
-      out[row0 + r + (long long)q * s] = v;
+      T v = lred[r * NR + q];
+      for (int pp = 1; pp < nparts; ++pp) v += lred[(pp * b + r) * NR + q];
+      out[(long long)q * s] = v;
     }
   }
 }
@@ -1754,11 +1798,15 @@ void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs
   const int NR = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8;
   const int nleaf = 1 << L;
   double fl = 0, by = 0;
-  for (const auto& M : terms) {
-    if (M.type != 0) continue;
-    int slots = 0;
-    for (int d = 1; d <= L; ++d) slots += M.kc[d] * NR;
-    if (slots > kMvSlots) fail(ACR_ERR_INTERNAL, "fused matvec: ranks too large");
+  for (const auto& J : jobs) {
+    int slots = 0, cols = 0;
+    for (int t = 0; t < J.nterm; ++t) {
+      const MVTerm& M = terms[J.term0 + t];
+      if (M.type != 0) continue;
+      cols += b;
+      for (int d = 1; d <= L; ++d) { slots += M.kc[d] * NR; cols += M.kc[d]; }
+    }
+    if (slots > kMvSlots || cols > kMvCols) fail(ACR_ERR_INTERNAL, "fused matvec: ranks too large");
   }
   std::vector<MVJob> use;
   long long b0 = 0;
