@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phases", action="store_true",
+                    help="print a per-stage timing table of the profiled step to stderr")
     ap.add_argument("--cpu-rows", type=int, default=8,
                     help="block rows of the operator the CPU oracle factors (bounded sample)")
     return ap.parse_args()
@@ -75,6 +77,16 @@ def dominant_class(acr, torch, op, b, args, precision):
     acr.acr_destroy(h)
     torch.cuda.synchronize()
     table = {c: acr.acr_profile_read(c) for c in acr.KERNEL_CLASSES}
+    if args.phases:
+        rows = acr.acr_profile_report()
+        by_stage = {}
+        for stage, level, cls, n, ms in rows:
+            by_stage.setdefault(stage, 0.0)
+            by_stage[stage] += ms
+        for stage, ms in sorted(by_stage.items(), key=lambda kv: -kv[1]):
+            print(f"[stage] {stage:24s} {ms:8.3f} ms", file=sys.stderr)
+        for stage, level, cls, n, ms in sorted(rows, key=lambda r: -r[4])[:40]:
+            print(f"[stage-level] {stage:24s} L{level:<3d} {cls:8s} {n:5d} {ms:8.3f} ms", file=sys.stderr)
     acr.acr_profile_start([])
     best = max(table.values(), key=lambda r: r["total_ms"])
     return best["class"], table

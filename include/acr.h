@@ -177,6 +177,15 @@ acr_status acr_profile_start(uint32_t class_mask);
 acr_status acr_profile_read(int32_t cls, int64_t* launches, double* total_ms, double* flops,
                             double* bytes);
 
+/* Text report of the launches recorded since acr_profile_start, one line per
+ * (stage, level, kernel class): "stage level class launches ms".  Stages are
+ * the factorisation and solve steps (for example "inverse", "products P,Q",
+ * "recompress D',E',F'", "solve forward"); level is the cyclic-reduction
+ * level (-1 outside the level loop).  Writes at most len bytes including
+ * the terminating NUL into buf (host memory, owned by the caller); *needed
+ * (may be NULL) receives the full length.  Waits for the recorded events. */
+acr_status acr_profile_report(char* buf, int64_t len, int64_t* needed);
+
 /* Release the library's cached (unused) device memory. */
 acr_status acr_trim_pool(void);
 

@@ -249,3 +249,20 @@ def acr_profile_read(cls) -> dict:
     _check(lib.acr_profile_read(idx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)))
     return {"class": KERNEL_CLASSES[idx], "launches": n.value, "total_ms": ms.value, "flops": fl.value,
             "bytes": by.value}
+
+
+def acr_profile_report() -> list:
+    """Per-stage timing of the launches recorded since acr_profile_start:
+    a list of (stage, level, kernel_class, launches, ms)."""
+    lib = load()
+    lib.acr_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.acr_profile_report.restype = ctypes.c_int
+    need = ctypes.c_int64(0)
+    _check(lib.acr_profile_report(None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(int(need.value) + 1)
+    _check(lib.acr_profile_report(buf, len(buf), ctypes.byref(need)))
+    rows = []
+    for line in buf.value.decode().splitlines():
+        *stage, level, cls, n, ms = line.split(" ")
+        rows.append((" ".join(stage), int(level), cls, int(n), float(ms)))
+    return rows

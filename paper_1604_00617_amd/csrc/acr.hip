@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -191,6 +192,7 @@ void Factor<T>::solve_fused(const double* B, double* Xout, int nrhs, hipStream_t
   F[0].resize((size_t)ny * blk);
   to_blocks<T>(st, s, ny, nrhs, B, (long long)nx * ny, F[0].get());
   for (int l = 0; l < nl; ++l) {
+    PhaseScope ph("solve forward", l);
     const Level<T>& Lv = lev[l];
     const int m = Lv.m, nodd = m / 2;
     G[l].resize((size_t)Lv.ne * blk);
@@ -221,6 +223,7 @@ void Factor<T>::solve_fused(const double* B, double* Xout, int nrhs, hipStream_t
     ghmv<T>(st, s, b, L, nrhs, jb, tm);
   }
   for (int l = nl - 1; l >= 0; --l) {
+    PhaseScope ph("solve backward", l);
     const Level<T>& Lv = lev[l];
     const int m = Lv.m, nodd = m / 2;
     U[l].resize((size_t)(m + 2) * blk);
@@ -415,11 +418,18 @@ std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_option
     lv.ne = m / 2 + 1;
     lv.diag = diag;
     const int nodd = m / 2;
+    PhaseScope lvl("level", (int)f->lev.size());
     // X_k = T(D_k^{-1}) for even k
     stage_check(st, D, status.get(), "D", (int)f->lev.size());
-    hinv<T>(st, lv.X, HV<T>{&D, 2, 0}, lv.nreal, status.get());
+    {
+      PhaseScope ph("inverse");
+      hinv<T>(st, lv.X, HV<T>{&D, 2, 0}, lv.nreal, status.get());
+    }
     stage_check(st, lv.X, status.get(), "inv", (int)f->lev.size());
-    recompress_multi<T>(st, {&lv.X}, eps, mr);
+    {
+      PhaseScope ph("recompress X");
+      recompress_multi<T>(st, {&lv.X}, eps, mr);
+    }
     stage_check(st, lv.X, status.get(), "X", (int)f->lev.size());
     HSet<T> P, Q;
     HSet<T> Dn, En, Fn;
@@ -430,8 +440,15 @@ std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_option
       cs[0].cols = e0.get(); cs[0].cmul = 2; cs[0].coff = 0;
       cs[1] = cs[0];
       cs[1].C = &Q; cs[1].cols = f0.get();
-      hscale_cols_multi<T>(st, cs);
-      recompress_multi<T>(st, {&P, &Q}, eps, mr);
+      {
+        PhaseScope ph("products P,Q");
+        hscale_cols_multi<T>(st, cs);
+      }
+      {
+        PhaseScope ph("recompress P,Q");
+        recompress_multi<T>(st, {&P, &Q}, eps, mr);
+      }
+      PhaseScope ph("products D',E',F'");
       // D'_j = D_i - diag(e_i) Q_j - diag(f_i) P_(j+1);  E'_j = -diag(e_i) P_j;  F'_j = -diag(f_i) Q_(j+1)
       std::vector<ScaleTerm<T>> terms(3);
       terms[0].h = HV<T>{&D, 2, 1};
@@ -452,8 +469,15 @@ std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_option
       pq[0].terms = {PTerm<T>{1.0, HV<T>{&lv.X, 1, 0}, HV<T>{&E, 2, 0}}};
       pq[1].C = &Q; pq[1].cnt_alloc = lv.ne; pq[1].nmat = lv.nreal;
       pq[1].terms = {PTerm<T>{1.0, HV<T>{&lv.X, 1, 0}, HV<T>{&F, 2, 0}}};
-      hprod_multi<T>(st, pq);
-      recompress_multi<T>(st, {&P, &Q}, eps, mr);
+      {
+        PhaseScope ph("products P,Q");
+        hprod_multi<T>(st, pq);
+      }
+      {
+        PhaseScope ph("recompress P,Q");
+        recompress_multi<T>(st, {&P, &Q}, eps, mr);
+      }
+      PhaseScope ph("products D',E',F'");
       std::vector<POut<T>> up(3);
       up[1].C = &En; up[1].cnt_alloc = nodd; up[1].nmat = nodd;
       up[1].terms = {PTerm<T>{-1.0, HV<T>{&E, 2, 1}, HV<T>{&P, 1, 0}}};
@@ -468,6 +492,7 @@ std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_option
         up[3].C = &FP; up[3].cnt_alloc = nodd; up[3].nmat = nodd;
         up[3].terms = {PTerm<T>{1.0, HV<T>{&F, 2, 1}, HV<T>{&P, 1, 1}}};
         hprod_multi<T>(st, up);
+        PhaseScope ph2("recompress EQ,FP");
         recompress_multi<T>(st, {&EQ, &FP}, ieps, 0);
         std::vector<ScaleTerm<T>> terms(3);
         terms[0].h = HV<T>{&D, 2, 1};
@@ -488,7 +513,10 @@ std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_option
     stage_check(st, P, status.get(), "P", (int)f->lev.size());
     stage_check(st, Q, status.get(), "Q", (int)f->lev.size());
     stage_check(st, Dn, status.get(), "D'-exact", (int)f->lev.size());
-    recompress_multi<T>(st, {&Dn, &En, &Fn}, eps, mr);
+    {
+      PhaseScope ph("recompress D',E',F'");
+      recompress_multi<T>(st, {&Dn, &En, &Fn}, eps, mr);
+    }
     stage_check(st, Dn, status.get(), "D'", (int)f->lev.size());
     stage_check(st, En, status.get(), "E'", (int)f->lev.size());
     stage_check(st, Fn, status.get(), "F'", (int)f->lev.size());
@@ -503,8 +531,11 @@ std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_option
     m = nodd;
     diag = false;
   }
-  hinv<T>(st, f->Xlast, HV<T>{&D, 1, 0}, 1, status.get());
-  recompress_multi<T>(st, {&f->Xlast}, eps, mr);
+  {
+    PhaseScope ph("last inverse", (int)f->lev.size());
+    hinv<T>(st, f->Xlast, HV<T>{&D, 1, 0}, 1, status.get());
+    recompress_multi<T>(st, {&f->Xlast}, eps, mr);
+  }
   int bad = 0;
   read_to_host(&bad, status.get(), sizeof(int), st);
   if (bad) fail(ACR_ERR_SINGULAR, "zero or non-finite pivot in a dense leaf or capacitance inverse");
@@ -712,6 +743,44 @@ acr_status acr_profile_read(int32_t cls, int64_t* launches, double* total_ms, do
     if (total_ms) *total_ms = ms;
     if (flops) *flops = fl;
     if (bytes) *bytes = by;
+  });
+}
+
+acr_status acr_profile_report(char* buf, int64_t len, int64_t* needed) {
+  return guard([&] {
+    Profiler& P = Profiler::get();
+    std::lock_guard<std::mutex> g(P.mu());
+    struct Agg { int64_t n = 0; double ms = 0; };
+    std::vector<std::pair<std::string, Agg>> rows;
+    std::map<std::string, size_t> index;
+    static const char* names[KC_COUNT] = {"gemm", "inverse", "qr", "applyq", "svd", "matvec", "copy", "other"};
+    for (auto& r : P.recs()) {
+      ACR_HIP(hipEventSynchronize(r.b));
+      float e = 0;
+      ACR_HIP(hipEventElapsedTime(&e, r.a, r.b));
+      const std::string key = std::string(r.phase ? r.phase : "-") + " " + std::to_string(r.level) + " " +
+                              names[r.cls];
+      auto it = index.find(key);
+      if (it == index.end()) {
+        index[key] = rows.size();
+        rows.push_back({key, Agg()});
+        it = index.find(key);
+      }
+      rows[it->second].second.n += 1;
+      rows[it->second].second.ms += e;
+    }
+    std::string out;
+    for (auto& kv : rows) {
+      char line[256];
+      std::snprintf(line, sizeof line, "%s %lld %.4f\n", kv.first.c_str(), (long long)kv.second.n, kv.second.ms);
+      out += line;
+    }
+    if (needed) *needed = (int64_t)out.size() + 1;
+    if (buf && len > 0) {
+      const size_t n = std::min<size_t>(out.size(), (size_t)len - 1);
+      std::memcpy(buf, out.data(), n);
+      buf[n] = 0;
+    }
   });
 }
 

@@ -154,9 +154,30 @@ class DBuf {
 // launch (counted from its shapes).
 enum KClass { KC_GEMM = 0, KC_INVERSE, KC_QR, KC_APPLYQ, KC_SVD, KC_MATVEC, KC_COPY, KC_OTHER, KC_COUNT };
 
+// Stage label of the launches recorded by this thread (set by PhaseScope;
+// static strings only) and the cyclic-reduction level it belongs to.
+struct Phase {
+  const char* name = "-";
+  int level = -1;
+  static Phase& cur() {
+    static thread_local Phase p;
+    return p;
+  }
+};
+struct PhaseScope {
+  Phase saved;
+  PhaseScope(const char* n, int level = -2) : saved(Phase::cur()) {
+    Phase::cur().name = n;
+    if (level != -2) Phase::cur().level = level;
+  }
+  ~PhaseScope() { Phase::cur() = saved; }
+};
+
 class Profiler {
  public:
   struct Rec {
+    const char* phase;
+    int level;
     int cls;
     hipEvent_t a, b;
     double flops, bytes;
@@ -202,12 +223,13 @@ struct ProfScope {
   bool act = false;
   Profiler::Rec r{};
   hipStream_t st = nullptr;
-  ProfScope(int cls, hipStream_t s, double flops, double bytes) {
+  ProfScope(int cls, hipStream_t s, double flops, double bytes, const Phase& ph = Phase::cur()) {
     Profiler& P = Profiler::get();
     if (!P.on(cls)) return;
     act = true;
     st = s;
     std::lock_guard<std::mutex> g(P.mu());
+    r.phase = ph.name; r.level = ph.level;
     r.cls = cls; r.flops = flops; r.bytes = bytes; r.dev_sweeps = nullptr; r.dev_flops = nullptr;
     r.a = P.event(); r.b = P.event();
     ACR_HIP(hipEventRecord(r.a, st));
@@ -347,8 +369,9 @@ inline void* DescArena::put(const void* data, size_t bytes, hipStream_t st) {
 template <typename... KArgs, typename... Args>
 void launch(hipStream_t st, int cls, double flops, double bytes, void (*kern)(KArgs...), dim3 grid,
             dim3 block, size_t shmem, Args... args) {
+  const Phase ph = Phase::cur();
   Queue::get().op(st, [=]() {
-    ProfScope ps(cls, st, flops, bytes);
+    ProfScope ps(cls, st, flops, bytes, ph);
     hipLaunchKernelGGL(kern, grid, block, shmem, st, args...);
     ACR_HIP(hipGetLastError());
   });

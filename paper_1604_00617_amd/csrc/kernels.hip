@@ -17,7 +17,8 @@ namespace acr {
 namespace {
 
 constexpr int WAVE = 64;
-constexpr size_t kMaxLds = 65536;   // dynamic + static LDS budget per workgroup
+constexpr size_t kMaxLds = 65536;        // LDS budget of a workgroup that shares its CU
+constexpr size_t kMaxLdsLarge = 163840;  // all the LDS a gfx950 workgroup may hold
 constexpr int kMvSlots = 512;        // reduced values per workgroup in the fused matvec
 constexpr int kMvCols = 512;         // row-block columns per workgroup in the fused matvec
 
@@ -1483,6 +1484,15 @@ int pick_tile(int M, int N) {
   return best;
 }
 
+// Let a kernel use more than 64 KB of dynamic LDS (once per kernel).
+void allow_large_lds(const void* kern) {
+  static std::vector<const void*> done;
+  if (std::find(done.begin(), done.end(), kern) != done.end()) return;
+  ACR_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(kMaxLdsLarge - 4096)));
+  done.push_back(kern);
+}
+
 template <typename J>
 const J* upload(const std::vector<J>& v, hipStream_t st) {
   return static_cast<const J*>(DescArena::get().put(v.data(), v.size() * sizeof(J), st));
@@ -1619,33 +1629,43 @@ void binverse(hipStream_t st, int n, int nprob, const Tin* A, long long sA, Tout
 
 template <typename T>
 void gqr(hipStream_t st, std::vector<QJob> jobs) {
+  // Panels that fit 64 KB of LDS share one launch; larger ones (up to the
+  // 160 KB a gfx950 workgroup may hold) get a launch of their own, so that
+  // the many small panels keep their occupancy; the rest work in global memory.
   std::vector<DBuf<T>> scratch;
-  std::vector<QJob> use;
-  size_t dyn = 0;
-  double fl = 0, by = 0;
-  long long b0 = 0;
+  std::vector<QJob> use[2];
+  size_t dyn[2] = {0, 0};
+  double fl[2] = {0, 0}, by[2] = {0, 0};
+  long long b0[2] = {0, 0};
   for (auto& J : jobs) {
     if (J.p <= 0 || J.k <= 0 || J.nmat <= 0 || J.ncl <= 0) continue;
     const size_t np = (size_t)J.nmat * J.ncl;
     const size_t panel = (size_t)J.p * J.k * sizeof(T), vb = (size_t)J.p * sizeof(T);
-    J.lds = panel + vb + 1024 <= kMaxLds;
-    if (J.lds) {
-      dyn = std::max(dyn, panel + vb);
+    int g = 0;
+    if (panel + vb + 1024 <= kMaxLds) {
+      J.lds = 1;
+    } else if (panel + vb + 4096 <= kMaxLdsLarge) {
+      J.lds = 1;
+      g = 1;
     } else {
+      J.lds = 0;
       scratch.emplace_back(np * J.p * J.k);
       J.ws = scratch.back().get();
-      dyn = std::max(dyn, vb);
     }
-    J.block0 = b0;
-    b0 += (long long)np;
+    dyn[g] = std::max(dyn[g], J.lds ? panel + vb : vb);
+    J.block0 = b0[g];
+    b0[g] += (long long)np;
     const double p = J.p, k = J.k, kr = std::min(J.p, J.k);
-    fl += np * (p >= k ? 2.0 * k * k * (p - k / 3.0) : 2.0 * p * p * (k - p / 3.0));
-    by += (double)sizeof(T) * np * (p * k + kr * k + (J.Vref ? p * kr : 0.0));
-    use.push_back(J);
+    fl[g] += np * (p >= k ? 2.0 * k * k * (p - k / 3.0) : 2.0 * p * p * (k - p / 3.0));
+    by[g] += (double)sizeof(T) * np * (p * k + kr * k + (J.Vref ? p * kr : 0.0));
+    use[g].push_back(J);
   }
-  if (use.empty()) return;
-  const QJob* dj = upload(use, st);
-  launch(st, KC_QR, fl, by, k_gqr<T>, dim3((unsigned)b0), dim3(256), dyn, dj, (int)use.size());
+  for (int g = 0; g < 2; ++g) {
+    if (use[g].empty()) continue;
+    if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_gqr<T>));
+    const QJob* dj = upload(use[g], st);
+    launch(st, KC_QR, fl[g], by[g], k_gqr<T>, dim3((unsigned)b0[g]), dim3(256), dyn[g], dj, (int)use[g].size());
+  }
 }
 
 template <typename T>
@@ -1720,8 +1740,9 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
   const SJob* dj = upload(use, st);
   const int nj = (int)use.size();
   const int nprob = (int)total;
+  const Phase ph = Phase::cur();
   Queue::get().op(st, [=]() {
-    ProfScope ps(KC_SVD, st, 0.0, by);
+    ProfScope ps(KC_SVD, st, 0.0, by, ph);
     ps.r.dev_flops = fl; ps.r.nprob = nprob;
     hipLaunchKernelGGL((k_grsvd<T>), dim3((unsigned)b0), dim3(256), 0, st, dj, nj);
     ACR_HIP(hipGetLastError());
