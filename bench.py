@@ -48,7 +48,8 @@ def parse():
 
 
 def run_steps(acr, torch, op, b, args, precision, steps, profile_cls=None):
-    """Run `steps` factor + refined-solve steps; returns (ms/step, iters, relres)."""
+    """Run `steps` factor + refined-solve steps; returns (ms/step, iters, relres, per-kernel
+    timing rows of the launches of class `profile_cls`, timed with HIP events)."""
     its = rel = None
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -64,49 +65,71 @@ def run_steps(acr, torch, op, b, args, precision, steps, profile_cls=None):
     torch.cuda.synchronize()
     prof = None
     if profile_cls is not None:
-        prof = acr.acr_profile_read(profile_cls)
+        prof = acr.acr_profile_report()["kernels"]
         acr.acr_profile_start([])
     return start.elapsed_time(stop) / steps, its, rel, prof
 
 
-def dominant_class(acr, torch, op, b, args, precision):
-    """One profiled step with every kernel class timed; the class with the most time."""
+def dominant_kernel(acr, torch, op, b, args, precision):
+    """One profiled step with every launch timed: the kernel with the most time,
+    its class, and the per-class totals."""
     acr.acr_profile_start(None)
     h = acr.acr_factor(op, args.leaf, args.eps, precision)
     acr.acr_solve_refined(h, op, b, tol=args.tol, maxit=50)
     acr.acr_destroy(h)
     torch.cuda.synchronize()
     table = {c: acr.acr_profile_read(c) for c in acr.KERNEL_CLASSES}
+    rep = acr.acr_profile_report()
     if args.phases:
-        rows = acr.acr_profile_report()
         by_stage = {}
-        for stage, level, cls, n, ms in rows:
-            by_stage.setdefault(stage, 0.0)
-            by_stage[stage] += ms
+        for stage, level, cls, n, ms, fl, by in rep["stages"]:
+            by_stage[stage] = by_stage.get(stage, 0.0) + ms
         for stage, ms in sorted(by_stage.items(), key=lambda kv: -kv[1]):
             print(f"[stage] {stage:24s} {ms:8.3f} ms", file=sys.stderr)
-        for stage, level, cls, n, ms in sorted(rows, key=lambda r: -r[4])[:40]:
+        for stage, level, cls, n, ms, fl, by in sorted(rep["stages"], key=lambda r: -r[4])[:40]:
             print(f"[stage-level] {stage:24s} L{level:<3d} {cls:8s} {n:5d} {ms:8.3f} ms", file=sys.stderr)
+        for name, cls, n, ms, fl, by in sorted(rep["kernels"], key=lambda r: -r[3]):
+            print(f"[kernel] {name:40s} {cls:8s} {n:5d} {ms:8.3f} ms", file=sys.stderr)
     acr.acr_profile_start([])
-    best = max(table.values(), key=lambda r: r["total_ms"])
-    return best["class"], table
+    name, cls = max(rep["kernels"], key=lambda r: r[3])[:2]
+    return name, cls, table
 
 
-def roofline(prof, precision):
-    launches = max(prof["launches"], 1)
-    avg_s = prof["total_ms"] / 1e3 / launches
-    cls = prof["class"]
+def traffic_per_launch(name):
+    """HBM bytes per launch of `name` from the committed rocprofv3 counter runs
+    (profiles/traffic.json), if they were taken on the current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_1604_00617_amd", "csrc", "kernels.hip")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if t.get("kernels_hip_sha256") != digest:
+        return None
+    k = t.get("kernels", {}).get(name)
+    return None if k is None else k["bytes_per_launch"]
+
+
+def roofline(row, precision):
+    name, cls, launches, ms, flops, nbytes = row
+    launches = max(launches, 1)
+    avg_s = ms / 1e3 / launches
+    traffic = traffic_per_launch(name)
+    common = {"kernel": name, "kernel_class": cls, "launches": launches, "avg_launch_us": avg_s * 1e6,
+              "traffic": traffic}
     if cls in ("gemm", "qr", "applyq", "svd", "inverse"):
-        # compute kernels on the vector ALUs (FP32 in the mixed form; inverses in FP64)
+        # vector-ALU kernels (FP32 in the mixed form; the small inverses work in FP64)
         peak = PEAKS["fp64_vector_TF"] if (precision == "fp64" or cls == "inverse") else PEAKS["fp32_vector_TF"]
-        ach = prof["flops"] / launches / avg_s / 1e12
-        return {"kernel_class": cls, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None, "launches": prof["launches"],
-                "avg_launch_us": avg_s * 1e6, "flops_per_launch": prof["flops"] / launches}
-    ach = prof["bytes"] / launches / avg_s / 1e9
-    return {"kernel_class": cls, "bound": "hbm", "achieved": ach, "peak": PEAKS["hbm_GBs"], "unit": "GB/s",
-            "frac": ach / PEAKS["hbm_GBs"], "traffic": None, "launches": prof["launches"],
-            "avg_launch_us": avg_s * 1e6, "bytes_per_launch": prof["bytes"] / launches}
+        ach = flops / launches / avg_s / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "flops_per_launch": flops / launches, **common}
+    ach = nbytes / launches / avg_s / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": PEAKS["hbm_GBs"], "unit": "GB/s",
+            "frac": ach / PEAKS["hbm_GBs"], "bytes_per_launch": nbytes / launches, **common}
 
 
 def cpu_baseline(args):
@@ -164,8 +187,9 @@ def main():
     # warm-up (also sizes the memory pool)
     for _ in range(args.warmup):
         run_steps(acr, torch, op, b, args, "mixed", 1)
-    cls, table = dominant_class(acr, torch, op, b, args, "mixed")
+    kname, cls, table = dominant_kernel(acr, torch, op, b, args, "mixed")
     ms, its, rel, prof = run_steps(acr, torch, op, b, args, "mixed", args.steps, profile_cls=cls)
+    krow = next(r for r in prof if r[0] == kname)
     h = acr.acr_factor(op, args.leaf, args.eps, "mixed")
     info = acr.acr_get_info(h)
     acr.acr_destroy(h)
@@ -191,7 +215,7 @@ def main():
         "relres": rel,
         "factor_max_rank": info["max_rank"],
         "factor_bytes": info["factor_bytes"],
-        "roofline": roofline(prof, "mixed"),
+        "roofline": roofline(krow, "mixed"),
         "kernel_classes_ms": {k: round(v["total_ms"], 3) for k, v in table.items()},
     }
     if not args.no_fp64:

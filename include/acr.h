@@ -177,13 +177,18 @@ acr_status acr_profile_start(uint32_t class_mask);
 acr_status acr_profile_read(int32_t cls, int64_t* launches, double* total_ms, double* flops,
                             double* bytes);
 
-/* Text report of the launches recorded since acr_profile_start, one line per
- * (stage, level, kernel class): "stage level class launches ms".  Stages are
- * the factorisation and solve steps (for example "inverse", "products P,Q",
- * "recompress D',E',F'", "solve forward"); level is the cyclic-reduction
- * level (-1 outside the level loop).  Writes at most len bytes including
- * the terminating NUL into buf (host memory, owned by the caller); *needed
- * (may be NULL) receives the full length.  Waits for the recorded events. */
+/* Text report of the launches recorded since acr_profile_start, one
+ * tab-separated line per group:
+ *   "stage  <stage> <level> <class> <launches> <ms> <flops> <bytes>"  per
+ *       (stage, level, kernel class); stages are the factorisation and solve
+ *       steps ("inverse", "products P,Q", "recompress D',E',F'", "solve
+ *       forward", ...), level the cyclic-reduction level (-1 outside the loop);
+ *   "kernel <name> <class> <launches> <ms> <flops> <bytes>"  per kernel, with
+ *       the name as kernel statistics of rocprofv3 print it ("k_gqr<float>").
+ * flops and bytes are the algorithmic counts of those launches.  Writes at
+ * most len bytes including the terminating NUL into buf (host memory, owned
+ * by the caller; may be NULL with len 0); *needed (may be NULL) receives the
+ * full length.  Waits for the recorded events. */
 acr_status acr_profile_report(char* buf, int64_t len, int64_t* needed);
 
 /* Release the library's cached (unused) device memory. */

@@ -251,9 +251,10 @@ def acr_profile_read(cls) -> dict:
             "bytes": by.value}
 
 
-def acr_profile_report() -> list:
-    """Per-stage timing of the launches recorded since acr_profile_start:
-    a list of (stage, level, kernel_class, launches, ms)."""
+def acr_profile_report() -> dict:
+    """Timing of the launches recorded since acr_profile_start:
+    {"stages": [(stage, level, class, launches, ms, flops, bytes)],
+     "kernels": [(name, class, launches, ms, flops, bytes)]}."""
     lib = load()
     lib.acr_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.acr_profile_report.restype = ctypes.c_int
@@ -261,8 +262,11 @@ def acr_profile_report() -> list:
     _check(lib.acr_profile_report(None, 0, ctypes.byref(need)))
     buf = ctypes.create_string_buffer(int(need.value) + 1)
     _check(lib.acr_profile_report(buf, len(buf), ctypes.byref(need)))
-    rows = []
+    out = {"stages": [], "kernels": []}
     for line in buf.value.decode().splitlines():
-        *stage, level, cls, n, ms = line.split(" ")
-        rows.append((" ".join(stage), int(level), cls, int(n), float(ms)))
-    return rows
+        f = line.split("\t")
+        if f[0] == "stage":
+            out["stages"].append((f[1], int(f[2]), f[3], int(f[4]), float(f[5]), float(f[6]), float(f[7])))
+        elif f[0] == "kernel":
+            out["kernels"].append((f[1], f[2], int(f[3]), float(f[4]), float(f[5]), float(f[6])))
+    return out

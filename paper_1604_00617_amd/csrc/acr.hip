@@ -750,29 +750,39 @@ acr_status acr_profile_report(char* buf, int64_t len, int64_t* needed) {
   return guard([&] {
     Profiler& P = Profiler::get();
     std::lock_guard<std::mutex> g(P.mu());
-    struct Agg { int64_t n = 0; double ms = 0; };
+    struct Agg { int cls = 0; int64_t n = 0; double ms = 0, flops = 0, bytes = 0; };
     std::vector<std::pair<std::string, Agg>> rows;
     std::map<std::string, size_t> index;
-    static const char* names[KC_COUNT] = {"gemm", "inverse", "qr", "applyq", "svd", "matvec", "copy", "other"};
-    for (auto& r : P.recs()) {
-      ACR_HIP(hipEventSynchronize(r.b));
-      float e = 0;
-      ACR_HIP(hipEventElapsedTime(&e, r.a, r.b));
-      const std::string key = std::string(r.phase ? r.phase : "-") + " " + std::to_string(r.level) + " " +
-                              names[r.cls];
+    auto add = [&](const std::string& key, int cls, float ms, double fl, double by) {
       auto it = index.find(key);
       if (it == index.end()) {
         index[key] = rows.size();
         rows.push_back({key, Agg()});
         it = index.find(key);
       }
-      rows[it->second].second.n += 1;
-      rows[it->second].second.ms += e;
+      Agg& a = rows[it->second].second;
+      a.cls = cls; a.n += 1; a.ms += ms; a.flops += fl; a.bytes += by;
+    };
+    static const char* names[KC_COUNT] = {"gemm", "inverse", "qr", "applyq", "svd", "matvec", "copy", "other"};
+    for (auto& r : P.recs()) {
+      ACR_HIP(hipEventSynchronize(r.b));
+      float e = 0;
+      ACR_HIP(hipEventElapsedTime(&e, r.a, r.b));
+      double fl = r.flops;
+      if (r.dev_flops) {
+        std::vector<double> f(r.nprob);
+        ACR_HIP(hipMemcpy(f.data(), r.dev_flops, r.nprob * sizeof(double), hipMemcpyDeviceToHost));
+        for (double v : f) fl += v;
+      }
+      add(std::string("stage\t") + (r.phase ? r.phase : "-") + "\t" + std::to_string(r.level) + "\t" +
+              names[r.cls], r.cls, e, fl, r.bytes);
+      add(std::string("kernel\t") + (r.kname ? r.kname : "-") + "\t" + names[r.cls], r.cls, e, fl, r.bytes);
     }
     std::string out;
     for (auto& kv : rows) {
-      char line[256];
-      std::snprintf(line, sizeof line, "%s %lld %.4f\n", kv.first.c_str(), (long long)kv.second.n, kv.second.ms);
+      char line[512];
+      std::snprintf(line, sizeof line, "%s\t%lld\t%.6f\t%.6e\t%.6e\n", kv.first.c_str(),
+                    (long long)kv.second.n, kv.second.ms, kv.second.flops, kv.second.bytes);
       out += line;
     }
     if (needed) *needed = (int64_t)out.size() + 1;

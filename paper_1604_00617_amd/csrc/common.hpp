@@ -177,6 +177,7 @@ class Profiler {
  public:
   struct Rec {
     const char* phase;
+    const char* kname;
     int level;
     int cls;
     hipEvent_t a, b;
@@ -223,13 +224,14 @@ struct ProfScope {
   bool act = false;
   Profiler::Rec r{};
   hipStream_t st = nullptr;
-  ProfScope(int cls, hipStream_t s, double flops, double bytes, const Phase& ph = Phase::cur()) {
+  ProfScope(int cls, hipStream_t s, double flops, double bytes, const Phase& ph = Phase::cur(),
+            const char* kname = "-") {
     Profiler& P = Profiler::get();
     if (!P.on(cls)) return;
     act = true;
     st = s;
     std::lock_guard<std::mutex> g(P.mu());
-    r.phase = ph.name; r.level = ph.level;
+    r.phase = ph.name; r.level = ph.level; r.kname = kname;
     r.cls = cls; r.flops = flops; r.bytes = bytes; r.dev_sweeps = nullptr; r.dev_flops = nullptr;
     r.a = P.event(); r.b = P.event();
     ACR_HIP(hipEventRecord(r.a, st));
@@ -367,11 +369,11 @@ inline void* DescArena::put(const void* data, size_t bytes, hipStream_t st) {
 
 // Record a kernel launch (timed by the profiler when its class is selected).
 template <typename... KArgs, typename... Args>
-void launch(hipStream_t st, int cls, double flops, double bytes, void (*kern)(KArgs...), dim3 grid,
-            dim3 block, size_t shmem, Args... args) {
+void launch(hipStream_t st, int cls, double flops, double bytes, const char* kname, void (*kern)(KArgs...),
+            dim3 grid, dim3 block, size_t shmem, Args... args) {
   const Phase ph = Phase::cur();
   Queue::get().op(st, [=]() {
-    ProfScope ps(cls, st, flops, bytes, ph);
+    ProfScope ps(cls, st, flops, bytes, ph, kname);
     hipLaunchKernelGGL(kern, grid, block, shmem, st, args...);
     ACR_HIP(hipGetLastError());
   });

@@ -8,8 +8,12 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <cctype>
 #include <cfloat>
 #include <cmath>
+#include <mutex>
+#include <set>
+#include <string>
 #include <vector>
 
 namespace acr {
@@ -19,8 +23,11 @@ namespace {
 constexpr int WAVE = 64;
 constexpr size_t kMaxLds = 65536;        // LDS budget of a workgroup that shares its CU
 constexpr size_t kMaxLdsLarge = 163840;  // all the LDS a gfx950 workgroup may hold
+constexpr size_t kMaxDynLarge = kMaxLdsLarge - 16384;   // dynamic part next to <= 16 KB static
 constexpr int kMvSlots = 512;        // reduced values per workgroup in the fused matvec
-constexpr int kMvCols = 512;         // row-block columns per workgroup in the fused matvec
+constexpr int kMvCols = 512;
+constexpr int kApplyRows = 8;        // Q application in registers: rows per lane (p <= 512)
+constexpr int kApplyCols = 8;        // and output columns per wave (t <= 32)         // row-block columns per workgroup in the fused matvec
 
 template <typename T>
 __device__ __forceinline__ const T* optr(const BOp& o, int m, int c) {
@@ -841,6 +848,124 @@ __global__ __launch_bounds__(256) void k_inverse_lds(int n, const Tin* A, long l
   if (tid == 0 && bad) status[0] = 1;
 }
 
+// ------------------------------------------------- QR, panel in registers
+// Householder QR of a p x k panel (p <= 64*QR_ROWS, k <= 4*QR_SLOTS) with the
+// panel in registers: wave w owns the columns q = w + 4u, lane l the rows
+// l + 64i.  Step j: the owner of column j forms the reflector (norm by a DPP
+// wave sum, v in FP64 as below) and publishes it in LDS (two buffers, so one
+// barrier per step suffices); every wave then applies it to its own columns
+// q > j.  Same outputs as k_gqr.
+template <typename T, int QR_ROWS, int QR_SLOTS>
+__global__ __launch_bounds__(256) void k_gqr_reg(const QJob* __restrict__ jobs, int njobs) {
+  __shared__ T vbuf[2][WAVE * QR_ROWS];
+  __shared__ T stau[2];
+  const QJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int prob = (int)(blockIdx.x - Jb.block0);
+  const int p = Jb.p, k = Jb.k, ncl = Jb.ncl;
+  const int m = prob / ncl, c = prob % ncl;
+  const BOp A = Jb.A;
+  const T* Ap = optr<T>(A, m, c);
+  const int kr = min(p, k);
+  T* const Vref = Jb.Vref ? static_cast<T*>(Jb.Vref) + (size_t)prob * p * kr : nullptr;
+  T* const taus = Jb.tau ? static_cast<T*>(Jb.tau) + (size_t)prob * kr : nullptr;
+  const int tid = threadIdx.x, lane = tid % WAVE;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
+  T w[QR_ROWS][QR_SLOTS];
+#pragma unroll
+  for (int i = 0; i < QR_ROWS; ++i)
+#pragma unroll
+    for (int u = 0; u < QR_SLOTS; ++u) {
+      const int r = lane + WAVE * i, q = wv + 4 * u;
+      w[i][u] = (r < p && q < k) ? Ap[r + (long long)q * A.ld] : T(0);
+    }
+  for (int j = 0; j < kr; ++j) {
+    const int buf = j & 1;
+    if (wv == (j & 3)) {
+      const int slot = j >> 2;
+      T x[QR_ROWS];
+#pragma unroll
+      for (int i = 0; i < QR_ROWS; ++i) x[i] = T(0);
+#pragma unroll
+      for (int u = 0; u < QR_SLOTS; ++u)
+        if (u == slot)
+#pragma unroll
+          for (int i = 0; i < QR_ROWS; ++i) x[i] = w[i][u];
+      double ss = 0.0, ap = 0.0;
+#pragma unroll
+      for (int i = 0; i < QR_ROWS; ++i) {
+        const int r = lane + WAVE * i;
+        const double xv = (double)x[i];
+        if (r > j && r < p) ss += xv * xv;
+        if (r == j) ap = xv;
+      }
+      const double tail = wave_sum(ss);
+      const double alpha = wave_sum(ap);
+      const double nrm = sqrt(alpha * alpha + tail);
+      const double beta = alpha >= 0.0 ? -nrm : nrm;
+      const bool refl = !(tail == 0.0 || nrm == 0.0);
+      const T tau = refl ? (T)((beta - alpha) / beta) : T(0);
+      // v = x / v0 formed in FP64: |v_r| <= 1 even for columns far below the
+      // FP32 normal range, where an FP32 reciprocal of v0 would overflow
+      const double v0 = alpha - beta;
+#pragma unroll
+      for (int i = 0; i < QR_ROWS; ++i) {
+        const int r = lane + WAVE * i;
+        T vv = T(0);
+        if (refl && r >= j && r < p) vv = (r == j) ? T(1) : (T)((double)x[i] / v0);
+        if (r < p) {
+          vbuf[buf][r] = vv;
+          if (Vref) Vref[(size_t)j * p + r] = vv;
+        }
+      }
+      if (lane == 0) {
+        stau[buf] = tau;
+        if (taus) taus[j] = tau;
+      }
+      const T diag = refl ? (T)beta : (T)alpha;
+#pragma unroll
+      for (int u = 0; u < QR_SLOTS; ++u)
+        if (u == slot)
+#pragma unroll
+          for (int i = 0; i < QR_ROWS; ++i) {
+            const int r = lane + WAVE * i;
+            if (r == j) w[i][u] = diag;
+            else if (r > j) w[i][u] = T(0);
+          }
+    }
+    __syncthreads();
+    const T tau = stau[buf];
+    if (tau != T(0)) {
+      T v[QR_ROWS];
+#pragma unroll
+      for (int i = 0; i < QR_ROWS; ++i) {
+        const int r = lane + WAVE * i;
+        v[i] = r < p ? vbuf[buf][r] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < QR_SLOTS; ++u) {
+        const int q = wv + 4 * u;
+        if (q > j && q < k) {
+          T d = T(0);
+#pragma unroll
+          for (int i = 0; i < QR_ROWS; ++i) d = fma(v[i], w[i][u], d);
+          d = wave_sum(d) * tau;
+#pragma unroll
+          for (int i = 0; i < QR_ROWS; ++i) w[i][u] = fma(-d, v[i], w[i][u]);
+        }
+      }
+    }
+  }
+  // R = upper trapezoid of the first kr rows
+  T* Rp = static_cast<T*>(Jb.R) + (size_t)prob * kr * k;
+#pragma unroll
+  for (int i = 0; i < QR_ROWS; ++i)
+#pragma unroll
+    for (int u = 0; u < QR_SLOTS; ++u) {
+      const int r = lane + WAVE * i, q = wv + 4 * u;
+      if (r < kr && q < k) Rp[r + (size_t)q * kr] = (r <= q) ? w[i][u] : T(0);
+    }
+}
+
 // ------------------------------------------------------------ QR (R only)
 // Householder QR of a p x k panel; one workgroup of 256 threads per problem.
 // The panel is copied to LDS when it fits, else to a global scratch copy.
@@ -945,6 +1070,55 @@ __global__ __launch_bounds__(256) void k_gapply_q(const AJob* __restrict__ jobs,
   const T* vr = static_cast<const T*>(Jb.Vref) + (size_t)prob * p * c;
   const T* ta = static_cast<const T*>(Jb.tau) + (size_t)prob * c;
   const int tid = threadIdx.x, wv = tid / WAVE, lane = tid % WAVE;
+  if (Jb.lds) {
+    // Reflectors (and their taus) in LDS; wave w owns the output columns
+    // q = w + 4u and keeps them in registers, lane l the rows l + 64 i, so the
+    // reflector steps need no barrier and no LDS stores.
+    constexpr int RMAX = kApplyRows, CMAX = kApplyCols;
+    extern __shared__ unsigned char smem_raw[];
+    T* vs = reinterpret_cast<T*>(smem_raw);
+    T* ts = vs + (size_t)p * c;
+    for (int e = tid; e < p * c; e += 256) vs[e] = vr[e];
+    for (int e = tid; e < c; e += 256) ts[e] = ta[e];
+    T yr[RMAX][CMAX];
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+#pragma unroll
+      for (int u = 0; u < CMAX; ++u) {
+        const int r = lane + WAVE * i, q = wv + 4 * u;
+        yr[i][u] = (r < c && q < t) ? z[r + (size_t)q * c] : T(0);
+      }
+    __syncthreads();
+    for (int j = c - 1; j >= 0; --j) {
+      const T tau = ts[j];
+      if (tau == T(0)) continue;
+      T v[RMAX];
+#pragma unroll
+      for (int i = 0; i < RMAX; ++i) {
+        const int r = lane + WAVE * i;
+        v[i] = r < p ? vs[(size_t)j * p + r] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < CMAX; ++u) {
+        if (wv + 4 * u < t) {
+          T d = T(0);
+#pragma unroll
+          for (int i = 0; i < RMAX; ++i) d = fma(v[i], yr[i][u], d);
+          d = wave_sum(d) * tau;
+#pragma unroll
+          for (int i = 0; i < RMAX; ++i) yr[i][u] = fma(-d, v[i], yr[i][u]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+#pragma unroll
+      for (int u = 0; u < CMAX; ++u) {
+        const int r = lane + WAVE * i, q = wv + 4 * u;
+        if (r < p && q < t) y[r + (long long)q * Y.ld] = yr[i][u];
+      }
+    return;
+  }
   for (int e = tid; e < p * t; e += 256) {
     const int r = e % p, q = e / p;
     y[r + (long long)q * Y.ld] = r < c ? z[r + (size_t)q * c] : T(0);
@@ -1000,7 +1174,18 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
   int* const rank = Jb.rank;
   double* const flops = Jb.flops;
   const int tid = threadIdx.x, wv = tid / WAVE, lane = tid % WAVE;
+  extern __shared__ unsigned char smem_raw[];
   T* W = static_cast<T*>(Jb.K) + (size_t)prob * c * c;
+  T* X = Xall + (size_t)prob * c * c;
+  T* J = Jall + (size_t)prob * c * c;
+  if (Jb.lds) {   // the core and both work matrices in LDS
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    for (int e = tid; e < c * c; e += 256) sm[e] = W[e];
+    W = sm;
+    X = sm + (size_t)c * c;
+    J = sm + 2 * (size_t)c * c;
+    __syncthreads();
+  }
   double fl = 0.0;
   int tp = 0;
   for (int j = 0; j < c; ++j) {
@@ -1077,8 +1262,6 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
     fl += 6.0 * (double)(c - j) * (c - j);
   }
   // X = R_top^T (c x tp), J_X = I (tp x tp), both with leading dimension c
-  T* X = Xall + (size_t)prob * c * c;
-  T* J = Jall + (size_t)prob * c * c;
   for (int e = tid; e < c * tp; e += 256) {
     const int q = e % c, i = e / c;
     X[q + (size_t)i * c] = q >= i ? W[i + (size_t)q * c] : T(0);
@@ -1488,10 +1671,39 @@ int pick_tile(int M, int N) {
 void allow_large_lds(const void* kern) {
   static std::vector<const void*> done;
   if (std::find(done.begin(), done.end(), kern) != done.end()) return;
-  ACR_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(kMaxLdsLarge - 4096)));
+  ACR_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLarge));
   done.push_back(kern);
 }
+
+// Kernel names as the profiler reports them ("k_gqr<float>"): the template
+// arguments spelled in the source are replaced by the instantiated types.
+template <typename X> const char* type_name();
+template <> const char* type_name<float>() { return "float"; }
+template <> const char* type_name<double>() { return "double"; }
+
+const char* kernel_name(const char* src, const char* t, const char* tin, const char* tout) {
+  static std::mutex mu;
+  static std::set<std::string> pool;
+  std::string out;
+  const std::string in(src);
+  for (size_t i = 0; i < in.size();) {
+    if (std::isalpha((unsigned char)in[i]) || in[i] == '_') {
+      size_t j = i;
+      while (j < in.size() && (std::isalnum((unsigned char)in[j]) || in[j] == '_')) ++j;
+      const std::string w = in.substr(i, j - i);
+      out += w == "T" ? t : w == "Tin" ? tin : w == "Tout" ? tout : w;
+      i = j;
+    } else {
+      out += in[i++];
+    }
+  }
+  std::lock_guard<std::mutex> g(mu);
+  return pool.insert(out).first->c_str();
+}
+
+#define KNAME_T(...) kernel_name(#__VA_ARGS__, type_name<T>(), "", "")
+#define KNAME_IO(...) kernel_name(#__VA_ARGS__, "", type_name<Tin>(), type_name<Tout>())
+#define KNAME0(...) kernel_name(#__VA_ARGS__, "", "", "")
 
 template <typename J>
 const J* upload(const std::vector<J>& v, hipStream_t st) {
@@ -1566,20 +1778,20 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
     const GJob* dj = reinterpret_cast<const GJob*>(dev + off[kd]);
     const int nj = (int)by[kd].size();
     const dim3 grid((unsigned)nblk[kd]);
-    auto go = [&](auto kern, int threads) {
-      launch(st, KC_GEMM, fl[kd], bytes[kd], kern, grid, dim3(threads), 0, dj, nj, dsegs);
+    auto go = [&](const char* name, auto kern, int threads) {
+      launch(st, KC_GEMM, fl[kd], bytes[kd], name, kern, grid, dim3(threads), 0, dj, nj, dsegs);
     };
     switch (kd) {
-      case 0: go(k_ggemm<T, 64, 64, 16, 4, 4>, 256); break;
-      case 1: go(k_ggemm<T, 64, 16, 16, 4, 4>, 64); break;
-      case 2: go(k_ggemm<T, 16, 64, 16, 4, 4>, 64); break;
-      case 3: go(k_ggemm<T, 32, 32, 16, 4, 4>, 64); break;
-      case 4: go(k_ggemm<T, 16, 16, 16, 2, 2>, 64); break;
-      case 5: go(k_gemm_dot<T>, 256); break;
-      case 6: go(k_gemm_rows<T, 16>, 256); break;
-      case 7: go(k_gemm_rows<T, sizeof(T) == 4 ? 32 : 16>, 256); break;
-      case 8: go(k_gemm_rows<T, 4>, 256); break;
-      default: go(k_gemm_small<T>, 256); break;
+      case 0: go(KNAME_T(k_ggemm<T, 64, 64, 16, 4, 4>), k_ggemm<T, 64, 64, 16, 4, 4>, 256); break;
+      case 1: go(KNAME_T(k_ggemm<T, 64, 16, 16, 4, 4>), k_ggemm<T, 64, 16, 16, 4, 4>, 64); break;
+      case 2: go(KNAME_T(k_ggemm<T, 16, 64, 16, 4, 4>), k_ggemm<T, 16, 64, 16, 4, 4>, 64); break;
+      case 3: go(KNAME_T(k_ggemm<T, 32, 32, 16, 4, 4>), k_ggemm<T, 32, 32, 16, 4, 4>, 64); break;
+      case 4: go(KNAME_T(k_ggemm<T, 16, 16, 16, 2, 2>), k_ggemm<T, 16, 16, 16, 2, 2>, 64); break;
+      case 5: go(KNAME_T(k_gemm_dot<T>), k_gemm_dot<T>, 256); break;
+      case 6: go(KNAME_T(k_gemm_rows<T, 16>), k_gemm_rows<T, 16>, 256); break;
+      case 7: go(sizeof(T) == 4 ? KNAME_T(k_gemm_rows<T, 32>) : KNAME_T(k_gemm_rows<T, 16>), k_gemm_rows<T, sizeof(T) == 4 ? 32 : 16>, 256); break;
+      case 8: go(KNAME_T(k_gemm_rows<T, 4>), k_gemm_rows<T, 4>, 256); break;
+      default: go(KNAME_T(k_gemm_small<T>), k_gemm_small<T>, 256); break;
     }
   }
 }
@@ -1603,19 +1815,19 @@ void binverse(hipStream_t st, int n, int nprob, const Tin* A, long long sA, Tout
   if (n <= 0 || nprob <= 0) return;
   const double fl = 2.0 * n * n * n * nprob, by = 2.0 * n * n * nprob * sizeof(Tin);
   if (n <= 64) {   // one row per lane, 64/N matrices per wave, four waves per workgroup
-    auto go = [&](auto kern, int Nt) {
+    auto go = [&](const char* name, auto kern, int Nt) {
       const long long per = 4LL * (WAVE / Nt);
-      launch(st, KC_INVERSE, fl, by, kern, dim3((unsigned)((nprob + per - 1) / per)), dim3(256), 0, n, nprob,
+      launch(st, KC_INVERSE, fl, by, name, kern, dim3((unsigned)((nprob + per - 1) / per)), dim3(256), 0, n, nprob,
              A, sA, X, sX, status);
     };
-    if (n <= 8) go(k_inverse_wave<Tin, Tout, 8>, 8);
-    else if (n <= 16) go(k_inverse_wave<Tin, Tout, 16>, 16);
-    else if (n <= 32) go(k_inverse_wave<Tin, Tout, 32>, 32);
-    else go(k_inverse_wave<Tin, Tout, 64>, 64);
+    if (n <= 8) go(KNAME_IO(k_inverse_wave<Tin, Tout, 8>), k_inverse_wave<Tin, Tout, 8>, 8);
+    else if (n <= 16) go(KNAME_IO(k_inverse_wave<Tin, Tout, 16>), k_inverse_wave<Tin, Tout, 16>, 16);
+    else if (n <= 32) go(KNAME_IO(k_inverse_wave<Tin, Tout, 32>), k_inverse_wave<Tin, Tout, 32>, 32);
+    else go(KNAME_IO(k_inverse_wave<Tin, Tout, 64>), k_inverse_wave<Tin, Tout, 64>, 64);
     return;
   }
   if (n <= 88) {   // in place: n*n doubles of LDS (+1.6 KB static) within 64 KB
-    launch(st, KC_INVERSE, fl, by, k_inverse_lds<Tin, Tout>, dim3(nprob), dim3(256),
+    launch(st, KC_INVERSE, fl, by, KNAME_IO(k_inverse_lds<Tin, Tout>), k_inverse_lds<Tin, Tout>, dim3(nprob), dim3(256),
            (size_t)n * n * sizeof(double), n, A, sA, X, sX, status);
     return;
   }
@@ -1623,7 +1835,7 @@ void binverse(hipStream_t st, int n, int nprob, const Tin* A, long long sA, Tout
   const bool use_lds = lds + 2048 <= kMaxLds;
   DBuf<double> ws;
   if (!use_lds || n > 128) ws.resize((size_t)nprob * n * (2 * n + 1));
-  launch(st, KC_INVERSE, fl, by, k_inverse<Tin, Tout>, dim3(nprob), dim3(256), use_lds ? lds : 0, n, A, sA,
+  launch(st, KC_INVERSE, fl, by, KNAME_IO(k_inverse<Tin, Tout>), k_inverse<Tin, Tout>, dim3(nprob), dim3(256), use_lds ? lds : 0, n, A, sA,
          X, sX, ws.get(), use_lds ? 1 : 0, status);
 }
 
@@ -1633,18 +1845,23 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
   // 160 KB a gfx950 workgroup may hold) get a launch of their own, so that
   // the many small panels keep their occupancy; the rest work in global memory.
   std::vector<DBuf<T>> scratch;
-  std::vector<QJob> use[2];
-  size_t dyn[2] = {0, 0};
-  double fl[2] = {0, 0}, by[2] = {0, 0};
-  long long b0[2] = {0, 0};
+  std::vector<QJob> use[3];
+  size_t dyn[3] = {0, 0, 0};
+  double fl[3] = {0, 0, 0}, by[3] = {0, 0, 0};
+  long long b0[3] = {0, 0, 0};
   for (auto& J : jobs) {
     if (J.p <= 0 || J.k <= 0 || J.nmat <= 0 || J.ncl <= 0) continue;
     const size_t np = (size_t)J.nmat * J.ncl;
     const size_t panel = (size_t)J.p * J.k * sizeof(T), vb = (size_t)J.p * sizeof(T);
     int g = 0;
-    if (panel + vb + 1024 <= kMaxLds) {
+    const int rows = (J.p + WAVE - 1) / WAVE, slots = (J.k + 3) / 4;
+    if (rows <= 8 && slots <= 16 && rows * slots * sizeof(T) <= 64 * 4) {   // panel in registers
+      g = 2;
+      J.lds = 0;
+      J.pad = (rows <= 1 ? 0 : rows <= 2 ? 1 : rows <= 4 ? 2 : 3) * 3 + (slots <= 4 ? 0 : slots <= 8 ? 1 : 2);
+    } else if (panel + vb + 1024 <= kMaxLds) {
       J.lds = 1;
-    } else if (panel + vb + 4096 <= kMaxLdsLarge) {
+    } else if (panel + vb <= kMaxDynLarge) {
       J.lds = 1;
       g = 1;
     } else {
@@ -1652,7 +1869,7 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
       scratch.emplace_back(np * J.p * J.k);
       J.ws = scratch.back().get();
     }
-    dyn[g] = std::max(dyn[g], J.lds ? panel + vb : vb);
+    if (g < 2) dyn[g] = std::max(dyn[g], J.lds ? panel + vb : vb);
     J.block0 = b0[g];
     b0[g] += (long long)np;
     const double p = J.p, k = J.k, kr = std::min(J.p, J.k);
@@ -1660,11 +1877,48 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
     by[g] += (double)sizeof(T) * np * (p * k + kr * k + (J.Vref ? p * kr : 0.0));
     use[g].push_back(J);
   }
+  if (!use[2].empty()) {
+    // one launch per register shape (rows per lane, columns per wave / 4)
+    std::vector<QJob> by_shape[12];
+    for (auto& J : use[2]) by_shape[J.pad].push_back(J);
+    for (int sh = 0; sh < 12; ++sh) {
+      auto& v = by_shape[sh];
+      if (v.empty()) continue;
+      long long nb = 0;
+      double f = 0, b = 0;
+      for (auto& J : v) {
+        J.block0 = nb;
+        const double np = (double)J.nmat * J.ncl, p = J.p, k = J.k;
+        nb += (long long)np;
+        f += np * (p >= k ? 2.0 * k * k * (p - k / 3.0) : 2.0 * p * p * (k - p / 3.0));
+        b += (double)sizeof(T) * np * (p * k + std::min(p, k) * k + (J.Vref ? p * std::min(p, k) : 0.0));
+      }
+      const QJob* dj = upload(v, st);
+      const int nj = (int)v.size();
+      auto go = [&](const char* name, auto kern) {
+        launch(st, KC_QR, f, b, name, kern, dim3((unsigned)nb), dim3(256), 0, dj, nj);
+      };
+      switch (sh) {
+        case 0: go(KNAME_T(k_gqr_reg<T, 1, 4>), k_gqr_reg<T, 1, 4>); break;
+        case 1: go(KNAME_T(k_gqr_reg<T, 1, 8>), k_gqr_reg<T, 1, 8>); break;
+        case 2: go(KNAME_T(k_gqr_reg<T, 1, 16>), k_gqr_reg<T, 1, 16>); break;
+        case 3: go(KNAME_T(k_gqr_reg<T, 2, 4>), k_gqr_reg<T, 2, 4>); break;
+        case 4: go(KNAME_T(k_gqr_reg<T, 2, 8>), k_gqr_reg<T, 2, 8>); break;
+        case 5: go(KNAME_T(k_gqr_reg<T, 2, 16>), k_gqr_reg<T, 2, 16>); break;
+        case 6: go(KNAME_T(k_gqr_reg<T, 4, 4>), k_gqr_reg<T, 4, 4>); break;
+        case 7: go(KNAME_T(k_gqr_reg<T, 4, 8>), k_gqr_reg<T, 4, 8>); break;
+        case 8: go(KNAME_T(k_gqr_reg<T, 4, 16>), k_gqr_reg<T, 4, 16>); break;
+        case 9: go(KNAME_T(k_gqr_reg<T, 8, 4>), k_gqr_reg<T, 8, 4>); break;
+        case 10: go(KNAME_T(k_gqr_reg<T, 8, 8>), k_gqr_reg<T, 8, 8>); break;
+        default: go(KNAME_T(k_gqr_reg<T, 8, 16>), k_gqr_reg<T, 8, 16>); break;
+      }
+    }
+  }
   for (int g = 0; g < 2; ++g) {
     if (use[g].empty()) continue;
     if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_gqr<T>));
     const QJob* dj = upload(use[g], st);
-    launch(st, KC_QR, fl[g], by[g], k_gqr<T>, dim3((unsigned)b0[g]), dim3(256), dyn[g], dj, (int)use[g].size());
+    launch(st, KC_QR, fl[g], by[g], KNAME_T(k_gqr<T>), k_gqr<T>, dim3((unsigned)b0[g]), dim3(256), dyn[g], dj, (int)use[g].size());
   }
 }
 
@@ -1678,21 +1932,36 @@ void bqr_r(hipStream_t st, int p, int k, int nmat, int ncl, const BOp& A, T* R, 
 
 template <typename T>
 void gapply_q(hipStream_t st, std::vector<AJob> jobs) {
-  std::vector<AJob> use;
-  double fl = 0, by = 0;
-  long long b0 = 0;
+  // reflectors + output tile in LDS: up to 64 KB in one launch, up to the
+  // full gfx950 workgroup LDS in a second one, otherwise in global memory
+  std::vector<AJob> use[2];
+  size_t dyn[2] = {0, 0};
+  double fl[2] = {0, 0}, by[2] = {0, 0};
+  long long b0[2] = {0, 0};
   for (auto& J : jobs) {
     if (J.p <= 0 || J.t <= 0 || J.nmat <= 0 || J.ncl <= 0) continue;
-    J.block0 = b0;
+    const size_t need = ((size_t)J.p * J.c + J.c) * sizeof(T);
+    int g = 0;
+    J.lds = J.p <= WAVE * kApplyRows && J.t <= 4 * kApplyCols;
+    if (J.lds && need + 2048 > kMaxLds) {
+      if (need <= kMaxDynLarge) g = 1;
+      else J.lds = 0;
+    }
+    if (J.lds) dyn[g] = std::max(dyn[g], need);
+    J.block0 = b0[g];
     const double np = (double)J.nmat * J.ncl;
-    b0 += (long long)np;
-    fl += 4.0 * np * J.t * ((double)J.p * J.c - 0.5 * J.c * J.c);
-    by += (double)sizeof(T) * np * ((double)J.p * J.c + (double)J.c * J.t + (double)J.p * J.t);
-    use.push_back(J);
+    b0[g] += (long long)np;
+    fl[g] += 4.0 * np * J.t * ((double)J.p * J.c - 0.5 * J.c * J.c);
+    by[g] += (double)sizeof(T) * np * ((double)J.p * J.c + (double)J.c * J.t + (double)J.p * J.t);
+    use[g].push_back(J);
   }
-  if (use.empty()) return;
-  const AJob* dj = upload(use, st);
-  launch(st, KC_APPLYQ, fl, by, k_gapply_q<T>, dim3((unsigned)b0), dim3(256), 0, dj, (int)use.size());
+  for (int g = 0; g < 2; ++g) {
+    if (use[g].empty()) continue;
+    if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_gapply_q<T>));
+    const AJob* dj = upload(use[g], st);
+    launch(st, KC_APPLYQ, fl[g], by[g], KNAME_T(k_gapply_q<T>), k_gapply_q<T>, dim3((unsigned)b0[g]), dim3(256),
+           dyn[g], dj, (int)use[g].size());
+  }
 }
 
 template <typename T>
@@ -1707,13 +1976,18 @@ void bapply_q(hipStream_t st, int p, int c, int t, int nmat, int ncl, const T* V
 
 template <typename T>
 void grsvd(hipStream_t st, std::vector<SJob> jobs) {
+  // The core and its two work matrices in LDS: launch 0 holds the jobs that
+  // fit next to the kernel's static arrays in 64 KB, launch 1 those that fit
+  // the full gfx950 workgroup LDS; larger cores work in global scratch.
+  constexpr size_t kStatic = 16384;
   std::vector<DBuf<T>> scratch;
-  std::vector<SJob> use;
+  std::vector<SJob> use[2];
   Profiler& P = Profiler::get();
   const bool prof = P.on(KC_SVD);
   double* fl = nullptr;
-  long long b0 = 0, total = 0;
-  double by = 0;
+  long long b0[2] = {0, 0}, total = 0;
+  size_t dyn[2] = {0, 0};
+  double by[2] = {0, 0};
   for (auto& J : jobs) {
     if (J.c <= 0 || J.nprob <= 0) continue;
     if (J.c > 512) fail(ACR_ERR_INVALID_ARG, "rank-revealing SVD core larger than 512");
@@ -1725,28 +1999,48 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     P.owned_d().emplace_back((size_t)total);
     fl = P.owned_d().back().get();
   }
+  long long done = 0;
   for (auto& J : jobs) {
     if (J.c <= 0 || J.nprob <= 0) continue;
-    scratch.emplace_back((size_t)J.nprob * J.c * J.c);
-    J.X = scratch.back().get();
-    scratch.emplace_back((size_t)J.nprob * J.c * J.c);
-    J.J = scratch.back().get();
-    J.flops = fl ? fl + b0 : nullptr;
-    J.block0 = b0;
-    b0 += J.nprob;
-    by += 4.0 * (double)J.c * J.c * J.nprob * sizeof(T);
-    use.push_back(J);
+    const size_t need = 3 * (size_t)J.c * J.c * sizeof(T);
+    int g = 0;
+    J.lds = 1;
+    if (need + kStatic > kMaxLds) {
+      if (need <= kMaxDynLarge) g = 1;
+      else J.lds = 0;
+    }
+    if (J.lds) {
+      dyn[g] = std::max(dyn[g], need);
+    } else {
+      scratch.emplace_back((size_t)J.nprob * J.c * J.c);
+      J.X = scratch.back().get();
+      scratch.emplace_back((size_t)J.nprob * J.c * J.c);
+      J.J = scratch.back().get();
+    }
+    J.flops = fl ? fl + done : nullptr;
+    done += J.nprob;
+    J.block0 = b0[g];
+    b0[g] += J.nprob;
+    by[g] += 4.0 * (double)J.c * J.c * J.nprob * sizeof(T);
+    use[g].push_back(J);
   }
-  const SJob* dj = upload(use, st);
-  const int nj = (int)use.size();
-  const int nprob = (int)total;
-  const Phase ph = Phase::cur();
-  Queue::get().op(st, [=]() {
-    ProfScope ps(KC_SVD, st, 0.0, by, ph);
-    ps.r.dev_flops = fl; ps.r.nprob = nprob;
-    hipLaunchKernelGGL((k_grsvd<T>), dim3((unsigned)b0), dim3(256), 0, st, dj, nj);
-    ACR_HIP(hipGetLastError());
-  });
+  for (int g = 0; g < 2; ++g) {
+    if (use[g].empty()) continue;
+    if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_grsvd<T>));
+    const SJob* dj = upload(use[g], st);
+    const int nj = (int)use[g].size();
+    const long long nb = b0[g];
+    const size_t shm = dyn[g];
+    launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd<T>), k_grsvd<T>, dim3((unsigned)nb), dim3(256), shm, dj, nj);
+  }
+  if (fl) {   // device-counted flops of every problem, credited to the last launch
+    const int n = (int)total;
+    Queue::get().op(st, [=]() {
+      std::lock_guard<std::mutex> g(Profiler::get().mu());
+      auto& recs = Profiler::get().recs();
+      if (!recs.empty() && recs.back().cls == KC_SVD) { recs.back().dev_flops = fl; recs.back().nprob = n; }
+    });
+  }
 }
 
 template <typename T>
@@ -1769,7 +2063,7 @@ void gtrunc(hipStream_t st, std::vector<TJob> jobs) {
   }
   if (use.empty()) return;
   const TJob* dj = upload(use, st);
-  launch(st, KC_COPY, 0.0, 0.0, k_gtrunc<T>, dim3((unsigned)b0), dim3(256), 0, dj, (int)use.size());
+  launch(st, KC_COPY, 0.0, 0.0, KNAME_T(k_gtrunc<T>), k_gtrunc<T>, dim3((unsigned)b0), dim3(256), 0, dj, (int)use.size());
 }
 
 template <typename T>
@@ -1782,7 +2076,7 @@ void btrunc_coef(hipStream_t st, int c, int kout, int nprob, const T* J, const i
 void gmax(hipStream_t st, const std::vector<MJob>& jobs) {
   if (jobs.empty()) return;
   const MJob* dj = upload(jobs, st);
-  launch(st, KC_OTHER, 0.0, 0.0, k_gmax, dim3((unsigned)jobs.size()), dim3(256), 0, dj);
+  launch(st, KC_OTHER, 0.0, 0.0, KNAME0(k_gmax), k_gmax, dim3((unsigned)jobs.size()), dim3(256), 0, dj);
 }
 
 void bmax_int(hipStream_t st, const int* rank, int n, int* out) {
@@ -1808,7 +2102,7 @@ void gcopy(hipStream_t st, std::vector<CJob> jobs) {
   if (use.empty()) return;
   if (b0 > 0x7fffffffLL) fail(ACR_ERR_INVALID_ARG, "grouped copy grid too large");
   const CJob* dj = upload(use, st);
-  launch(st, KC_COPY, 0.0, by, k_gcopy<T>, dim3((unsigned)b0), dim3(256), 0, dj, (int)use.size());
+  launch(st, KC_COPY, 0.0, by, KNAME_T(k_gcopy<T>), k_gcopy<T>, dim3((unsigned)b0), dim3(256), 0, dj, (int)use.size());
 }
 
 template <typename T>
@@ -1856,14 +2150,14 @@ void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs
   const MVTerm* dt = terms.empty() ? nullptr : upload(terms, st);
   const dim3 grid((unsigned)(8 * ((b0 + 7) / 8)));
   const int nj = (int)use.size();
-  auto go = [&](auto kern) {
-    launch(st, KC_MATVEC, fl, by, kern, grid, dim3(256), 0, dj, nj, dt, s, b, L, nrhs, b0);
+  auto go = [&](const char* name, auto kern) {
+    launch(st, KC_MATVEC, fl, by, name, kern, grid, dim3(256), 0, dj, nj, dt, s, b, L, nrhs, b0);
   };
   switch (NR) {
-    case 1: go(k_hmv<T, 1>); break;
-    case 2: go(k_hmv<T, 2>); break;
-    case 4: go(k_hmv<T, 4>); break;
-    default: go(k_hmv<T, 8>); break;
+    case 1: go(KNAME_T(k_hmv<T, 1>), k_hmv<T, 1>); break;
+    case 2: go(KNAME_T(k_hmv<T, 2>), k_hmv<T, 2>); break;
+    case 4: go(KNAME_T(k_hmv<T, 4>), k_hmv<T, 4>); break;
+    default: go(KNAME_T(k_hmv<T, 8>), k_hmv<T, 8>); break;
   }
 }
 
@@ -1887,7 +2181,7 @@ void badd(hipStream_t st, int rows, int cols, int nmat, T alpha, const BOp& src,
 template <typename T>
 void fill(hipStream_t st, T* p, size_t n, T v) {
   if (!n) return;
-  launch(st, KC_OTHER, 0.0, (double)n * sizeof(T), k_fill<T>, dim3(grid1((long long)n, 256, 16384)),
+  launch(st, KC_OTHER, 0.0, (double)n * sizeof(T), KNAME_T(k_fill<T>), k_fill<T>, dim3(grid1((long long)n, 256, 16384)),
          dim3(256), 0, p, n, v);
 }
 
@@ -1905,7 +2199,7 @@ template <typename T>
 void build_capacitance(hipStream_t st, int k, int npairs, const T* cores, T* G) {
   if (k <= 0 || npairs <= 0) return;
   dim3 g(grid1(4LL * k * k, 256, 64), npairs);
-  launch(st, KC_OTHER, 0.0, 0.0, k_build_cap<T>, g, dim3(256), 0, k, npairs, cores, G);
+  launch(st, KC_OTHER, 0.0, 0.0, KNAME_T(k_build_cap<T>), k_build_cap<T>, g, dim3(256), 0, k, npairs, cores, G);
 }
 
 template <typename T>
@@ -1913,7 +2207,7 @@ void build_leaves_tridiag(hipStream_t st, int s, int b, int nmat, int bmul, int 
                           const double* diag, const double* west, const double* east, T* leaves) {
   if (nmat <= 0) return;
   dim3 g(grid1((long long)s * b, 256, 256), nmat);
-  launch(st, KC_OTHER, 0.0, 0.0, k_leaves_tridiag<T>, g, dim3(256), 0, s, b, bmul, boff, diag, west, east,
+  launch(st, KC_OTHER, 0.0, 0.0, KNAME_T(k_leaves_tridiag<T>), k_leaves_tridiag<T>, g, dim3(256), 0, s, b, bmul, boff, diag, west, east,
          leaves);
 }
 
@@ -1922,21 +2216,21 @@ void build_rank1_factors(hipStream_t st, int s, int sd, int nmat, int bmul, int 
                          const double* west, const double* east, T* U, T* V) {
   if (nmat <= 0) return;
   dim3 g(grid1(s, 256, 64), nmat);
-  launch(st, KC_OTHER, 0.0, 0.0, k_rank1<T>, g, dim3(256), 0, s, sd, bmul, boff, west, east, U, V);
+  launch(st, KC_OTHER, 0.0, 0.0, KNAME_T(k_rank1<T>), k_rank1<T>, g, dim3(256), 0, s, sd, bmul, boff, west, east, U, V);
 }
 
 template <typename T>
 void gather_diag(hipStream_t st, int s, int nmat, int bmul, int boff, const double* src, T* dst) {
   if (nmat <= 0) return;
   dim3 g(grid1(s, 256, 64), nmat);
-  launch(st, KC_OTHER, 0.0, 0.0, k_gather_diag<T>, g, dim3(256), 0, s, bmul, boff, src, dst);
+  launch(st, KC_OTHER, 0.0, 0.0, KNAME_T(k_gather_diag<T>), k_gather_diag<T>, g, dim3(256), 0, s, bmul, boff, src, dst);
 }
 
 template <typename T>
 void to_blocks(hipStream_t st, int s, int nblk, int nrhs, const double* B, long long ld, T* V) {
   const long long n = (long long)s * nblk * nrhs;
   if (n <= 0) return;
-  launch(st, KC_OTHER, 0.0, (double)n * (8 + sizeof(T)), k_to_blocks<T>, dim3(grid1(n, 256, 16384)),
+  launch(st, KC_OTHER, 0.0, (double)n * (8 + sizeof(T)), KNAME_T(k_to_blocks<T>), k_to_blocks<T>, dim3(grid1(n, 256, 16384)),
          dim3(256), 0, s, nblk, nrhs, B, ld, V);
 }
 
@@ -1944,7 +2238,7 @@ template <typename T>
 void from_blocks(hipStream_t st, int s, int nblk, int nrhs, const T* V, double* B, long long ld) {
   const long long n = (long long)s * nblk * nrhs;
   if (n <= 0) return;
-  launch(st, KC_OTHER, 0.0, (double)n * (8 + sizeof(T)), k_from_blocks<T>, dim3(grid1(n, 256, 16384)),
+  launch(st, KC_OTHER, 0.0, (double)n * (8 + sizeof(T)), KNAME_T(k_from_blocks<T>), k_from_blocks<T>, dim3(grid1(n, 256, 16384)),
          dim3(256), 0, s, nblk, nrhs, V, B, ld);
 }
 
@@ -1954,7 +2248,7 @@ void bdiag_axpy(hipStream_t st, int s, int nrhs, int nmat, T alpha, const T* d, 
   if (nmat <= 0) return;
   dim3 g(grid1((long long)s * nrhs, 256, 256), nmat);
   launch(st, KC_MATVEC, 2.0 * s * nrhs * nmat, (double)sizeof(T) * nmat * (3.0 * s * nrhs + s),
-         k_bdiag_axpy<T>, g, dim3(256), 0, s, nrhs, alpha, d, dmul, doff, x, xmul, xoff, y, ymul, yoff);
+KNAME_T(k_bdiag_axpy<T>),          k_bdiag_axpy<T>, g, dim3(256), 0, s, nrhs, alpha, d, dmul, doff, x, xmul, xoff, y, ymul, yoff);
 }
 
 void stencil_residual(hipStream_t st, int nx, int ny, int nrhs, const double* diag,
@@ -1962,7 +2256,7 @@ void stencil_residual(hipStream_t st, int nx, int ny, int nrhs, const double* di
                       const double* north, const double* X, const double* B, double* R) {
   const long long N = (long long)nx * ny;
   dim3 g(grid1(N, 256, 8192), nrhs);
-  launch(st, KC_OTHER, 10.0 * N * nrhs, 8.0 * N * (5.0 + 3.0 * nrhs), k_residual, g, dim3(256), 0, nx, ny,
+  launch(st, KC_OTHER, 10.0 * N * nrhs, 8.0 * N * (5.0 + 3.0 * nrhs), KNAME0(k_residual), k_residual, g, dim3(256), 0, nx, ny,
          diag, west, east, south, north, X, B, R);
 }
 
@@ -1970,15 +2264,15 @@ void col_sumsq(hipStream_t st, long long n, int ncol, const double* A, double* o
   const int nparts = (int)std::min<long long>(512, std::max<long long>(1, (n + 4095) / 4096));
   const long long chunk = (n + nparts - 1) / nparts;
   DBuf<double> part((size_t)nparts * ncol);
-  launch(st, KC_OTHER, 0.0, 8.0 * n * ncol, k_col_sumsq_part, dim3(nparts, ncol), dim3(256), 0, n, chunk, A,
+  launch(st, KC_OTHER, 0.0, 8.0 * n * ncol, KNAME0(k_col_sumsq_part), k_col_sumsq_part, dim3(nparts, ncol), dim3(256), 0, n, chunk, A,
          part.get());
-  launch(st, KC_OTHER, 0.0, 0.0, k_col_sumsq_final, dim3(ncol), dim3(256), 0, nparts, (const double*)part.get(),
+  launch(st, KC_OTHER, 0.0, 0.0, KNAME0(k_col_sumsq_final), k_col_sumsq_final, dim3(ncol), dim3(256), 0, nparts, (const double*)part.get(),
          out);
 }
 
 void flag_nonfinite(hipStream_t st, long long n, const double* a, int* flag) {
   if (n <= 0) return;
-  launch(st, KC_OTHER, 0.0, 8.0 * n, k_count_nonfinite, dim3(grid1(n, 256, 4096)), dim3(256), 0, n, a, flag);
+  launch(st, KC_OTHER, 0.0, 8.0 * n, KNAME0(k_count_nonfinite), k_count_nonfinite, dim3(grid1(n, 256, 4096)), dim3(256), 0, n, a, flag);
 }
 
 template <typename T>
@@ -1990,7 +2284,7 @@ void scan_values(hipStream_t st, long long n, const T* a, bool* bad, double* ama
   DBuf<int> flag(1);
   DBuf<double> mx(g);
   memset_async(flag.get(), 0, sizeof(int), st);
-  launch(st, KC_OTHER, 0.0, (double)n * sizeof(T), k_scan_values<T>, dim3(g), dim3(256), 0, n, a, flag.get(),
+  launch(st, KC_OTHER, 0.0, (double)n * sizeof(T), KNAME_T(k_scan_values<T>), k_scan_values<T>, dim3(g), dim3(256), 0, n, a, flag.get(),
          mx.get());
   int hb = 0;
   std::vector<double> hm(g);
@@ -2005,7 +2299,7 @@ template void scan_values<float>(hipStream_t, long long, const float*, bool*, do
 template void scan_values<double>(hipStream_t, long long, const double*, bool*, double*);
 
 void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
-  launch(st, KC_OTHER, 0.0, 24.0 * n, k_axpy_d, dim3(grid1(n, 256, 16384)), dim3(256), 0, n, D, X);
+  launch(st, KC_OTHER, 0.0, 24.0 * n, KNAME0(k_axpy_d), k_axpy_d, dim3(grid1(n, 256, 16384)), dim3(256), 0, n, D, X);
 }
 
 #define INST(T)                                                                                   \

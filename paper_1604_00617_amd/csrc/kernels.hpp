@@ -56,13 +56,13 @@ struct SJob {
   int* rank = nullptr;
   double* flops = nullptr;
   double eps = 0.0;
-  int maxrank = 0, pad = 0;
+  int maxrank = 0, lds = 0;   // lds: K, X and J staged in LDS
 };
 
 // Y_(m,c) = Q_(m,c) [Z_(m, c^zxor); 0] with reflectors of a QJob.
 struct AJob {
   long long block0 = 0;
-  int p = 0, c = 0, t = 0, nmat = 0, ncl = 0, zxor = 0;
+  int p = 0, c = 0, t = 0, nmat = 0, ncl = 0, zxor = 0, lds = 0, pad = 0;
   const void* Vref = nullptr;
   const void* tau = nullptr;
   const void* Z = nullptr;
