@@ -184,7 +184,9 @@ acr_status acr_profile_read(int32_t cls, int64_t* launches, double* total_ms, do
  *       steps ("inverse", "products P,Q", "recompress D',E',F'", "solve
  *       forward", ...), level the cyclic-reduction level (-1 outside the loop);
  *   "kernel <name> <class> <launches> <ms> <flops> <bytes>"  per kernel, with
- *       the name as kernel statistics of rocprofv3 print it ("k_gqr<float>").
+ *       the name as kernel statistics of rocprofv3 print it ("k_gqr<float>");
+ *   "stagekernel <stage> <name> <launches> <ms> <flops> <bytes>"  per (stage,
+ *       kernel) over all levels.
  * flops and bytes are the algorithmic counts of those launches.  Writes at
  * most len bytes including the terminating NUL into buf (host memory, owned
  * by the caller; may be NULL with len 0); *needed (may be NULL) receives the

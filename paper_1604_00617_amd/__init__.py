@@ -269,4 +269,7 @@ def acr_profile_report() -> dict:
             out["stages"].append((f[1], int(f[2]), f[3], int(f[4]), float(f[5]), float(f[6]), float(f[7])))
         elif f[0] == "kernel":
             out["kernels"].append((f[1], f[2], int(f[3]), float(f[4]), float(f[5]), float(f[6])))
+        elif f[0] == "stagekernel":
+            out.setdefault("stage_kernels", []).append((f[1], f[2], int(f[3]), float(f[4]), float(f[5]),
+                                                        float(f[6])))
     return out

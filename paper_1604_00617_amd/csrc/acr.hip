@@ -777,6 +777,8 @@ acr_status acr_profile_report(char* buf, int64_t len, int64_t* needed) {
       add(std::string("stage\t") + (r.phase ? r.phase : "-") + "\t" + std::to_string(r.level) + "\t" +
               names[r.cls], r.cls, e, fl, r.bytes);
       add(std::string("kernel\t") + (r.kname ? r.kname : "-") + "\t" + names[r.cls], r.cls, e, fl, r.bytes);
+      add(std::string("stagekernel\t") + (r.phase ? r.phase : "-") + "\t" + (r.kname ? r.kname : "-"), r.cls, e, fl,
+          r.bytes);
     }
     std::string out;
     for (auto& kv : rows) {

@@ -848,6 +848,230 @@ __global__ __launch_bounds__(256) void k_inverse_lds(int n, const Tin* A, long l
   if (tid == 0 && bad) status[0] = 1;
 }
 
+// ------------------------------------ rank-revealing SVD, core in registers
+// Same computation and outputs as k_grsvd for cores of size c <= 64 whose
+// numerical rank (the number of pivoted Householder steps before the stop
+// test) is at most SV_TP: the column-pivoted QR runs with the core in
+// registers (wave w owns the physical columns q = w + 4u, lane = row; no
+// column swaps: the pivot column is processed in place and R is recorded by
+// physical column), then one wave runs the one-sided Jacobi iteration on
+// X = R_top^T with X and J in registers (cyclic pair order) and forms
+// U_K = Q_K [J; 0].  A problem whose rank exceeds SV_TP is flagged in redo[]
+// and left to k_grsvd.
+constexpr int SV_TP = 16;
+template <typename T>
+__global__ __launch_bounds__(256) void k_grsvd_reg(const SJob* __restrict__ jobs, int njobs) {
+  constexpr int SL = 16;   // column slots per wave (c <= 64)
+  __shared__ T Rt[64][65];
+  __shared__ T Vk[64][64];
+  __shared__ T tk[64];
+  __shared__ double cval[2][4];
+  __shared__ int cidx[2][4];
+  __shared__ double cfro[4];
+  const SJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int prob = (int)(blockIdx.x - Jb.block0);
+  const int c = Jb.c, maxrank = Jb.maxrank;
+  const double eps = Jb.eps;
+  const T* Kp = static_cast<const T*>(Jb.K) + (size_t)prob * c * c;
+  const int tid = threadIdx.x, lane = tid % WAVE;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
+  T w[SL];
+  bool used[SL];
+#pragma unroll
+  for (int u = 0; u < SL; ++u) {
+    const int q = wv + 4 * u;
+    w[u] = (lane < c && q < c) ? Kp[lane + (size_t)q * c] : T(0);
+    used[u] = false;
+  }
+  double delta2 = 0.0, fl = 0.0;
+  int tp = 0;
+  for (int j = 0; j < c; ++j) {
+    const int cb = j & 1;
+    // this wave's best unused column: squared norm of rows >= j
+    double best = -1.0, fro = 0.0;
+    int bq = 0x7fffffff;
+#pragma unroll
+    for (int u = 0; u < SL; ++u) {
+      const int q = wv + 4 * u;
+      if (q < c && !used[u]) {
+        const double xv = (double)w[u];
+        const double nn = wave_sum((lane >= j && lane < c) ? xv * xv : 0.0);
+        fro += nn;
+        if (nn > best) { best = nn; bq = q; }
+      }
+    }
+    if (lane == 0) {
+      cval[cb][wv] = best;
+      cidx[cb][wv] = bq;
+      if (j == 0) cfro[wv] = fro;
+    }
+    __syncthreads();
+    double gb = -1.0;
+    int pc = 0x7fffffff;
+    for (int o = 0; o < 4; ++o) {
+      const double v = cval[cb][o];
+      const int qq = cidx[cb][o];
+      if (v > gb || (v == gb && qq < pc)) { gb = v; pc = qq; }
+    }
+    if (j == 0) {   // stop rule of k_grsvd
+      const double fl2 = 16.0 * Eps<T>::v * Eps<T>::v * (cfro[0] + cfro[1] + cfro[2] + cfro[3]);
+      delta2 = eps > 0.0 ? fmax((0.01 * eps * eps) * gb / c, fl2) : 0.0;
+    }
+    if (gb <= delta2 || !(gb > 0.0)) break;   // same decision in every thread
+    if (wv == (pc & 3)) {
+      const int slot = pc >> 2;
+      T x = T(0);
+#pragma unroll
+      for (int u = 0; u < SL; ++u)
+        if (u == slot) x = w[u];
+      const double xv = (double)x;
+      const double tail = wave_sum((lane > j && lane < c) ? xv * xv : 0.0);
+      const double alpha = wave_sum(lane == j ? xv : 0.0);
+      const double nr = sqrt(alpha * alpha + tail);
+      const double beta = alpha >= 0.0 ? -nr : nr;
+      const bool refl = !(tail == 0.0 || nr == 0.0);
+      const double v0 = alpha - beta;
+      T vv = T(0);
+      if (refl && lane >= j && lane < c) vv = (lane == j) ? T(1) : (T)(xv / v0);
+      Vk[j][lane] = vv;
+      if (lane == 0) tk[j] = refl ? (T)((beta - alpha) / beta) : T(0);
+      const T diag = refl ? (T)beta : (T)alpha;
+#pragma unroll
+      for (int u = 0; u < SL; ++u)
+        if (u == slot) {
+          if (lane == j) w[u] = diag;
+          else if (lane > j) w[u] = T(0);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < SL; ++u)
+      if (wv + 4 * u == pc) used[u] = true;
+    __syncthreads();
+    const T tau = tk[j];
+    if (tau != T(0)) {
+      const T v = Vk[j][lane];
+#pragma unroll
+      for (int u = 0; u < SL; ++u) {
+        const int q = wv + 4 * u;
+        if (q < c && !used[u]) {
+          const T d = wave_sum(v * w[u]) * tau;
+          w[u] = fma(-d, v, w[u]);
+        }
+      }
+    }
+    if (lane == j)
+#pragma unroll
+      for (int u = 0; u < SL; ++u) {
+        const int q = wv + 4 * u;
+        if (q < c) Rt[j][q] = w[u];
+      }
+    tp = j + 1;
+    fl += 6.0 * (double)(c - j) * (c - j);
+  }
+  __syncthreads();
+  if (tp > SV_TP) {
+    if (tid == 0) Jb.redo[prob] = 1;
+    return;
+  }
+  if (wv != 0) return;
+  // one-sided Jacobi on X = R_top^T (c x tp): lane = row of X; J (tp x tp): lane = row
+  T x[SV_TP], jr[SV_TP];
+#pragma unroll
+  for (int i = 0; i < SV_TP; ++i) {
+    x[i] = (i < tp && lane < c) ? Rt[i][lane] : T(0);
+    jr[i] = (lane == i) ? T(1) : T(0);
+  }
+  double ssf = 0.0;
+#pragma unroll
+  for (int i = 0; i < SV_TP; ++i) ssf += (double)x[i] * (double)x[i];
+  const double negl2 = wave_sum(ssf) * Eps<T>::v * Eps<T>::v;
+  const double tol = 4.0 * Eps<T>::v;
+  for (int sweep = 0; sweep < 60 && tp > 1; ++sweep) {
+    int nrot = 0;
+#pragma unroll
+    for (int p0 = 0; p0 < SV_TP; ++p0)
+#pragma unroll
+      for (int q0 = p0 + 1; q0 < SV_TP; ++q0) {
+        if (q0 < tp) {
+          const double xa = x[p0], xb = x[q0];
+          const double al = wave_sum(xa * xa), be = wave_sum(xb * xb), ga = wave_sum(xa * xb);
+          if (fabs(ga) > tol * sqrt(al * be) && fmax(al, be) > negl2) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double az = fabs(zeta);
+            double t = (az > 1e15) ? 0.5 / az : 1.0 / (az + sqrt(1.0 + az * az));
+            t = copysign(t, zeta);
+            const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+            x[p0] = (T)(cs * xa - sn * xb);
+            x[q0] = (T)(sn * xa + cs * xb);
+            const double ja = jr[p0], jb = jr[q0];
+            jr[p0] = (T)(cs * ja - sn * jb);
+            jr[q0] = (T)(sn * ja + cs * jb);
+            ++nrot;
+          }
+        }
+      }
+    fl += 3.0 * (double)tp * (tp - 1) * c + (double)nrot * (6.0 * c + 6.0 * tp);
+    if (nrot == 0) break;
+  }
+  // singular values (column norms of X), their order (descending, ties by index)
+  T sv[SV_TP];
+#pragma unroll
+  for (int i = 0; i < SV_TP; ++i) {
+    const double s2 = wave_sum((double)x[i] * (double)x[i]);
+    sv[i] = i < tp ? (T)sqrt(s2) : T(0);
+  }
+  int pos[SV_TP];
+#pragma unroll
+  for (int i = 0; i < SV_TP; ++i) {
+    int ps = 0;
+#pragma unroll
+    for (int o = 0; o < SV_TP; ++o) ps += (o < tp) && (sv[o] > sv[i] || (sv[o] == sv[i] && o < i));
+    pos[i] = ps;
+  }
+  // U_K = Q_K [J; 0]: reflectors applied in reverse order to the columns of J
+  T y[SV_TP];
+#pragma unroll
+  for (int i = 0; i < SV_TP; ++i) y[i] = (lane < tp) ? jr[i] : T(0);
+  for (int j = tp - 1; j >= 0; --j) {
+    const T tau = tk[j];
+    if (tau == T(0)) continue;
+    const T v = lane < c ? Vk[j][lane] : T(0);
+#pragma unroll
+    for (int i = 0; i < SV_TP; ++i)
+      if (i < tp) {
+        const T d = wave_sum(v * y[i]) * tau;
+        y[i] = fma(-d, v, y[i]);
+      }
+  }
+  T* Y = static_cast<T*>(Jb.UK) + (size_t)prob * c * c;
+  if (lane < c) {
+#pragma unroll
+    for (int i = 0; i < SV_TP; ++i)
+      if (i < tp) Y[lane + (size_t)pos[i] * c] = y[i];
+    for (int q = tp; q < c; ++q) Y[lane + (size_t)q * c] = T(0);
+  }
+  T* so = static_cast<T*>(Jb.sig) + (size_t)prob * c;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < SV_TP; ++i)
+      if (i < tp) so[pos[i]] = sv[i];
+    for (int q = tp; q < c; ++q) so[q] = T(0);
+    T smax = T(0);
+#pragma unroll
+    for (int i = 0; i < SV_TP; ++i) smax = sv[i] > smax ? sv[i] : smax;
+    int t = 0;
+    if (smax > T(0)) {
+      const double thr = eps * (double)smax;
+#pragma unroll
+      for (int i = 0; i < SV_TP; ++i) t += (i < tp) && ((double)sv[i] > thr);
+    }
+    if (maxrank > 0 && t > maxrank) t = maxrank;
+    Jb.rank[prob] = t;
+    fl += 4.0 * (double)c * tp * tp;
+    if (Jb.flops) Jb.flops[prob] = fl;
+  }
+}
+
 // ------------------------------------------------- QR, panel in registers
 // Householder QR of a p x k panel (p <= 64*QR_ROWS, k <= 4*QR_SLOTS) with the
 // panel in registers: wave w owns the columns q = w + 4u, lane l the rows
@@ -1165,6 +1389,7 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
   __shared__ T s_beta;
   const SJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
   const int prob = (int)(blockIdx.x - Jb.block0);
+  if (Jb.redo && Jb.redo[prob] == 0) return;   // finished by k_grsvd_reg
   const int c = Jb.c, maxrank = Jb.maxrank;
   const double eps = Jb.eps;
   T* const Xall = static_cast<T*>(Jb.X);
@@ -1208,7 +1433,15 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
       if (tid == 0) {
-        if (j == 0) s_delta2 = eps > 0.0 ? (0.01 * eps * eps) * best / c : 0.0;
+        if (j == 0) {
+          // stop once the remaining columns are below 0.1 eps of the largest one
+          // (scaled by the core size) or at the rounding floor of the working
+          // precision, 4 u ||K||_F, below which they carry no information
+          double fro = 0.0;
+          for (int q = 0; q < c; ++q) fro += nrm[q];
+          const double fl2 = 16.0 * Eps<T>::v * Eps<T>::v * fro;
+          s_delta2 = eps > 0.0 ? fmax((0.01 * eps * eps) * best / c, fl2) : 0.0;
+        }
         s_piv = bi;
         s_stop = (best <= s_delta2) || !(best > 0.0);
       }
@@ -1976,22 +2209,26 @@ void bapply_q(hipStream_t st, int p, int c, int t, int nmat, int ncl, const T* V
 
 template <typename T>
 void grsvd(hipStream_t st, std::vector<SJob> jobs) {
-  // The core and its two work matrices in LDS: launch 0 holds the jobs that
-  // fit next to the kernel's static arrays in 64 KB, launch 1 those that fit
-  // the full gfx950 workgroup LDS; larger cores work in global scratch.
+  // Cores of size 48..64 go to k_grsvd_reg first; the few whose numerical rank
+  // exceeds its register budget are flagged and redone by k_grsvd, which
+  // returns at once for every other problem.  k_grsvd keeps the core and its
+  // two work matrices in LDS: launch 0 holds the jobs that fit next to the
+  // kernel's static arrays in 64 KB, launch 1 those that fit the full gfx950
+  // workgroup LDS; larger cores work in global scratch.
   constexpr size_t kStatic = 16384;
   std::vector<DBuf<T>> scratch;
-  std::vector<SJob> use[2];
+  std::vector<SJob> use[2], reg;
   Profiler& P = Profiler::get();
   const bool prof = P.on(KC_SVD);
   double* fl = nullptr;
-  long long b0[2] = {0, 0}, total = 0;
+  long long b0[2] = {0, 0}, total = 0, nreg = 0;
   size_t dyn[2] = {0, 0};
   double by[2] = {0, 0};
   for (auto& J : jobs) {
     if (J.c <= 0 || J.nprob <= 0) continue;
     if (J.c > 512) fail(ACR_ERR_INVALID_ARG, "rank-revealing SVD core larger than 512");
     total += J.nprob;
+    if (J.c >= 48 && J.c <= 64) nreg += J.nprob;
   }
   if (total == 0) return;
   if (prof) {
@@ -1999,9 +2236,24 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     P.owned_d().emplace_back((size_t)total);
     fl = P.owned_d().back().get();
   }
-  long long done = 0;
+  DBuf<int> redo((size_t)nreg);
+  if (nreg) memset_async(redo.get(), 0, (size_t)nreg * sizeof(int), st);
+  long long done = 0, rdone = 0, rb0 = 0;
+  double rby = 0;
   for (auto& J : jobs) {
     if (J.c <= 0 || J.nprob <= 0) continue;
+    J.flops = fl ? fl + done : nullptr;
+    done += J.nprob;
+    J.redo = nullptr;
+    if (J.c >= 48 && J.c <= 64) {
+      J.redo = redo.get() + rdone;
+      rdone += J.nprob;
+      SJob R = J;
+      R.block0 = rb0;
+      rb0 += J.nprob;
+      rby += 4.0 * (double)J.c * J.c * J.nprob * sizeof(T);
+      reg.push_back(R);
+    }
     const size_t need = 3 * (size_t)J.c * J.c * sizeof(T);
     int g = 0;
     J.lds = 1;
@@ -2017,21 +2269,23 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
       scratch.emplace_back((size_t)J.nprob * J.c * J.c);
       J.J = scratch.back().get();
     }
-    J.flops = fl ? fl + done : nullptr;
-    done += J.nprob;
     J.block0 = b0[g];
     b0[g] += J.nprob;
-    by[g] += 4.0 * (double)J.c * J.c * J.nprob * sizeof(T);
+    if (!J.redo) by[g] += 4.0 * (double)J.c * J.c * J.nprob * sizeof(T);
     use[g].push_back(J);
+  }
+  if (!reg.empty()) {
+    const SJob* dj = upload(reg, st);
+    launch(st, KC_SVD, 0.0, rby, KNAME_T(k_grsvd_reg<T>), k_grsvd_reg<T>, dim3((unsigned)rb0), dim3(256), 0, dj,
+           (int)reg.size());
   }
   for (int g = 0; g < 2; ++g) {
     if (use[g].empty()) continue;
     if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_grsvd<T>));
     const SJob* dj = upload(use[g], st);
     const int nj = (int)use[g].size();
-    const long long nb = b0[g];
-    const size_t shm = dyn[g];
-    launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd<T>), k_grsvd<T>, dim3((unsigned)nb), dim3(256), shm, dj, nj);
+    launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd<T>), k_grsvd<T>, dim3((unsigned)b0[g]), dim3(256), dyn[g], dj,
+           nj);
   }
   if (fl) {   // device-counted flops of every problem, credited to the last launch
     const int n = (int)total;

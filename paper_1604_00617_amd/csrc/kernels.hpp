@@ -57,6 +57,7 @@ struct SJob {
   double* flops = nullptr;
   double eps = 0.0;
   int maxrank = 0, lds = 0;   // lds: K, X and J staged in LDS
+  int* redo = nullptr;        // register path: per-problem "left to the general kernel" flags
 };
 
 // Y_(m,c) = Q_(m,c) [Z_(m, c^zxor); 0] with reflectors of a QJob.
