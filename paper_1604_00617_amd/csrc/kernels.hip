@@ -72,6 +72,39 @@ __device__ __forceinline__ double lane_read(double x, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// 64-bit lane move with DPP (out-of-range sources read the lane's own value).
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_mov_u64(unsigned long long x) {
+  const int lo = (int)(unsigned)x, hi = (int)(unsigned)(x >> 32);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  return ((unsigned long long)(unsigned)h2 << 32) | (unsigned)l2;
+}
+__device__ __forceinline__ unsigned long long lane_read_u64(unsigned long long x, int l) {
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)x, l);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(x >> 32), l);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+// Maximum of a 64-bit key over aligned groups of N lanes (N = 8, 16, 32, 64),
+// returned to every lane of the group: quad and mirror DPP steps give the
+// maximum of each row of 16 to all its lanes, lane reads combine rows.
+template <int N>
+__device__ __forceinline__ unsigned long long group_max_u64(unsigned long long k) {
+  auto mx = [](unsigned long long a, unsigned long long b) { return a > b ? a : b; };
+  k = mx(k, dpp_mov_u64<0xb1>(k));     // quad_perm [1,0,3,2]
+  k = mx(k, dpp_mov_u64<0x4e>(k));     // quad_perm [2,3,0,1]
+  if constexpr (N >= 8) k = mx(k, dpp_mov_u64<0x141>(k));    // row_half_mirror
+  if constexpr (N >= 16) k = mx(k, dpp_mov_u64<0x140>(k));   // row_mirror
+  if constexpr (N == 32) {
+    const unsigned long long a = mx(lane_read_u64(k, 15), lane_read_u64(k, 31));
+    const unsigned long long b = mx(lane_read_u64(k, 47), lane_read_u64(k, 63));
+    k = (threadIdx.x % WAVE) < 32 ? a : b;
+  } else if constexpr (N == 64) {
+    k = mx(mx(lane_read_u64(k, 15), lane_read_u64(k, 31)), mx(lane_read_u64(k, 47), lane_read_u64(k, 63)));
+  }
+  return k;
+}
+
 // Sum over the 64 lanes of a wave, returned to every lane: quad sums
 // (quad_perm), row-of-16 sums (row_shr 4, 8: the last lane of each row holds
 // its row's total), then row_bcast 15 / 31 carry the row totals into lane 63,
@@ -624,31 +657,23 @@ __global__ __launch_bounds__(256) void k_hmv(const MVJob* __restrict__ jobs, int
 // ---------------------------------------------------------------- inverse
 // Small inverses (n <= N <= 64): Gauss-Jordan with partial pivoting in FP64,
 // one row per lane.  A wave holds 64/N matrices (lane group g, row r = lane
-// mod N) with the working row in registers; the pivot row's entries are
-// broadcast with lane reads, so there is no LDS traffic and no barrier in the
-// elimination.  Rows are never swapped: the row chosen at step j is recorded,
-// and with the in-place storage (column j of the working matrix holds column
-// p_j of the accumulated transformation M, M A = P) the inverse is read back
-// as X[j, p_j'] = W[p_j, j'].
-template <int N>
-__device__ __forceinline__ double row_bcast(double v, int src) {
-  if constexpr (N == WAVE) {
-    const int sl = __builtin_amdgcn_readfirstlane(src);
-    const long long x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)x, sl);
-    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), sl);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-  } else {
-    return __shfl(v, src, N);
-  }
-}
-
+// mod N) with the working row in registers.  Rows are neither swapped nor
+// normalised during the elimination: at step j the pivot row p_j (largest
+// |entry| in column j among the rows not yet used) is published in LDS, every
+// other row subtracts its multiple of it, and the in-place storage turns
+// column j into column p_j of the accumulated transformation M (M A = D P,
+// D the pivots).  At the end each row is divided by its pivot and the inverse
+// is read back as X[j, p_j'] = W[p_j, j'] / d_(p_j).  The current column is
+// kept at a compile-time register position by rotating the row by 8 columns
+// after every 8 steps.
 template <typename Tin, typename Tout, int N>
 __global__ __launch_bounds__(256) void k_inverse_wave(int n, int nprob, const Tin* __restrict__ A,
                                                      long long sA, Tout* __restrict__ X, long long sX,
                                                      int* status) {
   constexpr int G = WAVE / N;
+  constexpr int JB = N < 8 ? N : 8;
   __shared__ int piv_row[4][WAVE];
+  __shared__ double prow[4][WAVE];
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
   const int g = lane / N, r = lane % N;
   const long long p = ((long long)blockIdx.x * 4 + wv) * G + g;
@@ -660,39 +685,62 @@ __global__ __launch_bounds__(256) void k_inverse_wave(int n, int nprob, const Ti
     a[c] = (valid && r < n && c < n) ? (double)Ap[r + (long long)c * n] : (r == c ? 1.0 : 0.0);
   bool used = false, bad = false;
   int mystep = r;
-  for (int j = 0; j < n; ++j) {
-    double f = 0.0;
+  double mypiv = 1.0;
+  double* pr = &prow[wv][g * N];
+  for (int jb = 0; jb < n; jb += JB) {
 #pragma unroll
-    for (int c = 0; c < N; ++c) f = (c == j) ? a[c] : f;
-    double best = used ? -1.0 : fabs(f);
-    int bi = r;
+    for (int jj = 0; jj < JB; ++jj) {
+      const int j = jb + jj;
+      if (j < n) {
+        const double f = a[jj];
+        // pivot: largest |f| over the unused rows, ties to the lowest row; the
+        // key is |f|'s bit pattern (monotone for non-negative doubles) with its
+        // 6 lowest bits replaced by 63 - row
+        const unsigned long long key =
+            used ? 0ull : ((__double_as_longlong(fabs(f)) & ~63ull) | (unsigned long long)(63 - r));
+        const unsigned long long kmax = group_max_u64<N>(key);
+        const int bi = 63 - (int)(kmax & 63ull);
+        const double best = __longlong_as_double((long long)(kmax & ~63ull));
+        if (!(best > 0.0) || !isfinite(best)) bad = true;
+        const bool is_piv = r == bi;
+        if (is_piv) {
+          used = true;
+          mystep = j;
+          mypiv = f;
 #pragma unroll
-    for (int off = N / 2; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, N);
-      const int oi = __shfl_xor(bi, off, N);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+          for (int c = 0; c < N; ++c) pr[c] = a[c];
+        }
+        // the other lanes of the group read what the pivot lane wrote: a
+        // wavefront-scope fence orders the accesses (LDS is in order per wave)
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const double qq = is_piv ? 0.0 : f / pr[jj];
+#pragma unroll
+        for (int c = 0; c < N; ++c) a[c] = fma(-qq, pr[c], a[c]);
+        a[jj] = is_piv ? 1.0 : -qq;
+        if (r == 0) piv_row[wv][g * N + j] = bi;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      }
     }
-    const double pv = row_bcast<N>(f, bi);
-    if (!(best > 0.0) || !isfinite(best)) bad = true;
-    const double inv = 1.0 / pv;
-    const bool is_piv = r == bi;
-    if (is_piv) { used = true; mystep = j; }
-    if (r == 0) piv_row[wv][g * N + j] = bi;
-    const double qq = is_piv ? -inv : f * inv;
+    double t[JB];
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-      const double pc = row_bcast<N>(a[c], bi);
-      const double base = is_piv ? 0.0 : a[c];
-      a[c] = (c == j) ? -qq : fma(-qq, pc, base);
-    }
+    for (int c = 0; c < JB; ++c) t[c] = a[c];
+#pragma unroll
+    for (int c = 0; c < N - JB; ++c) a[c] = a[c + JB];
+#pragma unroll
+    for (int c = 0; c < JB; ++c) a[N - JB + c] = t[c];
   }
   __syncthreads();
   if (valid && r < n) {
+    const double inv = 1.0 / mypiv;
+    const int R = ((n + JB - 1) / JB) * JB;   // total rotation: register c holds column (c + R) mod N
     Tout* Xp = X + p * sX;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
-      const int pc = piv_row[wv][g * N + c];   // < n unless the matrix is singular (then flagged)
-      if (c < n && pc < n) Xp[mystep + (long long)pc * n] = (Tout)a[c];
+      const int L = (c + R) % N;
+      if (L < n) {
+        const int pc = piv_row[wv][g * N + L];   // < n unless the matrix is singular (then flagged)
+        if (pc < n) Xp[mystep + (long long)pc * n] = (Tout)(a[c] * inv);
+      }
     }
     if (r == 0 && bad) status[0] = 1;
   }
