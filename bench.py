@@ -86,7 +86,7 @@ def dominant_kernel(acr, torch, op, b, args, precision):
             by_stage[stage] = by_stage.get(stage, 0.0) + ms
         for stage, ms in sorted(by_stage.items(), key=lambda kv: -kv[1]):
             print(f"[stage] {stage:24s} {ms:8.3f} ms", file=sys.stderr)
-        for stage, level, cls, n, ms, fl, by in sorted(rep["stages"], key=lambda r: -r[4])[:40]:
+        for stage, level, cls, n, ms, fl, by in sorted(rep["stages"], key=lambda r: -r[4])[:80]:
             print(f"[stage-level] {stage:24s} L{level:<3d} {cls:8s} {n:5d} {ms:8.3f} ms", file=sys.stderr)
         for name, cls, n, ms, fl, by in sorted(rep["kernels"], key=lambda r: -r[3]):
             print(f"[kernel] {name:40s} {cls:8s} {n:5d} {ms:8.3f} ms", file=sys.stderr)

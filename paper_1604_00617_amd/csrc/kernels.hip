@@ -26,6 +26,7 @@ constexpr size_t kMaxLdsLarge = 163840;  // all the LDS a gfx950 workgroup may h
 constexpr size_t kMaxDynLarge = kMaxLdsLarge - 16384;   // dynamic part next to <= 16 KB static
 constexpr int kMvSlots = 512;        // reduced values per workgroup in the fused matvec
 constexpr int kMvCols = 512;
+constexpr long long kSmallLaunch = 1024;   // workgroups below which shape variants share a launch
 constexpr int kApplyRows = 8;        // Q application in registers: rows per lane (p <= 512)
 constexpr int kApplyCols = 8;        // and output columns per wave (t <= 32)         // row-block columns per workgroup in the fused matvec
 
@@ -513,6 +514,14 @@ __global__ __launch_bounds__(256) void k_hmv(const MVJob* __restrict__ jobs, int
   const bool rowt = part < nparts;
   const int row0 = l * b;
   const long long vs = (long long)s * nrhs;
+  if (J.nterm == 0) {   // pure copy (or zero) job: no reductions, no barriers
+    if (rowt && part == 0) {
+      T* out = static_cast<T*>(J.out) + (long long)(J.omul * m + J.ooff) * vs + row0 + r;
+      const T* c0 = J.C0 ? static_cast<const T*>(J.C0) + (long long)(J.cmul * m + J.coff) * vs + row0 + r : nullptr;
+      for (int q = 0; q < nrhs; ++q) out[(long long)q * s] = c0 ? (T)J.beta * c0[(long long)q * s] : T(0);
+    }
+    return;
+  }
   T acc[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = T(0);
@@ -1128,11 +1137,7 @@ __global__ __launch_bounds__(256) void k_grsvd_reg(const SJob* __restrict__ jobs
 // barrier per step suffices); every wave then applies it to its own columns
 // q > j.  Same outputs as k_gqr.
 template <typename T, int QR_ROWS, int QR_SLOTS>
-__global__ __launch_bounds__(256) void k_gqr_reg(const QJob* __restrict__ jobs, int njobs) {
-  __shared__ T vbuf[2][WAVE * QR_ROWS];
-  __shared__ T stau[2];
-  const QJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
-  const int prob = (int)(blockIdx.x - Jb.block0);
+__device__ __forceinline__ void gqr_reg_body(const QJob& Jb, int prob, T (*vbuf)[WAVE * 8], T* stau) {
   const int p = Jb.p, k = Jb.k, ncl = Jb.ncl;
   const int m = prob / ncl, c = prob % ncl;
   const BOp A = Jb.A;
@@ -1236,6 +1241,39 @@ __global__ __launch_bounds__(256) void k_gqr_reg(const QJob* __restrict__ jobs, 
       const int r = lane + WAVE * i, q = wv + 4 * u;
       if (r < kr && q < k) Rp[r + (size_t)q * kr] = (r <= q) ? w[i][u] : T(0);
     }
+}
+
+template <typename T, int QR_ROWS, int QR_SLOTS>
+__global__ __launch_bounds__(256) void k_gqr_reg(const QJob* __restrict__ jobs, int njobs) {
+  __shared__ T vbuf[2][WAVE * 8];
+  __shared__ T stau[2];
+  const QJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  gqr_reg_body<T, QR_ROWS, QR_SLOTS>(Jb, (int)(blockIdx.x - Jb.block0), vbuf, stau);
+}
+
+// All register shapes in one launch (the job's shape code selects the body):
+// used when a launch is too small to fill the GPU, where one launch per
+// shape would only add their latencies.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gqr_any(const QJob* __restrict__ jobs, int njobs) {
+  __shared__ T vbuf[2][WAVE * 8];
+  __shared__ T stau[2];
+  const QJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int prob = (int)(blockIdx.x - Jb.block0);
+  switch (Jb.pad) {
+    case 0: gqr_reg_body<T, 1, 4>(Jb, prob, vbuf, stau); break;
+    case 1: gqr_reg_body<T, 1, 8>(Jb, prob, vbuf, stau); break;
+    case 2: gqr_reg_body<T, 1, 16>(Jb, prob, vbuf, stau); break;
+    case 3: gqr_reg_body<T, 2, 4>(Jb, prob, vbuf, stau); break;
+    case 4: gqr_reg_body<T, 2, 8>(Jb, prob, vbuf, stau); break;
+    case 5: gqr_reg_body<T, 2, 16>(Jb, prob, vbuf, stau); break;
+    case 6: gqr_reg_body<T, 4, 4>(Jb, prob, vbuf, stau); break;
+    case 7: gqr_reg_body<T, 4, 8>(Jb, prob, vbuf, stau); break;
+    case 8: gqr_reg_body<T, 4, 16>(Jb, prob, vbuf, stau); break;
+    case 9: gqr_reg_body<T, 8, 4>(Jb, prob, vbuf, stau); break;
+    case 10: gqr_reg_body<T, 8, 8>(Jb, prob, vbuf, stau); break;
+    default: gqr_reg_body<T, 8, 16>(Jb, prob, vbuf, stau); break;
+  }
 }
 
 // ------------------------------------------------------------ QR (R only)
@@ -2158,7 +2196,11 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
     by[g] += (double)sizeof(T) * np * (p * k + kr * k + (J.Vref ? p * kr : 0.0));
     use[g].push_back(J);
   }
-  if (!use[2].empty()) {
+  if (!use[2].empty() && b0[2] <= kSmallLaunch) {
+    const QJob* dj = upload(use[2], st);
+    launch(st, KC_QR, fl[2], by[2], KNAME_T(k_gqr_any<T>), k_gqr_any<T>, dim3((unsigned)b0[2]), dim3(256), 0, dj,
+           (int)use[2].size());
+  } else if (!use[2].empty()) {
     // one launch per register shape (rows per lane, columns per wave / 4)
     std::vector<QJob> by_shape[12];
     for (auto& J : use[2]) by_shape[J.pad].push_back(J);
