@@ -2318,8 +2318,12 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     if (J.c <= 0 || J.nprob <= 0) continue;
     if (J.c > 512) fail(ACR_ERR_INVALID_ARG, "rank-revealing SVD core larger than 512");
     total += J.nprob;
-    if (J.c >= 48 && J.c <= 64) nreg += J.nprob;
   }
+  // few problems: one launch of k_grsvd (two launches in sequence would only
+  // add their latencies)
+  const bool use_reg = total > kSmallLaunch;
+  for (auto& J : jobs)
+    if (use_reg && J.c >= 48 && J.c <= 64 && J.nprob > 0) nreg += J.nprob;
   if (total == 0) return;
   if (prof) {
     std::lock_guard<std::mutex> g(P.mu());
@@ -2335,7 +2339,7 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     J.flops = fl ? fl + done : nullptr;
     done += J.nprob;
     J.redo = nullptr;
-    if (J.c >= 48 && J.c <= 64) {
+    if (use_reg && J.c >= 48 && J.c <= 64) {
       J.redo = redo.get() + rdone;
       rdone += J.nprob;
       SJob R = J;
