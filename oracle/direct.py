@@ -30,16 +30,22 @@ def assemble(st) -> sp.csr_matrix:
     return A
 
 
+def block(st, i):
+    """Dense blocks D_i, E_i, F_i (s x s) of block row i of Eq. "system" (block = grid row)."""
+    s = st.nx
+    sl = slice(i * s, (i + 1) * s)
+    Di = np.diag(st.diag[sl]) + np.diag(st.west[sl][1:], -1) + np.diag(st.east[sl][:-1], 1)
+    return Di, np.diag(st.south[sl]), np.diag(st.north[sl])
+
+
 def blocks(st):
     """Dense blocks D_i (s x s), E_i, F_i (s x s) of Eq. "system" (block = grid row)."""
-    s, m = st.nx, st.ny
     D, E, F = [], [], []
-    for i in range(m):
-        sl = slice(i * s, (i + 1) * s)
-        Di = np.diag(st.diag[sl]) + np.diag(st.west[sl][1:], -1) + np.diag(st.east[sl][:-1], 1)
+    for i in range(st.ny):
+        Di, Ei, Fi = block(st, i)
         D.append(Di)
-        E.append(np.diag(st.south[sl]))
-        F.append(np.diag(st.north[sl]))
+        E.append(Ei)
+        F.append(Fi)
     return D, E, F
 
 
