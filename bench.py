@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", action="store_true",
                     help="print a per-stage timing table of the profiled step to stderr")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy 5 times (reference for the "
+                         "HBM byte counters of rocprofv3) and exit")
     ap.add_argument("--cpu-rows", type=int, default=8,
                     help="block rows of the operator the CPU oracle factors (bounded sample)")
     return ap.parse_args()
@@ -99,9 +102,9 @@ def dominant_kernel(acr, torch, op, b, args, precision):
 
 def traffic_per_launch(name):
     """HBM bytes per launch of `name` from the committed rocprofv3 counter runs
-    (profiles/traffic.json), if they were taken on the current kernel source."""
+    (profiles/hbm_traffic_varkappa1024_mixed.json), if they were taken on the current kernel source."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_varkappa1024_mixed.json")
     src = os.path.join(ROOT, "paper_1604_00617_amd", "csrc", "kernels.hip")
     try:
         with open(path) as f:
@@ -175,6 +178,15 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        x = torch.ones(256 * 2**20 // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 4, "copies": 5}), flush=True)
+        return
 
     import paper_1604_00617_amd as acr
     import workloads as W
