@@ -421,12 +421,29 @@ std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_option
     PhaseScope lvl("level", (int)f->lev.size());
     // X_k = T(D_k^{-1}) for even k
     stage_check(st, D, status.get(), "D", (int)f->lev.size());
+    bool closed = false;   // level 0: D_k tridiagonal, its inverse in closed form (exact rank 1)
     {
       PhaseScope ph("inverse");
-      hinv<T>(st, lv.X, HV<T>{&D, 2, 0}, lv.nreal, status.get());
+      if (diag && s <= 3072) {
+        std::vector<int> k1(L + 1, 1);
+        lv.X.alloc(st, lv.nreal, s, b, L, k1, false);
+        TriInvOut to;
+        for (int d = 1; d <= L; ++d) {
+          to.U[d] = lv.X.U[d].get();
+          to.V[d] = lv.X.V[d].get();
+          lv.X.kc[d] = 1;
+        }
+        DBuf<int> fb(1);
+        memset_async(fb.get(), 0, sizeof(int), st);
+        tridiag_inverse<T>(st, s, b, L, lv.nreal, 2, 0, op.diag, op.west, op.east, lv.X.lv.get(), to, fb.get());
+        int fbh = 0;
+        read_to_host(&fbh, fb.get(), sizeof(int), st);
+        closed = fbh == 0;
+      }
+      if (!closed) hinv<T>(st, lv.X, HV<T>{&D, 2, 0}, lv.nreal, status.get());
     }
     stage_check(st, lv.X, status.get(), "inv", (int)f->lev.size());
-    {
+    if (!closed) {   // the closed form is exact with rank-one blocks: T_eps leaves it unchanged
       PhaseScope ph("recompress X");
       recompress_multi<T>(st, {&lv.X}, eps, mr);
     }

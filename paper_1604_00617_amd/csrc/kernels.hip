@@ -1821,6 +1821,120 @@ __global__ void k_leaves_tridiag(int s, int b, int bmul, int boff, const double*
   }
 }
 
+// Inverse of a tridiagonal block in HODLR form.  With the pivots of the two
+// eliminations without pivoting, d_i (top down) and e_i (bottom up), the
+// inverse has diagonal g_i = 1 / (d_i + e_i - a_i), and every column z of it
+// satisfies z_i = rho_i z_(i+1) above its diagonal (rho_i = -b_i / d_i) and
+// z_i = tau_i z_(i-1) below (tau_i = -c_i / e_i).  Hence the leaves follow by
+// walking up and down each column from g_j, and the off-diagonal block of
+// clusters t (rows) and s (columns) is exactly rank one: for t above s,
+// U_t[i] = prod_(k=i..t1-1) rho_k and V_t[j] = g_j prod_(k=t1..j-1) rho_k
+// (t1 the first row of s); for t below s, U_t[i] = prod_(k=t0..i) tau_k and
+// V_t[j] = g_j prod_(k=j+1..t0-1) tau_k (t0 the first row of t).  All in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tridiag_inverse(int s, int b, int L, int bmul, int boff,
+                                                         const double* __restrict__ diag,
+                                                         const double* __restrict__ west,
+                                                         const double* __restrict__ east, T* __restrict__ lv,
+                                                         TriInvOut out, int* fallback) {
+  extern __shared__ unsigned char smem_raw[];
+  double* A = reinterpret_cast<double*>(smem_raw);   // a_i, then g_i
+  double* B = A + s;                                  // b_i, then rho_i
+  double* C = B + s;                                  // c_i, then tau_i
+  double* Dp = C + s;                                 // d_i
+  double* Ep = Dp + s;                                // e_i
+  __shared__ int bad;
+  const int m = blockIdx.x, tid = threadIdx.x;
+  const int blk = bmul * m + boff;
+  const double* dg = diag + (size_t)blk * s;
+  const double* we = west + (size_t)blk * s;
+  const double* ea = east + (size_t)blk * s;
+  if (tid == 0) bad = 0;
+  for (int i = tid; i < s; i += 256) {
+    A[i] = dg[i];
+    B[i] = i + 1 < s ? ea[i] : 0.0;
+    C[i] = i > 0 ? we[i] : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double d = A[0];
+    Dp[0] = d;
+    bool ok = d != 0.0 && isfinite(d);
+    for (int i = 1; i < s; ++i) {
+      d = A[i] - C[i] * B[i - 1] / d;
+      Dp[i] = d;
+      ok = ok && d != 0.0 && isfinite(d);
+    }
+    if (!ok) bad = 1;
+  } else if (tid == WAVE) {
+    double e = A[s - 1];
+    Ep[s - 1] = e;
+    bool ok = e != 0.0 && isfinite(e);
+    for (int i = s - 2; i >= 0; --i) {
+      e = A[i] - B[i] * C[i + 1] / e;
+      Ep[i] = e;
+      ok = ok && e != 0.0 && isfinite(e);
+    }
+    if (!ok) bad = 1;
+  }
+  __syncthreads();
+  if (bad) {
+    if (tid == 0) fallback[0] = 1;
+    return;
+  }
+  for (int i = tid; i < s; i += 256) {
+    const double gi = 1.0 / (Dp[i] + Ep[i] - A[i]);
+    const double ri = i + 1 < s ? -B[i] / Dp[i] : 0.0;
+    const double ti = i > 0 ? -C[i] / Ep[i] : 0.0;
+    A[i] = gi;
+    B[i] = ri;
+    C[i] = ti;
+  }
+  __syncthreads();
+  // leaves: column j of leaf l from its diagonal up and down
+  const int nleaf = 1 << L;
+  T* lvm = lv + (size_t)m * nleaf * b * b;
+  for (int j = tid; j < s; j += 256) {
+    const int l = j / b, j0 = l * b, jl = j - j0;
+    T* col = lvm + (size_t)l * b * b + (size_t)jl * b;
+    double v = A[j];
+    col[jl] = (T)v;
+    for (int i = j - 1; i >= j0; --i) {
+      v *= B[i];
+      col[i - j0] = (T)v;
+    }
+    v = A[j];
+    for (int i = j + 1; i < j0 + b; ++i) {
+      v *= C[i];
+      col[i - j0] = (T)v;
+    }
+  }
+  // rank-one factors of every depth: four serial passes per sibling pair
+  int ntask = 0;
+  for (int d = 1; d <= L; ++d) ntask += 4 << (d - 1);
+  for (int task = tid; task < ntask; task += 256) {
+    int d = 1, t = task;
+    while (t >= (4 << (d - 1))) { t -= 4 << (d - 1); ++d; }
+    const int pair = t >> 2, kind = t & 3;
+    const int sd = s >> d, t0 = 2 * pair * sd, t1 = t0 + sd;
+    T* Ud = static_cast<T*>(out.U[d]) + (size_t)m * s;
+    T* Vd = static_cast<T*>(out.V[d]) + (size_t)m * s;
+    if (kind == 0) {          // U of the upper block, rows of the first cluster
+      double u = 1.0;
+      for (int i = t1 - 1; i >= t0; --i) { u *= B[i]; Ud[i] = (T)u; }
+    } else if (kind == 1) {   // its V, rows of the second cluster
+      double q = 1.0;
+      for (int j = t1; j < t1 + sd; ++j) { Vd[j] = (T)(A[j] * q); q *= B[j]; }
+    } else if (kind == 2) {   // U of the lower block, rows of the second cluster
+      double u = 1.0;
+      for (int i = t1; i < t1 + sd; ++i) { u *= C[i]; Ud[i] = (T)u; }
+    } else {                  // its V, rows of the first cluster
+      double q = 1.0;
+      for (int j = t1 - 1; j >= t0; --j) { Vd[j] = (T)(A[j] * q); q *= C[j]; }
+    }
+  }
+}
+
 template <typename T>
 __global__ void k_rank1(int s, int sd, int bmul, int boff, const double* west, const double* east,
                         T* U, T* V) {
@@ -2560,6 +2674,18 @@ void build_leaves_tridiag(hipStream_t st, int s, int b, int nmat, int bmul, int 
 }
 
 template <typename T>
+void tridiag_inverse(hipStream_t st, int s, int b, int L, int nmat, int bmul, int boff, const double* diag,
+                     const double* west, const double* east, T* lv, const TriInvOut& out, int* fallback) {
+  if (nmat <= 0) return;
+  if (s > 3072 || L > kMvMaxDepth) fail(ACR_ERR_INTERNAL, "tridiagonal inverse: block too large");
+  const size_t dyn = 5 * (size_t)s * sizeof(double);
+  if (dyn > kMaxLds - 1024) allow_large_lds(reinterpret_cast<const void*>(k_tridiag_inverse<T>));
+  launch(st, KC_INVERSE, 0.0, (double)nmat * ((double)s * b + 2.0 * s * L) * sizeof(T),
+         KNAME_T(k_tridiag_inverse<T>), k_tridiag_inverse<T>, dim3(nmat), dim3(256), dyn, s, b, L, bmul, boff,
+         diag, west, east, lv, out, fallback);
+}
+
+template <typename T>
 void build_rank1_factors(hipStream_t st, int s, int sd, int nmat, int bmul, int boff,
                          const double* west, const double* east, T* U, T* V) {
   if (nmat <= 0) return;
@@ -2651,6 +2777,8 @@ void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
 }
 
 #define INST(T)                                                                                   \
+  template void tridiag_inverse<T>(hipStream_t, int, int, int, int, int, int, const double*, const double*, \
+                                   const double*, T*, const TriInvOut&, int*);                      \
   template void ggemm<T>(hipStream_t, std::vector<GJob>, const std::vector<GSeg>&);               \
   template void ghmv<T>(hipStream_t, int, int, int, int, std::vector<MVJob>, const std::vector<MVTerm>&); \
   template void gqr<T>(hipStream_t, std::vector<QJob>);                                           \

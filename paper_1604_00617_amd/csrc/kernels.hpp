@@ -132,6 +132,20 @@ template <typename T>
 void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs,
           const std::vector<MVTerm>& terms);
 
+// X_m = D^{-1} for the tridiagonal block D of block row bmul*m + boff of the
+// five-point operator (diag, west = D[i][i-1], east = D[i][i+1]), written
+// directly in HODLR form: leaves lv [nmat][2^L][b][b]; depth-d factors at
+// U[d] + m*s and V[d] + m*s (rank exactly 1).  *fallback is set to 1 when the
+// elimination without pivoting breaks down (a zero or non-finite pivot); the
+// caller then uses the general H-inverse.  Needs s <= 3072.
+struct TriInvOut {
+  void* U[kMvMaxDepth + 1] = {};
+  void* V[kMvMaxDepth + 1] = {};
+};
+template <typename T>
+void tridiag_inverse(hipStream_t st, int s, int b, int L, int nmat, int bmul, int boff, const double* diag,
+                     const double* west, const double* east, T* lv, const TriInvOut& out, int* fallback);
+
 template <typename T>
 void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs);
 template <typename T>
