@@ -535,7 +535,8 @@ void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double 
   std::vector<Item> items;
   for (HSet<T>* H : sets)
     for (int d = 1; d <= H->L; ++d) {
-      if (H->kc[d] == 0 || H->cnt == 0) continue;
+      // a block of rank <= 1 is already T_eps-truncated (up to a zero column)
+      if (H->kc[d] <= 1 || H->cnt == 0) continue;
       Item it;
       it.H = H; it.d = d; it.sd = H->sd(d); it.kcol = H->kc[d];
       it.c = std::min(it.sd, it.kcol); it.ncl = 1 << d; it.nprob = H->cnt * it.ncl;
