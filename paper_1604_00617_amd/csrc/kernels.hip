@@ -149,13 +149,13 @@ template <> struct Eps<double> { static constexpr double v = 1.1102230246251565e
 // each thread holds RM x RN outputs, operands are staged through LDS in TK
 // slices.
 template <typename T, int TM, int TN, int TK, int RM, int RN>
-__global__ __launch_bounds__((TM / RM) * (TN / RN)) void k_ggemm(const GJob* __restrict__ jobs,
+__device__ __forceinline__ void ggemm_body(const GJob* __restrict__ jobs,
                                                                 int njobs,
-                                                                const GSeg* __restrict__ segs) {
+                                                                const GSeg* __restrict__ segs, long long bid) {
   constexpr int TX = TM / RM, TY = TN / RN, NT = TX * TY;
   __shared__ T As[TK][TM + 1];
   __shared__ T Bs[TK][TN + 1];
-  const long long bid = blockIdx.x;
+  
   const GJob& J = jobs[job_of(jobs, njobs, bid)];
   const int tilesM = J.tilesM;
   const int tiles = tilesM * J.tilesN;
@@ -232,6 +232,12 @@ __global__ __launch_bounds__((TM / RM) * (TN / RN)) void k_ggemm(const GJob* __r
   }
 }
 
+template <typename T, int TM, int TN, int TK, int RM, int RN>
+__global__ __launch_bounds__((TM / RM) * (TN / RN)) void k_ggemm(const GJob* __restrict__ jobs, int njobs,
+    const GSeg* __restrict__ segs) {
+  ggemm_body<T, TM, TN, TK, RM, RN>(jobs, njobs, segs, blockIdx.x);
+}
+
 // Reduction GEMM C = sum_s scale_s A_s^T B_s with long K (A_s: K x M, B_s:
 // K x N, both column-major).  A workgroup owns an 8 x 8 output tile; its four
 // waves split K (wave w takes k = 64 w + lane, step 256), every lane keeps the
@@ -239,10 +245,10 @@ __global__ __launch_bounds__((TM / RM) * (TN / RN)) void k_ggemm(const GJob* __r
 // butterfly transpose-reduction leaves lane l with output l of its wave, and
 // the four waves are summed through LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_dot(const GJob* __restrict__ jobs, int njobs,
-                                                 const GSeg* __restrict__ segs) {
+__device__ __forceinline__ void gemm_dot_body(const GJob* __restrict__ jobs, int njobs,
+                                                 const GSeg* __restrict__ segs, long long bid) {
   __shared__ T red[4][64];
-  const long long bid = blockIdx.x;
+  
   const GJob& J = jobs[job_of(jobs, njobs, bid)];
   const int tilesM = J.tilesM;
   const int tiles = tilesM * J.tilesN;
@@ -304,17 +310,23 @@ __global__ __launch_bounds__(256) void k_gemm_dot(const GJob* __restrict__ jobs,
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_dot(const GJob* __restrict__ jobs, int njobs,
+    const GSeg* __restrict__ segs) {
+  gemm_dot_body<T>(jobs, njobs, segs, blockIdx.x);
+}
+
 // Short-K reduction GEMM C = sum_s scale_s A_s^T B_s with outputs up to
 // 16 x 16 per workgroup: 64-deep K slices of A^T and B are staged through LDS
 // with loads coalesced along K, then thread t accumulates output
 // (t % 16, t / 16) of the tile.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_small(const GJob* __restrict__ jobs, int njobs,
-                                                   const GSeg* __restrict__ segs) {
+__device__ __forceinline__ void gemm_small_body(const GJob* __restrict__ jobs, int njobs,
+                                                   const GSeg* __restrict__ segs, long long bid) {
   constexpr int KS = 64;
   __shared__ T As[KS][17];
   __shared__ T Bs[KS][17];
-  const long long bid = blockIdx.x;
+  
   const GJob& J = jobs[job_of(jobs, njobs, bid)];
   const int tilesM = J.tilesM;
   const int tiles = tilesM * J.tilesN;
@@ -356,6 +368,12 @@ __global__ __launch_bounds__(256) void k_gemm_small(const GJob* __restrict__ job
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_small(const GJob* __restrict__ jobs, int njobs,
+    const GSeg* __restrict__ segs) {
+  gemm_small_body<T>(jobs, njobs, segs, blockIdx.x);
+}
+
 // Row GEMM C = sum_s scale_s op(A_s) B_s for tall outputs with few columns
 // (N <= NMAX): a workgroup owns 64 output rows (one per lane).  The K
 // columns of all segments are taken as one flattened list and processed in
@@ -366,8 +384,8 @@ __global__ __launch_bounds__(256) void k_gemm_small(const GJob* __restrict__ job
 // instead of one per segment and K step.  The waves' partial sums are
 // combined through LDS at the end.
 template <typename T, int NMAX>
-__global__ __launch_bounds__(256) void k_gemm_rows(const GJob* __restrict__ jobs, int njobs,
-                                                  const GSeg* __restrict__ segs) {
+__device__ __forceinline__ void gemm_rows_body(const GJob* __restrict__ jobs, int njobs,
+                                                  const GSeg* __restrict__ segs, long long bid) {
   constexpr int UA = (sizeof(T) == 8 && NMAX >= 32) ? 16 : 32;   // A columns per wave and block
   constexpr int KB = 4 * UA;
   constexpr int BUF = (KB * NMAX > 3 * 64 * NMAX) ? KB * NMAX : 3 * 64 * NMAX;
@@ -381,7 +399,7 @@ __global__ __launch_bounds__(256) void k_gemm_rows(const GJob* __restrict__ jobs
   __shared__ const T* sB[kMaxSeg];
   __shared__ int sLda[kMaxSeg], sLdb[kMaxSeg], sTa[kMaxSeg], sK[kMaxSeg], sK0[kMaxSeg + 1];
   __shared__ T sSc[kMaxSeg];
-  const long long bid = blockIdx.x;
+  
   const GJob& J = jobs[job_of(jobs, njobs, bid)];
   const int tilesM = J.tilesM;
   const long long local = bid - J.block0;
@@ -473,6 +491,29 @@ __global__ __launch_bounds__(256) void k_gemm_rows(const GJob* __restrict__ jobs
       if (beta != T(0)) v = fma(beta, *cp, v);
       *cp = v;
     }
+  }
+}
+
+template <typename T, int NMAX>
+__global__ __launch_bounds__(256) void k_gemm_rows(const GJob* __restrict__ jobs, int njobs,
+    const GSeg* __restrict__ segs) {
+  gemm_rows_body<T, NMAX>(jobs, njobs, segs, blockIdx.x);
+}
+
+// Every GEMM kind in one launch (the job's kind selects the body; the narrow
+// tile shapes run as 64 x 64 tiles): used when a grouped GEMM is too small to
+// fill the GPU, where one launch per kind would only add their latencies.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_any(const GJob* __restrict__ jobs, int njobs,
+                                                 const GSeg* __restrict__ segs) {
+  const long long bid = blockIdx.x;
+  switch (jobs[job_of(jobs, njobs, bid)].kind) {
+    case 5: gemm_dot_body<T>(jobs, njobs, segs, bid); break;
+    case 6: gemm_rows_body<T, 16>(jobs, njobs, segs, bid); break;
+    case 7: gemm_rows_body<T, sizeof(T) == 4 ? 32 : 16>(jobs, njobs, segs, bid); break;
+    case 8: gemm_rows_body<T, 4>(jobs, njobs, segs, bid); break;
+    case 9: gemm_small_body<T>(jobs, njobs, segs, bid); break;
+    default: ggemm_body<T, 64, 64, 16, 4, 4>(jobs, njobs, segs, bid); break;
   }
 }
 
@@ -2184,7 +2225,51 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
     const double np = (double)J.nmat * J.ncl;
     fl[kind] += 2.0 * J.M * J.N * K * np;
     bytes[kind] += sizeof(T) * np * ((double)J.M * K + K * J.N + (double)J.M * J.N * (J.beta != 0.0 ? 2 : 1));
+    J.kind = kind;
     by[kind].push_back(J);
+  }
+  // A small call (few workgroups in all) runs as one launch of k_gemm_any,
+  // with the narrow tile shapes widened to 64 x 64.
+  {
+    int kinds = 0;
+    long long total = 0;
+    for (int kd = 0; kd < NK; ++kd) {
+      if (by[kd].empty()) continue;
+      ++kinds;
+      for (const auto& J : by[kd]) {
+        const long long tiles = kd >= 1 && kd <= 4 ? (long long)((J.M + 63) / 64) * ((J.N + 63) / 64)
+                                                   : (long long)J.tilesM * J.tilesN;
+        total += (long long)J.nmat * J.ncl * tiles;
+      }
+    }
+    if (kinds > 1 && total <= kSmallLaunch) {
+      std::vector<char> blob(segs.size() * sizeof(GSeg));
+      if (!segs.empty()) std::memcpy(blob.data(), segs.data(), blob.size());
+      std::vector<GJob> all;
+      double f = 0, by_ = 0;
+      long long b0 = 0;
+      for (int kd = 0; kd < NK; ++kd) {
+        f += fl[kd];
+        by_ += bytes[kd];
+        for (auto J : by[kd]) {
+          if (kd >= 1 && kd <= 4) {
+            J.kind = 0;
+            J.tilesM = (J.M + 63) / 64;
+            J.tilesN = (J.N + 63) / 64;
+          }
+          J.block0 = b0;
+          b0 += (long long)J.nmat * J.ncl * J.tilesM * J.tilesN;
+          all.push_back(J);
+        }
+      }
+      const size_t o = (blob.size() + 255) & ~size_t(255);
+      blob.resize(o + all.size() * sizeof(GJob));
+      std::memcpy(blob.data() + o, all.data(), all.size() * sizeof(GJob));
+      char* dev = static_cast<char*>(DescArena::get().put(blob.data(), blob.size(), st));
+      launch(st, KC_GEMM, f, by_, KNAME_T(k_gemm_any<T>), k_gemm_any<T>, dim3((unsigned)b0), dim3(256), 0,
+             reinterpret_cast<const GJob*>(dev + o), (int)all.size(), reinterpret_cast<const GSeg*>(dev));
+      return;
+    }
   }
   // one upload: segments, then the job lists of every kind
   std::vector<char> blob(segs.size() * sizeof(GSeg));

@@ -25,6 +25,7 @@ struct GJob {
   long long block0 = 0;
   int M = 0, N = 0, nmat = 0, ncl = 0;
   int tilesM = 0, tilesN = 0, seg0 = 0, nseg = 0;
+  int kind = 0, pad = 0;   // kernel kind (set by the launcher)
   double alpha = 1.0, beta = 0.0;
   BOp C;
 };
