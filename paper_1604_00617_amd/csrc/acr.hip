@@ -160,19 +160,7 @@ MVJob mv_job(int nmat, T* out, int omul, int ooff, int term0, int nterm, const T
 
 template <typename T>
 bool Factor<T>::fused_ok(int nrhs) const {
-  if (nrhs > 8 || L > kMvMaxDepth) return false;
-  const int NR = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8;
-  // a launch pairs at most two HODLR terms: their reduced values and row-block
-  // columns must fit the kernel's LDS tables (512 entries each)
-  auto fits = [&](const HSet<T>& H) {
-    int w = 0;
-    for (int d = 1; d <= H.L; ++d) w += H.kc[d];
-    return 2 * w * NR <= 512 && 2 * (H.b + w) <= 512;
-  };
-  if (!fits(Xlast)) return false;
-  for (const auto& l : lev)
-    if (!fits(l.X) || (!l.diag && (!fits(l.E) || !fits(l.F)))) return false;
-  return true;
+  return nrhs <= 8 && L <= kMvMaxDepth;
 }
 
 template <typename T>
@@ -181,7 +169,7 @@ void Factor<T>::solve(const double* B, double* Xout, int nrhs, hipStream_t st) {
   else solve_gemm(B, Xout, nrhs, st);
 }
 
-// Few right-hand sides: every step of a level is one fused matvec launch.
+// Few right-hand sides: every step of a level is one multi-term matvec.
 // U[l] holds the level-l unknowns with one zero pad block at each end.
 template <typename T>
 void Factor<T>::solve_fused(const double* B, double* Xout, int nrhs, hipStream_t st) {

@@ -24,11 +24,9 @@ constexpr int WAVE = 64;
 constexpr size_t kMaxLds = 65536;        // LDS budget of a workgroup that shares its CU
 constexpr size_t kMaxLdsLarge = 163840;  // all the LDS a gfx950 workgroup may hold
 constexpr size_t kMaxDynLarge = kMaxLdsLarge - 16384;   // dynamic part next to <= 16 KB static
-constexpr int kMvSlots = 512;        // reduced values per workgroup in the fused matvec
-constexpr int kMvCols = 512;
 constexpr long long kSmallLaunch = 1024;   // workgroups below which shape variants share a launch
 constexpr int kApplyRows = 8;        // Q application in registers: rows per lane (p <= 512)
-constexpr int kApplyCols = 8;        // and output columns per wave (t <= 32)         // row-block columns per workgroup in the fused matvec
+constexpr int kApplyCols = 8;        // and output columns per wave (t <= 32)
 
 template <typename T>
 __device__ __forceinline__ const T* optr(const BOp& o, int m, int c) {
@@ -517,191 +515,170 @@ __global__ __launch_bounds__(256) void k_gemm_any(const GJob* __restrict__ jobs,
   }
 }
 
-// ------------------------------------------------------ fused HODLR matvec
-// One workgroup per (job, matrix, leaf) computes the leaf's rows of
-//   beta * C0 + sum_t alpha_t op_t y_t.
-// A HODLR term adds the leaf block times y (leaf rows) and, for every depth
-// d, U_d[leaf rows] (V_d[sibling rows]^T y[sibling rows]) with the sibling of
-// the leaf's depth-d ancestor.  The small reductions are recomputed by each
-// leaf's workgroup (the sibling clusters of the depths are disjoint, so the
-// workgroup reads every V row of its matrix at most once); the leaves of one
-// matrix are placed on one XCD (block b runs on XCD b mod 8) to share its L2.
-// Phase 1: one wave per (term, depth) reduction, loads batched in registers;
-// meanwhile the other threads build a table of the row block's columns
-// (leaf columns and U columns of every term) and their multipliers.
-// Phase 2: every thread (row r, column slice) sums its columns, loads again
-// batched; the slices are combined through LDS.
+// ------------------------------------------------------------ HODLR matvec
+// out = beta * C0 + sum_t alpha_t op_t y_t for a batch of blocks, in two
+// launches.  k_hmv_reduce computes, for every HODLR term, matrix, depth d and
+// node tau of that depth, the projections V_d[tau]^T y[tau] (one wave per
+// node and chunk of up to 16 columns, written to a small buffer).
+// k_hmv_apply then gives every output row to one thread: the row of the leaf
+// times y on the leaf's rows, plus U_d[row] times the projection of the
+// sibling of the row's depth-d ancestor, for every depth; no barriers, the
+// leaf and U loads are independent and coalesced over the rows of a wave.
 template <typename T, int NR>
-__global__ __launch_bounds__(256) void k_hmv(const MVJob* __restrict__ jobs, int njobs,
-                                             const MVTerm* __restrict__ terms, int s, int b, int L,
-                                             int nrhs, long long nblocks) {
-  constexpr int CH = 16;                 // reduction columns per chunk
-  constexpr int RB = NR <= 1 ? 4 : NR <= 2 ? 2 : 1;   // rows per lane per batch
-  constexpr int CB = 32;                 // columns per thread per batch in phase 2
-  __shared__ T tv[kMvSlots];
-  __shared__ const T* ccol[kMvCols];
-  __shared__ T cval[kMvCols * NR];
-  __shared__ T lred[256 * NR];
-  const long long per = (nblocks + 7) / 8;
-  const long long lb = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (lb >= nblocks) return;   // uniform over the workgroup, before any barrier
-  const MVJob& J = jobs[job_of(jobs, njobs, lb)];
-  const int nleaf = 1 << L;
-  const long long local = lb - J.block0;
-  const int m = (int)(local / nleaf), l = (int)(local % nleaf);
-  const int tid = threadIdx.x, lane = tid % WAVE;
-  const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
-  const int nparts = 256 / b, r = tid % b, part = tid / b;
-  const bool rowt = part < nparts;
-  const int row0 = l * b;
-  const long long vs = (long long)s * nrhs;
-  if (J.nterm == 0) {   // pure copy (or zero) job: no reductions, no barriers
-    if (rowt && part == 0) {
-      T* out = static_cast<T*>(J.out) + (long long)(J.omul * m + J.ooff) * vs + row0 + r;
-      const T* c0 = J.C0 ? static_cast<const T*>(J.C0) + (long long)(J.cmul * m + J.coff) * vs + row0 + r : nullptr;
-      for (int q = 0; q < nrhs; ++q) out[(long long)q * s] = c0 ? (T)J.beta * c0[(long long)q * s] : T(0);
-    }
-    return;
+__global__ __launch_bounds__(256) void k_hmv_reduce(const MVRed* __restrict__ reds, int nred,
+                                                    const MVTerm* __restrict__ terms, int s, int nrhs,
+                                                    long long nunits, T* __restrict__ tbuf) {
+  constexpr int CH = 16;                               // columns per unit
+  constexpr int RB = NR <= 1 ? 4 : NR <= 2 ? 2 : 1;    // rows per lane per batch
+  const long long u = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  if (u >= nunits) return;   // uniform over the wave; no barriers below
+  const int lane = threadIdx.x % WAVE;
+  const MVRed& R = reds[job_of(reds, nred, u)];
+  const MVTerm& M = terms[R.term];
+  const long long local = u - R.block0;
+  const int m = (int)(local / R.upm);
+  int rem = (int)(local % R.upm), d = 1;
+  for (;; ++d) {
+    const int units = (1 << d) * ((M.kc[d] + CH - 1) / CH);
+    if (rem < units) break;
+    rem -= units;
   }
+  const int w = M.kc[d], nch = (w + CH - 1) / CH;
+  const int node = rem / nch, q0 = (rem % nch) * CH;
+  const int sd = s >> d;
+  const long long vs = (long long)s * nrhs;
+  const T* Vb = static_cast<const T*>(M.V[d]) + (long long)(M.mmul * m + M.moff) * M.k[d] * s +
+                (long long)q0 * s + (long long)node * sd;
+  const T* yb = static_cast<const T*>(M.y) + (long long)(M.ymul * m + M.yoff) * vs + (long long)node * sd;
+  T pr[CH][NR];
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+#pragma unroll
+    for (int q = 0; q < NR; ++q) pr[c][q] = T(0);
+  for (int i0 = 0; i0 < sd; i0 += WAVE * RB) {
+    T vv[RB][CH], yv[RB][NR];
+#pragma unroll
+    for (int e = 0; e < RB; ++e) {
+      const int i = i0 + e * WAVE + lane;
+      const bool ok = i < sd;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) yv[e][q] = (ok && q < nrhs) ? yb[i + (long long)q * s] : T(0);
+#pragma unroll
+      for (int c = 0; c < CH; ++c) vv[e][c] = (ok && q0 + c < w) ? Vb[i + (long long)c * s] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < RB; ++e)
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int q = 0; q < NR; ++q) pr[c][q] = fma(vv[e][c], yv[e][q], pr[c][q]);
+  }
+  // value v = c * NR + q (column q0 + c, right-hand side q) is stored by lane
+  // v mod 64
+  constexpr int NV = (CH * NR + WAVE - 1) / WAVE;
+  T mine[NV];
+#pragma unroll
+  for (int h = 0; h < NV; ++h) mine[h] = T(0);
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+    if (q0 + c < w)
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        const T tot = wave_sum(pr[c][q]);
+        if (lane == (c * NR + q) % WAVE) mine[(c * NR + q) / WAVE] = tot;
+      }
+  T* const to = tbuf + M.tbase + (long long)m * M.tstride + M.toff[d] + (long long)(node * w + q0) * NR;
+#pragma unroll
+  for (int h = 0; h < NV; ++h) {
+    const int v = h * WAVE + lane;
+    if (v < CH * NR && q0 + v / NR < w) to[v] = mine[h];
+  }
+}
+
+// One thread per output row (rows of all jobs' blocks numbered in order, a
+// job's rows from block0).  W64: every wave lies inside one leaf column block
+// (b and s multiples of 64), so the wave loads y on 64 leaf columns at once
+// and broadcasts each value with a lane read.
+template <typename T, int NR, bool W64>
+__global__ __launch_bounds__(64) void k_hmv_apply(const MVJob* __restrict__ jobs, int njobs,
+                                                  const MVTerm* __restrict__ terms, int s, int b, int L,
+                                                  int nrhs, long long nrows, const T* __restrict__ tbuf) {
+  const long long g = (long long)blockIdx.x * WAVE + threadIdx.x;
+  if (g >= nrows) return;   // never with W64: the rows fill whole waves
+  const int lane = threadIdx.x;
+  const MVJob& J = jobs[job_of(jobs, njobs, g)];
+  const long long local = g - J.block0;
+  const int m = (int)(local / s), row = (int)(local % s);
+  const int l = row / b, r = row % b, nleaf = 1 << L;
+  const long long vs = (long long)s * nrhs;
   T acc[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = T(0);
-  // C0 and the diagonal terms (loads issued first)
-  if (rowt && part == 0) {
-    if (J.C0) {
-      const T* c0 = static_cast<const T*>(J.C0) + (long long)(J.cmul * m + J.coff) * vs + row0 + r;
+  if (J.C0) {
+    const T* c0 = static_cast<const T*>(J.C0) + (long long)(J.cmul * m + J.coff) * vs + row;
 #pragma unroll
-      for (int q = 0; q < NR; ++q)
-        if (q < nrhs) acc[q] = (T)J.beta * c0[(long long)q * s];
-    }
-    for (int t = 0; t < J.nterm; ++t) {
-      const MVTerm& M = terms[J.term0 + t];
-      if (M.type != 1) continue;
-      const int mm = M.mmul * m + M.moff;
-      const T* y = static_cast<const T*>(M.y) + (long long)(M.ymul * m + M.yoff) * vs + row0 + r;
-      const T dv = (T)M.alpha * static_cast<const T*>(M.lv)[(long long)mm * s + row0 + r];
-#pragma unroll
-      for (int q = 0; q < NR; ++q)
-        if (q < nrhs) acc[q] = fma(dv, y[(long long)q * s], acc[q]);
-    }
+    for (int q = 0; q < NR; ++q)
+      if (q < nrhs) acc[q] = (T)J.beta * c0[(long long)q * s];
   }
-  // ---- phase 1
-  int npair = 0, ncol = 0, nslot = 0;
   for (int t = 0; t < J.nterm; ++t) {
     const MVTerm& M = terms[J.term0 + t];
-    if (M.type != 0) continue;
     const int mm = M.mmul * m + M.moff;
-    const T alpha = (T)M.alpha;
     const T* y = static_cast<const T*>(M.y) + (long long)(M.ymul * m + M.yoff) * vs;
-    int wsum = 0;
-    for (int d = 1; d <= L; ++d) {
-      const int w = M.kc[d];
-      if (w == 0) continue;
-      const int sd = s >> d;
-      const int sib = (l >> (L - d)) ^ 1;
-      if ((npair++ & 3) == wv) {
-        // this wave: tv[slot + q*NR + k] = V_d[sibling]^T y[sibling]
-        const T* Vb = static_cast<const T*>(M.V[d]) + (long long)mm * M.k[d] * s + (long long)sib * sd;
-        const T* yb = y + (long long)sib * sd;
-        const int slot = nslot + wsum * NR;
-        for (int q0 = 0; q0 < w; q0 += CH) {
-          T pr[CH][NR];
+    T ta[NR];
 #pragma unroll
-          for (int c = 0; c < CH; ++c)
+    for (int q = 0; q < NR; ++q) ta[q] = T(0);
+    if (M.type == 1) {   // diagonal
+      const T dv = static_cast<const T*>(M.lv)[(long long)mm * s + row];
 #pragma unroll
-            for (int q = 0; q < NR; ++q) pr[c][q] = T(0);
-          for (int i0 = 0; i0 < sd; i0 += WAVE * RB) {
-            T vv[RB][CH], yv[RB][NR];
+      for (int q = 0; q < NR; ++q)
+        if (q < nrhs) ta[q] = dv * y[row + (long long)q * s];
+    } else {
+      const T* lf = static_cast<const T*>(M.lv) + ((long long)mm * nleaf + l) * b * b + r;
+      const T* yl = y + (long long)l * b;
+      if (W64) {
+        for (int cb = 0; cb < b; cb += WAVE) {
+          T yw[NR];
 #pragma unroll
-            for (int u = 0; u < RB; ++u) {
-              const int i = i0 + u * WAVE + lane;
-              const bool ok = i < sd;
+          for (int q = 0; q < NR; ++q) yw[q] = q < nrhs ? yl[cb + lane + (long long)q * s] : T(0);
+#pragma unroll 16
+          for (int c = 0; c < WAVE; ++c) {
+            const T a = lf[(long long)(cb + c) * b];
 #pragma unroll
-              for (int q = 0; q < NR; ++q) yv[u][q] = (ok && q < nrhs) ? yb[i + (long long)q * s] : T(0);
-#pragma unroll
-              for (int c = 0; c < CH; ++c) vv[u][c] = (ok && q0 + c < w) ? Vb[i + (long long)(q0 + c) * s] : T(0);
-            }
-#pragma unroll
-            for (int u = 0; u < RB; ++u)
-#pragma unroll
-              for (int c = 0; c < CH; ++c)
-#pragma unroll
-                for (int q = 0; q < NR; ++q) pr[c][q] = fma(vv[u][c], yv[u][q], pr[c][q]);
-          }
-#pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            if (q0 + c < w) {
-#pragma unroll
-              for (int q = 0; q < NR; ++q) {
-                const T tot = wave_sum(pr[c][q]);
-                if (lane == 0) tv[slot + (q0 + c) * NR + q] = tot;
-              }
-            }
+            for (int q = 0; q < NR; ++q) ta[q] = fma(a, lane_read(yw[q], c), ta[q]);
           }
         }
+      } else {
+#pragma unroll 8
+        for (int c = 0; c < b; ++c) {
+          const T a = lf[(long long)c * b];
+#pragma unroll
+          for (int q = 0; q < NR; ++q)
+            if (q < nrhs) ta[q] = fma(a, yl[c + (long long)q * s], ta[q]);
+        }
       }
-      wsum += w;
-    }
-    // column table: leaf columns, then the U columns of every depth
-    const T* lf = static_cast<const T*>(M.lv) + ((long long)mm * nleaf + l) * b * b;
-    for (int e = tid; e < b; e += 256) ccol[ncol + e] = lf + (long long)e * b;
-    for (int e = tid; e < b * NR; e += 256) {
-      const int jc = e / NR, q = e % NR;
-      cval[(ncol + jc) * NR + q] = q < nrhs ? alpha * y[row0 + jc + (long long)q * s] : T(0);
-    }
-    for (int g = tid; g < wsum; g += 256) {
-      int d = 1, q = g;
-      while (q >= M.kc[d]) { q -= M.kc[d]; ++d; }
-      ccol[ncol + b + g] = static_cast<const T*>(M.U[d]) + (long long)mm * M.k[d] * s + (long long)q * s + row0;
-    }
-    ncol += b + wsum;
-    nslot += wsum * NR;
-  }
-  __syncthreads();
-  // multipliers of the U columns: alpha_t * reduced values
-  {
-    int c0 = 0, sl = 0;
-    for (int t = 0; t < J.nterm; ++t) {
-      const MVTerm& M = terms[J.term0 + t];
-      if (M.type != 0) continue;
-      int wsum = 0;
-      for (int d = 1; d <= L; ++d) wsum += M.kc[d];
-      const T alpha = (T)M.alpha;
-      for (int e = tid; e < wsum * NR; e += 256) cval[(c0 + b) * NR + e] = alpha * tv[sl + e];
-      c0 += b + wsum;
-      sl += wsum * NR;
-    }
-  }
-  __syncthreads();
-  // ---- phase 2: acc += sum over columns of column[r] * multiplier
-  if (rowt) {
-    for (int cb = part; cb < ncol; cb += nparts * CB) {
-      T a[CB];
+      const T* tb = tbuf + M.tbase + (long long)m * M.tstride;
+      for (int d = 1; d <= L; ++d) {
+        const int w = M.kc[d];
+        if (w == 0) continue;
+        const int sib = (l >> (L - d)) ^ 1;
+        const T* tv = tb + M.toff[d] + (long long)sib * w * NR;
+        const T* Ud = static_cast<const T*>(M.U[d]) + (long long)mm * M.k[d] * s + row;
+#pragma unroll 4
+        for (int q0 = 0; q0 < w; ++q0) {
+          const T uv = Ud[(long long)q0 * s];
 #pragma unroll
-      for (int u = 0; u < CB; ++u) {
-        const int c = cb + u * nparts;
-        a[u] = c < ncol ? ccol[c][r] : T(0);
-      }
-#pragma unroll
-      for (int u = 0; u < CB; ++u) {
-        const int c = cb + u * nparts;
-        if (c < ncol)
-#pragma unroll
-          for (int q = 0; q < NR; ++q) acc[q] = fma(a[u], cval[c * NR + q], acc[q]);
+          for (int q = 0; q < NR; ++q) ta[q] = fma(uv, tv[q0 * NR + q], ta[q]);
+        }
       }
     }
+    const T al = (T)M.alpha;
 #pragma unroll
-    for (int q = 0; q < NR; ++q) lred[(part * b + r) * NR + q] = acc[q];
+    for (int q = 0; q < NR; ++q) acc[q] = fma(al, ta[q], acc[q]);
   }
-  __syncthreads();
-  if (rowt && part == 0) {
-    T* out = static_cast<T*>(J.out) + (long long)(J.omul * m + J.ooff) * vs + row0 + r;
-    for (int q = 0; q < nrhs; ++q) {
-      T v = lred[r * NR + q];
-      for (int pp = 1; pp < nparts; ++pp) v += lred[(pp * b + r) * NR + q];
-      out[(long long)q * s] = v;
-    }
-  }
+  T* out = static_cast<T*>(J.out) + (long long)(J.omul * m + J.ooff) * vs + row;
+#pragma unroll
+  for (int q = 0; q < NR; ++q)
+    if (q < nrhs) out[(long long)q * s] = acc[q];
 }
 
 // ---------------------------------------------------------------- inverse
@@ -2655,57 +2632,94 @@ void gcopy(hipStream_t st, std::vector<CJob> jobs) {
 template <typename T>
 void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs,
           const std::vector<MVTerm>& terms) {
-  if (nrhs < 1 || nrhs > 8) fail(ACR_ERR_INTERNAL, "fused matvec takes 1..8 right-hand sides");
-  if (b < 1 || b > 256 || L > kMvMaxDepth || (b << L) != s) fail(ACR_ERR_INTERNAL, "fused matvec shape");
+  constexpr int CH = 16;
+  if (nrhs < 1 || nrhs > 8) fail(ACR_ERR_INTERNAL, "matvec takes 1..8 right-hand sides");
+  if (b < 1 || b > 256 || L > kMvMaxDepth || (b << L) != s) fail(ACR_ERR_INTERNAL, "matvec shape");
   const int NR = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8;
-  const int nleaf = 1 << L;
-  double fl = 0, by = 0;
-  for (const auto& J : jobs) {
-    int slots = 0, cols = 0;
-    for (int t = 0; t < J.nterm; ++t) {
-      const MVTerm& M = terms[J.term0 + t];
-      if (M.type != 0) continue;
-      cols += b;
-      for (int d = 1; d <= L; ++d) { slots += M.kc[d] * NR; cols += M.kc[d]; }
-    }
-    if (slots > kMvSlots || cols > kMvCols) fail(ACR_ERR_INTERNAL, "fused matvec: ranks too large");
-  }
+  // every job gets its own copies of its terms, with the places of their
+  // projections in the buffer
   std::vector<MVJob> use;
-  long long b0 = 0;
-  for (auto& J : jobs) {
+  std::vector<MVTerm> tm;
+  std::vector<MVRed> reds;
+  long long rows = 0, units = 0, tsize = 0;
+  double flr = 0, byr = 0, fla = 0, bya = 0;
+  for (auto J : jobs) {
     if (J.nmat <= 0) continue;
-    J.block0 = b0;
-    b0 += (long long)J.nmat * nleaf;
+    const int t0 = (int)tm.size();
     for (int t = 0; t < J.nterm; ++t) {
-      const MVTerm& M = terms[J.term0 + t];
-      double e = 0;
-      if (M.type == 1) {
-        e = s;
-      } else {
-        e = (double)s * b;
-        for (int d = 1; d <= L; ++d) e += 2.0 * s * M.kc[d];
+      MVTerm M = terms[J.term0 + t];
+      double e = s;
+      if (M.type == 0) {
+        int off = 0, upm = 0;
+        for (int d = 1; d <= L; ++d) {
+          if (M.kc[d] < 0 || M.kc[d] > M.k[d]) fail(ACR_ERR_INTERNAL, "matvec: rank above the allocation");
+          M.toff[d] = off;
+          off += (1 << d) * M.kc[d] * NR;
+          upm += (1 << d) * ((M.kc[d] + CH - 1) / CH);
+          flr += 2.0 * J.nmat * s * M.kc[d] * nrhs;
+          byr += (double)J.nmat * s * (M.kc[d] + (M.kc[d] ? nrhs : 0)) * sizeof(T);
+          e += (double)s * M.kc[d];
+        }
+        e += (double)s * (b - 1);
+        M.tbase = tsize;
+        M.tstride = off;
+        tsize += (long long)J.nmat * off;
+        if (upm > 0) {
+          MVRed R;
+          R.block0 = units;
+          R.term = (int)tm.size();
+          R.upm = upm;
+          reds.push_back(R);
+          units += (long long)J.nmat * upm;
+        }
       }
-      by += (double)J.nmat * (e + (double)s * nrhs) * sizeof(T);
-      fl += 2.0 * J.nmat * e * nrhs;
+      fla += 2.0 * J.nmat * e * nrhs;
+      bya += (double)J.nmat * (e + (double)s * nrhs) * sizeof(T);
+      tm.push_back(M);
     }
-    by += (double)J.nmat * s * nrhs * sizeof(T) * (J.C0 ? 2 : 1);
+    J.term0 = t0;
+    J.block0 = rows;
+    rows += (long long)J.nmat * s;
+    bya += (double)J.nmat * s * nrhs * sizeof(T) * (J.C0 ? 2 : 1);
     use.push_back(J);
   }
   if (use.empty()) return;
-  if (b0 > (1LL << 31) - 8) fail(ACR_ERR_INVALID_ARG, "fused matvec grid too large");
+  if ((rows + WAVE - 1) / WAVE > 0x7fffffffLL || (units + 3) / 4 > 0x7fffffffLL)
+    fail(ACR_ERR_INVALID_ARG, "matvec grid too large");
+  DBuf<T> tbuf((size_t)std::max<long long>(tsize, 1));
+  const MVTerm* dt = tm.empty() ? nullptr : upload(tm, st);
+  if (units > 0) {
+    const MVRed* dr = upload(reds, st);
+    const dim3 grid((unsigned)((units + 3) / 4));
+    const int nr = (int)reds.size();
+    auto go = [&](const char* name, auto kern) {
+      launch(st, KC_MATVEC, flr, byr, name, kern, grid, dim3(256), 0, dr, nr, dt, s, nrhs, units, tbuf.get());
+    };
+    switch (NR) {
+      case 1: go(KNAME_T(k_hmv_reduce<T, 1>), k_hmv_reduce<T, 1>); break;
+      case 2: go(KNAME_T(k_hmv_reduce<T, 2>), k_hmv_reduce<T, 2>); break;
+      case 4: go(KNAME_T(k_hmv_reduce<T, 4>), k_hmv_reduce<T, 4>); break;
+      default: go(KNAME_T(k_hmv_reduce<T, 8>), k_hmv_reduce<T, 8>); break;
+    }
+  }
   const MVJob* dj = upload(use, st);
-  const MVTerm* dt = terms.empty() ? nullptr : upload(terms, st);
-  const dim3 grid((unsigned)(8 * ((b0 + 7) / 8)));
+  const bool w64 = b % WAVE == 0;   // then s = b 2^L and the row count are multiples of 64
+  const dim3 grid((unsigned)((rows + WAVE - 1) / WAVE));
   const int nj = (int)use.size();
   auto go = [&](const char* name, auto kern) {
-    launch(st, KC_MATVEC, fl, by, name, kern, grid, dim3(256), 0, dj, nj, dt, s, b, L, nrhs, b0);
+    launch(st, KC_MATVEC, fla, bya, name, kern, grid, dim3(WAVE), 0, dj, nj, dt, s, b, L, nrhs, rows,
+           (const T*)tbuf.get());
   };
+#define ACR_HMV_APPLY(NRV)                                                                   \
+  if (w64) go(KNAME_T(k_hmv_apply<T, NRV, true>), k_hmv_apply<T, NRV, true>);              \
+  else go(KNAME_T(k_hmv_apply<T, NRV, false>), k_hmv_apply<T, NRV, false>);
   switch (NR) {
-    case 1: go(KNAME_T(k_hmv<T, 1>), k_hmv<T, 1>); break;
-    case 2: go(KNAME_T(k_hmv<T, 2>), k_hmv<T, 2>); break;
-    case 4: go(KNAME_T(k_hmv<T, 4>), k_hmv<T, 4>); break;
-    default: go(KNAME_T(k_hmv<T, 8>), k_hmv<T, 8>); break;
+    case 1: ACR_HMV_APPLY(1) break;
+    case 2: ACR_HMV_APPLY(2) break;
+    case 4: ACR_HMV_APPLY(4) break;
+    default: ACR_HMV_APPLY(8) break;
   }
+#undef ACR_HMV_APPLY
 }
 
 template <typename T>

@@ -101,11 +101,12 @@ struct CJob {
   long long sstride = 0, scl = 0;
 };
 
-// Fused multi-term HODLR matvec for a few right-hand sides (solve path):
+// Multi-term HODLR matvec for a few right-hand sides (solve path):
 //   out_m = beta * C0_m + sum_t alpha_t op_t(m) y_t(m)
 // with op_t a HODLR matrix of a set (all of one launch share s, b, L) or a
 // diagonal.  Vector blocks are s x nrhs, column-major, block stride s*nrhs;
-// block index of matrix m is mul*m + off for every operand.
+// block index of matrix m is mul*m + off for every operand.  The output may
+// not overlap any input.
 constexpr int kMvMaxDepth = 15;
 struct MVTerm {
   int type = 0;               // 0 HODLR, 1 diagonal
@@ -119,6 +120,15 @@ struct MVTerm {
   const void* V[kMvMaxDepth + 1] = {};
   int k[kMvMaxDepth + 1] = {};    // allocated columns per depth (matrix stride k*s)
   int kc[kMvMaxDepth + 1] = {};   // used columns
+  // set by the launcher: projections V_d[node]^T y[node] of matrix m at
+  // tbase + m * tstride + toff[d] + (node * kc[d] + column) * NR + rhs
+  long long tbase = 0;
+  int tstride = 0, pad2 = 0;
+  int toff[kMvMaxDepth + 1] = {};
+};
+struct MVRed {                    // projections of one term (launcher-internal)
+  long long block0 = 0;           // first wave
+  int term = 0, upm = 0;          // term index, waves per matrix
 };
 struct MVJob {
   long long block0 = 0;
