@@ -71,6 +71,11 @@ __device__ __forceinline__ double lane_read(double x, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, false);
+}
+
 // 64-bit lane move with DPP (out-of-range sources read the lane's own value).
 template <int CTRL>
 __device__ __forceinline__ unsigned long long dpp_mov_u64(unsigned long long x) {
@@ -119,10 +124,45 @@ __device__ __forceinline__ T wave_sum(T v) {
   return lane_read(v, 63);
 }
 
+// Sum within aligned groups of g lanes (g a power of two <= 64), returned to
+// every lane of the group: quad_perm swaps, then the half-row and row
+// mirrors (each step adds the partner half, so every lane of a group ends
+// with the same value); groups of 32 and 64 combine the four row totals
+// read as scalars.  Every lane of the wave must be active.
 template <typename T>
-__device__ __forceinline__ T group_sum(T v, int g) {   // sum within aligned groups of g lanes
-  for (int off = g / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+__device__ __forceinline__ T group_sum(T v, int g) {
+  if (g >= 2) v += dpp_mov<0xb1>(v);    // quad_perm [1,0,3,2]
+  if (g >= 4) v += dpp_mov<0x4e>(v);    // quad_perm [2,3,0,1]
+  if (g >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
+  if (g >= 16) v += dpp_mov<0x140>(v);  // row_mirror
+  if (g >= 32) {
+    const T r0 = lane_read(v, 0), r1 = lane_read(v, 16), r2 = lane_read(v, 32), r3 = lane_read(v, 48);
+    if (g == 32) v = (threadIdx.x % WAVE) < 32 ? r0 + r1 : r2 + r3;
+    else v = (r0 + r1) + (r2 + r3);
+  }
   return v;
+}
+
+// Largest value over the wave, ties to the smallest index; the pair is
+// returned to every lane.  Same DPP steps as group_sum.  Every lane of the
+// wave must be active.
+__device__ __forceinline__ void wave_argmax(double& best, int& bi) {
+  auto step = [&](double ob, int oi) {
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  };
+  step(dpp_mov<0xb1>(best), dpp_mov_i<0xb1>(bi));
+  step(dpp_mov<0x4e>(best), dpp_mov_i<0x4e>(bi));
+  step(dpp_mov<0x141>(best), dpp_mov_i<0x141>(bi));
+  step(dpp_mov<0x140>(best), dpp_mov_i<0x140>(bi));
+  double b0 = lane_read(best, 0);
+  int i0 = __builtin_amdgcn_readlane(bi, 0);
+  for (int r = 16; r < WAVE; r += 16) {
+    const double ob = lane_read(best, r);
+    const int oi = __builtin_amdgcn_readlane(bi, r);
+    if (ob > b0 || (ob == b0 && oi < i0)) { b0 = ob; i0 = oi; }
+  }
+  best = b0;
+  bi = i0;
 }
 
 // Block-wide sum over 256 threads (4 waves); every thread gets the result.
@@ -803,11 +843,7 @@ __global__ __launch_bounds__(256) void k_inverse(int n, const Tin* A, long long 
         const double v = fabs(W[(size_t)r * n2 + j]);
         if (v > best) { best = v; bi = r; }
       }
-      for (int off = WAVE / 2; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, WAVE);
-        const int oi = __shfl_xor(bi, off, WAVE);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
+      wave_argmax(best, bi);
       if (tid == 0) {
         piv = bi;
         pval = W[(size_t)bi * n2 + j];
@@ -869,11 +905,7 @@ __global__ __launch_bounds__(256) void k_inverse_lds(int n, const Tin* A, long l
         const double v = fabs(W[r * n + j]);
         if (v > best) { best = v; bi = r; }
       }
-      for (int off = WAVE / 2; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, WAVE);
-        const int oi = __shfl_xor(bi, off, WAVE);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
+      wave_argmax(best, bi);
       if (tid == 0) {
         piv = bi;
         perm[j] = bi;
@@ -1060,7 +1092,9 @@ __global__ __launch_bounds__(256) void k_grsvd_reg(const SJob* __restrict__ jobs
 #pragma unroll
   for (int i = 0; i < SV_TP; ++i) ssf += (double)x[i] * (double)x[i];
   const double negl2 = wave_sum(ssf) * Eps<T>::v * Eps<T>::v;
-  const double tol = 4.0 * Eps<T>::v;
+  // a pair counts as orthogonal once |cos| <= sqrt(c) u: rounding the rotated
+  // columns to the working precision leaves cosines of that size
+  const double tol = fmax(4.0, sqrt((double)c)) * Eps<T>::v;
   for (int sweep = 0; sweep < 60 && tp > 1; ++sweep) {
     int nrot = 0;
 #pragma unroll
@@ -1531,11 +1565,7 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
       int bi = j;
       for (int q = j + tid; q < c; q += WAVE)
         if (nrm[q] > best) { best = nrm[q]; bi = q; }
-      for (int off = WAVE / 2; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, WAVE);
-        const int oi = __shfl_xor(bi, off, WAVE);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
+      wave_argmax(best, bi);
       if (tid == 0) {
         if (j == 0) {
           // stop once the remaining columns are below 0.1 eps of the largest one
@@ -1614,7 +1644,9 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
     ssf += x * x;
   }
   const double negl2 = block_sum256(ssf, red) * Eps<T>::v * Eps<T>::v;
-  const double tol = 4.0 * Eps<T>::v;
+  // a pair counts as orthogonal once |cos| <= sqrt(c) u: rounding the rotated
+  // columns to the working precision leaves cosines of that size
+  const double tol = fmax(4.0, sqrt((double)c)) * Eps<T>::v;
   const int cp = (tp + 1) & ~1;
   const int npairs = cp / 2;
   int g = 256 / max(npairs, 1), gp = 1;
@@ -1692,8 +1724,11 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
     spos[q] = pos;
   }
   __syncthreads();
-  // U_K = Q_K [J_X; 0] with columns in sorted order; written to UK
-  T* Y = UK + (size_t)prob * c * c;
+  // U_K = Q_K [J_X; 0] with columns in sorted order, built in the work matrix
+  // X (free after the sort) when it is in LDS, else directly in UK.  Each wave
+  // owns its columns for every reflector, so the loop needs no barriers.
+  T* const Yg = UK + (size_t)prob * c * c;
+  T* const Y = Jb.lds ? X : Yg;
   for (int e = tid; e < c * c; e += 256) {
     const int r = e % c, q = e / c;    // q = source column (unsorted)
     T v = T(0);
@@ -1704,18 +1739,21 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
   __syncthreads();
   for (int j = tp - 1; j >= 0; --j) {
     const T tau = (T)taus[j];
-    if (tau != T(0)) {
-      const T* v = W + (size_t)j * c;
-      for (int q = wv; q < tp; q += 4) {
-        T* col = Y + (size_t)q * c;
-        T d = lane == 0 ? col[j] : T(0);
-        for (int r = j + 1 + lane; r < c; r += WAVE) d = fma(v[r], col[r], d);
-        d = wave_sum(d) * tau;
-        if (lane == 0) col[j] -= d;
-        for (int r = j + 1 + lane; r < c; r += WAVE) col[r] = fma(-d, v[r], col[r]);
-      }
+    if (tau == T(0)) continue;
+    const T* v = W + (size_t)j * c;
+    for (int q = wv; q < tp; q += 4) {
+      T* col = Y + (size_t)q * c;
+      const T cj = col[j];
+      T d = T(0);
+      for (int r = j + 1 + lane; r < c; r += WAVE) d = fma(v[r], col[r], d);
+      d = (cj + wave_sum(d)) * tau;
+      for (int r = j + 1 + lane; r < c; r += WAVE) col[r] = fma(-d, v[r], col[r]);
+      if (lane == 0) col[j] = cj - d;
     }
+  }
+  if (Jb.lds) {
     __syncthreads();
+    for (int e = tid; e < c * c; e += 256) Yg[e] = Y[e];
   }
   T* so = sig + (size_t)prob * c;
   for (int q = tid; q < c; q += 256) so[spos[q]] = snorm[q];
@@ -2119,10 +2157,10 @@ int pick_tile(int M, int N) {
 }
 
 // Let a kernel use more than 64 KB of dynamic LDS (once per kernel).
-void allow_large_lds(const void* kern) {
+void allow_large_lds(const void* kern, size_t dyn = kMaxDynLarge) {
   static std::vector<const void*> done;
   if (std::find(done.begin(), done.end(), kern) != done.end()) return;
-  ACR_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLarge));
+  ACR_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
   done.push_back(kern);
 }
 
@@ -2481,7 +2519,7 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
   // two work matrices in LDS: launch 0 holds the jobs that fit next to the
   // kernel's static arrays in 64 KB, launch 1 those that fit the full gfx950
   // workgroup LDS; larger cores work in global scratch.
-  constexpr size_t kStatic = 16384;
+  constexpr size_t kStatic = 16384;   // static LDS of k_grsvd (about 12.8 KB)
   std::vector<DBuf<T>> scratch;
   std::vector<SJob> use[2], reg;
   Profiler& P = Profiler::get();
@@ -2528,7 +2566,7 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     int g = 0;
     J.lds = 1;
     if (need + kStatic > kMaxLds) {
-      if (need <= kMaxDynLarge) g = 1;
+      if (need + kStatic <= kMaxLdsLarge) g = 1;
       else J.lds = 0;
     }
     if (J.lds) {
@@ -2551,7 +2589,7 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
   }
   for (int g = 0; g < 2; ++g) {
     if (use[g].empty()) continue;
-    if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_grsvd<T>));
+    if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_grsvd<T>), kMaxLdsLarge - kStatic);
     const SJob* dj = upload(use[g], st);
     const int nj = (int)use[g].size();
     launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd<T>), k_grsvd<T>, dim3((unsigned)b0[g]), dim3(256), dyn[g], dj,
