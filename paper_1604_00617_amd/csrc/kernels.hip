@@ -413,122 +413,72 @@ __global__ __launch_bounds__(256) void k_gemm_small(const GJob* __restrict__ job
 }
 
 // Row GEMM C = sum_s scale_s op(A_s) B_s for tall outputs with few columns
-// (N <= NMAX): a workgroup owns 64 output rows (one per lane).  The K
-// columns of all segments are taken as one flattened list and processed in
-// blocks of KB: per block, a column table (A column base, row stride, scale,
-// B row) is built in LDS, each wave issues the loads of its KB/4 A columns at
-// once, the B rows of the block are staged in LDS meanwhile, and the FMAs read
-// B as LDS broadcasts.  A workgroup so needs one memory round trip per block
-// instead of one per segment and K step.  The waves' partial sums are
-// combined through LDS at the end.
+// (N <= NMAX): every wave owns one tile of 64 output rows (one per lane) and
+// the whole K range, so the waves of a workgroup (four consecutive tiles of
+// the job) never wait for each other.  Per chunk of 32 columns of A a lane
+// issues its 32 loads at once; the matching rows of B are staged, scaled, in
+// the wave's own slice of LDS and read back as broadcasts.
 template <typename T, int NMAX>
 __device__ __forceinline__ void gemm_rows_body(const GJob* __restrict__ jobs, int njobs,
                                                   const GSeg* __restrict__ segs, long long bid) {
-  constexpr int UA = (sizeof(T) == 8 && NMAX >= 32) ? 16 : 32;   // A columns per wave and block
-  constexpr int KB = 4 * UA;
-  constexpr int BUF = (KB * NMAX > 3 * 64 * NMAX) ? KB * NMAX : 3 * 64 * NMAX;
-  __shared__ T buf[BUF];                 // B block [KB][NMAX], then the wave partial sums
-  __shared__ const T* cA[KB];
-  __shared__ const T* cB[KB];
-  __shared__ long long cRs[KB];
-  __shared__ int cLdb[KB];
-  __shared__ T cSc[KB];
-  __shared__ const T* sA[kMaxSeg];
-  __shared__ const T* sB[kMaxSeg];
-  __shared__ int sLda[kMaxSeg], sLdb[kMaxSeg], sTa[kMaxSeg], sK[kMaxSeg], sK0[kMaxSeg + 1];
-  __shared__ T sSc[kMaxSeg];
-  
+  constexpr int KC = 32;
+  __shared__ T bsh[4][KC * NMAX];
   const GJob& J = jobs[job_of(jobs, njobs, bid)];
-  const int tilesM = J.tilesM;
-  const long long local = bid - J.block0;
-  const int prob = (int)(local / tilesM);
-  const int tm = (int)(local % tilesM);
+  const int lane = threadIdx.x % WAVE;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const long long tile = (bid - J.block0) * 4 + wv;
+  if (tile >= (long long)J.nmat * J.ncl * J.tilesM) return;   // no barriers below
+  const int prob = (int)(tile / J.tilesM), tm = (int)(tile % J.tilesM);
   const int m = prob / J.ncl, c = prob % J.ncl;
-  const int M = J.M, N = J.N, nseg = J.nseg;
-  const int tid = threadIdx.x;
-  const int lane = tid % WAVE;
-  const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
+  const int M = J.M, N = J.N;
   const int i = tm * 64 + lane;
   const bool live = i < M;
-  if (tid < nseg) {
-    const GSeg& S = segs[J.seg0 + tid];
-    sA[tid] = optr<T>(S.A, m, c);
-    sB[tid] = optr<T>(S.B, m, c);
-    sLda[tid] = S.A.ld;
-    sLdb[tid] = S.B.ld;
-    sTa[tid] = S.A.trans;
-    sK[tid] = S.K;
-    sSc[tid] = (T)S.scale;
-  }
-  __syncthreads();
-  if (tid <= nseg) {
-    int k0 = 0;
-    for (int q = 0; q < tid; ++q) k0 += sK[q];
-    sK0[tid] = k0;
-  }
-  __syncthreads();
-  const int Ktot = sK0[nseg];
+  T* const bw = bsh[wv];
   T acc[NMAX];
 #pragma unroll
   for (int q = 0; q < NMAX; ++q) acc[q] = T(0);
-  for (int kb = 0; kb < Ktot; kb += KB) {
-    const int kcnt = min(KB, Ktot - kb);
-    if (tid < kcnt) {
-      const int k = kb + tid;
-      int sg = 0;
-      while (sg + 1 < nseg && sK0[sg + 1] <= k) ++sg;
-      const int ko = k - sK0[sg];
-      const long long lda = sLda[sg];
-      cA[tid] = sA[sg] + (sTa[sg] ? (long long)ko : ko * lda);
-      cRs[tid] = sTa[sg] ? lda : 1;
-      cSc[tid] = sSc[sg];
-      cB[tid] = sB[sg] + ko;
-      cLdb[tid] = sLdb[sg];
-    }
-    __syncthreads();
-    // this wave's A columns (all loads in flight together)
-    const int u0 = wv * UA;
-    T a[UA];
+  for (int sg = 0; sg < J.nseg; ++sg) {
+    const GSeg& S = segs[J.seg0 + sg];
+    const T* Ap = optr<T>(S.A, m, c);
+    const T* Bp = optr<T>(S.B, m, c);
+    const long long lda = S.A.ld, ldb = S.B.ld;
+    const bool ta = S.A.trans;
+    const T sc = (T)S.scale;
+    const int K = S.K;
+    const T* arow = ta ? Ap + (long long)i * lda : Ap + i;   // A(i, k) = arow[k * astep]
+    const long long astep = ta ? 1 : lda;
+    for (int k0 = 0; k0 < K; k0 += KC) {
+      const int kn = min(KC, K - k0);
+      T a[KC];
 #pragma unroll
-    for (int u = 0; u < UA; ++u) {
-      const int kk = u0 + u;
-      a[u] = (live && kk < kcnt) ? cA[kk][i * cRs[kk]] * cSc[kk] : T(0);
-    }
-    // B rows of the block
-    for (int e = tid; e < KB * N; e += 256) {
-      const int kk = e % KB, q = e / KB;
-      if (kk < kcnt) buf[kk * NMAX + q] = cB[kk][(long long)q * cLdb[kk]];
-    }
-    __syncthreads();
+      for (int u = 0; u < KC; ++u) a[u] = (live && u < kn) ? arow[(long long)(k0 + u) * astep] : T(0);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // earlier reads of bw are done
+      for (int e = lane; e < KC * NMAX; e += WAVE) {
+        const int kk = e / NMAX, q = e % NMAX;
+        bw[e] = (kk < kn && q < N) ? sc * Bp[(k0 + kk) + (long long)q * ldb] : T(0);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // bw visible to every lane
 #pragma unroll
-    for (int u = 0; u < UA; ++u) {
-      const int kk = u0 + u;
-      if (kk < kcnt) {
-        const T* br = buf + kk * NMAX;
+      for (int u = 0; u < KC; ++u) {
+        if (u < kn) {
+          const T* br = bw + u * NMAX;
 #pragma unroll
-        for (int q = 0; q < NMAX; ++q) acc[q] = fma(a[u], br[q], acc[q]);
+          for (int q = 0; q < NMAX; ++q) acc[q] = fma(a[u], br[q], acc[q]);
+        }
       }
     }
-    __syncthreads();
   }
-  if (wv > 0)
+  if (!live) return;
+  T* Cp = const_cast<T*>(optr<T>(J.C, m, c));
+  const long long ldc = J.C.ld;
+  const T alpha = (T)J.alpha, beta = (T)J.beta;
 #pragma unroll
-    for (int q = 0; q < NMAX; ++q) buf[((wv - 1) * NMAX + q) * 64 + lane] = acc[q];
-  __syncthreads();
-  if (wv == 0 && live) {
-    T* Cp = const_cast<T*>(optr<T>(J.C, m, c));
-    const int ldc = J.C.ld;
-    const T alpha = (T)J.alpha, beta = (T)J.beta;
-#pragma unroll
-    for (int q = 0; q < NMAX; ++q) {
-      if (q >= N) break;
-      const T v0 = acc[q] + buf[(0 * NMAX + q) * 64 + lane] + buf[(1 * NMAX + q) * 64 + lane] +
-                   buf[(2 * NMAX + q) * 64 + lane];
-      T* cp = Cp + i + (long long)q * ldc;
-      T v = alpha * v0;
-      if (beta != T(0)) v = fma(beta, *cp, v);
-      *cp = v;
-    }
+  for (int q = 0; q < NMAX; ++q) {
+    if (q >= N) break;
+    T* cp = Cp + i + (long long)q * ldc;
+    T v = alpha * acc[q];
+    if (beta != T(0)) v = fma(beta, *cp, v);
+    *cp = v;
   }
 }
 
@@ -2201,6 +2151,13 @@ const J* upload(const std::vector<J>& v, hipStream_t st) {
 
 }  // namespace
 
+// Workgroups of a grouped GEMM job: one per output tile, except for the row
+// kernel (kinds 6..8), whose workgroups take four 64-row tiles.
+long long gjob_blocks(const GJob& J) {
+  const long long t = (long long)J.nmat * J.ncl * J.tilesM * J.tilesN;
+  return J.kind >= 6 && J.kind <= 8 ? (t + 3) / 4 : t;
+}
+
 // Kernel kinds of the grouped GEMM: 0..4 = tile shapes of k_ggemm,
 // 5 = k_gemm_dot (long-K reductions A^T B with small outputs), 6..8 =
 // k_gemm_rows with 16 / 32 / 4 columns, 9 = k_gemm_small (short-K reductions).
@@ -2252,9 +2209,8 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
       if (by[kd].empty()) continue;
       ++kinds;
       for (const auto& J : by[kd]) {
-        const long long tiles = kd >= 1 && kd <= 4 ? (long long)((J.M + 63) / 64) * ((J.N + 63) / 64)
-                                                   : (long long)J.tilesM * J.tilesN;
-        total += (long long)J.nmat * J.ncl * tiles;
+        total += kd >= 1 && kd <= 4 ? (long long)J.nmat * J.ncl * ((J.M + 63) / 64) * ((J.N + 63) / 64)
+                                    : gjob_blocks(J);
       }
     }
     if (kinds > 1 && total <= kSmallLaunch) {
@@ -2273,7 +2229,7 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
             J.tilesN = (J.N + 63) / 64;
           }
           J.block0 = b0;
-          b0 += (long long)J.nmat * J.ncl * J.tilesM * J.tilesN;
+          b0 += gjob_blocks(J);
           all.push_back(J);
         }
       }
@@ -2295,7 +2251,7 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
     long long b0 = 0;
     for (auto& J : by[kd]) {
       J.block0 = b0;
-      b0 += (long long)J.nmat * J.ncl * J.tilesM * J.tilesN;
+      b0 += gjob_blocks(J);
     }
     if (b0 > 0x7fffffffLL) fail(ACR_ERR_INVALID_ARG, "grouped GEMM grid too large");
     nblk[kd] = b0;
