@@ -90,11 +90,14 @@ def dominant_kernel(acr, torch, op, b, args, precision):
         for stage, ms in sorted(by_stage.items(), key=lambda kv: -kv[1]):
             print(f"[stage] {stage:24s} {ms:8.3f} ms", file=sys.stderr)
         for stage, level, cls, n, ms, fl, by in sorted(rep["stages"], key=lambda r: -r[4])[:80]:
-            print(f"[stage-level] {stage:24s} L{level:<3d} {cls:8s} {n:5d} {ms:8.3f} ms", file=sys.stderr)
+            print(f"[stage-level] {stage:24s} L{level:<3d} {cls:8s} {n:5d} {ms:8.3f} ms {by / ms / 1e6:8.1f} GB/s",
+                  file=sys.stderr)
         for name, cls, n, ms, fl, by in sorted(rep["kernels"], key=lambda r: -r[3]):
-            print(f"[kernel] {name:40s} {cls:8s} {n:5d} {ms:8.3f} ms", file=sys.stderr)
+            print(f"[kernel] {name:40s} {cls:8s} {n:5d} {ms:8.3f} ms {by / ms / 1e6:8.1f} GB/s {fl / ms / 1e9:8.2f} TFLOP/s",
+                  file=sys.stderr)
         for stage, name, n, ms, fl, by in sorted(rep.get("stage_kernels", []), key=lambda r: -r[3])[:40]:
-            print(f"[stage-kernel] {stage:24s} {name:40s} {n:5d} {ms:8.3f} ms", file=sys.stderr)
+            print(f"[stage-kernel] {stage:24s} {name:40s} {n:5d} {ms:8.3f} ms {by / ms / 1e6:8.1f} GB/s",
+                  file=sys.stderr)
     acr.acr_profile_start([])
     name, cls = max(rep["kernels"], key=lambda r: r[3])[:2]
     return name, cls, table

@@ -1752,8 +1752,11 @@ __global__ void k_gmax(const MJob* __restrict__ jobs) {
 
 constexpr int kCopyChunk = 2048;
 
+// A workgroup copies one chunk of kCopyChunk elements of one matrix; every
+// thread issues its kCopyChunk / 256 loads before its stores.
 template <typename T>
-__global__ void k_gcopy(const CJob* __restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(256) void k_gcopy(const CJob* __restrict__ jobs, int njobs) {
+  constexpr int PER = kCopyChunk / 256;
   const CJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
   const long long local = blockIdx.x - Jb.block0;
   const int chunk = (int)(local % Jb.chunks);
@@ -1765,16 +1768,26 @@ __global__ void k_gcopy(const CJob* __restrict__ jobs, int njobs) {
   const T* sc = Jb.scale ? static_cast<const T*>(Jb.scale) + (long long)(Jb.smul * m + Jb.soff) * Jb.sstride +
                                (long long)c * Jb.scl
                          : nullptr;
-  const int rows = Jb.rows;
-  const long long n = (long long)rows * Jb.cols;
-  const long long e0 = (long long)chunk * kCopyChunk, e1 = min(n, e0 + kCopyChunk);
+  const int rows = Jb.rows, n = rows * Jb.cols, e0 = chunk * kCopyChunk + (int)threadIdx.x;
   const T alpha = (T)Jb.alpha;
-  for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const int r = (int)(e % rows), q = (int)(e / rows);
-    T v = alpha * sp[r + (long long)q * src.ld];
-    if (sc) v *= sc[Jb.sside ? q : r];
-    T* d = dp + r + (long long)q * dst.ld;
-    *d = Jb.accumulate ? *d + v : v;
+  T v[PER];
+  int rr[PER], qq[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = e0 + u * 256;
+    rr[u] = e % rows;
+    qq[u] = e / rows;
+    v[u] = e < n ? alpha * sp[rr[u] + (long long)qq[u] * src.ld] : T(0);
+  }
+  if (sc)
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+      if (e0 + u * 256 < n) v[u] *= sc[Jb.sside ? qq[u] : rr[u]];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    if (e0 + u * 256 >= n) break;
+    T* d = dp + rr[u] + (long long)qq[u] * dst.ld;
+    *d = Jb.accumulate ? *d + v[u] : v[u];
   }
 }
 
@@ -2611,6 +2624,7 @@ void gcopy(hipStream_t st, std::vector<CJob> jobs) {
   for (auto& J : jobs) {
     if (J.rows <= 0 || J.cols <= 0 || J.nmat <= 0 || J.ncl <= 0) continue;
     const long long n = (long long)J.rows * J.cols;
+    if (n > 0x7fffffffLL - kCopyChunk) fail(ACR_ERR_INVALID_ARG, "grouped copy: matrix too large");
     J.chunks = (int)((n + kCopyChunk - 1) / kCopyChunk);
     J.block0 = b0;
     b0 += (long long)J.nmat * J.ncl * J.chunks;
