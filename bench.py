@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 5 times (reference for the "
                          "HBM byte counters of rocprofv3) and exit")
-    ap.add_argument("--cpu-rows", type=int, default=8,
+    ap.add_argument("--cpu-rows", type=int, default=16,
                     help="block rows of the operator the CPU oracle factors (bounded sample)")
     return ap.parse_args()
 

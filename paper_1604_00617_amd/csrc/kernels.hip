@@ -1452,6 +1452,17 @@ __global__ __launch_bounds__(256) void k_gapply_q(const AJob* __restrict__ jobs,
   }
 }
 
+// Partner of index i in round rnd of the round-robin ordering of cp (even)
+// indices (index 0 stays, the others rotate through cp - 1 places); the
+// pairs of a round are those of the one-sided Jacobi loop of k_grsvd.
+__device__ __forceinline__ int rr_partner(int i, int rnd, int cp) {
+  const int m = cp - 1;
+  if (i == 0) return 1 + (rnd + m - 1) % m;
+  const int a = i - 1, r1 = (rnd + m - 1) % m;
+  if (a == r1) return 0;
+  return 1 + ((2 * r1 - a) % m + m) % m;
+}
+
 // ------------------------------------------------ rank-revealing SVD
 // Rank-revealing SVD of a recompression core K (c x c, column-major, used as
 // scratch in place), preconditioned one-sided Jacobi:
@@ -1475,6 +1486,9 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
   __shared__ int s_piv, s_stop, nrot;
   __shared__ double s_delta2, s_v0;
   __shared__ T s_beta;
+  __shared__ double gA[256], gB[256], vA[256], vB[256];   // FP32 cores, t' <= 16: Gram matrix and rotations
+  __shared__ double rc[16], rs[16], gdiag[16];
+  __shared__ int rp[16], gflag;
   const SJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
   const int prob = (int)(blockIdx.x - Jb.block0);
   if (Jb.redo && Jb.redo[prob] == 0) return;   // finished by k_grsvd_reg
@@ -1603,7 +1617,81 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
   while (gp * 2 <= g && gp * 2 <= WAVE) gp *= 2;
   g = gp;
   const int slots = 256 / g, gl = tid % g;
-  for (int sweep = 0; sweep < 60 && tp > 1; ++sweep) {
+  // FP32 cores with t' <= 16: the same rotations applied to the Gram matrix
+  // X^T X, formed and rotated in FP64 (one thread per entry), which needs no
+  // cross-lane sums.  FP64 keeps the smallest retained s_i^2 ~ (eps s_1)^2
+  // to a relative 1e-4 and more, ample for the FP32 truncation.
+  const bool gram = sizeof(T) == 4 && tp > 1 && tp <= 16;
+  if (gram) {
+    const int gi = tid / 16, gk = tid % 16;
+    const bool ent = gi < tp && gk < tp;
+    if (ent) {
+      const T* xi = X + (size_t)gi * c;
+      const T* xk = X + (size_t)gk * c;
+      double sacc = 0.0;
+      for (int q = 0; q < c; ++q) sacc = fma((double)xi[q], (double)xk[q], sacc);
+      gA[tid] = sacc;
+      vA[tid] = gi == gk ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    double* G = gA;
+    double* Gn = gB;
+    double* V = vA;
+    double* Vn = vB;
+    int nsw = 0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      ++nsw;
+      if (tid == 0) gflag = 0;
+      for (int rnd = 0; rnd < cp - 1; ++rnd) {
+        if (tid < 16) {   // one wave: the rotation of every index's pair
+          double cv = 1.0, sv = 0.0;
+          int px = tid;
+          if (tid < tp) {
+            const int k = rr_partner(tid, rnd, cp);
+            if (k < tp) {
+              px = k;
+              const int lo = min(tid, k), hi = max(tid, k);
+              const double al = G[lo * 17], be = G[hi * 17], ga = G[lo * 16 + hi];
+              if (fabs(ga) > tol * sqrt(al * be) && fmax(al, be) > negl2) {
+                const double zeta = (be - al) / (2.0 * ga);
+                const double az = fabs(zeta);
+                double t = (az > 1e15) ? 0.5 / az : 1.0 / (az + sqrt(1.0 + az * az));
+                t = copysign(t, zeta);
+                const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                cv = cs;
+                sv = tid == lo ? -sn : sn;   // new column x = cv x + sv (partner column)
+                gflag = 1;
+              }
+            }
+          }
+          rc[tid] = cv;
+          rs[tid] = sv;
+          rp[tid] = px;
+        }
+        __syncthreads();
+        if (ent) {   // G <- R^T G R, V <- V R
+          const int pi = rp[gi], pk = rp[gk];
+          const double ai = rc[gi], bi = rs[gi], ak = rc[gk], bk = rs[gk];
+          Gn[tid] = ai * (ak * G[gi * 16 + gk] + bk * G[gi * 16 + pk]) +
+                    bi * (ak * G[pi * 16 + gk] + bk * G[pi * 16 + pk]);
+          Vn[tid] = ak * V[gi * 16 + gk] + bk * V[gi * 16 + pk];
+        }
+        __syncthreads();
+        double* tg = G; G = Gn; Gn = tg;
+        double* tv = V; V = Vn; Vn = tv;
+      }
+      if (!gflag) break;
+      __syncthreads();   // every thread has read gflag before it is reset
+    }
+    if (tid < tp) gdiag[tid] = G[tid * 17];
+    for (int e = tid; e < tp * tp; e += 256) {
+      const int r = e % tp, i = e / tp;
+      J[r + (size_t)i * c] = (T)V[r * 16 + i];
+    }
+    fl += 2.0 * c * tp * tp + nsw * 12.0 * (double)tp * tp * (tp - 1);
+    __syncthreads();
+  }
+  for (int sweep = 0; sweep < 60 && tp > 1 && !gram; ++sweep) {
     if (tid == 0) nrot = 0;
     __syncthreads();
     for (int rnd = 0; rnd < cp - 1; ++rnd) {
@@ -1661,8 +1749,12 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
   for (int q = tid; q < c; q += 256) {
     double s2 = 0.0;
     if (q < tp) {
-      const T* xq = X + (size_t)q * c;
-      for (int r = 0; r < c; ++r) s2 += (double)xq[r] * (double)xq[r];
+      if (gram) {
+        s2 = fmax(gdiag[q], 0.0);
+      } else {
+        const T* xq = X + (size_t)q * c;
+        for (int r = 0; r < c; ++r) s2 += (double)xq[r] * (double)xq[r];
+      }
     }
     snorm[q] = (T)sqrt(s2);
   }
@@ -2488,7 +2580,7 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
   // two work matrices in LDS: launch 0 holds the jobs that fit next to the
   // kernel's static arrays in 64 KB, launch 1 those that fit the full gfx950
   // workgroup LDS; larger cores work in global scratch.
-  constexpr size_t kStatic = 16384;   // static LDS of k_grsvd (about 12.8 KB)
+  constexpr size_t kStatic = 21504;   // static LDS of k_grsvd (21000 bytes in FP32)
   std::vector<DBuf<T>> scratch;
   std::vector<SJob> use[2], reg;
   Profiler& P = Profiler::get();
