@@ -89,6 +89,12 @@ def dominant_kernel(acr, torch, op, b, args, precision):
             by_stage[stage] = by_stage.get(stage, 0.0) + ms
         for stage, ms in sorted(by_stage.items(), key=lambda kv: -kv[1]):
             print(f"[stage] {stage:24s} {ms:8.3f} ms", file=sys.stderr)
+        by_level = {}
+        for stage, level, cls, n, ms, fl, by in rep["stages"]:
+            cnt, tot = by_level.get(level, (0, 0.0))
+            by_level[level] = (cnt + n, tot + ms)
+        for level, (cnt, ms) in sorted(by_level.items()):
+            print(f"[level] L{level:<3d} {cnt:6d} launches {ms:8.3f} ms", file=sys.stderr)
         for stage, level, cls, n, ms, fl, by in sorted(rep["stages"], key=lambda r: -r[4])[:80]:
             print(f"[stage-level] {stage:24s} L{level:<3d} {cls:8s} {n:5d} {ms:8.3f} ms {by / ms / 1e6:8.1f} GB/s",
                   file=sys.stderr)
