@@ -50,9 +50,10 @@ def parse():
     return ap.parse_args()
 
 
-def run_steps(acr, torch, op, b, args, precision, steps, profile_cls=None):
-    """Run `steps` factor + refined-solve steps; returns (ms/step, iters, relres, per-kernel
-    timing rows of the launches of class `profile_cls`, timed with HIP events)."""
+def run_steps(acr, torch, op, b, args, precision, steps, profile_cls=None, krylov=False):
+    """Run `steps` factor + refined-solve steps (restarted FGMRES with the factor as right
+    preconditioner when `krylov`); returns (ms/step, preconditioner applications, relres,
+    per-kernel timing rows of the launches of class `profile_cls`, timed with HIP events)."""
     its = rel = None
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -62,7 +63,10 @@ def run_steps(acr, torch, op, b, args, precision, steps, profile_cls=None):
     start.record()
     for _ in range(steps):
         h = acr.acr_factor(op, args.leaf, args.eps, precision)
-        x, its, rel = acr.acr_solve_refined(h, op, b, tol=args.tol, maxit=50)
+        if krylov:
+            x, its, rel = acr.acr_solve_krylov(h, op, b, tol=args.tol, maxit=50, restart=20)
+        else:
+            x, its, rel = acr.acr_solve_refined(h, op, b, tol=args.tol, maxit=50)
         acr.acr_destroy(h)
     stop.record()
     torch.cuda.synchronize()
@@ -241,6 +245,12 @@ def main():
         "roofline": roofline(krow, "mixed"),
         "kernel_classes_ms": {k: round(v["total_ms"], 3) for k, v in table.items()},
     }
+    # the same step with FGMRES (ACR as right preconditioner, FP64 Krylov vectors) in
+    # place of stationary refinement
+    run_steps(acr, torch, op, b, args, "mixed", 1, krylov=True)
+    msk, itsk, relk, _ = run_steps(acr, torch, op, b, args, "mixed", args.steps, krylov=True)
+    out["mixed_fgmres"] = {"value": st.n / (msk / 1e3), "ms_per_step": msk, "preconditioner_applications": itsk,
+                           "relres": relk}
     if not args.no_fp64:
         run_steps(acr, torch, op, b, args, "fp64", 1)
         ms64, its64, rel64, _ = run_steps(acr, torch, op, b, args, "fp64", args.steps)

@@ -21,7 +21,8 @@
  *  - Vectors are FP64, column-major N x nrhs with leading dimension N.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
  *    on it; entry points that must read device results (acr_factor,
- *    acr_solve_refined) synchronise that stream before returning.
+ *    acr_solve_refined, acr_solve_krylov) synchronise that stream before
+ *    returning.
  *  - Every entry point returns an acr_status; on error no output is valid and
  *    acr_last_error() describes the failure (thread-local text).
  *  - The library allocates its own device memory (factor storage and
@@ -128,6 +129,24 @@ acr_status acr_solve(acr_handle h, const double* B, double* X, int32_t nrhs, voi
 acr_status acr_solve_refined(acr_handle h, const acr_operator* op, const double* B, double* X,
                              int32_t nrhs, double tol, int32_t maxit, int32_t* iters,
                              double* relres, void* stream);
+
+/* Restarted flexible GMRES, right-preconditioned by the ACR factor (ACR as
+ * a preconditioner of tunable accuracy, Section 4, closing paragraph; the
+ * Krylov alternative to acr_solve_refined where its contraction is slow or
+ * fails): per column b of B, x_0 = 0; each restart cycle builds up to
+ * `restart` (1..64) FP64 basis vectors v_j (classical Gram-Schmidt applied
+ * twice), z_j = M^{-1} v_j with acr_solve's pass, and sets x += Z y with y
+ * the least-squares solution of the Hessenberg system (Givens rotations on
+ * the host).  Stops when the true relative residual ||b - A x||/||b|| <= tol
+ * or after maxit applications of M^{-1}.  op must be the factored operator.
+ * B, X: N x nrhs FP64 column-major (ld = N); X must not alias B.  iters,
+ * relres: host outputs (may be NULL): the largest preconditioner count and
+ * relative residual over the columns.  Workspace: (2 restart + 3) N doubles.
+ * ACR_ERR_NOT_CONVERGED (X holds the last iterate) if tol is not reached.
+ * Synchronises `stream` (the small Hessenberg problem lives on the host). */
+acr_status acr_solve_krylov(acr_handle h, const acr_operator* op, const double* B, double* X,
+                            int32_t nrhs, double tol, int32_t maxit, int32_t restart,
+                            int32_t* iters, double* relres, void* stream);
 
 /* R = B - A X in FP64 for the stencil operator (N x nrhs, ld = N). */
 acr_status acr_residual(const acr_operator* op, const double* X, const double* B, double* R,

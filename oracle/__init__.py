@@ -14,6 +14,8 @@ Hierarchically Low-rank Schur Complements", arXiv:1604.00617):
                  then compress" (formatted arithmetic with best truncation).
 * ``refine``  -- iterative refinement with an FP64 residual (ACR used as a
                  preconditioner, Section 4 closing paragraph).
+* ``krylov``  -- restarted flexible GMRES right-preconditioned by any
+                 approximate inverse (the Krylov form of the same use).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  It shares no code with the GPU path and

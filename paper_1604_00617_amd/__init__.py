@@ -70,6 +70,8 @@ def load(path: str = LIB_PATH):
     lib.acr_solve.argtypes = [P, P, P, I32, P]
     lib.acr_solve_refined.argtypes = [P, ctypes.POINTER(_Operator), P, P, I32, D, I32,
                                       ctypes.POINTER(I32), ctypes.POINTER(D), P]
+    lib.acr_solve_krylov.argtypes = [P, ctypes.POINTER(_Operator), P, P, I32, D, I32, I32,
+                                     ctypes.POINTER(I32), ctypes.POINTER(D), P]
     lib.acr_residual.argtypes = [ctypes.POINTER(_Operator), P, P, P, I32, P]
     lib.acr_get_info.argtypes = [P, ctypes.POINTER(_Info)]
     lib.acr_get_block.argtypes = [P, I32, I32, I32, P, P]
@@ -77,8 +79,8 @@ def load(path: str = LIB_PATH):
     lib.acr_status_string.argtypes = [S]
     lib.acr_status_string.restype = ctypes.c_char_p
     lib.acr_last_error.restype = ctypes.c_char_p
-    for name in ("acr_factor", "acr_solve", "acr_solve_refined", "acr_residual", "acr_get_info",
-                 "acr_get_block", "acr_destroy", "acr_trim_pool"):
+    for name in ("acr_factor", "acr_solve", "acr_solve_refined", "acr_solve_krylov", "acr_residual",
+                 "acr_get_info", "acr_get_block", "acr_destroy", "acr_trim_pool"):
         getattr(lib, name).restype = S
     _lib = lib
     return lib
@@ -178,6 +180,26 @@ def acr_solve_refined(h: Handle, op: Operator, B, tol: float = 1e-10, maxit: int
     code = lib.acr_solve_refined(h.ptr, ctypes.byref(op._c()), Bc.data_ptr(), X.data_ptr(), Bc.shape[0],
                                  float(tol), int(maxit), ctypes.byref(its), ctypes.byref(rel),
                                  _stream(stream))
+    if code != 0 and (raise_on_fail or code != 4):
+        _check(code)
+    X = X.t()
+    return (X.reshape(B.shape) if B.dim() == 1 else X), its.value, rel.value
+
+
+def acr_solve_krylov(h: Handle, op: Operator, B, tol: float = 1e-10, maxit: int = 100, restart: int = 20,
+                     stream=None, raise_on_fail: bool = True):
+    """Restarted FGMRES right-preconditioned by the ACR factor; returns (X, preconditioner
+    applications, relative residual)."""
+    import torch
+    lib = load()
+    n = h.nx * h.ny
+    Bc = _as_colmajor(B, n)
+    X = torch.empty_like(Bc)
+    its = ctypes.c_int32(0)
+    rel = ctypes.c_double(0.0)
+    code = lib.acr_solve_krylov(h.ptr, ctypes.byref(op._c()), Bc.data_ptr(), X.data_ptr(), Bc.shape[0],
+                                float(tol), int(maxit), int(restart), ctypes.byref(its), ctypes.byref(rel),
+                                _stream(stream))
     if code != 0 and (raise_on_fail or code != 4):
         _check(code)
     X = X.t()

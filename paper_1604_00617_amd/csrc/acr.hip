@@ -674,6 +674,110 @@ acr_status acr_solve_refined(acr_handle h, const acr_operator* op, const double*
   return st0;
 }
 
+acr_status acr_solve_krylov(acr_handle h, const acr_operator* op, const double* B, double* X, int32_t nrhs,
+                            double tol, int32_t maxit, int32_t restart, int32_t* iters, double* relres,
+                            void* stream) {
+  int its_all = 0;
+  double rel_all = 0.0;
+  acr_status st0 = guard([&] {
+    check_op(op);
+    if (!h || !B || !X || nrhs < 1 || maxit < 0) fail(ACR_ERR_INVALID_ARG, "bad arguments");
+    if (restart < 1 || restart > 64) fail(ACR_ERR_INVALID_ARG, "restart must be in 1..64");
+    if (X == B) fail(ACR_ERR_INVALID_ARG, "X must not alias B");
+    if (op->nx != h->nx || op->ny != h->ny) fail(ACR_ERR_INVALID_ARG, "operator shape differs from the factor");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long n = (long long)op->nx * op->ny;
+    const int m = restart;
+    DBuf<double> V((size_t)(m + 1) * n), Z((size_t)m * n), R(n), zero(n), dv(2 * (m + 1) + 1);
+    memset_async(zero.get(), 0, (size_t)n * sizeof(double), st);
+    std::vector<double> hv(2 * (m + 1) + 1);
+    auto norm2 = [&](const double* v) {
+      col_sumsq(st, n, 1, v, dv.get());
+      double r = 0.0;
+      read_to_host(&r, dv.get(), sizeof(double), st);
+      return std::sqrt(r);
+    };
+    auto Aop = [&](const double* x, const double* b, double* r) {   // r = b - A x
+      stencil_residual(st, op->nx, op->ny, 1, op->diag, op->west, op->east, op->south, op->north, x, b, r);
+    };
+    for (int q = 0; q < nrhs; ++q) {
+      const double* b = B + (size_t)q * n;
+      double* x = X + (size_t)q * n;
+      memset_async(x, 0, (size_t)n * sizeof(double), st);
+      const double bn = norm2(b);
+      int its = 0;
+      double rel = 0.0;
+      std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+      for (;;) {
+        Aop(x, b, R.get());
+        const double beta = norm2(R.get());
+        rel = bn > 0.0 ? beta / bn : beta;
+        if (!(rel > tol) || its >= maxit || !std::isfinite(rel)) break;
+        // V_0 = r / beta
+        copy_d2d_async(V.get(), R.get(), (size_t)n * sizeof(double), st);
+        maxpy(st, n, 0, 1.0 / beta, 0.0, nullptr, nullptr, 0, V.get());
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;   // columns of the Hessenberg matrix built in this cycle
+        for (int j = 0; j < m && its < maxit; ++j) {
+          double* vj = V.get() + (size_t)j * n;
+          double* zj = Z.get() + (size_t)j * n;
+          double* w = V.get() + (size_t)(j + 1) * n;
+          h->f->solve(vj, zj, 1, st);   // z_j = M^{-1} v_j
+          ++its;
+          Aop(zj, zero.get(), w);        // w = -A z_j
+          // classical Gram-Schmidt twice: d = V^T w, w = -w + V d (= A z_j - V h);
+          // e = V^T w, w = w - V e; h = -d + e
+          mdot(st, n, j + 1, V.get(), n, w, dv.get());
+          maxpy(st, n, j + 1, -1.0, 1.0, dv.get(), V.get(), n, w);
+          mdot(st, n, j + 1, V.get(), n, w, dv.get() + (m + 1));
+          maxpy(st, n, j + 1, 1.0, -1.0, dv.get() + (m + 1), V.get(), n, w);
+          col_sumsq(st, n, 1, w, dv.get() + 2 * (m + 1));
+          read_to_host(hv.data(), dv.get(), hv.size() * sizeof(double), st);
+          double* hc = H.data() + (size_t)j * (m + 1);   // column j
+          for (int i = 0; i <= j; ++i) hc[i] = -hv[i] + hv[m + 1 + i];
+          const double hn = std::sqrt(std::max(hv[2 * (m + 1)], 0.0));
+          hc[j + 1] = hn;
+          for (int i = 0; i < j; ++i) {   // earlier rotations
+            const double a = cs[i] * hc[i] + sn[i] * hc[i + 1];
+            hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+            hc[i] = a;
+          }
+          const double den = std::hypot(hc[j], hc[j + 1]);
+          cs[j] = den > 0.0 ? hc[j] / den : 1.0;
+          sn[j] = den > 0.0 ? hc[j + 1] / den : 0.0;
+          hc[j] = den;
+          hc[j + 1] = 0.0;
+          g[j + 1] = -sn[j] * g[j];
+          g[j] = cs[j] * g[j];
+          k = j + 1;
+          if (hn > 0.0) maxpy(st, n, 0, 1.0 / hn, 0.0, nullptr, nullptr, 0, w);   // v_(j+1)
+          const double est = bn > 0.0 ? std::fabs(g[j + 1]) / bn : std::fabs(g[j + 1]);
+          if (!(est > tol) || !(hn > 0.0)) break;
+        }
+        // y = H^{-1} g (upper triangular k x k), x += Z y
+        for (int i = k - 1; i >= 0; --i) {
+          double v = g[i];
+          for (int l = i + 1; l < k; ++l) v -= H[(size_t)l * (m + 1) + i] * y[l];
+          const double d = H[(size_t)i * (m + 1) + i];
+          y[i] = d != 0.0 ? v / d : 0.0;
+        }
+        if (k > 0) {
+          const double* yd = static_cast<const double*>(DescArena::get().put(y.data(), k * sizeof(double), st));
+          maxpy(st, n, k, 1.0, 1.0, yd, Z.get(), n, x);
+        }
+      }
+      its_all = std::max(its_all, its);
+      rel_all = std::max(rel_all, rel);
+    }
+    if (!(rel_all <= tol))
+      fail(ACR_ERR_NOT_CONVERGED, "FGMRES stopped at relative residual " + std::to_string(rel_all));
+  });
+  if (iters) *iters = its_all;
+  if (relres) *relres = rel_all;
+  return st0;
+}
+
 acr_status acr_get_info(acr_handle h, acr_info* out) {
   return guard([&] {
     if (!h || !out) fail(ACR_ERR_INVALID_ARG, "NULL argument");

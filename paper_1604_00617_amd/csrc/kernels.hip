@@ -2151,6 +2151,31 @@ __global__ void k_col_sumsq_final(int nparts, const double* part, double* out) {
   if (threadIdx.x == 0) out[q] = s;
 }
 
+// Krylov vectors (FP64): partial dot products of nvec vectors V_i (stride
+// ldv) with w, then a fixed-order sum of the parts (deterministic).
+__global__ void k_mdot_part(long long n, long long chunk, const double* __restrict__ V, long long ldv,
+                            const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int i = blockIdx.y;
+  const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  const double* v = V + (long long)i * ldv;
+  double s = 0.0;
+  for (long long e = lo + threadIdx.x; e < hi; e += 256) s = fma(v[e], w[e], s);
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) part[(size_t)i * gridDim.x + blockIdx.x] = s;
+}
+
+// w = a w + sc * sum_i c_i V_i (the nvec coefficients c on the device).
+__global__ void k_maxpy(long long n, int nvec, double a, double sc, const double* __restrict__ c,
+                        const double* __restrict__ V, long long ldv, double* __restrict__ w) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int i = 0; i < nvec; ++i) acc = fma(c[i], V[(long long)i * ldv + e], acc);
+    w[e] = fma(a, w[e], sc * acc);
+  }
+}
+
 template <typename T>
 __global__ void k_scan_values(long long n, const T* a, int* bad, double* amax) {
   __shared__ double red[4];
@@ -2941,6 +2966,23 @@ void col_sumsq(hipStream_t st, long long n, int ncol, const double* A, double* o
          part.get());
   launch(st, KC_OTHER, 0.0, 0.0, KNAME0(k_col_sumsq_final), k_col_sumsq_final, dim3(ncol), dim3(256), 0, nparts, (const double*)part.get(),
          out);
+}
+
+void mdot(hipStream_t st, long long n, int nvec, const double* V, long long ldv, const double* w, double* out) {
+  if (nvec <= 0) return;
+  const int nparts = (int)std::min<long long>(512, std::max<long long>(1, (n + 4095) / 4096));
+  const long long chunk = (n + nparts - 1) / nparts;
+  DBuf<double> part((size_t)nparts * nvec);
+  launch(st, KC_OTHER, 2.0 * n * nvec, 8.0 * n * (nvec + 1), KNAME0(k_mdot_part), k_mdot_part, dim3(nparts, nvec),
+         dim3(256), 0, n, chunk, V, ldv, w, part.get());
+  launch(st, KC_OTHER, 0.0, 0.0, KNAME0(k_col_sumsq_final), k_col_sumsq_final, dim3(nvec), dim3(256), 0, nparts,
+         (const double*)part.get(), out);
+}
+
+void maxpy(hipStream_t st, long long n, int nvec, double a, double sc, const double* c, const double* V,
+           long long ldv, double* w) {
+  launch(st, KC_OTHER, 2.0 * n * nvec, 8.0 * n * (nvec + 2), KNAME0(k_maxpy), k_maxpy, dim3(grid1(n, 256, 16384)),
+         dim3(256), 0, n, nvec, a, sc, c, V, ldv, w);
 }
 
 void flag_nonfinite(hipStream_t st, long long n, const double* a, int* flag) {

@@ -290,5 +290,10 @@ void scan_values(hipStream_t st, long long n, const T* a, bool* bad, double* ama
 
 // X += D (both N x nrhs FP64).
 void axpy_d(hipStream_t st, long long n, const double* D, double* X);
+// Krylov vector kernels (FP64): out[i] = V_i . w for i < nvec (V_i at V + i*ldv,
+// deterministic two-stage sum); w = a w + sc * sum_i c_i V_i with c on the device.
+void mdot(hipStream_t st, long long n, int nvec, const double* V, long long ldv, const double* w, double* out);
+void maxpy(hipStream_t st, long long n, int nvec, double a, double sc, const double* c, const double* V,
+           long long ldv, double* w);
 
 }  // namespace acr

@@ -19,8 +19,9 @@ def declared():
 
 def test_header_declares_entry_points():
     names = declared()
-    for n in ("acr_factor", "acr_solve", "acr_solve_refined", "acr_residual", "acr_get_info",
-              "acr_get_block", "acr_destroy", "acr_status_string", "acr_last_error", "acr_trim_pool"):
+    for n in ("acr_factor", "acr_solve", "acr_solve_refined", "acr_solve_krylov", "acr_residual",
+              "acr_get_info", "acr_get_block", "acr_destroy", "acr_status_string", "acr_last_error",
+              "acr_trim_pool"):
         assert n in names
 
 

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import acr, bcr, direct, hodlr, refine
+from oracle import acr, bcr, direct, hodlr, krylov, refine
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -276,3 +276,55 @@ def test_refinement_with_acr_preconditioner():
     assert hist[-1] <= 1e-10
     assert direct.residual(st, x, b) <= 1e-10
     assert len(hist) - 1 <= 8
+
+
+def _krylov_min_residual(A, b, k):
+    """Definition of the k-th GMRES residual from x_0 = 0 without a
+    preconditioner: min over x in span{b, A b, ..., A^(k-1) b} of ||b - A x||
+    (least squares on an orthonormalised explicit Krylov basis)."""
+    cols = [b]
+    for _ in range(k - 1):
+        cols.append(A @ cols[-1])
+    Q, _ = np.linalg.qr(np.stack(cols, axis=1))
+    AQ = A @ Q
+    y = np.linalg.lstsq(AQ, b, rcond=None)[0]
+    return float(np.linalg.norm(b - AQ @ y))
+
+
+def test_fgmres_minimal_residual_property():
+    """Unpreconditioned FGMRES after k steps (no restart) reaches the minimal
+    residual over the k-th Krylov space: brute force on the nonsymmetric 36 x 36
+    upwind convection-diffusion operator."""
+    st = W.convdiff(6)
+    A = direct.assemble(st).toarray()
+    b = W.rhs(st.n, 1, seed=5)[:, 0]
+    for k in (1, 2, 4, 7):
+        _, its, hist = krylov.fgmres(lambda v: A @ v, b, lambda v: v, tol=0.0, maxit=k, restart=20)
+        assert its == k
+        ref = _krylov_min_residual(A, b, k) / np.linalg.norm(b)
+        assert abs(hist[-1] - ref) <= 1e-10 * max(ref, 1e-300) + 1e-14, (k, hist[-1], ref)
+
+
+def test_fgmres_exact_preconditioner_and_restarts():
+    st = W.poisson(8)
+    A = direct.assemble(st).toarray()
+    b = W.rhs(st.n, 1, seed=6)[:, 0]
+    # exact inverse: one application solves the system
+    x, its, hist = krylov.fgmres(lambda v: A @ v, b, lambda v: np.linalg.solve(A, v), tol=1e-12, maxit=5)
+    assert its == 1 and hist[-1] <= 1e-13
+    # no preconditioner, restart 3: the true residual never grows between cycles
+    x, its, hist = krylov.fgmres(lambda v: A @ v, b, lambda v: v, tol=1e-10, maxit=400, restart=3)
+    assert hist[-1] <= 1e-10
+    assert all(h1 <= h0 * (1 + 1e-12) for h0, h1 in zip(hist, hist[1:]))
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-8 * np.linalg.norm(np.linalg.solve(A, b))
+
+
+def test_fgmres_with_acr_preconditioner():
+    st = W.convdiff(48)
+    b = W.rhs(st.n, 1, seed=12)[:, 0]
+    A = direct.assemble(st)
+    fac = acr.factor(st, 12, 1e-2)
+    x, its, hist = krylov.fgmres(lambda v: A @ v, b, lambda v: acr.solve(fac, st, v), tol=1e-10, maxit=60)
+    assert hist[-1] <= 1e-10
+    xd = direct.solve(st, b)
+    assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)
