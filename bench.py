@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 5 times (reference for the "
                          "HBM byte counters of rocprofv3) and exit")
+    ap.add_argument("--helmholtz", type=float, default=None, metavar="K",
+                    help="instead of the benchmark workload, time the paper's Helmholtz problem "
+                         "(-Laplace u - K^2 u = -f, Gaussian source) on the --n grid: FP32 factor + "
+                         "FGMRES to --tol, with the factor as right preconditioner")
     ap.add_argument("--cpu-rows", type=int, default=16,
                     help="block rows of the operator the CPU oracle factors (bounded sample)")
     return ap.parse_args()
@@ -75,6 +79,29 @@ def run_steps(acr, torch, op, b, args, precision, steps, profile_cls=None, krylo
         prof = acr.acr_profile_report()["kernels"]
         acr.acr_profile_start([])
     return start.elapsed_time(stop) / steps, its, rel, prof
+
+
+def bench_helmholtz(acr, torch, W, args):
+    """Factor + FGMRES steps on the Helmholtz problem (mixed and FP64 factors); one JSON line."""
+    st = W.helmholtz(args.n, args.helmholtz)
+    op = acr.Operator.from_arrays(st.nx, st.ny, *st.arrays())
+    b = torch.from_numpy(W.helmholtz_rhs(args.n)).cuda()
+    res = {}
+    for prec in ("mixed", "fp64"):
+        run_steps(acr, torch, op, b, args, prec, max(args.warmup, 1), krylov=True)
+        ms, its, rel, _ = run_steps(acr, torch, op, b, args, prec, args.steps, krylov=True)
+        res[prec] = {"value": st.n / (ms / 1e3), "ms_per_step": ms, "preconditioner_applications": its,
+                     "relres": rel}
+    m = res["mixed"]
+    print(json.dumps({"metric": "ACR factor+FGMRES unknowns/s, Helmholtz", "value": m["value"],
+                      "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"Helmholtz -Laplace u - k^2 u = -f, k {args.helmholtz:g}, "
+                                             f"{args.n}x{args.n}, Gaussian source, leaf {args.leaf}, "
+                                             f"eps {args.eps:g}, FGMRES(20) to {args.tol:g}"},
+                      "preconditioner_applications": m["preconditioner_applications"], "relres": m["relres"],
+                      "fp64": res["fp64"]}), flush=True)
 
 
 def dominant_kernel(acr, torch, op, b, args, precision):
@@ -206,6 +233,9 @@ def main():
 
     acr.load()
     torch.cuda.set_device(0)
+    if args.helmholtz is not None:
+        bench_helmholtz(acr, torch, W, args)
+        return
     st = W.varkappa(args.n)
     op = acr.Operator.from_arrays(st.nx, st.ny, *st.arrays())
     b = torch.from_numpy(W.rhs(st.n, 1)).cuda()

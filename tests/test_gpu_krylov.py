@@ -10,6 +10,9 @@ ACR factor) and of the few-RHS solve widths.
 - Upwind convection-diffusion 128x128 with a loose factor (eps 1e-2): FGMRES
   still reaches 1e-10 (refinement's contraction is reported).
 - 2 and 4 right-hand sides through the matvec solve against one at a time.
+- The paper's Helmholtz problem (indefinite for k^2 > 2 pi^2, Gaussian source)
+  on 128 x 128 and 256 x 256 grids: FGMRES around the FP64 and the mixed factor
+  against sparse LU.
 """
 import numpy as np
 import pytest
@@ -91,3 +94,19 @@ def test_solve_widths_match_one_at_a_time(gpu, nrhs):
     for q in range(nrhs):
         xq = gpu.acr_solve(h, torch.from_numpy(np.ascontiguousarray(b[:, q])).cuda()).cpu().numpy()
         assert _relerr(xb[:, q], xq) <= 1e-12
+
+
+@pytest.mark.parametrize("side,k,prec", [(128, 10.0, "fp64"), (128, 40.0, "mixed"), (256, 60.0, "mixed")])
+def test_krylov_helmholtz(gpu, side, k, prec):
+    import torch
+    st = W.helmholtz(side, k)
+    op = _op(gpu, st)
+    h = gpu.acr_factor(op, 32, 1e-7, prec)
+    b = W.helmholtz_rhs(side)[:, 0].copy()
+    x, its, rel = gpu.acr_solve_krylov(h, op, torch.from_numpy(b).cuda(), tol=1e-10, maxit=100, restart=30)
+    x = x.cpu().numpy()
+    xd = direct.solve(st, b)
+    err = _relerr(x, xd)
+    print(f"helmholtz {side}, k {k}, {prec}: {its} applications, relres {rel:.2e}, vs LU {err:.2e}")
+    assert rel <= 1e-10 and direct.residual(st, x, b) <= 1e-10
+    assert err <= 1e-6

@@ -63,6 +63,31 @@ def test_direct_discrete_eigenfunction(n, p, q):
     assert np.linalg.norm(ub - phi / lam) / np.linalg.norm(phi / lam) < 1e-12
 
 
+@pytest.mark.parametrize("n,p,q,k", [(15, 1, 1, 0.0), (31, 2, 3, 10.0), (20, 4, 1, 25.0)])
+def test_helmholtz_discrete_eigenfunction(n, p, q, k):
+    """h^2-scaled -Laplace - k^2: A phi = (lambda_pq - (k h)^2) phi for the
+    discrete sine modes (k = 0 is the Poisson operator)."""
+    st = W.helmholtz(n, k)
+    x, y = W.node_coords(n, n)
+    h = 1.0 / (n + 1)
+    phi = np.sin(p * math.pi * x) * np.sin(q * math.pi * y)
+    lam = 4 * math.sin(p * math.pi * h / 2) ** 2 + 4 * math.sin(q * math.pi * h / 2) ** 2 - (k * h) ** 2
+    A = direct.assemble(st)
+    assert np.linalg.norm(A @ phi - lam * phi) <= 1e-12 * np.linalg.norm(phi)
+    if k == 0.0:
+        assert np.array_equal(st.diag, W.poisson(n).diag)
+
+
+def test_helmholtz_indefinite_and_source():
+    st = W.helmholtz(31, 20.0)
+    ev = np.linalg.eigvalsh(direct.assemble(st).toarray())
+    assert ev.min() < 0.0 < ev.max()          # k^2 = 400 > 2 pi^2: indefinite
+    b = W.helmholtz_rhs(31)
+    x, y = W.node_coords(31, 31)
+    c = np.argmin((x - 0.5) ** 2 + (y - 0.5) ** 2)
+    assert abs(b[c, 0] + 100.0 / 32 ** 2) < 1e-12   # f(1/2, 1/2) = 100, scaled by -h^2
+
+
 @pytest.mark.parametrize("n", [7, 24])
 def test_direct_manufactured_variable_kappa(n):
     """u = x(1-x)y(1-y), kappa = 1+x+y at face midpoints: the flux-form 5-point
@@ -325,6 +350,19 @@ def test_fgmres_with_acr_preconditioner():
     A = direct.assemble(st)
     fac = acr.factor(st, 12, 1e-2)
     x, its, hist = krylov.fgmres(lambda v: A @ v, b, lambda v: acr.solve(fac, st, v), tol=1e-10, maxit=60)
+    assert hist[-1] <= 1e-10
+    xd = direct.solve(st, b)
+    assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)
+
+
+def test_fgmres_acr_on_indefinite_helmholtz():
+    """ACR (no block pivoting) as the FGMRES preconditioner of the indefinite
+    Helmholtz operator (k = 20 on a 48 x 48 grid) reaches the LU solution."""
+    st = W.helmholtz(48, 20.0)
+    b = W.helmholtz_rhs(48)[:, 0]
+    A = direct.assemble(st)
+    fac = acr.factor(st, 12, 1e-6)
+    x, its, hist = krylov.fgmres(lambda v: A @ v, b, lambda v: acr.solve(fac, st, v), tol=1e-10, maxit=40)
     assert hist[-1] <= 1e-10
     xd = direct.solve(st, b)
     assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)

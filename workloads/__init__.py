@@ -217,6 +217,29 @@ def node_coords(nx: int, ny: int):
     return X.reshape(-1), Y.reshape(-1)
 
 
+def helmholtz(nx: int, kwave: float, ny: int | None = None) -> Stencil:
+    """Helmholtz operator of the paper's first experiment, written with the sign
+    of the Laplace operators here: -Laplace u - k^2 u (= -f for the paper's
+    Laplace u + k^2 u = f), 5-point, scaled by hx*hy.  Indefinite once k^2 exceeds
+    the smallest Dirichlet eigenvalue 2 pi^2."""
+    st = poisson(nx, ny)
+    hx, hy = 1.0 / (st.nx + 1), 1.0 / (st.ny + 1)
+    st.diag = st.diag - kwave * kwave * hx * hy
+    st.name = "helmholtz"
+    return st
+
+
+def helmholtz_rhs(nx: int, ny: int | None = None) -> np.ndarray:
+    """The paper's source f = 100 exp(-100 ((x - 1/2)^2 + (y - 1/2)^2)) at the
+    nodes, as the right-hand side of -Laplace u - k^2 u = -f scaled by hx*hy;
+    shape (n, 1), column-major."""
+    ny = nx if ny is None else ny
+    x, y = node_coords(nx, ny)
+    f = 100.0 * np.exp(-100.0 * ((x - 0.5) ** 2 + (y - 0.5) ** 2))
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
+    return np.asfortranarray((-hx * hy * f).reshape(-1, 1))
+
+
 # Named workloads (grid side, operator family, leaf, eps, nrhs).
 CONFIGS = {
     1: dict(kind="poisson", n=64, leaf=16, eps=1e-10, nrhs=1),
