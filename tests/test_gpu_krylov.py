@@ -13,6 +13,9 @@ ACR factor) and of the few-RHS solve widths.
 - The paper's Helmholtz problem (indefinite for k^2 > 2 pi^2, Gaussian source)
   on 128 x 128 and 256 x 256 grids: FGMRES around the FP64 and the mixed factor
   against sparse LU.
+- The paper's recirculating convection-diffusion (b = (cos 8 pi x, sin 8 pi y))
+  over an alpha sweep (1, 30, 100) on a 256 x 256 grid: FGMRES around the mixed factor
+  against sparse LU, with the factor's ranks reported.
 """
 import numpy as np
 import pytest
@@ -110,3 +113,22 @@ def test_krylov_helmholtz(gpu, side, k, prec):
     print(f"helmholtz {side}, k {k}, {prec}: {its} applications, relres {rel:.2e}, vs LU {err:.2e}")
     assert rel <= 1e-10 and direct.residual(st, x, b) <= 1e-10
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("alpha", [1.0, 30.0, 100.0])
+def test_krylov_recirculating(gpu, alpha):
+    """(Beyond alpha ~ 1e3 the upwind operator is too ill-conditioned for a 1e-10
+    residual in FP64: at 96 x 96 and alpha = 1e3 sparse LU's own residual is
+    8e-6, at alpha = 1e4 it is O(1).)"""
+    import torch
+    st = W.recirculating(256, alpha)
+    op = _op(gpu, st)
+    h = gpu.acr_factor(op, 32, 1e-6, "mixed")
+    b = W.rhs(st.n, 1, seed=31)[:, 0].copy()
+    x, its, rel = gpu.acr_solve_krylov(h, op, torch.from_numpy(b).cuda(), tol=1e-10, maxit=60, restart=30)
+    x = x.cpu().numpy()
+    xd = direct.solve(st, b)
+    info = gpu.acr_get_info(h)
+    print(f"recirculating 256, alpha {alpha:g}: {its} applications, relres {rel:.2e}, vs LU {_relerr(x, xd):.2e}, "
+          f"max rank {info['max_rank']}")
+    assert rel <= 1e-10 and direct.residual(st, x, b) <= 1e-10

@@ -6,6 +6,7 @@ import math
 import os
 
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 import workloads as W
@@ -366,3 +367,27 @@ def test_fgmres_acr_on_indefinite_helmholtz():
     assert hist[-1] <= 1e-10
     xd = direct.solve(st, b)
     assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 30.0, 3000.0])
+def test_recirculating_operator(alpha):
+    """b = (cos 8 pi x, sin 8 pi y) with upwinding: an M-matrix for every alpha,
+    the Poisson operator at alpha = 0, and exact on linear functions: for
+    u = x + 2y the scaled operator gives h^2 alpha (b_x + 2 b_y) at nodes away
+    from the boundary (the Laplacian of u vanishes, one-sided differences of a
+    linear function are exact)."""
+    n = 20
+    st = W.recirculating(n, alpha)
+    A = direct.assemble(st)
+    off = A - sp.diags(A.diagonal())
+    assert off.max() <= 0.0
+    assert np.all(A.diagonal() + np.asarray(off.sum(axis=1)).ravel() >= -1e-12)
+    if alpha == 0.0:
+        assert np.allclose(A.toarray(), direct.assemble(W.poisson(n)).toarray(), atol=0, rtol=0)
+    x, y = W.node_coords(n, n)
+    h = 1.0 / (n + 1)
+    u = x + 2 * y
+    Au = (A @ u).reshape(n, n)[1:-1, 1:-1]
+    bx, by = np.cos(8 * math.pi * x), np.sin(8 * math.pi * y)
+    ref = (h * h * alpha * (bx + 2 * by)).reshape(n, n)[1:-1, 1:-1]
+    assert np.abs(Au - ref).max() <= 1e-12 * max(1.0, alpha)

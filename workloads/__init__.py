@@ -189,6 +189,12 @@ def convdiff(nx: int, ny: int | None = None, seed: int = seed_for(4, 0),
     theta = math.pi * g
     bx = (beta * np.cos(theta)).reshape(-1)
     by = (beta * np.sin(theta)).reshape(-1)
+    return _upwind(nx, ny, bx, by, "convdiff")
+
+
+def _upwind(nx, ny, bx, by, name):
+    """-Laplace u + b . grad u, first-order upwinding, scaled by hx*hy (b at the nodes)."""
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
     base = poisson(nx, ny)
     # cell-area scaling: x-derivative terms carry hy, y-derivative terms carry hx
     bxp, bxm = np.maximum(bx, 0.0), np.minimum(bx, 0.0)
@@ -199,7 +205,15 @@ def convdiff(nx: int, ny: int | None = None, seed: int = seed_for(4, 0),
     south = base.south - hx * byp
     north = base.north + hx * bym
     _zero_outside(nx, ny, west, east, south, north)
-    return Stencil(nx, ny, diag, west, east, south, north, name="convdiff")
+    return Stencil(nx, ny, diag, west, east, south, north, name=name)
+
+
+def recirculating(nx: int, alpha: float, ny: int | None = None) -> Stencil:
+    """The paper's recirculating-flow problem -Laplace u + alpha b . grad u with
+    b = (cos 8 pi x, sin 8 pi y), first-order upwinding, scaled by hx*hy."""
+    ny = nx if ny is None else ny
+    x, y = node_coords(nx, ny)
+    return _upwind(nx, ny, alpha * np.cos(8 * math.pi * x), alpha * np.sin(8 * math.pi * y), "recirculating")
 
 
 def rhs(n: int, nrhs: int = 1, seed: int = seed_for(1, 9)) -> np.ndarray:
