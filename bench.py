@@ -261,7 +261,10 @@ def main():
     for _ in range(args.warmup):
         run_steps(acr, torch, op, b, args, "mixed", 1)
     kname, cls, table = dominant_kernel(acr, torch, op, b, args, "mixed")
-    ms, its, rel, prof = run_steps(acr, torch, op, b, args, "mixed", args.steps, profile_cls=cls)
+    # the reported time comes from steps without per-launch events; the dominant kernel's
+    # launch times from the same number of steps with HIP events around its launches
+    ms, its, rel, _ = run_steps(acr, torch, op, b, args, "mixed", args.steps)
+    _, _, _, prof = run_steps(acr, torch, op, b, args, "mixed", args.steps, profile_cls=cls)
     krow = next(r for r in prof if r[0] == kname)
     h = acr.acr_factor(op, args.leaf, args.eps, "mixed")
     info = acr.acr_get_info(h)

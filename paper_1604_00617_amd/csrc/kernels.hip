@@ -177,6 +177,20 @@ __device__ T block_sum256(T v, T* red) {
   return r;
 }
 
+// Sum over the NW waves of a workgroup; every thread gets the result.
+template <int NW, typename T>
+__device__ T block_sum_n(T v, T* red) {
+  if (NW == 1) return wave_sum(v);
+  v = wave_sum(v);
+  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  T r = red[0];
+  for (int i = 1; i < NW; ++i) r += red[i];
+  return r;
+}
+
 template <typename T> struct Eps;
 template <> struct Eps<float> { static constexpr double v = 5.9604644775390625e-8; };
 template <> struct Eps<double> { static constexpr double v = 1.1102230246251565e-16; };
@@ -1476,19 +1490,22 @@ __device__ __forceinline__ int rr_partner(int i, int rnd, int cp) {
 //  3. sort by s, rank_p = #{s_i > eps s_1} (capped by maxrank > 0).
 // Outputs per problem: sig[c] (sorted, zero past t'), UK (c x c, column k the
 // k-th left singular vector, zero past t').
-template <typename T>
-__global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, int njobs) {
-  __shared__ double nrm[512];
-  __shared__ double taus[512];
-  __shared__ T snorm[512];
-  __shared__ int spos[512];
-  __shared__ double red[4];
+// NW waves per core, cores of size c <= CMAX (the static arrays' size).
+template <typename T, int NW, int CMAX>
+__global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jobs, int njobs) {
+  constexpr int NTH = NW * 64;
+  constexpr int GD = NW == 4 ? 16 : 8;   // Gram path: t' <= GD, one thread per entry
+  __shared__ double nrm[CMAX];
+  __shared__ double taus[CMAX];
+  __shared__ T snorm[CMAX];
+  __shared__ int spos[CMAX];
+  __shared__ double red[NW];
   __shared__ int s_piv, s_stop, nrot;
   __shared__ double s_delta2, s_v0;
   __shared__ T s_beta;
-  __shared__ double gA[256], gB[256], vA[256], vB[256];   // FP32 cores, t' <= 16: Gram matrix and rotations
-  __shared__ double rc[16], rs[16], gdiag[16];
-  __shared__ int rp[16], gflag;
+  __shared__ double gA[GD * GD], gB[GD * GD], vA[GD * GD], vB[GD * GD];   // FP32 cores, t' <= GD: Gram matrix and rotations
+  __shared__ double rc[GD], rs[GD], gdiag[GD];
+  __shared__ int rp[GD], gflag;
   const SJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
   const int prob = (int)(blockIdx.x - Jb.block0);
   if (Jb.redo && Jb.redo[prob] == 0) return;   // finished by k_grsvd_reg
@@ -1507,7 +1524,7 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
   T* J = Jall + (size_t)prob * c * c;
   if (Jb.lds) {   // the core and both work matrices in LDS
     T* sm = reinterpret_cast<T*>(smem_raw);
-    for (int e = tid; e < c * c; e += 256) sm[e] = W[e];
+    for (int e = tid; e < c * c; e += NTH) sm[e] = W[e];
     W = sm;
     X = sm + (size_t)c * c;
     J = sm + 2 * (size_t)c * c;
@@ -1516,7 +1533,7 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
   double fl = 0.0;
   int tp = 0;
   for (int j = 0; j < c; ++j) {
-    for (int q = j + wv; q < c; q += 4) {
+    for (int q = j + wv; q < c; q += NW) {
       const T* col = W + (size_t)q * c;
       double ss = 0.0;
       for (int r = j + lane; r < c; r += WAVE) ss += (double)col[r] * (double)col[r];
@@ -1548,15 +1565,15 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
     if (s_stop) break;
     const int pc = s_piv;
     if (pc != j)
-      for (int r = tid; r < c; r += 256) {
+      for (int r = tid; r < c; r += NTH) {
         const T a = W[r + (size_t)j * c];
         W[r + (size_t)j * c] = W[r + (size_t)pc * c];
         W[r + (size_t)pc * c] = a;
       }
     __syncthreads();
     double ss = 0.0;
-    for (int r = j + 1 + tid; r < c; r += 256) ss += (double)W[r + (size_t)j * c] * (double)W[r + (size_t)j * c];
-    const double tail = block_sum256(ss, red);
+    for (int r = j + 1 + tid; r < c; r += NTH) ss += (double)W[r + (size_t)j * c] * (double)W[r + (size_t)j * c];
+    const double tail = block_sum_n<NW>(ss, red);
     if (tid == 0) {
       const double alpha = (double)W[j + (size_t)j * c];
       const double nr = sqrt(alpha * alpha + tail);
@@ -1574,10 +1591,10 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
     const T tau = (T)taus[j];
     if (tau != T(0)) {
       const double v0 = s_v0;
-      for (int r = j + 1 + tid; r < c; r += 256) W[r + (size_t)j * c] = (T)((double)W[r + (size_t)j * c] / v0);
+      for (int r = j + 1 + tid; r < c; r += NTH) W[r + (size_t)j * c] = (T)((double)W[r + (size_t)j * c] / v0);
       __syncthreads();
       const T* v = W + (size_t)j * c;
-      for (int q = j + 1 + wv; q < c; q += 4) {
+      for (int q = j + 1 + wv; q < c; q += NW) {
         T* col = W + (size_t)q * c;
         T d = lane == 0 ? col[j] : T(0);
         for (int r = j + 1 + lane; r < c; r += WAVE) d = fma(v[r], col[r], d);
@@ -1593,37 +1610,37 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
     fl += 6.0 * (double)(c - j) * (c - j);
   }
   // X = R_top^T (c x tp), J_X = I (tp x tp), both with leading dimension c
-  for (int e = tid; e < c * tp; e += 256) {
+  for (int e = tid; e < c * tp; e += NTH) {
     const int q = e % c, i = e / c;
     X[q + (size_t)i * c] = q >= i ? W[i + (size_t)q * c] : T(0);
   }
-  for (int e = tid; e < tp * tp; e += 256) {
+  for (int e = tid; e < tp * tp; e += NTH) {
     const int r = e % tp, i = e / tp;
     J[r + (size_t)i * c] = r == i ? T(1) : T(0);
   }
   __syncthreads();
   double ssf = 0.0;
-  for (int e = tid; e < c * tp; e += 256) {
+  for (int e = tid; e < c * tp; e += NTH) {
     const double x = X[(e % c) + (size_t)(e / c) * c];
     ssf += x * x;
   }
-  const double negl2 = block_sum256(ssf, red) * Eps<T>::v * Eps<T>::v;
+  const double negl2 = block_sum_n<NW>(ssf, red) * Eps<T>::v * Eps<T>::v;
   // a pair counts as orthogonal once |cos| <= sqrt(c) u: rounding the rotated
   // columns to the working precision leaves cosines of that size
   const double tol = fmax(4.0, sqrt((double)c)) * Eps<T>::v;
   const int cp = (tp + 1) & ~1;
   const int npairs = cp / 2;
-  int g = 256 / max(npairs, 1), gp = 1;
+  int g = NTH / max(npairs, 1), gp = 1;
   while (gp * 2 <= g && gp * 2 <= WAVE) gp *= 2;
   g = gp;
-  const int slots = 256 / g, gl = tid % g;
-  // FP32 cores with t' <= 16: the same rotations applied to the Gram matrix
+  const int slots = NTH / g, gl = tid % g;
+  // FP32 cores with t' <= GD: the same rotations applied to the Gram matrix
   // X^T X, formed and rotated in FP64 (one thread per entry), which needs no
   // cross-lane sums.  FP64 keeps the smallest retained s_i^2 ~ (eps s_1)^2
   // to a relative 1e-4 and more, ample for the FP32 truncation.
-  const bool gram = sizeof(T) == 4 && tp > 1 && tp <= 16;
+  const bool gram = sizeof(T) == 4 && tp > 1 && tp <= GD;
   if (gram) {
-    const int gi = tid / 16, gk = tid % 16;
+    const int gi = tid / GD, gk = tid % GD;
     const bool ent = gi < tp && gk < tp;
     if (ent) {
       const T* xi = X + (size_t)gi * c;
@@ -1643,7 +1660,7 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
       ++nsw;
       if (tid == 0) gflag = 0;
       for (int rnd = 0; rnd < cp - 1; ++rnd) {
-        if (tid < 16) {   // one wave: the rotation of every index's pair
+        if (tid < GD) {   // one wave: the rotation of every index's pair
           double cv = 1.0, sv = 0.0;
           int px = tid;
           if (tid < tp) {
@@ -1651,7 +1668,7 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
             if (k < tp) {
               px = k;
               const int lo = min(tid, k), hi = max(tid, k);
-              const double al = G[lo * 17], be = G[hi * 17], ga = G[lo * 16 + hi];
+              const double al = G[lo * (GD + 1)], be = G[hi * (GD + 1)], ga = G[lo * GD + hi];
               if (fabs(ga) > tol * sqrt(al * be) && fmax(al, be) > negl2) {
                 const double zeta = (be - al) / (2.0 * ga);
                 const double az = fabs(zeta);
@@ -1672,9 +1689,9 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
         if (ent) {   // G <- R^T G R, V <- V R
           const int pi = rp[gi], pk = rp[gk];
           const double ai = rc[gi], bi = rs[gi], ak = rc[gk], bk = rs[gk];
-          Gn[tid] = ai * (ak * G[gi * 16 + gk] + bk * G[gi * 16 + pk]) +
-                    bi * (ak * G[pi * 16 + gk] + bk * G[pi * 16 + pk]);
-          Vn[tid] = ak * V[gi * 16 + gk] + bk * V[gi * 16 + pk];
+          Gn[tid] = ai * (ak * G[gi * GD + gk] + bk * G[gi * GD + pk]) +
+                    bi * (ak * G[pi * GD + gk] + bk * G[pi * GD + pk]);
+          Vn[tid] = ak * V[gi * GD + gk] + bk * V[gi * GD + pk];
         }
         __syncthreads();
         double* tg = G; G = Gn; Gn = tg;
@@ -1683,10 +1700,10 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
       if (!gflag) break;
       __syncthreads();   // every thread has read gflag before it is reset
     }
-    if (tid < tp) gdiag[tid] = G[tid * 17];
-    for (int e = tid; e < tp * tp; e += 256) {
+    if (tid < tp) gdiag[tid] = G[tid * (GD + 1)];
+    for (int e = tid; e < tp * tp; e += NTH) {
       const int r = e % tp, i = e / tp;
-      J[r + (size_t)i * c] = (T)V[r * 16 + i];
+      J[r + (size_t)i * c] = (T)V[r * GD + i];
     }
     fl += 2.0 * c * tp * tp + nsw * 12.0 * (double)tp * tp * (tp - 1);
     __syncthreads();
@@ -1746,7 +1763,7 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
     if (nr == 0) break;
   }
   // singular values, sort (descending, ties by index)
-  for (int q = tid; q < c; q += 256) {
+  for (int q = tid; q < c; q += NTH) {
     double s2 = 0.0;
     if (q < tp) {
       if (gram) {
@@ -1759,7 +1776,7 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
     snorm[q] = (T)sqrt(s2);
   }
   __syncthreads();
-  for (int q = tid; q < c; q += 256) {
+  for (int q = tid; q < c; q += NTH) {
     const T v = snorm[q];
     int pos = 0;
     for (int o = 0; o < c; ++o) pos += (snorm[o] > v) || (snorm[o] == v && o < q);
@@ -1771,7 +1788,7 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
   // owns its columns for every reflector, so the loop needs no barriers.
   T* const Yg = UK + (size_t)prob * c * c;
   T* const Y = Jb.lds ? X : Yg;
-  for (int e = tid; e < c * c; e += 256) {
+  for (int e = tid; e < c * c; e += NTH) {
     const int r = e % c, q = e / c;    // q = source column (unsorted)
     T v = T(0);
     if (q < tp && r < tp) v = J[r + (size_t)q * c];
@@ -1783,7 +1800,7 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
     const T tau = (T)taus[j];
     if (tau == T(0)) continue;
     const T* v = W + (size_t)j * c;
-    for (int q = wv; q < tp; q += 4) {
+    for (int q = wv; q < tp; q += NW) {
       T* col = Y + (size_t)q * c;
       const T cj = col[j];
       T d = T(0);
@@ -1795,10 +1812,10 @@ __global__ __launch_bounds__(256) void k_grsvd(const SJob* __restrict__ jobs, in
   }
   if (Jb.lds) {
     __syncthreads();
-    for (int e = tid; e < c * c; e += 256) Yg[e] = Y[e];
+    for (int e = tid; e < c * c; e += NTH) Yg[e] = Y[e];
   }
   T* so = sig + (size_t)prob * c;
-  for (int q = tid; q < c; q += 256) so[spos[q]] = snorm[q];
+  for (int q = tid; q < c; q += NTH) so[spos[q]] = snorm[q];
   if (tid == 0) {
     T smax = T(0);
     for (int q = 0; q < c; ++q) smax = snorm[q] > smax ? snorm[q] : smax;
@@ -2604,21 +2621,25 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
   // returns at once for every other problem.  k_grsvd keeps the core and its
   // two work matrices in LDS: launch 0 holds the jobs that fit next to the
   // kernel's static arrays in 64 KB, launch 1 those that fit the full gfx950
-  // workgroup LDS; larger cores work in global scratch.
-  constexpr size_t kStatic = 21504;   // static LDS of k_grsvd (21000 bytes in FP32)
+  // workgroup LDS; larger cores work in global scratch.  When a call holds
+  // many cores of size <= 16 (most of the recompressions of a factorisation),
+  // those run one wave each (launch 2), so that many more fit on a CU.
+  constexpr size_t kStatic = 21504;   // static LDS of k_grsvd_t<T, 4, 512> (21000 bytes in FP32)
   std::vector<DBuf<T>> scratch;
-  std::vector<SJob> use[2], reg;
+  std::vector<SJob> use[3], reg;
   Profiler& P = Profiler::get();
   const bool prof = P.on(KC_SVD);
   double* fl = nullptr;
-  long long b0[2] = {0, 0}, total = 0, nreg = 0;
-  size_t dyn[2] = {0, 0};
-  double by[2] = {0, 0};
+  long long b0[3] = {0, 0, 0}, total = 0, nreg = 0, nsmall = 0;
+  size_t dyn[3] = {0, 0, 0};
+  double by[3] = {0, 0, 0};
   for (auto& J : jobs) {
     if (J.c <= 0 || J.nprob <= 0) continue;
     if (J.c > 512) fail(ACR_ERR_INVALID_ARG, "rank-revealing SVD core larger than 512");
     total += J.nprob;
+    if (J.c <= 16) nsmall += J.nprob;
   }
+  const bool use_small = nsmall > kSmallLaunch;
   // few problems: one launch of k_grsvd (two launches in sequence would only
   // add their latencies)
   const bool use_reg = total > kSmallLaunch;
@@ -2649,9 +2670,9 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
       reg.push_back(R);
     }
     const size_t need = 3 * (size_t)J.c * J.c * sizeof(T);
-    int g = 0;
+    int g = use_small && J.c <= 16 ? 2 : 0;
     J.lds = 1;
-    if (need + kStatic > kMaxLds) {
+    if (g == 0 && need + kStatic > kMaxLds) {
       if (need + kStatic <= kMaxLdsLarge) g = 1;
       else J.lds = 0;
     }
@@ -2673,13 +2694,18 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     launch(st, KC_SVD, 0.0, rby, KNAME_T(k_grsvd_reg<T>), k_grsvd_reg<T>, dim3((unsigned)rb0), dim3(256), 0, dj,
            (int)reg.size());
   }
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < 3; ++g) {
     if (use[g].empty()) continue;
-    if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_grsvd<T>), kMaxLdsLarge - kStatic);
     const SJob* dj = upload(use[g], st);
     const int nj = (int)use[g].size();
-    launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd<T>), k_grsvd<T>, dim3((unsigned)b0[g]), dim3(256), dyn[g], dj,
-           nj);
+    if (g == 2) {
+      launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd_t<T, 1, 16>), k_grsvd_t<T, 1, 16>, dim3((unsigned)b0[g]),
+             dim3(WAVE), dyn[g], dj, nj);
+      continue;
+    }
+    if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_grsvd_t<T, 4, 512>), kMaxLdsLarge - kStatic);
+    launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd_t<T, 4, 512>), k_grsvd_t<T, 4, 512>, dim3((unsigned)b0[g]),
+           dim3(256), dyn[g], dj, nj);
   }
   if (fl) {   // device-counted flops of every problem, credited to the last launch
     const int n = (int)total;
