@@ -28,10 +28,23 @@ constexpr long long kSmallLaunch = 1024;   // workgroups below which shape varia
 constexpr int kApplyRows = 8;        // Q application in registers: rows per lane (p <= 512)
 constexpr int kApplyCols = 8;        // and output columns per wave (t <= 32)
 
+// Device pointers taken from job descriptors reach a kernel as generic
+// pointers, for which the compiler emits FLAT accesses; a FLAT access also
+// counts against the LDS and scalar-load wait counter, so each wait for an LDS
+// read or a descriptor load (and the wait ahead of every barrier) would also
+// wait for the global loads and stores in flight.  gmem() restates such a
+// pointer in the global address space (every descriptor pointer is device
+// memory), so that the compiler emits global loads and stores, which only the
+// vector-memory counter tracks.
+template <typename T>
+__device__ __forceinline__ T* gmem(T* p) {
+  return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+
 template <typename T>
 __device__ __forceinline__ const T* optr(const BOp& o, int m, int c) {
   const int cc = (c >> o.cshift) ^ o.cxor;
-  return static_cast<const T*>(o.p) + (long long)(o.mmul * m + o.moff) * o.sm +
+  return gmem(static_cast<const T*>(o.p)) + (long long)(o.mmul * m + o.moff) * o.sm +
          (long long)(cc >> 1) * o.sc_pair + (long long)(cc & 1) * o.sc_odd;
 }
 
@@ -551,9 +564,9 @@ __global__ __launch_bounds__(256) void k_hmv_reduce(const MVRed* __restrict__ re
   const int node = rem / nch, q0 = (rem % nch) * CH;
   const int sd = s >> d;
   const long long vs = (long long)s * nrhs;
-  const T* Vb = static_cast<const T*>(M.V[d]) + (long long)(M.mmul * m + M.moff) * M.k[d] * s +
+  const T* Vb = gmem(static_cast<const T*>(M.V[d])) + (long long)(M.mmul * m + M.moff) * M.k[d] * s +
                 (long long)q0 * s + (long long)node * sd;
-  const T* yb = static_cast<const T*>(M.y) + (long long)(M.ymul * m + M.yoff) * vs + (long long)node * sd;
+  const T* yb = gmem(static_cast<const T*>(M.y)) + (long long)(M.ymul * m + M.yoff) * vs + (long long)node * sd;
   T pr[CH][NR];
 #pragma unroll
   for (int c = 0; c < CH; ++c)
@@ -619,7 +632,7 @@ __global__ __launch_bounds__(64) void k_hmv_apply(const MVJob* __restrict__ jobs
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = T(0);
   if (J.C0) {
-    const T* c0 = static_cast<const T*>(J.C0) + (long long)(J.cmul * m + J.coff) * vs + row;
+    const T* c0 = gmem(static_cast<const T*>(J.C0)) + (long long)(J.cmul * m + J.coff) * vs + row;
 #pragma unroll
     for (int q = 0; q < NR; ++q)
       if (q < nrhs) acc[q] = (T)J.beta * c0[(long long)q * s];
@@ -627,17 +640,17 @@ __global__ __launch_bounds__(64) void k_hmv_apply(const MVJob* __restrict__ jobs
   for (int t = 0; t < J.nterm; ++t) {
     const MVTerm& M = terms[J.term0 + t];
     const int mm = M.mmul * m + M.moff;
-    const T* y = static_cast<const T*>(M.y) + (long long)(M.ymul * m + M.yoff) * vs;
+    const T* y = gmem(static_cast<const T*>(M.y)) + (long long)(M.ymul * m + M.yoff) * vs;
     T ta[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) ta[q] = T(0);
     if (M.type == 1) {   // diagonal
-      const T dv = static_cast<const T*>(M.lv)[(long long)mm * s + row];
+      const T dv = gmem(static_cast<const T*>(M.lv))[(long long)mm * s + row];
 #pragma unroll
       for (int q = 0; q < NR; ++q)
         if (q < nrhs) ta[q] = dv * y[row + (long long)q * s];
     } else {
-      const T* lf = static_cast<const T*>(M.lv) + ((long long)mm * nleaf + l) * b * b + r;
+      const T* lf = gmem(static_cast<const T*>(M.lv)) + ((long long)mm * nleaf + l) * b * b + r;
       const T* yl = y + (long long)l * b;
       if (W64) {
         for (int cb = 0; cb < b; cb += WAVE) {
@@ -666,7 +679,7 @@ __global__ __launch_bounds__(64) void k_hmv_apply(const MVJob* __restrict__ jobs
         if (w == 0) continue;
         const int sib = (l >> (L - d)) ^ 1;
         const T* tv = tb + M.toff[d] + (long long)sib * w * NR;
-        const T* Ud = static_cast<const T*>(M.U[d]) + (long long)mm * M.k[d] * s + row;
+        const T* Ud = gmem(static_cast<const T*>(M.U[d])) + (long long)mm * M.k[d] * s + row;
 #pragma unroll 4
         for (int q0 = 0; q0 < w; ++q0) {
           const T uv = Ud[(long long)q0 * s];
@@ -679,7 +692,7 @@ __global__ __launch_bounds__(64) void k_hmv_apply(const MVJob* __restrict__ jobs
 #pragma unroll
     for (int q = 0; q < NR; ++q) acc[q] = fma(al, ta[q], acc[q]);
   }
-  T* out = static_cast<T*>(J.out) + (long long)(J.omul * m + J.ooff) * vs + row;
+  T* out = gmem(static_cast<T*>(J.out)) + (long long)(J.omul * m + J.ooff) * vs + row;
 #pragma unroll
   for (int q = 0; q < NR; ++q)
     if (q < nrhs) out[(long long)q * s] = acc[q];
@@ -943,7 +956,7 @@ __global__ __launch_bounds__(256) void k_grsvd_reg(const SJob* __restrict__ jobs
   const int prob = (int)(blockIdx.x - Jb.block0);
   const int c = Jb.c, maxrank = Jb.maxrank;
   const double eps = Jb.eps;
-  const T* Kp = static_cast<const T*>(Jb.K) + (size_t)prob * c * c;
+  const T* Kp = gmem(static_cast<const T*>(Jb.K)) + (size_t)prob * c * c;
   const int tid = threadIdx.x, lane = tid % WAVE;
   const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
   T w[SL];
@@ -1041,7 +1054,7 @@ __global__ __launch_bounds__(256) void k_grsvd_reg(const SJob* __restrict__ jobs
   }
   __syncthreads();
   if (tp > SV_TP) {
-    if (tid == 0) Jb.redo[prob] = 1;
+    if (tid == 0) gmem(Jb.redo)[prob] = 1;
     return;
   }
   if (wv != 0) return;
@@ -1116,14 +1129,14 @@ __global__ __launch_bounds__(256) void k_grsvd_reg(const SJob* __restrict__ jobs
         y[i] = fma(-d, v, y[i]);
       }
   }
-  T* Y = static_cast<T*>(Jb.UK) + (size_t)prob * c * c;
+  T* Y = gmem(static_cast<T*>(Jb.UK)) + (size_t)prob * c * c;
   if (lane < c) {
 #pragma unroll
     for (int i = 0; i < SV_TP; ++i)
       if (i < tp) Y[lane + (size_t)pos[i] * c] = y[i];
     for (int q = tp; q < c; ++q) Y[lane + (size_t)q * c] = T(0);
   }
-  T* so = static_cast<T*>(Jb.sig) + (size_t)prob * c;
+  T* so = gmem(static_cast<T*>(Jb.sig)) + (size_t)prob * c;
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < SV_TP; ++i)
@@ -1139,9 +1152,9 @@ __global__ __launch_bounds__(256) void k_grsvd_reg(const SJob* __restrict__ jobs
       for (int i = 0; i < SV_TP; ++i) t += (i < tp) && ((double)sv[i] > thr);
     }
     if (maxrank > 0 && t > maxrank) t = maxrank;
-    Jb.rank[prob] = t;
+    gmem(Jb.rank)[prob] = t;
     fl += 4.0 * (double)c * tp * tp;
-    if (Jb.flops) Jb.flops[prob] = fl;
+    if (Jb.flops) gmem(Jb.flops)[prob] = fl;
   }
 }
 
@@ -1159,8 +1172,8 @@ __device__ __forceinline__ void gqr_reg_body(const QJob& Jb, int prob, T (*vbuf)
   const BOp A = Jb.A;
   const T* Ap = optr<T>(A, m, c);
   const int kr = min(p, k);
-  T* const Vref = Jb.Vref ? static_cast<T*>(Jb.Vref) + (size_t)prob * p * kr : nullptr;
-  T* const taus = Jb.tau ? static_cast<T*>(Jb.tau) + (size_t)prob * kr : nullptr;
+  T* const Vref = Jb.Vref ? gmem(static_cast<T*>(Jb.Vref)) + (size_t)prob * p * kr : nullptr;
+  T* const taus = Jb.tau ? gmem(static_cast<T*>(Jb.tau)) + (size_t)prob * kr : nullptr;
   const int tid = threadIdx.x, lane = tid % WAVE;
   const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
   T w[QR_ROWS][QR_SLOTS];
@@ -1249,7 +1262,7 @@ __device__ __forceinline__ void gqr_reg_body(const QJob& Jb, int prob, T (*vbuf)
     }
   }
   // R = upper trapezoid of the first kr rows
-  T* Rp = static_cast<T*>(Jb.R) + (size_t)prob * kr * k;
+  T* Rp = gmem(static_cast<T*>(Jb.R)) + (size_t)prob * kr * k;
 #pragma unroll
   for (int i = 0; i < QR_ROWS; ++i)
 #pragma unroll
@@ -1294,8 +1307,9 @@ __global__ __launch_bounds__(256) void k_gqr_any(const QJob* __restrict__ jobs, 
 
 // ------------------------------------------------------------ QR (R only)
 // Householder QR of a p x k panel; one workgroup of 256 threads per problem.
-// The panel is copied to LDS when it fits, else to a global scratch copy.
-template <typename T>
+// The panel is copied to LDS (INLDS: every job of the launch) or to a global
+// scratch copy.
+template <typename T, bool INLDS>
 __global__ __launch_bounds__(256) void k_gqr(const QJob* __restrict__ jobs, int njobs) {
   extern __shared__ unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
@@ -1309,11 +1323,11 @@ __global__ __launch_bounds__(256) void k_gqr(const QJob* __restrict__ jobs, int 
   const BOp A = Jb.A;
   const T* Ap = optr<T>(A, m, c);
   const int krr = min(p, k);
-  T* const R = static_cast<T*>(Jb.R);
-  T* const Vref = Jb.Vref ? static_cast<T*>(Jb.Vref) + (size_t)prob * p * krr : nullptr;
-  T* const taus = Jb.tau ? static_cast<T*>(Jb.tau) + (size_t)prob * krr : nullptr;
+  T* const R = gmem(static_cast<T*>(Jb.R));
+  T* const Vref = Jb.Vref ? gmem(static_cast<T*>(Jb.Vref)) + (size_t)prob * p * krr : nullptr;
+  T* const taus = Jb.tau ? gmem(static_cast<T*>(Jb.tau)) + (size_t)prob * krr : nullptr;
   T* v = sm;                                  // Householder vector, p entries
-  T* W = Jb.lds ? sm + p : static_cast<T*>(Jb.ws) + (size_t)prob * p * k;
+  T* W = INLDS ? sm + p : gmem(static_cast<T*>(Jb.ws)) + (size_t)prob * p * k;
   const int tid = threadIdx.x, wv = tid / WAVE, lane = tid % WAVE;
   for (int e = tid; e < p * k; e += 256) {
     const int r = e % p, q = e / p;
@@ -1392,9 +1406,9 @@ __global__ __launch_bounds__(256) void k_gapply_q(const AJob* __restrict__ jobs,
   const int m = prob / ncl, cl = prob % ncl;
   const BOp Y = Jb.Y;
   T* y = const_cast<T*>(optr<T>(Y, m, cl));
-  const T* z = static_cast<const T*>(Jb.Z) + (size_t)(m * ncl + (cl ^ Jb.zxor)) * Jb.sZ;
-  const T* vr = static_cast<const T*>(Jb.Vref) + (size_t)prob * p * c;
-  const T* ta = static_cast<const T*>(Jb.tau) + (size_t)prob * c;
+  const T* z = gmem(static_cast<const T*>(Jb.Z)) + (size_t)(m * ncl + (cl ^ Jb.zxor)) * Jb.sZ;
+  const T* vr = gmem(static_cast<const T*>(Jb.Vref)) + (size_t)prob * p * c;
+  const T* ta = gmem(static_cast<const T*>(Jb.tau)) + (size_t)prob * c;
   const int tid = threadIdx.x, wv = tid / WAVE, lane = tid % WAVE;
   if (Jb.lds) {
     // Reflectors (and their taus) in LDS; wave w owns the output columns
@@ -1490,8 +1504,11 @@ __device__ __forceinline__ int rr_partner(int i, int rnd, int cp) {
 //  3. sort by s, rank_p = #{s_i > eps s_1} (capped by maxrank > 0).
 // Outputs per problem: sig[c] (sorted, zero past t'), UK (c x c, column k the
 // k-th left singular vector, zero past t').
-// NW waves per core, cores of size c <= CMAX (the static arrays' size).
-template <typename T, int NW, int CMAX>
+// NW waves per core, cores of size c <= CMAX (the static arrays' size).  With
+// INLDS every job of the launch keeps the core and both work matrices in LDS
+// (and the compiler emits LDS instructions for them); without, they work in
+// global scratch.
+template <typename T, int NW, int CMAX, bool INLDS>
 __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jobs, int njobs) {
   constexpr int NTH = NW * 64;
   constexpr int GD = NW == 4 ? 16 : 8;   // Gram path: t' <= GD, one thread per entry
@@ -1508,27 +1525,30 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
   __shared__ int rp[GD], gflag;
   const SJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
   const int prob = (int)(blockIdx.x - Jb.block0);
-  if (Jb.redo && Jb.redo[prob] == 0) return;   // finished by k_grsvd_reg
+  if (Jb.redo && gmem(Jb.redo)[prob] == 0) return;   // finished by k_grsvd_reg
   const int c = Jb.c, maxrank = Jb.maxrank;
   const double eps = Jb.eps;
-  T* const Xall = static_cast<T*>(Jb.X);
-  T* const Jall = static_cast<T*>(Jb.J);
-  T* const sig = static_cast<T*>(Jb.sig);
-  T* const UK = static_cast<T*>(Jb.UK);
-  int* const rank = Jb.rank;
-  double* const flops = Jb.flops;
+  T* const sig = gmem(static_cast<T*>(Jb.sig));
+  T* const UK = gmem(static_cast<T*>(Jb.UK));
+  int* const rank = gmem(Jb.rank);
+  double* const flops = gmem(Jb.flops);
   const int tid = threadIdx.x, wv = tid / WAVE, lane = tid % WAVE;
   extern __shared__ unsigned char smem_raw[];
-  T* W = static_cast<T*>(Jb.K) + (size_t)prob * c * c;
-  T* X = Xall + (size_t)prob * c * c;
-  T* J = Jall + (size_t)prob * c * c;
-  if (Jb.lds) {   // the core and both work matrices in LDS
+  T* W;
+  T* X;
+  T* J;
+  if constexpr (INLDS) {   // the core and both work matrices in LDS
     T* sm = reinterpret_cast<T*>(smem_raw);
-    for (int e = tid; e < c * c; e += NTH) sm[e] = W[e];
+    const T* src = gmem(static_cast<const T*>(Jb.K)) + (size_t)prob * c * c;
+    for (int e = tid; e < c * c; e += NTH) sm[e] = src[e];
     W = sm;
     X = sm + (size_t)c * c;
     J = sm + 2 * (size_t)c * c;
     __syncthreads();
+  } else {
+    W = gmem(static_cast<T*>(Jb.K)) + (size_t)prob * c * c;
+    X = gmem(static_cast<T*>(Jb.X)) + (size_t)prob * c * c;
+    J = gmem(static_cast<T*>(Jb.J)) + (size_t)prob * c * c;
   }
   double fl = 0.0;
   int tp = 0;
@@ -1787,7 +1807,7 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
   // X (free after the sort) when it is in LDS, else directly in UK.  Each wave
   // owns its columns for every reflector, so the loop needs no barriers.
   T* const Yg = UK + (size_t)prob * c * c;
-  T* const Y = Jb.lds ? X : Yg;
+  T* const Y = INLDS ? X : Yg;
   for (int e = tid; e < c * c; e += NTH) {
     const int r = e % c, q = e / c;    // q = source column (unsorted)
     T v = T(0);
@@ -1810,7 +1830,7 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
       if (lane == 0) col[j] = cj - d;
     }
   }
-  if (Jb.lds) {
+  if constexpr (INLDS) {
     __syncthreads();
     for (int e = tid; e < c * c; e += NTH) Yg[e] = Y[e];
   }
@@ -1836,9 +1856,9 @@ __global__ void k_gtrunc(const TJob* __restrict__ jobs, int njobs) {
   const TJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
   const int prob = (int)(blockIdx.x - Jb.block0);
   const int c = Jb.c, kout = Jb.kout;
-  const int t = Jb.rank[prob];
-  const T* J = static_cast<const T*>(Jb.UK) + (size_t)prob * c * c;
-  T* Jt = static_cast<T*>(Jb.Ut) + (size_t)prob * c * kout;
+  const int t = gmem(Jb.rank)[prob];
+  const T* J = gmem(static_cast<const T*>(Jb.UK)) + (size_t)prob * c * c;
+  T* Jt = gmem(static_cast<T*>(Jb.Ut)) + (size_t)prob * c * kout;
   for (int e = threadIdx.x; e < c * kout; e += blockDim.x) {
     const int r = e % c, q = e / c;
     Jt[e] = (q < t && q < c) ? J[r + (size_t)q * c] : T(0);
@@ -1849,7 +1869,7 @@ __global__ void k_gmax(const MJob* __restrict__ jobs) {
   __shared__ int sm[256];
   const MJob& Jb = jobs[blockIdx.x];
   int mx = 0;
-  for (int i = threadIdx.x; i < Jb.n; i += 256) mx = max(mx, Jb.rank[i]);
+  for (int i = threadIdx.x; i < Jb.n; i += 256) mx = max(mx, gmem(Jb.rank)[i]);
   sm[threadIdx.x] = mx;
   __syncthreads();
   for (int s2 = 128; s2 > 0; s2 >>= 1) {
@@ -1874,7 +1894,7 @@ __global__ __launch_bounds__(256) void k_gcopy(const CJob* __restrict__ jobs, in
   const BOp src = Jb.src, dst = Jb.dst;
   const T* sp = optr<T>(src, m, c);
   T* dp = const_cast<T*>(optr<T>(dst, m, c));
-  const T* sc = Jb.scale ? static_cast<const T*>(Jb.scale) + (long long)(Jb.smul * m + Jb.soff) * Jb.sstride +
+  const T* sc = Jb.scale ? gmem(static_cast<const T*>(Jb.scale)) + (long long)(Jb.smul * m + Jb.soff) * Jb.sstride +
                                (long long)c * Jb.scl
                          : nullptr;
   const int rows = Jb.rows, n = rows * Jb.cols, e0 = chunk * kCopyChunk + (int)threadIdx.x;
@@ -2045,8 +2065,8 @@ __global__ __launch_bounds__(256) void k_tridiag_inverse(int s, int b, int L, in
     while (t >= (4 << (d - 1))) { t -= 4 << (d - 1); ++d; }
     const int pair = t >> 2, kind = t & 3;
     const int sd = s >> d, t0 = 2 * pair * sd, t1 = t0 + sd;
-    T* Ud = static_cast<T*>(out.U[d]) + (size_t)m * s;
-    T* Vd = static_cast<T*>(out.V[d]) + (size_t)m * s;
+    T* Ud = gmem(static_cast<T*>(out.U[d])) + (size_t)m * s;
+    T* Vd = gmem(static_cast<T*>(out.V[d])) + (size_t)m * s;
     if (kind == 0) {          // U of the upper block, rows of the first cluster
       double u = 1.0;
       for (int i = t1 - 1; i >= t0; --i) { u *= B[i]; Ud[i] = (T)u; }
@@ -2481,10 +2501,10 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
   // 160 KB a gfx950 workgroup may hold) get a launch of their own, so that
   // the many small panels keep their occupancy; the rest work in global memory.
   std::vector<DBuf<T>> scratch;
-  std::vector<QJob> use[3];
-  size_t dyn[3] = {0, 0, 0};
-  double fl[3] = {0, 0, 0}, by[3] = {0, 0, 0};
-  long long b0[3] = {0, 0, 0};
+  std::vector<QJob> use[4];
+  size_t dyn[4] = {0, 0, 0, 0};
+  double fl[4] = {0, 0, 0, 0}, by[4] = {0, 0, 0, 0};
+  long long b0[4] = {0, 0, 0, 0};
   for (auto& J : jobs) {
     if (J.p <= 0 || J.k <= 0 || J.nmat <= 0 || J.ncl <= 0) continue;
     const size_t np = (size_t)J.nmat * J.ncl;
@@ -2502,10 +2522,11 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
       g = 1;
     } else {
       J.lds = 0;
+      g = 3;
       scratch.emplace_back(np * J.p * J.k);
       J.ws = scratch.back().get();
     }
-    if (g < 2) dyn[g] = std::max(dyn[g], J.lds ? panel + vb : vb);
+    if (g != 2) dyn[g] = std::max(dyn[g], J.lds ? panel + vb : vb);
     J.block0 = b0[g];
     b0[g] += (long long)np;
     const double p = J.p, k = J.k, kr = std::min(J.p, J.k);
@@ -2554,11 +2575,18 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
       }
     }
   }
-  for (int g = 0; g < 2; ++g) {
+  for (int g : {0, 1, 3}) {   // panels in LDS (64 KB, the full workgroup LDS), then in global scratch
     if (use[g].empty()) continue;
-    if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_gqr<T>));
     const QJob* dj = upload(use[g], st);
-    launch(st, KC_QR, fl[g], by[g], KNAME_T(k_gqr<T>), k_gqr<T>, dim3((unsigned)b0[g]), dim3(256), dyn[g], dj, (int)use[g].size());
+    const int nj = (int)use[g].size();
+    if (g == 3) {
+      launch(st, KC_QR, fl[g], by[g], KNAME_T(k_gqr<T, false>), k_gqr<T, false>, dim3((unsigned)b0[g]), dim3(256),
+             dyn[g], dj, nj);
+      continue;
+    }
+    if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_gqr<T, true>));
+    launch(st, KC_QR, fl[g], by[g], KNAME_T(k_gqr<T, true>), k_gqr<T, true>, dim3((unsigned)b0[g]), dim3(256),
+           dyn[g], dj, nj);
   }
 }
 
@@ -2626,13 +2654,13 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
   // those run one wave each (launch 2), so that many more fit on a CU.
   constexpr size_t kStatic = 21504;   // static LDS of k_grsvd_t<T, 4, 512> (21000 bytes in FP32)
   std::vector<DBuf<T>> scratch;
-  std::vector<SJob> use[3], reg;
+  std::vector<SJob> use[4], reg;
   Profiler& P = Profiler::get();
   const bool prof = P.on(KC_SVD);
   double* fl = nullptr;
-  long long b0[3] = {0, 0, 0}, total = 0, nreg = 0, nsmall = 0;
-  size_t dyn[3] = {0, 0, 0};
-  double by[3] = {0, 0, 0};
+  long long b0[4] = {0, 0, 0, 0}, total = 0, nreg = 0, nsmall = 0;
+  size_t dyn[4] = {0, 0, 0, 0};
+  double by[4] = {0, 0, 0, 0};
   for (auto& J : jobs) {
     if (J.c <= 0 || J.nprob <= 0) continue;
     if (J.c > 512) fail(ACR_ERR_INVALID_ARG, "rank-revealing SVD core larger than 512");
@@ -2674,7 +2702,7 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     J.lds = 1;
     if (g == 0 && need + kStatic > kMaxLds) {
       if (need + kStatic <= kMaxLdsLarge) g = 1;
-      else J.lds = 0;
+      else { J.lds = 0; g = 3; }
     }
     if (J.lds) {
       dyn[g] = std::max(dyn[g], need);
@@ -2694,18 +2722,24 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     launch(st, KC_SVD, 0.0, rby, KNAME_T(k_grsvd_reg<T>), k_grsvd_reg<T>, dim3((unsigned)rb0), dim3(256), 0, dj,
            (int)reg.size());
   }
-  for (int g = 0; g < 3; ++g) {
+  // launches: 0 and 1 in LDS (64 KB / the full workgroup LDS), 2 the small
+  // one-wave cores, 3 the cores that work in global scratch
+  for (int g = 0; g < 4; ++g) {
     if (use[g].empty()) continue;
     const SJob* dj = upload(use[g], st);
     const int nj = (int)use[g].size();
+    const dim3 grid((unsigned)b0[g]);
     if (g == 2) {
-      launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd_t<T, 1, 16>), k_grsvd_t<T, 1, 16>, dim3((unsigned)b0[g]),
+      launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd_t<T, 1, 16, true>), k_grsvd_t<T, 1, 16, true>, grid,
              dim3(WAVE), dyn[g], dj, nj);
-      continue;
+    } else if (g == 3) {
+      launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd_t<T, 4, 512, false>), k_grsvd_t<T, 4, 512, false>, grid,
+             dim3(256), 0, dj, nj);
+    } else {
+      if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_grsvd_t<T, 4, 512, true>), kMaxLdsLarge - kStatic);
+      launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd_t<T, 4, 512, true>), k_grsvd_t<T, 4, 512, true>, grid,
+             dim3(256), dyn[g], dj, nj);
     }
-    if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_grsvd_t<T, 4, 512>), kMaxLdsLarge - kStatic);
-    launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd_t<T, 4, 512>), k_grsvd_t<T, 4, 512>, dim3((unsigned)b0[g]),
-           dim3(256), dyn[g], dj, nj);
   }
   if (fl) {   // device-counted flops of every problem, credited to the last launch
     const int n = (int)total;
