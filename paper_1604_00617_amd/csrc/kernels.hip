@@ -1158,6 +1158,178 @@ __global__ __launch_bounds__(256) void k_grsvd_reg(const SJob* __restrict__ jobs
   }
 }
 
+// ------------------------------------------------- QR, one wave per panel
+// Value of lane `src` (any lane, per-lane index) through the LDS crossbar
+// (ds_bpermute: no LDS storage, no barrier).
+__device__ __forceinline__ float lane_fetch(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_fetch(double v, int src) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)x);
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(x >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Reflector of column j in the one-wave QR layout (below), from this lane's
+// entries x of that column (those of the owner lane row, j & 3, count): the
+// norm in FP64 (as in the other QR kernels) over the owner row by group_sum,
+// alpha by readlane, the same scalars formed in every lane, and this lane's
+// rows of v fetched from the owner row (ds_bpermute).  v = x / v0 is formed in
+// FP64, so |v_r| <= 1 also for columns far below the FP32 normal range.
+template <typename T, int RPL>
+__device__ __forceinline__ void wave_reflector(const T (&x)[RPL], int j, int p, int rg, T& tau, T& diag, T (&v)[RPL]) {
+  const int jo = j & 3, ji = j >> 4;
+  double ss = 0.0;
+  T xj = T(0);
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int r = rg + 16 * i;
+    const double xv = (double)x[i];
+    if (r > j && r < p) ss += xv * xv;
+    if (i == ji) xj = x[i];
+  }
+  const double tail = lane_read(group_sum(ss, 16), 16 * jo);
+  const double alpha = (double)lane_read(xj, 16 * jo + (j & 15));
+  const double nrm = sqrt(alpha * alpha + tail);
+  const double beta = alpha >= 0.0 ? -nrm : nrm;
+  const bool refl = !(tail == 0.0 || nrm == 0.0);
+  tau = refl ? (T)((beta - alpha) / beta) : T(0);
+  diag = refl ? (T)beta : (T)alpha;
+  const double rv = refl ? 1.0 / (alpha - beta) : 0.0;
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int r = rg + 16 * i;
+    const T got = lane_fetch((T)((double)x[i] * rv), 16 * jo + rg);
+    v[i] = (refl && r >= j && r < p) ? ((r == j) ? T(1) : got) : T(0);
+  }
+}
+
+// Householder QR of a p x k panel (p <= 16*RPL, k <= 4*CPL) held by one wave:
+// lane l keeps rows rg + 16 i (rg = l mod 16, i < RPL) of the columns
+// cg + 4 u (cg = l / 16, u < CPL).  The entries of a column then lie in one
+// DPP row of 16 lanes, so each dot product takes RPL in-lane products and the
+// four in-row DPP steps of group_sum, and the panel needs neither LDS storage
+// nor barriers.  Step j applies reflector j to the columns q > j; column j+1
+// is updated first and its reflector formed right away, so that the latency
+// of forming it overlaps the update of the other columns.  Column j keeps its
+// old entries (only R's diagonal, stored at once, is needed from it).  Same
+// outputs as k_gqr.
+template <typename T, int RPL, int CPL>
+__device__ __forceinline__ void gqr_wave_body(const QJob& Jb, int prob) {
+  const int p = Jb.p, k = Jb.k, ncl = Jb.ncl;
+  const int m = prob / ncl, c = prob % ncl;
+  const BOp A = Jb.A;
+  const T* Ap = optr<T>(A, m, c);
+  const int kr = min(p, k);
+  T* const Vref = Jb.Vref ? gmem(static_cast<T*>(Jb.Vref)) + (size_t)prob * p * kr : nullptr;
+  T* const taus = Jb.tau ? gmem(static_cast<T*>(Jb.tau)) + (size_t)prob * kr : nullptr;
+  T* const Rp = gmem(static_cast<T*>(Jb.R)) + (size_t)prob * kr * k;
+  const int lane = threadIdx.x % WAVE, rg = lane & 15, cg = lane >> 4;
+  T w[RPL][CPL];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int r = rg + 16 * i, q = cg + 4 * u;
+      w[i][u] = (r < p && q < k) ? Ap[r + (long long)q * A.ld] : T(0);
+    }
+  T tau, diag, v[RPL];
+  {
+    T x0[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) x0[i] = w[i][0];
+    wave_reflector<T, RPL>(x0, 0, p, rg, tau, diag, v);
+  }
+  for (int j = 0; j < kr; ++j) {
+    const int jo = j & 3, jn = j + 1, nn = jn >> 2;
+    const T mtau = -tau;
+    // column j+1 (slot nn of every lane row) after reflector j, and its reflector
+    T xn[RPL];
+    {
+      T wn[RPL];
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) wn[i] = T(0);
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        if (u == nn)
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) wn[i] = w[i][u];
+      T d = T(0);
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) d = fma(v[i], wn[i], d);
+      d = group_sum(d, 16);
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) xn[i] = fma(d * mtau, v[i], wn[i]);
+    }
+    T tau2, diag2, v2[RPL];
+    wave_reflector<T, RPL>(xn, jn, p, rg, tau2, diag2, v2);
+    // reflector j on every column q > j (column j+1 again, in its slot)
+    T d[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      d[u] = T(0);
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) d[u] = fma(v[i], w[i][u], d[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) d[u] = group_sum(d[u], 16);
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int q = cg + 4 * u;
+      const T f = (q > j && q < k) ? d[u] * mtau : T(0);
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) w[i][u] = fma(f, v[i], w[i][u]);
+    }
+    if (Vref && cg == jo)
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = rg + 16 * i;
+        if (r < p) Vref[(size_t)j * p + r] = v[i];
+      }
+    if (lane == 0) {
+      if (taus) taus[j] = tau;
+      Rp[j + (size_t)j * kr] = diag;
+    }
+    tau = tau2;
+    diag = diag2;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) v[i] = v2[i];
+  }
+  // R: the strict upper part of the first kr rows (diagonal stored above)
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int r = rg + 16 * i, q = cg + 4 * u;
+      if (r < kr && q < k && r != q) Rp[r + (size_t)q * kr] = (r < q) ? w[i][u] : T(0);
+    }
+}
+
+// Shape codes of k_gqr_wave: (rows per lane, column slots) for p <= 16*RPL,
+// k <= 4*CPL; FP64 panels use the shapes of at most 32 registers.  Taller
+// panels (p > 128) keep the four-wave kernels, which measure faster there.
+constexpr int kWaveQrShapes = 8;
+__host__ __device__ constexpr int wave_qr_rpl(int code) { return code < 3 ? 2 : code < 6 ? 4 : 8; }
+__host__ __device__ constexpr int wave_qr_cpl(int code) { return code < 6 ? 4 << (code % 3) : 4 << (code - 6); }
+
+// One wave (one workgroup) per panel; the job's shape code selects the body.
+template <typename T>
+__global__ __launch_bounds__(64) void k_gqr_wave(const QJob* __restrict__ jobs, int njobs) {
+  const QJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int prob = (int)(blockIdx.x - Jb.block0);
+  switch (Jb.pad) {
+    case 0: gqr_wave_body<T, 2, 4>(Jb, prob); break;
+    case 1: gqr_wave_body<T, 2, 8>(Jb, prob); break;
+    case 2: gqr_wave_body<T, 2, 16>(Jb, prob); break;
+    case 3: gqr_wave_body<T, 4, 4>(Jb, prob); break;
+    case 4: gqr_wave_body<T, 4, 8>(Jb, prob); break;
+    case 5: if constexpr (sizeof(T) == 4) gqr_wave_body<T, 4, 16>(Jb, prob); break;
+    case 6: gqr_wave_body<T, 8, 4>(Jb, prob); break;
+    default: if constexpr (sizeof(T) == 4) gqr_wave_body<T, 8, 8>(Jb, prob); break;
+  }
+}
+
 // ------------------------------------------------- QR, panel in registers
 // Householder QR of a p x k panel (p <= 64*QR_ROWS, k <= 4*QR_SLOTS) with the
 // panel in registers: wave w owns the columns q = w + 4u, lane l the rows
@@ -2500,18 +2672,34 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
   // Panels that fit 64 KB of LDS share one launch; larger ones (up to the
   // 160 KB a gfx950 workgroup may hold) get a launch of their own, so that
   // the many small panels keep their occupancy; the rest work in global memory.
+  // Panels of at most 64 register entries per lane go to k_gqr_wave (one wave
+  // each, group 4).
   std::vector<DBuf<T>> scratch;
-  std::vector<QJob> use[4];
-  size_t dyn[4] = {0, 0, 0, 0};
-  double fl[4] = {0, 0, 0, 0}, by[4] = {0, 0, 0, 0};
-  long long b0[4] = {0, 0, 0, 0};
+  std::vector<QJob> use[5];
+  size_t dyn[5] = {0, 0, 0, 0, 0};
+  double fl[5] = {0, 0, 0, 0, 0}, by[5] = {0, 0, 0, 0, 0};
+  long long b0[5] = {0, 0, 0, 0, 0};
+  auto wave_code = [](int p, int k) {
+    int best = -1;
+    for (int c = 0; c < kWaveQrShapes; ++c) {
+      const int rpl = wave_qr_rpl(c), cpl = wave_qr_cpl(c);
+      if (16 * rpl < p || 4 * cpl < k || rpl * cpl * (int)sizeof(T) > 256) continue;
+      if (best < 0 || rpl * cpl < wave_qr_rpl(best) * wave_qr_cpl(best)) best = c;
+    }
+    return best;
+  };
   for (auto& J : jobs) {
     if (J.p <= 0 || J.k <= 0 || J.nmat <= 0 || J.ncl <= 0) continue;
     const size_t np = (size_t)J.nmat * J.ncl;
     const size_t panel = (size_t)J.p * J.k * sizeof(T), vb = (size_t)J.p * sizeof(T);
     int g = 0;
     const int rows = (J.p + WAVE - 1) / WAVE, slots = (J.k + 3) / 4;
-    if (rows <= 8 && slots <= 16 && rows * slots * sizeof(T) <= 64 * 4) {   // panel in registers
+    const int wc = wave_code(J.p, J.k);
+    if (wc >= 0) {
+      g = 4;
+      J.lds = 0;
+      J.pad = wc;
+    } else if (rows <= 8 && slots <= 16 && rows * slots * sizeof(T) <= 64 * 4) {   // panel in registers
       g = 2;
       J.lds = 0;
       J.pad = (rows <= 1 ? 0 : rows <= 2 ? 1 : rows <= 4 ? 2 : 3) * 3 + (slots <= 4 ? 0 : slots <= 8 ? 1 : 2);
@@ -2526,13 +2714,18 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
       scratch.emplace_back(np * J.p * J.k);
       J.ws = scratch.back().get();
     }
-    if (g != 2) dyn[g] = std::max(dyn[g], J.lds ? panel + vb : vb);
+    if (g == 0 || g == 1 || g == 3) dyn[g] = std::max(dyn[g], J.lds ? panel + vb : vb);
     J.block0 = b0[g];
     b0[g] += (long long)np;
     const double p = J.p, k = J.k, kr = std::min(J.p, J.k);
     fl[g] += np * (p >= k ? 2.0 * k * k * (p - k / 3.0) : 2.0 * p * p * (k - p / 3.0));
     by[g] += (double)sizeof(T) * np * (p * k + kr * k + (J.Vref ? p * kr : 0.0));
     use[g].push_back(J);
+  }
+  if (!use[4].empty()) {
+    const QJob* dj = upload(use[4], st);
+    launch(st, KC_QR, fl[4], by[4], KNAME_T(k_gqr_wave<T>), k_gqr_wave<T>, dim3((unsigned)b0[4]), dim3(WAVE), 0, dj,
+           (int)use[4].size());
   }
   if (!use[2].empty() && b0[2] <= kSmallLaunch) {
     const QJob* dj = upload(use[2], st);
