@@ -1568,11 +1568,109 @@ __global__ __launch_bounds__(256) void k_gqr(const QJob* __restrict__ jobs, int 
   }
 }
 
+// Y = Q [Z; 0] with one wave per problem (p <= 16*RPL, t <= 4*CPL), in the
+// layout of the one-wave QR: lane l keeps rows rg + 16 i (rg = l mod 16) of
+// the output columns cg + 4 u (cg = l / 16), so a reflector step takes RPL
+// in-lane products and the in-row group_sum per column slot, and no barrier.
+// The reflectors and their taus are staged in LDS (vs); the next reflector is
+// read while the current one is applied.
+template <typename T, int RPL, int CPL>
+__device__ __forceinline__ void gapply_wave_body(const AJob& Jb, int prob, T* vs) {
+  const int p = Jb.p, c = Jb.c, t = Jb.t, ncl = Jb.ncl;
+  const int m = prob / ncl, cl = prob % ncl;
+  const BOp Y = Jb.Y;
+  T* y = const_cast<T*>(optr<T>(Y, m, cl));
+  const T* z = gmem(static_cast<const T*>(Jb.Z)) + (size_t)(m * ncl + (cl ^ Jb.zxor)) * Jb.sZ;
+  const T* vr = gmem(static_cast<const T*>(Jb.Vref)) + (size_t)prob * p * c;
+  const T* ta = gmem(static_cast<const T*>(Jb.tau)) + (size_t)prob * c;
+  const int lane = threadIdx.x % WAVE, rg = lane & 15, cg = lane >> 4;
+  T* ts = vs + (size_t)p * c;
+  for (int e = lane; e < p * c; e += WAVE) vs[e] = vr[e];
+  for (int e = lane; e < c; e += WAVE) ts[e] = ta[e];
+  T yr[RPL][CPL];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int r = rg + 16 * i, q = cg + 4 * u;
+      yr[i][u] = (r < c && q < t) ? z[r + (size_t)q * c] : T(0);
+    }
+  // wavefront-scope fence: the staged reflectors are visible to every lane
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  T vn[RPL], taun = c > 0 ? ts[c - 1] : T(0);
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int r = rg + 16 * i;
+    vn[i] = (c > 0 && r < p) ? vs[(size_t)(c - 1) * p + r] : T(0);
+  }
+  for (int j = c - 1; j >= 0; --j) {
+    T v[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) v[i] = vn[i];
+    const T mtau = -taun;
+    const int jn = j > 0 ? j - 1 : 0;
+    taun = ts[jn];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int r = rg + 16 * i;
+      vn[i] = r < p ? vs[(size_t)jn * p + r] : T(0);
+    }
+    T d[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      d[u] = T(0);
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) d[u] = fma(v[i], yr[i][u], d[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) d[u] = group_sum(d[u], 16) * mtau;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) yr[i][u] = fma(d[u], v[i], yr[i][u]);
+  }
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int r = rg + 16 * i, q = cg + 4 * u;
+      if (r < p && q < t) y[r + (long long)q * Y.ld] = yr[i][u];
+    }
+}
+
+// The job's shape code (RPL index * 3 + CPL index, each over {2, 4, 8})
+// selects the one-wave body; FP64 uses the shapes of at most 32 registers.
+template <typename T>
+__device__ __forceinline__ void gapply_wave(const AJob& Jb, int prob, T* vs) {
+  switch (Jb.pad) {
+    case 0: gapply_wave_body<T, 2, 2>(Jb, prob, vs); break;
+    case 1: gapply_wave_body<T, 2, 4>(Jb, prob, vs); break;
+    case 2: gapply_wave_body<T, 2, 8>(Jb, prob, vs); break;
+    case 3: gapply_wave_body<T, 4, 2>(Jb, prob, vs); break;
+    case 4: gapply_wave_body<T, 4, 4>(Jb, prob, vs); break;
+    case 5: gapply_wave_body<T, 4, 8>(Jb, prob, vs); break;
+    case 6: gapply_wave_body<T, 8, 2>(Jb, prob, vs); break;
+    case 7: gapply_wave_body<T, 8, 4>(Jb, prob, vs); break;
+    default: if constexpr (sizeof(T) == 4) gapply_wave_body<T, 8, 8>(Jb, prob, vs); break;
+  }
+}
+
 // Y = Q [Z; 0] for the Householder Q of a QR with reflectors (v_j, tau_j):
-// Y is p x t (column-major, ld = Y.ld, in place), Z is c x t (ld c).
+// Y is p x t (column-major, ld = Y.ld, in place), Z is c x t (ld c).  Jobs
+// with lds == 2 run four problems per workgroup, one wave each (gapply_wave,
+// reflectors in the wave's LDS slot of wslot elements); the others one problem
+// per workgroup.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gapply_q(const AJob* __restrict__ jobs, int njobs) {
   const AJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  if (Jb.lds == 2) {
+    extern __shared__ unsigned char smem_raw[];
+    const int wq = threadIdx.x / WAVE;
+    const long long pw = (long long)(blockIdx.x - Jb.block0) * 4 + wq;
+    if (pw >= (long long)Jb.nmat * Jb.ncl) return;
+    gapply_wave<T>(Jb, (int)pw, reinterpret_cast<T*>(smem_raw) + (size_t)wq * Jb.wslot);
+    return;
+  }
   const int prob = (int)(blockIdx.x - Jb.block0);
   const int p = Jb.p, c = Jb.c, t = Jb.t, ncl = Jb.ncl;
   const int m = prob / ncl, cl = prob % ncl;
@@ -2794,24 +2892,44 @@ void bqr_r(hipStream_t st, int p, int k, int nmat, int ncl, const BOp& A, T* R, 
 template <typename T>
 void gapply_q(hipStream_t st, std::vector<AJob> jobs) {
   // reflectors + output tile in LDS: up to 64 KB in one launch, up to the
-  // full gfx950 workgroup LDS in a second one, otherwise in global memory
+  // full gfx950 workgroup LDS in a second one, otherwise in global memory.
+  // Problems of at most 128 rows and 32 output columns whose reflectors take
+  // at most 16 KB run one wave each, four to a workgroup of launch 0.
   std::vector<AJob> use[2];
   size_t dyn[2] = {0, 0};
   double fl[2] = {0, 0}, by[2] = {0, 0};
   long long b0[2] = {0, 0};
+  auto ix = [](int n, int unit) { return n <= 2 * unit ? 0 : n <= 4 * unit ? 1 : 2; };
+  auto wave_ok = [&](const AJob& J, size_t need) {
+    const int code = ix(J.p, 16) * 3 + ix(J.t, 4);
+    return J.p <= 128 && J.t <= 32 && need <= 16384 && (sizeof(T) == 4 || code != 8);
+  };
+  size_t wneed = 0;
+  for (auto& J : jobs) {
+    if (J.p <= 0 || J.t <= 0 || J.nmat <= 0 || J.ncl <= 0) continue;
+    const size_t need = ((size_t)J.p * J.c + J.c) * sizeof(T);
+    if (wave_ok(J, need)) wneed = std::max(wneed, need);
+  }
+  dyn[0] = 4 * wneed;
   for (auto& J : jobs) {
     if (J.p <= 0 || J.t <= 0 || J.nmat <= 0 || J.ncl <= 0) continue;
     const size_t need = ((size_t)J.p * J.c + J.c) * sizeof(T);
     int g = 0;
+    const double np = (double)J.nmat * J.ncl;
+    long long nb = (long long)np;
     J.lds = J.p <= WAVE * kApplyRows && J.t <= 4 * kApplyCols;
-    if (J.lds && need + 2048 > kMaxLds) {
+    if (wave_ok(J, need)) {
+      J.lds = 2;
+      J.pad = ix(J.p, 16) * 3 + ix(J.t, 4);
+      J.wslot = (int)(wneed / sizeof(T));
+      nb = (nb + 3) / 4;
+    } else if (J.lds && need + 2048 > kMaxLds) {
       if (need <= kMaxDynLarge) g = 1;
       else J.lds = 0;
     }
-    if (J.lds) dyn[g] = std::max(dyn[g], need);
+    if (J.lds == 1) dyn[g] = std::max(dyn[g], need);
     J.block0 = b0[g];
-    const double np = (double)J.nmat * J.ncl;
-    b0[g] += (long long)np;
+    b0[g] += nb;
     fl[g] += 4.0 * np * J.t * ((double)J.p * J.c - 0.5 * J.c * J.c);
     by[g] += (double)sizeof(T) * np * ((double)J.p * J.c + (double)J.c * J.t + (double)J.p * J.t);
     use[g].push_back(J);

@@ -65,6 +65,7 @@ struct SJob {
 struct AJob {
   long long block0 = 0;
   int p = 0, c = 0, t = 0, nmat = 0, ncl = 0, zxor = 0, lds = 0, pad = 0;
+  int wslot = 0, pad2 = 0;
   const void* Vref = nullptr;
   const void* tau = nullptr;
   const void* Z = nullptr;
