@@ -1822,13 +1822,27 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
   }
   double fl = 0.0;
   int tp = 0;
+  // Cores of at most 16 (one wave): four columns at a time, one per row of
+  // 16 lanes (lane = row + 16 * column offset), summed by group_sum over 16
+  // lanes.
+  constexpr bool SMALL = CMAX <= 16 && NW == 1;
   for (int j = 0; j < c; ++j) {
-    for (int q = j + wv; q < c; q += NW) {
-      const T* col = W + (size_t)q * c;
-      double ss = 0.0;
-      for (int r = j + lane; r < c; r += WAVE) ss += (double)col[r] * (double)col[r];
-      ss = wave_sum(ss);
-      if (lane == 0) nrm[q] = ss;
+    if constexpr (SMALL) {
+      const int r = lane & 15;
+      for (int q0 = j; q0 < c; q0 += 4) {
+        const int q = q0 + (lane >> 4);
+        const double x = (q < c && r >= j && r < c) ? (double)W[r + (size_t)q * c] : 0.0;
+        const double ss = group_sum(x * x, 16);
+        if (r == 0 && q < c) nrm[q] = ss;
+      }
+    } else {
+      for (int q = j + wv; q < c; q += NW) {
+        const T* col = W + (size_t)q * c;
+        double ss = 0.0;
+        for (int r = j + lane; r < c; r += WAVE) ss += (double)col[r] * (double)col[r];
+        ss = wave_sum(ss);
+        if (lane == 0) nrm[q] = ss;
+      }
     }
     __syncthreads();
     if (tid < WAVE) {
@@ -1884,13 +1898,26 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
       for (int r = j + 1 + tid; r < c; r += NTH) W[r + (size_t)j * c] = (T)((double)W[r + (size_t)j * c] / v0);
       __syncthreads();
       const T* v = W + (size_t)j * c;
-      for (int q = j + 1 + wv; q < c; q += NW) {
-        T* col = W + (size_t)q * c;
-        T d = lane == 0 ? col[j] : T(0);
-        for (int r = j + 1 + lane; r < c; r += WAVE) d = fma(v[r], col[r], d);
-        d = wave_sum(d) * tau;
-        if (lane == 0) col[j] -= d;
-        for (int r = j + 1 + lane; r < c; r += WAVE) col[r] = fma(-d, v[r], col[r]);
+      if constexpr (SMALL) {
+        // v_j = 1 is implicit; rows below j hold v
+        const int r = lane & 15;
+        const T vr = r == j ? T(1) : (r > j && r < c) ? v[r] : T(0);
+        for (int q0 = j + 1; q0 < c; q0 += 4) {
+          const int q = q0 + (lane >> 4);
+          const bool ok = q < c && r >= j && r < c;
+          const T x = ok ? W[r + (size_t)q * c] : T(0);
+          const T d = group_sum(vr * x, 16) * tau;
+          if (ok) W[r + (size_t)q * c] = fma(-d, vr, x);
+        }
+      } else {
+        for (int q = j + 1 + wv; q < c; q += NW) {
+          T* col = W + (size_t)q * c;
+          T d = lane == 0 ? col[j] : T(0);
+          for (int r = j + 1 + lane; r < c; r += WAVE) d = fma(v[r], col[r], d);
+          d = wave_sum(d) * tau;
+          if (lane == 0) col[j] -= d;
+          for (int r = j + 1 + lane; r < c; r += WAVE) col[r] = fma(-d, v[r], col[r]);
+        }
       }
     }
     __syncthreads();
@@ -2090,14 +2117,26 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
     const T tau = (T)taus[j];
     if (tau == T(0)) continue;
     const T* v = W + (size_t)j * c;
-    for (int q = wv; q < tp; q += NW) {
-      T* col = Y + (size_t)q * c;
-      const T cj = col[j];
-      T d = T(0);
-      for (int r = j + 1 + lane; r < c; r += WAVE) d = fma(v[r], col[r], d);
-      d = (cj + wave_sum(d)) * tau;
-      for (int r = j + 1 + lane; r < c; r += WAVE) col[r] = fma(-d, v[r], col[r]);
-      if (lane == 0) col[j] = cj - d;
+    if constexpr (SMALL) {
+      const int r = lane & 15;
+      const T vr = r == j ? T(1) : (r > j && r < c) ? v[r] : T(0);
+      for (int q0 = 0; q0 < tp; q0 += 4) {
+        const int q = q0 + (lane >> 4);
+        const bool ok = q < tp && r >= j && r < c;
+        const T x = ok ? Y[r + (size_t)q * c] : T(0);
+        const T d = group_sum(vr * x, 16) * tau;
+        if (ok) Y[r + (size_t)q * c] = fma(-d, vr, x);
+      }
+    } else {
+      for (int q = wv; q < tp; q += NW) {
+        T* col = Y + (size_t)q * c;
+        const T cj = col[j];
+        T d = T(0);
+        for (int r = j + 1 + lane; r < c; r += WAVE) d = fma(v[r], col[r], d);
+        d = (cj + wave_sum(d)) * tau;
+        for (int r = j + 1 + lane; r < c; r += WAVE) col[r] = fma(-d, v[r], col[r]);
+        if (lane == 0) col[j] = cj - d;
+      }
     }
   }
   if constexpr (INLDS) {
