@@ -1822,17 +1822,18 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
   }
   double fl = 0.0;
   int tp = 0;
-  // Cores of at most 16 (one wave): four columns at a time, one per row of
-  // 16 lanes (lane = row + 16 * column offset), summed by group_sum over 16
-  // lanes.
-  constexpr bool SMALL = CMAX <= 16 && NW == 1;
+  // Cores of at most 32: each wave takes 64 / cgl columns at a time, one per
+  // group of cgl lanes (lane = row + cgl * column offset), summed by group_sum
+  // over cgl lanes; larger cores take one column per wave.
+  const int cgl = c <= 16 ? 16 : c <= 32 ? 32 : WAVE, cw = WAVE / cgl;
+  const bool grouped = cgl < WAVE;
   for (int j = 0; j < c; ++j) {
-    if constexpr (SMALL) {
-      const int r = lane & 15;
-      for (int q0 = j; q0 < c; q0 += 4) {
-        const int q = q0 + (lane >> 4);
+    if (grouped) {
+      const int r = lane % cgl;
+      for (int q0 = j + wv * cw; q0 < c; q0 += NW * cw) {
+        const int q = q0 + lane / cgl;
         const double x = (q < c && r >= j && r < c) ? (double)W[r + (size_t)q * c] : 0.0;
-        const double ss = group_sum(x * x, 16);
+        const double ss = group_sum(x * x, cgl);
         if (r == 0 && q < c) nrm[q] = ss;
       }
     } else {
@@ -1898,15 +1899,15 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
       for (int r = j + 1 + tid; r < c; r += NTH) W[r + (size_t)j * c] = (T)((double)W[r + (size_t)j * c] / v0);
       __syncthreads();
       const T* v = W + (size_t)j * c;
-      if constexpr (SMALL) {
+      if (grouped) {
         // v_j = 1 is implicit; rows below j hold v
-        const int r = lane & 15;
+        const int r = lane % cgl;
         const T vr = r == j ? T(1) : (r > j && r < c) ? v[r] : T(0);
-        for (int q0 = j + 1; q0 < c; q0 += 4) {
-          const int q = q0 + (lane >> 4);
+        for (int q0 = j + 1 + wv * cw; q0 < c; q0 += NW * cw) {
+          const int q = q0 + lane / cgl;
           const bool ok = q < c && r >= j && r < c;
           const T x = ok ? W[r + (size_t)q * c] : T(0);
-          const T d = group_sum(vr * x, 16) * tau;
+          const T d = group_sum(vr * x, cgl) * tau;
           if (ok) W[r + (size_t)q * c] = fma(-d, vr, x);
         }
       } else {
@@ -2117,14 +2118,14 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
     const T tau = (T)taus[j];
     if (tau == T(0)) continue;
     const T* v = W + (size_t)j * c;
-    if constexpr (SMALL) {
-      const int r = lane & 15;
+    if (grouped) {
+      const int r = lane % cgl;
       const T vr = r == j ? T(1) : (r > j && r < c) ? v[r] : T(0);
-      for (int q0 = 0; q0 < tp; q0 += 4) {
-        const int q = q0 + (lane >> 4);
+      for (int q0 = wv * cw; q0 < tp; q0 += NW * cw) {
+        const int q = q0 + lane / cgl;
         const bool ok = q < tp && r >= j && r < c;
         const T x = ok ? Y[r + (size_t)q * c] : T(0);
-        const T d = group_sum(vr * x, 16) * tau;
+        const T d = group_sum(vr * x, cgl) * tau;
         if (ok) Y[r + (size_t)q * c] = fma(-d, vr, x);
       }
     } else {
