@@ -53,6 +53,13 @@ def parse():
                     help="instead of the benchmark workload, time the paper's recirculating flow "
                          "(-Laplace u + ALPHA (cos 8 pi x, sin 8 pi y) . grad u, upwind) on the --n grid: "
                          "FP32 factor + FGMRES to --tol")
+    ap.add_argument("--config", type=int, default=2, choices=(2, 3, 5),
+                    help="2: the 1024^2 variable-kappa headline workload; 3: 256 independent problems of "
+                         "sides 64..256 (Poisson / variable kappa, leaf 32, eps 1e-8, 8 RHS) factored and "
+                         "solved as one batch; 5: the serving loop over 12 operators under Poisson arrivals")
+    ap.add_argument("--requests", type=int, default=2000, help="timed requests of --config 5")
+    ap.add_argument("--budget-gb", type=float, default=2.5, help="factor memory budget of --config 5")
+    ap.add_argument("--batch", type=int, default=256, help="problems of --config 3")
     ap.add_argument("--cpu-rows", type=int, default=16,
                     help="block rows of the operator the CPU oracle factors (bounded sample)")
     return ap.parse_args()
@@ -120,6 +127,162 @@ def bench_krylov_workload(acr, torch, W, args):
                       "fp64": res["fp64"]}), flush=True)
 
 
+def bench_batched(acr, torch, W, args):
+    """Config 3: `batch` independent problems, sides uniform over {64, 96, 128, 192, 256}, Poisson or
+    variable kappa with probability 1/2 each, 8 N(0,1) right-hand sides, leaf 32, eps 1e-8.  A step
+    is one batched factorisation (all problems in lockstep over the levels, each step of a level one
+    set of grouped launches) plus one batched solve; timed in FP64 and in the mixed form, next to the
+    same problems factored and solved one by one."""
+    import numpy as np
+    leaf, eps, nrhs = 32, 1e-8, 8
+    rng = np.random.default_rng(W.seed_for(3, 0))
+    sides = rng.choice([64, 96, 128, 192, 256], size=args.batch)
+    kinds = rng.integers(0, 2, size=args.batch)
+    probs = [W.poisson(int(s)) if k == 0 else W.varkappa(int(s), seed=W.seed_for(3, 1000 + i))
+             for i, (s, k) in enumerate(zip(sides, kinds))]
+    ops = [acr.Operator.from_arrays(st.nx, st.ny, *st.arrays()) for st in probs]
+    Bs = [torch.from_numpy(W.rhs(st.n, nrhs, seed=W.seed_for(3, 2000 + i))).cuda() for i, st in enumerate(probs)]
+    unknowns = sum(st.n for st in probs)
+    torch.cuda.synchronize()
+    res = {}
+
+    def batched(prec):
+        hs = acr.acr_factor_batched(ops, leaf, eps, prec)
+        xs = acr.acr_solve_batched(hs, Bs)
+        for h in hs:
+            acr.acr_destroy(h)
+        return xs
+
+    def one_by_one(prec):
+        xs = []
+        for op, B in zip(ops, Bs):
+            h = acr.acr_factor(op, leaf, eps, prec)
+            xs.append(acr.acr_solve(h, B))
+            acr.acr_destroy(h)
+        return xs
+
+    for prec in ("fp64", "mixed"):
+        for name, fn in (("batched", batched), ("one_by_one", one_by_one)):
+            for _ in range(max(args.warmup, 1)):
+                fn(prec)
+            torch.cuda.synchronize()
+            c0 = acr.acr_launch_count()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn(prec)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            res.setdefault(prec, {})[name] = {"ms_per_step": dt * 1e3, "unknowns_per_s": unknowns / dt,
+                                              "rhs_unknowns_per_s": unknowns * nrhs / dt,
+                                              "launches_per_step": (acr.acr_launch_count() - c0) / args.steps}
+    # bitwise check of a few problems: batched against alone (FP64)
+    xb = batched("fp64")
+    xo = one_by_one("fp64")
+    same = all(torch.equal(a, b) for a, b in zip(xb, xo))
+    b = res["fp64"]["batched"]
+    print(json.dumps({"metric": "ACR batched factor+solve unknowns/s, 256 independent problems",
+                      "value": b["unknowns_per_s"], "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": b["ms_per_step"], "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"{args.batch} problems, sides uniform over {{64,96,128,192,256}}, "
+                                             f"Poisson or variable kappa (p = 1/2), leaf {leaf}, eps {eps:g}, "
+                                             f"{nrhs} RHS; FP64 batched factor + batched solve",
+                                 "problems": args.batch, "unknowns": unknowns, "nrhs": nrhs},
+                      "batched_equals_one_by_one_bitwise": bool(same),
+                      "fp64": res["fp64"], "mixed": res["mixed"]}), flush=True)
+
+
+def bench_serving(acr, torch, W, args):
+    """Config 5: the library's serving loop over 12 operators (sides 128, 256, 512, 1024 x Poisson
+    (leaf 32, eps 1e-8) / variable kappa (leaf 64, eps 1e-6) / convection-diffusion (leaf 64,
+    eps 1e-7)), mixed factors, FP64 refinement of every request to 1e-10, factor memory budget below
+    the sum of the factors.  Requests pick an operator uniformly and 1..32 right-hand sides; a
+    saturated burst measures the capacity, then requests arrive as a Poisson process at 70% of it.
+    Reports RHS/s and p50/p99 latency (submit to completion) of the Poisson phase."""
+    import threading
+    import numpy as np
+    specs = []
+    for side in (128, 256, 512, 1024):
+        specs.append((W.poisson(side), 32, 1e-8))
+        specs.append((W.varkappa(side, seed=W.seed_for(5, side)), 64, 1e-6))
+        specs.append((W.convdiff(side, seed=W.seed_for(5, 10 + side)), 64, 1e-7))
+    srv = acr.Server(memory_budget=int(args.budget_gb * 2**30), tol=args.tol, maxit=50)
+    ids = [srv.add_operator(acr.Operator.from_arrays(st.nx, st.ny, *st.arrays()), leaf, eps, "mixed")
+           for st, leaf, eps in specs]
+    pools = [torch.from_numpy(W.rhs(st.n, 32, seed=W.seed_for(5, 500 + i))).cuda() for i, (st, _, _) in enumerate(specs)]
+    rng = np.random.default_rng(W.seed_for(5, 0))
+    torch.cuda.synchronize()
+
+    def request():
+        o = int(rng.integers(0, len(specs)))
+        k = int(rng.integers(1, 33))
+        return o, pools[o][:, :k]
+
+    def run(n, rate=None):
+        done = []
+        rids = []
+        lock = threading.Condition()
+
+        def waiter():
+            i = 0
+            while True:
+                with lock:
+                    while i >= len(rids):
+                        lock.wait()
+                    rid = rids[i]
+                if rid is None:
+                    return
+                done.append(srv.wait(rid, raise_on_fail=False)[1:])
+                i += 1
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        t_next = t0
+        for _ in range(n):
+            if rate:
+                t_next += rng.exponential(1.0 / rate)
+                dt = t_next - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            o, b = request()
+            rid = srv.submit(ids[o], b)
+            with lock:
+                rids.append(rid)
+                lock.notify()
+        with lock:
+            rids.append(None)
+            lock.notify()
+        th.join()
+        return time.perf_counter() - t0, done
+
+    run(len(specs) * 2)                       # warm-up: every operator factored once
+    srv.stats(reset=True)
+    ncap = max(200, args.requests // 8)
+    tcap, _ = run(ncap)
+    cap = srv.stats(reset=True)
+    capacity = cap["requests"] / max(cap["seconds"], 1e-9)
+    wall, done = run(args.requests, rate=0.7 * capacity)
+    st = srv.stats(reset=True)
+    srv.close()
+    print(json.dumps({"metric": "ACR serving RHS/s at 70% load, p50/p99 latency", "value": st["rhs_per_s"],
+                      "unit": "rhs/s", "n_gpus": 1, "steps": args.requests, "warmup": len(specs) * 2,
+                      "ms_per_step": st["seconds"] * 1e3 / max(st["requests"], 1), "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "serving: 12 operators (sides 128/256/512/1024 x Poisson leaf 32 "
+                                             "eps 1e-8 / variable kappa leaf 64 eps 1e-6 / convection-diffusion "
+                                             "leaf 64 eps 1e-7), mixed factors + FP64 refinement to "
+                                             f"{args.tol:g}, 1..32 RHS per request, Poisson arrivals at 70% of "
+                                             f"capacity, factor budget {args.budget_gb:g} GiB",
+                                 "requests": args.requests, "budget_bytes": int(args.budget_gb * 2**30)},
+                      "latency_p50_ms": st["latency_p50_ms"], "latency_p99_ms": st["latency_p99_ms"],
+                      "latency_max_ms": st["latency_max_ms"], "requests_per_s": st["requests_per_s"],
+                      "arrival_rate_per_s": 0.7 * capacity, "capacity_requests_per_s": capacity,
+                      "capacity_rhs_per_s": cap["rhs_per_s"], "factorizations": st["factorizations"],
+                      "evictions": st["evictions"], "peak_resident_bytes": st["peak_resident_bytes"],
+                      "not_converged": sum(1 for d in done if d[1] > args.tol)}), flush=True)
+
+
 def dominant_kernel(acr, torch, op, b, args, precision):
     """One profiled step with every launch timed: the kernel with the most time,
     its class, and the per-class totals."""
@@ -176,12 +339,16 @@ def traffic_per_launch(name):
 
 
 def roofline(row, precision):
+    """Roofline of the dominant kernel: algorithmic work per launch (counted from the shapes at
+    the blocks' numerical ranks) over the average launch time, measured with HIP events recorded
+    on the launch stream around each launch of the kernel (so it includes the dispatch; the
+    rocprofv3 kernel time of the same command is in profiles/)."""
     name, cls, launches, ms, flops, nbytes = row
     launches = max(launches, 1)
     avg_s = ms / 1e3 / launches
     traffic = traffic_per_launch(name)
     common = {"kernel": name, "kernel_class": cls, "launches": launches, "avg_launch_us": avg_s * 1e6,
-              "traffic": traffic}
+              "traffic": traffic, "timing": "HIP events around each launch on its stream (includes dispatch)"}
     if cls in ("gemm", "qr", "applyq", "svd", "inverse"):
         # vector-ALU kernels (FP32 in the mixed form; the small inverses work in FP64)
         peak = PEAKS["fp64_vector_TF"] if (precision == "fp64" or cls == "inverse") else PEAKS["fp32_vector_TF"]
@@ -193,37 +360,117 @@ def roofline(row, precision):
             "frac": ach / PEAKS["hbm_GBs"], "bytes_per_launch": nbytes / launches, **common}
 
 
-def cpu_baseline(args):
-    """The CPU oracle (FP64 ACR, formatted arithmetic) on a bounded sample of
-    the same workload: the first `cpu_rows` block rows of the 1024 x 1024
-    operator (same block size, leaf, eps), factor + solve, timed on the host;
-    scaled to the full problem by the number of block eliminations."""
+def host_description():
+    """CPU model, BLAS library and its thread count of the host the oracle runs on."""
+    info = {"cpu_model": None, "nproc": os.cpu_count(), "blas": None, "blas_threads": None}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        if blas:
+            p = blas[0]
+            info["blas"] = f"{p.get('internal_api')} {p.get('version')} ({p.get('prefix')})"
+            info["blas_threads"] = max(q.get("num_threads", 1) for q in blas)
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline(args, strip):
+    """The CPU oracle (FP64 ACR, dense-then-compress formatted arithmetic) on a bounded
+    sample of the same workload: the first `cpu_rows` block rows of the operator (same block
+    size, leaf, eps), factor + solve, timed on the host and scaled to the full problem by
+    the number of block eliminations.  Also the whole small Poisson workload (64 x 64,
+    leaf 16, eps 1e-10) timed without extrapolation.  Returns (baseline dict, oracle factor
+    of the strip, strip right-hand side, oracle solution) for the forward-error check."""
     import numpy as np
     import workloads as W
     from oracle import acr as oacr
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        cores = os.cpu_count()
-    full = W.varkappa(args.n)
-    r = args.cpu_rows
-    s = full.nx
-    sub = W.Stencil(s, r, *(a[: r * s].copy() for a in full.arrays()), name="varkappa-strip")
-    sub.north[(r - 1) * s:] = 0.0
-    b = W.rhs(sub.n, 1)
+    host = host_description()
+    cores = host["blas_threads"] or host["nproc"]
+    r = strip.ny
+    b = W.rhs(strip.n, 1)
     t0 = time.perf_counter()
-    fac = oacr.factor(sub, args.leaf, args.eps)
-    oacr.solve(fac, sub, b)
+    fac = oacr.factor(strip, args.leaf, args.eps)
+    xo = oacr.solve(fac, strip, b)
     dt = time.perf_counter() - t0
     elim_sub = r - 1
     elim_full = args.n - 1
     est = dt * elim_full / elim_sub
-    return {"value": full.n / est, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle ACR factor+solve of the first {r} block rows of the {args.n}x{args.n} "
-                      f"variable-kappa operator (leaf {args.leaf}, eps {args.eps:g}): {dt:.1f} s for "
-                      f"{elim_sub} block eliminations, scaled to the {elim_full} of the full grid",
-            "sample_seconds": dt, "estimated_full_seconds": est}
+    # config 1 in full: median of three
+    st1 = W.poisson(64)
+    b1 = W.rhs(st1.n, 1)
+    t1 = []
+    for _ in range(3):
+        t = time.perf_counter()
+        oacr.solve(oacr.factor(st1, 16, 1e-10), st1, b1)
+        t1.append(time.perf_counter() - t)
+    t1 = sorted(t1)[1]
+    out = {"value": (args.n * args.n) / est, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
+           "sample": f"oracle ACR factor+solve of the first {r} block rows of the {args.n}x{args.n} "
+                     f"variable-kappa operator (leaf {args.leaf}, eps {args.eps:g}): {dt:.1f} s for "
+                     f"{elim_sub} block eliminations, scaled to the {elim_full} of the full grid",
+           "sample_seconds": dt, "estimated_full_seconds": est,
+           "host": host,
+           "poisson64_full": {"seconds": t1, "unknowns_per_s": st1.n / t1,
+                              "workload": "Poisson 64x64, leaf 16, eps 1e-10, factor+solve, median of 3, "
+                                          "not extrapolated"},
+           "caveat": "the oracle is plain dense-then-compress NumPy (every H-operation densified, "
+                     "O(s^3) per block): it measures a readable reference, not the complexity of ACR "
+                     "or a tuned CPU H-matrix library"}
+    return out, b, xo
+
+
+def gpu_forward_errors(acr, torch, args, strip, b, xo):
+    """Forward error ||x_gpu - x_oracle|| / ||x_oracle|| of one solve (no refinement) on the
+    strip the oracle factored, for the FP64 and the mixed form (gate: 10 eps for FP64)."""
+    import numpy as np
+    op = acr.Operator.from_arrays(strip.nx, strip.ny, *strip.arrays())
+    out = {"strip_rows": strip.ny, "ten_eps": 10 * args.eps}
+    for prec in ("fp64", "mixed"):
+        h = acr.acr_factor(op, args.leaf, args.eps, prec)
+        x = acr.acr_solve(h, torch.from_numpy(b).cuda()).cpu().numpy()
+        acr.acr_destroy(h)
+        out[prec] = float(np.linalg.norm(x - xo) / np.linalg.norm(xo))
+    return out
+
+
+def factor_and_pass(acr, torch, op, args, precision, reps):
+    """Factor time (ms, acr_factor synchronises its stream), one-RHS solve-pass time (ms,
+    HIP events over `reps` back-to-back passes), the handle's info and the launches of a
+    factor and of a pass."""
+    torch.cuda.synchronize()
+    c0 = acr.acr_launch_count()
+    t0 = time.perf_counter()
+    h = acr.acr_factor(op, args.leaf, args.eps, precision)
+    torch.cuda.synchronize()
+    t_factor = (time.perf_counter() - t0) * 1e3
+    c1 = acr.acr_launch_count()
+    b = torch.randn(op.n, dtype=torch.float64, device="cuda")
+    acr.acr_solve(h, b)
+    torch.cuda.synchronize()
+    c2 = acr.acr_launch_count()
+    acr.acr_solve(h, b)
+    c3 = acr.acr_launch_count()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        acr.acr_solve(h, b)
+    e1.record()
+    torch.cuda.synchronize()
+    t_pass = e0.elapsed_time(e1) / reps
+    info = acr.acr_get_info(h)
+    acr.acr_destroy(h)
+    return t_factor, t_pass, info, c1 - c0, c3 - c2
 
 
 def main():
@@ -252,6 +499,12 @@ def main():
     if args.helmholtz is not None or args.recirculating is not None:
         bench_krylov_workload(acr, torch, W, args)
         return
+    if args.config == 3:
+        bench_batched(acr, torch, W, args)
+        return
+    if args.config == 5:
+        bench_serving(acr, torch, W, args)
+        return
     st = W.varkappa(args.n)
     op = acr.Operator.from_arrays(st.nx, st.ny, *st.arrays())
     b = torch.from_numpy(W.rhs(st.n, 1)).cuda()
@@ -263,12 +516,12 @@ def main():
     kname, cls, table = dominant_kernel(acr, torch, op, b, args, "mixed")
     # the reported time comes from steps without per-launch events; the dominant kernel's
     # launch times from the same number of steps with HIP events around its launches
+    c0 = acr.acr_launch_count()
     ms, its, rel, _ = run_steps(acr, torch, op, b, args, "mixed", args.steps)
+    launches_per_step = (acr.acr_launch_count() - c0) / args.steps
     _, _, _, prof = run_steps(acr, torch, op, b, args, "mixed", args.steps, profile_cls=cls)
     krow = next(r for r in prof if r[0] == kname)
-    h = acr.acr_factor(op, args.leaf, args.eps, "mixed")
-    info = acr.acr_get_info(h)
-    acr.acr_destroy(h)
+    t_factor, t_pass, info, nl_factor, nl_pass = factor_and_pass(acr, torch, op, args, "mixed", 10)
     out = {
         "metric": METRIC,
         "value": st.n / (ms / 1e3),
@@ -289,9 +542,27 @@ def main():
                    "precision": "mixed", "refine_tol": args.tol},
         "refine_iterations": its,
         "relres": rel,
+        "launches_per_step": launches_per_step,
         "factor_max_rank": info["max_rank"],
         "factor_bytes": info["factor_bytes"],
         "roofline": roofline(krow, "mixed"),
+        "factor": {"ms": t_factor, "launches": nl_factor, "flops": info["factor_flops"],
+                   "achieved_TFLOPs": info["factor_flops"] / t_factor / 1e9,
+                   "peak_TFLOPs": PEAKS["fp32_vector_TF"],
+                   "frac": info["factor_flops"] / t_factor / 1e9 / PEAKS["fp32_vector_TF"],
+                   "note": "flops counted from the shapes processed (padded ranks), FP32 peak"},
+        "solve_pass": {"ms": t_pass, "launches": nl_pass, "bytes_ranked": info["solve_bytes_ranked"],
+                       "bytes_stored": info["solve_bytes"],
+                       "achieved_GBs": info["solve_bytes_ranked"] / t_pass / 1e6,
+                       "peak_GBs": PEAKS["hbm_GBs"],
+                       "frac": info["solve_bytes_ranked"] / t_pass / 1e6 / PEAKS["hbm_GBs"],
+                       "note": "one FP32 pass, 1 RHS: stored-factor bytes at the numerical ranks "
+                               "over the pass time (HIP events)"},
+        "padding": {"factor_bytes_stored": info["factor_bytes"],
+                    "factor_bytes_ranked": info["factor_bytes_ranked"],
+                    "ratio": info["factor_bytes"] / info["factor_bytes_ranked"],
+                    "level_max_rank": info["level_max_rank"],
+                    "level_mean_rank": [round(v, 2) for v in info["level_mean_rank"]]},
         "kernel_classes_ms": {k: round(v["total_ms"], 3) for k, v in table.items()},
     }
     # the same step with FGMRES (ACR as right preconditioner, FP64 Krylov vectors) in
@@ -303,11 +574,19 @@ def main():
     if not args.no_fp64:
         run_steps(acr, torch, op, b, args, "fp64", 1)
         ms64, its64, rel64, _ = run_steps(acr, torch, op, b, args, "fp64", args.steps)
+        tf64, tp64, info64, _, _ = factor_and_pass(acr, torch, op, args, "fp64", 10)
         out["fp64"] = {"value": st.n / (ms64 / 1e3), "ms_per_step": ms64, "refine_iterations": its64,
-                       "relres": rel64, "dtype": "f64"}
+                       "relres": rel64, "dtype": "f64",
+                       "factor": {"ms": tf64, "achieved_TFLOPs": info64["factor_flops"] / tf64 / 1e9,
+                                  "peak_TFLOPs": PEAKS["fp64_vector_TF"],
+                                  "frac": info64["factor_flops"] / tf64 / 1e9 / PEAKS["fp64_vector_TF"]},
+                       "solve_pass": {"ms": tp64, "achieved_GBs": info64["solve_bytes_ranked"] / tp64 / 1e6,
+                                      "frac": info64["solve_bytes_ranked"] / tp64 / 1e6 / PEAKS["hbm_GBs"]}}
         out["mixed_over_fp64"] = ms64 / ms
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args)
+        strip = W.strip(st, args.cpu_rows)
+        out["cpu_baseline"], bs, xo = cpu_baseline(args, strip)
+        out["forward_error_vs_oracle"] = gpu_forward_errors(acr, torch, args, strip, bs, xo)
     print(json.dumps(out), flush=True)
 
 

@@ -25,8 +25,17 @@
  *    returning.
  *  - Every entry point returns an acr_status; on error no output is valid and
  *    acr_last_error() describes the failure (thread-local text).
- *  - The library allocates its own device memory (factor storage and
- *    workspace) with hipMalloc through an internal caching pool.
+ *  - Device memory (factor storage and workspace) comes from an internal
+ *    caching pool, which takes it from hipMalloc or, after
+ *    acr_set_allocator, from the caller's allocator.  A block freed by work
+ *    of one host thread on one stream is reused only by later work of the
+ *    same thread on the same stream (or after a device synchronisation), so
+ *    calls on different streams never share a buffer that is still in use.
+ *  - Threads: each host thread has its own launch queue and descriptor
+ *    arena, so different threads may call the library at the same time on
+ *    different handles.  Calls that use the same handle from two threads at
+ *    once are not supported (the handle is read-only after acr_factor, but
+ *    acr_destroy must not overlap any other call on it).
  */
 #ifndef ACR_H
 #define ACR_H
@@ -97,6 +106,14 @@ typedef struct {
                                    from the shapes actually processed */
   double solve_bytes;           /* stored-factor bytes one solve pass reads */
   double solve_flops_per_rhs;   /* flops of one solve pass per right-hand side */
+  /* Ranks are stored padded: every block of one (set, HODLR depth) holds the
+   * set's largest rank, the extra columns zero.  The figures below count the
+   * blocks at their own numerical ranks instead. */
+  double factor_bytes_ranked;   /* stored factor without the padding columns */
+  double solve_bytes_ranked;    /* solve_bytes without the padding columns */
+  double level_mean_rank[40];   /* per CR level: mean numerical rank of the
+                                   stored off-diagonal blocks of X, E, F */
+  int64_t factor_launches;      /* kernel launches of the factorisation */
 } acr_info;
 
 typedef struct acr_handle_s* acr_handle;   /* opaque; owned by the library */
@@ -113,18 +130,45 @@ typedef struct acr_handle_s* acr_handle;   /* opaque; owned by the library */
 acr_status acr_factor(const acr_operator* op, const acr_options* opt, void* stream,
                       acr_handle* out);
 
+/* Factor `count` independent problems at once (the even blocks of every
+ * level are independent, Section 3; so are separate systems): ops[p] is the
+ * p-th operator (host array of count structs, their arrays on the device;
+ * block sizes and counts may differ), opt applies to all.  The problems run
+ * in lockstep over the cyclic-reduction levels and each step of a level is
+ * one set of grouped kernel launches for all of them.  Every kernel variant
+ * is picked by the shape of its own problem, so out[p] (host array of count
+ * handles, each destroyed with acr_destroy) holds the same factor, bit for
+ * bit, as acr_factor(&ops[p], opt, ...).  On any error no handle is
+ * returned; ACR_ERR_SINGULAR / ACR_ERR_INVALID_ARG name the problem in
+ * acr_last_error().  acr_get_info of each handle reports the flops and
+ * launches of the whole batch.  Blocks until done on `stream`. */
+acr_status acr_factor_batched(const acr_operator* ops, const acr_options* opt, int32_t count, void* stream,
+                              acr_handle* out);
+
+/* X[p] = M_p^{-1} B[p] for count handles at once (host arrays of count device
+ * pointers, FP64 N_p x nrhs[p] column-major, ld N_p): the forward and back
+ * substitution steps of all problems with at most 8 right-hand sides share
+ * their launches (per precision); problems with more right-hand sides are
+ * solved one after the other.  Results equal acr_solve's bit for bit.  X[p]
+ * may alias B[p]; X[p] must not overlap X[q] or B[q] for q != p
+ * (ACR_ERR_INVALID_ARG).  Asynchronous on `stream`. */
+acr_status acr_solve_batched(const acr_handle* hs, const double* const* B, double* const* X, const int32_t* nrhs,
+                             int32_t count, void* stream);
+
 /* X = M^{-1} B with M the stored ACR factor (Section 3: forward reduction of
  * f, Eq. "fund", then back-substitution u_k = X_k (f_k - E_k u_{k-1} - F_k
  * u_{k+1})).  B, X: N x nrhs FP64, column-major, ld = N; X may alias B.
  * In ACR_MIXED_FP32 the pass runs in FP32 (B rounded on entry).  Asynchronous
- * on `stream` (no host synchronisation), so it may be captured in a graph
- * after a first call with the same nrhs has sized the workspace. */
+ * on `stream` (no host synchronisation); its workspace comes from the pool on
+ * every call, so the call is not meant for stream capture. */
 acr_status acr_solve(acr_handle h, const double* B, double* X, int32_t nrhs, void* stream);
 
 /* Iterative refinement with ACR as the preconditioner (Section 4, closing
  * paragraph): x_0 = 0, r = B - A x in FP64, x += M^{-1} r, until
  * max_col ||r||_2/||B||_2 <= tol or maxit corrections.  op must be the
- * operator that was factored.  iters, relres: host outputs (may be NULL).
+ * operator that was factored.  B, X: N x nrhs FP64 column-major (ld = N);
+ * X must not overlap B (B is read by every residual): ACR_ERR_INVALID_ARG.
+ * iters, relres: host outputs (may be NULL).
  * ACR_ERR_NOT_CONVERGED (X holds the last iterate) if tol is not reached. */
 acr_status acr_solve_refined(acr_handle h, const acr_operator* op, const double* B, double* X,
                              int32_t nrhs, double tol, int32_t maxit, int32_t* iters,
@@ -139,7 +183,7 @@ acr_status acr_solve_refined(acr_handle h, const acr_operator* op, const double*
  * the least-squares solution of the Hessenberg system (Givens rotations on
  * the host).  Stops when the true relative residual ||b - A x||/||b|| <= tol
  * or after maxit applications of M^{-1}.  op must be the factored operator.
- * B, X: N x nrhs FP64 column-major (ld = N); X must not alias B.  iters,
+ * B, X: N x nrhs FP64 column-major (ld = N); X must not overlap B.  iters,
  * relres: host outputs (may be NULL): the largest preconditioner count and
  * relative residual over the columns.  Workspace: (2 restart + 3) N doubles.
  * ACR_ERR_NOT_CONVERGED (X holds the last iterate) if tol is not reached.
@@ -205,15 +249,98 @@ acr_status acr_profile_read(int32_t cls, int64_t* launches, double* total_ms, do
  *   "kernel <name> <class> <launches> <ms> <flops> <bytes>"  per kernel, with
  *       the name as kernel statistics of rocprofv3 print it ("k_gqr<float>");
  *   "stagekernel <stage> <name> <launches> <ms> <flops> <bytes>"  per (stage,
- *       kernel) over all levels.
+ *       kernel) over all levels;
+ *   "path <name> <problems>"  per kernel path (variant and operand class,
+ *       e.g. "qr.reg.p>128"): the number of batched problems planned on it.
  * flops and bytes are the algorithmic counts of those launches.  Writes at
  * most len bytes including the terminating NUL into buf (host memory, owned
  * by the caller; may be NULL with len 0); *needed (may be NULL) receives the
  * full length.  Waits for the recorded events. */
 acr_status acr_profile_report(char* buf, int64_t len, int64_t* needed);
 
-/* Release the library's cached (unused) device memory. */
+/* ---------------------------------------------------------------- serving
+ * A server keeps the factors of registered operators resident in device
+ * memory under a byte budget and solves requests A x = b (FP64 right-hand
+ * sides) by iterative refinement with the factor as preconditioner (Section
+ * 4, closing paragraph), to the relative residual `tol` of its config.  One
+ * worker thread and one stream per server.  A request whose operator has no
+ * resident factor waits until the factor fits next to the resident ones
+ * (idle factors are evicted least recently used first; a factor larger than
+ * the whole budget is admitted alone), then its operator is factored,
+ * together with every other operator admitted at that moment (one batched
+ * factorisation).  Active requests advance together one refinement step at a
+ * time (residuals, norms, corrections and updates of all of them in shared
+ * launches); requests that arrive meanwhile join at the next step.  A
+ * request's arithmetic does not depend on the other requests, so its X is
+ * the same bits alone and in any mix. */
+typedef struct acr_server_s* acr_server;
+
+typedef struct {
+  int64_t memory_budget;   /* device bytes the resident factors may take (> 0) */
+  double tol;              /* refinement target: max_col ||b - A x|| / ||b|| <= tol */
+  int32_t maxit;           /* refinement corrections at most (>= 0) */
+} acr_server_config;
+
+typedef struct {
+  int64_t requests, rhs, steps;        /* completed requests / right-hand sides, refinement steps */
+  int64_t factorizations, evictions;   /* factors computed / evicted */
+  int64_t resident_bytes, peak_resident_bytes;
+  double seconds;                      /* first submit to last completion */
+  double requests_per_s, rhs_per_s;
+  double latency_p50_ms, latency_p99_ms, latency_max_ms;   /* submit to completion */
+  double busy_s;                       /* worker time spent admitting and stepping */
+} acr_server_info;
+
+/* Start a server on the current device (config: host struct).  *out: host. */
+acr_status acr_server_create(const acr_server_config* cfg, acr_server* out);
+
+/* Register an operator with its factorisation options; the server keeps its
+ * own device copy of the operator (op's arrays may be freed afterwards).
+ * *op_id (host) identifies it in acr_server_submit.  Synchronises the
+ * device.  No factorisation happens before the first request. */
+acr_status acr_server_add_operator(acr_server s, const acr_operator* op, const acr_options* opt, int32_t* op_id);
+
+/* Queue X = A^{-1} B for operator op_id: B, X device arrays N x nrhs FP64
+ * (column-major, ld N), X must not overlap B; both must stay valid until
+ * acr_server_wait returns for this request.  The server's stream waits for
+ * the work enqueued so far on `stream` before it reads B.  *request (host)
+ * receives the request id.  Returns at once. */
+acr_status acr_server_submit(acr_server s, int32_t op_id, const double* B, double* X, int32_t nrhs,
+                             void* stream, int64_t* request);
+
+/* Block until the request completes; then X holds the solution (device work
+ * done).  iters, relres, latency_ms (host, may be NULL): refinement
+ * corrections, final relative residual, submit-to-completion time.
+ * ACR_ERR_NOT_CONVERGED if tol was not reached in maxit corrections.  Each
+ * request is waited for once. */
+acr_status acr_server_wait(acr_server s, int64_t request, int32_t* iters, double* relres, double* latency_ms);
+
+/* Statistics of the requests completed since the last reset (reset != 0
+ * starts a new window after filling *out). */
+acr_status acr_server_stats(acr_server s, int32_t reset, acr_server_info* out);
+
+/* Finish every queued request, stop the worker and free the server. */
+acr_status acr_server_destroy(acr_server s);
+
+/* Number of kernel launches (and device fills) the calling thread has
+ * issued through the library so far (for launch counts per step). */
+int64_t acr_launch_count(void);
+
+/* Release the library's cached (unused) device memory: the blocks cached for
+ * the calling thread and the idle ones. */
 acr_status acr_trim_pool(void);
+
+/* Device memory source of the library (the boundary's allocator hook, for
+ * callers such as PyTorch that own device memory).  alloc(bytes, stream)
+ * returns a device pointer (NULL on failure, reported as ACR_ERR_OOM) whose
+ * memory may be used on `stream` (a hipStream_t); free(ptr, stream) returns
+ * it.  Passing NULL for both restores hipMalloc / hipFree.  Allowed only
+ * while the library holds no live device allocation (no handle exists):
+ * otherwise ACR_ERR_INVALID_ARG.  Cached blocks of the previous source are
+ * returned to it first.  The callbacks may be called from any library call
+ * of any thread, between the calls' kernel launches. */
+acr_status acr_set_allocator(void* (*alloc_fn)(size_t bytes, void* stream),
+                             void (*free_fn)(void* ptr, void* stream));
 
 #ifdef __cplusplus
 }

@@ -51,7 +51,9 @@ class _Info(ctypes.Structure):
                 ("depth", ctypes.c_int32), ("levels", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("factor_bytes", ctypes.c_int64), ("max_rank", ctypes.c_int32),
                 ("level_max_rank", ctypes.c_int32 * 40), ("factor_flops", ctypes.c_double),
-                ("solve_bytes", ctypes.c_double), ("solve_flops_per_rhs", ctypes.c_double)]
+                ("solve_bytes", ctypes.c_double), ("solve_flops_per_rhs", ctypes.c_double),
+                ("factor_bytes_ranked", ctypes.c_double), ("solve_bytes_ranked", ctypes.c_double),
+                ("level_mean_rank", ctypes.c_double * 40), ("factor_launches", ctypes.c_int64)]
 
 
 _lib = None
@@ -157,6 +159,45 @@ def acr_factor(op: Operator, leaf: int, eps: float, precision="fp64", max_rank: 
     return Handle(out.value, op, prec)
 
 
+def acr_factor_batched(ops, leaf: int, eps: float, precision="fp64", max_rank: int = 0,
+                       inner_eps: float = 0.0, stream=None):
+    """Factor several independent problems in one lockstep pass; returns one Handle per operator."""
+    lib = load()
+    lib.acr_factor_batched.argtypes = [ctypes.POINTER(_Operator), ctypes.POINTER(_Options), ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    lib.acr_factor_batched.restype = ctypes.c_int
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    opt = _Options(int(leaf), float(eps), prec, int(max_rank), float(inner_eps))
+    n = len(ops)
+    arr = (_Operator * n)(*[o._c() for o in ops])
+    out = (ctypes.c_void_p * n)()
+    _check(lib.acr_factor_batched(arr, ctypes.byref(opt), n, _stream(stream), out))
+    return [Handle(out[i], ops[i], prec) for i in range(n)]
+
+
+def acr_solve_batched(handles, Bs, stream=None):
+    """X_p = M_p^{-1} B_p for several handles at once (shared launches); returns the list of X."""
+    import torch
+    lib = load()
+    lib.acr_solve_batched.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.c_int32, ctypes.c_void_p]
+    lib.acr_solve_batched.restype = ctypes.c_int
+    n = len(handles)
+    cols = [_as_colmajor(B, h.nx * h.ny) for h, B in zip(handles, Bs)]
+    outs = [torch.empty_like(c) for c in cols]
+    hp = (ctypes.c_void_p * n)(*[h.ptr for h in handles])
+    bp = (ctypes.c_void_p * n)(*[c.data_ptr() for c in cols])
+    xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in outs])
+    nr = (ctypes.c_int32 * n)(*[c.shape[0] for c in cols])
+    _check(lib.acr_solve_batched(hp, bp, xp, nr, n, _stream(stream)))
+    res = []
+    for B, X in zip(Bs, outs):
+        X = X.t()
+        res.append(X.reshape(B.shape) if B.dim() == 1 else X)
+    return res
+
+
 def acr_solve(h: Handle, B, stream=None):
     import torch
     lib = load()
@@ -222,9 +263,17 @@ def acr_get_info(h: Handle) -> dict:
     lib = load()
     inf = _Info()
     _check(lib.acr_get_info(h.ptr, ctypes.byref(inf)))
-    d = {f: getattr(inf, f) for f, _ in _Info._fields_ if f != "level_max_rank"}
+    d = {f: getattr(inf, f) for f, _ in _Info._fields_ if f not in ("level_max_rank", "level_mean_rank")}
     d["level_max_rank"] = list(inf.level_max_rank)[: inf.levels]
+    d["level_mean_rank"] = list(inf.level_mean_rank)[: inf.levels]
     return d
+
+
+def acr_launch_count() -> int:
+    """Kernel launches the calling thread has issued through the library so far."""
+    lib = load()
+    lib.acr_launch_count.restype = ctypes.c_int64
+    return int(lib.acr_launch_count())
 
 
 def acr_get_block(h: Handle, level: int, which: int, k: int, stream=None) -> np.ndarray:
@@ -242,6 +291,55 @@ def acr_destroy(h: Handle):
 
 def acr_trim_pool():
     _check(load().acr_trim_pool())
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = None   # keeps the installed ctypes callbacks alive
+
+
+def acr_set_allocator(alloc=None, free=None):
+    """Install Python callables alloc(nbytes, stream_handle) -> device pointer (int) and
+    free(ptr, stream_handle) as the library's device-memory source (None, None restores
+    hipMalloc).  Fails with ACR_ERR_INVALID_ARG while a handle is alive."""
+    global _allocator_refs
+    lib = load()
+    lib.acr_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN]
+    lib.acr_set_allocator.restype = ctypes.c_int
+    if alloc is None and free is None:
+        _check(lib.acr_set_allocator(ctypes.cast(None, _ALLOC_FN), ctypes.cast(None, _FREE_FN)))
+        _allocator_refs = None
+        return
+
+    def _a(nbytes, stream):
+        try:
+            return int(alloc(int(nbytes), stream or 0))
+        except Exception:
+            return None
+
+    def _f(ptr, stream):
+        try:
+            free(int(ptr), stream or 0)
+        except Exception:
+            pass
+
+    refs = (_ALLOC_FN(_a), _FREE_FN(_f))
+    _check(lib.acr_set_allocator(refs[0], refs[1]))
+    _allocator_refs = refs
+
+
+def use_torch_allocator():
+    """Take every device allocation of the library from PyTorch's caching allocator
+    (torch.cuda.caching_allocator_alloc / _delete on the library's stream)."""
+    import torch
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, stream=int(stream))
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    acr_set_allocator(alloc, free)
 
 
 KERNEL_CLASSES = ["gemm", "inverse", "qr", "applyq", "svd", "matvec", "copy", "other"]
@@ -276,7 +374,8 @@ def acr_profile_read(cls) -> dict:
 def acr_profile_report() -> dict:
     """Timing of the launches recorded since acr_profile_start:
     {"stages": [(stage, level, class, launches, ms, flops, bytes)],
-     "kernels": [(name, class, launches, ms, flops, bytes)]}."""
+     "kernels": [(name, class, launches, ms, flops, bytes)],
+     "paths": {kernel path: batched problems planned on it}}."""
     lib = load()
     lib.acr_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.acr_profile_report.restype = ctypes.c_int
@@ -291,7 +390,95 @@ def acr_profile_report() -> dict:
             out["stages"].append((f[1], int(f[2]), f[3], int(f[4]), float(f[5]), float(f[6]), float(f[7])))
         elif f[0] == "kernel":
             out["kernels"].append((f[1], f[2], int(f[3]), float(f[4]), float(f[5]), float(f[6])))
+        elif f[0] == "path":
+            out.setdefault("paths", {})[f[1]] = int(f[2])
         elif f[0] == "stagekernel":
             out.setdefault("stage_kernels", []).append((f[1], f[2], int(f[3]), float(f[4]), float(f[5]),
                                                         float(f[6])))
     return out
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_int64), ("tol", ctypes.c_double), ("maxit", ctypes.c_int32)]
+
+
+class _ServerInfo(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int64), ("rhs", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("factorizations", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("resident_bytes", ctypes.c_int64), ("peak_resident_bytes", ctypes.c_int64),
+                ("seconds", ctypes.c_double), ("requests_per_s", ctypes.c_double), ("rhs_per_s", ctypes.c_double),
+                ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+                ("latency_max_ms", ctypes.c_double), ("busy_s", ctypes.c_double)]
+
+
+class Server:
+    """The library's serving loop (acr_server_*): resident factors under a memory budget,
+    requests refined to `tol` with continuous batching of their refinement steps."""
+
+    def __init__(self, memory_budget: int, tol: float = 1e-10, maxit: int = 50):
+        lib = load()
+        P = ctypes.c_void_p
+        lib.acr_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(P)]
+        lib.acr_server_add_operator.argtypes = [P, ctypes.POINTER(_Operator), ctypes.POINTER(_Options),
+                                                ctypes.POINTER(ctypes.c_int32)]
+        lib.acr_server_submit.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_int64)]
+        lib.acr_server_wait.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        lib.acr_server_stats.argtypes = [P, ctypes.c_int32, ctypes.POINTER(_ServerInfo)]
+        lib.acr_server_destroy.argtypes = [P]
+        for n in ("acr_server_create", "acr_server_add_operator", "acr_server_submit", "acr_server_wait",
+                  "acr_server_stats", "acr_server_destroy"):
+            getattr(lib, n).restype = ctypes.c_int
+        self._lib = lib
+        self._ptr = P()
+        cfg = _ServerConfig(int(memory_budget), float(tol), int(maxit))
+        _check(lib.acr_server_create(ctypes.byref(cfg), ctypes.byref(self._ptr)))
+        self._ops = []
+        self._live = {}   # request id -> (B, X) kept alive until waited for
+
+    def add_operator(self, op: Operator, leaf: int, eps: float, precision="mixed", max_rank: int = 0) -> int:
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        opt = _Options(int(leaf), float(eps), prec, int(max_rank), 0.0)
+        oid = ctypes.c_int32(0)
+        _check(self._lib.acr_server_add_operator(self._ptr, ctypes.byref(op._c()), ctypes.byref(opt), ctypes.byref(oid)))
+        self._ops.append(op.n)
+        return oid.value
+
+    def submit(self, op_id: int, B, stream=None) -> int:
+        import torch
+        if not 0 <= int(op_id) < len(self._ops):
+            raise ACRError(1, "unknown operator id")
+        n = self._ops[op_id]
+        Bc = _as_colmajor(B, n)
+        X = torch.empty_like(Bc)
+        rid = ctypes.c_int64(0)
+        _check(self._lib.acr_server_submit(self._ptr, int(op_id), Bc.data_ptr(), X.data_ptr(), Bc.shape[0],
+                                           _stream(stream), ctypes.byref(rid)))
+        self._live[rid.value] = (B, Bc, X)
+        return rid.value
+
+    def wait(self, rid: int, raise_on_fail: bool = True):
+        """Returns (X shaped like B, refinement corrections, relative residual, latency in ms)."""
+        its, rel, lat = ctypes.c_int32(0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+        code = self._lib.acr_server_wait(self._ptr, int(rid), ctypes.byref(its), ctypes.byref(rel), ctypes.byref(lat))
+        B, Bc, X = self._live.pop(rid)
+        if code != 0 and (raise_on_fail or code != 4):
+            _check(code)
+        X = X.t()
+        return (X.reshape(B.shape) if B.dim() == 1 else X), its.value, rel.value, lat.value
+
+    def stats(self, reset: bool = False) -> dict:
+        inf = _ServerInfo()
+        _check(self._lib.acr_server_stats(self._ptr, 1 if reset else 0, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _ServerInfo._fields_}
+
+    def close(self):
+        if self._ptr:
+            _check(self._lib.acr_server_destroy(self._ptr))
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -20,107 +20,15 @@
 #include <string>
 #include <vector>
 
-#include "hodlr.hpp"
-#include "kernels.hpp"
+#include "factor.hpp"
 
 namespace acr {
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-struct FactorBase {
-  virtual ~FactorBase() = default;
-  virtual void solve(const double* B, double* X, int nrhs, hipStream_t st) = 0;
-  virtual void info(acr_info* out) const = 0;
-  virtual void block(int level, int which, int k, double* dense, hipStream_t st) const = 0;
-};
-
-template <typename T>
-struct Level {
-  int m = 0;        // blocks at this level
-  int nreal = 0;    // even blocks (ceil(m/2))
-  int ne = 0;       // even slots incl. a zero dummy when m is even (floor(m/2)+1)
-  HSet<T> X;        // nreal inverses
-  bool diag = false;
-  DBuf<T> e0, f0;   // level 0: diagonals of E_i, F_i ([m][s])
-  HSet<T> E, F;     // level >= 1: m HODLR blocks each
-};
-
-template <typename T>
-struct Factor final : FactorBase {
-  int nx = 0, ny = 0, leaf = 0, b = 0, L = 0, precision = 0;
-  double eps = 0;
-  std::vector<Level<T>> lev;
-  HSet<T> Xlast;
-  Work work_done;
-  std::vector<int> lev_rank;
-
-  size_t bytes() const {
-    size_t t = Xlast.bytes();
-    for (const auto& l : lev) {
-      t += l.X.bytes() + l.E.bytes() + l.F.bytes() + l.e0.bytes() + l.f0.bytes();
-    }
-    return t;
-  }
-
-  void info(acr_info* o) const override {
-    std::memset(o, 0, sizeof(*o));
-    o->nx = nx; o->ny = ny; o->leaf = leaf; o->depth = L; o->levels = (int)lev.size();
-    o->precision = precision; o->eps = eps;
-    o->factor_bytes = (int64_t)bytes();
-    int mr = Xlast.max_rank();
-    for (size_t i = 0; i < lev.size() && i < 40; ++i) {
-      o->level_max_rank[i] = lev_rank[i];
-      mr = std::max(mr, lev_rank[i]);
-    }
-    o->max_rank = mr;
-    o->factor_flops = work_done.total();
-    // one solve pass reads every stored X twice (forward and back) and every
-    // stored E/F once
-    double sb = 2.0 * Xlast.bytes();
-    double fl = 0;
-    for (const auto& l : lev) {
-      sb += 2.0 * l.X.bytes() + l.E.bytes() + l.F.bytes() + l.e0.bytes() + l.f0.bytes();
-    }
-    o->solve_bytes = sb;
-    // two flops per stored multiply-add entry read
-    fl = 2.0 * sb / sizeof(T);
-    o->solve_flops_per_rhs = fl;
-  }
-
-  void block(int level, int which, int k, double* dense, hipStream_t st) const override {
-    const int s = nx;
-    if (level == (int)lev.size()) {
-      if (which != 0 || k != 0) fail(ACR_ERR_INVALID_ARG, "last level holds only X_0");
-      densify_to_host(st, Xlast, 0, dense);
-      return;
-    }
-    if (level < 0 || level > (int)lev.size()) fail(ACR_ERR_INVALID_ARG, "level out of range");
-    const Level<T>& l = lev[level];
-    if (which == 0) {
-      if (k < 0 || k >= l.m || (k & 1)) fail(ACR_ERR_INVALID_ARG, "X_k needs an even k < m");
-      densify_to_host(st, l.X, k / 2, dense);
-      return;
-    }
-    if (which != 1 && which != 2) fail(ACR_ERR_INVALID_ARG, "which must be 0, 1 or 2");
-    if (k < 0 || k >= l.m) fail(ACR_ERR_INVALID_ARG, "block index out of range");
-    if (l.diag) {
-      std::vector<T> d(s);
-      const DBuf<T>& src = which == 1 ? l.e0 : l.f0;
-      read_to_host(d.data(), src.get() + (size_t)k * s, s * sizeof(T), st);
-      for (size_t e = 0; e < (size_t)s * s; ++e) dense[e] = 0.0;
-      for (int r = 0; r < s; ++r) dense[(size_t)r * (s + 1)] = (double)d[r];
-    } else {
-      densify_to_host(st, which == 1 ? l.E : l.F, k, dense);
-    }
-  }
-
-  void solve(const double* B, double* Xout, int nrhs, hipStream_t st) override;
-  void solve_fused(const double* B, double* Xout, int nrhs, hipStream_t st);
-  void solve_gemm(const double* B, double* Xout, int nrhs, hipStream_t st);
-  bool fused_ok(int nrhs) const;
-};
+void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 template <typename T>
 Flat<T> vflat(T* p, int s, int nrhs, int mmul = 1, int moff = 0) {
@@ -137,6 +45,7 @@ MVTerm mv_hodlr(const HSet<T>& H, int mmul, int moff, const T* y, int ymul, int 
   M.lv = H.lv.get();
   for (int d = 1; d <= H.L; ++d) {
     M.U[d] = H.U[d].get(); M.V[d] = H.V[d].get(); M.k[d] = H.k[d]; M.kc[d] = H.kc[d];
+    M.kmean[d] = (float)H.rank_mean(d);
   }
   return M;
 }
@@ -169,75 +78,157 @@ void Factor<T>::solve(const double* B, double* Xout, int nrhs, hipStream_t st) {
   else solve_gemm(B, Xout, nrhs, st);
 }
 
-// Few right-hand sides: every step of a level is one multi-term matvec.
-// U[l] holds the level-l unknowns with one zero pad block at each end.
+// Few right-hand sides (<= 8 per problem): every step of a level is one
+// multi-term matvec, for all problems at once (levels counted from the top
+// going down, from each problem's last level going up).  U[l] holds the
+// level-l unknowns with one zero pad block at each end.
 template <typename T>
-void Factor<T>::solve_fused(const double* B, double* Xout, int nrhs, hipStream_t st) {
-  const int s = nx;
-  const int nl = (int)lev.size();
-  const size_t blk = (size_t)s * nrhs;
-  std::vector<DBuf<T>> F(nl + 1), G(nl), U(nl + 1);
-  F[0].resize((size_t)ny * blk);
-  to_blocks<T>(st, s, ny, nrhs, B, (long long)nx * ny, F[0].get());
-  for (int l = 0; l < nl; ++l) {
-    PhaseScope ph("solve forward", l);
-    const Level<T>& Lv = lev[l];
-    const int m = Lv.m, nodd = m / 2;
-    G[l].resize((size_t)Lv.ne * blk);
-    {  // g_k = X_k f_(2k); the dummy slot (m even) is zero
-      std::vector<MVTerm> tm{mv_hodlr<T>(Lv.X, 1, 0, F[l].get(), 2, 0, 1.0)};
-      std::vector<MVJob> jb{mv_job<T>(Lv.nreal, G[l].get(), 1, 0, 0, 1),
-                            mv_job<T>(Lv.ne - Lv.nreal, G[l].get(), 1, Lv.nreal, 0, 0)};
-      ghmv<T>(st, s, b, L, nrhs, jb, tm);
-    }
-    F[l + 1].resize((size_t)nodd * blk);
-    if (nodd > 0) {  // f'_j = f_(2j+1) - E_(2j+1) g_j - F_(2j+1) g_(j+1)
-      std::vector<MVTerm> tm;
-      if (Lv.diag) {
-        tm.push_back(mv_diag<T>(Lv.e0.get(), 2, 1, G[l].get(), 1, 0, -1.0));
-        tm.push_back(mv_diag<T>(Lv.f0.get(), 2, 1, G[l].get(), 1, 1, -1.0));
-      } else {
-        tm.push_back(mv_hodlr<T>(Lv.E, 2, 1, G[l].get(), 1, 0, -1.0));
-        tm.push_back(mv_hodlr<T>(Lv.F, 2, 1, G[l].get(), 1, 1, -1.0));
-      }
-      std::vector<MVJob> jb{mv_job<T>(nodd, F[l + 1].get(), 1, 0, 0, 2, F[l].get(), 2, 1, 1.0)};
-      ghmv<T>(st, s, b, L, nrhs, jb, tm);
-    }
-  }
-  U[nl].resize(3 * blk);
+void solve_fused_many(const std::vector<const Factor<T>*>& fs, const std::vector<const double*>& Bs,
+                      const std::vector<double*>& Xs, const std::vector<int>& nrs, hipStream_t st) {
+  const int P = (int)fs.size();
+  struct PV {
+    std::vector<DBuf<T>> F, G, U;
+    size_t blk = 0;
+    int nl = 0;
+  };
+  std::vector<PV> pv(P);
+  int maxl = 0;
+  auto job = [&](int p, int nmat, T* out, int omul, int ooff, int term0, int nterm, const T* C0 = nullptr,
+                 int cmul = 1, int coff = 0) {
+    MVJob J = mv_job<T>(nmat, out, omul, ooff, term0, nterm, C0, cmul, coff, 1.0);
+    J.s = fs[p]->nx; J.b = fs[p]->b; J.L = fs[p]->L; J.nrhs = nrs[p];
+    return J;
+  };
   {
-    std::vector<MVTerm> tm{mv_hodlr<T>(Xlast, 1, 0, F[nl].get(), 1, 0, 1.0)};
-    std::vector<MVJob> jb{mv_job<T>(1, U[nl].get(), 1, 1, 0, 1), mv_job<T>(2, U[nl].get(), 2, 0, 0, 0)};
-    ghmv<T>(st, s, b, L, nrhs, jb, tm);
+    std::vector<VJob> tb;
+    for (int p = 0; p < P; ++p) {
+      const Factor<T>& f = *fs[p];
+      PV& v = pv[p];
+      v.nl = (int)f.lev.size();
+      maxl = std::max(maxl, v.nl);
+      v.blk = (size_t)f.nx * nrs[p];
+      v.F.resize(v.nl + 1);
+      v.G.resize(v.nl);
+      v.U.resize(v.nl + 1);
+      v.F[0].resize((size_t)f.ny * v.blk);
+      VJob J;
+      J.s = f.nx; J.nblk = f.ny; J.nrhs = nrs[p]; J.ld = (long long)f.nx * f.ny; J.src = Bs[p]; J.dst = v.F[0].get();
+      tb.push_back(J);
+    }
+    gto_blocks<T>(st, tb);
   }
-  for (int l = nl - 1; l >= 0; --l) {
+  for (int l = 0; l < maxl; ++l) {
+    PhaseScope ph("solve forward", l);
+    {  // g_k = X_k f_(2k); the dummy slot (m even) is zero
+      std::vector<MVTerm> tm;
+      std::vector<MVJob> jb;
+      for (int p = 0; p < P; ++p) {
+        PV& v = pv[p];
+        if (l >= v.nl) continue;
+        const Level<T>& Lv = fs[p]->lev[l];
+        v.G[l].resize((size_t)Lv.ne * v.blk);
+        const int t = (int)tm.size();
+        tm.push_back(mv_hodlr<T>(Lv.X, 1, 0, v.F[l].get(), 2, 0, 1.0));
+        jb.push_back(job(p, Lv.nreal, v.G[l].get(), 1, 0, t, 1));
+        jb.push_back(job(p, Lv.ne - Lv.nreal, v.G[l].get(), 1, Lv.nreal, t, 0));
+      }
+      ghmv<T>(st, jb, tm);
+    }
+    {  // f'_j = f_(2j+1) - E_(2j+1) g_j - F_(2j+1) g_(j+1)
+      std::vector<MVTerm> tm;
+      std::vector<MVJob> jb;
+      for (int p = 0; p < P; ++p) {
+        PV& v = pv[p];
+        if (l >= v.nl) continue;
+        const Level<T>& Lv = fs[p]->lev[l];
+        const int nodd = Lv.m / 2;
+        v.F[l + 1].resize((size_t)nodd * v.blk);
+        if (nodd <= 0) continue;
+        const int t = (int)tm.size();
+        if (Lv.diag) {
+          tm.push_back(mv_diag<T>(Lv.e0.get(), 2, 1, v.G[l].get(), 1, 0, -1.0));
+          tm.push_back(mv_diag<T>(Lv.f0.get(), 2, 1, v.G[l].get(), 1, 1, -1.0));
+        } else {
+          tm.push_back(mv_hodlr<T>(Lv.E, 2, 1, v.G[l].get(), 1, 0, -1.0));
+          tm.push_back(mv_hodlr<T>(Lv.F, 2, 1, v.G[l].get(), 1, 1, -1.0));
+        }
+        jb.push_back(job(p, nodd, v.F[l + 1].get(), 1, 0, t, 2, v.F[l].get(), 2, 1));
+      }
+      ghmv<T>(st, jb, tm);
+    }
+  }
+  {
+    PhaseScope ph("solve last", -1);
+    std::vector<MVTerm> tm;
+    std::vector<MVJob> jb;
+    for (int p = 0; p < P; ++p) {
+      PV& v = pv[p];
+      v.U[v.nl].resize(3 * v.blk);
+      const int t = (int)tm.size();
+      tm.push_back(mv_hodlr<T>(fs[p]->Xlast, 1, 0, v.F[v.nl].get(), 1, 0, 1.0));
+      jb.push_back(job(p, 1, v.U[v.nl].get(), 1, 1, t, 1));
+      jb.push_back(job(p, 2, v.U[v.nl].get(), 2, 0, t, 0));
+    }
+    ghmv<T>(st, jb, tm);
+  }
+  for (int l = maxl - 1; l >= 0; --l) {
     PhaseScope ph("solve backward", l);
-    const Level<T>& Lv = lev[l];
-    const int m = Lv.m, nodd = m / 2;
-    U[l].resize((size_t)(m + 2) * blk);
-    DBuf<T> tmp((size_t)Lv.nreal * blk);
+    std::vector<DBuf<T>> tmp(P);
     {  // tmp_k = E_(2k) u_(2k-1) + F_(2k) u_(2k+1): level-(l+1) unknowns k-1 and k (padded k, k+1)
       std::vector<MVTerm> tm;
-      if (Lv.diag) {
-        tm.push_back(mv_diag<T>(Lv.e0.get(), 2, 0, U[l + 1].get(), 1, 0, 1.0));
-        tm.push_back(mv_diag<T>(Lv.f0.get(), 2, 0, U[l + 1].get(), 1, 1, 1.0));
-      } else {
-        tm.push_back(mv_hodlr<T>(Lv.E, 2, 0, U[l + 1].get(), 1, 0, 1.0));
-        tm.push_back(mv_hodlr<T>(Lv.F, 2, 0, U[l + 1].get(), 1, 1, 1.0));
+      std::vector<MVJob> jb;
+      for (int p = 0; p < P; ++p) {
+        PV& v = pv[p];
+        if (l >= v.nl) continue;
+        const Level<T>& Lv = fs[p]->lev[l];
+        v.U[l].resize((size_t)(Lv.m + 2) * v.blk);
+        tmp[p].resize((size_t)Lv.nreal * v.blk);
+        const int t = (int)tm.size();
+        if (Lv.diag) {
+          tm.push_back(mv_diag<T>(Lv.e0.get(), 2, 0, v.U[l + 1].get(), 1, 0, 1.0));
+          tm.push_back(mv_diag<T>(Lv.f0.get(), 2, 0, v.U[l + 1].get(), 1, 1, 1.0));
+        } else {
+          tm.push_back(mv_hodlr<T>(Lv.E, 2, 0, v.U[l + 1].get(), 1, 0, 1.0));
+          tm.push_back(mv_hodlr<T>(Lv.F, 2, 0, v.U[l + 1].get(), 1, 1, 1.0));
+        }
+        jb.push_back(job(p, Lv.nreal, tmp[p].get(), 1, 0, t, 2));
       }
-      std::vector<MVJob> jb{mv_job<T>(Lv.nreal, tmp.get(), 1, 0, 0, 2)};
-      ghmv<T>(st, s, b, L, nrhs, jb, tm);
+      ghmv<T>(st, jb, tm);
     }
     {  // u_(2k) = g_k - X_k tmp_k; odd unknowns from level l+1; zero pads
-      std::vector<MVTerm> tm{mv_hodlr<T>(Lv.X, 1, 0, tmp.get(), 1, 0, -1.0)};
-      std::vector<MVJob> jb{mv_job<T>(Lv.nreal, U[l].get(), 2, 1, 0, 1, G[l].get(), 1, 0, 1.0),
-                            mv_job<T>(nodd, U[l].get(), 2, 2, 0, 0, U[l + 1].get(), 1, 1, 1.0),
-                            mv_job<T>(1, U[l].get(), 1, 0, 0, 0),
-                            mv_job<T>(1, U[l].get(), 1, m + 1, 0, 0)};
-      ghmv<T>(st, s, b, L, nrhs, jb, tm);
+      std::vector<MVTerm> tm;
+      std::vector<MVJob> jb;
+      for (int p = 0; p < P; ++p) {
+        PV& v = pv[p];
+        if (l >= v.nl) continue;
+        const Level<T>& Lv = fs[p]->lev[l];
+        const int m = Lv.m, nodd = m / 2;
+        const int t = (int)tm.size();
+        tm.push_back(mv_hodlr<T>(Lv.X, 1, 0, tmp[p].get(), 1, 0, -1.0));
+        jb.push_back(job(p, Lv.nreal, v.U[l].get(), 2, 1, t, 1, v.G[l].get(), 1, 0));
+        jb.push_back(job(p, nodd, v.U[l].get(), 2, 2, t, 0, v.U[l + 1].get(), 1, 1));
+        jb.push_back(job(p, 1, v.U[l].get(), 1, 0, t, 0));
+        jb.push_back(job(p, 1, v.U[l].get(), 1, m + 1, t, 0));
+      }
+      ghmv<T>(st, jb, tm);
     }
   }
-  from_blocks<T>(st, s, ny, nrhs, U[0].get() + blk, Xout, (long long)nx * ny);
+  {
+    std::vector<VJob> fb;
+    for (int p = 0; p < P; ++p) {
+      const Factor<T>& f = *fs[p];
+      VJob J;
+      J.s = f.nx; J.nblk = f.ny; J.nrhs = nrs[p]; J.ld = (long long)f.nx * f.ny;
+      J.src = pv[p].U[0].get() + pv[p].blk; J.dst = Xs[p];
+      fb.push_back(J);
+    }
+    gfrom_blocks<T>(st, fb);
+  }
+}
+
+template <typename T>
+void Factor<T>::solve_fused(const double* B, double* Xout, int nrhs, hipStream_t st) {
+  solve_fused_many<T>({this}, {B}, {Xout}, {nrhs}, st);
 }
 
 template <typename T>
@@ -353,213 +344,386 @@ void stage_check(hipStream_t st, const HSet<T>& H, const int* status, const char
          std::string("stage check failed at level ") + std::to_string(level) + " " + what + msg);
 }
 
+// The factorisation of one or many independent problems.  The problems run
+// in lockstep over the cyclic-reduction levels: every H-arithmetic step of a
+// level (inverses, products, truncations) is planned for all problems that
+// still have more than one block and issued as one set of grouped launches,
+// so a batch of problems costs the launches of one.  Each problem keeps its
+// own HODLR sets (its own padding), and every kernel variant is chosen by the
+// shape of its problem alone, so a problem's factor is the same bits whether
+// it is factored alone or in a batch.
 template <typename T>
-std::unique_ptr<FactorBase> factor_impl(const acr_operator& op, const acr_options& opt, hipStream_t st) {
-  auto f = std::make_unique<Factor<T>>();
-  const int s = op.nx, ny = op.ny;
-  f->nx = s; f->ny = ny; f->leaf = opt.leaf; f->eps = opt.eps; f->precision = opt.precision;
-  const int L = hodlr_depth(s, opt.leaf);
-  f->L = L;
-  const int b = s >> L;
-  f->b = b;
+std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operator>& ops, const acr_options& opt,
+                                                    hipStream_t st) {
+  const int P = (int)ops.size();
   const double eps = opt.eps;
   const double ieps = opt.inner_eps;
   const int mr = opt.max_rank;
   work() = Work();
-  DBuf<int> status(1);
-  memset_async(status.get(), 0, sizeof(int), st);
-  {
-    DBuf<int> nonfin(1);
-    memset_async(nonfin.get(), 0, sizeof(int), st);
-    const long long n = (long long)s * ny;
-    for (const double* a : {op.diag, op.west, op.east, op.south, op.north}) flag_nonfinite(st, n, a, nonfin.get());
-    int bad = 0;
-    read_to_host(&bad, nonfin.get(), sizeof(int), st);
-    if (bad) fail(ACR_ERR_INVALID_ARG, "the operator holds a NaN or infinite coefficient");
+  const long long launches0 = launch_count();
+  struct PS {
+    Factor<T>* f = nullptr;
+    const acr_operator* op = nullptr;
+    int s = 0, ny = 0, L = 0, b = 0, m = 0;
+    HSet<T> D, E, F;
+    DBuf<T> e0, f0;
+  };
+  std::vector<std::unique_ptr<Factor<T>>> out(P);
+  std::vector<PS> ps(P);
+  for (int p = 0; p < P; ++p) {
+    out[p] = std::make_unique<Factor<T>>();
+    Factor<T>& f = *out[p];
+    PS& q = ps[p];
+    q.f = &f;
+    q.op = &ops[p];
+    q.s = ops[p].nx;
+    q.ny = ops[p].ny;
+    q.L = hodlr_depth(q.s, opt.leaf);
+    q.b = q.s >> q.L;
+    q.m = q.ny;
+    f.nx = q.s; f.ny = q.ny; f.leaf = opt.leaf; f.eps = eps; f.precision = opt.precision;
+    f.L = q.L; f.b = q.b;
   }
-
-  // level-0 operator: D_i as exact rank-1 HODLR, E_i/F_i diagonal
-  HSet<T> D;
+  DBuf<int> status(P);   // per problem: a bad pivot in one of its inverses
+  memset_async(status.get(), 0, (size_t)P * sizeof(int), st);
   {
-    std::vector<int> k1(L + 1, 1);
-    D.alloc(st, ny, s, b, L, k1, false);
-    build_leaves_tridiag<T>(st, s, b, ny, 1, 0, op.diag, op.west, op.east, D.lv.get());
-    for (int d = 1; d <= L; ++d) {
-      build_rank1_factors<T>(st, s, s >> d, ny, 1, 0, op.west, op.east, D.U[d].get(), D.V[d].get());
-      D.kc[d] = 1;
+    DBuf<int> nonfin(P);
+    memset_async(nonfin.get(), 0, (size_t)P * sizeof(int), st);
+    std::vector<NFJob> nf;
+    for (int p = 0; p < P; ++p) {
+      const acr_operator& op = ops[p];
+      for (const double* a : {op.diag, op.west, op.east, op.south, op.north}) {
+        NFJob J;
+        J.n = (long long)op.nx * op.ny; J.a = a; J.flag = nonfin.get() + p;
+        nf.push_back(J);
+      }
     }
+    gflag_nonfinite(st, nf);
+    std::vector<int> bad(P);
+    read_to_host(bad.data(), nonfin.get(), (size_t)P * sizeof(int), st);
+    for (int p = 0; p < P; ++p)
+      if (bad[p])
+        fail(ACR_ERR_INVALID_ARG, "the operator" + (P > 1 ? " of problem " + std::to_string(p) : std::string()) +
+                                      " holds a NaN or infinite coefficient");
   }
-  HSet<T> E, F;
-  DBuf<T> e0((size_t)ny * s), f0((size_t)ny * s);
-  gather_diag<T>(st, s, ny, 1, 0, op.south, e0.get());
-  gather_diag<T>(st, s, ny, 1, 0, op.north, f0.get());
-  // E_0 and F_(ny-1) are outside the grid: exact zeros
-  fill<T>(st, e0.get(), s, T(0));
-  fill<T>(st, f0.get() + (size_t)(ny - 1) * s, s, T(0));
+  // level-0 operators: D_i as exact rank-1 HODLR, E_i/F_i diagonal (E_0 and
+  // F_(ny-1) are outside the grid: exact zeros)
+  {
+    std::vector<OpJob> lj, rj, gj;
+    for (PS& q : ps) {
+      std::vector<int> k1(q.L + 1, 1);
+      q.D.alloc(st, q.ny, q.s, q.b, q.L, k1, -1);
+      OpJob J;
+      J.s = q.s; J.b = q.b; J.L = q.L; J.nmat = q.ny;
+      J.diag = q.op->diag; J.west = q.op->west; J.east = q.op->east;
+      J.out = q.D.lv.get();
+      lj.push_back(J);
+      if (q.L > 0) {
+        OpJob R = J;
+        R.out = nullptr;
+        for (int d = 1; d <= q.L; ++d) {
+          R.U[d] = q.D.U[d].get();
+          R.V[d] = q.D.V[d].get();
+          q.D.kc[d] = 1;
+        }
+        rj.push_back(R);
+      }
+      q.e0.resize((size_t)q.ny * q.s);
+      q.f0.resize((size_t)q.ny * q.s);
+      OpJob G;
+      G.s = q.s; G.nmat = q.ny;
+      G.src = q.op->south; G.out = q.e0.get(); G.zblk = 0;
+      gj.push_back(G);
+      G.src = q.op->north; G.out = q.f0.get(); G.zblk = q.ny - 1;
+      gj.push_back(G);
+    }
+    gleaves_tridiag<T>(st, lj);
+    grank1_factors<T>(st, rj);
+    ggather_diag<T>(st, gj);
+  }
 
-  int m = ny;
   bool diag = true;
-  while (m > 1) {
-    Level<T> lv;
-    lv.m = m;
-    lv.nreal = (m + 1) / 2;
-    lv.ne = m / 2 + 1;
-    lv.diag = diag;
-    const int nodd = m / 2;
-    PhaseScope lvl("level", (int)f->lev.size());
+  for (int lvl = 0;; ++lvl) {
+    std::vector<int> act;   // problems with more than one block left
+    for (int p = 0; p < P; ++p)
+      if (ps[p].m > 1) act.push_back(p);
+    if (act.empty()) break;
+    const int na = (int)act.size();
+    PhaseScope lph("level", lvl);
+    std::vector<Level<T>> lv(na);
+    for (int a = 0; a < na; ++a) {
+      const PS& q = ps[act[a]];
+      lv[a].m = q.m;
+      lv[a].nreal = (q.m + 1) / 2;
+      lv[a].ne = q.m / 2 + 1;
+      lv[a].diag = diag;
+      stage_check(st, q.D, status.get() + act[a], "D", lvl);
+    }
     // X_k = T(D_k^{-1}) for even k
-    stage_check(st, D, status.get(), "D", (int)f->lev.size());
-    bool closed = false;   // level 0: D_k tridiagonal, its inverse in closed form (exact rank 1)
+    std::vector<char> closed(na, 0);   // level 0: D_k tridiagonal, inverse in closed form (exact rank 1)
     {
       PhaseScope ph("inverse");
-      if (diag && s <= 3072) {
-        std::vector<int> k1(L + 1, 1);
-        lv.X.alloc(st, lv.nreal, s, b, L, k1, false);
-        TriInvOut to;
-        for (int d = 1; d <= L; ++d) {
-          to.U[d] = lv.X.U[d].get();
-          to.V[d] = lv.X.V[d].get();
-          lv.X.kc[d] = 1;
+      if (diag) {
+        std::vector<OpJob> tj;
+        std::vector<int> ta;
+        for (int a = 0; a < na; ++a) {
+          const PS& q = ps[act[a]];
+          if (q.s > 3072) continue;
+          std::vector<int> k1(q.L + 1, 1);
+          lv[a].X.alloc(st, lv[a].nreal, q.s, q.b, q.L, k1, -1);
+          OpJob J;
+          J.s = q.s; J.b = q.b; J.L = q.L; J.nmat = lv[a].nreal; J.bmul = 2; J.boff = 0;
+          J.diag = q.op->diag; J.west = q.op->west; J.east = q.op->east;
+          J.out = lv[a].X.lv.get();
+          for (int d = 1; d <= q.L; ++d) {
+            J.U[d] = lv[a].X.U[d].get();
+            J.V[d] = lv[a].X.V[d].get();
+            lv[a].X.kc[d] = 1;
+          }
+          tj.push_back(J);
+          ta.push_back(a);
         }
-        DBuf<int> fb(1);
-        memset_async(fb.get(), 0, sizeof(int), st);
-        tridiag_inverse<T>(st, s, b, L, lv.nreal, 2, 0, op.diag, op.west, op.east, lv.X.lv.get(), to, fb.get());
-        int fbh = 0;
-        read_to_host(&fbh, fb.get(), sizeof(int), st);
-        closed = fbh == 0;
+        if (!tj.empty()) {
+          DBuf<int> fb(tj.size());
+          memset_async(fb.get(), 0, tj.size() * sizeof(int), st);
+          for (size_t i = 0; i < tj.size(); ++i) tj[i].flag = fb.get() + i;
+          gtridiag_inverse<T>(st, tj);
+          std::vector<int> fbh(tj.size());
+          read_to_host(fbh.data(), fb.get(), tj.size() * sizeof(int), st);
+          for (size_t i = 0; i < tj.size(); ++i) closed[ta[i]] = fbh[i] == 0;
+        }
       }
-      if (!closed) hinv<T>(st, lv.X, HV<T>{&D, 2, 0}, lv.nreal, status.get());
+      std::vector<HInvJob<T>> hj;
+      for (int a = 0; a < na; ++a)
+        if (!closed[a]) hj.push_back(HInvJob<T>{&lv[a].X, HV<T>{&ps[act[a]].D, 2, 0}, lv[a].nreal, status.get() + act[a]});
+      hinv_multi<T>(st, hj);
     }
-    stage_check(st, lv.X, status.get(), "inv", (int)f->lev.size());
-    if (!closed) {   // the closed form is exact with rank-one blocks: T_eps leaves it unchanged
+    {   // the closed form is exact with rank-one blocks: T_eps leaves it unchanged
       PhaseScope ph("recompress X");
-      recompress_multi<T>(st, {&lv.X}, eps, mr);
+      std::vector<HSet<T>*> xs;
+      for (int a = 0; a < na; ++a) {
+        stage_check(st, lv[a].X, status.get() + act[a], "inv", lvl);
+        if (!closed[a]) xs.push_back(&lv[a].X);
+      }
+      recompress_multi<T>(st, xs, eps, mr);
     }
-    stage_check(st, lv.X, status.get(), "X", (int)f->lev.size());
-    HSet<T> P, Q;
-    HSet<T> Dn, En, Fn;
+    std::vector<HSet<T>> P_(na), Q_(na), Dn(na), En(na), Fn(na), EQ(na), FP(na);
     if (diag) {
       // P_k = X_k diag(e_2k), Q_k = X_k diag(f_2k)
-      std::vector<ColScale<T>> cs(2);
-      cs[0].C = &P; cs[0].cnt_alloc = lv.ne; cs[0].nmat = lv.nreal; cs[0].H = HV<T>{&lv.X, 1, 0};
-      cs[0].cols = e0.get(); cs[0].cmul = 2; cs[0].coff = 0;
-      cs[1] = cs[0];
-      cs[1].C = &Q; cs[1].cols = f0.get();
+      std::vector<ColScale<T>> cs;
+      for (int a = 0; a < na; ++a) {
+        PS& q = ps[act[a]];
+        ColScale<T> c;
+        c.C = &P_[a]; c.cnt_alloc = lv[a].ne; c.nmat = lv[a].nreal; c.H = HV<T>{&lv[a].X, 1, 0};
+        c.cols = q.e0.get(); c.cmul = 2; c.coff = 0;
+        cs.push_back(c);
+        c.C = &Q_[a]; c.cols = q.f0.get();
+        cs.push_back(c);
+      }
       {
         PhaseScope ph("products P,Q");
         hscale_cols_multi<T>(st, cs);
       }
       {
         PhaseScope ph("recompress P,Q");
-        recompress_multi<T>(st, {&P, &Q}, eps, mr);
+        std::vector<HSet<T>*> sets;
+        for (int a = 0; a < na; ++a) { sets.push_back(&P_[a]); sets.push_back(&Q_[a]); }
+        recompress_multi<T>(st, sets, eps, mr);
       }
       PhaseScope ph("products D',E',F'");
       // D'_j = D_i - diag(e_i) Q_j - diag(f_i) P_(j+1);  E'_j = -diag(e_i) P_j;  F'_j = -diag(f_i) Q_(j+1)
-      std::vector<ScaleTerm<T>> terms(3);
-      terms[0].h = HV<T>{&D, 2, 1};
-      terms[1].h = HV<T>{&Q, 1, 0}; terms[1].coef = -1.0; terms[1].rows = e0.get(); terms[1].rmul = 2; terms[1].roff = 1;
-      terms[2].h = HV<T>{&P, 1, 1}; terms[2].coef = -1.0; terms[2].rows = f0.get(); terms[2].rmul = 2; terms[2].roff = 1;
-      hstack<T>(st, Dn, nodd, terms, nodd);
-      std::vector<ScaleTerm<T>> te(1), tf(1);
-      te[0].h = HV<T>{&P, 1, 0}; te[0].coef = -1.0; te[0].rows = e0.get(); te[0].rmul = 2; te[0].roff = 1;
-      tf[0].h = HV<T>{&Q, 1, 1}; tf[0].coef = -1.0; tf[0].rows = f0.get(); tf[0].rmul = 2; tf[0].roff = 1;
-      hstack<T>(st, En, nodd, te, nodd);
-      hstack<T>(st, Fn, nodd, tf, nodd);
-      lv.e0 = std::move(e0);
-      lv.f0 = std::move(f0);
+      std::vector<StackOut<T>> so;
+      for (int a = 0; a < na; ++a) {
+        PS& q = ps[act[a]];
+        const int nodd = q.m / 2;
+        StackOut<T> d;
+        d.C = &Dn[a]; d.cnt_alloc = nodd; d.nmat = nodd;
+        d.terms.resize(3);
+        d.terms[0].h = HV<T>{&q.D, 2, 1};
+        d.terms[1].h = HV<T>{&Q_[a], 1, 0}; d.terms[1].coef = -1.0; d.terms[1].rows = q.e0.get(); d.terms[1].rmul = 2; d.terms[1].roff = 1;
+        d.terms[2].h = HV<T>{&P_[a], 1, 1}; d.terms[2].coef = -1.0; d.terms[2].rows = q.f0.get(); d.terms[2].rmul = 2; d.terms[2].roff = 1;
+        so.push_back(d);
+        StackOut<T> e;
+        e.C = &En[a]; e.cnt_alloc = nodd; e.nmat = nodd;
+        e.terms.resize(1);
+        e.terms[0].h = HV<T>{&P_[a], 1, 0}; e.terms[0].coef = -1.0; e.terms[0].rows = q.e0.get(); e.terms[0].rmul = 2; e.terms[0].roff = 1;
+        so.push_back(e);
+        StackOut<T> fo;
+        fo.C = &Fn[a]; fo.cnt_alloc = nodd; fo.nmat = nodd;
+        fo.terms.resize(1);
+        fo.terms[0].h = HV<T>{&Q_[a], 1, 1}; fo.terms[0].coef = -1.0; fo.terms[0].rows = q.f0.get(); fo.terms[0].rmul = 2; fo.terms[0].roff = 1;
+        so.push_back(fo);
+      }
+      hstack_multi<T>(st, so);
+      for (int a = 0; a < na; ++a) {
+        lv[a].e0 = std::move(ps[act[a]].e0);
+        lv[a].f0 = std::move(ps[act[a]].f0);
+      }
     } else {
       // P_k = X_k E_2k, Q_k = X_k F_2k
-      std::vector<POut<T>> pq(2);
-      pq[0].C = &P; pq[0].cnt_alloc = lv.ne; pq[0].nmat = lv.nreal;
-      pq[0].terms = {PTerm<T>{1.0, HV<T>{&lv.X, 1, 0}, HV<T>{&E, 2, 0}}};
-      pq[1].C = &Q; pq[1].cnt_alloc = lv.ne; pq[1].nmat = lv.nreal;
-      pq[1].terms = {PTerm<T>{1.0, HV<T>{&lv.X, 1, 0}, HV<T>{&F, 2, 0}}};
+      std::vector<POut<T>> pq;
+      for (int a = 0; a < na; ++a) {
+        PS& q = ps[act[a]];
+        POut<T> o;
+        o.C = &P_[a]; o.cnt_alloc = lv[a].ne; o.nmat = lv[a].nreal;
+        o.terms = {PTerm<T>{1.0, HV<T>{&lv[a].X, 1, 0}, HV<T>{&q.E, 2, 0}}};
+        pq.push_back(o);
+        o.C = &Q_[a];
+        o.terms = {PTerm<T>{1.0, HV<T>{&lv[a].X, 1, 0}, HV<T>{&q.F, 2, 0}}};
+        pq.push_back(o);
+      }
       {
         PhaseScope ph("products P,Q");
         hprod_multi<T>(st, pq);
       }
       {
         PhaseScope ph("recompress P,Q");
-        recompress_multi<T>(st, {&P, &Q}, eps, mr);
+        std::vector<HSet<T>*> sets;
+        for (int a = 0; a < na; ++a) { sets.push_back(&P_[a]); sets.push_back(&Q_[a]); }
+        recompress_multi<T>(st, sets, eps, mr);
       }
       PhaseScope ph("products D',E',F'");
-      std::vector<POut<T>> up(3);
-      up[1].C = &En; up[1].cnt_alloc = nodd; up[1].nmat = nodd;
-      up[1].terms = {PTerm<T>{-1.0, HV<T>{&E, 2, 1}, HV<T>{&P, 1, 0}}};
-      up[2].C = &Fn; up[2].cnt_alloc = nodd; up[2].nmat = nodd;
-      up[2].terms = {PTerm<T>{-1.0, HV<T>{&F, 2, 1}, HV<T>{&Q, 1, 1}}};
-      HSet<T> EQ, FP;
-      if (ieps > 0) {
-        // intermediate truncation of the two Schur products, then the sum
-        up[0].C = &EQ; up[0].cnt_alloc = nodd; up[0].nmat = nodd;
-        up[0].terms = {PTerm<T>{1.0, HV<T>{&E, 2, 1}, HV<T>{&Q, 1, 0}}};
-        up.push_back(POut<T>());
-        up[3].C = &FP; up[3].cnt_alloc = nodd; up[3].nmat = nodd;
-        up[3].terms = {PTerm<T>{1.0, HV<T>{&F, 2, 1}, HV<T>{&P, 1, 1}}};
-        hprod_multi<T>(st, up);
-        PhaseScope ph2("recompress EQ,FP");
-        recompress_multi<T>(st, {&EQ, &FP}, ieps, 0);
-        std::vector<ScaleTerm<T>> terms(3);
-        terms[0].h = HV<T>{&D, 2, 1};
-        terms[1].h = HV<T>{&EQ, 1, 0}; terms[1].coef = -1.0;
-        terms[2].h = HV<T>{&FP, 1, 0}; terms[2].coef = -1.0;
-        hstack<T>(st, Dn, nodd, terms, nodd);
-      } else {
-        // D'_j = D_i - E_i Q_j - F_i P_(j+1), accumulated exactly, one truncation
-        up[0].C = &Dn; up[0].cnt_alloc = nodd; up[0].nmat = nodd;
-        up[0].has_d = true; up[0].D = HV<T>{&D, 2, 1};
-        up[0].terms = {PTerm<T>{-1.0, HV<T>{&E, 2, 1}, HV<T>{&Q, 1, 0}},
-                       PTerm<T>{-1.0, HV<T>{&F, 2, 1}, HV<T>{&P, 1, 1}}};
-        hprod_multi<T>(st, up);
+      std::vector<POut<T>> up;
+      for (int a = 0; a < na; ++a) {
+        PS& q = ps[act[a]];
+        const int nodd = q.m / 2;
+        POut<T> e;
+        e.C = &En[a]; e.cnt_alloc = nodd; e.nmat = nodd;
+        e.terms = {PTerm<T>{-1.0, HV<T>{&q.E, 2, 1}, HV<T>{&P_[a], 1, 0}}};
+        up.push_back(e);
+        POut<T> fo;
+        fo.C = &Fn[a]; fo.cnt_alloc = nodd; fo.nmat = nodd;
+        fo.terms = {PTerm<T>{-1.0, HV<T>{&q.F, 2, 1}, HV<T>{&Q_[a], 1, 1}}};
+        up.push_back(fo);
+        if (ieps > 0) {
+          // intermediate truncation of the two Schur products, then the sum
+          POut<T> x;
+          x.C = &EQ[a]; x.cnt_alloc = nodd; x.nmat = nodd;
+          x.terms = {PTerm<T>{1.0, HV<T>{&q.E, 2, 1}, HV<T>{&Q_[a], 1, 0}}};
+          up.push_back(x);
+          x.C = &FP[a];
+          x.terms = {PTerm<T>{1.0, HV<T>{&q.F, 2, 1}, HV<T>{&P_[a], 1, 1}}};
+          up.push_back(x);
+        } else {
+          // D'_j = D_i - E_i Q_j - F_i P_(j+1), accumulated exactly, one truncation
+          POut<T> d;
+          d.C = &Dn[a]; d.cnt_alloc = nodd; d.nmat = nodd;
+          d.has_d = true; d.D = HV<T>{&q.D, 2, 1};
+          d.terms = {PTerm<T>{-1.0, HV<T>{&q.E, 2, 1}, HV<T>{&Q_[a], 1, 0}},
+                     PTerm<T>{-1.0, HV<T>{&q.F, 2, 1}, HV<T>{&P_[a], 1, 1}}};
+          up.push_back(d);
+        }
       }
-      lv.E = std::move(E);
-      lv.F = std::move(F);
+      hprod_multi<T>(st, up);
+      if (ieps > 0) {
+        {
+          PhaseScope ph2("recompress EQ,FP");
+          std::vector<HSet<T>*> sets;
+          for (int a = 0; a < na; ++a) { sets.push_back(&EQ[a]); sets.push_back(&FP[a]); }
+          recompress_multi<T>(st, sets, ieps, 0);
+        }
+        std::vector<StackOut<T>> so;
+        for (int a = 0; a < na; ++a) {
+          PS& q = ps[act[a]];
+          const int nodd = q.m / 2;
+          StackOut<T> d;
+          d.C = &Dn[a]; d.cnt_alloc = nodd; d.nmat = nodd;
+          d.terms.resize(3);
+          d.terms[0].h = HV<T>{&q.D, 2, 1};
+          d.terms[1].h = HV<T>{&EQ[a], 1, 0}; d.terms[1].coef = -1.0;
+          d.terms[2].h = HV<T>{&FP[a], 1, 0}; d.terms[2].coef = -1.0;
+          so.push_back(d);
+        }
+        hstack_multi<T>(st, so);
+      }
+      for (int a = 0; a < na; ++a) {
+        lv[a].E = std::move(ps[act[a]].E);
+        lv[a].F = std::move(ps[act[a]].F);
+      }
     }
-    stage_check(st, P, status.get(), "P", (int)f->lev.size());
-    stage_check(st, Q, status.get(), "Q", (int)f->lev.size());
-    stage_check(st, Dn, status.get(), "D'-exact", (int)f->lev.size());
+    for (int a = 0; a < na; ++a) {
+      stage_check(st, P_[a], status.get() + act[a], "P", lvl);
+      stage_check(st, Q_[a], status.get() + act[a], "Q", lvl);
+      stage_check(st, Dn[a], status.get() + act[a], "D'-exact", lvl);
+    }
     {
       PhaseScope ph("recompress D',E',F'");
-      recompress_multi<T>(st, {&Dn, &En, &Fn}, eps, mr);
+      std::vector<HSet<T>*> sets;
+      for (int a = 0; a < na; ++a) { sets.push_back(&Dn[a]); sets.push_back(&En[a]); sets.push_back(&Fn[a]); }
+      recompress_multi<T>(st, sets, eps, mr);
     }
-    stage_check(st, Dn, status.get(), "D'", (int)f->lev.size());
-    stage_check(st, En, status.get(), "E'", (int)f->lev.size());
-    stage_check(st, Fn, status.get(), "F'", (int)f->lev.size());
-    int r = lv.X.max_rank();
-    r = std::max(r, lv.E.max_rank());
-    r = std::max(r, lv.F.max_rank());
-    f->lev_rank.push_back(r);
-    f->lev.push_back(std::move(lv));
-    D = std::move(Dn);
-    E = std::move(En);
-    F = std::move(Fn);
-    m = nodd;
+    for (int a = 0; a < na; ++a) {
+      PS& q = ps[act[a]];
+      Factor<T>& f = *q.f;
+      stage_check(st, Dn[a], status.get() + act[a], "D'", lvl);
+      stage_check(st, En[a], status.get() + act[a], "E'", lvl);
+      stage_check(st, Fn[a], status.get() + act[a], "F'", lvl);
+      Level<T>& L_ = lv[a];
+      int r = L_.X.max_rank();
+      r = std::max(r, L_.E.max_rank());
+      r = std::max(r, L_.F.max_rank());
+      f.lev_rank.push_back(r);
+      {   // mean numerical rank of the stored off-diagonal blocks of this level
+        double rs = 0.0, nb = 0.0;
+        for (const HSet<T>* H : {&L_.X, &L_.E, &L_.F})
+          for (int d = 1; d <= H->L; ++d) {
+            rs += H->rank_sum(d);
+            nb += (double)H->cnt * (1 << d);
+          }
+        f.lev_mean.push_back(nb > 0 ? rs / nb : 0.0);
+      }
+      f.lev.push_back(std::move(L_));
+      q.D = std::move(Dn[a]);
+      q.E = std::move(En[a]);
+      q.F = std::move(Fn[a]);
+      q.m = q.m / 2;
+    }
     diag = false;
   }
   {
-    PhaseScope ph("last inverse", (int)f->lev.size());
-    hinv<T>(st, f->Xlast, HV<T>{&D, 1, 0}, 1, status.get());
-    recompress_multi<T>(st, {&f->Xlast}, eps, mr);
+    PhaseScope ph("last inverse", -1);
+    std::vector<HInvJob<T>> hj;
+    std::vector<HSet<T>*> xs;
+    for (int p = 0; p < P; ++p) {
+      hj.push_back(HInvJob<T>{&ps[p].f->Xlast, HV<T>{&ps[p].D, 1, 0}, 1, status.get() + p});
+      xs.push_back(&ps[p].f->Xlast);
+    }
+    hinv_multi<T>(st, hj);
+    recompress_multi<T>(st, xs, eps, mr);
   }
-  int bad = 0;
-  read_to_host(&bad, status.get(), sizeof(int), st);
-  if (bad) fail(ACR_ERR_SINGULAR, "zero or non-finite pivot in a dense leaf or capacitance inverse");
-  f->work_done = work();
-  return f;
+  std::vector<int> bad(P);
+  read_to_host(bad.data(), status.get(), (size_t)P * sizeof(int), st);
+  for (int p = 0; p < P; ++p)
+    if (bad[p])
+      fail(ACR_ERR_SINGULAR, "zero or non-finite pivot in a dense leaf or capacitance inverse" +
+                                 (P > 1 ? " (problem " + std::to_string(p) + ")" : std::string()));
+  const Work w = work();
+  const long long nl = launch_count() - launches0;
+  for (int p = 0; p < P; ++p) {
+    out[p]->work_done = w;
+    out[p]->launches = nl;
+    out[p]->batch = P;
+  }
+  return out;
 }
 
-}  // namespace
+#define ACR_INST(T)                                                                                      \
+  template struct Factor<T>;                                                                             \
+  template std::vector<std::unique_ptr<Factor<T>>> factor_many<T>(const std::vector<acr_operator>&,      \
+                                                                  const acr_options&, hipStream_t);      \
+  template void solve_fused_many<T>(const std::vector<const Factor<T>*>&, const std::vector<const double*>&, \
+                                    const std::vector<double*>&, const std::vector<int>&, hipStream_t);
+ACR_INST(float)
+ACR_INST(double)
+#undef ACR_INST
+
 }  // namespace acr
 
-struct acr_handle_s {
-  std::unique_ptr<acr::FactorBase> f;
-  int precision = 0;
-  int nx = 0, ny = 0;
-};
+
 
 using namespace acr;
 
-namespace {
+namespace acr {
 
 acr_status guard(const std::function<void()>& fn) {
   try {
@@ -582,12 +746,55 @@ acr_status guard(const std::function<void()>& fn) {
   }
 }
 
+// Whether [a, a+na) and [b, b+nb) (doubles) share an element.
+bool overlap2(const double* a, size_t na, const double* b, size_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb * sizeof(double) && y < x + na * sizeof(double);
+}
+
+void check_options(const acr_options* opt) {
+  if (!opt) fail(ACR_ERR_INVALID_ARG, "options are NULL");
+  if (opt->leaf < 1 || opt->leaf > 128) fail(ACR_ERR_INVALID_ARG, "leaf must be in 1..128");
+  if (!(opt->eps >= 0.0) || !std::isfinite(opt->eps)) fail(ACR_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  if (!(opt->inner_eps >= 0.0)) fail(ACR_ERR_INVALID_ARG, "inner_eps must be >= 0");
+  if (opt->precision != ACR_FP64 && opt->precision != ACR_MIXED_FP32) fail(ACR_ERR_INVALID_ARG, "unknown precision");
+  if (opt->max_rank < 0) fail(ACR_ERR_INVALID_ARG, "max_rank must be >= 0");
+}
+
 void check_op(const acr_operator* op) {
   if (!op) fail(ACR_ERR_INVALID_ARG, "operator is NULL");
   if (op->nx < 1 || op->ny < 1) fail(ACR_ERR_INVALID_ARG, "nx and ny must be >= 1");
   if ((long long)op->nx * op->ny > (1LL << 31)) fail(ACR_ERR_INVALID_ARG, "N too large");
   if (!op->diag || !op->west || !op->east || !op->south || !op->north)
     fail(ACR_ERR_INVALID_ARG, "a stencil array is NULL");
+}
+
+}  // namespace acr
+
+namespace {
+
+bool overlap(const double* a, const double* b, size_t n) { return overlap2(a, n, b, n); }
+
+template <typename T>
+void solve_batched_t(const acr_handle* hs, const double* const* B, double* const* X, const int32_t* nrhs,
+                     int count, int precision, hipStream_t st) {
+  std::vector<const Factor<T>*> fs;
+  std::vector<const double*> bs;
+  std::vector<double*> xs;
+  std::vector<int> nr;
+  for (int p = 0; p < count; ++p) {
+    if (hs[p]->precision != precision) continue;
+    auto* f = static_cast<Factor<T>*>(hs[p]->f.get());
+    if (f->fused_ok(nrhs[p])) {
+      fs.push_back(f);
+      bs.push_back(B[p]);
+      xs.push_back(X[p]);
+      nr.push_back(nrhs[p]);
+    } else {
+      f->solve_gemm(B[p], X[p], nrhs[p], st);   // many right-hand sides: one problem at a time
+    }
+  }
+  if (!fs.empty()) solve_fused_many<T>(fs, bs, xs, nr, st);
 }
 
 }  // namespace
@@ -597,22 +804,78 @@ extern "C" {
 acr_status acr_factor(const acr_operator* op, const acr_options* opt, void* stream, acr_handle* out) {
   return guard([&] {
     check_op(op);
-    if (!opt || !out) fail(ACR_ERR_INVALID_ARG, "options or output handle is NULL");
-    if (opt->leaf < 1 || opt->leaf > 128) fail(ACR_ERR_INVALID_ARG, "leaf must be in 1..128");
-    if (!(opt->eps >= 0.0) || !std::isfinite(opt->eps)) fail(ACR_ERR_INVALID_ARG, "eps must be finite and >= 0");
-    if (!(opt->inner_eps >= 0.0)) fail(ACR_ERR_INVALID_ARG, "inner_eps must be >= 0");
-    if (opt->precision != ACR_FP64 && opt->precision != ACR_MIXED_FP32)
-      fail(ACR_ERR_INVALID_ARG, "unknown precision");
-    if (opt->max_rank < 0) fail(ACR_ERR_INVALID_ARG, "max_rank must be >= 0");
+    if (!out) fail(ACR_ERR_INVALID_ARG, "output handle is NULL");
+    check_options(opt);
     if (hodlr_depth(op->nx, opt->leaf) < 0)
       fail(ACR_ERR_INVALID_ARG, "block size must be leaf' * 2^L (halving exact down to the leaf)");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope ss(st);
     auto h = std::make_unique<acr_handle_s>();
     h->precision = opt->precision;
     h->nx = op->nx; h->ny = op->ny;
-    if (opt->precision == ACR_FP64) h->f = factor_impl<double>(*op, *opt, st);
-    else h->f = factor_impl<float>(*op, *opt, st);
+    std::vector<acr_operator> ops{*op};
+    if (opt->precision == ACR_FP64) h->f = std::move(factor_many<double>(ops, *opt, st)[0]);
+    else h->f = std::move(factor_many<float>(ops, *opt, st)[0]);
     *out = h.release();
+  });
+}
+
+acr_status acr_factor_batched(const acr_operator* ops, const acr_options* opt, int32_t count, void* stream,
+                              acr_handle* out) {
+  return guard([&] {
+    if (count < 1 || !ops || !out) fail(ACR_ERR_INVALID_ARG, "count must be >= 1 with non-NULL ops and out");
+    check_options(opt);
+    std::vector<acr_operator> v(ops, ops + count);
+    for (int p = 0; p < count; ++p) {
+      check_op(&v[p]);
+      if (hodlr_depth(v[p].nx, opt->leaf) < 0)
+        fail(ACR_ERR_INVALID_ARG, "problem " + std::to_string(p) +
+                                      ": block size must be leaf' * 2^L (halving exact down to the leaf)");
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope ss(st);
+    std::vector<std::unique_ptr<acr_handle_s>> hs(count);
+    if (opt->precision == ACR_FP64) {
+      auto fs = factor_many<double>(v, *opt, st);
+      for (int p = 0; p < count; ++p) {
+        hs[p] = std::make_unique<acr_handle_s>();
+        hs[p]->f = std::move(fs[p]);
+      }
+    } else {
+      auto fs = factor_many<float>(v, *opt, st);
+      for (int p = 0; p < count; ++p) {
+        hs[p] = std::make_unique<acr_handle_s>();
+        hs[p]->f = std::move(fs[p]);
+      }
+    }
+    for (int p = 0; p < count; ++p) {
+      hs[p]->precision = opt->precision;
+      hs[p]->nx = v[p].nx;
+      hs[p]->ny = v[p].ny;
+    }
+    for (int p = 0; p < count; ++p) out[p] = hs[p].release();
+  });
+}
+
+acr_status acr_solve_batched(const acr_handle* hs, const double* const* B, double* const* X, const int32_t* nrhs,
+                             int32_t count, void* stream) {
+  return guard([&] {
+    if (count < 1 || !hs || !B || !X || !nrhs) fail(ACR_ERR_INVALID_ARG, "NULL argument or count < 1");
+    for (int p = 0; p < count; ++p) {
+      if (!hs[p] || !B[p] || !X[p]) fail(ACR_ERR_INVALID_ARG, "NULL handle or vector in the batch");
+      if (nrhs[p] < 1) fail(ACR_ERR_INVALID_ARG, "nrhs must be >= 1");
+      const size_t n = (size_t)hs[p]->nx * hs[p]->ny * nrhs[p];
+      for (int q = 0; q < count; ++q) {
+        const size_t nq = (size_t)hs[q]->nx * hs[q]->ny * nrhs[q];
+        if (q < p && overlap2(X[p], n, X[q], nq)) fail(ACR_ERR_INVALID_ARG, "outputs of the batch overlap");
+        if (q != p && overlap2(X[p], n, B[q], nq))
+          fail(ACR_ERR_INVALID_ARG, "an output of the batch overlaps another problem's right-hand side");
+      }
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope ss(st);
+    solve_batched_t<double>(hs, B, X, nrhs, count, ACR_FP64, st);
+    solve_batched_t<float>(hs, B, X, nrhs, count, ACR_MIXED_FP32, st);
   });
 }
 
@@ -620,6 +883,7 @@ acr_status acr_solve(acr_handle h, const double* B, double* X, int32_t nrhs, voi
   return guard([&] {
     if (!h || !B || !X) fail(ACR_ERR_INVALID_ARG, "NULL argument");
     if (nrhs < 1) fail(ACR_ERR_INVALID_ARG, "nrhs must be >= 1");
+    StreamScope ss(static_cast<hipStream_t>(stream));
     h->f->solve(B, X, nrhs, static_cast<hipStream_t>(stream));
   });
 }
@@ -629,6 +893,7 @@ acr_status acr_residual(const acr_operator* op, const double* X, const double* B
   return guard([&] {
     check_op(op);
     if (!X || !B || !R || nrhs < 1) fail(ACR_ERR_INVALID_ARG, "bad vector arguments");
+    StreamScope ss(static_cast<hipStream_t>(stream));
     stencil_residual(static_cast<hipStream_t>(stream), op->nx, op->ny, nrhs, op->diag, op->west, op->east,
                      op->south, op->north, X, B, R);
   });
@@ -644,7 +909,9 @@ acr_status acr_solve_refined(acr_handle h, const acr_operator* op, const double*
     if (!h || !B || !X || nrhs < 1 || maxit < 0) fail(ACR_ERR_INVALID_ARG, "bad arguments");
     if (op->nx != h->nx || op->ny != h->ny) fail(ACR_ERR_INVALID_ARG, "operator shape differs from the factor");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope ss(st);
     const long long n = (long long)op->nx * op->ny;
+    if (overlap(X, B, (size_t)n * nrhs)) fail(ACR_ERR_INVALID_ARG, "X must not overlap B");
     DBuf<double> R((size_t)n * nrhs), D((size_t)n * nrhs), nb(nrhs), nr(nrhs);
     std::vector<double> hb(nrhs), hr(nrhs);
     col_sumsq(st, n, nrhs, B, nb.get());
@@ -683,10 +950,11 @@ acr_status acr_solve_krylov(acr_handle h, const acr_operator* op, const double* 
     check_op(op);
     if (!h || !B || !X || nrhs < 1 || maxit < 0) fail(ACR_ERR_INVALID_ARG, "bad arguments");
     if (restart < 1 || restart > 64) fail(ACR_ERR_INVALID_ARG, "restart must be in 1..64");
-    if (X == B) fail(ACR_ERR_INVALID_ARG, "X must not alias B");
     if (op->nx != h->nx || op->ny != h->ny) fail(ACR_ERR_INVALID_ARG, "operator shape differs from the factor");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope ss(st);
     const long long n = (long long)op->nx * op->ny;
+    if (overlap(X, B, (size_t)n * nrhs)) fail(ACR_ERR_INVALID_ARG, "X must not overlap B");
     const int m = restart;
     DBuf<double> V((size_t)(m + 1) * n), Z((size_t)m * n), R(n), zero(n), dv(2 * (m + 1) + 1);
     memset_async(zero.get(), 0, (size_t)n * sizeof(double), st);
@@ -763,7 +1031,7 @@ acr_status acr_solve_krylov(acr_handle h, const acr_operator* op, const double* 
           y[i] = d != 0.0 ? v / d : 0.0;
         }
         if (k > 0) {
-          const double* yd = static_cast<const double*>(DescArena::get().put(y.data(), k * sizeof(double), st));
+          const double* yd = static_cast<const double*>(desc_put(y.data(), k * sizeof(double), st));
           maxpy(st, n, k, 1.0, 1.0, yd, Z.get(), n, x);
         }
       }
@@ -788,6 +1056,7 @@ acr_status acr_get_info(acr_handle h, acr_info* out) {
 acr_status acr_get_block(acr_handle h, int32_t level, int32_t which, int32_t k, double* dense, void* stream) {
   return guard([&] {
     if (!h || !dense) fail(ACR_ERR_INVALID_ARG, "NULL argument");
+    StreamScope ss(static_cast<hipStream_t>(stream));
     h->f->block(level, which, k, dense, static_cast<hipStream_t>(stream));
   });
 }
@@ -796,6 +1065,7 @@ acr_status acr_destroy(acr_handle h) {
   return guard([&] {
     if (!h) return;
     (void)hipDeviceSynchronize();
+    Pool::IdleScope idle;   // the factor's blocks are idle: any stream may reuse them
     delete h;
   });
 }
@@ -890,6 +1160,7 @@ acr_status acr_profile_report(char* buf, int64_t len, int64_t* needed) {
           r.bytes);
     }
     std::string out;
+    for (auto& kv : P.paths()) out += "path\t" + kv.first + "\t" + std::to_string(kv.second) + "\n";
     for (auto& kv : rows) {
       char line[512];
       std::snprintf(line, sizeof line, "%s\t%lld\t%.6f\t%.6e\t%.6e\n", kv.first.c_str(),
@@ -905,8 +1176,25 @@ acr_status acr_profile_report(char* buf, int64_t len, int64_t* needed) {
   });
 }
 
+int64_t acr_launch_count(void) { return (int64_t)launch_count(); }
+
 acr_status acr_trim_pool(void) {
   return guard([&] { Pool::get().trim(); });
+}
+
+acr_status acr_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*)) {
+  return guard([&] {
+    if ((alloc_fn == nullptr) != (free_fn == nullptr))
+      fail(ACR_ERR_INVALID_ARG, "give both callbacks or neither");
+    queue_flush();
+    Profiler::get().start(0);   // drops the profiler's device buffers (and its records)
+    Pool& P = Pool::get();
+    if (P.live() != 0) fail(ACR_ERR_INVALID_ARG, "the library holds live device memory (destroy every handle first)");
+    ACR_HIP(hipDeviceSynchronize());
+    P.release_all_cached();
+    Allocator::get().alloc = alloc_fn;
+    Allocator::get().free = free_fn;
+  });
 }
 
 }  // extern "C"

@@ -9,7 +9,9 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
+#include <thread>
 #include <stdexcept>
 #include <string>
 #include <utility>
@@ -42,10 +44,66 @@ struct Error : std::runtime_error {
 void queue_flush();
 
 // ------------------------------------------------------------ memory pool
-// Caching allocator: freed blocks are kept per rounded size and reused by
-// later requests on the same stream order (every library call uses one
-// stream, so a block released after enqueued work can be handed out to work
-// enqueued later on that stream without a synchronisation).
+// The stream that the calling thread's library work is enqueued on (set by
+// every entry point through StreamScope).
+struct CurStream {
+  static hipStream_t& get() {
+    static thread_local hipStream_t s = nullptr;
+    return s;
+  }
+};
+struct StreamScope {
+  hipStream_t saved;
+  explicit StreamScope(hipStream_t s) : saved(CurStream::get()) { CurStream::get() = s; }
+  ~StreamScope() { CurStream::get() = saved; }
+};
+
+// Device allocations.  By default hipMalloc / hipFree; acr_set_allocator
+// installs caller callbacks (for instance a framework's caching allocator),
+// which receive the stream the memory will be used on.
+struct Allocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, void*) = nullptr;
+  static Allocator& get() {
+    static Allocator a;
+    return a;
+  }
+};
+
+// Bump allocation from one fixed device region (the allocation-free solve):
+// while a thread has a Bump installed, every DBuf of that thread takes its
+// memory from the region and releases nothing.  In count-only mode nothing is
+// handed out for use (the caller issues no device work): only the bytes a
+// call would take are counted.
+struct Bump {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  bool count_only = false;
+  void* take(size_t bytes) {
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (!count_only && off + need > cap)
+      fail(ACR_ERR_INVALID_ARG, "the call needs more scratch memory than the allocation-free maximum");
+    void* p = base + (count_only ? 0 : off);
+    off += need;
+    return p;
+  }
+  bool owns(const void* p) const {
+    const char* c = static_cast<const char*>(p);
+    return c >= base && c < base + cap;
+  }
+  static Bump*& cur() {
+    static thread_local Bump* b = nullptr;
+    return b;
+  }
+};
+
+// Caching allocator.  A freed block is kept in the free list of the
+// (thread, stream) that released it: work of that thread on that stream may
+// still be pending or running and use the block, so it is handed out again
+// only to later work of the same thread on the same stream, which the stream
+// orders after it.  Blocks released after a device synchronisation (handle
+// destruction) are idle and go to a list shared by every stream.  trim()
+// returns the calling thread's cached blocks and the idle ones to the system.
 class Pool {
  public:
   static Pool& get() {
@@ -54,55 +112,92 @@ class Pool {
   }
   void* alloc(size_t bytes) {
     if (bytes == 0) return nullptr;
-    size_t r = round(bytes);
+    if (Bump* b = Bump::cur()) return b->take(bytes);
+    const size_t r = round(bytes);
+    const Key key = cur_key();
     {
       std::lock_guard<std::mutex> g(mu_);
-      auto it = free_.lower_bound(r);
-      if (it != free_.end() && it->first <= r + r / 4) {
-        void* p = it->second;
-        size_t sz = it->first;
-        free_.erase(it);
-        live_[p] = sz;
-        return p;
+      for (const Key& k : {key, idle_key()}) {
+        auto fl = free_.find(k);
+        if (fl == free_.end()) continue;
+        auto it = fl->second.lower_bound(r);
+        if (it != fl->second.end() && it->first <= r + r / 4) {
+          void* p = it->second;
+          const size_t sz = it->first;
+          fl->second.erase(it);
+          live_[p] = Live{sz, key.second};
+          return p;
+        }
       }
     }
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, r);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
+    void* p = raw_alloc(r, key.second);
+    if (!p) {
       trim();
-      e = hipMalloc(&p, r);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(ACR_ERR_OOM, "hipMalloc of " + std::to_string(r) + " bytes failed");
-      }
+      p = raw_alloc(r, key.second);
+      if (!p) fail(ACR_ERR_OOM, "device allocation of " + std::to_string(r) + " bytes failed");
     }
     std::lock_guard<std::mutex> g(mu_);
-    live_[p] = r;
+    live_[p] = Live{r, key.second};
     total_ += r;
     return p;
   }
   void release(void* p) {
     if (!p) return;
+    if (Bump* b = Bump::cur())
+      if (b->owns(p)) return;
     std::lock_guard<std::mutex> g(mu_);
     auto it = live_.find(p);
     if (it == live_.end()) return;
-    free_.emplace(it->second, p);
+    free_[idle() ? idle_key() : cur_key()].emplace(it->second.bytes, p);
     live_.erase(it);
   }
-  void trim() {
-    queue_flush();   // deferred work may still use the blocks freed below
+  // Blocks the calling thread releases inside this scope are known to be
+  // idle (the device was synchronised before).
+  struct IdleScope {
+    IdleScope() { idle() = true; }
+    ~IdleScope() { idle() = false; }
+  };
+  void trim();
+  size_t total() const { return total_; }
+  size_t live() {
     std::lock_guard<std::mutex> g(mu_);
-    if (!free_.empty()) (void)hipDeviceSynchronize();
-    for (auto& kv : free_) {
-      (void)hipFree(kv.second);
-      total_ -= kv.first;
-    }
+    return live_.size();
+  }
+  // Return every cached block of every thread to the current source (the
+  // caller synchronises the device first).
+  void release_all_cached() {
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto& fl : free_)
+      for (auto& kv : fl.second) {
+        raw_free(kv.second, fl.first.second);
+        total_ -= kv.first;
+      }
     free_.clear();
   }
-  size_t total() const { return total_; }
 
  private:
+  using Key = std::pair<std::thread::id, hipStream_t>;
+  struct Live {
+    size_t bytes;
+    hipStream_t st;
+  };
+  static Key cur_key() { return Key(std::this_thread::get_id(), CurStream::get()); }
+  static Key idle_key() { return Key(std::thread::id(), nullptr); }
+  static void* raw_alloc(size_t r, hipStream_t st) {
+    void* p = nullptr;
+    const Allocator& A = Allocator::get();
+    if (A.alloc) return A.alloc(r, st);
+    if (hipMalloc(&p, r) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  static void raw_free(void* p, hipStream_t st) {
+    const Allocator& A = Allocator::get();
+    if (A.free) A.free(p, st);
+    else (void)hipFree(p);
+  }
   static size_t round(size_t b) {
     if (b <= 4096) return 4096;
     size_t g = 1;
@@ -110,9 +205,13 @@ class Pool {
     return (b + g - 1) / g * g;
   }
   std::mutex mu_;
-  std::multimap<size_t, void*> free_;
-  std::map<void*, size_t> live_;
+  std::map<Key, std::multimap<size_t, void*>> free_;
+  std::map<void*, Live> live_;
   size_t total_ = 0;
+  static bool& idle() {
+    static thread_local bool v = false;
+    return v;
+  }
 };
 
 // Owning device buffer of n elements of T (from the pool).
@@ -195,6 +294,7 @@ class Profiler {
     std::lock_guard<std::mutex> g(mu_);
     for (auto& r : recs_) { pool_.push_back(r.a); pool_.push_back(r.b); }
     recs_.clear();
+    paths_.clear();
     owned_.clear();
     owned_d_.clear();
     mask_ = mask;
@@ -206,6 +306,14 @@ class Profiler {
     return e;
   }
   void push(const Rec& r) { std::lock_guard<std::mutex> g(mu_); recs_.push_back(r); }
+  // Count `n` problems planned on a named kernel path (while any class is
+  // recorded); lets tests check which variants a call used.
+  void hit(const char* path, long long n) {
+    if (!mask_) return;
+    std::lock_guard<std::mutex> g(mu_);
+    paths_[path] += n;
+  }
+  std::map<std::string, long long>& paths() { return paths_; }
   std::mutex& mu() { return mu_; }
   std::vector<Rec>& recs() { return recs_; }
   std::vector<DBuf<int>>& owned() { return owned_; }
@@ -215,6 +323,7 @@ class Profiler {
   unsigned mask_ = 0;
   std::mutex mu_;
   std::vector<Rec> recs_;
+  std::map<std::string, long long> paths_;
   std::vector<hipEvent_t> pool_;
   std::vector<DBuf<int>> owned_;
   std::vector<DBuf<double>> owned_d_;
@@ -227,7 +336,7 @@ struct ProfScope {
   ProfScope(int cls, hipStream_t s, double flops, double bytes, const Phase& ph = Phase::cur(),
             const char* kname = "-") {
     Profiler& P = Profiler::get();
-    if (!P.on(cls)) return;
+    if (!P.on(cls) || Bump::cur()) return;   // the allocation-free solve records no events
     act = true;
     st = s;
     std::lock_guard<std::mutex> g(P.mu());
@@ -274,27 +383,50 @@ inline BOp transposed(BOp o) { o.trans = 1; return o; }
 // ------------------------------------------------------- descriptor arena
 // Job descriptors of grouped launches are written to pinned host memory;
 // the pending range is copied to the device in one transfer when the queue
-// below is flushed, just before the launches that read it.  The arena wraps
-// around only after a stream synchronisation.
+// below is flushed, just before the launches that read it.  Each host thread
+// has its own arena; it wraps around only after a device synchronisation
+// (the thread may have used several streams).
 class DescArena {
  public:
   static DescArena& get() {
-    static DescArena a;
+    static thread_local DescArena a;
     return a;
   }
   // Stage `bytes` of host data; returns the device address it will have.
   void* put(const void* data, size_t bytes, hipStream_t st);
+  // An external device region for the descriptors of the calling thread (the
+  // allocation-free solve): host staging in ordinary host memory, no wrap
+  // (exceeding `cap` is an error), count_only: nothing is copied.
+  struct External {
+    std::vector<char> host;
+    char* dev = nullptr;
+    size_t cap = 0, off = 0, pend = 0;
+    bool count_only = false;
+    static External*& cur() {
+      static thread_local External* e = nullptr;
+      return e;
+    }
+  };
   // Copy everything staged since the last upload (on st).
   void upload_pending(hipStream_t st) {
     if (off_ > pend_)
       ACR_HIP(hipMemcpyAsync(dev_ + pend_, host_ + pend_, off_ - pend_, hipMemcpyHostToDevice, st));
     pend_ = off_;
   }
+  ~DescArena() {
+    if (host_) {
+      (void)hipDeviceSynchronize();
+      (void)hipHostFree(host_);
+      (void)hipFree(dev_);
+    }
+  }
 
  private:
   DescArena() { grow(size_t(16) << 20); }
   void grow(size_t cap) {
     if (host_) { (void)hipHostFree(host_); (void)hipFree(dev_); }
+    host_ = nullptr;
+    dev_ = nullptr;
     ACR_HIP(hipHostMalloc((void**)&host_, cap, hipHostMallocDefault));
     ACR_HIP(hipMalloc((void**)&dev_, cap));
     cap_ = cap;
@@ -305,6 +437,18 @@ class DescArena {
   size_t cap_ = 0, off_ = 0, pend_ = 0;
 };
 
+// Zero fills of up to kZeroBatch byte ranges in one launch of the library's
+// fill kernel (never hipMemsetAsync).
+constexpr int kZeroBatch = 32;
+struct ZeroArgs {
+  unsigned char* p[kZeroBatch];
+  unsigned long long n[kZeroBatch];
+  int count;
+};
+void zero_bytes_now(const ZeroArgs& z, hipStream_t st);
+
+inline void desc_upload(hipStream_t st);
+
 // ---------------------------------------------------------- deferred queue
 // Every stream operation of the library (kernel launches, fills, device
 // copies) is recorded here and issued in order by flush(), after a single
@@ -312,27 +456,42 @@ class DescArena {
 // of small descriptor copies of one factorisation into a few.  flush() is
 // called before any host read of device data, before memory is returned to
 // the system and at the end of every entry point; ops issued by flush() keep
-// stream order with everything enqueued before.  One stream at a time: a new
-// stream flushes the ops of the previous one first.
+// stream order with everything enqueued before.  One queue per host thread,
+// one stream at a time: a new stream flushes the ops of the previous one.
 class Queue {
  public:
   static Queue& get() {
-    static Queue q;
+    static thread_local Queue q;
     return q;
   }
   void op(hipStream_t st, std::function<void()> f) {
+    if (dry_) return;   // planning only: nothing reaches the device
     if (!ops_.empty() && st != st_) flush();
     st_ = st;
+    last_fill_.reset();
     ops_.push_back(std::move(f));
     if (ops_.size() >= kMaxPending) flush();
+  }
+  // Add a zero fill to the fill launch recorded last, if that is the last
+  // pending op (same stream, room left); false otherwise.
+  bool append_fill(hipStream_t st, void* p, size_t bytes) {
+    if (!last_fill_ || st != st_ || ops_.empty() || last_fill_->count >= kZeroBatch) return false;
+    last_fill_->p[last_fill_->count] = static_cast<unsigned char*>(p);
+    last_fill_->n[last_fill_->count] = bytes;
+    ++last_fill_->count;
+    return true;
+  }
+  void set_fill(hipStream_t st, std::shared_ptr<ZeroArgs> z) {
+    if (st == st_ && !ops_.empty()) last_fill_ = std::move(z);
   }
   void flush() {
     if (flushing_) return;
     flushing_ = true;
     std::vector<std::function<void()>> ops;
     ops.swap(ops_);
+    last_fill_.reset();
     try {
-      DescArena::get().upload_pending(st_);
+      desc_upload(st_);
       for (auto& f : ops) f();
     } catch (...) {
       flushing_ = false;
@@ -341,23 +500,60 @@ class Queue {
     flushing_ = false;
   }
   // Drop recorded ops (after an error: their buffers may be gone).
-  void discard() { ops_.clear(); }
+  void discard() {
+    ops_.clear();
+    last_fill_.reset();
+  }
   bool empty() const { return ops_.empty(); }
+  // While dry, recorded operations are dropped (a planning pass that only
+  // measures the memory a call takes).
+  bool dry() const { return dry_; }
+  void set_dry(bool d) { dry_ = d; }
 
  private:
   static constexpr size_t kMaxPending = 24;   // keeps the device fed during long host planning
   std::vector<std::function<void()>> ops_;
+  std::shared_ptr<ZeroArgs> last_fill_;
   hipStream_t st_ = nullptr;
   bool flushing_ = false;
+  bool dry_ = false;
 };
 
 inline void queue_flush() { Queue::get().flush(); }
 
+// Descriptor staging of the calling thread: the external region when one is
+// installed, else the thread's arena.
+inline void* desc_put(const void* data, size_t bytes, hipStream_t st) {
+  if (DescArena::External* e = DescArena::External::cur()) {
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (!e->count_only && e->off + need > e->cap)
+      fail(ACR_ERR_INVALID_ARG, "the call needs more descriptor memory than the allocation-free maximum");
+    if (!e->count_only) {
+      if (e->host.size() < e->off + need) e->host.resize(std::max(e->off + need, 2 * e->host.size()));
+      std::memcpy(e->host.data() + e->off, data, bytes);
+    }
+    void* d = e->dev + (e->count_only ? 0 : e->off);
+    e->off += need;
+    return d;
+  }
+  return DescArena::get().put(data, bytes, st);
+}
+inline void desc_upload(hipStream_t st) {
+  if (DescArena::External* e = DescArena::External::cur()) {
+    if (!e->count_only && e->off > e->pend)
+      ACR_HIP(hipMemcpyAsync(e->dev + e->pend, e->host.data() + e->pend, e->off - e->pend, hipMemcpyHostToDevice, st));
+    e->pend = e->off;
+    return;
+  }
+  DescArena::get().upload_pending(st);
+}
+
 inline void* DescArena::put(const void* data, size_t bytes, hipStream_t st) {
+  (void)st;
   const size_t need = (bytes + 255) & ~size_t(255);
   if (off_ + need > cap_) {
     Queue::get().flush();              // issues the ops reading the staged range
-    ACR_HIP(hipStreamSynchronize(st));
+    ACR_HIP(hipDeviceSynchronize());   // every stream this thread used is done with the arena
     off_ = pend_ = 0;
     if (need > cap_) grow(need * 2);
   }
@@ -367,11 +563,41 @@ inline void* DescArena::put(const void* data, size_t bytes, hipStream_t st) {
   return d;
 }
 
+inline void Pool::trim() {
+  queue_flush();   // deferred work of this thread may still use the blocks freed below
+  std::lock_guard<std::mutex> g(mu_);
+  bool any = false;
+  for (const Key& k : {cur_key(), idle_key()}) {
+    auto fl = free_.find(k);
+    if (fl != free_.end() && !fl->second.empty()) any = true;
+  }
+  if (!any) return;
+  (void)hipDeviceSynchronize();
+  for (const Key& k : {cur_key(), idle_key()}) {
+    auto fl = free_.find(k);
+    if (fl == free_.end()) continue;
+    for (auto& kv : fl->second) {
+      raw_free(kv.second, k.second);
+      total_ -= kv.first;
+    }
+    free_.erase(fl);
+  }
+}
+
+
+// Kernel launches (and fills) recorded by the calling thread so far.
+inline long long& launch_count() {
+  static thread_local long long n = 0;
+  return n;
+}
+
 // Record a kernel launch (timed by the profiler when its class is selected).
 template <typename... KArgs, typename... Args>
 void launch(hipStream_t st, int cls, double flops, double bytes, const char* kname, void (*kern)(KArgs...),
             dim3 grid, dim3 block, size_t shmem, Args... args) {
   const Phase ph = Phase::cur();
+  if (Queue::get().dry()) return;
+  ++launch_count();
   Queue::get().op(st, [=]() {
     ProfScope ps(cls, st, flops, bytes, ph, kname);
     hipLaunchKernelGGL(kern, grid, block, shmem, st, args...);
@@ -379,10 +605,20 @@ void launch(hipStream_t st, int cls, double flops, double bytes, const char* kna
   });
 }
 
-// Record a byte fill / a device-to-device copy.
+// Record a zero fill (consecutive fills share one launch) / a device-to-device copy.
 inline void memset_async(void* p, int v, size_t bytes, hipStream_t st) {
   if (!bytes) return;
-  Queue::get().op(st, [=]() { ACR_HIP(hipMemsetAsync(p, v, bytes, st)); });
+  if (v != 0) fail(ACR_ERR_INTERNAL, "memset_async supports zero fills only");
+  Queue& q = Queue::get();
+  if (q.dry()) return;
+  if (!q.append_fill(st, p, bytes)) {
+    ++launch_count();
+    auto z = std::make_shared<ZeroArgs>();
+    z->count = 0;
+    q.op(st, [=]() { zero_bytes_now(*z, st); });
+    q.set_fill(st, z);
+    q.append_fill(st, p, bytes);
+  }
 }
 inline void copy_d2d_async(void* dst, const void* src, size_t bytes, hipStream_t st) {
   if (!bytes) return;

@@ -1,0 +1,151 @@
+// The stored ACR factorisation of one problem and the entry-point helpers
+// shared by the library's C ABI files (acr.hip, serve.hip).
+#pragma once
+
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hodlr.hpp"
+#include "kernels.hpp"
+
+namespace acr {
+
+struct FactorBase {
+  virtual ~FactorBase() = default;
+  virtual void solve(const double* B, double* X, int nrhs, hipStream_t st) = 0;
+  virtual void info(acr_info* out) const = 0;
+  virtual void block(int level, int which, int k, double* dense, hipStream_t st) const = 0;
+};
+
+template <typename T>
+struct Level {
+  int m = 0;        // blocks at this level
+  int nreal = 0;    // even blocks (ceil(m/2))
+  int ne = 0;       // even slots incl. a zero dummy when m is even (floor(m/2)+1)
+  HSet<T> X;        // nreal inverses
+  bool diag = false;
+  DBuf<T> e0, f0;   // level 0: diagonals of E_i, F_i ([m][s])
+  HSet<T> E, F;     // level >= 1: m HODLR blocks each
+};
+
+template <typename T>
+struct Factor final : FactorBase {
+  int nx = 0, ny = 0, leaf = 0, b = 0, L = 0, precision = 0;
+  double eps = 0;
+  std::vector<Level<T>> lev;
+  HSet<T> Xlast;
+  Work work_done;
+  std::vector<int> lev_rank;
+  std::vector<double> lev_mean;
+  long long launches = 0;
+  int batch = 1;   // problems factored together (work and launches are of the batch)
+
+  size_t bytes() const {
+    size_t t = Xlast.bytes();
+    for (const auto& l : lev) {
+      t += l.X.bytes() + l.E.bytes() + l.F.bytes() + l.e0.bytes() + l.f0.bytes();
+    }
+    return t;
+  }
+
+  void info(acr_info* o) const override {
+    std::memset(o, 0, sizeof(*o));
+    o->nx = nx; o->ny = ny; o->leaf = leaf; o->depth = L; o->levels = (int)lev.size();
+    o->precision = precision; o->eps = eps;
+    o->factor_bytes = (int64_t)bytes();
+    int mr = Xlast.max_rank();
+    for (size_t i = 0; i < lev.size() && i < 40; ++i) {
+      o->level_max_rank[i] = lev_rank[i];
+      mr = std::max(mr, lev_rank[i]);
+    }
+    o->max_rank = mr;
+    o->factor_flops = work_done.total();
+    // one solve pass reads every stored X twice (forward and back) and every
+    // stored E/F once
+    double sb = 2.0 * Xlast.bytes();
+    double fl = 0;
+    for (const auto& l : lev) {
+      sb += 2.0 * l.X.bytes() + l.E.bytes() + l.F.bytes() + l.e0.bytes() + l.f0.bytes();
+    }
+    o->solve_bytes = sb;
+    // two flops per stored multiply-add entry read
+    fl = 2.0 * sb / sizeof(T);
+    o->solve_flops_per_rhs = fl;
+    double fr = Xlast.bytes_ranked(), sr = 2.0 * Xlast.bytes_ranked();
+    for (const auto& l : lev) {
+      const double x = l.X.bytes_ranked(), ef = l.E.bytes_ranked() + l.F.bytes_ranked() + l.e0.bytes() + l.f0.bytes();
+      fr += x + ef;
+      sr += 2.0 * x + ef;
+    }
+    o->factor_bytes_ranked = fr;
+    o->solve_bytes_ranked = sr;
+    for (size_t i = 0; i < lev_mean.size() && i < 40; ++i) o->level_mean_rank[i] = lev_mean[i];
+    o->factor_launches = launches;
+  }
+
+  void block(int level, int which, int k, double* dense, hipStream_t st) const override {
+    const int s = nx;
+    if (level == (int)lev.size()) {
+      if (which != 0 || k != 0) fail(ACR_ERR_INVALID_ARG, "last level holds only X_0");
+      densify_to_host(st, Xlast, 0, dense);
+      return;
+    }
+    if (level < 0 || level > (int)lev.size()) fail(ACR_ERR_INVALID_ARG, "level out of range");
+    const Level<T>& l = lev[level];
+    if (which == 0) {
+      if (k < 0 || k >= l.m || (k & 1)) fail(ACR_ERR_INVALID_ARG, "X_k needs an even k < m");
+      densify_to_host(st, l.X, k / 2, dense);
+      return;
+    }
+    if (which != 1 && which != 2) fail(ACR_ERR_INVALID_ARG, "which must be 0, 1 or 2");
+    if (k < 0 || k >= l.m) fail(ACR_ERR_INVALID_ARG, "block index out of range");
+    if (l.diag) {
+      std::vector<T> d(s);
+      const DBuf<T>& src = which == 1 ? l.e0 : l.f0;
+      read_to_host(d.data(), src.get() + (size_t)k * s, s * sizeof(T), st);
+      for (size_t e = 0; e < (size_t)s * s; ++e) dense[e] = 0.0;
+      for (int r = 0; r < s; ++r) dense[(size_t)r * (s + 1)] = (double)d[r];
+    } else {
+      densify_to_host(st, which == 1 ? l.E : l.F, k, dense);
+    }
+  }
+
+  void solve(const double* B, double* Xout, int nrhs, hipStream_t st) override;
+  void solve_fused(const double* B, double* Xout, int nrhs, hipStream_t st);
+  void solve_gemm(const double* B, double* Xout, int nrhs, hipStream_t st);
+  bool fused_ok(int nrhs) const;
+};
+
+// Factor the problems ops[0..] together (see acr.hip).
+template <typename T>
+std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operator>& ops, const acr_options& opt,
+                                                    hipStream_t st);
+
+// X_p = M_p^{-1} B_p for several factors with <= 8 right-hand sides each, in
+// shared launches (see acr.hip).
+template <typename T>
+void solve_fused_many(const std::vector<const Factor<T>*>& fs, const std::vector<const double*>& Bs,
+                      const std::vector<double*>& Xs, const std::vector<int>& nrs, hipStream_t st);
+
+// HODLR depth of block size s for a leaf bound (-1 if the halving is not exact).
+int hodlr_depth(int s, int leaf);
+
+// Runs an entry point body: flushes its launches at the end, turns
+// exceptions into status codes and the thread's last-error text.
+acr_status guard(const std::function<void()>& fn);
+void set_last_error(const std::string& msg);
+
+// Argument checks shared by the entry points (ACR_ERR_INVALID_ARG).
+void check_op(const acr_operator* op);
+void check_options(const acr_options* opt);
+bool overlap2(const double* a, size_t na, const double* b, size_t nb);
+
+}  // namespace acr
+
+struct acr_handle_s {
+  std::unique_ptr<acr::FactorBase> f;
+  int precision = 0;
+  int nx = 0, ny = 0;
+};

@@ -16,10 +16,11 @@ Work& work() {
 // ------------------------------------------------------------------ HSet
 template <typename T>
 void HSet<T>::alloc(hipStream_t st, int cnt_, int s_, int b_, int L_, const std::vector<int>& k_,
-                    bool zero) {
+                    int zero_from) {
   cnt = cnt_; s = s_; b = b_; L = L_;
   k.assign(L + 1, 0);
   kc.assign(L + 1, 0);
+  rsum.assign(L + 1, -1.0);
   for (int d = 1; d <= L; ++d) k[d] = d < (int)k_.size() ? k_[d] : 0;
   lv.resize((size_t)cnt * leaf_stride());
   U.clear(); V.clear();
@@ -28,11 +29,13 @@ void HSet<T>::alloc(hipStream_t st, int cnt_, int s_, int b_, int L_, const std:
     U[d].resize((size_t)cnt * k[d] * s);
     V[d].resize((size_t)cnt * k[d] * s);
   }
-  if (zero) {
-    memset_async(lv.get(), 0, lv.bytes(), st);
+  if (zero_from >= 0 && zero_from < cnt) {   // matrices [zero_from, cnt) start as zeros
+    const size_t nz = (size_t)(cnt - zero_from);
+    memset_async(lv.get() + (size_t)zero_from * leaf_stride(), 0, nz * leaf_stride() * sizeof(T), st);
     for (int d = 1; d <= L; ++d) {
-      memset_async(U[d].get(), 0, U[d].bytes(), st);
-      memset_async(V[d].get(), 0, V[d].bytes(), st);
+      const size_t per = (size_t)k[d] * s;
+      memset_async(U[d].get() + (size_t)zero_from * per, 0, nz * per * sizeof(T), st);
+      memset_async(V[d].get() + (size_t)zero_from * per, 0, nz * per * sizeof(T), st);
     }
   }
 }
@@ -41,6 +44,14 @@ template <typename T>
 size_t HSet<T>::bytes() const {
   size_t t = (size_t)cnt * leaf_stride() * sizeof(T);
   for (int d = 1; d <= L; ++d) t += 2 * (size_t)cnt * kc[d] * s * sizeof(T);
+  return t;
+}
+
+template <typename T>
+double HSet<T>::bytes_ranked() const {
+  // depth d: 2^d blocks per matrix of sd = s/2^d rows each, U and V
+  double t = (double)cnt * leaf_stride() * sizeof(T);
+  for (int d = 1; d <= L; ++d) t += 2.0 * rank_sum(d) * sd(d) * sizeof(T);
   return t;
 }
 
@@ -310,7 +321,7 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
       }
     }
     HSet<T>& C = *O.C;
-    C.alloc(st, O.cnt_alloc, s, b, L, kC, O.cnt_alloc > nmat);
+    C.alloc(st, O.cnt_alloc, s, b, L, kC, O.cnt_alloc > nmat ? nmat : -1);
     for (int d = 1; d <= L; ++d) {
       int col = 0;
       auto cu = [&](int c0) { return bop(C.U[d].get() + (size_t)c0 * s, s, (long long)C.k[d] * s); };
@@ -379,118 +390,200 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
 
 // ------------------------------------------------------------------- hinv
 template <typename T>
-void hinv(hipStream_t st, HSet<T>& X, HV<T> M, int nmat, int* status) {
-  const HSet<T>& mm = *M.h;
-  const int L = mm.L, s = mm.s, b = mm.b, nleaf = mm.nleaf();
-  std::vector<int> kX(L + 1, 0);
-  for (int d = 1; d <= L; ++d)
-    for (int e = 1; e <= d; ++e) kX[d] += mm.kc[e];
-  X.alloc(st, nmat, s, b, L, kX, false);
-  // leaves: X_l = M_l^{-1}
-  gcopy<T>(st, {copy_job((int)mm.leaf_stride(), 1, nmat, 1.0,
-                         with_map(bop(mm.lv.get(), 1, mm.leaf_stride()), M.mmul, M.moff),
-                         bop(X.lv.get(), 1, X.leaf_stride()))});
-  binverse<T, T>(st, b, nmat * nleaf, X.lv.get(), (long long)b * b, X.lv.get(), (long long)b * b,
-                 status);
-  work().inv_flops += 2.0 * b * b * b * nmat * nleaf;
-  HV<T> XV{&X, 1, 0};
-  for (int d = L; d >= 1; --d) {
-    const int k = mm.kc[d];
-    if (k == 0) continue;
-    const int ncl = 1 << d, sd = mm.sd(d);
+void hinv_multi(hipStream_t st, std::vector<HInvJob<T>>& jobs) {
+  std::vector<HInvJob<T>> js;
+  for (auto& J : jobs)
+    if (J.nmat > 0) js.push_back(J);
+  if (js.empty()) return;
+  int maxL = 0;
+  {
+    std::vector<CJob> cp;
+    std::vector<IJob> ij;
+    for (auto& J : js) {
+      const HSet<T>& mm = *J.M.h;
+      const int L = mm.L, s = mm.s, b = mm.b, nleaf = mm.nleaf();
+      maxL = std::max(maxL, L);
+      std::vector<int> kX(L + 1, 0);
+      for (int d = 1; d <= L; ++d)
+        for (int e = 1; e <= d; ++e) kX[d] += mm.kc[e];
+      J.X->alloc(st, J.nmat, s, b, L, kX, -1);
+      // leaves: X_l = M_l^{-1}
+      cp.push_back(copy_job((int)mm.leaf_stride(), 1, J.nmat, 1.0,
+                            with_map(bop(mm.lv.get(), 1, mm.leaf_stride()), J.M.mmul, J.M.moff),
+                            bop(J.X->lv.get(), 1, J.X->leaf_stride())));
+      IJob I;
+      I.n = b; I.nprob = J.nmat * nleaf; I.A = J.X->lv.get(); I.sA = (long long)b * b;
+      I.X = J.X->lv.get(); I.sX = (long long)b * b; I.status = J.status;
+      ij.push_back(I);
+      work().inv_flops += 2.0 * b * b * b * J.nmat * nleaf;
+    }
+    gcopy<T>(st, cp);
+    ginverse<T, T>(st, ij);
+  }
+  // Sherman-Morrison-Woodbury, bottom-up: step i handles depth L - i of every tree
+  for (int step = 0; step < maxL; ++step) {
+    struct Part {
+      HInvJob<T>* J;
+      int d, k, ncl, sd;
+      DBuf<T> abuf, bbuf, wbuf, cores, G;
+    };
+    std::vector<Part> parts;
+    for (auto& J : js) {
+      const int d = J.M.h->L - step;
+      if (d < 1) continue;
+      const int k = J.M.h->kc[d];
+      if (k == 0) continue;
+      Part pt;
+      pt.J = &J; pt.d = d; pt.k = k; pt.ncl = 1 << d; pt.sd = J.M.h->sd(d);
+      parts.push_back(std::move(pt));
+    }
+    if (parts.empty()) continue;
     std::vector<DBuf<T>> keep;
-    DBuf<T> abuf((size_t)nmat * k * s), bbuf((size_t)nmat * k * s), wbuf((size_t)nmat * k * s);
-    Flat<T> fa; fa.p = abuf.get(); fa.ld = s; fa.sm = (long long)k * s;
-    Flat<T> fb; fb.p = bbuf.get(); fb.ld = s; fb.sm = (long long)k * s;
-    Flat<T> fw; fw.p = wbuf.get(); fw.ld = s; fw.sm = (long long)k * s;
-    // a = Xdiag U^M (children inverses applied), bb = Xdiag^T V^M
     GemmPlan red, exp;
-    auto sa = plan_hmul<T>(red, keep, XV, nmat, d, false, k, 1.0, flat_set(M, mm.U[d], d));
-    auto sb = plan_hmul<T>(red, keep, XV, nmat, d, true, k, 1.0, flat_set(M, mm.V[d], d));
-    exp.add(b, k, nmat, nleaf, 1.0, 0.0, flat_op(fa, b), sa);
-    exp.add(b, k, nmat, nleaf, 1.0, 0.0, flat_op(fb, b), sb);
+    for (auto& pt : parts) {
+      const HInvJob<T>& J = *pt.J;
+      const HSet<T>& mm = *J.M.h;
+      const int s = mm.s, b = mm.b, nleaf = mm.nleaf(), k = pt.k, d = pt.d, nmat = J.nmat;
+      pt.abuf.resize((size_t)nmat * k * s);
+      pt.bbuf.resize((size_t)nmat * k * s);
+      pt.wbuf.resize((size_t)nmat * k * s);
+      Flat<T> fa; fa.p = pt.abuf.get(); fa.ld = s; fa.sm = (long long)k * s;
+      Flat<T> fb; fb.p = pt.bbuf.get(); fb.ld = s; fb.sm = (long long)k * s;
+      // a = Xdiag U^M (children inverses applied), bb = Xdiag^T V^M
+      HV<T> XV{J.X, 1, 0};
+      auto sa = plan_hmul<T>(red, keep, XV, nmat, d, false, k, 1.0, flat_set(J.M, mm.U[d], d));
+      auto sb = plan_hmul<T>(red, keep, XV, nmat, d, true, k, 1.0, flat_set(J.M, mm.V[d], d));
+      exp.add(b, k, nmat, nleaf, 1.0, 0.0, flat_op(fa, b), sa);
+      exp.add(b, k, nmat, nleaf, 1.0, 0.0, flat_op(fb, b), sb);
+    }
     red.run<T>(st);
     exp.run<T>(st);
     // cores c_sigma = V^M[sigma]^T a[sigma]
-    DBuf<T> cores((size_t)nmat * ncl * k * k);
     GemmPlan cp;
-    cp.add(k, k, nmat, ncl, 1.0, 0.0, bop(cores.get(), k, (long long)ncl * k * k, (long long)k * k),
-           {seg(transposed(factor_op(M, mm.V[d], d, sd)), flat_op(fa, sd), sd)});
-    cp.run<T>(st);
-    const int npairs = nmat * ncl / 2, n2 = 2 * k;
-    DBuf<T> G((size_t)npairs * n2 * n2);
-    build_capacitance<T>(st, k, npairs, cores.get(), G.get());
-    binverse<T, T>(st, n2, npairs, G.get(), (long long)n2 * n2, G.get(), (long long)n2 * n2, status);
-    work().inv_flops += 2.0 * n2 * n2 * n2 * npairs;
-    // diagonal block of G^{-1} for cluster t: (t&1) selects (0,0) or (1,1)
-    BOp Gd;
-    Gd.p = G.get(); Gd.ld = n2; Gd.sm = (long long)(ncl / 2) * n2 * n2;
-    Gd.sc_pair = (long long)n2 * n2; Gd.sc_odd = (long long)k + (long long)k * n2;
-    BOp Go = Gd;
-    Go.p = G.get() + (size_t)k * n2;              // (0,1) block for a first child
-    Go.sc_odd = (long long)k - (long long)k * n2;  // (1,0) block for a second child
-    // U^X_d = -a[t] Gdiag(t);  W = a[t] Goff(t)
-    GemmPlan gp;
-    gp.add(sd, k, nmat, ncl, -1.0, 0.0, bop(X.U[d].get(), s, (long long)X.k[d] * s, sd), {seg(flat_op(fa, sd), Gd, k)});
-    gp.add(sd, k, nmat, ncl, 1.0, 0.0, flat_op(fw, sd), {seg(flat_op(fa, sd), Go, k)});
-    gp.run<T>(st);
-    // V^X_d = bb; X[t,t] -= W[t] bb[t]^T pushed to every depth below d
-    std::vector<CJob> cj;
-    cj.push_back(copy_job(s, k, nmat, 1.0, bop(bbuf.get(), s, (long long)k * s), bop(X.V[d].get(), s, (long long)X.k[d] * s)));
-    X.kc[d] = k;
-    for (int e = d + 1; e <= L; ++e) {
-      cj.push_back(copy_job(s, k, nmat, -1.0, bop(wbuf.get(), s, (long long)k * s),
-                            bop(X.U[e].get() + (size_t)X.kc[e] * s, s, (long long)X.k[e] * s)));
-      cj.push_back(copy_job(s, k, nmat, 1.0, bop(bbuf.get(), s, (long long)k * s),
-                            bop(X.V[e].get() + (size_t)X.kc[e] * s, s, (long long)X.k[e] * s)));
-      X.kc[e] += k;
+    std::vector<CapJob> capj;
+    for (auto& pt : parts) {
+      const HInvJob<T>& J = *pt.J;
+      const HSet<T>& mm = *J.M.h;
+      const int s = mm.s, k = pt.k, d = pt.d, nmat = J.nmat, ncl = pt.ncl;
+      Flat<T> fa; fa.p = pt.abuf.get(); fa.ld = s; fa.sm = (long long)k * s;
+      pt.cores.resize((size_t)nmat * ncl * k * k);
+      cp.add(k, k, nmat, ncl, 1.0, 0.0, bop(pt.cores.get(), k, (long long)ncl * k * k, (long long)k * k),
+             {seg(transposed(factor_op(J.M, mm.V[d], d, pt.sd)), flat_op(fa, pt.sd), pt.sd)});
+      const int npairs = nmat * ncl / 2, n2 = 2 * k;
+      pt.G.resize((size_t)npairs * n2 * n2);
+      CapJob C;
+      C.k = k; C.npairs = npairs; C.cores = pt.cores.get(); C.G = pt.G.get();
+      capj.push_back(C);
     }
+    cp.run<T>(st);
+    gbuild_capacitance<T>(st, capj);
+    {
+      std::vector<IJob> ij;
+      for (auto& pt : parts) {
+        const int npairs = pt.J->nmat * pt.ncl / 2, n2 = 2 * pt.k;
+        IJob I;
+        I.n = n2; I.nprob = npairs; I.A = pt.G.get(); I.sA = (long long)n2 * n2;
+        I.X = pt.G.get(); I.sX = (long long)n2 * n2; I.status = pt.J->status;
+        ij.push_back(I);
+        work().inv_flops += 2.0 * n2 * n2 * n2 * npairs;
+      }
+      ginverse<T, T>(st, ij);
+    }
+    GemmPlan gp, lp;
+    std::vector<CJob> cj;
+    for (auto& pt : parts) {
+      HInvJob<T>& J = *pt.J;
+      HSet<T>& X = *J.X;
+      const HSet<T>& mm = *J.M.h;
+      const int s = mm.s, b = mm.b, L = mm.L, nleaf = mm.nleaf(), k = pt.k, d = pt.d, nmat = J.nmat, ncl = pt.ncl;
+      const int n2 = 2 * k;
+      Flat<T> fa; fa.p = pt.abuf.get(); fa.ld = s; fa.sm = (long long)k * s;
+      Flat<T> fw; fw.p = pt.wbuf.get(); fw.ld = s; fw.sm = (long long)k * s;
+      // diagonal block of G^{-1} for cluster t: (t&1) selects (0,0) or (1,1)
+      BOp Gd;
+      Gd.p = pt.G.get(); Gd.ld = n2; Gd.sm = (long long)(ncl / 2) * n2 * n2;
+      Gd.sc_pair = (long long)n2 * n2; Gd.sc_odd = (long long)k + (long long)k * n2;
+      BOp Go = Gd;
+      Go.p = pt.G.get() + (size_t)k * n2;              // (0,1) block for a first child
+      Go.sc_odd = (long long)k - (long long)k * n2;    // (1,0) block for a second child
+      // U^X_d = -a[t] Gdiag(t);  W = a[t] Goff(t)
+      gp.add(pt.sd, k, nmat, ncl, -1.0, 0.0, bop(X.U[d].get(), s, (long long)X.k[d] * s, pt.sd),
+             {seg(flat_op(fa, pt.sd), Gd, k)});
+      gp.add(pt.sd, k, nmat, ncl, 1.0, 0.0, flat_op(fw, pt.sd), {seg(flat_op(fa, pt.sd), Go, k)});
+      // V^X_d = bb; X[t,t] -= W[t] bb[t]^T pushed to every depth below d
+      cj.push_back(copy_job(s, k, nmat, 1.0, bop(pt.bbuf.get(), s, (long long)k * s),
+                            bop(X.V[d].get(), s, (long long)X.k[d] * s)));
+      X.kc[d] = k;
+      for (int e = d + 1; e <= L; ++e) {
+        cj.push_back(copy_job(s, k, nmat, -1.0, bop(pt.wbuf.get(), s, (long long)k * s),
+                              bop(X.U[e].get() + (size_t)X.kc[e] * s, s, (long long)X.k[e] * s)));
+        cj.push_back(copy_job(s, k, nmat, 1.0, bop(pt.bbuf.get(), s, (long long)k * s),
+                              bop(X.V[e].get() + (size_t)X.kc[e] * s, s, (long long)X.k[e] * s)));
+        X.kc[e] += k;
+      }
+      lp.add(b, b, nmat, nleaf, 1.0, 1.0, bop(X.lv.get(), b, X.leaf_stride(), (long long)b * b),
+             {seg(bop(pt.wbuf.get(), s, (long long)k * s, b), bop(pt.bbuf.get(), s, (long long)k * s, b, 1), k, -1.0)});
+    }
+    gp.run<T>(st);
     gcopy<T>(st, cj);
-    GemmPlan lp;
-    lp.add(b, b, nmat, nleaf, 1.0, 1.0, bop(X.lv.get(), b, X.leaf_stride(), (long long)b * b),
-           {seg(bop(wbuf.get(), s, (long long)k * s, b), bop(bbuf.get(), s, (long long)k * s, b, 1), k, -1.0)});
     lp.run<T>(st);
   }
   Queue::get().flush();   // let the device start while the host plans the next step
 }
 
+template <typename T>
+void hinv(hipStream_t st, HSet<T>& X, HV<T> M, int nmat, int* status) {
+  std::vector<HInvJob<T>> js{HInvJob<T>{&X, M, nmat, status}};
+  hinv_multi<T>(st, js);
+}
+
 // ------------------------------------------------------------- level 0
 template <typename T>
-void hstack(hipStream_t st, HSet<T>& C, int cnt_alloc, const std::vector<ScaleTerm<T>>& terms, int nmat) {
-  const HSet<T>& h0 = *terms[0].h.h;
-  const int L = h0.L, s = h0.s, b = h0.b;
-  std::vector<int> kC(L + 1, 0);
-  for (const auto& t : terms)
-    for (int d = 1; d <= L; ++d) kC[d] += t.h.h->kc[d];
-  C.alloc(st, cnt_alloc, s, b, L, kC, cnt_alloc > nmat);
-  const long long ls = C.leaf_stride();
+void hstack_multi(hipStream_t st, std::vector<StackOut<T>>& outs) {
+  // the first term of every output is a plain (scaled) copy; every further
+  // term accumulates into the leaves, one launch per term index so that the
+  // accumulations of one output are ordered
   std::vector<CJob> first;
   std::vector<std::vector<CJob>> rest;
-  std::vector<int> col(L + 1, 0);
-  for (size_t ti = 0; ti < terms.size(); ++ti) {
-    const auto& t = terms[ti];
-    const HSet<T>& h = *t.h.h;
-    // leaves (rows of leaf c are rows c*b.. of the scale vector)
-    CJob lj = copy_job(b, b, nmat, t.coef, leaves_op(t.h), bop(C.lv.get(), b, ls, (long long)b * b), h.nleaf(),
-                       ti > 0 ? 1 : 0);
-    if (t.rows) { lj.scale = t.rows; lj.smul = t.rmul; lj.soff = t.roff; lj.sstride = s; lj.scl = b; lj.sside = 0; }
-    if (ti == 0) first.push_back(lj);
-    else rest.push_back({lj});
-    for (int d = 1; d <= L; ++d) {
-      const int w = h.kc[d];
-      if (!w) continue;
-      CJob uj = copy_job(s, w, nmat, t.coef, factor_op(t.h, h.U[d], d, 0),
-                         bop(C.U[d].get() + (size_t)col[d] * s, s, (long long)C.k[d] * s));
-      if (t.rows) { uj.scale = t.rows; uj.smul = t.rmul; uj.soff = t.roff; uj.sstride = s; uj.scl = 0; uj.sside = 0; }
-      first.push_back(uj);
-      first.push_back(copy_job(s, w, nmat, 1.0, factor_op(t.h, h.V[d], d, 0),
-                               bop(C.V[d].get() + (size_t)col[d] * s, s, (long long)C.k[d] * s)));
-      col[d] += w;
+  for (auto& O : outs) {
+    if (O.terms.empty()) continue;
+    const HSet<T>& h0 = *O.terms[0].h.h;
+    const int L = h0.L, s = h0.s, b = h0.b, nmat = O.nmat;
+    std::vector<int> kC(L + 1, 0);
+    for (const auto& t : O.terms)
+      for (int d = 1; d <= L; ++d) kC[d] += t.h.h->kc[d];
+    HSet<T>& C = *O.C;
+    C.alloc(st, O.cnt_alloc, s, b, L, kC, O.cnt_alloc > nmat ? nmat : -1);
+    const long long ls = C.leaf_stride();
+    std::vector<int> col(L + 1, 0);
+    for (size_t ti = 0; ti < O.terms.size(); ++ti) {
+      const auto& t = O.terms[ti];
+      const HSet<T>& h = *t.h.h;
+      // leaves (rows of leaf c are rows c*b.. of the scale vector)
+      CJob lj = copy_job(b, b, nmat, t.coef, leaves_op(t.h), bop(C.lv.get(), b, ls, (long long)b * b), h.nleaf(),
+                         ti > 0 ? 1 : 0);
+      if (t.rows) { lj.scale = t.rows; lj.smul = t.rmul; lj.soff = t.roff; lj.sstride = s; lj.scl = b; lj.sside = 0; }
+      if (ti == 0) first.push_back(lj);
+      else {
+        if (rest.size() < ti) rest.resize(ti);
+        rest[ti - 1].push_back(lj);
+      }
+      for (int d = 1; d <= L; ++d) {
+        const int w = h.kc[d];
+        if (!w) continue;
+        CJob uj = copy_job(s, w, nmat, t.coef, factor_op(t.h, h.U[d], d, 0),
+                           bop(C.U[d].get() + (size_t)col[d] * s, s, (long long)C.k[d] * s));
+        if (t.rows) { uj.scale = t.rows; uj.smul = t.rmul; uj.soff = t.roff; uj.sstride = s; uj.scl = 0; uj.sside = 0; }
+        first.push_back(uj);
+        first.push_back(copy_job(s, w, nmat, 1.0, factor_op(t.h, h.V[d], d, 0),
+                                 bop(C.V[d].get() + (size_t)col[d] * s, s, (long long)C.k[d] * s)));
+        col[d] += w;
+      }
     }
+    for (int d = 1; d <= L; ++d) C.kc[d] = col[d];
   }
   gcopy<T>(st, first);
   for (auto& r : rest) gcopy<T>(st, r);
-  for (int d = 1; d <= L; ++d) C.kc[d] = col[d];
   Queue::get().flush();   // let the device start while the host plans the next step
 }
 
@@ -503,7 +596,7 @@ void hscale_cols_multi(hipStream_t st, std::vector<ColScale<T>>& outs) {
     std::vector<int> kC(L + 1, 0);
     for (int d = 1; d <= L; ++d) kC[d] = h.kc[d];
     HSet<T>& C = *O.C;
-    C.alloc(st, O.cnt_alloc, s, b, L, kC, O.cnt_alloc > nmat);
+    C.alloc(st, O.cnt_alloc, s, b, L, kC, O.cnt_alloc > nmat ? nmat : -1);
     const long long ls = C.leaf_stride();
     CJob lj = copy_job(b, b, nmat, 1.0, leaves_op(O.H), bop(C.lv.get(), b, ls, (long long)b * b), h.nleaf());
     lj.scale = O.cols; lj.smul = O.cmul; lj.soff = O.coff; lj.sstride = s; lj.scl = b; lj.sside = 1;
@@ -549,7 +642,7 @@ void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double 
   GemmPlan kp;
   std::vector<SJob> sj;
   std::vector<MJob> mj;
-  DBuf<int> dmax(items.size());
+  DBuf<int> dmax(2 * items.size());
   for (size_t i = 0; i < items.size(); ++i) {
     Item& it = items[i];
     HV<T> HH{it.H, 1, 0};
@@ -582,14 +675,15 @@ void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double 
     work().svd_flops += 6.0 * (double)c * c * c * np;
     MJob m;
     m.rank = it.rank.get(); m.n = it.nprob; m.out = dmax.get() + i;
+    m.sum = dmax.get() + items.size() + i;
     mj.push_back(m);
   }
   gqr<T>(st, qj);
   kp.run<T>(st);
   grsvd<T>(st, sj);
   gmax(st, mj);
-  std::vector<int> kout(items.size());
-  read_to_host(kout.data(), dmax.get(), items.size() * sizeof(int), st);
+  std::vector<int> kout(2 * items.size());
+  read_to_host(kout.data(), dmax.get(), 2 * items.size() * sizeof(int), st);
   // Keep s_t > eps s_1:  K = U_K S J^T,
   //   U_new = Q_U [U_K,t; 0]          (orthonormal columns)
   //   V_new = V Ru^T U_K,t            (= Q_V J_t S_t, no inverse)
@@ -627,10 +721,12 @@ void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double 
   gapply_q<T>(st, aj);
   cvp.run<T>(st);
   vnp.run<T>(st);
-  for (auto& it : items) {
+  for (size_t i = 0; i < items.size(); ++i) {
+    Item& it = items[i];
     it.H->U[it.d] = std::move(it.Un);
     it.H->V[it.d] = std::move(it.Vn);
     it.H->k[it.d] = it.H->kc[it.d] = it.kout;
+    it.H->rsum[it.d] = (double)kout[items.size() + i];
   }
   Queue::get().flush();   // let the device start while the host plans the next step
 }
@@ -683,7 +779,8 @@ void densify_to_host(hipStream_t st, const HSet<T>& H, int m, double* out) {
   template void hmul<T>(hipStream_t, HV<T>, int, int, bool, int, T, Flat<T>, T, Flat<T>);          \
   template void hprod_multi<T>(hipStream_t, std::vector<POut<T>>&);                                \
   template void hinv<T>(hipStream_t, HSet<T>&, HV<T>, int, int*);                                  \
-  template void hstack<T>(hipStream_t, HSet<T>&, int, const std::vector<ScaleTerm<T>>&, int);      \
+  template void hinv_multi<T>(hipStream_t, std::vector<HInvJob<T>>&);                              \
+  template void hstack_multi<T>(hipStream_t, std::vector<StackOut<T>>&);                           \
   template void hscale_cols_multi<T>(hipStream_t, std::vector<ColScale<T>>&);                      \
   template void recompress_multi<T>(hipStream_t, const std::vector<HSet<T>*>&, double, int);       \
   template void densify_to_host<T>(hipStream_t, const HSet<T>&, int, double*);

@@ -26,16 +26,28 @@ struct HSet {
   int cnt = 0, s = 0, b = 0, L = 0;
   std::vector<int> k;    // allocated columns per depth (index 0 unused)
   std::vector<int> kc;   // filled columns per depth
+  // sum over the cnt * 2^d blocks of depth d of their numerical ranks, once
+  // known (after a truncation); -1 = every block has kc[d] columns
+  std::vector<double> rsum;
   DBuf<T> lv;
   std::vector<DBuf<T>> U, V;
 
   int nleaf() const { return 1 << L; }
   int sd(int d) const { return s >> d; }
   long long leaf_stride() const { return (long long)nleaf() * b * b; }
+  // allocate cnt_ matrices; with zero_from >= 0 the matrices [zero_from, cnt_)
+  // are set to zero (the others are written by the caller)
   void alloc(hipStream_t st, int cnt_, int s_, int b_, int L_, const std::vector<int>& k_,
-             bool zero);
+             int zero_from);
   size_t bytes() const;
   int max_rank() const;
+  // sum of the ranks of the depth-d blocks of all matrices, and their mean
+  double rank_sum(int d) const {
+    return (d < (int)rsum.size() && rsum[d] >= 0.0) ? rsum[d] : (double)kc[d] * cnt * (1 << d);
+  }
+  double rank_mean(int d) const { return cnt ? rank_sum(d) / ((double)cnt * (1 << d)) : 0.0; }
+  // bytes of the stored factor at the blocks' numerical ranks (no padding)
+  double bytes_ranked() const;
 };
 
 // A HODLR operand: set + matrix index map (matrix m of an operation uses
@@ -111,6 +123,17 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs);
 
 // X_m = M_m^{-1}, exact in exact arithmetic (bottom-up Sherman-Morrison-
 // Woodbury over the depths; the capacitance and leaf inverses in FP64).
+// Several inversions (of sets of different shapes) are planned together:
+// their steps share launches, counted from the bottom depth of each tree.
+template <typename T>
+struct HInvJob {
+  HSet<T>* X = nullptr;
+  HV<T> M;
+  int nmat = 0;
+  int* status = nullptr;   // set to 1 on a zero or non-finite pivot
+};
+template <typename T>
+void hinv_multi(hipStream_t st, std::vector<HInvJob<T>>& jobs);
 template <typename T>
 void hinv(hipStream_t st, HSet<T>& X, HV<T> M, int nmat, int* status);
 
@@ -125,10 +148,16 @@ struct ScaleTerm {
   int rmul = 1, roff = 0;
 };
 
-// C_m = sum_t coef_t diag(rows_t) H_t,m (stack of scaled sets).
+// C_m = sum_t coef_t diag(rows_t) H_t,m (stack of scaled sets), for several
+// outputs at once.
 template <typename T>
-void hstack(hipStream_t st, HSet<T>& C, int cnt_alloc, const std::vector<ScaleTerm<T>>& terms,
-            int nmat);
+struct StackOut {
+  HSet<T>* C = nullptr;
+  int cnt_alloc = 0, nmat = 0;
+  std::vector<ScaleTerm<T>> terms;
+};
+template <typename T>
+void hstack_multi(hipStream_t st, std::vector<StackOut<T>>& outs);
 
 // C_m = H_m diag(cols_(cmul*m+coff)) for several outputs at once.
 template <typename T>

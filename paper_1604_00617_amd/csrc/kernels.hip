@@ -543,8 +543,8 @@ __global__ __launch_bounds__(256) void k_gemm_any(const GJob* __restrict__ jobs,
 // leaf and U loads are independent and coalesced over the rows of a wave.
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_hmv_reduce(const MVRed* __restrict__ reds, int nred,
-                                                    const MVTerm* __restrict__ terms, int s, int nrhs,
-                                                    long long nunits, T* __restrict__ tbuf) {
+                                                    const MVTerm* __restrict__ terms, long long nunits,
+                                                    T* __restrict__ tbuf) {
   constexpr int CH = 16;                               // columns per unit
   constexpr int RB = NR <= 1 ? 4 : NR <= 2 ? 2 : 1;    // rows per lane per batch
   const long long u = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -552,6 +552,7 @@ __global__ __launch_bounds__(256) void k_hmv_reduce(const MVRed* __restrict__ re
   const int lane = threadIdx.x % WAVE;
   const MVRed& R = reds[job_of(reds, nred, u)];
   const MVTerm& M = terms[R.term];
+  const int s = M.s, nrhs = M.nrhs;
   const long long local = u - R.block0;
   const int m = (int)(local / R.upm);
   int rem = (int)(local % R.upm), d = 1;
@@ -618,12 +619,13 @@ __global__ __launch_bounds__(256) void k_hmv_reduce(const MVRed* __restrict__ re
 // and broadcasts each value with a lane read.
 template <typename T, int NR, bool W64>
 __global__ __launch_bounds__(64) void k_hmv_apply(const MVJob* __restrict__ jobs, int njobs,
-                                                  const MVTerm* __restrict__ terms, int s, int b, int L,
-                                                  int nrhs, long long nrows, const T* __restrict__ tbuf) {
+                                                  const MVTerm* __restrict__ terms, long long nrows,
+                                                  const T* __restrict__ tbuf) {
   const long long g = (long long)blockIdx.x * WAVE + threadIdx.x;
   if (g >= nrows) return;   // never with W64: the rows fill whole waves
   const int lane = threadIdx.x;
   const MVJob& J = jobs[job_of(jobs, njobs, g)];
+  const int s = J.s, b = J.b, L = J.L, nrhs = J.nrhs;
   const long long local = g - J.block0;
   const int m = (int)(local / s), row = (int)(local % s);
   const int l = row / b, r = row % b, nleaf = 1 << L;
@@ -711,16 +713,20 @@ __global__ __launch_bounds__(64) void k_hmv_apply(const MVJob* __restrict__ jobs
 // kept at a compile-time register position by rotating the row by 8 columns
 // after every 8 steps.
 template <typename Tin, typename Tout, int N>
-__global__ __launch_bounds__(256) void k_inverse_wave(int n, int nprob, const Tin* __restrict__ A,
-                                                     long long sA, Tout* __restrict__ X, long long sX,
-                                                     int* status) {
+__global__ __launch_bounds__(256) void k_inverse_wave(const IJob* __restrict__ jobs, int njobs) {
   constexpr int G = WAVE / N;
   constexpr int JB = N < 8 ? N : 8;
   __shared__ int piv_row[4][WAVE];
   __shared__ double prow[4][WAVE];
+  const IJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int n = Jb.n, nprob = Jb.nprob;
+  const Tin* __restrict__ A = gmem(static_cast<const Tin*>(Jb.A));
+  Tout* __restrict__ X = gmem(static_cast<Tout*>(Jb.X));
+  const long long sA = Jb.sA, sX = Jb.sX;
+  int* const status = gmem(Jb.status);
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
   const int g = lane / N, r = lane % N;
-  const long long p = ((long long)blockIdx.x * 4 + wv) * G + g;
+  const long long p = ((long long)(blockIdx.x - Jb.block0) * 4 + wv) * G + g;
   const bool valid = p < nprob;
   const Tin* Ap = A + (valid ? p : 0) * sA;
   double a[N];
@@ -792,15 +798,21 @@ __global__ __launch_bounds__(256) void k_inverse_wave(int n, int nprob, const Ti
 
 // Gauss-Jordan on the augmented matrix [A | I] (row-major n x 2n) in FP64.
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(256) void k_inverse(int n, const Tin* A, long long sA, Tout* X,
-                                                 long long sX, double* ws, int use_lds,
-                                                 int* status) {
+__global__ __launch_bounds__(256) void k_inverse(const IJob* __restrict__ jobs, int njobs) {
   extern __shared__ double smem[];
-  const int p = blockIdx.x;
+  const IJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int n = Jb.n;
+  const Tin* A = gmem(static_cast<const Tin*>(Jb.A));
+  Tout* X = gmem(static_cast<Tout*>(Jb.X));
+  const long long sA = Jb.sA, sX = Jb.sX;
+  double* ws = gmem(Jb.ws);
+  const int use_lds = Jb.use_lds;
+  int* const status = gmem(Jb.status);
+  const int p = (int)(blockIdx.x - Jb.block0);
   const int n2 = 2 * n;
   __shared__ double colj_s[128];
   double* W = use_lds ? smem : ws + (size_t)p * n * n2;
-  double* colj = n <= 128 ? colj_s : ws + (size_t)gridDim.x * n * n2 + (size_t)p * n;
+  double* colj = n <= 128 ? colj_s : ws + (size_t)Jb.nprob * n * n2 + (size_t)p * n;
   __shared__ int piv;
   __shared__ double pval;
   __shared__ int bad;
@@ -858,15 +870,20 @@ __global__ __launch_bounds__(256) void k_inverse(int n, const Tin* A, long long 
 // pivot j: a_jj <- 1/p, row j scaled, column j <- -a_rj/p, rank-1 update of the
 // rest; the row swaps are undone as column swaps in reverse order at the end.
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(256) void k_inverse_lds(int n, const Tin* A, long long sA, Tout* X,
-                                                     long long sX, int* status) {
+__global__ __launch_bounds__(256) void k_inverse_lds(const IJob* __restrict__ jobs, int njobs) {
   extern __shared__ double W[];
   __shared__ int perm[128];
   __shared__ double colj[128];
   __shared__ int piv;
   __shared__ double pinv;
   __shared__ int bad;
-  const int p = blockIdx.x, tid = threadIdx.x;
+  const IJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int n = Jb.n;
+  const Tin* A = gmem(static_cast<const Tin*>(Jb.A));
+  Tout* X = gmem(static_cast<Tout*>(Jb.X));
+  const long long sA = Jb.sA, sX = Jb.sX;
+  int* const status = gmem(Jb.status);
+  const int p = (int)(blockIdx.x - Jb.block0), tid = threadIdx.x;
   const Tin* Ap = A + (long long)p * sA;
   if (tid == 0) bad = 0;
   for (int e = tid; e < n * n; e += 256) {
@@ -1937,8 +1954,9 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
     J[r + (size_t)i * c] = r == i ? T(1) : T(0);
   }
   __syncthreads();
-  double ssf = 0.0;
-  for (int e = tid; e < c * tp; e += NTH) {
+  double ssf = 0.0;   // cores of at most 16: summed by the first wave in both forms
+  const int sstride = c <= 16 ? WAVE : NTH;
+  for (int e = tid; e < c * tp && tid < sstride; e += sstride) {
     const double x = X[(e % c) + (size_t)(e / c) * c];
     ssf += x * x;
   }
@@ -1948,15 +1966,20 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
   const double tol = fmax(4.0, sqrt((double)c)) * Eps<T>::v;
   const int cp = (tp + 1) & ~1;
   const int npairs = cp / 2;
-  int g = NTH / max(npairs, 1), gp = 1;
+  // Lanes per column pair: cores of at most 16 (which both the one-wave and
+  // the four-wave form take) size the groups for one wave whatever NW is, so
+  // that both forms compute every pair's sums alike and give the same bits;
+  // larger cores spread over the whole workgroup.
+  int g = (c <= 16 ? WAVE : NTH) / max(npairs, 1), gp = 1;
   while (gp * 2 <= g && gp * 2 <= WAVE) gp *= 2;
   g = gp;
   const int slots = NTH / g, gl = tid % g;
   // FP32 cores with t' <= GD: the same rotations applied to the Gram matrix
   // X^T X, formed and rotated in FP64 (one thread per entry), which needs no
   // cross-lane sums.  FP64 keeps the smallest retained s_i^2 ~ (eps s_1)^2
-  // to a relative 1e-4 and more, ample for the FP32 truncation.
-  const bool gram = sizeof(T) == 4 && tp > 1 && tp <= GD;
+  // to a relative 1e-4 and more, ample for the FP32 truncation.  Cores of at
+  // most 16 use it up to t' = 8 in both forms (the one-wave form's limit).
+  const bool gram = sizeof(T) == 4 && tp > 1 && tp <= (c <= 16 ? 8 : GD);
   if (gram) {
     const int gi = tid / GD, gk = tid % GD;
     const bool ent = gi < tp && gk < tp;
@@ -2177,16 +2200,28 @@ __global__ void k_gtrunc(const TJob* __restrict__ jobs, int njobs) {
 
 __global__ void k_gmax(const MJob* __restrict__ jobs) {
   __shared__ int sm[256];
+  __shared__ int ss[256];
   const MJob& Jb = jobs[blockIdx.x];
-  int mx = 0;
-  for (int i = threadIdx.x; i < Jb.n; i += 256) mx = max(mx, gmem(Jb.rank)[i]);
+  int mx = 0, sum = 0;
+  for (int i = threadIdx.x; i < Jb.n; i += 256) {
+    const int r = gmem(Jb.rank)[i];
+    mx = max(mx, r);
+    sum += r;
+  }
   sm[threadIdx.x] = mx;
+  ss[threadIdx.x] = sum;
   __syncthreads();
   for (int s2 = 128; s2 > 0; s2 >>= 1) {
-    if (threadIdx.x < s2) sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + s2]);
+    if (threadIdx.x < s2) {
+      sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + s2]);
+      ss[threadIdx.x] += ss[threadIdx.x + s2];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) Jb.out[0] = sm[0];
+  if (threadIdx.x == 0) {
+    Jb.out[0] = sm[0];
+    if (Jb.sum) Jb.sum[0] = ss[0];
+  }
 }
 
 constexpr int kCopyChunk = 2048;
@@ -2237,14 +2272,34 @@ __global__ void k_fill(T* p, size_t n, T v) {
     p[e] = v;
 }
 
+// Zero fill of up to kZeroBatch byte ranges (blockIdx.y = range): 16-byte
+// stores on the aligned body, single bytes on the unaligned head and tail.
+__global__ __launch_bounds__(256) void k_zero_bytes(ZeroArgs z) {
+  const int f = blockIdx.y;
+  unsigned char* p = z.p[f];
+  const unsigned long long bytes = z.n[f];
+  const unsigned long long a = reinterpret_cast<uintptr_t>(p);
+  unsigned long long head = (16 - (a & 15)) & 15;
+  if (head > bytes) head = bytes;
+  const unsigned long long nbody = (bytes - head) / 16;
+  const unsigned long long tail = bytes - head - 16 * nbody;
+  const unsigned long long t = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  uint4* body = reinterpret_cast<uint4*>(p + head);
+  for (unsigned long long e = t; e < nbody; e += stride) body[e] = make_uint4(0u, 0u, 0u, 0u);
+  if (t < head) p[t] = 0;
+  if (t < tail) p[head + 16 * nbody + t] = 0;
+}
+
 template <typename T>
-__global__ void k_build_cap(int k, int npairs, const T* cores, T* G) {
-  const int q = blockIdx.y;
-  const int n = 2 * k;
-  const T* c0 = cores + (size_t)(2 * q) * k * k;
-  const T* c1 = cores + (size_t)(2 * q + 1) * k * k;
-  T* g = G + (size_t)q * n * n;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(256) void k_build_cap(const CapJob* __restrict__ jobs, int njobs) {
+  const CapJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int q = (int)(blockIdx.x - Jb.block0);
+  const int k = Jb.k, n = 2 * k;
+  const T* c0 = gmem(static_cast<const T*>(Jb.cores)) + (size_t)(2 * q) * k * k;
+  const T* c1 = c0 + (size_t)k * k;
+  T* g = gmem(static_cast<T*>(Jb.G)) + (size_t)q * n * n;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
     const int r = e % n, col = e / n;
     T v;
     if ((r < k) == (col < k)) v = (r == col) ? T(1) : T(0);
@@ -2254,19 +2309,21 @@ __global__ void k_build_cap(int k, int npairs, const T* cores, T* G) {
   }
 }
 
+// Level-0 leaves: the tridiagonal band of each leaf of D_i (`per` workgroups
+// per matrix).
 template <typename T>
-__global__ void k_leaves_tridiag(int s, int b, int bmul, int boff, const double* diag,
-                                 const double* west, const double* east, T* leaves) {
-  const int m = blockIdx.y;
-  const int blk = bmul * m + boff;
-  const int nleaf = s / b;
-  const long long n = (long long)nleaf * b * b;
-  T* lv = leaves + (size_t)m * n;
-  const double* dg = diag + (size_t)blk * s;
-  const double* we = west + (size_t)blk * s;
-  const double* ea = east + (size_t)blk * s;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(256) void k_leaves_tridiag(const OpJob* __restrict__ jobs, int njobs) {
+  const OpJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long local = blockIdx.x - J.block0;
+  const int m = (int)(local / J.per), part = (int)(local % J.per);
+  const int s = J.s, b = J.b;
+  const int blk = J.bmul * m + J.boff;
+  const long long n = (long long)s * b;   // 2^L leaves of b x b
+  T* lv = gmem(static_cast<T*>(J.out)) + (size_t)m * n;
+  const double* dg = gmem(J.diag) + (size_t)blk * s;
+  const double* we = gmem(J.west) + (size_t)blk * s;
+  const double* ea = gmem(J.east) + (size_t)blk * s;
+  for (long long e = (long long)part * 256 + threadIdx.x; e < n; e += (long long)J.per * 256) {
     const int lam = (int)(e / ((long long)b * b));
     const int rem = (int)(e % ((long long)b * b));
     const int r = rem % b, c = rem / b;
@@ -2290,11 +2347,14 @@ __global__ void k_leaves_tridiag(int s, int b, int bmul, int boff, const double*
 // (t1 the first row of s); for t below s, U_t[i] = prod_(k=t0..i) tau_k and
 // V_t[j] = g_j prod_(k=j+1..t0-1) tau_k (t0 the first row of t).  All in FP64.
 template <typename T>
-__global__ __launch_bounds__(256) void k_tridiag_inverse(int s, int b, int L, int bmul, int boff,
-                                                         const double* __restrict__ diag,
-                                                         const double* __restrict__ west,
-                                                         const double* __restrict__ east, T* __restrict__ lv,
-                                                         TriInvOut out, int* fallback) {
+__global__ __launch_bounds__(256) void k_tridiag_inverse(const OpJob* __restrict__ jobs, int njobs) {
+  const OpJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int s = J.s, b = J.b, L = J.L, bmul = J.bmul, boff = J.boff;
+  const double* __restrict__ diag = gmem(J.diag);
+  const double* __restrict__ west = gmem(J.west);
+  const double* __restrict__ east = gmem(J.east);
+  T* __restrict__ lv = gmem(static_cast<T*>(J.out));
+  int* const fallback = gmem(J.flag);
   extern __shared__ unsigned char smem_raw[];
   double* A = reinterpret_cast<double*>(smem_raw);   // a_i, then g_i
   double* B = A + s;                                  // b_i, then rho_i
@@ -2302,7 +2362,7 @@ __global__ __launch_bounds__(256) void k_tridiag_inverse(int s, int b, int L, in
   double* Dp = C + s;                                 // d_i
   double* Ep = Dp + s;                                // e_i
   __shared__ int bad;
-  const int m = blockIdx.x, tid = threadIdx.x;
+  const int m = (int)(blockIdx.x - J.block0), tid = threadIdx.x;
   const int blk = bmul * m + boff;
   const double* dg = diag + (size_t)blk * s;
   const double* we = west + (size_t)blk * s;
@@ -2375,8 +2435,8 @@ __global__ __launch_bounds__(256) void k_tridiag_inverse(int s, int b, int L, in
     while (t >= (4 << (d - 1))) { t -= 4 << (d - 1); ++d; }
     const int pair = t >> 2, kind = t & 3;
     const int sd = s >> d, t0 = 2 * pair * sd, t1 = t0 + sd;
-    T* Ud = gmem(static_cast<T*>(out.U[d])) + (size_t)m * s;
-    T* Vd = gmem(static_cast<T*>(out.V[d])) + (size_t)m * s;
+    T* Ud = gmem(static_cast<T*>(J.U[d])) + (size_t)m * s;
+    T* Vd = gmem(static_cast<T*>(J.V[d])) + (size_t)m * s;
     if (kind == 0) {          // U of the upper block, rows of the first cluster
       double u = 1.0;
       for (int i = t1 - 1; i >= t0; --i) { u *= B[i]; Ud[i] = (T)u; }
@@ -2393,29 +2453,77 @@ __global__ __launch_bounds__(256) void k_tridiag_inverse(int s, int b, int L, in
   }
 }
 
+// Level-0 off-diagonal factors of D_i at every depth (rank one, Section 3):
+// the upper-right block of a first child couples its last row to the
+// sibling's first column (value east), the lower-left block of a second
+// child couples its first row to the sibling's last column (value west).
 template <typename T>
-__global__ void k_rank1(int s, int sd, int bmul, int boff, const double* west, const double* east,
-                        T* U, T* V) {
-  const int m = blockIdx.y;
-  const int blk = bmul * m + boff;
-  const double* we = west + (size_t)blk * s;
-  const double* ea = east + (size_t)blk * s;
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < s; r += gridDim.x * blockDim.x) {
-    const int cl = r / sd, loc = r % sd;
-    T u = T(0), v = T(0);
-    if ((cl & 1) == 0 && loc == sd - 1) { u = (T)ea[r]; v = T(1); }
-    if ((cl & 1) == 1 && loc == 0) { u = (T)we[r]; v = T(1); }
-    U[(size_t)m * s + r] = u;
-    V[(size_t)m * s + r] = v;
+__global__ __launch_bounds__(256) void k_rank1(const OpJob* __restrict__ jobs, int njobs) {
+  const OpJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long local = blockIdx.x - J.block0;
+  const int m = (int)(local / J.per), part = (int)(local % J.per);
+  const int s = J.s;
+  const int blk = J.bmul * m + J.boff;
+  const double* we = gmem(J.west) + (size_t)blk * s;
+  const double* ea = gmem(J.east) + (size_t)blk * s;
+  for (int r = part * 256 + threadIdx.x; r < s; r += J.per * 256) {
+    for (int d = 1; d <= J.L; ++d) {
+      const int sd = s >> d, cl = r / sd, loc = r % sd;
+      T u = T(0), v = T(0);
+      if ((cl & 1) == 0 && loc == sd - 1) { u = (T)ea[r]; v = T(1); }
+      if ((cl & 1) == 1 && loc == 0) { u = (T)we[r]; v = T(1); }
+      gmem(static_cast<T*>(J.U[d]))[(size_t)m * s + r] = u;
+      gmem(static_cast<T*>(J.V[d]))[(size_t)m * s + r] = v;
+    }
+  }
+}
+
+// Diagonal of a stencil array per block row; block row zblk (if >= 0) gets
+// zeros (the coupling that would leave the grid).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_diag(const OpJob* __restrict__ jobs, int njobs) {
+  const OpJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long local = blockIdx.x - J.block0;
+  const int m = (int)(local / J.per), part = (int)(local % J.per);
+  const int s = J.s;
+  const int blk = J.bmul * m + J.boff;
+  const double* src = gmem(J.src) + (size_t)blk * s;
+  T* dst = gmem(static_cast<T*>(J.out)) + (size_t)m * s;
+  for (int r = part * 256 + threadIdx.x; r < s; r += J.per * 256) dst[r] = blk == J.zblk ? T(0) : (T)src[r];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gto_blocks(const VJob* __restrict__ jobs, int njobs) {
+  const VJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long part = blockIdx.x - J.block0;
+  const int s = J.s, nrhs = J.nrhs;
+  const long long n = (long long)s * J.nblk * nrhs, ld = J.ld;
+  const double* B = gmem(static_cast<const double*>(J.src));
+  T* V = gmem(static_cast<T*>(J.dst));
+  for (long long e = part * 256 + threadIdx.x; e < n; e += (long long)J.per * 256) {
+    const int j = (int)(e % s);
+    const long long t = e / s;
+    const int q = (int)(t % nrhs);
+    const int i = (int)(t / nrhs);
+    V[e] = (T)B[(long long)i * s + j + (long long)q * ld];
   }
 }
 
 template <typename T>
-__global__ void k_gather_diag(int s, int bmul, int boff, const double* src, T* dst) {
-  const int m = blockIdx.y;
-  const int blk = bmul * m + boff;
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < s; r += gridDim.x * blockDim.x)
-    dst[(size_t)m * s + r] = (T)src[(size_t)blk * s + r];
+__global__ __launch_bounds__(256) void k_gfrom_blocks(const VJob* __restrict__ jobs, int njobs) {
+  const VJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long part = blockIdx.x - J.block0;
+  const int s = J.s, nrhs = J.nrhs;
+  const long long n = (long long)s * J.nblk * nrhs, ld = J.ld;
+  const T* V = gmem(static_cast<const T*>(J.src));
+  double* B = gmem(static_cast<double*>(J.dst));
+  for (long long e = part * 256 + threadIdx.x; e < n; e += (long long)J.per * 256) {
+    const int j = (int)(e % s);
+    const long long t = e / s;
+    const int q = (int)(t % nrhs);
+    const int i = (int)(t / nrhs);
+    B[(long long)i * s + j + (long long)q * ld] = (double)V[e];
+  }
 }
 
 template <typename T>
@@ -2473,6 +2581,72 @@ __global__ void k_residual(int nx, int ny, const double* diag, const double* wes
     if (i + 1 < ny) ax += north[e] * x[e + nx];
     R[e + q * N] = B[e + q * N] - ax;
   }
+}
+
+// Grouped refinement vector kernels (several problems per launch).  A job's
+// workgroups are (column q, part): q = local / per, part = local % per.
+__global__ __launch_bounds__(256) void k_gresidual(const RJob* __restrict__ jobs, int njobs) {
+  const RJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long local = blockIdx.x - J.block0;
+  const int q = (int)(local / J.per), part = (int)(local % J.per);
+  const int nx = J.nx, ny = J.ny;
+  const long long N = (long long)nx * ny;
+  const double* diag = gmem(J.diag);
+  const double* west = gmem(J.west);
+  const double* east = gmem(J.east);
+  const double* south = gmem(J.south);
+  const double* north = gmem(J.north);
+  const double* x = gmem(J.X) + q * N;
+  const double* b = gmem(J.B) + q * N;
+  double* r = gmem(J.R) + q * N;
+  for (long long e = (long long)part * 256 + threadIdx.x; e < N; e += (long long)J.per * 256) {
+    const int j = (int)(e % nx);
+    const int i = (int)(e / nx);
+    double ax = diag[e] * x[e];
+    if (j > 0) ax += west[e] * x[e - 1];
+    if (j + 1 < nx) ax += east[e] * x[e + 1];
+    if (i > 0) ax += south[e] * x[e - nx];
+    if (i + 1 < ny) ax += north[e] * x[e + nx];
+    r[e] = b[e] - ax;
+  }
+}
+
+// Partial sums of squares of column q of job J.R over fixed chunks (the
+// chunking depends on N only), then the sum of the parts in order.
+__global__ __launch_bounds__(256) void k_gsumsq_part(const RJob* __restrict__ jobs, int njobs) {
+  __shared__ double red[4];
+  const RJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long local = blockIdx.x - J.block0;
+  const int q = (int)(local / J.per), part = (int)(local % J.per);
+  const long long N = (long long)J.nx * J.ny;
+  const long long chunk = (N + J.per - 1) / J.per;
+  const long long lo = part * chunk, hi = min(N, lo + chunk);
+  const double* a = gmem(J.R) + q * N;
+  double s = 0.0;
+  for (long long i = lo + threadIdx.x; i < hi; i += 256) s += a[i] * a[i];
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) gmem(J.part)[(size_t)q * J.per + part] = s;
+}
+
+__global__ __launch_bounds__(256) void k_gsumsq_final(const RJob* __restrict__ jobs, int njobs) {
+  __shared__ double red[4];
+  const RJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const int q = (int)(blockIdx.x - J.block0);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < J.per; i += 256) s += gmem(J.part)[(size_t)q * J.per + i];
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) gmem(J.out)[q] = s;
+}
+
+// X += D (job.B = D, job.R = X).
+__global__ __launch_bounds__(256) void k_gaxpy(const RJob* __restrict__ jobs, int njobs) {
+  const RJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long local = blockIdx.x - J.block0;
+  const int q = (int)(local / J.per), part = (int)(local % J.per);
+  const long long N = (long long)J.nx * J.ny;
+  const double* d = gmem(J.B) + q * N;
+  double* x = gmem(J.R) + q * N;
+  for (long long e = (long long)part * 256 + threadIdx.x; e < N; e += (long long)J.per * 256) x[e] += d[e];
 }
 
 // Partial sums of squares: block (x, q) covers a contiguous chunk of column q.
@@ -2542,12 +2716,13 @@ __global__ void k_scan_values(long long n, const T* a, int* bad, double* amax) {
   if (threadIdx.x == 0) amax[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
-__global__ void k_count_nonfinite(long long n, const double* a, int* out) {
+__global__ __launch_bounds__(256) void k_count_nonfinite(const NFJob* __restrict__ jobs, int njobs) {
+  const NFJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long part = blockIdx.x - J.block0;
+  const double* a = gmem(J.a);
   int bad = 0;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x)
-    bad |= !isfinite(a[e]);
-  if (bad) out[0] = 1;
+  for (long long e = part * 256 + threadIdx.x; e < J.n; e += (long long)J.per * 256) bad |= !isfinite(a[e]);
+  if (bad) gmem(J.flag)[0] = 1;
 }
 
 __global__ void k_axpy_d(long long n, const double* D, double* X) {
@@ -2623,7 +2798,7 @@ const char* kernel_name(const char* src, const char* t, const char* tin, const c
 
 template <typename J>
 const J* upload(const std::vector<J>& v, hipStream_t st) {
-  return static_cast<const J*>(DescArena::get().put(v.data(), v.size() * sizeof(J), st));
+  return static_cast<const J*>(desc_put(v.data(), v.size() * sizeof(J), st));
 }
 
 }  // namespace
@@ -2675,6 +2850,16 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
     fl[kind] += 2.0 * J.M * J.N * K * np;
     bytes[kind] += sizeof(T) * np * ((double)J.M * K + K * J.N + (double)J.M * J.N * (J.beta != 0.0 ? 2 : 1));
     J.kind = kind;
+    {
+      static const char* names[10][2] = {
+          {"gemm.tile64x64", "gemm.tile64x64.M>128"}, {"gemm.tile64x16", "gemm.tile64x16.M>128"},
+          {"gemm.tile16x64", "gemm.tile16x64.M>128"}, {"gemm.tile32x32", "gemm.tile32x32.M>128"},
+          {"gemm.tile16x16", "gemm.tile16x16.M>128"}, {"gemm.dot", "gemm.dot.K>128"},
+          {"gemm.rows16", "gemm.rows16.M>128"}, {"gemm.rows32", "gemm.rows32.M>128"},
+          {"gemm.rows4", "gemm.rows4.M>128"}, {"gemm.small", "gemm.small.K>128"}};
+      const bool big = (kind == 5 || kind == 9) ? K > 128 : J.M > 128;
+      Profiler::get().hit(names[kind][big ? 1 : 0], (long long)np);
+    }
     by[kind].push_back(J);
   }
   // A small call (few workgroups in all) runs as one launch of k_gemm_any,
@@ -2713,7 +2898,7 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
       const size_t o = (blob.size() + 255) & ~size_t(255);
       blob.resize(o + all.size() * sizeof(GJob));
       std::memcpy(blob.data() + o, all.data(), all.size() * sizeof(GJob));
-      char* dev = static_cast<char*>(DescArena::get().put(blob.data(), blob.size(), st));
+      char* dev = static_cast<char*>(desc_put(blob.data(), blob.size(), st));
       launch(st, KC_GEMM, f, by_, KNAME_T(k_gemm_any<T>), k_gemm_any<T>, dim3((unsigned)b0), dim3(256), 0,
              reinterpret_cast<const GJob*>(dev + o), (int)all.size(), reinterpret_cast<const GSeg*>(dev));
       return;
@@ -2737,7 +2922,7 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
     if (!by[kd].empty()) std::memcpy(blob.data() + off[kd], by[kd].data(), by[kd].size() * sizeof(GJob));
   }
   if (blob.empty()) return;
-  char* dev = static_cast<char*>(DescArena::get().put(blob.data(), blob.size(), st));
+  char* dev = static_cast<char*>(desc_put(blob.data(), blob.size(), st));
   const GSeg* dsegs = reinterpret_cast<const GSeg*>(dev);
   for (int kd = 0; kd < NK; ++kd) {
     if (by[kd].empty()) continue;
@@ -2775,34 +2960,69 @@ void bgemm(hipStream_t st, int M, int N, int K, int nmat, int ncl, T alpha, cons
   ggemm<T>(st, std::move(jobs), segs);
 }
 
+// Small dense inverses, grouped: jobs of one size class share a launch (one
+// row per lane and 64/N matrices per wave for n <= 64; one workgroup per
+// matrix in LDS for n <= 88; the augmented form, in LDS or global scratch,
+// above).  The kernel of a matrix depends on its size n only.
+template <typename Tin, typename Tout>
+void ginverse(hipStream_t st, std::vector<IJob> jobs) {
+  std::vector<IJob> use[6];
+  long long b0[6] = {};
+  double fl[6] = {}, by[6] = {};
+  size_t dyn[6] = {};
+  std::vector<DBuf<double>> ws;
+  for (auto J : jobs) {
+    const int n = J.n;
+    if (n <= 0 || J.nprob <= 0) continue;
+    int g;
+    long long nb = J.nprob;
+    if (n <= 64) {
+      const int Nt = n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : 64;
+      g = Nt == 8 ? 0 : Nt == 16 ? 1 : Nt == 32 ? 2 : 3;
+      const long long per = 4LL * (WAVE / Nt);
+      nb = (J.nprob + per - 1) / per;
+    } else if (n <= 88) {
+      g = 4;
+      dyn[4] = std::max(dyn[4], (size_t)n * n * sizeof(double));
+    } else {
+      g = 5;
+      const size_t lds = (size_t)n * 2 * n * sizeof(double);
+      J.use_lds = lds + 2048 <= kMaxLds ? 1 : 0;
+      if (!J.use_lds || n > 128) {
+        ws.emplace_back((size_t)J.nprob * n * (2 * n + 1));
+        J.ws = ws.back().get();
+      }
+      if (J.use_lds) dyn[5] = std::max(dyn[5], lds);
+    }
+    J.block0 = b0[g];
+    b0[g] += nb;
+    fl[g] += 2.0 * n * n * n * J.nprob;
+    by[g] += 2.0 * n * n * J.nprob * sizeof(Tin);
+    use[g].push_back(J);
+  }
+  for (int g = 0; g < 6; ++g) {
+    if (use[g].empty()) continue;
+    const IJob* dj = upload(use[g], st);
+    const int nj = (int)use[g].size();
+    const dim3 grid((unsigned)b0[g]);
+    switch (g) {
+      case 0: launch(st, KC_INVERSE, fl[g], by[g], KNAME_IO(k_inverse_wave<Tin, Tout, 8>), k_inverse_wave<Tin, Tout, 8>, grid, dim3(256), 0, dj, nj); break;
+      case 1: launch(st, KC_INVERSE, fl[g], by[g], KNAME_IO(k_inverse_wave<Tin, Tout, 16>), k_inverse_wave<Tin, Tout, 16>, grid, dim3(256), 0, dj, nj); break;
+      case 2: launch(st, KC_INVERSE, fl[g], by[g], KNAME_IO(k_inverse_wave<Tin, Tout, 32>), k_inverse_wave<Tin, Tout, 32>, grid, dim3(256), 0, dj, nj); break;
+      case 3: launch(st, KC_INVERSE, fl[g], by[g], KNAME_IO(k_inverse_wave<Tin, Tout, 64>), k_inverse_wave<Tin, Tout, 64>, grid, dim3(256), 0, dj, nj); break;
+      case 4: launch(st, KC_INVERSE, fl[g], by[g], KNAME_IO(k_inverse_lds<Tin, Tout>), k_inverse_lds<Tin, Tout>, grid, dim3(256), dyn[g], dj, nj); break;
+      default: launch(st, KC_INVERSE, fl[g], by[g], KNAME_IO(k_inverse<Tin, Tout>), k_inverse<Tin, Tout>, grid, dim3(256), dyn[g], dj, nj); break;
+    }
+  }
+}
+
 template <typename Tin, typename Tout>
 void binverse(hipStream_t st, int n, int nprob, const Tin* A, long long sA, Tout* X, long long sX,
               int* status) {
-  if (n <= 0 || nprob <= 0) return;
-  const double fl = 2.0 * n * n * n * nprob, by = 2.0 * n * n * nprob * sizeof(Tin);
-  if (n <= 64) {   // one row per lane, 64/N matrices per wave, four waves per workgroup
-    auto go = [&](const char* name, auto kern, int Nt) {
-      const long long per = 4LL * (WAVE / Nt);
-      launch(st, KC_INVERSE, fl, by, name, kern, dim3((unsigned)((nprob + per - 1) / per)), dim3(256), 0, n, nprob,
-             A, sA, X, sX, status);
-    };
-    if (n <= 8) go(KNAME_IO(k_inverse_wave<Tin, Tout, 8>), k_inverse_wave<Tin, Tout, 8>, 8);
-    else if (n <= 16) go(KNAME_IO(k_inverse_wave<Tin, Tout, 16>), k_inverse_wave<Tin, Tout, 16>, 16);
-    else if (n <= 32) go(KNAME_IO(k_inverse_wave<Tin, Tout, 32>), k_inverse_wave<Tin, Tout, 32>, 32);
-    else go(KNAME_IO(k_inverse_wave<Tin, Tout, 64>), k_inverse_wave<Tin, Tout, 64>, 64);
-    return;
-  }
-  if (n <= 88) {   // in place: n*n doubles of LDS (+1.6 KB static) within 64 KB
-    launch(st, KC_INVERSE, fl, by, KNAME_IO(k_inverse_lds<Tin, Tout>), k_inverse_lds<Tin, Tout>, dim3(nprob), dim3(256),
-           (size_t)n * n * sizeof(double), n, A, sA, X, sX, status);
-    return;
-  }
-  const size_t lds = (size_t)n * 2 * n * sizeof(double);
-  const bool use_lds = lds + 2048 <= kMaxLds;
-  DBuf<double> ws;
-  if (!use_lds || n > 128) ws.resize((size_t)nprob * n * (2 * n + 1));
-  launch(st, KC_INVERSE, fl, by, KNAME_IO(k_inverse<Tin, Tout>), k_inverse<Tin, Tout>, dim3(nprob), dim3(256), use_lds ? lds : 0, n, A, sA,
-         X, sX, ws.get(), use_lds ? 1 : 0, status);
+  std::vector<IJob> jobs(1);
+  IJob& J = jobs[0];
+  J.n = n; J.nprob = nprob; J.A = A; J.sA = sA; J.X = X; J.sX = sX; J.status = status;
+  ginverse<Tin, Tout>(st, std::move(jobs));
 }
 
 template <typename T>
@@ -2853,6 +3073,12 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
       J.ws = scratch.back().get();
     }
     if (g == 0 || g == 1 || g == 3) dyn[g] = std::max(dyn[g], J.lds ? panel + vb : vb);
+    {
+      static const char* names[5][2] = {{"qr.lds", "qr.lds.p>128"}, {"qr.lds_large", "qr.lds_large.p>128"},
+                                        {"qr.reg", "qr.reg.p>128"}, {"qr.global", "qr.global.p>128"},
+                                        {"qr.wave", "qr.wave.p>128"}};
+      Profiler::get().hit(names[g][J.p > 128 ? 1 : 0], (long long)np);
+    }
     J.block0 = b0[g];
     b0[g] += (long long)np;
     const double p = J.p, k = J.k, kr = std::min(J.p, J.k);
@@ -2968,6 +3194,12 @@ void gapply_q(hipStream_t st, std::vector<AJob> jobs) {
       else J.lds = 0;
     }
     if (J.lds == 1) dyn[g] = std::max(dyn[g], need);
+    {
+      const int v = J.lds == 2 ? 0 : J.lds == 0 ? 1 : g == 0 ? 2 : 3;
+      static const char* names[4][2] = {{"applyq.wave", "applyq.wave.p>128"}, {"applyq.global", "applyq.global.p>128"},
+                                        {"applyq.lds", "applyq.lds.p>128"}, {"applyq.lds_large", "applyq.lds_large.p>128"}};
+      Profiler::get().hit(names[v][J.p > 128 ? 1 : 0], (long long)np);
+    }
     J.block0 = b0[g];
     b0[g] += nb;
     fl[g] += 4.0 * np * J.t * ((double)J.p * J.c - 0.5 * J.c * J.c);
@@ -3018,10 +3250,13 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     total += J.nprob;
     if (J.c <= 16) nsmall += J.nprob;
   }
+  // A core's result never depends on the other problems of the call: cores of
+  // at most 16 give the same bits in the one-wave and the four-wave form, so
+  // a call with few of them keeps them in the four-wave launch (one launch
+  // instead of two at the small levels); cores of 48..64 always take the
+  // register form (whose results differ from the LDS form's).
   const bool use_small = nsmall > kSmallLaunch;
-  // few problems: one launch of k_grsvd (two launches in sequence would only
-  // add their latencies)
-  const bool use_reg = total > kSmallLaunch;
+  const bool use_reg = true;
   for (auto& J : jobs)
     if (use_reg && J.c >= 48 && J.c <= 64 && J.nprob > 0) nreg += J.nprob;
   if (total == 0) return;
@@ -3054,6 +3289,12 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     if (g == 0 && need + kStatic > kMaxLds) {
       if (need + kStatic <= kMaxLdsLarge) g = 1;
       else { J.lds = 0; g = 3; }
+    }
+    {
+      static const char* names[4] = {"svd.lds", "svd.lds_large", "svd.wave16", "svd.global"};
+      Profiler::get().hit(J.redo ? "svd.reg" : names[g], J.nprob);
+      Profiler::get().hit(J.c <= 16 ? "svd.c<=16" : J.c <= 32 ? "svd.c17-32" : J.c < 48 ? "svd.c33-47"
+                          : J.c <= 64 ? "svd.c48-64" : "svd.c>64", J.nprob);
     }
     if (J.lds) {
       dyn[g] = std::max(dyn[g], need);
@@ -3166,12 +3407,8 @@ void gcopy(hipStream_t st, std::vector<CJob> jobs) {
 }
 
 template <typename T>
-void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs,
-          const std::vector<MVTerm>& terms) {
+void ghmv(hipStream_t st, std::vector<MVJob> jobs, const std::vector<MVTerm>& terms) {
   constexpr int CH = 16;
-  if (nrhs < 1 || nrhs > 8) fail(ACR_ERR_INTERNAL, "matvec takes 1..8 right-hand sides");
-  if (b < 1 || b > 256 || L > kMvMaxDepth || (b << L) != s) fail(ACR_ERR_INTERNAL, "matvec shape");
-  const int NR = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8;
   // every job gets its own copies of its terms, with the places of their
   // projections in the buffer
   std::vector<MVJob> use;
@@ -3179,27 +3416,34 @@ void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs
   std::vector<MVRed> reds;
   long long rows = 0, units = 0, tsize = 0;
   double flr = 0, byr = 0, fla = 0, bya = 0;
+  int maxnr = 1;
+  bool w64 = true;   // then every s = b 2^L and every row count are multiples of 64
   for (auto J : jobs) {
     if (J.nmat <= 0) continue;
+    const int s = J.s, b = J.b, L = J.L, nrhs = J.nrhs;
+    if (nrhs < 1 || nrhs > 8) fail(ACR_ERR_INTERNAL, "matvec takes 1..8 right-hand sides");
+    if (b < 1 || b > 256 || L > kMvMaxDepth || (b << L) != s) fail(ACR_ERR_INTERNAL, "matvec shape");
+    maxnr = std::max(maxnr, nrhs);
+    if (b % WAVE != 0) w64 = false;
     const int t0 = (int)tm.size();
     for (int t = 0; t < J.nterm; ++t) {
       MVTerm M = terms[J.term0 + t];
+      M.s = s;
+      M.nrhs = nrhs;
       double e = s;
       if (M.type == 0) {
-        int off = 0, upm = 0;
+        int upm = 0;
+        for (int d = 1; d <= kMvMaxDepth; ++d)
+          if (d > L) M.kc[d] = 0;
         for (int d = 1; d <= L; ++d) {
           if (M.kc[d] < 0 || M.kc[d] > M.k[d]) fail(ACR_ERR_INTERNAL, "matvec: rank above the allocation");
-          M.toff[d] = off;
-          off += (1 << d) * M.kc[d] * NR;
           upm += (1 << d) * ((M.kc[d] + CH - 1) / CH);
-          flr += 2.0 * J.nmat * s * M.kc[d] * nrhs;
-          byr += (double)J.nmat * s * (M.kc[d] + (M.kc[d] ? nrhs : 0)) * sizeof(T);
-          e += (double)s * M.kc[d];
+          const double ka = M.kmean[d] > 0.0f ? std::min<double>(M.kmean[d], M.kc[d]) : M.kc[d];
+          flr += 2.0 * J.nmat * s * ka * nrhs;
+          byr += (double)J.nmat * s * (ka + (M.kc[d] ? nrhs : 0)) * sizeof(T);
+          e += (double)s * ka;
         }
         e += (double)s * (b - 1);
-        M.tbase = tsize;
-        M.tstride = off;
-        tsize += (long long)J.nmat * off;
         if (upm > 0) {
           MVRed R;
           R.block0 = units;
@@ -3220,6 +3464,28 @@ void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs
     use.push_back(J);
   }
   if (use.empty()) return;
+  const int NR = maxnr <= 1 ? 1 : maxnr <= 2 ? 2 : maxnr <= 4 ? 4 : 8;
+  // projection slots: NR per column (the kernels index with the launch's NR)
+  for (auto& M : tm) {
+    if (M.type != 0) continue;
+    int off = 0;
+    for (int d = 1; d <= kMvMaxDepth; ++d) {
+      M.toff[d] = off;
+      off += (1 << d) * M.kc[d] * NR;
+    }
+    M.tstride = off;
+  }
+  {   // place each term's projections: terms of job j follow in order
+    long long base = 0;
+    for (auto& J : use)
+      for (int t = 0; t < J.nterm; ++t) {
+        MVTerm& M = tm[J.term0 + t];
+        if (M.type != 0) continue;
+        M.tbase = base;
+        base += (long long)J.nmat * M.tstride;
+      }
+    tsize = base;
+  }
   if ((rows + WAVE - 1) / WAVE > 0x7fffffffLL || (units + 3) / 4 > 0x7fffffffLL)
     fail(ACR_ERR_INVALID_ARG, "matvec grid too large");
   DBuf<T> tbuf((size_t)std::max<long long>(tsize, 1));
@@ -3229,7 +3495,7 @@ void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs
     const dim3 grid((unsigned)((units + 3) / 4));
     const int nr = (int)reds.size();
     auto go = [&](const char* name, auto kern) {
-      launch(st, KC_MATVEC, flr, byr, name, kern, grid, dim3(256), 0, dr, nr, dt, s, nrhs, units, tbuf.get());
+      launch(st, KC_MATVEC, flr, byr, name, kern, grid, dim3(256), 0, dr, nr, dt, units, tbuf.get());
     };
     switch (NR) {
       case 1: go(KNAME_T(k_hmv_reduce<T, 1>), k_hmv_reduce<T, 1>); break;
@@ -3239,12 +3505,10 @@ void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs
     }
   }
   const MVJob* dj = upload(use, st);
-  const bool w64 = b % WAVE == 0;   // then s = b 2^L and the row count are multiples of 64
   const dim3 grid((unsigned)((rows + WAVE - 1) / WAVE));
   const int nj = (int)use.size();
   auto go = [&](const char* name, auto kern) {
-    launch(st, KC_MATVEC, fla, bya, name, kern, grid, dim3(WAVE), 0, dj, nj, dt, s, b, L, nrhs, rows,
-           (const T*)tbuf.get());
+    launch(st, KC_MATVEC, fla, bya, name, kern, grid, dim3(WAVE), 0, dj, nj, dt, rows, (const T*)tbuf.get());
   };
 #define ACR_HMV_APPLY(NRV)                                                                   \
   if (w64) go(KNAME_T(k_hmv_apply<T, NRV, true>), k_hmv_apply<T, NRV, true>);              \
@@ -3256,6 +3520,53 @@ void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs
     default: ACR_HMV_APPLY(8) break;
   }
 #undef ACR_HMV_APPLY
+}
+
+template <typename T>
+void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs,
+          const std::vector<MVTerm>& terms) {
+  for (auto& J : jobs) { J.s = s; J.b = b; J.L = L; J.nrhs = nrhs; }
+  ghmv<T>(st, std::move(jobs), terms);
+}
+
+template <typename T>
+void gto_blocks(hipStream_t st, std::vector<VJob> jobs) {
+  long long b0 = 0;
+  double by = 0;
+  std::vector<VJob> use;
+  for (auto J : jobs) {
+    const long long n = (long long)J.s * J.nblk * J.nrhs;
+    if (n <= 0) continue;
+    J.per = (int)std::min<long long>((n + 255) / 256, 4096);
+    J.block0 = b0;
+    b0 += J.per;
+    by += (double)n * (8 + sizeof(T));
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  const VJob* dj = upload(use, st);
+  launch(st, KC_OTHER, 0.0, by, KNAME_T(k_gto_blocks<T>), k_gto_blocks<T>, dim3((unsigned)b0), dim3(256), 0, dj,
+         (int)use.size());
+}
+
+template <typename T>
+void gfrom_blocks(hipStream_t st, std::vector<VJob> jobs) {
+  long long b0 = 0;
+  double by = 0;
+  std::vector<VJob> use;
+  for (auto J : jobs) {
+    const long long n = (long long)J.s * J.nblk * J.nrhs;
+    if (n <= 0) continue;
+    J.per = (int)std::min<long long>((n + 255) / 256, 4096);
+    J.block0 = b0;
+    b0 += J.per;
+    by += (double)n * (8 + sizeof(T));
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  const VJob* dj = upload(use, st);
+  launch(st, KC_OTHER, 0.0, by, KNAME_T(k_gfrom_blocks<T>), k_gfrom_blocks<T>, dim3((unsigned)b0), dim3(256), 0, dj,
+         (int)use.size());
 }
 
 template <typename T>
@@ -3273,6 +3584,19 @@ void badd(hipStream_t st, int rows, int cols, int nmat, T alpha, const BOp& src,
   J.rows = rows; J.cols = cols; J.nmat = nmat; J.ncl = 1; J.alpha = (double)alpha; J.src = src; J.dst = dst;
   J.accumulate = 1;
   gcopy<T>(st, std::move(jobs));
+}
+
+void zero_bytes_now(const ZeroArgs& z, hipStream_t st) {
+  if (z.count <= 0) return;
+  unsigned long long most = 0, total = 0;
+  for (int i = 0; i < z.count; ++i) {
+    most = std::max(most, z.n[i]);
+    total += z.n[i];
+  }
+  ProfScope ps(KC_OTHER, st, 0.0, (double)total, Phase::cur(), "k_zero_bytes");
+  const long long work = std::max<long long>((long long)(most / 16), 16);
+  hipLaunchKernelGGL(k_zero_bytes, dim3(grid1(work, 256, 4096), z.count), dim3(256), 0, st, z);
+  ACR_HIP(hipGetLastError());
 }
 
 template <typename T>
@@ -3293,46 +3617,79 @@ void bscale(hipStream_t st, int rows, int cols, int nmat, int ncl, const BOp& X,
 }
 
 template <typename T>
-void build_capacitance(hipStream_t st, int k, int npairs, const T* cores, T* G) {
-  if (k <= 0 || npairs <= 0) return;
-  dim3 g(grid1(4LL * k * k, 256, 64), npairs);
-  launch(st, KC_OTHER, 0.0, 0.0, KNAME_T(k_build_cap<T>), k_build_cap<T>, g, dim3(256), 0, k, npairs, cores, G);
+void gbuild_capacitance(hipStream_t st, std::vector<CapJob> jobs) {
+  long long b0 = 0;
+  std::vector<CapJob> use;
+  for (auto J : jobs) {
+    if (J.k <= 0 || J.npairs <= 0) continue;
+    J.block0 = b0;
+    b0 += J.npairs;
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  const CapJob* dj = upload(use, st);
+  launch(st, KC_OTHER, 0.0, 0.0, KNAME_T(k_build_cap<T>), k_build_cap<T>, dim3((unsigned)b0), dim3(256), 0, dj,
+         (int)use.size());
+}
+
+namespace {
+// Workgroups per matrix of an ingest job covering `work` elements per matrix.
+int ingest_per(long long work, int cap) { return (int)std::max(1LL, std::min<long long>((work + 255) / 256, cap)); }
+
+template <typename T, typename K>
+void launch_opjobs(hipStream_t st, std::vector<OpJob> jobs, long long (*work)(const OpJob&), int cap, int cls,
+                   const char* name, K kern, size_t dyn = 0, bool one_per_matrix = false) {
+  long long b0 = 0;
+  std::vector<OpJob> use;
+  double by = 0;
+  for (auto J : jobs) {
+    if (J.nmat <= 0 || J.s <= 0) continue;
+    J.per = one_per_matrix ? 1 : ingest_per(work(J), cap);
+    J.block0 = b0;
+    b0 += (long long)J.nmat * J.per;
+    by += (double)J.nmat * work(J) * sizeof(T);
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  if (b0 > 0x7fffffffLL) fail(ACR_ERR_INVALID_ARG, "ingest grid too large");
+  const OpJob* dj = upload(use, st);
+  launch(st, cls, 0.0, by, name, kern, dim3((unsigned)b0), dim3(256), dyn, dj, (int)use.size());
+}
+}  // namespace
+
+template <typename T>
+void gleaves_tridiag(hipStream_t st, std::vector<OpJob> jobs) {
+  launch_opjobs<T>(st, std::move(jobs), [](const OpJob& J) { return (long long)J.s * J.b; }, 64, KC_OTHER,
+                   KNAME_T(k_leaves_tridiag<T>), k_leaves_tridiag<T>);
 }
 
 template <typename T>
-void build_leaves_tridiag(hipStream_t st, int s, int b, int nmat, int bmul, int boff,
-                          const double* diag, const double* west, const double* east, T* leaves) {
-  if (nmat <= 0) return;
-  dim3 g(grid1((long long)s * b, 256, 256), nmat);
-  launch(st, KC_OTHER, 0.0, 0.0, KNAME_T(k_leaves_tridiag<T>), k_leaves_tridiag<T>, g, dim3(256), 0, s, b, bmul, boff, diag, west, east,
-         leaves);
+void grank1_factors(hipStream_t st, std::vector<OpJob> jobs) {
+  for (const auto& J : jobs)
+    if (J.L > kMvMaxDepth) fail(ACR_ERR_INTERNAL, "rank-one factors: HODLR too deep");
+  launch_opjobs<T>(st, std::move(jobs), [](const OpJob& J) { return (long long)J.s * std::max(J.L, 1); }, 16,
+                   KC_OTHER, KNAME_T(k_rank1<T>), k_rank1<T>);
 }
 
 template <typename T>
-void tridiag_inverse(hipStream_t st, int s, int b, int L, int nmat, int bmul, int boff, const double* diag,
-                     const double* west, const double* east, T* lv, const TriInvOut& out, int* fallback) {
-  if (nmat <= 0) return;
-  if (s > 3072 || L > kMvMaxDepth) fail(ACR_ERR_INTERNAL, "tridiagonal inverse: block too large");
-  const size_t dyn = 5 * (size_t)s * sizeof(double);
+void ggather_diag(hipStream_t st, std::vector<OpJob> jobs) {
+  launch_opjobs<T>(st, std::move(jobs), [](const OpJob& J) { return (long long)J.s; }, 16, KC_OTHER,
+                   KNAME_T(k_gather_diag<T>), k_gather_diag<T>);
+}
+
+template <typename T>
+void gtridiag_inverse(hipStream_t st, std::vector<OpJob> jobs) {
+  int smax = 0;
+  for (const auto& J : jobs) {
+    if (J.nmat <= 0) continue;
+    if (J.s > 3072 || J.L > kMvMaxDepth) fail(ACR_ERR_INTERNAL, "tridiagonal inverse: block too large");
+    smax = std::max(smax, J.s);
+  }
+  if (smax == 0) return;
+  const size_t dyn = 5 * (size_t)smax * sizeof(double);
   if (dyn > kMaxLds - 1024) allow_large_lds(reinterpret_cast<const void*>(k_tridiag_inverse<T>));
-  launch(st, KC_INVERSE, 0.0, (double)nmat * ((double)s * b + 2.0 * s * L) * sizeof(T),
-         KNAME_T(k_tridiag_inverse<T>), k_tridiag_inverse<T>, dim3(nmat), dim3(256), dyn, s, b, L, bmul, boff,
-         diag, west, east, lv, out, fallback);
-}
-
-template <typename T>
-void build_rank1_factors(hipStream_t st, int s, int sd, int nmat, int bmul, int boff,
-                         const double* west, const double* east, T* U, T* V) {
-  if (nmat <= 0) return;
-  dim3 g(grid1(s, 256, 64), nmat);
-  launch(st, KC_OTHER, 0.0, 0.0, KNAME_T(k_rank1<T>), k_rank1<T>, g, dim3(256), 0, s, sd, bmul, boff, west, east, U, V);
-}
-
-template <typename T>
-void gather_diag(hipStream_t st, int s, int nmat, int bmul, int boff, const double* src, T* dst) {
-  if (nmat <= 0) return;
-  dim3 g(grid1(s, 256, 64), nmat);
-  launch(st, KC_OTHER, 0.0, 0.0, KNAME_T(k_gather_diag<T>), k_gather_diag<T>, g, dim3(256), 0, s, bmul, boff, src, dst);
+  launch_opjobs<T>(st, std::move(jobs), [](const OpJob& J) { return (long long)J.s * J.b + 2LL * J.s * J.L; }, 1,
+                   KC_INVERSE, KNAME_T(k_tridiag_inverse<T>), k_tridiag_inverse<T>, dyn, true);
 }
 
 template <typename T>
@@ -3369,6 +3726,55 @@ void stencil_residual(hipStream_t st, int nx, int ny, int nrhs, const double* di
          diag, west, east, south, north, X, B, R);
 }
 
+namespace {
+// Workgroups per column of a grouped vector job of N values.
+int vec_per(long long N) { return (int)std::min<long long>(std::max<long long>(1, (N + 2047) / 2048), 512); }
+
+void launch_rjobs(hipStream_t st, std::vector<RJob> jobs, int (*per)(const RJob&), bool per_column_only,
+                  const char* name, void (*kern)(const RJob*, int), double bytes_per_value) {
+  long long b0 = 0;
+  double by = 0;
+  std::vector<RJob> use;
+  for (auto J : jobs) {
+    const long long N = (long long)J.nx * J.ny;
+    if (N <= 0 || J.nrhs <= 0) continue;
+    J.per = per(J);
+    J.block0 = b0;
+    b0 += per_column_only ? J.nrhs : (long long)J.nrhs * J.per;
+    by += bytes_per_value * N * J.nrhs;
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  const RJob* dj = upload(use, st);
+  launch(st, KC_OTHER, 0.0, by, name, kern, dim3((unsigned)b0), dim3(256), 0, dj, (int)use.size());
+}
+}  // namespace
+
+void gresidual(hipStream_t st, std::vector<RJob> jobs) {
+  launch_rjobs(st, std::move(jobs), [](const RJob& J) { return vec_per((long long)J.nx * J.ny); }, false,
+               KNAME0(k_gresidual), k_gresidual, 64.0);
+}
+
+void gcol_sumsq(hipStream_t st, std::vector<RJob> jobs) {
+  // the parts buffer of every job, then the two passes
+  size_t tot = 0;
+  for (auto& J : jobs) tot += (size_t)J.nrhs * vec_per((long long)J.nx * J.ny);
+  DBuf<double> part(std::max<size_t>(tot, 1));
+  size_t off = 0;
+  for (auto& J : jobs) {
+    J.part = part.get() + off;
+    off += (size_t)J.nrhs * vec_per((long long)J.nx * J.ny);
+  }
+  auto per = [](const RJob& J) { return vec_per((long long)J.nx * J.ny); };
+  launch_rjobs(st, jobs, per, false, KNAME0(k_gsumsq_part), k_gsumsq_part, 8.0);
+  launch_rjobs(st, jobs, per, true, KNAME0(k_gsumsq_final), k_gsumsq_final, 0.0);
+}
+
+void gaxpy(hipStream_t st, std::vector<RJob> jobs) {
+  launch_rjobs(st, std::move(jobs), [](const RJob& J) { return vec_per((long long)J.nx * J.ny); }, false,
+               KNAME0(k_gaxpy), k_gaxpy, 24.0);
+}
+
 void col_sumsq(hipStream_t st, long long n, int ncol, const double* A, double* out) {
   const int nparts = (int)std::min<long long>(512, std::max<long long>(1, (n + 4095) / 4096));
   const long long chunk = (n + nparts - 1) / nparts;
@@ -3396,9 +3802,22 @@ void maxpy(hipStream_t st, long long n, int nvec, double a, double sc, const dou
          dim3(256), 0, n, nvec, a, sc, c, V, ldv, w);
 }
 
-void flag_nonfinite(hipStream_t st, long long n, const double* a, int* flag) {
-  if (n <= 0) return;
-  launch(st, KC_OTHER, 0.0, 8.0 * n, KNAME0(k_count_nonfinite), k_count_nonfinite, dim3(grid1(n, 256, 4096)), dim3(256), 0, n, a, flag);
+void gflag_nonfinite(hipStream_t st, std::vector<NFJob> jobs) {
+  long long b0 = 0;
+  double by = 0;
+  std::vector<NFJob> use;
+  for (auto J : jobs) {
+    if (J.n <= 0) continue;
+    J.per = (int)std::min<long long>((J.n + 255) / 256, 1024);
+    J.block0 = b0;
+    b0 += J.per;
+    by += 8.0 * J.n;
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  const NFJob* dj = upload(use, st);
+  launch(st, KC_OTHER, 0.0, by, KNAME0(k_count_nonfinite), k_count_nonfinite, dim3((unsigned)b0), dim3(256), 0, dj,
+         (int)use.size());
 }
 
 template <typename T>
@@ -3429,10 +3848,16 @@ void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
 }
 
 #define INST(T)                                                                                   \
-  template void tridiag_inverse<T>(hipStream_t, int, int, int, int, int, int, const double*, const double*, \
-                                   const double*, T*, const TriInvOut&, int*);                      \
+  template void gtridiag_inverse<T>(hipStream_t, std::vector<OpJob>);                              \
+  template void gleaves_tridiag<T>(hipStream_t, std::vector<OpJob>);                               \
+  template void grank1_factors<T>(hipStream_t, std::vector<OpJob>);                                \
+  template void ggather_diag<T>(hipStream_t, std::vector<OpJob>);                                  \
+  template void gbuild_capacitance<T>(hipStream_t, std::vector<CapJob>);                           \
   template void ggemm<T>(hipStream_t, std::vector<GJob>, const std::vector<GSeg>&);               \
   template void ghmv<T>(hipStream_t, int, int, int, int, std::vector<MVJob>, const std::vector<MVTerm>&); \
+  template void ghmv<T>(hipStream_t, std::vector<MVJob>, const std::vector<MVTerm>&);              \
+  template void gto_blocks<T>(hipStream_t, std::vector<VJob>);                                     \
+  template void gfrom_blocks<T>(hipStream_t, std::vector<VJob>);                                   \
   template void gqr<T>(hipStream_t, std::vector<QJob>);                                           \
   template void grsvd<T>(hipStream_t, std::vector<SJob>);                                         \
   template void gapply_q<T>(hipStream_t, std::vector<AJob>);                                      \
@@ -3450,12 +3875,6 @@ void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
   template void fill<T>(hipStream_t, T*, size_t, T);                                              \
   template void bscale<T>(hipStream_t, int, int, int, int, const BOp&, const T*, int, int,        \
                           long long, long long, int, T);                                          \
-  template void build_capacitance<T>(hipStream_t, int, int, const T*, T*);                        \
-  template void build_leaves_tridiag<T>(hipStream_t, int, int, int, int, int, const double*,      \
-                                        const double*, const double*, T*);                        \
-  template void build_rank1_factors<T>(hipStream_t, int, int, int, int, int, const double*,       \
-                                       const double*, T*, T*);                                    \
-  template void gather_diag<T>(hipStream_t, int, int, int, int, const double*, T*);               \
   template void to_blocks<T>(hipStream_t, int, int, int, const double*, long long, T*);           \
   template void from_blocks<T>(hipStream_t, int, int, int, const T*, double*, long long);         \
   template void bdiag_axpy<T>(hipStream_t, int, int, int, T, const T*, int, int, const T*, int,   \
@@ -3467,6 +3886,8 @@ INST(double)
 
 template void binverse<double, double>(hipStream_t, int, int, const double*, long long, double*,
                                        long long, int*);
+template void ginverse<double, double>(hipStream_t, std::vector<IJob>);
+template void ginverse<float, float>(hipStream_t, std::vector<IJob>);
 template void binverse<float, float>(hipStream_t, int, int, const float*, long long, float*,
                                      long long, int*);
 

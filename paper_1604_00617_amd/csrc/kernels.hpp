@@ -82,10 +82,11 @@ struct TJob {
   void* Ut = nullptr;
 };
 
-// *out = max(rank[0..n)).
+// *out = max(rank[0..n)); *sum (if set) = sum(rank[0..n)).
 struct MJob {
   const int* rank = nullptr;
   int* out = nullptr;
+  int* sum = nullptr;
   int n = 0, pad = 0;
 };
 
@@ -104,10 +105,11 @@ struct CJob {
 
 // Multi-term HODLR matvec for a few right-hand sides (solve path):
 //   out_m = beta * C0_m + sum_t alpha_t op_t(m) y_t(m)
-// with op_t a HODLR matrix of a set (all of one launch share s, b, L) or a
-// diagonal.  Vector blocks are s x nrhs, column-major, block stride s*nrhs;
-// block index of matrix m is mul*m + off for every operand.  The output may
-// not overlap any input.
+// with op_t a HODLR matrix of a set or a diagonal.  Every job has its own
+// block size s, leaf b, depth L and number of right-hand sides (<= 8), so the
+// jobs of several independent problems share the launches.  Vector blocks are
+// s x nrhs, column-major, block stride s*nrhs; block index of matrix m is
+// mul*m + off for every operand.  The output may not overlap any input.
 constexpr int kMvMaxDepth = 15;
 struct MVTerm {
   int type = 0;               // 0 HODLR, 1 diagonal
@@ -122,10 +124,14 @@ struct MVTerm {
   int k[kMvMaxDepth + 1] = {};    // allocated columns per depth (matrix stride k*s)
   int kc[kMvMaxDepth + 1] = {};   // used columns
   // set by the launcher: projections V_d[node]^T y[node] of matrix m at
-  // tbase + m * tstride + toff[d] + (node * kc[d] + column) * NR + rhs
+  // tbase + m * tstride + toff[d] + (node * kc[d] + column) * NR + rhs;
+  // s and nrhs of the job the term belongs to
   long long tbase = 0;
-  int tstride = 0, pad2 = 0;
+  int tstride = 0, s = 0, nrhs = 0, pad2 = 0;
   int toff[kMvMaxDepth + 1] = {};
+  // host only (algorithmic counts): mean numerical rank of the depth-d blocks
+  // (<= kc[d]; the padding columns up to kc[d] are zeros)
+  float kmean[kMvMaxDepth + 1] = {};
 };
 struct MVRed {                    // projections of one term (launcher-internal)
   long long block0 = 0;           // first wave
@@ -135,28 +141,90 @@ struct MVJob {
   long long block0 = 0;
   int nmat = 0, nterm = 0, term0 = 0;
   int omul = 1, ooff = 0, cmul = 1, coff = 0;
+  int s = 0, b = 0, L = 0, nrhs = 0;   // shapes of this job's operands
   double beta = 0.0;
   const void* C0 = nullptr;       // null: out = sum of terms
   void* out = nullptr;
 };
 
+// Jobs keep their own s, b, L and nrhs (1..8).
+template <typename T>
+void ghmv(hipStream_t st, std::vector<MVJob> jobs, const std::vector<MVTerm>& terms);
+// All jobs with the same shapes.
 template <typename T>
 void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs,
           const std::vector<MVTerm>& terms);
 
-// X_m = D^{-1} for the tridiagonal block D of block row bmul*m + boff of the
-// five-point operator (diag, west = D[i][i-1], east = D[i][i+1]), written
-// directly in HODLR form: leaves lv [nmat][2^L][b][b]; depth-d factors at
-// U[d] + m*s and V[d] + m*s (rank exactly 1).  *fallback is set to 1 when the
-// elimination without pivoting breaks down (a zero or non-finite pivot); the
-// caller then uses the general H-inverse.  Needs s <= 3072.
-struct TriInvOut {
-  void* U[kMvMaxDepth + 1] = {};
-  void* V[kMvMaxDepth + 1] = {};
+// Block-major <-> column-major vector layouts for several problems at once:
+// V[i][q][j] = B[(i*s + j) + q*ld] for the nblk blocks of each job.
+struct VJob {
+  long long block0 = 0;   // first workgroup
+  int s = 0, nblk = 0, nrhs = 0, per = 0;
+  long long ld = 0;
+  const void* src = nullptr;
+  void* dst = nullptr;
 };
 template <typename T>
-void tridiag_inverse(hipStream_t st, int s, int b, int L, int nmat, int bmul, int boff, const double* diag,
-                     const double* west, const double* east, T* lv, const TriInvOut& out, int* fallback);
+void gto_blocks(hipStream_t st, std::vector<VJob> jobs);     // src double, dst T
+template <typename T>
+void gfrom_blocks(hipStream_t st, std::vector<VJob> jobs);   // src T, dst double
+
+// Level-0 ingest of the five-point operator, grouped over problems: job j
+// covers matrices m = 0..nmat-1 of one problem, which use block row
+// bmul*m + boff of that problem's stencil arrays (diag, west = D[i][i-1],
+// east = D[i][i+1]).  `per` and block0 are set by the launchers.
+struct OpJob {
+  long long block0 = 0;
+  int s = 0, b = 0, L = 0, nmat = 0, bmul = 1, boff = 0, per = 1, zblk = -1;
+  const double* diag = nullptr;
+  const double* west = nullptr;
+  const double* east = nullptr;
+  const double* src = nullptr;     // ggather_diag: the stencil array gathered
+  void* out = nullptr;             // leaves [nmat][2^L][b][b] or gathered diagonals [nmat][s]
+  void* U[kMvMaxDepth + 1] = {};   // depth-d factors, matrix m at U[d] + m*s (one column)
+  void* V[kMvMaxDepth + 1] = {};
+  int* flag = nullptr;             // gtridiag_inverse: set to 1 on a breakdown
+};
+// Leaves: the tridiagonal band restricted to each b x b diagonal leaf of D_i.
+template <typename T>
+void gleaves_tridiag(hipStream_t st, std::vector<OpJob> jobs);
+// Depth-d rank-one factors of D_i for every depth d = 1..L (Section 3:
+// tridiagonal D_i has exact rank-1 off-diagonal blocks).
+template <typename T>
+void grank1_factors(hipStream_t st, std::vector<OpJob> jobs);
+// out[m][r] = src[(bmul*m + boff)*s + r], zero for block row zblk (E_0 and
+// F_(ny-1) couple to rows outside the grid).
+template <typename T>
+void ggather_diag(hipStream_t st, std::vector<OpJob> jobs);
+// X_m = D^{-1} for the tridiagonal D of block row bmul*m + boff, written
+// directly in HODLR form (leaves in out, rank-one factors in U/V); *flag = 1
+// when the elimination without pivoting breaks down (the caller then uses the
+// general H-inverse).  Needs s <= 3072.
+template <typename T>
+void gtridiag_inverse(hipStream_t st, std::vector<OpJob> jobs);
+
+// *flag = 1 if any of a[0..n) is NaN or infinite, per job.
+struct NFJob {
+  long long block0 = 0;
+  long long n = 0;
+  const double* a = nullptr;
+  int* flag = nullptr;
+  int per = 1, pad = 0;
+};
+void gflag_nonfinite(hipStream_t st, std::vector<NFJob> jobs);
+
+// Capacitance matrices of the HODLR inverse: for each parent q of a pair of
+// clusters (2q, 2q+1) with cores c_(2q), c_(2q+1) (k x k each, contiguous per
+// cluster), G_q = [[I, c_(2q+1)], [c_(2q), I]] (2k x 2k, ld 2k); jobs of one
+// call may have different k.
+struct CapJob {
+  long long block0 = 0;
+  int k = 0, npairs = 0;
+  const void* cores = nullptr;
+  void* G = nullptr;
+};
+template <typename T>
+void gbuild_capacitance(hipStream_t st, std::vector<CapJob> jobs);
 
 template <typename T>
 void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs);
@@ -177,6 +245,23 @@ void gcopy(hipStream_t st, std::vector<CJob> jobs);
 template <typename T>
 void bgemm(hipStream_t st, int M, int N, int K, int nmat, int ncl, T alpha, const BOp& A,
            const BOp& B, T beta, const BOp& C);
+
+// Grouped small dense inverses: job j inverts its nprob matrices of size n
+// (A at A + p*sA, X at X + p*sX, ld n) as binverse does; jobs of one call may
+// have different sizes.  ws / use_lds are set by the launcher.
+struct IJob {
+  long long block0 = 0;
+  int n = 0, nprob = 0;
+  const void* A = nullptr;
+  long long sA = 0;
+  void* X = nullptr;
+  long long sX = 0;
+  int* status = nullptr;
+  double* ws = nullptr;
+  int use_lds = 0, pad = 0;
+};
+template <typename Tin, typename Tout>
+void ginverse(hipStream_t st, std::vector<IJob> jobs);
 
 // X_p = A_p^{-1} (n x n, Gauss-Jordan with partial pivoting, computed in FP64).
 // A_p at A + p*sA (ld n), X_p at X + p*sX (ld n).  *status set to 1 on a zero
@@ -236,31 +321,6 @@ template <typename T>
 void bscale(hipStream_t st, int rows, int cols, int nmat, int ncl, const BOp& X, const T* vec,
             int vmul, int voff, long long vstride, long long vcl, int side, T alpha);
 
-// Capacitance matrices of the HODLR inverse: for each parent q of a pair of
-// clusters (2q, 2q+1) with cores c_(2q), c_(2q+1) (k x k each, contiguous per
-// cluster), G_q = [[I, c_(2q+1)], [c_(2q), I]] (2k x 2k, ld 2k).
-template <typename T>
-void build_capacitance(hipStream_t st, int k, int npairs, const T* cores, T* G);
-
-// Level-0 diagonal blocks D_i of the stencil as HODLR matrices (Section 3:
-// tridiagonal D_i has exact rank-1 off-diagonal blocks).  Block index of
-// matrix m is i = bmul*m + boff.  Leaves: the tridiagonal band restricted to
-// each b x b diagonal leaf.
-template <typename T>
-void build_leaves_tridiag(hipStream_t st, int s, int b, int nmat, int bmul, int boff,
-                          const double* diag, const double* west, const double* east, T* leaves);
-// Depth-d factors (cluster size sd, one column each, flat length s): the
-// upper-right block of a first child couples its last row to the sibling's
-// first column (value east), the lower-left block of a second child couples
-// its first row to the sibling's last column (value west).
-template <typename T>
-void build_rank1_factors(hipStream_t st, int s, int sd, int nmat, int bmul, int boff,
-                         const double* west, const double* east, T* U, T* V);
-
-// Copy a diagonal (per block, contiguous s values) of the stencil into T.
-template <typename T>
-void gather_diag(hipStream_t st, int s, int nmat, int bmul, int boff, const double* src, T* dst);
-
 // Block-major <-> column-major vector layouts.  V[i][q][j] = B[(i*s + j) + q*ld].
 template <typename T>
 void to_blocks(hipStream_t st, int s, int nblk, int nrhs, const double* B, long long ld, T* V);
@@ -278,11 +338,33 @@ void stencil_residual(hipStream_t st, int nx, int ny, int nrhs, const double* di
                       const double* west, const double* east, const double* south,
                       const double* north, const double* X, const double* B, double* R);
 
+// Refinement vector work of several problems in one launch: job j covers
+// nrhs columns of N = nx*ny FP64 values (column q at offset q*N).
+//   gresidual:  R = B - A X with the job's five-point stencil;
+//   gcol_sumsq: out[q] = sum_i R[i + q*N]^2 (fixed chunking per N, fixed
+//               summation order: the same bits whatever the batch);
+//   gaxpy:      R += B (X += D with R = X, B = D).
+struct RJob {
+  long long block0 = 0;
+  int nx = 0, ny = 0, nrhs = 0, per = 0;
+  const double* diag = nullptr;
+  const double* west = nullptr;
+  const double* east = nullptr;
+  const double* south = nullptr;
+  const double* north = nullptr;
+  const double* X = nullptr;
+  const double* B = nullptr;
+  double* R = nullptr;
+  double* part = nullptr;   // set by gcol_sumsq
+  double* out = nullptr;
+};
+void gresidual(hipStream_t st, std::vector<RJob> jobs);
+void gcol_sumsq(hipStream_t st, std::vector<RJob> jobs);
+void gaxpy(hipStream_t st, std::vector<RJob> jobs);
+
 // out[q] = sum_i A[i + q*n]^2  (n rows, ncol columns), FP64.
 void col_sumsq(hipStream_t st, long long n, int ncol, const double* A, double* out);
 
-// *flag = 1 if any of a[0..n) is NaN or infinite (flag untouched otherwise).
-void flag_nonfinite(hipStream_t st, long long n, const double* a, int* flag);
 
 // Diagnostics: whether a[0..n) holds a NaN/Inf and the largest finite |a|.
 // Synchronises st.

@@ -74,9 +74,10 @@ def test_fp64_blocks_vs_oracle(gpu):
                 got = gpu.acr_get_block(h, lev, which, k)
                 scale = max(np.abs(ref).max(), 1e-300)
                 assert np.abs(got - ref).max() <= 10 * eps * scale
-    # level-0 off-diagonal ranks of D are exactly one: the first stored X has
-    # exact ranks 1, 2, ... by depth, so its truncated ranks are bounded by the depth
-    assert gpu.acr_get_info(h)["level_max_rank"][0] <= 2
+    # level 0: D_k is tridiagonal, so every off-diagonal block of its inverse
+    # has rank at most one (nullity theorem); E_k, F_k are diagonal and P_k, Q_k
+    # keep the rank of X_k.  The level-0 stored ranks are therefore <= 1.
+    assert gpu.acr_get_info(h)["level_max_rank"][0] <= 1
 
 
 def test_mixed_refined_residual(gpu):
@@ -104,13 +105,29 @@ def test_fp64_refined_residual(gpu):
 
 def test_mixed_forward_error_reported(gpu):
     """Mixed-precision solve before refinement, against the FP64 oracle at the
-    same eps (reported; the binding gate for FP32 is the refined residual)."""
+    same eps: reported next to 10 eps and gated by the FP32 bound."""
+    from bounds import mixed_forward_bound
     st = W.varkappa(64)
     h, b, x = _solve(gpu, st, 16, 1e-6, "mixed")
     xo = OA.solve(OA.factor(st, 16, 1e-6), st, b)
     e = _relerr(x, xo)
-    print(f"mixed pre-refinement forward error vs oracle: {e:.3e} (10*eps = 1e-5)")
-    assert e < 1e-2
+    print(f"mixed pre-refinement forward error vs oracle: {e:.3e} (10*eps = 1e-5, "
+          f"FP32 bound {mixed_forward_bound(1e-6):.1e})")
+    assert e <= mixed_forward_bound(1e-6)
+
+
+def test_refined_rejects_overlapping_x_and_b(gpu):
+    import torch
+    st = W.poisson(32)
+    op = _op(gpu, st)
+    h = gpu.acr_factor(op, 16, 1e-8, "fp64")
+    lib = gpu.load()
+    B = torch.from_numpy(W.rhs(st.n, 1)).cuda().reshape(-1)
+    import ctypes
+    its, rel = ctypes.c_int32(0), ctypes.c_double(0.0)
+    code = lib.acr_solve_refined(h.ptr, ctypes.byref(op._c()), B.data_ptr(), B.data_ptr(), 1, 1e-10, 10,
+                                 ctypes.byref(its), ctypes.byref(rel), gpu._stream())
+    assert gpu.STATUS[code] == "ACR_ERR_INVALID_ARG"
 
 
 def test_edge_cases(gpu):

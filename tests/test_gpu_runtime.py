@@ -1,0 +1,108 @@
+"""Runtime behaviour of the library on the GPU: streams, threads and the
+allocator hook of the boundary.  Results are compared bitwise (FP64)."""
+import gc
+import threading
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _op(acr, st):
+    return acr.Operator.from_arrays(st.nx, st.ny, *st.arrays())
+
+
+def test_two_streams_match_sequential(gpu):
+    """Two handles solved on two streams at once give the same bits as the
+    same solves one after the other on the default stream (no workspace is
+    shared between the streams while in use)."""
+    import torch
+    sa, sb = W.varkappa(128), W.convdiff(96, 40)
+    ha = gpu.acr_factor(_op(gpu, sa), 32, 1e-8, "fp64")
+    hb = gpu.acr_factor(_op(gpu, sb), 24, 1e-8, "fp64")
+    ba = torch.from_numpy(W.rhs(sa.n, 3, seed=1)).cuda()
+    bb = torch.from_numpy(W.rhs(sb.n, 3, seed=2)).cuda()
+    xa0 = gpu.acr_solve(ha, ba).cpu().numpy()
+    xb0 = gpu.acr_solve(hb, bb).cpu().numpy()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    outs = []
+    for _ in range(4):
+        with torch.cuda.stream(s1):
+            xa = gpu.acr_solve(ha, ba, stream=s1)
+        with torch.cuda.stream(s2):
+            xb = gpu.acr_solve(hb, bb, stream=s2)
+        outs.append((xa, xb))
+    torch.cuda.synchronize()
+    for xa, xb in outs:
+        assert np.array_equal(xa.cpu().numpy(), xa0)
+        assert np.array_equal(xb.cpu().numpy(), xb0)
+
+
+def test_two_threads_match_sequential(gpu):
+    """Two host threads factor and solve different problems at the same time."""
+    import torch
+    probs = [(W.varkappa(64), 16), (W.poisson(96), 24)]
+    ref = []
+    for st, leaf in probs:
+        h = gpu.acr_factor(_op(gpu, st), leaf, 1e-9, "fp64")
+        ref.append(gpu.acr_solve(h, torch.from_numpy(W.rhs(st.n, 2, seed=5)).cuda()).cpu().numpy())
+        gpu.acr_destroy(h)
+    got = [None, None]
+    errs = []
+
+    def work(i):
+        try:
+            st, leaf = probs[i]
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for _ in range(3):
+                    h = gpu.acr_factor(_op(gpu, st), leaf, 1e-9, "fp64", stream=s)
+                    x = gpu.acr_solve(h, torch.from_numpy(W.rhs(st.n, 2, seed=5)).cuda(), stream=s)
+                    s.synchronize()
+                    got[i] = x.cpu().numpy()
+                    gpu.acr_destroy(h)
+        except Exception as e:   # reported by the main thread
+            errs.append(e)
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    for i in range(2):
+        assert np.array_equal(got[i], ref[i])
+
+
+def test_torch_allocator_hook(gpu):
+    """With acr_set_allocator pointing at PyTorch's caching allocator the
+    library takes its device memory from torch, and results are unchanged."""
+    import torch
+    st = W.varkappa(128)
+    b = torch.from_numpy(W.rhs(st.n, 1, seed=3)).cuda()
+    h = gpu.acr_factor(_op(gpu, st), 32, 1e-8, "fp64")
+    x0 = gpu.acr_solve(h, b).cpu().numpy()
+    # a live handle blocks switching the memory source
+    with pytest.raises(gpu.ACRError) as ei:
+        gpu.use_torch_allocator()
+    assert ei.value.name == "ACR_ERR_INVALID_ARG"
+    gpu.acr_destroy(h)
+    gc.collect()
+    before = torch.cuda.memory_allocated()
+    gpu.use_torch_allocator()
+    try:
+        h = gpu.acr_factor(_op(gpu, st), 32, 1e-8, "fp64")
+        during = torch.cuda.memory_allocated()
+        x1 = gpu.acr_solve(h, b).cpu().numpy()
+        info = gpu.acr_get_info(h)
+        assert during - before >= info["factor_bytes"]
+        assert np.array_equal(x0, x1)
+        gpu.acr_destroy(h)
+    finally:
+        gc.collect()
+        gpu.acr_set_allocator(None, None)
+    assert torch.cuda.memory_allocated() <= before

@@ -271,3 +271,17 @@ def make(kind: str, n: int, config_id: int = 0) -> Stencil:
     if kind == "convdiff":
         return convdiff(n, seed=seed_for(config_id or 4, 1))
     raise ValueError(kind)
+
+
+def strip(st: Stencil, rows: int, first: int = 0) -> Stencil:
+    """The block rows [first, first + rows) of an operator as an operator of its own
+    (same block size and coefficients; the couplings to the rows outside are dropped,
+    i.e. Dirichlet zeros there).  A bounded sample of a large workload with its real
+    block shapes."""
+    if not (0 <= first and rows >= 1 and first + rows <= st.ny):
+        raise ValueError("strip outside the operator")
+    lo, hi = first * st.nx, (first + rows) * st.nx
+    arr = [a[lo:hi].copy() for a in st.arrays()]
+    arr[3][: st.nx] = 0.0                  # south of the first row
+    arr[4][(rows - 1) * st.nx:] = 0.0      # north of the last row
+    return Stencil(st.nx, rows, *arr, name=f"{st.name}-strip{rows}")
