@@ -163,6 +163,21 @@ acr_status acr_solve_batched(const acr_handle* hs, const double* const* B, doubl
  * every call, so the call is not meant for stream capture. */
 acr_status acr_solve(acr_handle h, const double* B, double* X, int32_t nrhs, void* stream);
 
+/* acr_solve without any device allocation, for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results (bit for bit) and kernels as
+ * acr_solve; its workspace and job descriptors live in a fixed scratch array
+ * of 64 MiB that the library holds on every GPU it runs on until the process
+ * ends (60 MiB of workspace, 4 MiB of descriptors).  A solve that needs more
+ * (it grows with N * nrhs: about 24 N nrhs bytes in FP32 factors, twice that
+ * in FP64) is rejected with ACR_ERR_INVALID_ARG before any work is issued.
+ * The call issues no hipMalloc, hipFree, allocating library routine or
+ * profiler event.  All calls on one GPU share that GPU's scratch and the
+ * scratch keeps the last call's contents: calls that overlap in time on one
+ * GPU (other threads or other streams) race and are not allowed.  The
+ * handle must exist (acr_factor allocates) and its factor is read only. */
+acr_status acr_solve_noalloc(acr_handle h, const double* B, double* X, int32_t nrhs, void* stream);
+
 /* Iterative refinement with ACR as the preconditioner (Section 4, closing
  * paragraph): x_0 = 0, r = B - A x in FP64, x += M^{-1} r, until
  * max_col ||r||_2/||B||_2 <= tol or maxit corrections.  op must be the

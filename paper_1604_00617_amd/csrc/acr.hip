@@ -719,6 +719,56 @@ ACR_INST(double)
 
 }  // namespace acr
 
+namespace acr {
+namespace {
+
+// Scratch of the allocation-free solve (acr_solve_noalloc): the workspace of
+// one call, then its job descriptors.  Each GPU the library runs on holds its
+// own copy of the array until the process ends.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr size_t kNoAllocDescBytes = size_t(4) << 20;
+constexpr size_t kNoAllocWorkBytes = kNoAllocBytes - kNoAllocDescBytes;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on device `dev` (the host-side name is only a
+// stand-in): looked up once per device, with that device current.
+char* scratch_on_device(int dev) {
+  static std::mutex mu;
+  static std::map<int, char*> ptrs;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = ptrs.find(dev);
+  if (it != ptrs.end()) return it->second;
+  void* p = nullptr;
+  ACR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) fail(ACR_ERR_DEVICE, "no device address for the allocation-free scratch");
+  ptrs[dev] = static_cast<char*>(p);
+  return static_cast<char*>(p);
+}
+
+// Installs the scratch as the calling thread's memory and descriptor source.
+struct NoAllocScope {
+  Bump bump;
+  DescArena::External ext;
+  NoAllocScope(char* base, bool count_only) {
+    bump.base = base;
+    bump.cap = kNoAllocWorkBytes;
+    bump.count_only = count_only;
+    ext.dev = base + kNoAllocWorkBytes;
+    ext.cap = kNoAllocDescBytes;
+    ext.count_only = count_only;
+    Bump::cur() = &bump;
+    DescArena::External::cur() = &ext;
+    Queue::get().set_dry(count_only);
+  }
+  ~NoAllocScope() {
+    Queue::get().set_dry(false);
+    Bump::cur() = nullptr;
+    DescArena::External::cur() = nullptr;
+  }
+};
+
+}  // namespace
+}  // namespace acr
 
 
 using namespace acr;
@@ -885,6 +935,34 @@ acr_status acr_solve(acr_handle h, const double* B, double* X, int32_t nrhs, voi
     if (nrhs < 1) fail(ACR_ERR_INVALID_ARG, "nrhs must be >= 1");
     StreamScope ss(static_cast<hipStream_t>(stream));
     h->f->solve(B, X, nrhs, static_cast<hipStream_t>(stream));
+  });
+}
+
+acr_status acr_solve_noalloc(acr_handle h, const double* B, double* X, int32_t nrhs, void* stream) {
+  return guard([&] {
+    if (!h || !B || !X) fail(ACR_ERR_INVALID_ARG, "NULL argument");
+    if (nrhs < 1) fail(ACR_ERR_INVALID_ARG, "nrhs must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope ss(st);
+    queue_flush();   // nothing of an earlier call may be issued from the scratch
+    int dev = 0;
+    ACR_HIP(hipGetDevice(&dev));
+    char* base = scratch_on_device(dev);
+    size_t need_work = 0, need_desc = 0;
+    {   // planning pass: the memory the call takes, nothing issued
+      NoAllocScope ns(base, true);
+      h->f->solve(B, X, nrhs, st);
+      need_work = ns.bump.off;
+      need_desc = ns.ext.off;
+    }
+    if (need_work > kNoAllocWorkBytes || need_desc > kNoAllocDescBytes)
+      fail(ACR_ERR_INVALID_ARG, "acr_solve_noalloc: this solve needs " + std::to_string(need_work >> 20) +
+                                    " MiB of workspace and " + std::to_string(need_desc >> 10) +
+                                    " KiB of descriptors; the maximum is " + std::to_string(kNoAllocWorkBytes >> 20) +
+                                    " MiB and " + std::to_string(kNoAllocDescBytes >> 10) + " KiB (use acr_solve)");
+    NoAllocScope ns(base, false);
+    h->f->solve(B, X, nrhs, st);
+    queue_flush();   // issue everything while the scratch is still the descriptor source
   });
 }
 
