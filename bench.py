@@ -60,6 +60,10 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000, help="timed requests of --config 5")
     ap.add_argument("--budget-gb", type=float, default=2.5, help="factor memory budget of --config 5")
     ap.add_argument("--batch", type=int, default=256, help="problems of --config 3")
+    ap.add_argument("--alpha-sweep", type=str, default=None, metavar="A1,A2,...",
+                    help="instead of the benchmark workload, factor the paper's recirculating flow on the --n "
+                         "grid for each alpha (mixed and FP64) and report factor time, ranks and storage; "
+                         "FGMRES to --tol where the operator's own conditioning allows it")
     ap.add_argument("--cpu-rows", type=int, default=16,
                     help="block rows of the operator the CPU oracle factors (bounded sample)")
     return ap.parse_args()
@@ -190,6 +194,54 @@ def bench_batched(acr, torch, W, args):
                                  "problems": args.batch, "unknowns": unknowns, "nrhs": nrhs},
                       "batched_equals_one_by_one_bitwise": bool(same),
                       "fp64": res["fp64"], "mixed": res["mixed"]}), flush=True)
+
+
+def bench_alpha_sweep(acr, torch, W, args):
+    """The paper's second experiment: ACR's cost against the convection strength alpha of
+    -Laplace u + alpha (cos 8 pi x, sin 8 pi y) . grad u (first-order upwind).  Per alpha: factor
+    time (median of --steps), stored ranks and bytes of the mixed and the FP64 factor, and the
+    FGMRES(20) count to --tol with the mixed factor as preconditioner (for alpha where the target
+    is reachable in FP64 at all)."""
+    alphas = [float(a) for a in args.alpha_sweep.split(",")]
+    rows = []
+    for a in alphas:
+        st = W.recirculating(args.n, a)
+        op = acr.Operator.from_arrays(st.nx, st.ny, *st.arrays())
+        row = {"alpha": a}
+        for prec in ("mixed", "fp64"):
+            h = acr.acr_factor(op, args.leaf, args.eps, prec)   # warm-up
+            acr.acr_destroy(h)
+            ts = []
+            for _ in range(max(args.steps, 1)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                h = acr.acr_factor(op, args.leaf, args.eps, prec)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+                info = acr.acr_get_info(h)
+                if prec == "mixed" and len(ts) == args.steps and a <= 100:
+                    b = torch.from_numpy(W.rhs(st.n, 1)).cuda()
+                    _, its, rel = acr.acr_solve_krylov(h, op, b, tol=args.tol, maxit=60, restart=20,
+                                                       raise_on_fail=False)
+                    row["fgmres_applications"] = its
+                    row["fgmres_relres"] = rel
+                acr.acr_destroy(h)
+            ts.sort()
+            row[prec] = {"factor_ms": ts[len(ts) // 2], "max_rank": info["max_rank"],
+                         "level_max_rank": info["level_max_rank"],
+                         "level_mean_rank": [round(v, 2) for v in info["level_mean_rank"]],
+                         "factor_bytes": info["factor_bytes"]}
+        rows.append(row)
+        print(f"[alpha] {a:g}: mixed factor {row['mixed']['factor_ms']:.1f} ms, max rank "
+              f"{row['mixed']['max_rank']}, fp64 factor {row['fp64']['factor_ms']:.1f} ms", file=sys.stderr, flush=True)
+    m0 = rows[0]["mixed"]["factor_ms"]
+    print(json.dumps({"metric": "ACR factor time vs convection strength (recirculating flow)",
+                      "value": max(r["mixed"]["factor_ms"] for r in rows) / m0, "unit": "max/min factor time",
+                      "n_gpus": 1, "steps": args.steps, "warmup": 1, "higher_is_better": False,
+                      "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"recirculating flow {args.n}x{args.n}, leaf {args.leaf}, "
+                                             f"eps {args.eps:g}, alpha in {alphas}"},
+                      "sweep": rows}), flush=True)
 
 
 def bench_serving(acr, torch, W, args):
@@ -498,6 +550,9 @@ def main():
     torch.cuda.set_device(0)
     if args.helmholtz is not None or args.recirculating is not None:
         bench_krylov_workload(acr, torch, W, args)
+        return
+    if args.alpha_sweep:
+        bench_alpha_sweep(acr, torch, W, args)
         return
     if args.config == 3:
         bench_batched(acr, torch, W, args)

@@ -337,6 +337,31 @@ acr_status acr_server_stats(acr_server s, int32_t reset, acr_server_info* out);
 /* Finish every queued request, stop the worker and free the server. */
 acr_status acr_server_destroy(acr_server s);
 
+/* ------------------------------------------------------------- autotuner
+ * Kernel-variant choices per shape key, measured on the device: the tile
+ * shape of the grouped GEMM per (precision, M, N, K size class, problem-count
+ * size class) -- every tile gives the same bits -- and the Householder QR
+ * form (one wave, registers, LDS) per (precision, panel rows, columns), whose
+ * forms differ in rounding.  Keys hold a problem's own shapes only, so with
+ * any fixed table a problem's result is the same whatever it is batched
+ * with.  Without a table the built-in choices apply. */
+/* Start (on != 0) or stop noting the shape keys the library meets. */
+acr_status acr_tune_record(int32_t on);
+/* Measure every noted key that has no table entry yet (micro-benchmarks on
+ * synthetic operands on `stream`; synchronises it) and add the fastest
+ * choice; *added (host, may be NULL): entries added.  Tuning is off while it
+ * measures; the table's use afterwards follows acr_tune_enable. */
+acr_status acr_tune_run(void* stream, int32_t* added);
+/* Use (on != 0) or ignore the table. */
+acr_status acr_tune_enable(int32_t on);
+/* Write the table as JSON {"arch": <device architecture>, "entries": {key: choice}}. */
+acr_status acr_tune_save(const char* path);
+/* Replace the table by the file's entries and use it; ACR_ERR_INVALID_ARG if
+ * the file was written for another architecture or is malformed. */
+acr_status acr_tune_load(const char* path);
+/* Drop the table and the noted keys; built-in choices from now on. */
+acr_status acr_tune_clear(void);
+
 /* Number of kernel launches (and device fills) the calling thread has
  * issued through the library so far (for launch counts per step). */
 int64_t acr_launch_count(void);

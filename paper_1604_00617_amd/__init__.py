@@ -482,3 +482,44 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def _tune_lib():
+    lib = load()
+    lib.acr_tune_record.argtypes = [ctypes.c_int32]
+    lib.acr_tune_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
+    lib.acr_tune_enable.argtypes = [ctypes.c_int32]
+    lib.acr_tune_save.argtypes = [ctypes.c_char_p]
+    lib.acr_tune_load.argtypes = [ctypes.c_char_p]
+    for n in ("acr_tune_record", "acr_tune_run", "acr_tune_enable", "acr_tune_save", "acr_tune_load",
+              "acr_tune_clear"):
+        getattr(lib, n).restype = ctypes.c_int
+    return lib
+
+
+def acr_tune_record(on: bool = True):
+    """Start or stop noting the shape keys the library meets (autotuner)."""
+    _check(_tune_lib().acr_tune_record(1 if on else 0))
+
+
+def acr_tune_run(stream=None) -> int:
+    """Measure every noted key without a table entry; returns the entries added."""
+    n = ctypes.c_int32(0)
+    _check(_tune_lib().acr_tune_run(_stream(stream), ctypes.byref(n)))
+    return n.value
+
+
+def acr_tune_enable(on: bool = True):
+    _check(_tune_lib().acr_tune_enable(1 if on else 0))
+
+
+def acr_tune_save(path):
+    _check(_tune_lib().acr_tune_save(os.fsencode(str(path))))
+
+
+def acr_tune_load(path):
+    _check(_tune_lib().acr_tune_load(os.fsencode(str(path))))
+
+
+def acr_tune_clear():
+    _check(_tune_lib().acr_tune_clear())

@@ -825,6 +825,15 @@ namespace {
 
 bool overlap(const double* a, const double* b, size_t n) { return overlap2(a, n, b, n); }
 
+// Architecture name of the current device (the tuning table's key).
+std::string device_arch() {
+  int dev = 0;
+  ACR_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t pr;
+  ACR_HIP(hipGetDeviceProperties(&pr, dev));
+  return std::string(pr.gcnArchName);
+}
+
 template <typename T>
 void solve_batched_t(const acr_handle* hs, const double* const* B, double* const* X, const int32_t* nrhs,
                      int count, int precision, hipStream_t st) {
@@ -1255,6 +1264,101 @@ acr_status acr_profile_report(char* buf, int64_t len, int64_t* needed) {
 }
 
 int64_t acr_launch_count(void) { return (int64_t)launch_count(); }
+
+acr_status acr_tune_record(int32_t on) {
+  return guard([&] { Tuner::get().recording = on != 0; });
+}
+
+acr_status acr_tune_run(void* stream, int32_t* added) {
+  return guard([&] {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope ss(st);
+    const int n = tune_run(st);
+    if (added) *added = n;
+  });
+}
+
+acr_status acr_tune_enable(int32_t on) {
+  return guard([&] { Tuner::get().active = on != 0; });
+}
+
+acr_status acr_tune_save(const char* path) {
+  return guard([&] {
+    if (!path) fail(ACR_ERR_INVALID_ARG, "NULL path");
+    Tuner& t = Tuner::get();
+    std::string out = "{\n  \"arch\": \"" + device_arch() + "\",\n  \"entries\": {";
+    {
+      std::lock_guard<std::mutex> g(t.mu);
+      bool first = true;
+      for (auto& kv : t.table) {
+        out += std::string(first ? "\n" : ",\n") + "    \"" + kv.first + "\": " + std::to_string(kv.second);
+        first = false;
+      }
+    }
+    out += "\n  }\n}\n";
+    FILE* f = std::fopen(path, "w");
+    if (!f) fail(ACR_ERR_INVALID_ARG, std::string("cannot write ") + path);
+    const size_t w = std::fwrite(out.data(), 1, out.size(), f);
+    std::fclose(f);
+    if (w != out.size()) fail(ACR_ERR_INVALID_ARG, std::string("short write to ") + path);
+  });
+}
+
+acr_status acr_tune_load(const char* path) {
+  return guard([&] {
+    if (!path) fail(ACR_ERR_INVALID_ARG, "NULL path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) fail(ACR_ERR_INVALID_ARG, std::string("cannot read ") + path);
+    std::string txt;
+    char buf[4096];
+    size_t r;
+    while ((r = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, r);
+    std::fclose(f);
+    // a flat JSON object: "arch": "<name>", "entries": {"<key>": <int>, ...}
+    auto str_after = [&](size_t pos, size_t* end) {
+      const size_t a = txt.find('"', pos);
+      const size_t b = a == std::string::npos ? a : txt.find('"', a + 1);
+      if (b == std::string::npos) fail(ACR_ERR_INVALID_ARG, "malformed tuning file");
+      *end = b + 1;
+      return txt.substr(a + 1, b - a - 1);
+    };
+    const size_t ka = txt.find("\"arch\"");
+    if (ka == std::string::npos) fail(ACR_ERR_INVALID_ARG, "tuning file without \"arch\"");
+    size_t e = 0;
+    const std::string arch = str_after(txt.find(':', ka) + 1, &e);
+    if (arch != device_arch())
+      fail(ACR_ERR_INVALID_ARG, "tuning file is for " + arch + ", this device is " + device_arch());
+    const size_t ke = txt.find("\"entries\"");
+    if (ke == std::string::npos) fail(ACR_ERR_INVALID_ARG, "tuning file without \"entries\"");
+    size_t pos = txt.find('{', ke);
+    const size_t close = txt.find('}', pos);
+    if (pos == std::string::npos || close == std::string::npos) fail(ACR_ERR_INVALID_ARG, "malformed tuning file");
+    std::map<std::string, int> table;
+    for (;;) {
+      const size_t q = txt.find('"', pos);
+      if (q == std::string::npos || q > close) break;
+      const std::string key = str_after(q, &e);
+      const size_t colon = txt.find(':', e);
+      if (colon == std::string::npos || colon > close) fail(ACR_ERR_INVALID_ARG, "malformed tuning file");
+      table[key] = std::atoi(txt.c_str() + colon + 1);
+      pos = colon + 1;
+    }
+    Tuner& t = Tuner::get();
+    std::lock_guard<std::mutex> g(t.mu);
+    t.table.swap(table);
+    t.active = true;
+  });
+}
+
+acr_status acr_tune_clear(void) {
+  return guard([&] {
+    Tuner& t = Tuner::get();
+    std::lock_guard<std::mutex> g(t.mu);
+    t.table.clear();
+    t.seen.clear();
+    t.active = false;
+  });
+}
 
 acr_status acr_trim_pool(void) {
   return guard([&] { Pool::get().trim(); });

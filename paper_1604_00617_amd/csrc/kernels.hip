@@ -2803,6 +2803,45 @@ const J* upload(const std::vector<J>& v, hipStream_t st) {
 
 }  // namespace
 
+// ------------------------------------------------------------- autotuner
+// Choices of kernel variant per shape key, measured on the device (see
+// tune_run) and kept in a table that can be saved and loaded as JSON for one
+// GPU architecture.  Keys hold shapes only, never anything about the other
+// problems of a call, so a problem's result does not depend on what it is
+// batched with:
+//   "gemm.<f|d>.<M>.<N>.<Kbits>.<Pbits>"  tile shape of the grouped GEMM
+//       (k_ggemm's five tiles; they give the same bits, each output sums its
+//       K terms in the same order whatever the tile): kind 0..4;
+//   "qr.<f|d>.<p>.<k>"  Householder QR form of a p x k panel: 4 one wave,
+//       2 registers of four waves, 0 LDS (the forms give different bits).
+Tuner& Tuner::get() {
+  static Tuner t;
+  return t;
+}
+
+int Tuner::lookup(const std::string& key) {
+  if (!active) return -1;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = table.find(key);
+  return it == table.end() ? -1 : it->second;
+}
+
+void Tuner::note(const std::string& key, long long nprob) {
+  if (!recording) return;
+  std::lock_guard<std::mutex> g(mu);
+  long long& v = seen[key];
+  v = std::max(v, nprob);
+}
+
+namespace {
+int bits(long long v) {
+  int b = 0;
+  while (v > 0) { ++b; v >>= 1; }
+  return b;
+}
+template <typename T> char tchar() { return sizeof(T) == 4 ? 'f' : 'd'; }
+}  // namespace
+
 // Workgroups of a grouped GEMM job: one per output tile, except for the row
 // kernel (kinds 6..8), whose workgroups take four 64-row tiles.
 long long gjob_blocks(const GJob& J) {
@@ -2814,8 +2853,9 @@ long long gjob_blocks(const GJob& J) {
 // 5 = k_gemm_dot (long-K reductions A^T B with small outputs), 6..8 =
 // k_gemm_rows with 16 / 32 / 4 columns, 9 = k_gemm_small (short-K reductions).
 template <typename T>
-void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs) {
+void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs, int force_tile) {
   constexpr int NK = 10;
+  Tuner& tuner = Tuner::get();
   std::vector<GJob> by[NK];
   double fl[NK] = {}, bytes[NK] = {};
   for (auto& J : jobs) {
@@ -2843,6 +2883,16 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
       J.tilesN = 1;
     } else {
       kind = pick_tile(J.M, J.N);
+      if (force_tile >= 0) {
+        kind = force_tile;
+      } else if (tuner.active || tuner.recording) {
+        const long long npr = (long long)J.nmat * J.ncl;
+        char key[96];
+        std::snprintf(key, sizeof key, "gemm.%c.%d.%d.%d.%d", tchar<T>(), J.M, J.N, bits((long long)K), bits(npr));
+        tuner.note(key, npr);
+        const int c = tuner.lookup(key);
+        if (c >= 0 && c <= 4) kind = c;
+      }
       J.tilesM = (J.M + kTiles[kind].tm - 1) / kTiles[kind].tm;
       J.tilesN = (J.N + kTiles[kind].tn - 1) / kTiles[kind].tn;
     }
@@ -2875,7 +2925,7 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
                                     : gjob_blocks(J);
       }
     }
-    if (kinds > 1 && total <= kSmallLaunch) {
+    if (kinds > 1 && total <= kSmallLaunch && force_tile < 0) {
       std::vector<char> blob(segs.size() * sizeof(GSeg));
       if (!segs.empty()) std::memcpy(blob.data(), segs.data(), blob.size());
       std::vector<GJob> all;
@@ -3026,7 +3076,8 @@ void binverse(hipStream_t st, int n, int nprob, const Tin* A, long long sA, Tout
 }
 
 template <typename T>
-void gqr(hipStream_t st, std::vector<QJob> jobs) {
+void gqr(hipStream_t st, std::vector<QJob> jobs, int force_form) {
+  Tuner& tuner = Tuner::get();
   // Panels that fit 64 KB of LDS share one launch; larger ones (up to the
   // 160 KB a gfx950 workgroup may hold) get a launch of their own, so that
   // the many small panels keep their occupancy; the rest work in global memory.
@@ -3052,12 +3103,27 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
     const size_t panel = (size_t)J.p * J.k * sizeof(T), vb = (size_t)J.p * sizeof(T);
     int g = 0;
     const int rows = (J.p + WAVE - 1) / WAVE, slots = (J.k + 3) / 4;
-    const int wc = wave_code(J.p, J.k);
-    if (wc >= 0) {
+    int wc = wave_code(J.p, J.k);
+    const bool reg_ok = rows <= 8 && slots <= 16 && rows * slots * sizeof(T) <= 64 * 4;
+    const bool lds_ok = panel + vb + 1024 <= kMaxLds;
+    {   // a tuned (or forced) form: one wave (4), registers (2) or LDS (0)
+      int want = force_form;
+      if (want < 0 && (tuner.active || tuner.recording) && (int)(wc >= 0) + (int)reg_ok + (int)lds_ok > 1) {
+        char key[64];
+        std::snprintf(key, sizeof key, "qr.%c.%d.%d", tchar<T>(), J.p, J.k);
+        tuner.note(key, (long long)np);
+        want = tuner.lookup(key);
+      }
+      if (want == 2 && reg_ok) wc = -1;
+      else if (want == 0 && lds_ok) wc = -2;
+    }
+    if (wc == -2) {
+      J.lds = 1;   // LDS form (g = 0)
+    } else if (wc >= 0) {
       g = 4;
       J.lds = 0;
       J.pad = wc;
-    } else if (rows <= 8 && slots <= 16 && rows * slots * sizeof(T) <= 64 * 4) {   // panel in registers
+    } else if (reg_ok) {   // panel in registers
       g = 2;
       J.lds = 0;
       J.pad = (rows <= 1 ? 0 : rows <= 2 ? 1 : rows <= 4 ? 2 : 3) * 3 + (slots <= 4 ? 0 : slots <= 8 ? 1 : 2);
@@ -3145,6 +3211,128 @@ void gqr(hipStream_t st, std::vector<QJob> jobs) {
     launch(st, KC_QR, fl[g], by[g], KNAME_T(k_gqr<T, true>), k_gqr<T, true>, dim3((unsigned)b0[g]), dim3(256),
            dyn[g], dj, nj);
   }
+}
+
+// --------------------------------------------------------- tuning runs
+namespace {
+
+// Average time of fn() (which enqueues on st) over `reps` runs after one warm-up.
+template <typename F>
+double time_on_device(hipStream_t st, int reps, F&& fn) {
+  fn();
+  queue_flush();
+  hipEvent_t a, b;
+  ACR_HIP(hipEventCreate(&a));
+  ACR_HIP(hipEventCreate(&b));
+  ACR_HIP(hipEventRecord(a, st));
+  for (int r = 0; r < reps; ++r) {
+    fn();
+    queue_flush();
+  }
+  ACR_HIP(hipEventRecord(b, st));
+  ACR_HIP(hipEventSynchronize(b));
+  float ms = 0.0f;
+  ACR_HIP(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
+
+template <typename T>
+__global__ void k_tune_fill(T* p, size_t n, unsigned seed) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    unsigned h = (unsigned)e * 2654435761u ^ seed;
+    h ^= h >> 13; h *= 0x5bd1e995u; h ^= h >> 15;
+    p[e] = (T)((double)(h & 0xffffff) / 16777216.0 - 0.5);
+  }
+}
+
+template <typename T>
+void tune_fill(hipStream_t st, T* p, size_t n, unsigned seed) {
+  launch(st, KC_OTHER, 0.0, 0.0, "k_tune_fill", k_tune_fill<T>, dim3(grid1((long long)n, 256, 4096)), dim3(256), 0,
+         p, n, seed);
+}
+
+// Fastest tile of a recorded GEMM key: M x N x K products of the key's size
+// classes on synthetic operands.
+template <typename T>
+int tune_gemm(hipStream_t st, int M, int N, int kbits, int pbits) {
+  const int K = kbits <= 1 ? 1 : (1 << (kbits - 1)) + (1 << (kbits - 1)) / 2;
+  const long long np = std::min<long long>(pbits <= 1 ? 1 : (1LL << (pbits - 1)) + (1LL << (pbits - 1)) / 2, 16384);
+  DBuf<T> A((size_t)np * M * K), B((size_t)np * K * N), C((size_t)np * M * N);
+  tune_fill<T>(st, A.get(), A.size(), 1u);
+  tune_fill<T>(st, B.get(), B.size(), 2u);
+  GSeg g;
+  g.A = bop(A.get(), M, (long long)M * K);
+  g.B = bop(B.get(), K, (long long)K * N);
+  g.K = K;
+  GJob J;
+  J.M = M; J.N = N; J.nmat = (int)np; J.ncl = 1; J.C = bop(C.get(), M, (long long)M * N); J.seg0 = 0; J.nseg = 1;
+  int best = -1;
+  double bt = 1e300;
+  for (int kind = 0; kind < 5; ++kind) {
+    const double t = time_on_device(st, 5, [&] { ggemm<T>(st, {J}, {g}, kind); });
+    if (t < bt) { bt = t; best = kind; }
+  }
+  return best;
+}
+
+// Fastest QR form of a recorded panel key among the forms it allows.
+template <typename T>
+int tune_qr(hipStream_t st, int p, int k, long long nprob) {
+  const long long np = std::max<long long>(1, std::min<long long>(nprob, 8192));
+  const int c = std::min(p, k);
+  DBuf<T> A((size_t)np * p * k), R((size_t)np * c * k), V((size_t)np * p * c), tau((size_t)np * c);
+  tune_fill<T>(st, A.get(), A.size(), 3u);
+  QJob J;
+  J.p = p; J.k = k; J.nmat = (int)np; J.ncl = 1; J.A = bop(A.get(), p, (long long)p * k);
+  J.R = R.get(); J.Vref = V.get(); J.tau = tau.get();
+  int best = -1;
+  double bt = 1e300;
+  for (int form : {4, 2, 0}) {
+    const double t = time_on_device(st, 5, [&] { gqr<T>(st, {J}, form); });
+    if (t < bt) { bt = t; best = form; }
+  }
+  return best;
+}
+
+}  // namespace
+
+int tune_run(hipStream_t st) {
+  Tuner& tu = Tuner::get();
+  std::map<std::string, long long> keys;
+  {
+    std::lock_guard<std::mutex> g(tu.mu);
+    keys = tu.seen;
+  }
+  const bool was = tu.active;
+  tu.active = false;   // measure the forms themselves
+  int n = 0;
+  try {
+    for (auto& kv : keys) {
+      {
+        std::lock_guard<std::mutex> g(tu.mu);
+        if (tu.table.count(kv.first)) continue;
+      }
+      char t = 0;
+      int a = 0, b = 0, c = 0, d = 0;
+      int choice = -1;
+      if (std::sscanf(kv.first.c_str(), "gemm.%c.%d.%d.%d.%d", &t, &a, &b, &c, &d) == 5) {
+        choice = t == 'f' ? tune_gemm<float>(st, a, b, c, d) : tune_gemm<double>(st, a, b, c, d);
+      } else if (std::sscanf(kv.first.c_str(), "qr.%c.%d.%d", &t, &a, &b) == 3) {
+        choice = t == 'f' ? tune_qr<float>(st, a, b, kv.second) : tune_qr<double>(st, a, b, kv.second);
+      }
+      if (choice < 0) continue;
+      std::lock_guard<std::mutex> g(tu.mu);
+      tu.table[kv.first] = choice;
+      ++n;
+    }
+  } catch (...) {
+    tu.active = was;
+    throw;
+  }
+  tu.active = was;
+  return n;
 }
 
 template <typename T>
@@ -3853,12 +4041,12 @@ void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
   template void grank1_factors<T>(hipStream_t, std::vector<OpJob>);                                \
   template void ggather_diag<T>(hipStream_t, std::vector<OpJob>);                                  \
   template void gbuild_capacitance<T>(hipStream_t, std::vector<CapJob>);                           \
-  template void ggemm<T>(hipStream_t, std::vector<GJob>, const std::vector<GSeg>&);               \
+  template void ggemm<T>(hipStream_t, std::vector<GJob>, const std::vector<GSeg>&, int);          \
   template void ghmv<T>(hipStream_t, int, int, int, int, std::vector<MVJob>, const std::vector<MVTerm>&); \
   template void ghmv<T>(hipStream_t, std::vector<MVJob>, const std::vector<MVTerm>&);              \
   template void gto_blocks<T>(hipStream_t, std::vector<VJob>);                                     \
   template void gfrom_blocks<T>(hipStream_t, std::vector<VJob>);                                   \
-  template void gqr<T>(hipStream_t, std::vector<QJob>);                                           \
+  template void gqr<T>(hipStream_t, std::vector<QJob>, int);                                      \
   template void grsvd<T>(hipStream_t, std::vector<SJob>);                                         \
   template void gapply_q<T>(hipStream_t, std::vector<AJob>);                                      \
   template void gtrunc<T>(hipStream_t, std::vector<TJob>);                                        \

@@ -3,6 +3,9 @@
 // p = m*ncl + c (matrix m, cluster c) unless stated otherwise.
 #pragma once
 
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -226,10 +229,26 @@ struct CapJob {
 template <typename T>
 void gbuild_capacitance(hipStream_t st, std::vector<CapJob> jobs);
 
+// force_tile (0..4) / force_form (4 one wave, 2 registers, 0 LDS) bypass the
+// tuned or built-in choice (tuning runs).
 template <typename T>
-void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs);
+void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs, int force_tile = -1);
 template <typename T>
-void gqr(hipStream_t st, std::vector<QJob> jobs);
+void gqr(hipStream_t st, std::vector<QJob> jobs, int force_form = -1);
+
+// Kernel-variant table of the autotuner (see kernels.hip): key -> choice.
+struct Tuner {
+  std::mutex mu;
+  std::map<std::string, int> table;        // measured choices
+  std::map<std::string, long long> seen;   // keys met while recording (largest problem count)
+  bool active = false;                     // use the table
+  bool recording = false;                  // note the keys met
+  static Tuner& get();
+  int lookup(const std::string& key);
+  void note(const std::string& key, long long nprob);
+};
+// Measure every recorded key that has no entry yet; returns how many were added.
+int tune_run(hipStream_t st);
 template <typename T>
 void grsvd(hipStream_t st, std::vector<SJob> jobs);
 template <typename T>

@@ -141,38 +141,59 @@ void finish(acr_server_s* S, Request* r, acr_status status, const std::string& e
   S->cv_done.notify_all();
 }
 
-// Admit pending requests whose factor is (or can be made) resident.
+// Admit pending requests whose factor is (or can be made) resident.  Order of
+// the operators to factor: those whose oldest request has waited longer than
+// kStarveMs first (oldest first), then by the number of requests waiting for
+// them.  A resident factor that pending requests wait for is evicted only to
+// make room for a starving operator, so factors are reused by the requests
+// they were made for instead of being recomputed.
+constexpr double kStarveMs = 250.0;
+
 void admit(acr_server_s* S) {
   hipStream_t st = S->st;
-  std::vector<int> need;   // operators to factor, in order of first request
+  const auto now = Clock::now();
+  struct Need {
+    int op;
+    int count = 0;
+    double wait_ms = 0.0;
+  };
+  std::vector<Need> need;
+  std::vector<int> wanted(S->ops.size(), 0);
   for (auto& r : S->pending) {
+    ++wanted[r->op];
     OpEntry& E = *S->ops[r->op];
-    if (!E.factor && std::find(need.begin(), need.end(), r->op) == need.end()) need.push_back(r->op);
+    if (E.factor) continue;
+    const double w = std::chrono::duration<double, std::milli>(now - r->t0).count();
+    auto it = std::find_if(need.begin(), need.end(), [&](const Need& n) { return n.op == r->op; });
+    if (it == need.end()) {
+      need.push_back(Need{r->op, 1, w});
+    } else {
+      ++it->count;
+      it->wait_ms = std::max(it->wait_ms, w);
+    }
   }
+  std::stable_sort(need.begin(), need.end(), [](const Need& a, const Need& b) {
+    const bool sa = a.wait_ms > kStarveMs, sb = b.wait_ms > kStarveMs;
+    if (sa != sb) return sa;
+    if (sa) return a.wait_ms > b.wait_ms;
+    return a.count > b.count;
+  });
   std::vector<int> go;     // operators that fit now
   size_t planned = 0;
-  for (int o : need) {
-    OpEntry& E = *S->ops[o];
+  const size_t budget = (size_t)S->cfg.memory_budget;
+  for (const Need& nd : need) {
+    OpEntry& E = *S->ops[nd.op];
     const size_t want = E.est;
-    size_t budget = (size_t)S->cfg.memory_budget;
+    const bool starving = nd.wait_ms > kStarveMs;
     while (S->resident + planned + want > budget) {
-      // evict the least recently used resident factor that no active request
-      // uses, preferring those no pending request waits for; its memory goes
-      // back to this thread's pool for this stream, so later work reuses it
-      // in stream order after every step that read it
+      // least recently used idle factor; one that requests wait for only for a
+      // starving operator.  Its memory goes back to this thread's pool for this
+      // stream, so later work reuses it in stream order after the steps that read it.
       int victim = -1;
-      bool victim_wanted = true;
       for (size_t i = 0; i < S->ops.size(); ++i) {
         OpEntry& V = *S->ops[i];
-        if (!V.factor || V.users > 0) continue;
-        bool wanted = false;
-        for (auto& r : S->pending) wanted = wanted || r->op == (int)i;
-        const bool better = victim < 0 || (victim_wanted && !wanted) ||
-                            (victim_wanted == wanted && V.last_use < S->ops[victim]->last_use);
-        if (better) {
-          victim = (int)i;
-          victim_wanted = wanted;
-        }
+        if (!V.factor || V.users > 0 || (wanted[i] && !starving)) continue;
+        if (victim < 0 || V.last_use < S->ops[victim]->last_use) victim = (int)i;
       }
       if (victim < 0) break;
       OpEntry& V = *S->ops[victim];
@@ -183,7 +204,7 @@ void admit(acr_server_s* S) {
       ++S->evictions;
     }
     if (S->resident + planned + want > budget && !(S->resident == 0 && planned == 0)) continue;
-    go.push_back(o);
+    go.push_back(nd.op);
     planned += want;
   }
   // one batched factorisation per distinct option set
@@ -344,9 +365,10 @@ void worker_main(acr_server_s* S) {
     }
     const auto t0 = Clock::now();
     try {
-      // (with nothing active every resident factor is idle and evictable, so
-      // admission always makes progress: a factor over the whole budget is
-      // admitted alone)
+      // (with nothing active every resident factor is idle; a factor that
+      // requests wait for is kept unless an operator starves, and waiting
+      // requests start to starve after kStarveMs, so admission always makes
+      // progress: a factor over the whole budget is admitted alone)
       if (!S->pending.empty()) admit(S);
       if (!S->active.empty()) step(S);
       queue_flush();
