@@ -77,6 +77,19 @@ typedef struct {
   const double* north;   /* [N] diagonal of F_i (couples block i to i+1) */
 } acr_operator;
 
+/* The block-tridiagonal operator given by dense blocks (Section 3, Eq.
+ * "system", general blocks), for small problems and tests: D_i, E_i, F_i of
+ * block row i are nx x nx column-major FP64 device arrays at D + i*nx*nx etc.
+ * (E_0 and F_(ny-1) are ignored).  Owned by the caller, read during
+ * acr_factor_dense only. */
+typedef struct {
+  int32_t nx;            /* block size s, >= 1 */
+  int32_t ny;            /* number of blocks, >= 1 */
+  const double* D;       /* [ny][nx][nx] */
+  const double* E;       /* [ny][nx][nx] */
+  const double* F;       /* [ny][nx][nx] */
+} acr_dense_operator;
+
 /* Factorisation options.
  * The block size nx must be leaf' * 2^L for the HODLR split to be exact: a
  * cluster of size s > leaf is split into two halves of size s/2 (so s must be
@@ -91,6 +104,12 @@ typedef struct {
   double inner_eps;      /* tolerance for intermediate truncations of the
                             products inside one Schur update (0 = accumulate
                             exactly, truncate once per stored block) */
+  int32_t stop_blocks;   /* early stop of the recursion (Section 3: it may end
+                            once the system is small enough): levels run while
+                            more than stop_blocks blocks remain (0 or 1: down
+                            to one block); the remaining m blocks are inverted
+                            as one dense (m*nx)^2 matrix in FP64 (m <= 16 and
+                            m*nx <= 1024, else ACR_ERR_INVALID_ARG) */
 } acr_options;
 
 /* Summary of a factorisation. */
@@ -114,6 +133,7 @@ typedef struct {
   double level_mean_rank[40];   /* per CR level: mean numerical rank of the
                                    stored off-diagonal blocks of X, E, F */
   int64_t factor_launches;      /* kernel launches of the factorisation */
+  int32_t stop_blocks;          /* blocks of the dense remainder (1 = none) */
 } acr_info;
 
 typedef struct acr_handle_s* acr_handle;   /* opaque; owned by the library */
@@ -129,6 +149,15 @@ typedef struct acr_handle_s* acr_handle;   /* opaque; owned by the library */
  * zero or non-finite pivot (there is no pivoting across blocks). */
 acr_status acr_factor(const acr_operator* op, const acr_options* opt, void* stream,
                       acr_handle* out);
+
+/* acr_factor for an operator of dense blocks: every block is first held as a
+ * HODLR matrix with each off-diagonal block cut to eps (the block taken as
+ * U = block, V = I and recompressed as in the factorisation), then the same
+ * level recursion runs with general (non-diagonal) E_i and F_i from level 0.
+ * The handle works with acr_solve / acr_solve_batched / acr_get_block /
+ * acr_get_info (the refinement entry points take stencil operators only).
+ * Costs O(nx^3) per block to compress; meant for small problems. */
+acr_status acr_factor_dense(const acr_dense_operator* op, const acr_options* opt, void* stream, acr_handle* out);
 
 /* Factor `count` independent problems at once (the even blocks of every
  * level are independent, Section 3; so are separate systems): ops[p] is the
@@ -216,7 +245,9 @@ acr_status acr_get_info(acr_handle h, acr_info* out);
 
 /* Copy out the stored blocks of one CR level for inspection (FP64, host
  * buffers, dense): which = 0 -> X_k of even block k (level < levels) or the
- * last inverse (level == levels, k = 0); 1 -> E_k; 2 -> F_k.  dense: host
+ * last inverse (level == levels, k = 0; after an early stop at m > 1 blocks,
+ * block (i, j) of the dense remainder inverse for k = i*m + j); 1 -> E_k;
+ * 2 -> F_k.  dense: host
  * [nx*nx] column-major.  Synchronises `stream`.  Intended for tests. */
 acr_status acr_get_block(acr_handle h, int32_t level, int32_t which, int32_t k, double* dense,
                          void* stream);

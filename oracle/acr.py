@@ -36,10 +36,16 @@ class Factor:
     eps: float
     levels: list = field(default_factory=list)   # per level: (X dict, E list, F list)
     Xlast: object = None
+    Xdense: object = None    # early stop: inverse of the remaining block-tridiagonal system
 
 
-def factor_blocks(D, E, F, leaf: int, eps: float) -> Factor:
-    """ACR reduction of dense level-0 blocks (lists of s x s arrays)."""
+def factor_blocks(D, E, F, leaf: int, eps: float, stop_blocks: int = 1) -> Factor:
+    """ACR reduction of dense level-0 blocks (lists of s x s arrays).
+
+    The recursion may stop early (Section 3: the reduction can end once the
+    system is small enough): levels run while more than ``stop_blocks`` blocks
+    remain, and the remaining block-tridiagonal system (its stored blocks) is
+    then inverted as one dense matrix, without truncation."""
     T = lambda M: hodlr.compress(M, leaf, eps)
     dn = hodlr.densify
     fac = Factor(leaf, eps)
@@ -47,7 +53,7 @@ def factor_blocks(D, E, F, leaf: int, eps: float) -> Factor:
     Dh = [T(Di) for Di in D]
     Eh = [T(Ei) for Ei in E]
     Fh = [T(Fi) for Fi in F]
-    while len(Dh) > 1:
+    while len(Dh) > max(stop_blocks, 1):
         m = len(Dh)
         X, P, Q = {}, {}, {}
         for k in range(0, m, 2):
@@ -66,13 +72,24 @@ def factor_blocks(D, E, F, leaf: int, eps: float) -> Factor:
             Fn.append(T(-dn(Fh[i]) @ dn(Q[i + 1])) if i + 1 < m else T(np.zeros((s, s))))
         fac.levels.append((X, Eh, Fh))
         Dh, Eh, Fh = Dn, En, Fn
-    fac.Xlast = T(np.linalg.inv(dn(Dh[0])))
+    if len(Dh) == 1:
+        fac.Xlast = T(np.linalg.inv(dn(Dh[0])))
+    else:
+        m, s = len(Dh), dn(Dh[0]).shape[0]
+        A = np.zeros((m * s, m * s))
+        for i in range(m):
+            A[i * s:(i + 1) * s, i * s:(i + 1) * s] = dn(Dh[i])
+            if i > 0:
+                A[i * s:(i + 1) * s, (i - 1) * s:i * s] = dn(Eh[i])
+            if i + 1 < m:
+                A[i * s:(i + 1) * s, (i + 1) * s:(i + 2) * s] = dn(Fh[i])
+        fac.Xdense = np.linalg.inv(A)
     return fac
 
 
-def factor(st, leaf: int, eps: float) -> Factor:
+def factor(st, leaf: int, eps: float, stop_blocks: int = 1) -> Factor:
     D, E, F = blocks(st)
-    return factor_blocks(D, E, F, leaf, eps)
+    return factor_blocks(D, E, F, leaf, eps, stop_blocks)
 
 
 def solve_blocks(fac: Factor, f_blocks):
@@ -89,7 +106,13 @@ def solve_blocks(fac: Factor, f_blocks):
                 v = v - mv(F[i], g[i + 1])
             fn.append(v)
         fs.append(fn)
-    u = [mv(fac.Xlast, fs[-1][0])]
+    if fac.Xdense is not None:   # early stop: the remaining system at once
+        fl = fs[-1]
+        s = fl[0].shape[0]
+        ud = fac.Xdense @ np.concatenate(fl, axis=0)
+        u = [ud[i * s:(i + 1) * s] for i in range(len(fl))]
+    else:
+        u = [mv(fac.Xlast, fs[-1][0])]
     for lev in range(len(fac.levels) - 1, -1, -1):
         X, E, F = fac.levels[lev]
         f = fs[lev]
@@ -133,4 +156,5 @@ def stored_entries(fac: Factor) -> int:
     for X, E, F in fac.levels:
         for H in list(X.values()) + list(E) + list(F):
             tot += hodlr.stored_entries(H)
-    return tot + hodlr.stored_entries(fac.Xlast)
+    last = fac.Xdense.size if fac.Xdense is not None else hodlr.stored_entries(fac.Xlast)
+    return tot + last

@@ -43,7 +43,7 @@ class _Operator(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int32), ("eps", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("max_rank", ctypes.c_int32), ("inner_eps", ctypes.c_double)]
+                ("max_rank", ctypes.c_int32), ("inner_eps", ctypes.c_double), ("stop_blocks", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -53,7 +53,8 @@ class _Info(ctypes.Structure):
                 ("level_max_rank", ctypes.c_int32 * 40), ("factor_flops", ctypes.c_double),
                 ("solve_bytes", ctypes.c_double), ("solve_flops_per_rhs", ctypes.c_double),
                 ("factor_bytes_ranked", ctypes.c_double), ("solve_bytes_ranked", ctypes.c_double),
-                ("level_mean_rank", ctypes.c_double * 40), ("factor_launches", ctypes.c_int64)]
+                ("level_mean_rank", ctypes.c_double * 40), ("factor_launches", ctypes.c_int64),
+                ("stop_blocks", ctypes.c_int32)]
 
 
 _lib = None
@@ -125,6 +126,36 @@ class Operator:
         return self.nx * self.ny
 
 
+class _DenseOperator(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("D", ctypes.c_void_p), ("E", ctypes.c_void_p), ("F", ctypes.c_void_p)]
+
+
+@dataclass
+class DenseOperator:
+    """Block-tridiagonal operator of dense blocks: D, E, F float64 device tensors of shape
+    (ny, nx, nx) holding column-major blocks (block i is D[i].T in row-major terms)."""
+    nx: int
+    ny: int
+    D: "object"
+    E: "object"
+    F: "object"
+
+    @classmethod
+    def from_blocks(cls, D, E, F, device="cuda"):
+        """D, E, F: lists of ny (nx x nx) numpy arrays."""
+        import torch
+        conv = lambda bl: torch.as_tensor(np.ascontiguousarray(np.stack([b.T for b in bl]))).to(device)
+        return cls(D[0].shape[0], len(D), conv(D), conv(E), conv(F))
+
+    def _c(self) -> _DenseOperator:
+        return _DenseOperator(self.nx, self.ny, self.D.data_ptr(), self.E.data_ptr(), self.F.data_ptr())
+
+    @property
+    def n(self):
+        return self.nx * self.ny
+
+
 class Handle:
     def __init__(self, ptr: int, op: Operator, precision: int):
         self.ptr = ptr
@@ -150,24 +181,38 @@ def _as_colmajor(B, n):
 
 
 def acr_factor(op: Operator, leaf: int, eps: float, precision="fp64", max_rank: int = 0,
-               inner_eps: float = 0.0, stream=None) -> Handle:
+               inner_eps: float = 0.0, stop_blocks: int = 1, stream=None) -> Handle:
     lib = load()
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    opt = _Options(int(leaf), float(eps), prec, int(max_rank), float(inner_eps))
+    opt = _Options(int(leaf), float(eps), prec, int(max_rank), float(inner_eps), int(stop_blocks))
     out = ctypes.c_void_p()
     _check(lib.acr_factor(ctypes.byref(op._c()), ctypes.byref(opt), _stream(stream), ctypes.byref(out)))
     return Handle(out.value, op, prec)
 
 
+def acr_factor_dense(op: "DenseOperator", leaf: int, eps: float, precision="fp64", max_rank: int = 0,
+                     stop_blocks: int = 1, stream=None) -> Handle:
+    """Factor an operator given by dense blocks (each block compressed to eps first)."""
+    lib = load()
+    lib.acr_factor_dense.argtypes = [ctypes.POINTER(_DenseOperator), ctypes.POINTER(_Options), ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_void_p)]
+    lib.acr_factor_dense.restype = ctypes.c_int
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    opt = _Options(int(leaf), float(eps), prec, int(max_rank), 0.0, int(stop_blocks))
+    out = ctypes.c_void_p()
+    _check(lib.acr_factor_dense(ctypes.byref(op._c()), ctypes.byref(opt), _stream(stream), ctypes.byref(out)))
+    return Handle(out.value, op, prec)
+
+
 def acr_factor_batched(ops, leaf: int, eps: float, precision="fp64", max_rank: int = 0,
-                       inner_eps: float = 0.0, stream=None):
+                       inner_eps: float = 0.0, stop_blocks: int = 1, stream=None):
     """Factor several independent problems in one lockstep pass; returns one Handle per operator."""
     lib = load()
     lib.acr_factor_batched.argtypes = [ctypes.POINTER(_Operator), ctypes.POINTER(_Options), ctypes.c_int32,
                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
     lib.acr_factor_batched.restype = ctypes.c_int
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    opt = _Options(int(leaf), float(eps), prec, int(max_rank), float(inner_eps))
+    opt = _Options(int(leaf), float(eps), prec, int(max_rank), float(inner_eps), int(stop_blocks))
     n = len(ops)
     arr = (_Operator * n)(*[o._c() for o in ops])
     out = (ctypes.c_void_p * n)()
@@ -438,7 +483,7 @@ class Server:
 
     def add_operator(self, op: Operator, leaf: int, eps: float, precision="mixed", max_rank: int = 0) -> int:
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        opt = _Options(int(leaf), float(eps), prec, int(max_rank), 0.0)
+        opt = _Options(int(leaf), float(eps), prec, int(max_rank), 0.0, 1)
         oid = ctypes.c_int32(0)
         _check(self._lib.acr_server_add_operator(self._ptr, ctypes.byref(op._c()), ctypes.byref(opt), ctypes.byref(oid)))
         self._ops.append(op.n)

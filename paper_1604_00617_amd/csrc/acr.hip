@@ -78,6 +78,26 @@ void Factor<T>::solve(const double* B, double* Xout, int nrhs, hipStream_t st) {
   else solve_gemm(B, Xout, nrhs, st);
 }
 
+// Last step after an early stop: output block i (padded position i + 1) of
+// U = Xd F, with F the m blocks of s x nrhs (block-major) and Xd the dense
+// (m s)^2 inverse: one K-segmented GEMM job, cluster = output block, segment
+// = input block.
+template <typename T>
+void plan_dense_last(GemmPlan& plan, const Factor<T>& f, const T* F, T* U, int nrhs) {
+  const int m = f.mstop, s = f.nx, n = m * s;
+  const long long blk = (long long)s * nrhs;
+  if (m > kMaxSeg) fail(ACR_ERR_INVALID_ARG, "early stop keeps at most 16 blocks");
+  std::vector<GSeg> sg;
+  for (int j = 0; j < m; ++j) {
+    GSeg g;
+    g.A = bop(f.Xd.get() + (size_t)j * s * n, n, 0, s);   // rows of output block i, columns of block j
+    g.B = bop(F + j * blk, s, 0, 0);
+    g.K = s;
+    sg.push_back(g);
+  }
+  plan.add(s, nrhs, 1, m, 1.0, 0.0, bop(U + blk, s, 0, blk), sg);
+}
+
 // Few right-hand sides (<= 8 per problem): every step of a level is one
 // multi-term matvec, for all problems at once (levels counted from the top
 // going down, from each problem's last level going up).  U[l] holds the
@@ -161,15 +181,25 @@ void solve_fused_many(const std::vector<const Factor<T>*>& fs, const std::vector
     PhaseScope ph("solve last", -1);
     std::vector<MVTerm> tm;
     std::vector<MVJob> jb;
+    GemmPlan dense;
     for (int p = 0; p < P; ++p) {
       PV& v = pv[p];
+      const Factor<T>& f = *fs[p];
+      if (f.mstop > 1) {   // u = Xd f over the remaining blocks; zero pads
+        v.U[v.nl].resize((size_t)(f.mstop + 2) * v.blk);
+        plan_dense_last<T>(dense, f, v.F[v.nl].get(), v.U[v.nl].get(), nrs[p]);
+        jb.push_back(job(p, 1, v.U[v.nl].get(), 1, 0, 0, 0));
+        jb.push_back(job(p, 1, v.U[v.nl].get(), 1, f.mstop + 1, 0, 0));
+        continue;
+      }
       v.U[v.nl].resize(3 * v.blk);
       const int t = (int)tm.size();
-      tm.push_back(mv_hodlr<T>(fs[p]->Xlast, 1, 0, v.F[v.nl].get(), 1, 0, 1.0));
+      tm.push_back(mv_hodlr<T>(f.Xlast, 1, 0, v.F[v.nl].get(), 1, 0, 1.0));
       jb.push_back(job(p, 1, v.U[v.nl].get(), 1, 1, t, 1));
       jb.push_back(job(p, 2, v.U[v.nl].get(), 2, 0, t, 0));
     }
     ghmv<T>(st, jb, tm);
+    dense.run<T>(st);
   }
   for (int l = maxl - 1; l >= 0; --l) {
     PhaseScope ph("solve backward", l);
@@ -261,11 +291,19 @@ void Factor<T>::solve_gemm(const double* B, double* Xout, int nrhs, hipStream_t 
               vflat(F[l + 1].get(), s, nrhs));
     }
   }
-  // final block; U[l] holds level-l unknowns with one zero pad block at each end
-  U[nl].resize(3 * blk);
-  fill<T>(st, U[nl].get(), 3 * blk, T(0));
-  hmul<T>(st, HV<T>{&Xlast, 1, 0}, 1, 0, false, nrhs, T(1), vflat(F[nl].get(), s, nrhs), T(0),
-          vflat(U[nl].get() + blk, s, nrhs));
+  // final block(s); U[l] holds level-l unknowns with one zero pad block at each end
+  if (mstop > 1) {
+    U[nl].resize((size_t)(mstop + 2) * blk);
+    fill<T>(st, U[nl].get(), (size_t)(mstop + 2) * blk, T(0));
+    GemmPlan dense;
+    plan_dense_last<T>(dense, *this, F[nl].get(), U[nl].get(), nrhs);
+    dense.run<T>(st);
+  } else {
+    U[nl].resize(3 * blk);
+    fill<T>(st, U[nl].get(), 3 * blk, T(0));
+    hmul<T>(st, HV<T>{&Xlast, 1, 0}, 1, 0, false, nrhs, T(1), vflat(F[nl].get(), s, nrhs), T(0),
+            vflat(U[nl].get() + blk, s, nrhs));
+  }
   for (int l = nl - 1; l >= 0; --l) {
     const Level<T>& L_ = lev[l];
     const int m = L_.m, nodd = m / 2;
@@ -354,7 +392,7 @@ void stage_check(hipStream_t st, const HSet<T>& H, const int* status, const char
 // it is factored alone or in a batch.
 template <typename T>
 std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operator>& ops, const acr_options& opt,
-                                                    hipStream_t st) {
+                                                    hipStream_t st, const acr_dense_operator* dense) {
   const int P = (int)ops.size();
   const double eps = opt.eps;
   const double ieps = opt.inner_eps;
@@ -370,6 +408,15 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
   };
   std::vector<std::unique_ptr<Factor<T>>> out(P);
   std::vector<PS> ps(P);
+  const int stop = std::max(opt.stop_blocks, 1);
+  for (int p = 0; p < P; ++p) {
+    int m = ops[p].ny;
+    while (m > stop) m /= 2;
+    if (m > 1 && ((long long)m * ops[p].nx > 1024 || m > kMaxSeg))
+      fail(ACR_ERR_INVALID_ARG, "stop_blocks leaves a dense remainder of " + std::to_string(m) + " blocks of " +
+                                    std::to_string(ops[p].nx) + " (at most 16 blocks and 1024 unknowns)" +
+                                    (P > 1 ? " in problem " + std::to_string(p) : std::string()));
+  }
   for (int p = 0; p < P; ++p) {
     out[p] = std::make_unique<Factor<T>>();
     Factor<T>& f = *out[p];
@@ -386,6 +433,50 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
   }
   DBuf<int> status(P);   // per problem: a bad pivot in one of its inverses
   memset_async(status.get(), 0, (size_t)P * sizeof(int), st);
+  if (dense) {
+    // dense blocks: full-rank HODLR form, each off-diagonal block cut to eps;
+    // E_i and F_i are general matrices from level 0 on
+    PS& q = ps[0];
+    const size_t nb = (size_t)q.ny * q.s * q.s;
+    {
+      DBuf<int> nonfin(1);
+      memset_async(nonfin.get(), 0, sizeof(int), st);
+      std::vector<NFJob> nf;
+      for (const double* a : {dense->D, dense->E, dense->F}) {
+        NFJob J;
+        J.n = (long long)nb; J.a = a; J.flag = nonfin.get();
+        nf.push_back(J);
+      }
+      gflag_nonfinite(st, nf);
+      int bad = 0;
+      read_to_host(&bad, nonfin.get(), sizeof(int), st);
+      if (bad) fail(ACR_ERR_INVALID_ARG, "the dense operator holds a NaN or infinite coefficient");
+    }
+    std::vector<HJob> hj;
+    std::vector<int> kfull(q.L + 1, 0);
+    for (int d = 1; d <= q.L; ++d) kfull[d] = q.s >> d;
+    HSet<T>* sets[3] = {&q.D, &q.E, &q.F};
+    const double* src[3] = {dense->D, dense->E, dense->F};
+    const int zm[3] = {-1, 0, q.ny - 1};
+    for (int i = 0; i < 3; ++i) {
+      HSet<T>& H = *sets[i];
+      H.alloc(st, q.ny, q.s, q.b, q.L, kfull, -1);
+      HJob J;
+      J.s = q.s; J.b = q.b; J.L = q.L; J.nmat = q.ny; J.A = src[i]; J.zm = zm[i];
+      J.lv = H.lv.get();
+      for (int d = 1; d <= q.L; ++d) {
+        J.U[d] = H.U[d].get();
+        J.V[d] = H.V[d].get();
+        H.kc[d] = kfull[d];
+      }
+      hj.push_back(J);
+    }
+    gdense_to_hodlr<T>(st, hj);
+    {
+      PhaseScope ph("compress blocks");
+      recompress_multi<T>(st, {&q.D, &q.E, &q.F}, eps, mr);
+    }
+  } else {
   {
     DBuf<int> nonfin(P);
     memset_async(nonfin.get(), 0, (size_t)P * sizeof(int), st);
@@ -441,12 +532,13 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
     grank1_factors<T>(st, rj);
     ggather_diag<T>(st, gj);
   }
+  }
 
-  bool diag = true;
+  bool diag = dense == nullptr;   // level 0 of a stencil: E_i, F_i diagonal
   for (int lvl = 0;; ++lvl) {
-    std::vector<int> act;   // problems with more than one block left
+    std::vector<int> act;   // problems with more than max(stop_blocks, 1) blocks left
     for (int p = 0; p < P; ++p)
-      if (ps[p].m > 1) act.push_back(p);
+      if (ps[p].m > stop) act.push_back(p);
     if (act.empty()) break;
     const int na = (int)act.size();
     PhaseScope lph("level", lvl);
@@ -684,10 +776,51 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
     PhaseScope ph("last inverse", -1);
     std::vector<HInvJob<T>> hj;
     std::vector<HSet<T>*> xs;
+    std::vector<DenseJob> dj;
+    std::vector<IJob> ij;
+    std::vector<DBuf<double>> dense;
     for (int p = 0; p < P; ++p) {
-      hj.push_back(HInvJob<T>{&ps[p].f->Xlast, HV<T>{&ps[p].D, 1, 0}, 1, status.get() + p});
-      xs.push_back(&ps[p].f->Xlast);
+      PS& q = ps[p];
+      if (q.m == 1) {
+        hj.push_back(HInvJob<T>{&q.f->Xlast, HV<T>{&q.D, 1, 0}, 1, status.get() + p});
+        xs.push_back(&q.f->Xlast);
+        continue;
+      }
+      // early stop: the remaining block-tridiagonal system, dense, inverted in FP64
+      const int m = q.m, s = q.s, n = m * s;
+      const bool at0 = q.f->lev.empty();   // no level ran: E, F are the level-0 diagonals
+      dense.emplace_back((size_t)n * n);
+      double* A = dense.back().get();
+      memset_async(A, 0, (size_t)n * n * sizeof(double), st);
+      auto hodlr_job = [&](const HSet<T>& H, int idx, double* o) {
+        DenseJob J;
+        J.type = 0; J.s = s; J.b = H.b; J.L = H.L; J.midx = idx; J.lv = H.lv.get(); J.out = o; J.ld = n;
+        for (int d = 1; d <= H.L; ++d) {
+          J.U[d] = H.U[d].get(); J.V[d] = H.V[d].get(); J.k[d] = H.k[d]; J.kc[d] = H.kc[d];
+        }
+        return J;
+      };
+      auto diag_job = [&](const DBuf<T>& v, int idx, double* o) {
+        DenseJob J;
+        J.type = 1; J.s = s; J.midx = idx; J.lv = v.get(); J.out = o; J.ld = n;
+        return J;
+      };
+      for (int i = 0; i < m; ++i) {
+        double* di = A + (size_t)i * s + (size_t)i * s * n;
+        dj.push_back(hodlr_job(q.D, i, di));
+        if (i > 0) dj.push_back(at0 ? diag_job(q.e0, i, di - (size_t)s * n) : hodlr_job(q.E, i, di - (size_t)s * n));
+        if (i + 1 < m) dj.push_back(at0 ? diag_job(q.f0, i, di + (size_t)s * n) : hodlr_job(q.F, i, di + (size_t)s * n));
+      }
+      q.f->mstop = m;
+      q.f->Xd.resize((size_t)n * n);
+      IJob I;
+      I.n = n; I.nprob = 1; I.A = A; I.sA = (long long)n * n; I.X = q.f->Xd.get(); I.sX = (long long)n * n;
+      I.status = status.get() + p;
+      ij.push_back(I);
+      work().inv_flops += 2.0 * (double)n * n * n;
     }
+    gdense_blocks<T>(st, dj);
+    ginverse<double, T>(st, ij);
     hinv_multi<T>(st, hj);
     recompress_multi<T>(st, xs, eps, mr);
   }
@@ -710,7 +843,8 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
 #define ACR_INST(T)                                                                                      \
   template struct Factor<T>;                                                                             \
   template std::vector<std::unique_ptr<Factor<T>>> factor_many<T>(const std::vector<acr_operator>&,      \
-                                                                  const acr_options&, hipStream_t);      \
+                                                                  const acr_options&, hipStream_t,       \
+                                                                  const acr_dense_operator*);            \
   template void solve_fused_many<T>(const std::vector<const Factor<T>*>&, const std::vector<const double*>&, \
                                     const std::vector<double*>&, const std::vector<int>&, hipStream_t);
 ACR_INST(float)
@@ -809,6 +943,7 @@ void check_options(const acr_options* opt) {
   if (!(opt->inner_eps >= 0.0)) fail(ACR_ERR_INVALID_ARG, "inner_eps must be >= 0");
   if (opt->precision != ACR_FP64 && opt->precision != ACR_MIXED_FP32) fail(ACR_ERR_INVALID_ARG, "unknown precision");
   if (opt->max_rank < 0) fail(ACR_ERR_INVALID_ARG, "max_rank must be >= 0");
+  if (opt->stop_blocks < 0) fail(ACR_ERR_INVALID_ARG, "stop_blocks must be >= 0");
 }
 
 void check_op(const acr_operator* op) {
@@ -875,6 +1010,31 @@ acr_status acr_factor(const acr_operator* op, const acr_options* opt, void* stre
     std::vector<acr_operator> ops{*op};
     if (opt->precision == ACR_FP64) h->f = std::move(factor_many<double>(ops, *opt, st)[0]);
     else h->f = std::move(factor_many<float>(ops, *opt, st)[0]);
+    *out = h.release();
+  });
+}
+
+acr_status acr_factor_dense(const acr_dense_operator* op, const acr_options* opt, void* stream, acr_handle* out) {
+  return guard([&] {
+    if (!op || !out) fail(ACR_ERR_INVALID_ARG, "NULL argument");
+    if (op->nx < 1 || op->ny < 1) fail(ACR_ERR_INVALID_ARG, "nx and ny must be >= 1");
+    if ((long long)op->nx * op->nx * op->ny > (1LL << 31)) fail(ACR_ERR_INVALID_ARG, "operator too large");
+    if (!op->D || !op->E || !op->F) fail(ACR_ERR_INVALID_ARG, "a block array is NULL");
+    check_options(opt);
+    if (hodlr_depth(op->nx, opt->leaf) < 0)
+      fail(ACR_ERR_INVALID_ARG, "block size must be leaf' * 2^L (halving exact down to the leaf)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope ss(st);
+    acr_operator shape{};
+    shape.nx = op->nx;
+    shape.ny = op->ny;
+    std::vector<acr_operator> v{shape};
+    auto h = std::make_unique<acr_handle_s>();
+    h->precision = opt->precision;
+    h->nx = op->nx;
+    h->ny = op->ny;
+    if (opt->precision == ACR_FP64) h->f = std::move(factor_many<double>(v, *opt, st, op)[0]);
+    else h->f = std::move(factor_many<float>(v, *opt, st, op)[0]);
     *out = h.release();
   });
 }

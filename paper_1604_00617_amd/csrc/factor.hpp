@@ -36,6 +36,10 @@ struct Factor final : FactorBase {
   double eps = 0;
   std::vector<Level<T>> lev;
   HSet<T> Xlast;
+  // early stop (stop_blocks): the inverse of the remaining block-tridiagonal
+  // system of mstop > 1 blocks, dense (mstop*nx)^2 column-major
+  int mstop = 1;
+  DBuf<T> Xd;
   Work work_done;
   std::vector<int> lev_rank;
   std::vector<double> lev_mean;
@@ -43,7 +47,7 @@ struct Factor final : FactorBase {
   int batch = 1;   // problems factored together (work and launches are of the batch)
 
   size_t bytes() const {
-    size_t t = Xlast.bytes();
+    size_t t = Xlast.bytes() + Xd.bytes();
     for (const auto& l : lev) {
       t += l.X.bytes() + l.E.bytes() + l.F.bytes() + l.e0.bytes() + l.f0.bytes();
     }
@@ -64,7 +68,7 @@ struct Factor final : FactorBase {
     o->factor_flops = work_done.total();
     // one solve pass reads every stored X twice (forward and back) and every
     // stored E/F once
-    double sb = 2.0 * Xlast.bytes();
+    double sb = 2.0 * Xlast.bytes() + Xd.bytes();
     double fl = 0;
     for (const auto& l : lev) {
       sb += 2.0 * l.X.bytes() + l.E.bytes() + l.F.bytes() + l.e0.bytes() + l.f0.bytes();
@@ -73,7 +77,7 @@ struct Factor final : FactorBase {
     // two flops per stored multiply-add entry read
     fl = 2.0 * sb / sizeof(T);
     o->solve_flops_per_rhs = fl;
-    double fr = Xlast.bytes_ranked(), sr = 2.0 * Xlast.bytes_ranked();
+    double fr = Xlast.bytes_ranked() + Xd.bytes(), sr = 2.0 * Xlast.bytes_ranked() + Xd.bytes();
     for (const auto& l : lev) {
       const double x = l.X.bytes_ranked(), ef = l.E.bytes_ranked() + l.F.bytes_ranked() + l.e0.bytes() + l.f0.bytes();
       fr += x + ef;
@@ -83,11 +87,21 @@ struct Factor final : FactorBase {
     o->solve_bytes_ranked = sr;
     for (size_t i = 0; i < lev_mean.size() && i < 40; ++i) o->level_mean_rank[i] = lev_mean[i];
     o->factor_launches = launches;
+    o->stop_blocks = mstop;
   }
 
   void block(int level, int which, int k, double* dense, hipStream_t st) const override {
     const int s = nx;
     if (level == (int)lev.size()) {
+      if (mstop > 1) {   // block (k / mstop, k % mstop) of the dense remainder inverse
+        if (which != 0 || k < 0 || k >= mstop * mstop) fail(ACR_ERR_INVALID_ARG, "last level: k = i*mstop + j");
+        const int i = k / mstop, j = k % mstop, n = mstop * s;
+        std::vector<T> h((size_t)n * s);
+        read_to_host(h.data(), Xd.get() + (size_t)j * s * n, h.size() * sizeof(T), st);
+        for (int c = 0; c < s; ++c)
+          for (int r = 0; r < s; ++r) dense[r + (size_t)c * s] = (double)h[(size_t)i * s + r + (size_t)c * n];
+        return;
+      }
       if (which != 0 || k != 0) fail(ACR_ERR_INVALID_ARG, "last level holds only X_0");
       densify_to_host(st, Xlast, 0, dense);
       return;
@@ -119,9 +133,11 @@ struct Factor final : FactorBase {
 };
 
 // Factor the problems ops[0..] together (see acr.hip).
+// With `dense` (then ops holds one entry giving nx, ny only) the single
+// problem's blocks come from the dense operator instead of a stencil.
 template <typename T>
 std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operator>& ops, const acr_options& opt,
-                                                    hipStream_t st);
+                                                    hipStream_t st, const acr_dense_operator* dense = nullptr);
 
 // X_p = M_p^{-1} B_p for several factors with <= 8 right-hand sides each, in
 // shared launches (see acr.hip).

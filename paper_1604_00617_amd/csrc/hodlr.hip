@@ -183,11 +183,14 @@ void hmul(hipStream_t st, HV<T> H, int nmat, int dfrom, bool trans, int ncol, T 
 // stays zero), and out = leaves(A) Y + sum_e U^A_e[rows] T_e[sibling ancestor]
 // holds every Adiag_{>d} U^B_d in its column block d.  Same for the
 // transposed side.  Stages: copies in, reductions + cores, ancestor parts,
-// copies, expansions + leaves, copies out.
+// expansions + leaves, copies out.
 template <typename T>
 void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
   GemmPlan s1, s2, s3;
-  std::vector<CJob> cin, cmid, cout;
+  // copies: cin = everything that reads only the operands (stacked inputs,
+  // and the parts of C taken over unchanged), before the products; cout =
+  // everything that reads products (ancestor parts, expanded factors), after
+  std::vector<CJob> cin, cout;
   std::vector<DBuf<T>> keep;
   struct Anc {
     int w = 0;
@@ -328,8 +331,8 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
       auto cv = [&](int c0) { return bop(C.V[d].get() + (size_t)c0 * s, s, (long long)C.k[d] * s); };
       if (O.has_d && O.D.h->kc[d]) {
         const int w = O.D.h->kc[d];
-        cmid.push_back(copy_job(s, w, nmat, 1.0, factor_op(O.D, O.D.h->U[d], d, 0), cu(col)));
-        cmid.push_back(copy_job(s, w, nmat, 1.0, factor_op(O.D, O.D.h->V[d], d, 0), cv(col)));
+        cin.push_back(copy_job(s, w, nmat, 1.0, factor_op(O.D, O.D.h->U[d], d, 0), cu(col)));
+        cin.push_back(copy_job(s, w, nmat, 1.0, factor_op(O.D, O.D.h->V[d], d, 0), cv(col)));
         col += w;
       }
       for (size_t t = 0; t < O.terms.size(); ++t) {
@@ -341,20 +344,20 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
         if (kB > 0) {   // (Adiag U^B) V^B^T: column block d of the A-side pass
           const int NB = cBo[t][L + 1];
           cout.push_back(copy_job(s, kB, nmat, 1.0, bop(outA[t] + (size_t)cBo[t][d] * s, s, (long long)NB * s), cu(col)));
-          cmid.push_back(copy_job(s, kB, nmat, 1.0, factor_op(B, bb.V[d], d, 0), cv(col)));
+          cin.push_back(copy_job(s, kB, nmat, 1.0, factor_op(B, bb.V[d], d, 0), cv(col)));
           col += kB;
         }
         if (kA > 0) {   // U^A (Bdiag^T V^A)^T: column block d of the transposed pass
           const int NA = cAo[t][L + 1];
-          cmid.push_back(copy_job(s, kA, nmat, coef, factor_op(A, a.U[d], d, 0), cu(col)));
+          cin.push_back(copy_job(s, kA, nmat, coef, factor_op(A, a.U[d], d, 0), cu(col)));
           cout.push_back(copy_job(s, kA, nmat, 1.0, bop(outB[t] + (size_t)cAo[t][d] * s, s, (long long)NA * s), cv(col)));
           col += kA;
         }
         for (int e = 1; e < d; ++e) {
           const Anc& an = anc[t][e];
           if (!an.w) continue;
-          cmid.push_back(copy_job(s, an.w, nmat, coef, with_map(bop(an.up, s, an.ups), an.upm, an.upo), cu(col)));
-          cmid.push_back(copy_job(s, an.w, nmat, 1.0, with_map(bop(an.vp, s, an.vps), an.vpm, an.vpo), cv(col)));
+          cout.push_back(copy_job(s, an.w, nmat, coef, with_map(bop(an.up, s, an.ups), an.upm, an.upo), cu(col)));
+          cout.push_back(copy_job(s, an.w, nmat, 1.0, with_map(bop(an.vp, s, an.vps), an.vpm, an.vpo), cv(col)));
           col += an.w;
         }
       }
@@ -374,7 +377,7 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
     }
     const BOp CL = bop(C.lv.get(), b, C.leaf_stride(), (long long)b * b);
     if (O.has_d)
-      cmid.push_back(copy_job((int)O.D.h->leaf_stride(), 1, nmat, 1.0,
+      cin.push_back(copy_job((int)O.D.h->leaf_stride(), 1, nmat, 1.0,
                               with_map(bop(O.D.h->lv.get(), 1, O.D.h->leaf_stride()), O.D.mmul, O.D.moff),
                               bop(C.lv.get(), 1, C.leaf_stride())));
     if (!ls.empty()) s3.add(b, b, nmat, nleaf, 1.0, O.has_d ? 1.0 : 0.0, CL, ls);
@@ -382,7 +385,6 @@ void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs) {
   gcopy<T>(st, cin);
   s1.run<T>(st);
   s2.run<T>(st);
-  gcopy<T>(st, cmid);
   s3.run<T>(st);
   gcopy<T>(st, cout);
   Queue::get().flush();   // let the device start while the host plans the next step
@@ -460,7 +462,6 @@ void hinv_multi(hipStream_t st, std::vector<HInvJob<T>>& jobs) {
     exp.run<T>(st);
     // cores c_sigma = V^M[sigma]^T a[sigma]
     GemmPlan cp;
-    std::vector<CapJob> capj;
     for (auto& pt : parts) {
       const HInvJob<T>& J = *pt.J;
       const HSet<T>& mm = *J.M.h;
@@ -471,18 +472,15 @@ void hinv_multi(hipStream_t st, std::vector<HInvJob<T>>& jobs) {
              {seg(transposed(factor_op(J.M, mm.V[d], d, pt.sd)), flat_op(fa, pt.sd), pt.sd)});
       const int npairs = nmat * ncl / 2, n2 = 2 * k;
       pt.G.resize((size_t)npairs * n2 * n2);
-      CapJob C;
-      C.k = k; C.npairs = npairs; C.cores = pt.cores.get(); C.G = pt.G.get();
-      capj.push_back(C);
     }
     cp.run<T>(st);
-    gbuild_capacitance<T>(st, capj);
-    {
+    {   // G_q^{-1}, with G_q = [[I, c_(2q+1)], [c_(2q), I]] formed from the cores as it is read
       std::vector<IJob> ij;
       for (auto& pt : parts) {
         const int npairs = pt.J->nmat * pt.ncl / 2, n2 = 2 * pt.k;
         IJob I;
-        I.n = n2; I.nprob = npairs; I.A = pt.G.get(); I.sA = (long long)n2 * n2;
+        I.n = n2; I.nprob = npairs; I.A = nullptr; I.sA = (long long)n2 * n2;
+        I.cap_k = pt.k; I.cores = pt.cores.get();
         I.X = pt.G.get(); I.sX = (long long)n2 * n2; I.status = pt.J->status;
         ij.push_back(I);
         work().inv_flops += 2.0 * n2 * n2 * n2 * npairs;
@@ -622,8 +620,8 @@ void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double 
   struct Item {
     HSet<T>* H = nullptr;
     int d = 0, sd = 0, kcol = 0, c = 0, ncl = 0, nprob = 0, kout = 0;
-    DBuf<T> Ru, Rv, Uref, Utau, K, sig, UK, Ut, Un, Vn, Cv;
-    DBuf<int> rank;
+    long long roff = 0;   // this item's ranks in the shared rank buffer
+    DBuf<T> Ru, Rv, Uref, Utau, K, sig, UK, Un, Vn, Cv;
   };
   std::vector<Item> items;
   for (HSet<T>* H : sets)
@@ -641,8 +639,12 @@ void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double 
   std::vector<QJob> qj;
   GemmPlan kp;
   std::vector<SJob> sj;
-  std::vector<MJob> mj;
-  DBuf<int> dmax(2 * items.size());
+  long long nrank = 0;
+  for (auto& it : items) {
+    it.roff = nrank;
+    nrank += it.nprob;
+  }
+  DBuf<int> ranks((size_t)nrank);
   for (size_t i = 0; i < items.size(); ++i) {
     Item& it = items[i];
     HV<T> HH{it.H, 1, 0};
@@ -667,45 +669,46 @@ void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double 
     BOp Rvb = bop(it.Rv.get(), it.c, (long long)it.ncl * c * kc, (long long)c * kc);
     kp.add(it.c, it.c, it.H->cnt, it.ncl, 1.0, 0.0, bop(it.K.get(), it.c, (long long)it.ncl * c * c, (long long)c * c),
            {seg(Rub, transposed(swapped(Rvb)), it.kcol)});
-    it.sig.resize(np * c); it.UK.resize(np * c * c); it.rank.resize(np);
+    it.sig.resize(np * c); it.UK.resize(np * c * c);
     SJob sv;
     sv.c = it.c; sv.nprob = it.nprob; sv.K = it.K.get(); sv.sig = it.sig.get(); sv.UK = it.UK.get();
-    sv.rank = it.rank.get(); sv.eps = eps; sv.maxrank = maxrank;
+    sv.rank = ranks.get() + it.roff; sv.eps = eps; sv.maxrank = maxrank;
     sj.push_back(sv);
     work().svd_flops += 6.0 * (double)c * c * c * np;
-    MJob m;
-    m.rank = it.rank.get(); m.n = it.nprob; m.out = dmax.get() + i;
-    m.sum = dmax.get() + items.size() + i;
-    mj.push_back(m);
   }
   gqr<T>(st, qj);
   kp.run<T>(st);
   grsvd<T>(st, sj);
-  gmax(st, mj);
-  std::vector<int> kout(2 * items.size());
-  read_to_host(kout.data(), dmax.get(), 2 * items.size() * sizeof(int), st);
-  // Keep s_t > eps s_1:  K = U_K S J^T,
+  // every block's numerical rank, one copy; the set's rank per depth is their maximum
+  std::vector<int> hr((size_t)nrank);
+  read_to_host(hr.data(), ranks.get(), (size_t)nrank * sizeof(int), st);
+  std::vector<long long> rsum(items.size(), 0);
+  for (size_t i = 0; i < items.size(); ++i) {
+    int mx = 0;
+    for (int q = 0; q < items[i].nprob; ++q) {
+      const int r = hr[(size_t)items[i].roff + q];
+      mx = std::max(mx, r);
+      rsum[i] += r;
+    }
+    items[i].kout = mx;
+  }
+  // Keep s_t > eps s_1:  K = U_K S J^T, with the SVD's U_K already zero past
+  // each block's rank (t columns kept: the set's maximum rank),
   //   U_new = Q_U [U_K,t; 0]          (orthonormal columns)
   //   V_new = V Ru^T U_K,t            (= Q_V J_t S_t, no inverse)
-  std::vector<TJob> tj;
   std::vector<AJob> aj;
   GemmPlan cvp, vnp;
   for (size_t i = 0; i < items.size(); ++i) {
     Item& it = items[i];
-    it.kout = kout[i];
     if (it.kout == 0) continue;
     HV<T> HH{it.H, 1, 0};
     const int s = it.H->s, c = it.c, ko = it.kout, kc = it.kcol;
     const size_t np = it.nprob;
-    it.Ut.resize(np * c * ko);
-    TJob t;
-    t.c = c; t.kout = ko; t.nprob = it.nprob; t.UK = it.UK.get(); t.rank = it.rank.get(); t.Ut = it.Ut.get();
-    tj.push_back(t);
     it.Un.resize((size_t)it.H->cnt * ko * s);
     it.Vn.resize((size_t)it.H->cnt * ko * s);
     AJob a;
     a.p = it.sd; a.c = c; a.t = ko; a.nmat = it.H->cnt; a.ncl = it.ncl; a.zxor = 0;
-    a.Vref = it.Uref.get(); a.tau = it.Utau.get(); a.Z = it.Ut.get(); a.sZ = (long long)c * ko;
+    a.Vref = it.Uref.get(); a.tau = it.Utau.get(); a.Z = it.UK.get(); a.sZ = (long long)c * c;
     a.Y = bop(it.Un.get(), s, (long long)ko * s, it.sd);
     aj.push_back(a);
     work().qr_flops += 4.0 * it.sd * c * ko * np;
@@ -713,11 +716,10 @@ void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double 
     BOp Rub = bop(it.Ru.get(), c, (long long)it.ncl * c * kc, (long long)c * kc);
     BOp Cvb = bop(it.Cv.get(), kc, (long long)it.ncl * kc * ko, (long long)kc * ko);
     cvp.add(kc, ko, it.H->cnt, it.ncl, 1.0, 0.0, Cvb,
-            {seg(transposed(Rub), bop(it.Ut.get(), c, (long long)it.ncl * c * ko, (long long)c * ko), c)});
+            {seg(transposed(Rub), bop(it.UK.get(), c, (long long)it.ncl * c * c, (long long)c * c), c)});
     vnp.add(it.sd, ko, it.H->cnt, it.ncl, 1.0, 0.0, bop(it.Vn.get(), s, (long long)ko * s, it.sd),
             {seg(factor_op(HH, it.H->V[it.d], it.d, it.sd), swapped(Cvb), kc)});
   }
-  gtrunc<T>(st, tj);
   gapply_q<T>(st, aj);
   cvp.run<T>(st);
   vnp.run<T>(st);
@@ -726,7 +728,7 @@ void recompress_multi(hipStream_t st, const std::vector<HSet<T>*>& sets, double 
     it.H->U[it.d] = std::move(it.Un);
     it.H->V[it.d] = std::move(it.Vn);
     it.H->k[it.d] = it.H->kc[it.d] = it.kout;
-    it.H->rsum[it.d] = (double)kout[items.size() + i];
+    it.H->rsum[it.d] = (double)rsum[i];
   }
   Queue::get().flush();   // let the device start while the host plans the next step
 }

@@ -116,8 +116,8 @@ struct POut {
   std::vector<PTerm<T>> terms;
 };
 
-// All outputs are planned together: four grouped GEMM launches plus one
-// grouped copy, whatever the number of outputs, terms and depths.
+// All outputs are planned together: three grouped GEMM stages and two grouped
+// copies, whatever the number of outputs, terms and depths.
 template <typename T>
 void hprod_multi(hipStream_t st, std::vector<POut<T>>& outs);
 

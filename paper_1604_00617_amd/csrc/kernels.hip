@@ -712,6 +712,20 @@ __global__ __launch_bounds__(64) void k_hmv_apply(const MVJob* __restrict__ jobs
 // is read back as X[j, p_j'] = W[p_j, j'] / d_(p_j).  The current column is
 // kept at a compile-time register position by rotating the row by 8 columns
 // after every 8 steps.
+// Entry (r, c) of matrix p of an inverse job: from A, or in capacitance
+// mode formed from the two cores of the pair p.
+template <typename Tin>
+__device__ __forceinline__ double inv_entry(const IJob& J, long long p, int r, int c) {
+  if (J.cap_k > 0) {
+    const int k = J.cap_k;
+    if ((r < k) == (c < k)) return r == c ? 1.0 : 0.0;
+    const Tin* cores = gmem(static_cast<const Tin*>(J.cores));
+    if (r < k) return (double)cores[(size_t)(2 * p + 1) * k * k + r + (size_t)(c - k) * k];   // c_(2p+1)
+    return (double)cores[(size_t)(2 * p) * k * k + (r - k) + (size_t)c * k];                  // c_(2p)
+  }
+  return (double)gmem(static_cast<const Tin*>(J.A))[p * J.sA + r + (long long)c * J.n];
+}
+
 template <typename Tin, typename Tout, int N>
 __global__ __launch_bounds__(256) void k_inverse_wave(const IJob* __restrict__ jobs, int njobs) {
   constexpr int G = WAVE / N;
@@ -728,11 +742,12 @@ __global__ __launch_bounds__(256) void k_inverse_wave(const IJob* __restrict__ j
   const int g = lane / N, r = lane % N;
   const long long p = ((long long)(blockIdx.x - Jb.block0) * 4 + wv) * G + g;
   const bool valid = p < nprob;
-  const Tin* Ap = A + (valid ? p : 0) * sA;
+  (void)A;
+  (void)sA;
   double a[N];
 #pragma unroll
   for (int c = 0; c < N; ++c)
-    a[c] = (valid && r < n && c < n) ? (double)Ap[r + (long long)c * n] : (r == c ? 1.0 : 0.0);
+    a[c] = (valid && r < n && c < n) ? inv_entry<Tin>(Jb, p, r, c) : (r == c ? 1.0 : 0.0);
   bool used = false, bad = false;
   int mystep = r;
   double mypiv = 1.0;
@@ -816,12 +831,13 @@ __global__ __launch_bounds__(256) void k_inverse(const IJob* __restrict__ jobs, 
   __shared__ int piv;
   __shared__ double pval;
   __shared__ int bad;
-  const Tin* Ap = A + (long long)p * sA;
+  (void)A;
+  (void)sA;
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
   for (int e = tid; e < n * n2; e += blockDim.x) {
     const int r = e / n2, c = e % n2;
-    W[e] = c < n ? (double)Ap[r + (long long)c * n] : (c - n == r ? 1.0 : 0.0);
+    W[e] = c < n ? inv_entry<Tin>(Jb, p, r, c) : (c - n == r ? 1.0 : 0.0);
   }
   __syncthreads();
   for (int j = 0; j < n; ++j) {
@@ -884,11 +900,12 @@ __global__ __launch_bounds__(256) void k_inverse_lds(const IJob* __restrict__ jo
   const long long sA = Jb.sA, sX = Jb.sX;
   int* const status = gmem(Jb.status);
   const int p = (int)(blockIdx.x - Jb.block0), tid = threadIdx.x;
-  const Tin* Ap = A + (long long)p * sA;
+  (void)A;
+  (void)sA;
   if (tid == 0) bad = 0;
   for (int e = tid; e < n * n; e += 256) {
     const int r = e % n, c = e / n;
-    W[r * n + c] = (double)Ap[e];
+    W[r * n + c] = inv_entry<Tin>(Jb, p, r, c);
   }
   __syncthreads();
   for (int j = 0; j < n; ++j) {
@@ -1146,11 +1163,23 @@ __global__ __launch_bounds__(256) void k_grsvd_reg(const SJob* __restrict__ jobs
         y[i] = fma(-d, v, y[i]);
       }
   }
+  // numerical rank (every lane holds every sv): keep s_i > eps s_1, capped
+  T smax = T(0);
+#pragma unroll
+  for (int i = 0; i < SV_TP; ++i) smax = sv[i] > smax ? sv[i] : smax;
+  int t = 0;
+  if (smax > T(0)) {
+    const double thr = eps * (double)smax;
+#pragma unroll
+    for (int i = 0; i < SV_TP; ++i) t += (i < tp) && ((double)sv[i] > thr);
+  }
+  if (maxrank > 0 && t > maxrank) t = maxrank;
+  // U_K in sorted order, columns past the rank zero (the truncated factor)
   T* Y = gmem(static_cast<T*>(Jb.UK)) + (size_t)prob * c * c;
   if (lane < c) {
 #pragma unroll
     for (int i = 0; i < SV_TP; ++i)
-      if (i < tp) Y[lane + (size_t)pos[i] * c] = y[i];
+      if (i < tp) Y[lane + (size_t)pos[i] * c] = pos[i] < t ? y[i] : T(0);
     for (int q = tp; q < c; ++q) Y[lane + (size_t)q * c] = T(0);
   }
   T* so = gmem(static_cast<T*>(Jb.sig)) + (size_t)prob * c;
@@ -1159,16 +1188,6 @@ __global__ __launch_bounds__(256) void k_grsvd_reg(const SJob* __restrict__ jobs
     for (int i = 0; i < SV_TP; ++i)
       if (i < tp) so[pos[i]] = sv[i];
     for (int q = tp; q < c; ++q) so[q] = T(0);
-    T smax = T(0);
-#pragma unroll
-    for (int i = 0; i < SV_TP; ++i) smax = sv[i] > smax ? sv[i] : smax;
-    int t = 0;
-    if (smax > T(0)) {
-      const double thr = eps * (double)smax;
-#pragma unroll
-      for (int i = 0; i < SV_TP; ++i) t += (i < tp) && ((double)sv[i] > thr);
-    }
-    if (maxrank > 0 && t > maxrank) t = maxrank;
     gmem(Jb.rank)[prob] = t;
     fl += 4.0 * (double)c * tp * tp;
     if (Jb.flops) gmem(Jb.flops)[prob] = fl;
@@ -1804,7 +1823,7 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
   __shared__ T snorm[CMAX];
   __shared__ int spos[CMAX];
   __shared__ double red[NW];
-  __shared__ int s_piv, s_stop, nrot;
+  __shared__ int s_piv, s_stop, nrot, s_rank;
   __shared__ double s_delta2, s_v0;
   __shared__ T s_beta;
   __shared__ double gA[GD * GD], gB[GD * GD], vA[GD * GD], vB[GD * GD];   // FP32 cores, t' <= GD: Gram matrix and rotations
@@ -2123,6 +2142,17 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
     for (int o = 0; o < c; ++o) pos += (snorm[o] > v) || (snorm[o] == v && o < q);
     spos[q] = pos;
   }
+  if (tid == 0) {   // numerical rank: keep s_i > eps s_1, capped
+    T smax = T(0);
+    for (int q = 0; q < c; ++q) smax = snorm[q] > smax ? snorm[q] : smax;
+    int t = 0;
+    if (smax > T(0)) {
+      const double thr = eps * (double)smax;
+      for (int q = 0; q < c; ++q) t += ((double)snorm[q] > thr);
+    }
+    if (maxrank > 0 && t > maxrank) t = maxrank;
+    s_rank = t;
+  }
   __syncthreads();
   // U_K = Q_K [J_X; 0] with columns in sorted order, built in the work matrix
   // X (free after the sort) when it is in LDS, else directly in UK.  Each wave
@@ -2163,64 +2193,20 @@ __global__ __launch_bounds__(NW * 64) void k_grsvd_t(const SJob* __restrict__ jo
       }
     }
   }
+  // the truncated factor: U_K columns past the rank are zero
+  __syncthreads();
+  const int t_rank = s_rank;
   if constexpr (INLDS) {
-    __syncthreads();
-    for (int e = tid; e < c * c; e += NTH) Yg[e] = Y[e];
+    for (int e = tid; e < c * c; e += NTH) Yg[e] = e / c < t_rank ? Y[e] : T(0);
+  } else {
+    for (int e = t_rank * c + tid; e < c * c; e += NTH) Yg[e] = T(0);
   }
   T* so = sig + (size_t)prob * c;
   for (int q = tid; q < c; q += NTH) so[spos[q]] = snorm[q];
   if (tid == 0) {
-    T smax = T(0);
-    for (int q = 0; q < c; ++q) smax = snorm[q] > smax ? snorm[q] : smax;
-    int t = 0;
-    if (smax > T(0)) {
-      const double thr = eps * (double)smax;
-      for (int q = 0; q < c; ++q) t += ((double)snorm[q] > thr);
-    }
-    if (maxrank > 0 && t > maxrank) t = maxrank;
-    rank[prob] = t;
+    rank[prob] = t_rank;
     fl += 4.0 * (double)c * tp * tp;
     if (flops) flops[prob] = fl;
-  }
-}
-
-template <typename T>
-__global__ void k_gtrunc(const TJob* __restrict__ jobs, int njobs) {
-  const TJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
-  const int prob = (int)(blockIdx.x - Jb.block0);
-  const int c = Jb.c, kout = Jb.kout;
-  const int t = gmem(Jb.rank)[prob];
-  const T* J = gmem(static_cast<const T*>(Jb.UK)) + (size_t)prob * c * c;
-  T* Jt = gmem(static_cast<T*>(Jb.Ut)) + (size_t)prob * c * kout;
-  for (int e = threadIdx.x; e < c * kout; e += blockDim.x) {
-    const int r = e % c, q = e / c;
-    Jt[e] = (q < t && q < c) ? J[r + (size_t)q * c] : T(0);
-  }
-}
-
-__global__ void k_gmax(const MJob* __restrict__ jobs) {
-  __shared__ int sm[256];
-  __shared__ int ss[256];
-  const MJob& Jb = jobs[blockIdx.x];
-  int mx = 0, sum = 0;
-  for (int i = threadIdx.x; i < Jb.n; i += 256) {
-    const int r = gmem(Jb.rank)[i];
-    mx = max(mx, r);
-    sum += r;
-  }
-  sm[threadIdx.x] = mx;
-  ss[threadIdx.x] = sum;
-  __syncthreads();
-  for (int s2 = 128; s2 > 0; s2 >>= 1) {
-    if (threadIdx.x < s2) {
-      sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + s2]);
-      ss[threadIdx.x] += ss[threadIdx.x + s2];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    Jb.out[0] = sm[0];
-    if (Jb.sum) Jb.sum[0] = ss[0];
   }
 }
 
@@ -2289,24 +2275,6 @@ __global__ __launch_bounds__(256) void k_zero_bytes(ZeroArgs z) {
   for (unsigned long long e = t; e < nbody; e += stride) body[e] = make_uint4(0u, 0u, 0u, 0u);
   if (t < head) p[t] = 0;
   if (t < tail) p[head + 16 * nbody + t] = 0;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_build_cap(const CapJob* __restrict__ jobs, int njobs) {
-  const CapJob& Jb = jobs[job_of(jobs, njobs, blockIdx.x)];
-  const int q = (int)(blockIdx.x - Jb.block0);
-  const int k = Jb.k, n = 2 * k;
-  const T* c0 = gmem(static_cast<const T*>(Jb.cores)) + (size_t)(2 * q) * k * k;
-  const T* c1 = c0 + (size_t)k * k;
-  T* g = gmem(static_cast<T*>(Jb.G)) + (size_t)q * n * n;
-  for (int e = threadIdx.x; e < n * n; e += 256) {
-    const int r = e % n, col = e / n;
-    T v;
-    if ((r < k) == (col < k)) v = (r == col) ? T(1) : T(0);
-    else if (r < k) v = c1[r + (size_t)(col - k) * k];      // upper-right: c_(2q+1)
-    else v = c0[(r - k) + (size_t)col * k];                  // lower-left: c_(2q)
-    g[e] = v;
-  }
 }
 
 // Level-0 leaves: the tridiagonal band of each leaf of D_i (`per` workgroups
@@ -2580,6 +2548,72 @@ __global__ void k_residual(int nx, int ny, const double* diag, const double* wes
     if (i > 0) ax += south[e] * x[e - nx];
     if (i + 1 < ny) ax += north[e] * x[e + nx];
     R[e + q * N] = B[e + q * N] - ax;
+  }
+}
+
+// Full-rank HODLR form of a dense block (see HJob): `per` workgroups per
+// matrix walk the s*s entries; entry (r, c) goes to the leaf of r when r and
+// c share it, else to U of the depth-d cluster of r (column c - sib start),
+// and every depth's V gets the identity on the sibling rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_to_hodlr(const HJob* __restrict__ jobs, int njobs) {
+  const HJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long local = blockIdx.x - J.block0;
+  const int m = (int)(local / J.per), part = (int)(local % J.per);
+  const int s = J.s, b = J.b, L = J.L;
+  const double* A = gmem(J.A) + (size_t)m * s * s;
+  const long long n = (long long)s * s;
+  for (long long e = (long long)part * 256 + threadIdx.x; e < n; e += (long long)J.per * 256) {
+    const int r = (int)(e % s), c = (int)(e / s);
+    const double a = m == J.zm ? 0.0 : A[e];
+    if (r / b == c / b) {
+      const int l = r / b;
+      gmem(static_cast<T*>(J.lv))[((size_t)m * (s / b) + l) * b * b + (r - l * b) + (size_t)(c - l * b) * b] = (T)a;
+    } else {
+      int d = 1;   // first depth at which the clusters of r and c differ
+      while (d < L && r / (s >> d) == c / (s >> d)) ++d;
+      const int sd = s >> d, q = c % sd;   // column q of U_tau, tau = cluster of r
+      gmem(static_cast<T*>(J.U[d]))[(size_t)m * sd * s + (size_t)q * s + r] = (T)a;
+    }
+    // V_tau = I on the rows of sib(tau): for every depth, V[d] column q at row c is
+    // 1 when q == c mod sd (each (c, d, q) written once: by the entry with r == 0)
+    if (r == 0) {
+      for (int d = 1; d <= L; ++d) {
+        const int sd = s >> d;
+        T* V = gmem(static_cast<T*>(J.V[d])) + (size_t)m * sd * s;
+        for (int q = 0; q < sd; ++q) V[(size_t)q * s + c] = q == c % sd ? T(1) : T(0);
+      }
+    }
+  }
+}
+
+// Dense s x s block from a HODLR matrix (or a diagonal): entry (r, c) lies in
+// the leaf of r when r and c share it, else in the off-diagonal block of the
+// first depth d at which their clusters differ: sum_q U_d[q][r] V_d[q][c].
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_blocks(const DenseJob* __restrict__ jobs, int njobs) {
+  const DenseJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long part = blockIdx.x - J.block0;
+  const int s = J.s, b = J.b, L = J.L;
+  const long long n = (long long)s * s;
+  double* out = gmem(J.out);
+  for (long long e = part * 256 + threadIdx.x; e < n; e += (long long)J.per * 256) {
+    const int r = (int)(e % s), c = (int)(e / s);
+    double v = 0.0;
+    if (J.type == 1) {
+      if (r == c) v = (double)gmem(static_cast<const T*>(J.lv))[(long long)J.midx * s + r];
+    } else if (r / b == c / b) {
+      const int l = r / b;
+      v = (double)gmem(static_cast<const T*>(J.lv))[((long long)J.midx * (s / b) + l) * b * b + (r - l * b) +
+                                                     (long long)(c - l * b) * b];
+    } else {
+      int d = 1;   // r and c lie in different leaves, so their clusters differ at some d <= L
+      while (d < L && r / (s >> d) == c / (s >> d)) ++d;
+      const T* U = gmem(static_cast<const T*>(J.U[d])) + (long long)J.midx * J.k[d] * s;
+      const T* V = gmem(static_cast<const T*>(J.V[d])) + (long long)J.midx * J.k[d] * s;
+      for (int q = 0; q < J.kc[d]; ++q) v += (double)U[r + (long long)q * s] * (double)V[c + (long long)q * s];
+    }
+    out[r + (long long)c * J.ld] = v;
   }
 }
 
@@ -3539,39 +3573,6 @@ void brsvd(hipStream_t st, int c, int nprob, T* K, T* sig, T* UK, int* rank, dou
   grsvd<T>(st, std::move(jobs));
 }
 
-template <typename T>
-void gtrunc(hipStream_t st, std::vector<TJob> jobs) {
-  std::vector<TJob> use;
-  long long b0 = 0;
-  for (auto& J : jobs) {
-    if (J.c <= 0 || J.kout <= 0 || J.nprob <= 0) continue;
-    J.block0 = b0;
-    b0 += J.nprob;
-    use.push_back(J);
-  }
-  if (use.empty()) return;
-  const TJob* dj = upload(use, st);
-  launch(st, KC_COPY, 0.0, 0.0, KNAME_T(k_gtrunc<T>), k_gtrunc<T>, dim3((unsigned)b0), dim3(256), 0, dj, (int)use.size());
-}
-
-template <typename T>
-void btrunc_coef(hipStream_t st, int c, int kout, int nprob, const T* J, const int* rank, T* Jt) {
-  std::vector<TJob> jobs(1);
-  jobs[0].c = c; jobs[0].kout = kout; jobs[0].nprob = nprob; jobs[0].UK = J; jobs[0].rank = rank; jobs[0].Ut = Jt;
-  gtrunc<T>(st, std::move(jobs));
-}
-
-void gmax(hipStream_t st, const std::vector<MJob>& jobs) {
-  if (jobs.empty()) return;
-  const MJob* dj = upload(jobs, st);
-  launch(st, KC_OTHER, 0.0, 0.0, KNAME0(k_gmax), k_gmax, dim3((unsigned)jobs.size()), dim3(256), 0, dj);
-}
-
-void bmax_int(hipStream_t st, const int* rank, int n, int* out) {
-  std::vector<MJob> jobs(1);
-  jobs[0].rank = rank; jobs[0].n = n; jobs[0].out = out;
-  gmax(st, jobs);
-}
 
 template <typename T>
 void gcopy(hipStream_t st, std::vector<CJob> jobs) {
@@ -3804,22 +3805,6 @@ void bscale(hipStream_t st, int rows, int cols, int nmat, int ncl, const BOp& X,
   gcopy<T>(st, std::move(jobs));
 }
 
-template <typename T>
-void gbuild_capacitance(hipStream_t st, std::vector<CapJob> jobs) {
-  long long b0 = 0;
-  std::vector<CapJob> use;
-  for (auto J : jobs) {
-    if (J.k <= 0 || J.npairs <= 0) continue;
-    J.block0 = b0;
-    b0 += J.npairs;
-    use.push_back(J);
-  }
-  if (use.empty()) return;
-  const CapJob* dj = upload(use, st);
-  launch(st, KC_OTHER, 0.0, 0.0, KNAME_T(k_build_cap<T>), k_build_cap<T>, dim3((unsigned)b0), dim3(256), 0, dj,
-         (int)use.size());
-}
-
 namespace {
 // Workgroups per matrix of an ingest job covering `work` elements per matrix.
 int ingest_per(long long work, int cap) { return (int)std::max(1LL, std::min<long long>((work + 255) / 256, cap)); }
@@ -3938,6 +3923,41 @@ void launch_rjobs(hipStream_t st, std::vector<RJob> jobs, int (*per)(const RJob&
 }
 }  // namespace
 
+template <typename T>
+void gdense_to_hodlr(hipStream_t st, std::vector<HJob> jobs) {
+  long long b0 = 0;
+  std::vector<HJob> use;
+  for (auto J : jobs) {
+    if (J.nmat <= 0 || J.s <= 0) continue;
+    if (J.L > kMvMaxDepth) fail(ACR_ERR_INTERNAL, "dense ingest: HODLR too deep");
+    J.per = (int)std::min<long long>(((long long)J.s * J.s + 1023) / 1024, 256);
+    J.block0 = b0;
+    b0 += (long long)J.nmat * J.per;
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  const HJob* dj = upload(use, st);
+  launch(st, KC_COPY, 0.0, 0.0, KNAME_T(k_dense_to_hodlr<T>), k_dense_to_hodlr<T>, dim3((unsigned)b0), dim3(256), 0,
+         dj, (int)use.size());
+}
+
+template <typename T>
+void gdense_blocks(hipStream_t st, std::vector<DenseJob> jobs) {
+  long long b0 = 0;
+  std::vector<DenseJob> use;
+  for (auto J : jobs) {
+    if (J.s <= 0) continue;
+    J.per = (int)std::min<long long>(((long long)J.s * J.s + 1023) / 1024, 256);
+    J.block0 = b0;
+    b0 += J.per;
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  const DenseJob* dj = upload(use, st);
+  launch(st, KC_COPY, 0.0, 0.0, KNAME_T(k_dense_blocks<T>), k_dense_blocks<T>, dim3((unsigned)b0), dim3(256), 0, dj,
+         (int)use.size());
+}
+
 void gresidual(hipStream_t st, std::vector<RJob> jobs) {
   launch_rjobs(st, std::move(jobs), [](const RJob& J) { return vec_per((long long)J.nx * J.ny); }, false,
                KNAME0(k_gresidual), k_gresidual, 64.0);
@@ -4040,16 +4060,16 @@ void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
   template void gleaves_tridiag<T>(hipStream_t, std::vector<OpJob>);                               \
   template void grank1_factors<T>(hipStream_t, std::vector<OpJob>);                                \
   template void ggather_diag<T>(hipStream_t, std::vector<OpJob>);                                  \
-  template void gbuild_capacitance<T>(hipStream_t, std::vector<CapJob>);                           \
   template void ggemm<T>(hipStream_t, std::vector<GJob>, const std::vector<GSeg>&, int);          \
   template void ghmv<T>(hipStream_t, int, int, int, int, std::vector<MVJob>, const std::vector<MVTerm>&); \
   template void ghmv<T>(hipStream_t, std::vector<MVJob>, const std::vector<MVTerm>&);              \
   template void gto_blocks<T>(hipStream_t, std::vector<VJob>);                                     \
+  template void gdense_blocks<T>(hipStream_t, std::vector<DenseJob>);                              \
+  template void gdense_to_hodlr<T>(hipStream_t, std::vector<HJob>);                                \
   template void gfrom_blocks<T>(hipStream_t, std::vector<VJob>);                                   \
   template void gqr<T>(hipStream_t, std::vector<QJob>, int);                                      \
   template void grsvd<T>(hipStream_t, std::vector<SJob>);                                         \
   template void gapply_q<T>(hipStream_t, std::vector<AJob>);                                      \
-  template void gtrunc<T>(hipStream_t, std::vector<TJob>);                                        \
   template void gcopy<T>(hipStream_t, std::vector<CJob>);                                         \
   template void bgemm<T>(hipStream_t, int, int, int, int, int, T, const BOp&, const BOp&, T,      \
                          const BOp&);                                                             \
@@ -4057,7 +4077,6 @@ void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
   template void bapply_q<T>(hipStream_t, int, int, int, int, int, const T*, const T*, const T*,   \
                             long long, int, const BOp&);                                          \
   template void brsvd<T>(hipStream_t, int, int, T*, T*, T*, int*, double, int);                   \
-  template void btrunc_coef<T>(hipStream_t, int, int, int, const T*, const int*, T*);             \
   template void bcopy<T>(hipStream_t, int, int, int, T, const BOp&, const BOp&);                  \
   template void badd<T>(hipStream_t, int, int, int, T, const BOp&, const BOp&);                   \
   template void fill<T>(hipStream_t, T*, size_t, T);                                              \
@@ -4075,6 +4094,7 @@ INST(double)
 template void binverse<double, double>(hipStream_t, int, int, const double*, long long, double*,
                                        long long, int*);
 template void ginverse<double, double>(hipStream_t, std::vector<IJob>);
+template void ginverse<double, float>(hipStream_t, std::vector<IJob>);
 template void ginverse<float, float>(hipStream_t, std::vector<IJob>);
 template void binverse<float, float>(hipStream_t, int, int, const float*, long long, float*,
                                      long long, int*);

@@ -76,23 +76,6 @@ struct AJob {
   BOp Y;
 };
 
-// Ut_p = UK_p[:, :kout] with columns >= rank_p zeroed (c x kout).
-struct TJob {
-  long long block0 = 0;
-  int c = 0, kout = 0, nprob = 0, pad = 0;
-  const void* UK = nullptr;
-  const int* rank = nullptr;
-  void* Ut = nullptr;
-};
-
-// *out = max(rank[0..n)); *sum (if set) = sum(rank[0..n)).
-struct MJob {
-  const int* rank = nullptr;
-  int* out = nullptr;
-  int* sum = nullptr;
-  int n = 0, pad = 0;
-};
-
 // dst_(m,c) (= or +=) alpha * diag? * src_(m,c), rows x cols each; optional
 // scale vector: element (r, q) is multiplied by
 // scale[(smul*m + soff)*sstride + c*scl + (sside ? q : r)].
@@ -216,18 +199,6 @@ struct NFJob {
 };
 void gflag_nonfinite(hipStream_t st, std::vector<NFJob> jobs);
 
-// Capacitance matrices of the HODLR inverse: for each parent q of a pair of
-// clusters (2q, 2q+1) with cores c_(2q), c_(2q+1) (k x k each, contiguous per
-// cluster), G_q = [[I, c_(2q+1)], [c_(2q), I]] (2k x 2k, ld 2k); jobs of one
-// call may have different k.
-struct CapJob {
-  long long block0 = 0;
-  int k = 0, npairs = 0;
-  const void* cores = nullptr;
-  void* G = nullptr;
-};
-template <typename T>
-void gbuild_capacitance(hipStream_t st, std::vector<CapJob> jobs);
 
 // force_tile (0..4) / force_form (4 one wave, 2 registers, 0 LDS) bypass the
 // tuned or built-in choice (tuning runs).
@@ -235,6 +206,40 @@ template <typename T>
 void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs, int force_tile = -1);
 template <typename T>
 void gqr(hipStream_t st, std::vector<QJob> jobs, int force_form = -1);
+
+// Full-rank HODLR form of dense s x s blocks (the dense operator ingest):
+// for matrix m (at A + m*s*s, column-major): leaves = the diagonal b x b
+// blocks; at depth d the block A[tau, sib tau] is stored as U_tau = that
+// block (sd columns, rows of tau) and V_tau = I (rows of sib tau).  U[d], V[d]
+// have sd columns per matrix (k[d] = sd).
+struct HJob {
+  long long block0 = 0;
+  int s = 0, b = 0, L = 0, nmat = 0, per = 1, zm = -1;   // matrix zm is taken as zero
+  const double* A = nullptr;
+  void* lv = nullptr;
+  void* U[kMvMaxDepth + 1] = {};
+  void* V[kMvMaxDepth + 1] = {};
+};
+template <typename T>
+void gdense_to_hodlr(hipStream_t st, std::vector<HJob> jobs);
+
+// Dense assembly of one s x s block of a block-tridiagonal system (early
+// stop): out[r + c*ld] (FP64) = entry (r, c) of matrix midx of a HODLR set
+// (type 0: leaves lv, factors U/V as in MVTerm) or diag(d) with d = lv + midx*s
+// (type 1).  `per` workgroups per block (set by the launcher).
+struct DenseJob {
+  long long block0 = 0;
+  int type = 0, s = 0, b = 0, L = 0, midx = 0, per = 1;
+  const void* lv = nullptr;
+  const void* U[kMvMaxDepth + 1] = {};
+  const void* V[kMvMaxDepth + 1] = {};
+  int k[kMvMaxDepth + 1] = {};
+  int kc[kMvMaxDepth + 1] = {};
+  double* out = nullptr;
+  long long ld = 0;
+};
+template <typename T>
+void gdense_blocks(hipStream_t st, std::vector<DenseJob> jobs);
 
 // Kernel-variant table of the autotuner (see kernels.hip): key -> choice.
 struct Tuner {
@@ -253,9 +258,6 @@ template <typename T>
 void grsvd(hipStream_t st, std::vector<SJob> jobs);
 template <typename T>
 void gapply_q(hipStream_t st, std::vector<AJob> jobs);
-template <typename T>
-void gtrunc(hipStream_t st, std::vector<TJob> jobs);
-void gmax(hipStream_t st, const std::vector<MJob>& jobs);
 template <typename T>
 void gcopy(hipStream_t st, std::vector<CJob> jobs);
 
@@ -277,7 +279,12 @@ struct IJob {
   long long sX = 0;
   int* status = nullptr;
   double* ws = nullptr;
-  int use_lds = 0, pad = 0;
+  int use_lds = 0;
+  // capacitance mode (cap_k > 0, n = 2 cap_k): matrix p is not read from A
+  // but formed from the cores c_(2p), c_(2p+1) (cap_k x cap_k each, contiguous)
+  // as [[I, c_(2p+1)], [c_(2p), I]]
+  int cap_k = 0;
+  const void* cores = nullptr;
 };
 template <typename Tin, typename Tout>
 void ginverse(hipStream_t st, std::vector<IJob> jobs);
@@ -314,12 +321,6 @@ void bapply_q(hipStream_t st, int p, int c, int t, int nmat, int ncl, const T* V
 template <typename T>
 void brsvd(hipStream_t st, int c, int nprob, T* K, T* sig, T* UK, int* rank, double eps, int maxrank);
 
-// Truncation: Jt = J[:, :kout] with columns >= rank_p zeroed (c x kout per problem).
-template <typename T>
-void btrunc_coef(hipStream_t st, int c, int kout, int nprob, const T* J, const int* rank, T* Jt);
-
-// max over rank[0..n) into *out (device int).
-void bmax_int(hipStream_t st, const int* rank, int n, int* out);
 
 // dst_m = alpha * src_m (rows x cols each; ld / stride per matrix / maps in
 // the BOps; cluster fields ignored).

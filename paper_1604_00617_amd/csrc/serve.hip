@@ -214,7 +214,8 @@ void admit(acr_server_s* S) {
     for (int o : go) {
       const acr_options& x = S->ops[o]->opt;
       const bool same = x.leaf == o0.leaf && x.eps == o0.eps && x.precision == o0.precision &&
-                        x.max_rank == o0.max_rank && x.inner_eps == o0.inner_eps;
+                        x.max_rank == o0.max_rank && x.inner_eps == o0.inner_eps &&
+                        x.stop_blocks == o0.stop_blocks;
       (same ? grp : rest).push_back(o);
     }
     std::vector<acr_operator> v;

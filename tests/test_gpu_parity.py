@@ -203,3 +203,97 @@ def test_mixed_denormal_columns_regression(gpu):
     b = W.rhs(st.n, 1, seed=5)
     x, its, rel = gpu.acr_solve_refined(h, op, torch.from_numpy(b).cuda(), tol=1e-10, maxit=30)
     assert direct.residual(st, x.cpu().numpy(), b) <= 1e-10
+
+
+@pytest.mark.parametrize("stop,rows", [(2, 19), (5, 19), (16, 19), (16, 12)])
+def test_early_stop_vs_oracle(gpu, stop, rows):
+    """stop_blocks: the recursion ends once at most `stop` blocks remain and the
+    rest is inverted densely; against the oracle with the same stop (FP64, 10 eps),
+    exact (eps = 0) against LU, and every stored block of the dense remainder."""
+    import torch
+    st = W.strip(W.varkappa(24), rows)
+    b = W.rhs(st.n, 2, seed=8)
+    eps = 1e-6
+    h = gpu.acr_factor(_op(gpu, st), 6, eps, "fp64", stop_blocks=stop)
+    x = gpu.acr_solve(h, torch.from_numpy(b).cuda()).cpu().numpy()
+    fac = OA.factor(st, 6, eps, stop_blocks=stop)
+    xo = OA.solve(fac, st, b)
+    info = gpu.acr_get_info(h)
+    m = info["stop_blocks"]
+    assert info["levels"] == len(fac.levels)
+    assert (m > 1) == (fac.Xdense is not None)
+    assert _relerr(x, xo) <= 10 * eps
+    if m > 1:
+        s = st.nx
+        for i in range(m):
+            for j in range(m):
+                ref = fac.Xdense[i * s:(i + 1) * s, j * s:(j + 1) * s]
+                got = gpu.acr_get_block(h, info["levels"], 0, i * m + j)
+                assert np.abs(got - ref).max() <= 10 * eps * np.abs(fac.Xdense).max()
+    h0 = gpu.acr_factor(_op(gpu, st), 6, 0.0, "fp64", stop_blocks=stop)
+    x0 = gpu.acr_solve(h0, torch.from_numpy(b).cuda()).cpu().numpy()
+    assert _relerr(x0, direct.solve(st, b)) < 1e-11
+    # mixed form + refinement
+    op = _op(gpu, st)
+    hm = gpu.acr_factor(op, 6, eps, "mixed", stop_blocks=stop)
+    xr, its, rel = gpu.acr_solve_refined(hm, op, torch.from_numpy(b).cuda(), tol=1e-10, maxit=30)
+    assert direct.residual(st, xr.cpu().numpy(), b) <= 1e-10
+
+
+def test_early_stop_limits(gpu):
+    st = W.varkappa(128)
+    with pytest.raises(gpu.ACRError) as ei:      # 16 blocks of 128 left: 2048 unknowns
+        gpu.acr_factor(_op(gpu, st), 32, 1e-6, "fp64", stop_blocks=16)
+    assert ei.value.name == "ACR_ERR_INVALID_ARG"
+
+
+def _dense_blocks(st, delta=0.05):
+    """Dense blocks of a stencil with smooth full (numerically low-rank off the
+    diagonal) couplings added to every D_i, E_i, F_i."""
+    D, E, F = [], [], []
+    s = st.nx
+    x = (np.arange(s) + 1.0) / (s + 1)
+    K = np.exp(-np.abs(x[:, None] - x[None, :]) * 3.0)
+    for i in range(st.ny):
+        Di, Ei, Fi = direct.block(st, i)
+        D.append(Di + delta * K)
+        E.append(Ei + 0.5 * delta * K if i > 0 else np.zeros((s, s)))
+        F.append(Fi + 0.5 * delta * K.T if i + 1 < st.ny else np.zeros((s, s)))
+    return D, E, F
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dense_operator_vs_oracle(gpu, prec):
+    """The dense-block operator kind: every block compressed to eps on the GPU,
+    then the same recursion with general E_i, F_i from level 0; against the
+    oracle on the same blocks (FP64: 10 eps; mixed: the FP32 bound)."""
+    import torch
+    from bounds import mixed_forward_bound
+    st = W.varkappa(64)
+    D, E, F = _dense_blocks(st)
+    op = gpu.DenseOperator.from_blocks(D, E, F)
+    eps = 1e-8
+    h = gpu.acr_factor_dense(op, 16, eps, prec)
+    f = W.rhs(st.n, 3, seed=9)
+    x = gpu.acr_solve(h, torch.from_numpy(f).cuda()).cpu().numpy()
+    fac = OA.factor_blocks(D, E, F, 16, eps)
+    s = st.nx
+    u = OA.solve_blocks(fac, [f[i * s:(i + 1) * s] for i in range(st.ny)])
+    xo = np.concatenate(u, axis=0)
+    e = _relerr(x, xo)
+    bound = 10 * eps if prec == "fp64" else mixed_forward_bound(eps)
+    print(f"dense operator {prec}: vs oracle {e:.2e} (bound {bound:.1e}); ranks {gpu.acr_get_info(h)['level_max_rank']}")
+    assert e <= bound
+    if prec == "fp64":
+        # the dense A u = f holds for the oracle's exact-to-eps solution
+        A = np.zeros((st.n, st.n))
+        for i in range(st.ny):
+            A[i * s:(i + 1) * s, i * s:(i + 1) * s] = D[i]
+            if i > 0:
+                A[i * s:(i + 1) * s, (i - 1) * s:i * s] = E[i]
+            if i + 1 < st.ny:
+                A[i * s:(i + 1) * s, (i + 1) * s:(i + 2) * s] = F[i]
+        xd = np.linalg.solve(A, f)
+        assert _relerr(x, xd) <= 1e-6
+        X0 = gpu.acr_get_block(h, 0, 0, 0)
+        assert np.abs(X0 - hodlr.densify(fac.levels[0][0][0])).max() <= 10 * eps * np.abs(X0).max()

@@ -257,6 +257,32 @@ def test_acr_eps0_reproduces_bcr():
     assert np.linalg.norm(x - xb) / np.linalg.norm(xb) < 1e-12
 
 
+@pytest.mark.parametrize("stop", [2, 3, 5, 40])
+def test_acr_early_stop(stop):
+    """Early stop of the recursion (Section 3: the reduction may end once the
+    system is small enough): with eps = 0 every stop point reproduces LU, and
+    stopping at or beyond the block count is a dense solve of the whole system;
+    at eps > 0 the error stays within the truncation band of the full recursion."""
+    st = W.strip(W.varkappa(24), 19)          # 19 blocks of 24: odd counts on the way down
+    b = W.rhs(st.n, 2, seed=5)
+    xl = direct.solve(st, b)
+    x0 = acr.solve(acr.factor(st, 6, 0.0, stop_blocks=stop), st, b)
+    assert np.linalg.norm(x0 - xl) / np.linalg.norm(xl) < 1e-12
+    fac = acr.factor(st, 6, 1e-6, stop_blocks=stop)
+    nblk = st.ny
+    levels = 0
+    while nblk > max(stop, 1):
+        nblk //= 2
+        levels += 1
+    assert len(fac.levels) == levels and (fac.Xdense is not None) == (nblk > 1)
+    if fac.Xdense is not None:
+        assert fac.Xdense.shape == (nblk * st.nx, nblk * st.nx)
+    x = acr.solve(fac, st, b)
+    full = acr.solve(acr.factor(st, 6, 1e-6), st, b)
+    e, ef = (np.linalg.norm(v - xl) / np.linalg.norm(xl) for v in (x, full))
+    assert e <= max(10 * ef, 1e-12)
+
+
 def test_acr_error_decreases_with_eps():
     st = W.varkappa(64, seed=W.seed_for(1, 2))
     b = W.rhs(st.n, 1)
