@@ -90,6 +90,29 @@ typedef struct {
   const double* F;       /* [ny][nx][nx] */
 } acr_dense_operator;
 
+/* A 3-D operator (Section 4, closing remarks: 3-D discretisations are block
+ * tridiagonal with one block per plane) as a 7-point stencil on an
+ * nx x ny x nz grid, unknown index (k*ny + i)*nx + j (k the plane):
+ *   (A u) = diag u + west u[j-1] + east u[j+1] + south u[i-1] + north u[i+1]
+ *           + down u[k-1] + up u[k+1].
+ * Block k is plane k (s = nx*ny unknowns): D_k its five-point operator,
+ * E_k = diag(down), F_k = diag(up); nz blocks.  Couplings that would leave
+ * the grid (west at j = 0, east at j = nx-1, south at i = 0, north at
+ * i = ny-1, down at k = 0, up at k = nz-1) are ignored.  Owned by the
+ * caller, read during the call only. */
+typedef struct {
+  int32_t nx;            /* row length of a plane, >= 1 */
+  int32_t ny;            /* rows per plane, >= 1 */
+  int32_t nz;            /* planes (blocks), >= 1 */
+  const double* diag;    /* [N] */
+  const double* west;    /* [N] couples j to j-1 */
+  const double* east;    /* [N] couples j to j+1 */
+  const double* south;   /* [N] couples i to i-1 (inside a plane) */
+  const double* north;   /* [N] couples i to i+1 (inside a plane) */
+  const double* down;    /* [N] couples plane k to k-1 */
+  const double* up;      /* [N] couples plane k to k+1 */
+} acr_operator3d;
+
 /* Factorisation options.
  * The block size nx must be leaf' * 2^L for the HODLR split to be exact: a
  * cluster of size s > leaf is split into two halves of size s/2 (so s must be
@@ -158,6 +181,19 @@ acr_status acr_factor(const acr_operator* op, const acr_options* opt, void* stre
  * acr_get_info (the refinement entry points take stencil operators only).
  * Costs O(nx^3) per block to compress; meant for small problems. */
 acr_status acr_factor_dense(const acr_dense_operator* op, const acr_options* opt, void* stream, acr_handle* out);
+
+/* acr_factor for a 3-D operator: the block size is the plane, s = nx*ny, and
+ * each D_k enters as its exact HODLR form (a leaf holds the plane operator
+ * restricted to it; an off-diagonal block is rank nx where the two clusters
+ * hold whole rows of the plane (the y couplings across the split) and rank 1
+ * inside a row (the x coupling)).  Needs s = leaf' * 2^L and, at every depth,
+ * clusters that split on row boundaries or inside one row (s/2^d a multiple
+ * of nx, or nx a multiple of s/2^(d-1)); ACR_ERR_INVALID_ARG otherwise.  The
+ * off-diagonal ranks of the inverses grow with the plane's side, which makes
+ * the method superlinear in 3-D; a coarse eps with acr_solve_krylov_3d uses
+ * the factor as a preconditioner of tunable accuracy.  The handle works with
+ * acr_solve, acr_get_block, acr_get_info and the _3d refinement calls. */
+acr_status acr_factor_3d(const acr_operator3d* op, const acr_options* opt, void* stream, acr_handle* out);
 
 /* Factor `count` independent problems at once (the even blocks of every
  * level are independent, Section 3; so are separate systems): ops[p] is the
@@ -239,6 +275,17 @@ acr_status acr_solve_krylov(acr_handle h, const acr_operator* op, const double* 
 /* R = B - A X in FP64 for the stencil operator (N x nrhs, ld = N). */
 acr_status acr_residual(const acr_operator* op, const double* X, const double* B, double* R,
                         int32_t nrhs, void* stream);
+
+/* acr_residual, acr_solve_refined and acr_solve_krylov for a 3-D operator
+ * factored with acr_factor_3d (same arguments and rules; N = nx*ny*nz). */
+acr_status acr_residual_3d(const acr_operator3d* op, const double* X, const double* B, double* R,
+                           int32_t nrhs, void* stream);
+acr_status acr_solve_refined_3d(acr_handle h, const acr_operator3d* op, const double* B, double* X,
+                                int32_t nrhs, double tol, int32_t maxit, int32_t* iters,
+                                double* relres, void* stream);
+acr_status acr_solve_krylov_3d(acr_handle h, const acr_operator3d* op, const double* B, double* X,
+                               int32_t nrhs, double tol, int32_t maxit, int32_t restart,
+                               int32_t* iters, double* relres, void* stream);
 
 /* Fill *out (host) with the factor summary. */
 acr_status acr_get_info(acr_handle h, acr_info* out);

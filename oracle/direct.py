@@ -68,3 +68,44 @@ def residual(st, x: np.ndarray, b: np.ndarray) -> float:
     b2 = b.reshape(A.shape[0], -1)
     r = b2 - A @ x2
     return float(np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(b2, axis=0)))
+
+
+# --- 3-D operators (one block per z plane; Section 4, closing remarks) ---
+
+def assemble3d(st) -> sp.csr_matrix:
+    """Sparse A from a ``workloads.Stencil3`` (unknown index (k*ny + i)*nx + j)."""
+    nx, ny = st.nx, st.ny
+    n = st.n
+    idx = np.arange(n)
+    rows, cols, vals = [idx], [idx], [st.diag]
+    offs = ((st.west, -1), (st.east, 1), (st.south, -nx), (st.north, nx), (st.down, -nx * ny), (st.up, nx * ny))
+    for arr, off in offs:
+        nz = arr != 0.0
+        r = idx[nz]
+        rows.append(r)
+        cols.append(r + off)
+        vals.append(arr[nz])
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+
+
+def blocks3d(st):
+    """Dense blocks of the block-tridiagonal form of a 3-D operator: block k is
+    the plane z = k, D_k its 5-point operator (s = nx*ny), E_k = diag(down),
+    F_k = diag(up)."""
+    s = st.nx * st.ny
+    D, E, F = [], [], []
+    for k in range(st.nz):
+        sl = slice(k * s, (k + 1) * s)
+        Dk = np.diag(st.diag[sl]) + np.diag(st.west[sl][1:], -1) + np.diag(st.east[sl][:-1], 1)
+        Dk += np.diag(st.south[sl][st.nx:], -st.nx) + np.diag(st.north[sl][:-st.nx], st.nx)
+        D.append(Dk)
+        E.append(np.diag(st.down[sl]))
+        F.append(np.diag(st.up[sl]))
+    return D, E, F
+
+
+def solve3d(st, b: np.ndarray) -> np.ndarray:
+    """x = A^{-1} b for a 3-D operator by sparse LU."""
+    A = assemble3d(st).tocsc()
+    b2 = b.reshape(A.shape[0], -1)
+    return spla.splu(A).solve(np.ascontiguousarray(b2)).reshape(b.shape)

@@ -126,6 +126,41 @@ class Operator:
         return self.nx * self.ny
 
 
+class _Operator3d(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)] + [
+        (f, ctypes.c_void_p) for f in ("diag", "west", "east", "south", "north", "down", "up")]
+
+
+@dataclass
+class Operator3d:
+    """7-point stencil operator on the device (FP64 arrays of length nx*ny*nz); as a
+    block-tridiagonal system one block per plane (block size nx*ny, nz blocks)."""
+    nx: int
+    ny: int
+    nz: int
+    diag: "object"
+    west: "object"
+    east: "object"
+    south: "object"
+    north: "object"
+    down: "object"
+    up: "object"
+
+    @classmethod
+    def from_arrays(cls, nx, ny, nz, diag, west, east, south, north, down, up, device="cuda"):
+        import torch
+        conv = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+        return cls(nx, ny, nz, *[conv(a) for a in (diag, west, east, south, north, down, up)])
+
+    def _c(self) -> _Operator3d:
+        return _Operator3d(self.nx, self.ny, self.nz, *[a.data_ptr() for a in (
+            self.diag, self.west, self.east, self.south, self.north, self.down, self.up)])
+
+    @property
+    def n(self):
+        return self.nx * self.ny * self.nz
+
+
 class _DenseOperator(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("D", ctypes.c_void_p), ("E", ctypes.c_void_p), ("F", ctypes.c_void_p)]
@@ -159,7 +194,10 @@ class DenseOperator:
 class Handle:
     def __init__(self, ptr: int, op: Operator, precision: int):
         self.ptr = ptr
-        self.nx, self.ny = op.nx, op.ny
+        if isinstance(op, Operator3d):   # block = plane
+            self.nx, self.ny = op.nx * op.ny, op.nz
+        else:
+            self.nx, self.ny = op.nx, op.ny
         self.precision = precision
 
     def __del__(self):
@@ -187,6 +225,20 @@ def acr_factor(op: Operator, leaf: int, eps: float, precision="fp64", max_rank: 
     opt = _Options(int(leaf), float(eps), prec, int(max_rank), float(inner_eps), int(stop_blocks))
     out = ctypes.c_void_p()
     _check(lib.acr_factor(ctypes.byref(op._c()), ctypes.byref(opt), _stream(stream), ctypes.byref(out)))
+    return Handle(out.value, op, prec)
+
+
+def acr_factor_3d(op: Operator3d, leaf: int, eps: float, precision="fp64", max_rank: int = 0,
+                  inner_eps: float = 0.0, stop_blocks: int = 1, stream=None) -> Handle:
+    """Factor a 3-D operator (block = plane, exact HODLR plane operators at level 0)."""
+    lib = load()
+    lib.acr_factor_3d.argtypes = [ctypes.POINTER(_Operator3d), ctypes.POINTER(_Options), ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_void_p)]
+    lib.acr_factor_3d.restype = ctypes.c_int
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    opt = _Options(int(leaf), float(eps), prec, int(max_rank), float(inner_eps), int(stop_blocks))
+    out = ctypes.c_void_p()
+    _check(lib.acr_factor_3d(ctypes.byref(op._c()), ctypes.byref(opt), _stream(stream), ctypes.byref(out)))
     return Handle(out.value, op, prec)
 
 
@@ -263,9 +315,13 @@ def acr_solve_refined(h: Handle, op: Operator, B, tol: float = 1e-10, maxit: int
     X = torch.empty_like(Bc)
     its = ctypes.c_int32(0)
     rel = ctypes.c_double(0.0)
-    code = lib.acr_solve_refined(h.ptr, ctypes.byref(op._c()), Bc.data_ptr(), X.data_ptr(), Bc.shape[0],
-                                 float(tol), int(maxit), ctypes.byref(its), ctypes.byref(rel),
-                                 _stream(stream))
+    fn = lib.acr_solve_refined
+    if isinstance(op, Operator3d):
+        fn = lib.acr_solve_refined_3d
+        fn.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Operator3d)] + lib.acr_solve_refined.argtypes[2:]
+        fn.restype = ctypes.c_int
+    code = fn(h.ptr, ctypes.byref(op._c()), Bc.data_ptr(), X.data_ptr(), Bc.shape[0],
+              float(tol), int(maxit), ctypes.byref(its), ctypes.byref(rel), _stream(stream))
     if code != 0 and (raise_on_fail or code != 4):
         _check(code)
     X = X.t()
@@ -283,9 +339,13 @@ def acr_solve_krylov(h: Handle, op: Operator, B, tol: float = 1e-10, maxit: int 
     X = torch.empty_like(Bc)
     its = ctypes.c_int32(0)
     rel = ctypes.c_double(0.0)
-    code = lib.acr_solve_krylov(h.ptr, ctypes.byref(op._c()), Bc.data_ptr(), X.data_ptr(), Bc.shape[0],
-                                float(tol), int(maxit), int(restart), ctypes.byref(its), ctypes.byref(rel),
-                                _stream(stream))
+    fn = lib.acr_solve_krylov
+    if isinstance(op, Operator3d):
+        fn = lib.acr_solve_krylov_3d
+        fn.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Operator3d)] + lib.acr_solve_krylov.argtypes[2:]
+        fn.restype = ctypes.c_int
+    code = fn(h.ptr, ctypes.byref(op._c()), Bc.data_ptr(), X.data_ptr(), Bc.shape[0],
+              float(tol), int(maxit), int(restart), ctypes.byref(its), ctypes.byref(rel), _stream(stream))
     if code != 0 and (raise_on_fail or code != 4):
         _check(code)
     X = X.t()
@@ -298,8 +358,12 @@ def acr_residual(op: Operator, X, B, stream=None):
     Xc = _as_colmajor(X, op.n)
     Bc = _as_colmajor(B, op.n)
     R = torch.empty_like(Bc)
-    _check(lib.acr_residual(ctypes.byref(op._c()), Xc.data_ptr(), Bc.data_ptr(), R.data_ptr(),
-                            Bc.shape[0], _stream(stream)))
+    fn = lib.acr_residual
+    if isinstance(op, Operator3d):
+        fn = lib.acr_residual_3d
+        fn.argtypes = [ctypes.POINTER(_Operator3d)] + lib.acr_residual.argtypes[1:]
+        fn.restype = ctypes.c_int
+    _check(fn(ctypes.byref(op._c()), Xc.data_ptr(), Bc.data_ptr(), R.data_ptr(), Bc.shape[0], _stream(stream)))
     R = R.t()
     return R.reshape(B.shape) if B.dim() == 1 else R
 

@@ -392,7 +392,8 @@ void stage_check(hipStream_t st, const HSet<T>& H, const int* status, const char
 // it is factored alone or in a batch.
 template <typename T>
 std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operator>& ops, const acr_options& opt,
-                                                    hipStream_t st, const acr_dense_operator* dense) {
+                                                    hipStream_t st, const acr_dense_operator* dense,
+                                                    const acr_operator3d* op3) {
   const int P = (int)ops.size();
   const double eps = opt.eps;
   const double ieps = opt.inner_eps;
@@ -403,6 +404,9 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
     Factor<T>* f = nullptr;
     const acr_operator* op = nullptr;
     int s = 0, ny = 0, L = 0, b = 0, m = 0;
+    int pnx = 0;                           // 3-D: a block is a plane of rows of pnx unknowns
+    const double* ys = nullptr;            // 3-D: in-plane couplings to r - pnx, r + pnx
+    const double* yn = nullptr;
     HSet<T> D, E, F;
     DBuf<T> e0, f0;
   };
@@ -430,6 +434,11 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
     q.m = q.ny;
     f.nx = q.s; f.ny = q.ny; f.leaf = opt.leaf; f.eps = eps; f.precision = opt.precision;
     f.L = q.L; f.b = q.b;
+  }
+  if (op3) {
+    ps[0].pnx = op3->nx;
+    ps[0].ys = op3->south;
+    ps[0].yn = op3->north;
   }
   DBuf<int> status(P);   // per problem: a bad pivot in one of its inverses
   memset_async(status.get(), 0, (size_t)P * sizeof(int), st);
@@ -483,7 +492,8 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
     std::vector<NFJob> nf;
     for (int p = 0; p < P; ++p) {
       const acr_operator& op = ops[p];
-      for (const double* a : {op.diag, op.west, op.east, op.south, op.north}) {
+      for (const double* a : {op.diag, op.west, op.east, op.south, op.north, ps[p].ys, ps[p].yn}) {
+        if (!a) continue;
         NFJob J;
         J.n = (long long)op.nx * op.ny; J.a = a; J.flag = nonfin.get() + p;
         nf.push_back(J);
@@ -497,16 +507,20 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
         fail(ACR_ERR_INVALID_ARG, "the operator" + (P > 1 ? " of problem " + std::to_string(p) : std::string()) +
                                       " holds a NaN or infinite coefficient");
   }
-  // level-0 operators: D_i as exact rank-1 HODLR, E_i/F_i diagonal (E_0 and
-  // F_(ny-1) are outside the grid: exact zeros)
+  // level-0 operators: D_i as exact rank-1 HODLR (3-D: the plane operator,
+  // exact ranks pnx or 1 by depth), E_i/F_i diagonal (E_0 and F_(ny-1) are
+  // outside the grid: exact zeros)
   {
-    std::vector<OpJob> lj, rj, gj;
+    std::vector<OpJob> lj, rj, pj, gj;
     for (PS& q : ps) {
       std::vector<int> k1(q.L + 1, 1);
+      if (q.pnx > 0)
+        for (int d = 1; d <= q.L; ++d) k1[d] = plane_rank(q.s, d, q.pnx);
       q.D.alloc(st, q.ny, q.s, q.b, q.L, k1, -1);
       OpJob J;
       J.s = q.s; J.b = q.b; J.L = q.L; J.nmat = q.ny;
       J.diag = q.op->diag; J.west = q.op->west; J.east = q.op->east;
+      J.pnx = q.pnx; J.south = q.ys; J.north = q.yn;
       J.out = q.D.lv.get();
       lj.push_back(J);
       if (q.L > 0) {
@@ -515,9 +529,9 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
         for (int d = 1; d <= q.L; ++d) {
           R.U[d] = q.D.U[d].get();
           R.V[d] = q.D.V[d].get();
-          q.D.kc[d] = 1;
+          q.D.kc[d] = k1[d];
         }
-        rj.push_back(R);
+        (q.pnx > 0 ? pj : rj).push_back(R);
       }
       q.e0.resize((size_t)q.ny * q.s);
       q.f0.resize((size_t)q.ny * q.s);
@@ -530,6 +544,7 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
     }
     gleaves_tridiag<T>(st, lj);
     grank1_factors<T>(st, rj);
+    gplane_factors<T>(st, pj);
     ggather_diag<T>(st, gj);
   }
   }
@@ -560,7 +575,7 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
         std::vector<int> ta;
         for (int a = 0; a < na; ++a) {
           const PS& q = ps[act[a]];
-          if (q.s > 3072) continue;
+          if (q.s > 3072 || q.pnx > 0) continue;   // closed form: tridiagonal D only
           std::vector<int> k1(q.L + 1, 1);
           lv[a].X.alloc(st, lv[a].nreal, q.s, q.b, q.L, k1, -1);
           OpJob J;
@@ -844,7 +859,8 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
   template struct Factor<T>;                                                                             \
   template std::vector<std::unique_ptr<Factor<T>>> factor_many<T>(const std::vector<acr_operator>&,      \
                                                                   const acr_options&, hipStream_t,       \
-                                                                  const acr_dense_operator*);            \
+                                                                  const acr_dense_operator*,             \
+                                                                  const acr_operator3d*);                \
   template void solve_fused_many<T>(const std::vector<const Factor<T>*>&, const std::vector<const double*>&, \
                                     const std::vector<double*>&, const std::vector<int>&, hipStream_t);
 ACR_INST(float)
@@ -954,11 +970,146 @@ void check_op(const acr_operator* op) {
     fail(ACR_ERR_INVALID_ARG, "a stencil array is NULL");
 }
 
+void check_op3(const acr_operator3d* op) {
+  if (!op) fail(ACR_ERR_INVALID_ARG, "operator is NULL");
+  if (op->nx < 1 || op->ny < 1 || op->nz < 1) fail(ACR_ERR_INVALID_ARG, "nx, ny and nz must be >= 1");
+  if ((long long)op->nx * op->ny * op->nz > (1LL << 31) || (long long)op->nx * op->ny > (1LL << 30))
+    fail(ACR_ERR_INVALID_ARG, "N too large");
+  if (!op->diag || !op->west || !op->east || !op->south || !op->north || !op->down || !op->up)
+    fail(ACR_ERR_INVALID_ARG, "a stencil array is NULL");
+}
+
 }  // namespace acr
 
 namespace {
 
 bool overlap(const double* a, const double* b, size_t n) { return overlap2(a, n, b, n); }
+
+// Iterative refinement with the factor of h as M (the body of the
+// acr_solve_refined entry points): resid(X, B, R, nrhs) sets R = B - A X.
+template <typename Resid>
+void refine_body(acr_handle h, long long n, const double* B, double* X, int nrhs, double tol, int maxit,
+                 hipStream_t st, int& its, double& rel, Resid resid) {
+  if (!h || !B || !X || nrhs < 1 || maxit < 0) fail(ACR_ERR_INVALID_ARG, "bad arguments");
+  StreamScope ss(st);
+  if (overlap(X, B, (size_t)n * nrhs)) fail(ACR_ERR_INVALID_ARG, "X must not overlap B");
+  DBuf<double> R((size_t)n * nrhs), D((size_t)n * nrhs), nb(nrhs), nr(nrhs);
+  std::vector<double> hb(nrhs), hr(nrhs);
+  col_sumsq(st, n, nrhs, B, nb.get());
+  memset_async(X, 0, (size_t)n * nrhs * sizeof(double), st);
+  copy_d2d_async(R.get(), B, (size_t)n * nrhs * sizeof(double), st);
+  read_to_host(hb.data(), nb.get(), nrhs * sizeof(double), st);
+  for (its = 0;; ++its) {
+    if (its > 0) {
+      resid(X, B, R.get(), nrhs);
+    }
+    col_sumsq(st, n, nrhs, R.get(), nr.get());
+    read_to_host(hr.data(), nr.get(), nrhs * sizeof(double), st);
+    rel = 0.0;
+    for (int q = 0; q < nrhs; ++q) {
+      const double v = hb[q] > 0 ? std::sqrt(hr[q] / hb[q]) : std::sqrt(hr[q]);
+      rel = std::max(rel, v);
+    }
+    if (!(rel > tol) || its >= maxit || !std::isfinite(rel)) break;
+    h->f->solve(R.get(), D.get(), nrhs, st);
+    axpy_d(st, n * nrhs, D.get(), X);
+  }
+  if (!(rel <= tol)) fail(ACR_ERR_NOT_CONVERGED, "refinement stopped at relative residual " + std::to_string(rel));
+}
+
+// Restarted FGMRES right-preconditioned by the factor of h (the body of the
+// acr_solve_krylov entry points): resid(x, b, r) sets r = b - A x (one column).
+template <typename Resid>
+void krylov_body(acr_handle h, long long n, const double* B, double* X, int nrhs, double tol, int maxit,
+                 int restart, hipStream_t st, int& its_all, double& rel_all, Resid resid) {
+  if (!h || !B || !X || nrhs < 1 || maxit < 0) fail(ACR_ERR_INVALID_ARG, "bad arguments");
+  if (restart < 1 || restart > 64) fail(ACR_ERR_INVALID_ARG, "restart must be in 1..64");
+  StreamScope ss(st);
+  if (overlap(X, B, (size_t)n * nrhs)) fail(ACR_ERR_INVALID_ARG, "X must not overlap B");
+  const int m = restart;
+  DBuf<double> V((size_t)(m + 1) * n), Z((size_t)m * n), R(n), zero(n), dv(2 * (m + 1) + 1);
+  memset_async(zero.get(), 0, (size_t)n * sizeof(double), st);
+  std::vector<double> hv(2 * (m + 1) + 1);
+  auto norm2 = [&](const double* v) {
+    col_sumsq(st, n, 1, v, dv.get());
+    double r = 0.0;
+    read_to_host(&r, dv.get(), sizeof(double), st);
+    return std::sqrt(r);
+  };
+  auto Aop = resid;   // r = b - A x
+  for (int q = 0; q < nrhs; ++q) {
+    const double* b = B + (size_t)q * n;
+    double* x = X + (size_t)q * n;
+    memset_async(x, 0, (size_t)n * sizeof(double), st);
+    const double bn = norm2(b);
+    int its = 0;
+    double rel = 0.0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    for (;;) {
+      Aop(x, b, R.get());
+      const double beta = norm2(R.get());
+      rel = bn > 0.0 ? beta / bn : beta;
+      if (!(rel > tol) || its >= maxit || !std::isfinite(rel)) break;
+      // V_0 = r / beta
+      copy_d2d_async(V.get(), R.get(), (size_t)n * sizeof(double), st);
+      maxpy(st, n, 0, 1.0 / beta, 0.0, nullptr, nullptr, 0, V.get());
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int k = 0;   // columns of the Hessenberg matrix built in this cycle
+      for (int j = 0; j < m && its < maxit; ++j) {
+        double* vj = V.get() + (size_t)j * n;
+        double* zj = Z.get() + (size_t)j * n;
+        double* w = V.get() + (size_t)(j + 1) * n;
+        h->f->solve(vj, zj, 1, st);   // z_j = M^{-1} v_j
+        ++its;
+        Aop(zj, zero.get(), w);        // w = -A z_j
+        // classical Gram-Schmidt twice: d = V^T w, w = -w + V d (= A z_j - V h);
+        // e = V^T w, w = w - V e; h = -d + e
+        mdot(st, n, j + 1, V.get(), n, w, dv.get());
+        maxpy(st, n, j + 1, -1.0, 1.0, dv.get(), V.get(), n, w);
+        mdot(st, n, j + 1, V.get(), n, w, dv.get() + (m + 1));
+        maxpy(st, n, j + 1, 1.0, -1.0, dv.get() + (m + 1), V.get(), n, w);
+        col_sumsq(st, n, 1, w, dv.get() + 2 * (m + 1));
+        read_to_host(hv.data(), dv.get(), hv.size() * sizeof(double), st);
+        double* hc = H.data() + (size_t)j * (m + 1);   // column j
+        for (int i = 0; i <= j; ++i) hc[i] = -hv[i] + hv[m + 1 + i];
+        const double hn = std::sqrt(std::max(hv[2 * (m + 1)], 0.0));
+        hc[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {   // earlier rotations
+          const double a = cs[i] * hc[i] + sn[i] * hc[i + 1];
+          hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+          hc[i] = a;
+        }
+        const double den = std::hypot(hc[j], hc[j + 1]);
+        cs[j] = den > 0.0 ? hc[j] / den : 1.0;
+        sn[j] = den > 0.0 ? hc[j + 1] / den : 0.0;
+        hc[j] = den;
+        hc[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        k = j + 1;
+        if (hn > 0.0) maxpy(st, n, 0, 1.0 / hn, 0.0, nullptr, nullptr, 0, w);   // v_(j+1)
+        const double est = bn > 0.0 ? std::fabs(g[j + 1]) / bn : std::fabs(g[j + 1]);
+        if (!(est > tol) || !(hn > 0.0)) break;
+      }
+      // y = H^{-1} g (upper triangular k x k), x += Z y
+      for (int i = k - 1; i >= 0; --i) {
+        double v = g[i];
+        for (int l = i + 1; l < k; ++l) v -= H[(size_t)l * (m + 1) + i] * y[l];
+        const double d = H[(size_t)i * (m + 1) + i];
+        y[i] = d != 0.0 ? v / d : 0.0;
+      }
+      if (k > 0) {
+        const double* yd = static_cast<const double*>(desc_put(y.data(), k * sizeof(double), st));
+        maxpy(st, n, k, 1.0, 1.0, yd, Z.get(), n, x);
+      }
+    }
+    its_all = std::max(its_all, its);
+    rel_all = std::max(rel_all, rel);
+  }
+  if (!(rel_all <= tol))
+    fail(ACR_ERR_NOT_CONVERGED, "FGMRES stopped at relative residual " + std::to_string(rel_all));
+}
 
 // Architecture name of the current device (the tuning table's key).
 std::string device_arch() {
@@ -1010,6 +1161,38 @@ acr_status acr_factor(const acr_operator* op, const acr_options* opt, void* stre
     std::vector<acr_operator> ops{*op};
     if (opt->precision == ACR_FP64) h->f = std::move(factor_many<double>(ops, *opt, st)[0]);
     else h->f = std::move(factor_many<float>(ops, *opt, st)[0]);
+    *out = h.release();
+  });
+}
+
+acr_status acr_factor_3d(const acr_operator3d* op, const acr_options* opt, void* stream, acr_handle* out) {
+  return guard([&] {
+    check_op3(op);
+    if (!out) fail(ACR_ERR_INVALID_ARG, "output handle is NULL");
+    check_options(opt);
+    const int s = op->nx * op->ny;
+    const int L = hodlr_depth(s, opt->leaf);
+    if (L < 0) fail(ACR_ERR_INVALID_ARG, "plane size nx*ny must be leaf' * 2^L (halving exact down to the leaf)");
+    for (int d = 1; d <= L; ++d) {   // every split on a row boundary or inside one row
+      const int sd = s >> d;
+      if (sd % op->nx != 0 && op->nx % (2 * sd) != 0)
+        fail(ACR_ERR_INVALID_ARG, "the HODLR split of a plane must fall on row boundaries or inside a row "
+                                  "(s/2^d a multiple of nx, or nx a multiple of s/2^(d-1))");
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope ss(st);
+    acr_operator blk{};   // block form: one block per plane, z couplings as E_k / F_k
+    blk.nx = s;
+    blk.ny = op->nz;
+    blk.diag = op->diag; blk.west = op->west; blk.east = op->east;
+    blk.south = op->down; blk.north = op->up;
+    std::vector<acr_operator> v{blk};
+    auto h = std::make_unique<acr_handle_s>();
+    h->precision = opt->precision;
+    h->nx = s;
+    h->ny = op->nz;
+    if (opt->precision == ACR_FP64) h->f = std::move(factor_many<double>(v, *opt, st, nullptr, op)[0]);
+    else h->f = std::move(factor_many<float>(v, *opt, st, nullptr, op)[0]);
     *out = h.release();
   });
 }
@@ -1146,6 +1329,17 @@ acr_status acr_residual(const acr_operator* op, const double* X, const double* B
   });
 }
 
+acr_status acr_residual_3d(const acr_operator3d* op, const double* X, const double* B, double* R,
+                           int32_t nrhs, void* stream) {
+  return guard([&] {
+    check_op3(op);
+    if (!X || !B || !R || nrhs < 1) fail(ACR_ERR_INVALID_ARG, "bad vector arguments");
+    StreamScope ss(static_cast<hipStream_t>(stream));
+    const double* a7[7] = {op->diag, op->west, op->east, op->south, op->north, op->down, op->up};
+    stencil_residual3d(static_cast<hipStream_t>(stream), op->nx, op->ny, op->nz, nrhs, a7, X, B, R);
+  });
+}
+
 acr_status acr_solve_refined(acr_handle h, const acr_operator* op, const double* B, double* X,
                              int32_t nrhs, double tol, int32_t maxit, int32_t* iters, double* relres,
                              void* stream) {
@@ -1153,35 +1347,35 @@ acr_status acr_solve_refined(acr_handle h, const acr_operator* op, const double*
   double rel = INFINITY;
   acr_status st0 = guard([&] {
     check_op(op);
-    if (!h || !B || !X || nrhs < 1 || maxit < 0) fail(ACR_ERR_INVALID_ARG, "bad arguments");
-    if (op->nx != h->nx || op->ny != h->ny) fail(ACR_ERR_INVALID_ARG, "operator shape differs from the factor");
+    if (op->nx != (h ? h->nx : op->nx) || op->ny != (h ? h->ny : op->ny))
+      fail(ACR_ERR_INVALID_ARG, "operator shape differs from the factor");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    StreamScope ss(st);
-    const long long n = (long long)op->nx * op->ny;
-    if (overlap(X, B, (size_t)n * nrhs)) fail(ACR_ERR_INVALID_ARG, "X must not overlap B");
-    DBuf<double> R((size_t)n * nrhs), D((size_t)n * nrhs), nb(nrhs), nr(nrhs);
-    std::vector<double> hb(nrhs), hr(nrhs);
-    col_sumsq(st, n, nrhs, B, nb.get());
-    memset_async(X, 0, (size_t)n * nrhs * sizeof(double), st);
-    copy_d2d_async(R.get(), B, (size_t)n * nrhs * sizeof(double), st);
-    read_to_host(hb.data(), nb.get(), nrhs * sizeof(double), st);
-    for (its = 0;; ++its) {
-      if (its > 0) {
-        stencil_residual(st, op->nx, op->ny, nrhs, op->diag, op->west, op->east, op->south, op->north, X, B,
-                         R.get());
-      }
-      col_sumsq(st, n, nrhs, R.get(), nr.get());
-      read_to_host(hr.data(), nr.get(), nrhs * sizeof(double), st);
-      rel = 0.0;
-      for (int q = 0; q < nrhs; ++q) {
-        const double v = hb[q] > 0 ? std::sqrt(hr[q] / hb[q]) : std::sqrt(hr[q]);
-        rel = std::max(rel, v);
-      }
-      if (!(rel > tol) || its >= maxit || !std::isfinite(rel)) break;
-      h->f->solve(R.get(), D.get(), nrhs, st);
-      axpy_d(st, n * nrhs, D.get(), X);
-    }
-    if (!(rel <= tol)) fail(ACR_ERR_NOT_CONVERGED, "refinement stopped at relative residual " + std::to_string(rel));
+    refine_body(h, (long long)op->nx * op->ny, B, X, nrhs, tol, maxit, st, its, rel,
+                [&](const double* x, const double* b, double* r, int nr) {
+                  stencil_residual(st, op->nx, op->ny, nr, op->diag, op->west, op->east, op->south, op->north,
+                                   x, b, r);
+                });
+  });
+  if (iters) *iters = its;
+  if (relres) *relres = rel;
+  return st0;
+}
+
+acr_status acr_solve_refined_3d(acr_handle h, const acr_operator3d* op, const double* B, double* X,
+                                int32_t nrhs, double tol, int32_t maxit, int32_t* iters, double* relres,
+                                void* stream) {
+  int its = 0;
+  double rel = INFINITY;
+  acr_status st0 = guard([&] {
+    check_op3(op);
+    if (h && (op->nx * op->ny != h->nx || op->nz != h->ny))
+      fail(ACR_ERR_INVALID_ARG, "operator shape differs from the factor");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double* a7[7] = {op->diag, op->west, op->east, op->south, op->north, op->down, op->up};
+    refine_body(h, (long long)op->nx * op->ny * op->nz, B, X, nrhs, tol, maxit, st, its, rel,
+                [&](const double* x, const double* b, double* r, int nr) {
+                  stencil_residual3d(st, op->nx, op->ny, op->nz, nr, a7, x, b, r);
+                });
   });
   if (iters) *iters = its;
   if (relres) *relres = rel;
@@ -1191,105 +1385,42 @@ acr_status acr_solve_refined(acr_handle h, const acr_operator* op, const double*
 acr_status acr_solve_krylov(acr_handle h, const acr_operator* op, const double* B, double* X, int32_t nrhs,
                             double tol, int32_t maxit, int32_t restart, int32_t* iters, double* relres,
                             void* stream) {
-  int its_all = 0;
-  double rel_all = 0.0;
+  int its = 0;
+  double rel = 0.0;
   acr_status st0 = guard([&] {
     check_op(op);
-    if (!h || !B || !X || nrhs < 1 || maxit < 0) fail(ACR_ERR_INVALID_ARG, "bad arguments");
-    if (restart < 1 || restart > 64) fail(ACR_ERR_INVALID_ARG, "restart must be in 1..64");
-    if (op->nx != h->nx || op->ny != h->ny) fail(ACR_ERR_INVALID_ARG, "operator shape differs from the factor");
+    if (op->nx != (h ? h->nx : op->nx) || op->ny != (h ? h->ny : op->ny))
+      fail(ACR_ERR_INVALID_ARG, "operator shape differs from the factor");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    StreamScope ss(st);
-    const long long n = (long long)op->nx * op->ny;
-    if (overlap(X, B, (size_t)n * nrhs)) fail(ACR_ERR_INVALID_ARG, "X must not overlap B");
-    const int m = restart;
-    DBuf<double> V((size_t)(m + 1) * n), Z((size_t)m * n), R(n), zero(n), dv(2 * (m + 1) + 1);
-    memset_async(zero.get(), 0, (size_t)n * sizeof(double), st);
-    std::vector<double> hv(2 * (m + 1) + 1);
-    auto norm2 = [&](const double* v) {
-      col_sumsq(st, n, 1, v, dv.get());
-      double r = 0.0;
-      read_to_host(&r, dv.get(), sizeof(double), st);
-      return std::sqrt(r);
-    };
-    auto Aop = [&](const double* x, const double* b, double* r) {   // r = b - A x
-      stencil_residual(st, op->nx, op->ny, 1, op->diag, op->west, op->east, op->south, op->north, x, b, r);
-    };
-    for (int q = 0; q < nrhs; ++q) {
-      const double* b = B + (size_t)q * n;
-      double* x = X + (size_t)q * n;
-      memset_async(x, 0, (size_t)n * sizeof(double), st);
-      const double bn = norm2(b);
-      int its = 0;
-      double rel = 0.0;
-      std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-      for (;;) {
-        Aop(x, b, R.get());
-        const double beta = norm2(R.get());
-        rel = bn > 0.0 ? beta / bn : beta;
-        if (!(rel > tol) || its >= maxit || !std::isfinite(rel)) break;
-        // V_0 = r / beta
-        copy_d2d_async(V.get(), R.get(), (size_t)n * sizeof(double), st);
-        maxpy(st, n, 0, 1.0 / beta, 0.0, nullptr, nullptr, 0, V.get());
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int k = 0;   // columns of the Hessenberg matrix built in this cycle
-        for (int j = 0; j < m && its < maxit; ++j) {
-          double* vj = V.get() + (size_t)j * n;
-          double* zj = Z.get() + (size_t)j * n;
-          double* w = V.get() + (size_t)(j + 1) * n;
-          h->f->solve(vj, zj, 1, st);   // z_j = M^{-1} v_j
-          ++its;
-          Aop(zj, zero.get(), w);        // w = -A z_j
-          // classical Gram-Schmidt twice: d = V^T w, w = -w + V d (= A z_j - V h);
-          // e = V^T w, w = w - V e; h = -d + e
-          mdot(st, n, j + 1, V.get(), n, w, dv.get());
-          maxpy(st, n, j + 1, -1.0, 1.0, dv.get(), V.get(), n, w);
-          mdot(st, n, j + 1, V.get(), n, w, dv.get() + (m + 1));
-          maxpy(st, n, j + 1, 1.0, -1.0, dv.get() + (m + 1), V.get(), n, w);
-          col_sumsq(st, n, 1, w, dv.get() + 2 * (m + 1));
-          read_to_host(hv.data(), dv.get(), hv.size() * sizeof(double), st);
-          double* hc = H.data() + (size_t)j * (m + 1);   // column j
-          for (int i = 0; i <= j; ++i) hc[i] = -hv[i] + hv[m + 1 + i];
-          const double hn = std::sqrt(std::max(hv[2 * (m + 1)], 0.0));
-          hc[j + 1] = hn;
-          for (int i = 0; i < j; ++i) {   // earlier rotations
-            const double a = cs[i] * hc[i] + sn[i] * hc[i + 1];
-            hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
-            hc[i] = a;
-          }
-          const double den = std::hypot(hc[j], hc[j + 1]);
-          cs[j] = den > 0.0 ? hc[j] / den : 1.0;
-          sn[j] = den > 0.0 ? hc[j + 1] / den : 0.0;
-          hc[j] = den;
-          hc[j + 1] = 0.0;
-          g[j + 1] = -sn[j] * g[j];
-          g[j] = cs[j] * g[j];
-          k = j + 1;
-          if (hn > 0.0) maxpy(st, n, 0, 1.0 / hn, 0.0, nullptr, nullptr, 0, w);   // v_(j+1)
-          const double est = bn > 0.0 ? std::fabs(g[j + 1]) / bn : std::fabs(g[j + 1]);
-          if (!(est > tol) || !(hn > 0.0)) break;
-        }
-        // y = H^{-1} g (upper triangular k x k), x += Z y
-        for (int i = k - 1; i >= 0; --i) {
-          double v = g[i];
-          for (int l = i + 1; l < k; ++l) v -= H[(size_t)l * (m + 1) + i] * y[l];
-          const double d = H[(size_t)i * (m + 1) + i];
-          y[i] = d != 0.0 ? v / d : 0.0;
-        }
-        if (k > 0) {
-          const double* yd = static_cast<const double*>(desc_put(y.data(), k * sizeof(double), st));
-          maxpy(st, n, k, 1.0, 1.0, yd, Z.get(), n, x);
-        }
-      }
-      its_all = std::max(its_all, its);
-      rel_all = std::max(rel_all, rel);
-    }
-    if (!(rel_all <= tol))
-      fail(ACR_ERR_NOT_CONVERGED, "FGMRES stopped at relative residual " + std::to_string(rel_all));
+    krylov_body(h, (long long)op->nx * op->ny, B, X, nrhs, tol, maxit, restart, st, its, rel,
+                [&](const double* x, const double* b, double* r) {
+                  stencil_residual(st, op->nx, op->ny, 1, op->diag, op->west, op->east, op->south, op->north,
+                                   x, b, r);
+                });
   });
-  if (iters) *iters = its_all;
-  if (relres) *relres = rel_all;
+  if (iters) *iters = its;
+  if (relres) *relres = rel;
+  return st0;
+}
+
+acr_status acr_solve_krylov_3d(acr_handle h, const acr_operator3d* op, const double* B, double* X,
+                               int32_t nrhs, double tol, int32_t maxit, int32_t restart, int32_t* iters,
+                               double* relres, void* stream) {
+  int its = 0;
+  double rel = 0.0;
+  acr_status st0 = guard([&] {
+    check_op3(op);
+    if (h && (op->nx * op->ny != h->nx || op->nz != h->ny))
+      fail(ACR_ERR_INVALID_ARG, "operator shape differs from the factor");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double* a7[7] = {op->diag, op->west, op->east, op->south, op->north, op->down, op->up};
+    krylov_body(h, (long long)op->nx * op->ny * op->nz, B, X, nrhs, tol, maxit, restart, st, its, rel,
+                [&](const double* x, const double* b, double* r) {
+                  stencil_residual3d(st, op->nx, op->ny, op->nz, 1, a7, x, b, r);
+                });
+  });
+  if (iters) *iters = its;
+  if (relres) *relres = rel;
   return st0;
 }
 

@@ -134,10 +134,15 @@ struct Factor final : FactorBase {
 
 // Factor the problems ops[0..] together (see acr.hip).
 // With `dense` (then ops holds one entry giving nx, ny only) the single
-// problem's blocks come from the dense operator instead of a stencil.
+// problem's blocks come from the dense operator instead of a stencil.  With
+// `op3` the single problem is a 3-D operator: ops[0] then holds its block
+// form (nx = plane size, ny = planes, diag/west/east of the planes,
+// south/north = down/up) and op3 supplies the row length and the in-plane
+// y couplings.
 template <typename T>
 std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operator>& ops, const acr_options& opt,
-                                                    hipStream_t st, const acr_dense_operator* dense = nullptr);
+                                                    hipStream_t st, const acr_dense_operator* dense = nullptr,
+                                                    const acr_operator3d* op3 = nullptr);
 
 // X_p = M_p^{-1} B_p for several factors with <= 8 right-hand sides each, in
 // shared launches (see acr.hip).
@@ -155,6 +160,7 @@ void set_last_error(const std::string& msg);
 
 // Argument checks shared by the entry points (ACR_ERR_INVALID_ARG).
 void check_op(const acr_operator* op);
+void check_op3(const acr_operator3d* op);
 void check_options(const acr_options* opt);
 bool overlap2(const double* a, size_t na, const double* b, size_t nb);
 

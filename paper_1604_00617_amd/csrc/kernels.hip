@@ -2296,11 +2296,51 @@ __global__ __launch_bounds__(256) void k_leaves_tridiag(const OpJob* __restrict_
     const int rem = (int)(e % ((long long)b * b));
     const int r = rem % b, c = rem / b;
     const int gr = lam * b + r;
+    const int pnx = J.pnx;
     double v = 0.0;
     if (c == r) v = dg[gr];
-    else if (c == r - 1) v = we[gr];
-    else if (c == r + 1) v = ea[gr];
+    else if (c == r - 1) v = (pnx == 0 || gr % pnx != 0) ? we[gr] : 0.0;
+    else if (c == r + 1) v = (pnx == 0 || (gr + 1) % pnx != 0) ? ea[gr] : 0.0;
+    else if (pnx > 0 && c == r - pnx) v = gmem(J.south)[(size_t)blk * s + gr];
+    else if (pnx > 0 && c == r + pnx) v = gmem(J.north)[(size_t)blk * s + gr];
     lv[e] = (T)v;
+  }
+}
+
+// Off-diagonal factors of a plane operator (see gplane_factors).  At depth d
+// with children of sd unknowns, rank pnx: column q of the first child's U is
+// north at its row sd - pnx + q, of the second child's U south at its row q,
+// and V holds 1 at the same rows; rank 1: east at the first child's last row,
+// west at the second child's first row.  Every entry of U[d] and V[d] is
+// written (zeros elsewhere).
+template <typename T>
+__global__ __launch_bounds__(256) void k_plane_factors(const OpJob* __restrict__ jobs, int njobs) {
+  const OpJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long local = blockIdx.x - J.block0;
+  const int m = (int)(local / J.per), part = (int)(local % J.per);
+  const int s = J.s, pnx = J.pnx;
+  const int blk = J.bmul * m + J.boff;
+  const size_t off = (size_t)blk * s;
+  for (int r = part * 256 + threadIdx.x; r < s; r += J.per * 256) {
+    for (int d = 1; d <= J.L; ++d) {
+      const int sd = s >> d, cl = r / sd, loc = r % sd;
+      const int k = sd % pnx == 0 ? pnx : 1;
+      int q = -1;
+      double u = 0.0;
+      if (k == 1) {
+        if ((cl & 1) == 0 && loc == sd - 1) { q = 0; u = gmem(J.east)[off + r]; }
+        if ((cl & 1) == 1 && loc == 0) { q = 0; u = gmem(J.west)[off + r]; }
+      } else {
+        if ((cl & 1) == 0 && loc >= sd - pnx) { q = loc - (sd - pnx); u = gmem(J.north)[off + r]; }
+        if ((cl & 1) == 1 && loc < pnx) { q = loc; u = gmem(J.south)[off + r]; }
+      }
+      T* U = gmem(static_cast<T*>(J.U[d])) + (size_t)m * k * s + r;
+      T* V = gmem(static_cast<T*>(J.V[d])) + (size_t)m * k * s + r;
+      for (int c = 0; c < k; ++c) {
+        U[(size_t)c * s] = c == q ? (T)u : T(0);
+        V[(size_t)c * s] = c == q ? T(1) : T(0);
+      }
+    }
   }
 }
 
@@ -2547,6 +2587,29 @@ __global__ void k_residual(int nx, int ny, const double* diag, const double* wes
     if (j + 1 < nx) ax += east[e] * x[e + 1];
     if (i > 0) ax += south[e] * x[e - nx];
     if (i + 1 < ny) ax += north[e] * x[e + nx];
+    R[e + q * N] = B[e + q * N] - ax;
+  }
+}
+
+__global__ void k_residual3d(int nx, int ny, int nz, const double* diag, const double* west,
+                             const double* east, const double* south, const double* north,
+                             const double* down, const double* up, const double* X, const double* B,
+                             double* R) {
+  const long long P = (long long)nx * ny, N = P * nz;
+  const int q = blockIdx.y;
+  const double* x = X + q * N;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < N;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(e % nx);
+    const int i = (int)((e / nx) % ny);
+    const long long k = e / P;
+    double ax = diag[e] * x[e];
+    if (j > 0) ax += west[e] * x[e - 1];
+    if (j + 1 < nx) ax += east[e] * x[e + 1];
+    if (i > 0) ax += south[e] * x[e - nx];
+    if (i + 1 < ny) ax += north[e] * x[e + nx];
+    if (k > 0) ax += down[e] * x[e - P];
+    if (k + 1 < nz) ax += up[e] * x[e + P];
     R[e + q * N] = B[e + q * N] - ax;
   }
 }
@@ -3844,6 +3907,21 @@ void grank1_factors(hipStream_t st, std::vector<OpJob> jobs) {
                    KC_OTHER, KNAME_T(k_rank1<T>), k_rank1<T>);
 }
 
+int plane_rank(int s, int d, int pnx) { return (s >> d) % pnx == 0 ? pnx : 1; }
+
+template <typename T>
+void gplane_factors(hipStream_t st, std::vector<OpJob> jobs) {
+  for (const auto& J : jobs)
+    if (J.L > kMvMaxDepth || J.pnx <= 0) fail(ACR_ERR_INTERNAL, "plane factors: bad job");
+  launch_opjobs<T>(st, std::move(jobs),
+                   [](const OpJob& J) {
+                     long long w = 0;
+                     for (int d = 1; d <= J.L; ++d) w += (long long)J.s * plane_rank(J.s, d, J.pnx);
+                     return std::max(w, (long long)J.s);
+                   },
+                   16, KC_OTHER, KNAME_T(k_plane_factors<T>), k_plane_factors<T>);
+}
+
 template <typename T>
 void ggather_diag(hipStream_t st, std::vector<OpJob> jobs) {
   launch_opjobs<T>(st, std::move(jobs), [](const OpJob& J) { return (long long)J.s; }, 16, KC_OTHER,
@@ -3897,6 +3975,14 @@ void stencil_residual(hipStream_t st, int nx, int ny, int nrhs, const double* di
   dim3 g(grid1(N, 256, 8192), nrhs);
   launch(st, KC_OTHER, 10.0 * N * nrhs, 8.0 * N * (5.0 + 3.0 * nrhs), KNAME0(k_residual), k_residual, g, dim3(256), 0, nx, ny,
          diag, west, east, south, north, X, B, R);
+}
+
+void stencil_residual3d(hipStream_t st, int nx, int ny, int nz, int nrhs, const double* const* a7,
+                        const double* X, const double* B, double* R) {
+  const long long N = (long long)nx * ny * nz;
+  dim3 g(grid1(N, 256, 8192), nrhs);
+  launch(st, KC_OTHER, 14.0 * N * nrhs, 8.0 * N * (7.0 + 3.0 * nrhs), KNAME0(k_residual3d), k_residual3d, g,
+         dim3(256), 0, nx, ny, nz, a7[0], a7[1], a7[2], a7[3], a7[4], a7[5], a7[6], X, B, R);
 }
 
 namespace {
@@ -4059,6 +4145,7 @@ void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
   template void gtridiag_inverse<T>(hipStream_t, std::vector<OpJob>);                              \
   template void gleaves_tridiag<T>(hipStream_t, std::vector<OpJob>);                               \
   template void grank1_factors<T>(hipStream_t, std::vector<OpJob>);                                \
+  template void gplane_factors<T>(hipStream_t, std::vector<OpJob>);                                \
   template void ggather_diag<T>(hipStream_t, std::vector<OpJob>);                                  \
   template void ggemm<T>(hipStream_t, std::vector<GJob>, const std::vector<GSeg>&, int);          \
   template void ghmv<T>(hipStream_t, int, int, int, int, std::vector<MVJob>, const std::vector<MVTerm>&); \

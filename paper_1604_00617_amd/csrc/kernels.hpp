@@ -162,18 +162,31 @@ void gfrom_blocks(hipStream_t st, std::vector<VJob> jobs);   // src T, dst doubl
 struct OpJob {
   long long block0 = 0;
   int s = 0, b = 0, L = 0, nmat = 0, bmul = 1, boff = 0, per = 1, zblk = -1;
+  int pnx = 0;                     // 3-D operators: row length of a plane (0: five-point)
   const double* diag = nullptr;
   const double* west = nullptr;
   const double* east = nullptr;
+  const double* south = nullptr;   // 3-D: in-plane couplings to r - pnx and r + pnx
+  const double* north = nullptr;
   const double* src = nullptr;     // ggather_diag: the stencil array gathered
   void* out = nullptr;             // leaves [nmat][2^L][b][b] or gathered diagonals [nmat][s]
   void* U[kMvMaxDepth + 1] = {};   // depth-d factors, matrix m at U[d] + m*s (one column)
   void* V[kMvMaxDepth + 1] = {};
   int* flag = nullptr;             // gtridiag_inverse: set to 1 on a breakdown
 };
-// Leaves: the tridiagonal band restricted to each b x b diagonal leaf of D_i.
+// Leaves: the tridiagonal band restricted to each b x b diagonal leaf of D_i
+// (3-D, pnx > 0: the plane's five-point operator, x couplings cut at the ends
+// of each row of pnx unknowns).
 template <typename T>
 void gleaves_tridiag(hipStream_t st, std::vector<OpJob> jobs);
+// Exact factors of the off-diagonal blocks of a plane operator D_k (3-D,
+// pnx > 0) at every depth d = 1..L: where the children of a cluster hold whole
+// rows of the plane (s/2^d a multiple of pnx) the block couples the last pnx
+// unknowns of the first child to the first pnx of the second (rank pnx, the
+// y couplings); inside one row it is the single x coupling (rank 1).
+int plane_rank(int s, int d, int pnx);
+template <typename T>
+void gplane_factors(hipStream_t st, std::vector<OpJob> jobs);
 // Depth-d rank-one factors of D_i for every depth d = 1..L (Section 3:
 // tridiagonal D_i has exact rank-1 off-diagonal blocks).
 template <typename T>
@@ -379,6 +392,9 @@ struct RJob {
   double* out = nullptr;
 };
 void gresidual(hipStream_t st, std::vector<RJob> jobs);
+// R = B - A X for a 7-point operator (3-D; nx*ny*nz FP64 values per column).
+void stencil_residual3d(hipStream_t st, int nx, int ny, int nz, int nrhs, const double* const* a7,
+                        const double* X, const double* B, double* R);
 void gcol_sumsq(hipStream_t st, std::vector<RJob> jobs);
 void gaxpy(hipStream_t st, std::vector<RJob> jobs);
 

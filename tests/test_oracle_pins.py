@@ -417,3 +417,114 @@ def test_recirculating_operator(alpha):
     bx, by = np.cos(8 * math.pi * x), np.sin(8 * math.pi * y)
     ref = (h * h * alpha * (bx + 2 * by)).reshape(n, n)[1:-1, 1:-1]
     assert np.abs(Au - ref).max() <= 1e-12 * max(1.0, alpha)
+
+
+# ------------------------------------------------------- 3-D operators (NEXT)
+def _grid3(st):
+    h = 1.0 / (st.nx + 1)
+    x = (np.arange(st.nx) + 1.0) * h
+    y = (np.arange(st.ny) + 1.0) / (st.ny + 1)
+    z = (np.arange(st.nz) + 1.0) / (st.nz + 1)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return X.reshape(-1), Y.reshape(-1), Z.reshape(-1)
+
+
+@pytest.mark.parametrize("p,q,r", [(1, 1, 1), (2, 3, 1), (5, 1, 4)])
+def test_poisson3d_discrete_eigenfunction(p, q, r):
+    """The 7-point Laplacian (scaled by h^2) has the eigenvectors
+    sin(p pi x) sin(q pi y) sin(r pi z) with eigenvalue
+    4 (sin^2(p pi h/2) + sin^2(q pi h/2) + sin^2(r pi h/2)); checked on the
+    sparse assembly and on the block form (plane blocks) built separately."""
+    n = 7
+    st = W.poisson3d(n)
+    X, Y, Z = _grid3(st)
+    h = 1.0 / (n + 1)
+    u = np.sin(p * math.pi * X) * np.sin(q * math.pi * Y) * np.sin(r * math.pi * Z)
+    lam = 4.0 * sum(math.sin(k * math.pi * h / 2) ** 2 for k in (p, q, r))
+    assert np.abs(direct.assemble3d(st) @ u - lam * u).max() <= 1e-12
+    D, E, F = direct.blocks3d(st)
+    s = st.s
+    Au = np.zeros_like(u)
+    for k in range(st.nz):
+        Au[k * s:(k + 1) * s] = D[k] @ u[k * s:(k + 1) * s]
+        if k > 0:
+            Au[k * s:(k + 1) * s] += E[k] @ u[(k - 1) * s:k * s]
+        if k + 1 < st.nz:
+            Au[k * s:(k + 1) * s] += F[k] @ u[(k + 1) * s:(k + 2) * s]
+    assert np.abs(Au - lam * u).max() <= 1e-12
+    assert np.all(E[0] == 0) and np.all(F[-1] == 0)
+
+
+def test_varkappa3d_flux_form():
+    """Flux form: symmetric, off-diagonals <= 0, zero row sum at nodes away from
+    the boundary (the diagonal is the sum of the six face coefficients), and
+    the face contrast is at most the requested 1e3."""
+    st = W.varkappa3d(10)
+    A = direct.assemble3d(st)
+    assert abs(A - A.T).max() == 0.0
+    off = A - sp.diags(A.diagonal())
+    assert off.max() <= 0.0
+    rs = np.asarray(A.sum(axis=1)).ravel().reshape(10, 10, 10)
+    assert np.abs(rs[1:-1, 1:-1, 1:-1]).max() <= 1e-12 * st.diag.max()
+    faces = -np.concatenate([a[a != 0] for a in (st.west, st.east, st.south, st.north, st.down, st.up)])
+    assert faces.max() / faces.min() <= 1e3 * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("nx,ny,leaf", [(8, 8, 16), (16, 8, 32), (32, 4, 16)])
+def test_plane_operator_exact_hodlr_ranks(nx, ny, leaf):
+    """A plane's five-point operator with the halving split has off-diagonal
+    blocks of exact rank nx where the two clusters hold whole rows (the y
+    couplings across the split) and rank 1 inside a row (the x coupling);
+    E_k, F_k are diagonal (rank 0 off the leaves)."""
+    st = W.varkappa3d(8) if (nx, ny) == (8, 8) else None
+    if st is None:
+        p = W.poisson3d(nx, ny, 4)
+        rng = np.random.default_rng(5)
+        for a in (p.west, p.east, p.south, p.north):
+            a *= rng.uniform(0.5, 2.0, a.size) * (a != 0)
+        st = p
+    D, E, F = direct.blocks3d(st)
+    s = st.s
+    for Dk in D[:2]:
+        H = hodlr.compress(Dk, leaf, 1e-14)
+        for d, rs in hodlr.ranks(H).items():
+            sd = s >> d
+            want = nx if sd % nx == 0 else 1
+            assert all(r == want for r in rs), (d, rs, want)
+        assert np.abs(hodlr.densify(H) - Dk).max() <= 1e-14 * np.abs(Dk).max()
+    H = hodlr.compress(E[1], leaf, 1e-14)
+    assert all(r == 0 for rs in hodlr.ranks(H).values() for r in rs)
+
+
+def test_acr3d_eps0_equals_lu_and_error_decreases():
+    """ACR over the planes of a 3-D operator: eps = 0 is exact (sparse LU), and
+    the error decreases with eps."""
+    st = W.varkappa3d(8)
+    D, E, F = direct.blocks3d(st)
+    s = st.s
+    b = W.rhs(st.n, 2, seed=31)
+    xd = direct.solve3d(st, b)
+    errs = []
+    for eps in (0.0, 1e-8, 1e-4, 1e-2):
+        fac = acr.factor_blocks(D, E, F, 16, eps)
+        x = np.concatenate(acr.solve_blocks(fac, [b[k * s:(k + 1) * s] for k in range(st.nz)]), axis=0)
+        errs.append(np.linalg.norm(x - xd) / np.linalg.norm(xd))
+    assert errs[0] <= 1e-12
+    assert errs[1] <= 1e-6
+    assert errs[1] <= errs[2] <= errs[3]
+
+
+def test_fgmres_with_acr3d_preconditioner():
+    """A coarse ACR factor of a 3-D operator as the FGMRES preconditioner
+    reaches the sparse-LU solution."""
+    st = W.varkappa3d(8)
+    D, E, F = direct.blocks3d(st)
+    s = st.s
+    A = direct.assemble3d(st)
+    b = W.rhs(st.n, 1, seed=32)[:, 0]
+    fac = acr.factor_blocks(D, E, F, 16, 1e-2)
+    apply = lambda v: np.concatenate(acr.solve_blocks(fac, [v[k * s:(k + 1) * s] for k in range(st.nz)]))
+    x, its, hist = krylov.fgmres(lambda v: A @ v, b, apply, tol=1e-10, maxit=40)
+    assert hist[-1] <= 1e-10
+    xd = direct.solve3d(st, b)
+    assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)

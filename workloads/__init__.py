@@ -285,3 +285,120 @@ def strip(st: Stencil, rows: int, first: int = 0) -> Stencil:
     arr[3][: st.nx] = 0.0                  # south of the first row
     arr[4][(rows - 1) * st.nx:] = 0.0      # north of the last row
     return Stencil(st.nx, rows, *arr, name=f"{st.name}-strip{rows}")
+
+
+# ---------------------------------------------------------------------------
+# 3-D operators: 7-point stencils on the unit cube (the block-tridiagonal form
+# with one block per z plane, Section 4's closing remarks on 3-D problems).
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Stencil3:
+    """7-point stencil on the interior nodes of an nx x ny x nz grid, unknown
+    index ``(k*ny + i)*nx + j`` (k the plane z, i the row y, j the column x)::
+
+        (A u)[k,i,j] = diag*u + west*u[k,i,j-1] + east*u[k,i,j+1]
+                       + south*u[k,i-1,j] + north*u[k,i+1,j]
+                       + down*u[k-1,i,j] + up*u[k+1,i,j]
+
+    As a block-tridiagonal system the block is one plane (s = nx*ny unknowns,
+    D_k the plane's 5-point operator), E_k = diag(down), F_k = diag(up), and
+    there are nz blocks.  Couplings that would leave the grid are exact zeros.
+    Operators are scaled by h^2 (h the mesh width), so entries are O(1)."""
+    nx: int
+    ny: int
+    nz: int
+    diag: np.ndarray
+    west: np.ndarray
+    east: np.ndarray
+    south: np.ndarray
+    north: np.ndarray
+    down: np.ndarray
+    up: np.ndarray
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def s(self) -> int:
+        return self.nx * self.ny
+
+    def arrays(self):
+        return (self.diag, self.west, self.east, self.south, self.north, self.down, self.up)
+
+
+def _zero_outside3(nx, ny, nz, west, east, south, north, down, up):
+    for a in (west, east, south, north, down, up):
+        assert a.shape == (nx * ny * nz,)
+    west.reshape(nz, ny, nx)[:, :, 0] = 0.0
+    east.reshape(nz, ny, nx)[:, :, nx - 1] = 0.0
+    south.reshape(nz, ny, nx)[:, 0, :] = 0.0
+    north.reshape(nz, ny, nx)[:, ny - 1, :] = 0.0
+    down.reshape(nz, ny, nx)[0] = 0.0
+    up.reshape(nz, ny, nx)[nz - 1] = 0.0
+
+
+def poisson3d(n: int, ny: int | None = None, nz: int | None = None) -> Stencil3:
+    """Constant-coefficient -Laplace, 7-point, on a cube grid of equal spacing
+    h = 1/(n+1) in every direction (ny, nz default to n), scaled by h^2."""
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    N = n * ny * nz
+    diag = np.full(N, 6.0)
+    arr = [np.full(N, -1.0) for _ in range(6)]
+    _zero_outside3(n, ny, nz, *arr)
+    return Stencil3(n, ny, nz, diag, *arr, name="poisson3d")
+
+
+def random_fourier_field(points: np.ndarray, length: float, rng: np.random.Generator,
+                         features: int = 512) -> np.ndarray:
+    """Approximately stationary Gaussian field with covariance exp(-r^2/(2 length^2))
+    at the given points (shape (..., dim)): sqrt(2/M) sum_m cos(w_m . x + b_m) with
+    w_m ~ N(0, I/length^2) and b_m ~ U(0, 2 pi) (random Fourier features),
+    normalised to zero mean and unit variance over the points."""
+    dim = points.shape[-1]
+    w = rng.standard_normal((features, dim)) / length
+    b = rng.uniform(0.0, 2.0 * math.pi, features)
+    flat = points.reshape(-1, dim)
+    g = np.empty(flat.shape[0])
+    for lo in range(0, flat.shape[0], 65536):   # bounded memory
+        ph = flat[lo:lo + 65536] @ w.T + b
+        g[lo:lo + 65536] = np.sqrt(2.0 / features) * np.cos(ph).sum(axis=1)
+    g = g - g.mean()
+    sd = g.std()
+    return (g / sd if sd > 0 else g).reshape(points.shape[:-1])
+
+
+def varkappa3d(n: int, seed: int = seed_for(6, 0), length: float = 0.1,
+               contrast: float = 1e3) -> Stencil3:
+    """-div(kappa grad u) on the n^3 cube grid in flux form, kappa = exp(g) at the
+    face midpoints with g a random Fourier field, scaled so that
+    max(kappa)/min(kappa) over the face samples equals ``contrast``; scaled by h^2."""
+    h = 1.0 / (n + 1)
+    rng = np.random.default_rng(seed)
+    node = (np.arange(n) + 1.0) * h
+    face = (np.arange(n + 1) + 0.5) * h
+    # faces normal to x: (z node, y node, x face); to y: (z, y face, x); to z: (z face, y, x)
+    def pts(zs, ys, xs):
+        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+        return np.stack([X, Y, Z], axis=-1)
+    px, py, pz = pts(node, node, face), pts(node, face, node), pts(face, node, node)
+    allp = np.concatenate([px.reshape(-1, 3), py.reshape(-1, 3), pz.reshape(-1, 3)])
+    g = random_fourier_field(allp, length, rng)
+    lo, hi = g.min(), g.max()
+    scale = math.log(contrast) / (hi - lo)
+    k = np.exp((g - 0.5 * (hi + lo)) * scale)
+    nxf = px.shape[0] * px.shape[1] * px.shape[2]
+    nyf = py.shape[0] * py.shape[1] * py.shape[2]
+    kx = k[:nxf].reshape(n, n, n + 1)
+    ky = k[nxf:nxf + nyf].reshape(n, n + 1, n)
+    kz = k[nxf + nyf:].reshape(n + 1, n, n)
+    kw, ke = kx[:, :, :n], kx[:, :, 1:]
+    ks, kn = ky[:, :n, :], ky[:, 1:, :]
+    kd, ku = kz[:n], kz[1:]
+    diag = (kw + ke + ks + kn + kd + ku).reshape(-1).copy()
+    arr = [(-a).reshape(-1).copy() for a in (kw, ke, ks, kn, kd, ku)]
+    _zero_outside3(n, n, n, *arr)
+    return Stencil3(n, n, n, diag, *arr, name="varkappa3d")
