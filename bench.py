@@ -68,6 +68,9 @@ def parse():
                     help="instead of the benchmark workload, ACR over the planes of the 3-D variable-"
                          "coefficient operator on N^3 grids: factor time, ranks and storage at coarse eps "
                          "(mixed and FP64) and FGMRES(20) to --tol with the factor as preconditioner")
+    ap.add_argument("--tune", type=str, default=None, metavar="PATH",
+                    help="use the autotuner's table at PATH for the timed steps (written first, from one "
+                         "recorded step and the tuner's measurements, when PATH does not exist)")
     ap.add_argument("--cpu-rows", type=int, default=16,
                     help="block rows of the operator the CPU oracle factors (bounded sample)")
     return ap.parse_args()
@@ -630,6 +633,24 @@ def main():
     b = torch.from_numpy(W.rhs(st.n, 1)).cuda()
     torch.cuda.synchronize()
 
+    tuned = None
+    if args.tune:
+        if not os.path.exists(args.tune):
+            acr.acr_tune_clear()
+            acr.acr_tune_record(True)
+            run_steps(acr, torch, op, b, args, "mixed", 1)
+            if not args.no_fp64:
+                run_steps(acr, torch, op, b, args, "fp64", 1)
+            acr.acr_tune_record(False)
+            acr.acr_tune_run()
+            acr.acr_tune_save(args.tune)
+        acr.acr_tune_load(args.tune)
+        acr.acr_tune_enable(True)
+        ent = json.load(open(args.tune))["entries"]
+        tuned = {"table": os.path.basename(args.tune), "entries": len(ent),
+                 "gemm_mfma_entries": sum(1 for k, v in ent.items() if k.startswith("gemm.f.") and v >= 10),
+                 "gemm_f_entries": sum(1 for k in ent if k.startswith("gemm.f."))}
+        print(f"[tune] {tuned}", file=sys.stderr, flush=True)
     # warm-up (also sizes the memory pool)
     for _ in range(args.warmup):
         run_steps(acr, torch, op, b, args, "mixed", 1)
@@ -685,6 +706,8 @@ def main():
                     "level_mean_rank": [round(v, 2) for v in info["level_mean_rank"]]},
         "kernel_classes_ms": {k: round(v["total_ms"], 3) for k, v in table.items()},
     }
+    if tuned:
+        out["tuned"] = tuned
     # the same step with FGMRES (ACR as right preconditioner, FP64 Krylov vectors) in
     # place of stationary refinement
     run_steps(acr, torch, op, b, args, "mixed", 1, krylov=True)

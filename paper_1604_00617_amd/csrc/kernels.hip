@@ -303,6 +303,114 @@ __global__ __launch_bounds__((TM / RM) * (TN / RN)) void k_ggemm(const GJob* __r
   ggemm_body<T, TM, TN, TK, RM, RN>(jobs, njobs, segs, blockIdx.x);
 }
 
+// The FP32 tile GEMM on the matrix cores (v_mfma_f32_16x16x4f32): the same
+// jobs, tiles and LDS staging as ggemm_body, but a wave owns BM x BN output
+// blocks of 16 x 16 and each K step of four is one MFMA per block.  Lane l
+// feeds A[i0 + l % 16][k + l / 16] and B[k + l / 16][j0 + l % 16] and holds
+// rows 4 (l / 16) .. 4 (l / 16) + 3 of column l % 16 of the block.  Every
+// output sums its K terms four at a time in K order whatever the tile, so the
+// five tile shapes give the same bits (as the vector tiles do among
+// themselves in FP64).  LDS rows are padded to 16 banks apart so that the two
+// 16-lane halves of a 32-lane LDS access read disjoint banks.
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+template <int TM, int TN, int WM, int WN, int TK = 16>
+__device__ __forceinline__ void ggemm_mfma_body(const GJob* __restrict__ jobs, int njobs,
+                                                const GSeg* __restrict__ segs, long long bid) {
+  constexpr int NT = WM * WN * WAVE;
+  constexpr int BM = TM / (16 * WM), BN = TN / (16 * WN);
+  constexpr int LA = TM % 32 == 0 ? TM + 16 : TM, LB = TN % 32 == 0 ? TN + 16 : TN;
+  static_assert(BM >= 1 && BN >= 1 && BM * 16 * WM == TM && BN * 16 * WN == TN, "tile");
+  __shared__ float As[TK][LA];
+  __shared__ float Bs[TK][LB];
+
+  const GJob& J = jobs[job_of(jobs, njobs, bid)];
+  const int tilesM = J.tilesM;
+  const int tiles = tilesM * J.tilesN;
+  const long long local = bid - J.block0;
+  const int prob = (int)(local / tiles);
+  const int t = (int)(local % tiles);
+  const int tm = t % tilesM, tn = t / tilesM;
+  const int m = prob / J.ncl, c = prob % J.ncl;
+  const int M = J.M, N = J.N;
+  const int tid = threadIdx.x;
+  const int lane = tid % WAVE;
+  const int w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+  const int wm = w % WM, wn = w / WM;
+  const int i0 = tm * TM, j0 = tn * TN;
+  const int lr = lane % 16, lk = lane / 16;
+  v4f32 acc[BM][BN];
+#pragma unroll
+  for (int r = 0; r < BM; ++r)
+#pragma unroll
+    for (int q = 0; q < BN; ++q) acc[r][q] = v4f32{0.f, 0.f, 0.f, 0.f};
+  for (int sg = 0; sg < J.nseg; ++sg) {
+    const GSeg& S = segs[J.seg0 + sg];
+    const int K = S.K;
+    const int lda = S.A.ld, ldb = S.B.ld, ta = S.A.trans, tb = S.B.trans;
+    const float sscale = (float)S.scale;
+    const float* Ap = optr<float>(S.A, m, c);
+    const float* Bp = optr<float>(S.B, m, c);
+    for (int k0 = 0; k0 < K; k0 += TK) {
+      for (int e = tid; e < TM * TK; e += NT) {
+        int i, kk;
+        if (!ta) { i = e % TM; kk = e / TM; } else { kk = e % TK; i = e / TK; }
+        const int gi = i0 + i, gk = k0 + kk;
+        float v = 0.f;
+        if (gi < M && gk < K) v = ta ? Ap[gk + (long long)gi * lda] : Ap[gi + (long long)gk * lda];
+        As[kk][i] = v * sscale;
+      }
+      for (int e = tid; e < TK * TN; e += NT) {
+        int kk, jj;
+        if (!tb) { kk = e % TK; jj = e / TK; } else { jj = e % TN; kk = e / TN; }
+        const int gk = k0 + kk, gj = j0 + jj;
+        float v = 0.f;
+        if (gk < K && gj < N) v = tb ? Bp[gj + (long long)gk * ldb] : Bp[gk + (long long)gj * ldb];
+        Bs[kk][jj] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kq = 0; kq < TK; kq += 4) {
+        float a[BM], b[BN];
+#pragma unroll
+        for (int r = 0; r < BM; ++r) a[r] = As[kq + lk][(wm * BM + r) * 16 + lr];
+#pragma unroll
+        for (int q = 0; q < BN; ++q) b[q] = Bs[kq + lk][(wn * BN + q) * 16 + lr];
+#pragma unroll
+        for (int r = 0; r < BM; ++r)
+#pragma unroll
+          for (int q = 0; q < BN; ++q) acc[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b[q], acc[r][q], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  float* Cp = const_cast<float*>(optr<float>(J.C, m, c));
+  const int ldc = J.C.ld;
+  const float alpha = (float)J.alpha, beta = (float)J.beta;
+#pragma unroll
+  for (int q = 0; q < BN; ++q) {
+    const int gj = j0 + (wn * BN + q) * 16 + lr;
+    if (gj >= N) continue;
+#pragma unroll
+    for (int r = 0; r < BM; ++r)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int gi = i0 + (wm * BM + r) * 16 + 4 * lk + u;
+        if (gi >= M) continue;
+        float* cp = Cp + gi + (long long)gj * ldc;
+        float v = alpha * acc[r][q][u];
+        if (beta != 0.f) v = fmaf(beta, *cp, v);
+        *cp = v;
+      }
+  }
+}
+
+template <int TM, int TN, int WM, int WN, int TK>
+__global__ __launch_bounds__(WM * WN * WAVE) void k_ggemm_mfma(const GJob* __restrict__ jobs, int njobs,
+                                                              const GSeg* __restrict__ segs) {
+  ggemm_mfma_body<TM, TN, WM, WN, TK>(jobs, njobs, segs, blockIdx.x);
+}
+
 // Reduction GEMM C = sum_s scale_s A_s^T B_s with long K (A_s: K x M, B_s:
 // K x N, both column-major).  A workgroup owns an 8 x 8 output tile; its four
 // waves split K (wave w takes k = 64 w + lane, step 256), every lane keeps the
@@ -528,6 +636,9 @@ __global__ __launch_bounds__(256) void k_gemm_any(const GJob* __restrict__ jobs,
     case 7: gemm_rows_body<T, sizeof(T) == 4 ? 32 : 16>(jobs, njobs, segs, bid); break;
     case 8: gemm_rows_body<T, 4>(jobs, njobs, segs, bid); break;
     case 9: gemm_small_body<T>(jobs, njobs, segs, bid); break;
+    case 10:
+      if constexpr (sizeof(T) == 4) ggemm_mfma_body<64, 64, 2, 2, 16>(jobs, njobs, segs, bid);
+      break;
     default: ggemm_body<T, 64, 64, 16, 4, 4>(jobs, njobs, segs, bid); break;
   }
 }
@@ -2906,9 +3017,12 @@ const J* upload(const std::vector<J>& v, hipStream_t st) {
 // GPU architecture.  Keys hold shapes only, never anything about the other
 // problems of a call, so a problem's result does not depend on what it is
 // batched with:
-//   "gemm.<f|d>.<M>.<N>.<Kbits>.<Pbits>"  tile shape of the grouped GEMM
-//       (k_ggemm's five tiles; they give the same bits, each output sums its
-//       K terms in the same order whatever the tile): kind 0..4;
+//   "gemm.<f|d>.<M>.<N>.<Kbits>.<Pbits>"  tile shape of the grouped GEMM:
+//       kind 0..4 = k_ggemm's five tiles on the vector units, 10..14 (FP32
+//       only) = the same tiles on the matrix cores (k_ggemm_mfma).  Within
+//       each engine the tiles give the same bits (every output sums its K
+//       terms in the same order whatever the tile); the two engines round
+//       differently (one FMA per term against four products per MFMA);
 //   "qr.<f|d>.<p>.<k>"  Householder QR form of a p x k panel: 4 one wave,
 //       2 registers of four waves, 0 LDS (the forms give different bits).
 Tuner& Tuner::get() {
@@ -2948,10 +3062,12 @@ long long gjob_blocks(const GJob& J) {
 
 // Kernel kinds of the grouped GEMM: 0..4 = tile shapes of k_ggemm,
 // 5 = k_gemm_dot (long-K reductions A^T B with small outputs), 6..8 =
-// k_gemm_rows with 16 / 32 / 4 columns, 9 = k_gemm_small (short-K reductions).
+// k_gemm_rows with 16 / 32 / 4 columns, 9 = k_gemm_small (short-K reductions),
+// 10..14 = the tiles of 0..4 on the matrix cores (FP32, chosen by the tuner
+// only: on the shapes of the factorisation the vector tiles are faster).
 template <typename T>
 void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs, int force_tile) {
-  constexpr int NK = 10;
+  constexpr int NK = 15;
   Tuner& tuner = Tuner::get();
   std::vector<GJob> by[NK];
   double fl[NK] = {}, bytes[NK] = {};
@@ -2988,22 +3104,26 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
         std::snprintf(key, sizeof key, "gemm.%c.%d.%d.%d.%d", tchar<T>(), J.M, J.N, bits((long long)K), bits(npr));
         tuner.note(key, npr);
         const int c = tuner.lookup(key);
-        if (c >= 0 && c <= 4) kind = c;
+        if ((c >= 0 && c <= 4) || (sizeof(T) == 4 && c >= 10 && c <= 14)) kind = c;
       }
-      J.tilesM = (J.M + kTiles[kind].tm - 1) / kTiles[kind].tm;
-      J.tilesN = (J.N + kTiles[kind].tn - 1) / kTiles[kind].tn;
+      if (kind >= 10 && sizeof(T) != 4) kind -= 10;
+      J.tilesM = (J.M + kTiles[kind % 10].tm - 1) / kTiles[kind % 10].tm;
+      J.tilesN = (J.N + kTiles[kind % 10].tn - 1) / kTiles[kind % 10].tn;
     }
     const double np = (double)J.nmat * J.ncl;
     fl[kind] += 2.0 * J.M * J.N * K * np;
     bytes[kind] += sizeof(T) * np * ((double)J.M * K + K * J.N + (double)J.M * J.N * (J.beta != 0.0 ? 2 : 1));
     J.kind = kind;
     {
-      static const char* names[10][2] = {
+      static const char* names[15][2] = {
           {"gemm.tile64x64", "gemm.tile64x64.M>128"}, {"gemm.tile64x16", "gemm.tile64x16.M>128"},
           {"gemm.tile16x64", "gemm.tile16x64.M>128"}, {"gemm.tile32x32", "gemm.tile32x32.M>128"},
           {"gemm.tile16x16", "gemm.tile16x16.M>128"}, {"gemm.dot", "gemm.dot.K>128"},
           {"gemm.rows16", "gemm.rows16.M>128"}, {"gemm.rows32", "gemm.rows32.M>128"},
-          {"gemm.rows4", "gemm.rows4.M>128"}, {"gemm.small", "gemm.small.K>128"}};
+          {"gemm.rows4", "gemm.rows4.M>128"}, {"gemm.small", "gemm.small.K>128"},
+          {"gemm.mfma64x64", "gemm.mfma64x64.M>128"}, {"gemm.mfma64x16", "gemm.mfma64x16.M>128"},
+          {"gemm.mfma16x64", "gemm.mfma16x64.M>128"}, {"gemm.mfma32x32", "gemm.mfma32x32.M>128"},
+          {"gemm.mfma16x16", "gemm.mfma16x16.M>128"}};
       const bool big = (kind == 5 || kind == 9) ? K > 128 : J.M > 128;
       Profiler::get().hit(names[kind][big ? 1 : 0], (long long)np);
     }
@@ -3018,8 +3138,9 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
       if (by[kd].empty()) continue;
       ++kinds;
       for (const auto& J : by[kd]) {
-        total += kd >= 1 && kd <= 4 ? (long long)J.nmat * J.ncl * ((J.M + 63) / 64) * ((J.N + 63) / 64)
-                                    : gjob_blocks(J);
+        total += (kd >= 1 && kd <= 4) || kd >= 11
+                     ? (long long)J.nmat * J.ncl * ((J.M + 63) / 64) * ((J.N + 63) / 64)
+                     : gjob_blocks(J);
       }
     }
     if (kinds > 1 && total <= kSmallLaunch && force_tile < 0) {
@@ -3032,8 +3153,8 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
         f += fl[kd];
         by_ += bytes[kd];
         for (auto J : by[kd]) {
-          if (kd >= 1 && kd <= 4) {
-            J.kind = 0;
+          if ((kd >= 1 && kd <= 4) || kd >= 11) {   // widened to the 64 x 64 tile of its engine
+            J.kind = kd >= 11 ? 10 : 0;
             J.tilesM = (J.M + 63) / 64;
             J.tilesN = (J.N + 63) / 64;
           }
@@ -3079,6 +3200,16 @@ void ggemm(hipStream_t st, std::vector<GJob> jobs, const std::vector<GSeg>& segs
     auto go = [&](const char* name, auto kern, int threads) {
       launch(st, KC_GEMM, fl[kd], bytes[kd], name, kern, grid, dim3(threads), 0, dj, nj, dsegs);
     };
+    if (kd >= 10) {   // FP32 tiles on the matrix cores
+      switch (kd) {
+        case 10: go(KNAME0(k_ggemm_mfma<64, 64, 2, 2, 16>), k_ggemm_mfma<64, 64, 2, 2, 16>, 256); break;
+        case 11: go(KNAME0(k_ggemm_mfma<64, 16, 1, 1, 16>), k_ggemm_mfma<64, 16, 1, 1, 16>, 64); break;
+        case 12: go(KNAME0(k_ggemm_mfma<16, 64, 1, 1, 16>), k_ggemm_mfma<16, 64, 1, 1, 16>, 64); break;
+        case 13: go(KNAME0(k_ggemm_mfma<32, 32, 1, 1, 16>), k_ggemm_mfma<32, 32, 1, 1, 16>, 64); break;
+        default: go(KNAME0(k_ggemm_mfma<16, 16, 1, 1, 16>), k_ggemm_mfma<16, 16, 1, 1, 16>, 64); break;
+      }
+      continue;
+    }
     switch (kd) {
       case 0: go(KNAME_T(k_ggemm<T, 64, 64, 16, 4, 4>), k_ggemm<T, 64, 64, 16, 4, 4>, 256); break;
       case 1: go(KNAME_T(k_ggemm<T, 64, 16, 16, 4, 4>), k_ggemm<T, 64, 16, 16, 4, 4>, 64); break;
@@ -3367,7 +3498,8 @@ int tune_gemm(hipStream_t st, int M, int N, int kbits, int pbits) {
   J.M = M; J.N = N; J.nmat = (int)np; J.ncl = 1; J.C = bop(C.get(), M, (long long)M * N); J.seg0 = 0; J.nseg = 1;
   int best = -1;
   double bt = 1e300;
-  for (int kind = 0; kind < 5; ++kind) {
+  for (int kind : {0, 1, 2, 3, 4, 10, 11, 12, 13, 14}) {
+    if (kind >= 10 && sizeof(T) != 4) break;
     const double t = time_on_device(st, 5, [&] { ggemm<T>(st, {J}, {g}, kind); });
     if (t < bt) { bt = t; best = kind; }
   }

@@ -71,3 +71,52 @@ def test_autotuner_table(gpu, tmp_path):
         gpu.acr_tune_load(p3)
     assert ei.value.name == "ACR_ERR_INVALID_ARG"
     gpu.acr_tune_clear()
+
+
+def test_mfma_tiles(gpu, tmp_path):
+    """FP32 GEMM tiles on the matrix cores (kinds 10..14, picked only through the
+    table): the five MFMA tiles give the same bits as each other, the results stay
+    within the mixed-precision bound of the oracle, and the profiler shows the
+    MFMA tiles ran."""
+    import torch
+    from bounds import mixed_forward_bound
+    st, leaf, eps = W.varkappa(128), 32, 1e-8
+    b = W.rhs(st.n, 2, seed=W.seed_for(3, 720))
+    op = _op(gpu, st)
+
+    def solve():
+        h = gpu.acr_factor(op, leaf, eps, "mixed")
+        x = gpu.acr_solve(h, torch.from_numpy(b).cuda()).cpu().numpy()
+        gpu.acr_destroy(h)
+        return x
+
+    gpu.acr_tune_clear()
+    gpu.acr_tune_record(True)
+    x_vec = solve()
+    gpu.acr_tune_record(False)
+    gpu.acr_tune_run()
+    path = tmp_path / "t.json"
+    gpu.acr_tune_save(path)
+    table = json.loads(path.read_text())
+    keys = [k for k in table["entries"] if k.startswith("gemm.f.")]
+    assert keys
+    xo = OA.solve(OA.factor(st, leaf, eps), st, b)
+    outs = []
+    for kind in (10, 11, 12, 13, 14):
+        t = dict(table, entries={k: kind for k in keys})
+        p = tmp_path / f"k{kind}.json"
+        p.write_text(json.dumps(t))
+        gpu.acr_tune_load(p)
+        gpu.acr_profile_start(None)
+        outs.append(solve())
+        paths = gpu.acr_profile_report().get("paths", {})
+        gpu.acr_profile_start([])
+        assert any(k.startswith("gemm.mfma") for k in paths), paths
+    for x in outs[1:]:
+        assert np.array_equal(x, outs[0])
+    e_m = np.linalg.norm(outs[0] - xo) / np.linalg.norm(xo)
+    e_v = np.linalg.norm(x_vec - xo) / np.linalg.norm(xo)
+    print(f"mixed vs oracle: vector tiles {e_v:.2e}, MFMA tiles {e_m:.2e} (bound {mixed_forward_bound(eps):.1e}); "
+          f"{len(keys)} FP32 GEMM keys, tuner picks {sorted(set(table['entries'][k] for k in keys))}")
+    assert e_m <= mixed_forward_bound(eps) and e_v <= mixed_forward_bound(eps)
+    gpu.acr_tune_clear()
