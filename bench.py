@@ -53,7 +53,7 @@ def parse():
                     help="instead of the benchmark workload, time the paper's recirculating flow "
                          "(-Laplace u + ALPHA (cos 8 pi x, sin 8 pi y) . grad u, upwind) on the --n grid: "
                          "FP32 factor + FGMRES to --tol")
-    ap.add_argument("--config", type=int, default=2, choices=(2, 3, 5),
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4, 5),
                     help="2: the 1024^2 variable-kappa headline workload; 3: 256 independent problems of "
                          "sides 64..256 (Poisson / variable kappa, leaf 32, eps 1e-8, 8 RHS) factored and "
                          "solved as one batch; 5: the serving loop over 12 operators under Poisson arrivals")
@@ -136,6 +136,141 @@ def bench_krylov_workload(acr, torch, W, args):
                       "preconditioner_applications": m["preconditioner_applications"], "relres": m["relres"],
                       "factor_max_rank": info["max_rank"], "factor_bytes": info["factor_bytes"],
                       "fp64": res["fp64"]}), flush=True)
+
+
+def _median_ms(torch, fn, steps):
+    ts = []
+    for _ in range(max(steps, 1)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def bench_config1(acr, torch, W, args):
+    """Config 1: Poisson 64 x 64 (64 blocks of 64), FP64 ACR at leaf 16, eps 1e-10, one N(0,1)
+    right-hand side; a step is factor + one solve (no refinement).  The oracle leg times the CPU
+    ACR on the same problem and gives the forward errors against it, against exact block cyclic
+    reduction and against LU."""
+    import numpy as np
+    st = W.poisson(64)
+    leaf, eps = 16, 1e-10
+    op = acr.Operator.from_arrays(st.nx, st.ny, *st.arrays())
+    b = W.rhs(st.n, 1)
+    bd = torch.from_numpy(b).cuda()
+    out = {}
+
+    def step():
+        h = acr.acr_factor(op, leaf, eps, "fp64")
+        out["x"] = acr.acr_solve(h, bd)
+        acr.acr_destroy(h)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    c0 = acr.acr_launch_count()
+    ms = _median_ms(torch, step, args.steps)
+    launches = (acr.acr_launch_count() - c0) / max(args.steps, 1)
+    x = out["x"].cpu().numpy()
+    line = {"metric": "ACR factor+solve unknowns/s, Poisson 64x64 FP64", "value": st.n / (ms / 1e3),
+            "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "h^2-scaled Poisson 64x64 (64 blocks of 64), 5-point, Dirichlet, FP64 ACR, "
+                                   "leaf 16, eps 1e-10, 1 RHS N(0,1), factor + one solve (median of steps)"},
+            "launches_per_step": launches}
+    if not args.no_cpu_baseline:
+        line.update(config1_oracle_leg(st, b, x, leaf, eps))
+    print(json.dumps(line), flush=True)
+
+
+def config1_oracle_leg(st, b, x, leaf, eps):
+    """CPU side of config 1: the oracle ACR timed in full (median of three) and the GPU
+    solution's forward errors against it, exact BCR and LU."""
+    import numpy as np
+    from oracle import acr as oacr
+    from oracle import bcr, direct
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        xo = oacr.solve(oacr.factor(st, leaf, eps), st, b)
+        ts.append(time.perf_counter() - t0)
+    t = sorted(ts)[1]
+    rel = lambda u, v: float(np.linalg.norm(u - v) / np.linalg.norm(v))
+    host = host_description()
+    return {"forward_error": {"vs_oracle_acr": rel(x, xo), "vs_exact_bcr": rel(x, bcr.bcr_solve(st, b)),
+                              "vs_lu": rel(x, direct.solve(st, b)), "gate_ten_eps": 10 * eps},
+            "cpu_baseline": {"value": st.n / t, "unit": "unknowns/s", "cores": host["blas_threads"] or host["nproc"],
+                             "kind": "oracle", "sample": "the whole workload (oracle ACR factor + solve, median "
+                                                         "of three, not extrapolated)", "host": host}}
+
+
+def bench_config4(acr, torch, W, args):
+    """Config 4: upwind convection-diffusion 512 x 512, leaf 64, eps 1e-7, 64 N(0,1) right-hand
+    sides; a step is the FP32 factor + FP64 refinement of all 64 columns to --tol (the FP32 solve
+    passes take the 64 columns at once), next to the FP64 form.  The oracle leg gives the forward
+    error of one solve on the first block rows (the oracle's bounded sample)."""
+    import numpy as np
+    st = W.make("convdiff", 512, 4)
+    leaf, eps, nrhs = 64, 1e-7, 64
+    op = acr.Operator.from_arrays(st.nx, st.ny, *st.arrays())
+    B = torch.from_numpy(W.rhs(st.n, nrhs, seed=W.seed_for(4, 9))).cuda()
+    res = {}
+    for prec in ("mixed", "fp64"):
+        info = {}
+
+        def step():
+            h = acr.acr_factor(op, leaf, eps, prec)
+            _, its, rel = acr.acr_solve_refined(h, op, B, tol=args.tol, maxit=50)
+            info.update(its=its, rel=rel)
+            acr.acr_destroy(h)
+
+        for _ in range(max(args.warmup, 1)):
+            step()
+        ms = _median_ms(torch, step, args.steps)
+        res[prec] = {"ms_per_step": ms, "rhs_unknowns_per_s": st.n * nrhs / (ms / 1e3),
+                     "refine_iterations": info["its"], "relres": info["rel"]}
+    line = {"metric": "ACR factor + 64-RHS refined solve, RHS-unknowns/s, convection-diffusion 512x512",
+            "value": res["mixed"]["rhs_unknowns_per_s"], "unit": "rhs-unknowns/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["mixed"]["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "upwind convection-diffusion 512x512, beta = 1000 (cos t, sin t), t = pi g, "
+                                   "leaf 64, eps 1e-7, 64 RHS N(0,1); FP32 factor + FP64 refinement of the 64 "
+                                   f"columns to {args.tol:g}"},
+            "mixed": res["mixed"], "fp64": res["fp64"],
+            "mixed_over_fp64": res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]}
+    if not args.no_cpu_baseline:
+        strip = W.strip(st, args.cpu_rows)
+        sop = acr.Operator.from_arrays(strip.nx, strip.ny, *strip.arrays())
+        bs = W.rhs(strip.n, nrhs, seed=W.seed_for(4, 10))
+        xs = {}
+        for prec in ("fp64", "mixed"):
+            h = acr.acr_factor(sop, leaf, eps, prec)
+            xs[prec] = acr.acr_solve(h, torch.from_numpy(bs).cuda()).cpu().numpy()
+            acr.acr_destroy(h)
+        line.update(config4_oracle_leg(strip, bs, xs, leaf, eps, st.ny))
+    print(json.dumps(line), flush=True)
+
+
+def config4_oracle_leg(strip, bs, xs, leaf, eps, rows_full):
+    """CPU side of config 4: the oracle ACR on a strip of block rows with 64 right-hand
+    sides, timed and scaled by block eliminations, and the forward errors of the GPU solves."""
+    import numpy as np
+    from oracle import acr as oacr
+    t0 = time.perf_counter()
+    xo = oacr.solve(oacr.factor(strip, leaf, eps), strip, bs)
+    dt = time.perf_counter() - t0
+    est = dt * (rows_full - 1) / (strip.ny - 1)
+    rel = lambda u, v: float(np.max(np.linalg.norm(u - v, axis=0) / np.linalg.norm(v, axis=0)))
+    host = host_description()
+    return {"forward_error_strip": {"rows": strip.ny, "fp64": rel(xs["fp64"], xo), "mixed": rel(xs["mixed"], xo),
+                                    "gate_ten_eps": 10 * eps},
+            "cpu_baseline": {"value": strip.nx * rows_full * bs.shape[1] / est, "unit": "rhs-unknowns/s",
+                             "cores": host["blas_threads"] or host["nproc"], "kind": "oracle",
+                             "sample": f"oracle ACR factor + 64-RHS solve of the first {strip.ny} block rows: "
+                                       f"{dt:.1f} s, scaled to the {rows_full - 1} block eliminations of the grid",
+                             "host": host}}
 
 
 def bench_batched(acr, torch, W, args):
@@ -622,8 +757,14 @@ def main():
     if args.threed:
         bench_threed(acr, torch, W, args)
         return
+    if args.config == 1:
+        bench_config1(acr, torch, W, args)
+        return
     if args.config == 3:
         bench_batched(acr, torch, W, args)
+        return
+    if args.config == 4:
+        bench_config4(acr, torch, W, args)
         return
     if args.config == 5:
         bench_serving(acr, torch, W, args)

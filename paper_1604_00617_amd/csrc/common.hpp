@@ -481,6 +481,8 @@ class Queue {
     ++last_fill_->count;
     return true;
   }
+  // The fill just recorded takes later consecutive fills, as long as it is
+  // still pending (recording it may have flushed the queue).
   void set_fill(hipStream_t st, std::shared_ptr<ZeroArgs> z) {
     if (st == st_ && !ops_.empty()) last_fill_ = std::move(z);
   }
@@ -613,11 +615,15 @@ inline void memset_async(void* p, int v, size_t bytes, hipStream_t st) {
   if (q.dry()) return;
   if (!q.append_fill(st, p, bytes)) {
     ++launch_count();
+    // the new fill holds its first range before it is recorded: recording may
+    // flush the queue (and run the fill) at once, and later fills then start
+    // a launch of their own
     auto z = std::make_shared<ZeroArgs>();
-    z->count = 0;
+    z->count = 1;
+    z->p[0] = static_cast<unsigned char*>(p);
+    z->n[0] = bytes;
     q.op(st, [=]() { zero_bytes_now(*z, st); });
     q.set_fill(st, z);
-    q.append_fill(st, p, bytes);
   }
 }
 inline void copy_d2d_async(void* dst, const void* src, size_t bytes, hipStream_t st) {

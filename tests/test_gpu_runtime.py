@@ -106,3 +106,55 @@ def test_torch_allocator_hook(gpu):
         gc.collect()
         gpu.acr_set_allocator(None, None)
     assert torch.cuda.memory_allocated() <= before
+
+
+def test_poisoned_memory_batched(gpu):
+    """Every fresh device block the library takes is filled with NaN bytes
+    (0xFF) by the allocator hook: a factorisation that read memory it had not
+    written (a zero fill that never ran, a dummy matrix left unset) would carry
+    NaN into its result.  A batch of mixed sizes, factored and solved twice
+    with the pool trimmed in between, gives the same bits as without poison,
+    in FP64 and in the mixed form."""
+    import torch
+    rng = np.random.default_rng(W.seed_for(3, 950))
+    sides = rng.choice([64, 96, 128], size=40)
+    probs = [W.poisson(int(s)) if i % 2 else W.varkappa(int(s), seed=W.seed_for(3, 960 + i))
+             for i, s in enumerate(sides)]
+    ops = [_op(gpu, st) for st in probs]
+    Bs = [torch.from_numpy(W.rhs(st.n, 3, seed=W.seed_for(3, 990 + i))).cuda() for i, st in enumerate(probs)]
+
+    def run(prec):
+        hs = gpu.acr_factor_batched(ops, 32, 1e-8, prec)
+        xs = [x.cpu().numpy() for x in gpu.acr_solve_batched(hs, Bs)]
+        for h in hs:
+            gpu.acr_destroy(h)
+        return xs
+
+    ref = {p: run(p) for p in ("fp64", "mixed")}
+    gc.collect()
+    gpu.acr_trim_pool()
+    live = {}
+
+    def alloc(nbytes, stream):
+        t = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        t.fill_(255)
+        live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def free(ptr, stream):
+        live.pop(ptr, None)
+
+    gpu.acr_set_allocator(alloc, free)
+    try:
+        for rep in range(2):
+            for p in ("fp64", "mixed"):
+                xs = run(p)
+                for i, (a, b) in enumerate(zip(xs, ref[p])):
+                    assert np.all(np.isfinite(a)), f"{p} rep {rep}: problem {i} has non-finite values"
+                    assert np.array_equal(a, b), f"{p} rep {rep}: problem {i} differs under poisoned memory"
+            gc.collect()
+            gpu.acr_trim_pool()
+    finally:
+        gc.collect()
+        gpu.acr_trim_pool()
+        gpu.acr_set_allocator(None, None)
