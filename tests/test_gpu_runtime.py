@@ -158,3 +158,71 @@ def test_poisoned_memory_batched(gpu):
         gc.collect()
         gpu.acr_trim_pool()
         gpu.acr_set_allocator(None, None)
+
+
+def _poisoned(gpu, torch):
+    """Allocator hook handing out NaN-filled (0xFF) device blocks."""
+    live = {}
+
+    def alloc(nbytes, stream):
+        t = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        t.fill_(255)
+        live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def free(ptr, stream):
+        live.pop(ptr, None)
+
+    return alloc, free
+
+
+def test_poisoned_memory_entry_points(gpu):
+    """The same check for the other factor and solve paths: solo factors of both
+    precisions with refinement and FGMRES, early stop, dense-block and 3-D
+    operators.  Every result equals the one computed on ordinary memory."""
+    import torch
+    st = W.varkappa(256)
+    op = _op(gpu, st)
+    b = torch.from_numpy(W.rhs(st.n, 2, seed=5)).cuda()
+    s3 = W.varkappa3d(16)
+    op3 = gpu.Operator3d.from_arrays(s3.nx, s3.ny, s3.nz, *s3.arrays())
+    b3 = torch.from_numpy(W.rhs(s3.n, 1, seed=6)).cuda()
+    sd = W.varkappa(64)
+    from oracle import direct
+    D, E, F = direct.blocks(sd)
+    dop = gpu.DenseOperator.from_blocks(D, E, F)
+    bd = torch.from_numpy(W.rhs(sd.n, 1, seed=7)).cuda()
+
+    def run():
+        out = []
+        for prec in ("fp64", "mixed"):
+            h = gpu.acr_factor(op, 64, 1e-6, prec)
+            out.append(gpu.acr_solve(h, b).cpu().numpy())
+            out.append(gpu.acr_solve_refined(h, op, b, tol=1e-10)[0].cpu().numpy())
+            out.append(gpu.acr_solve_krylov(h, op, b, tol=1e-10)[0].cpu().numpy())
+            gpu.acr_destroy(h)
+            h = gpu.acr_factor(op, 64, 1e-6, prec, stop_blocks=4)
+            out.append(gpu.acr_solve(h, b).cpu().numpy())
+            gpu.acr_destroy(h)
+            h = gpu.acr_factor_3d(op3, 32, 1e-4, prec)
+            out.append(gpu.acr_solve_krylov(h, op3, b3, tol=1e-10)[0].cpu().numpy())
+            gpu.acr_destroy(h)
+            h = gpu.acr_factor_dense(dop, 16, 1e-8, prec)
+            out.append(gpu.acr_solve(h, bd).cpu().numpy())
+            gpu.acr_destroy(h)
+        return out
+
+    ref = run()
+    gc.collect()
+    gpu.acr_trim_pool()
+    alloc, free = _poisoned(gpu, torch)
+    gpu.acr_set_allocator(alloc, free)
+    try:
+        got = run()
+    finally:
+        gc.collect()
+        gpu.acr_trim_pool()
+        gpu.acr_set_allocator(None, None)
+    for i, (a, r) in enumerate(zip(got, ref)):
+        assert np.all(np.isfinite(a)), f"result {i} has non-finite values under poisoned memory"
+        assert np.array_equal(a, r), f"result {i} differs under poisoned memory"
