@@ -3642,6 +3642,8 @@ void bapply_q(hipStream_t st, int p, int c, int t, int nmat, int ncl, const T* V
   gapply_q<T>(st, std::move(jobs));
 }
 
+constexpr int kSvdMaxCore = 1024;
+
 template <typename T>
 void grsvd(hipStream_t st, std::vector<SJob> jobs) {
   // Cores of size 48..64 go to k_grsvd_reg first; the few whose numerical rank
@@ -3654,16 +3656,16 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
   // those run one wave each (launch 2), so that many more fit on a CU.
   constexpr size_t kStatic = 21504;   // static LDS of k_grsvd_t<T, 4, 512> (21000 bytes in FP32)
   std::vector<DBuf<T>> scratch;
-  std::vector<SJob> use[4], reg;
+  std::vector<SJob> use[5], reg;
   Profiler& P = Profiler::get();
   const bool prof = P.on(KC_SVD);
   double* fl = nullptr;
-  long long b0[4] = {0, 0, 0, 0}, total = 0, nreg = 0, nsmall = 0;
-  size_t dyn[4] = {0, 0, 0, 0};
-  double by[4] = {0, 0, 0, 0};
+  long long b0[5] = {0, 0, 0, 0, 0}, total = 0, nreg = 0, nsmall = 0;
+  size_t dyn[5] = {0, 0, 0, 0, 0};
+  double by[5] = {0, 0, 0, 0, 0};
   for (auto& J : jobs) {
     if (J.c <= 0 || J.nprob <= 0) continue;
-    if (J.c > 512) fail(ACR_ERR_INVALID_ARG, "rank-revealing SVD core larger than 512");
+    if (J.c > kSvdMaxCore) fail(ACR_ERR_INVALID_ARG, "rank-revealing SVD core larger than 1024");
     total += J.nprob;
     if (J.c <= 16) nsmall += J.nprob;
   }
@@ -3705,10 +3707,10 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     J.lds = 1;
     if (g == 0 && need + kStatic > kMaxLds) {
       if (need + kStatic <= kMaxLdsLarge) g = 1;
-      else { J.lds = 0; g = 3; }
+      else { J.lds = 0; g = J.c > 512 ? 4 : 3; }
     }
     {
-      static const char* names[4] = {"svd.lds", "svd.lds_large", "svd.wave16", "svd.global"};
+      static const char* names[5] = {"svd.lds", "svd.lds_large", "svd.wave16", "svd.global", "svd.global1024"};
       Profiler::get().hit(J.redo ? "svd.reg" : names[g], J.nprob);
       Profiler::get().hit(J.c <= 16 ? "svd.c<=16" : J.c <= 32 ? "svd.c17-32" : J.c < 48 ? "svd.c33-47"
                           : J.c <= 64 ? "svd.c48-64" : "svd.c>64", J.nprob);
@@ -3732,8 +3734,9 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
            (int)reg.size());
   }
   // launches: 0 and 1 in LDS (64 KB / the full workgroup LDS), 2 the small
-  // one-wave cores, 3 the cores that work in global scratch
-  for (int g = 0; g < 4; ++g) {
+  // one-wave cores, 3 the cores that work in global scratch, 4 those of more
+  // than 512 columns
+  for (int g = 0; g < 5; ++g) {
     if (use[g].empty()) continue;
     const SJob* dj = upload(use[g], st);
     const int nj = (int)use[g].size();
@@ -3744,6 +3747,9 @@ void grsvd(hipStream_t st, std::vector<SJob> jobs) {
     } else if (g == 3) {
       launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd_t<T, 4, 512, false>), k_grsvd_t<T, 4, 512, false>, grid,
              dim3(256), 0, dj, nj);
+    } else if (g == 4) {
+      launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd_t<T, 4, kSvdMaxCore, false>),
+             k_grsvd_t<T, 4, kSvdMaxCore, false>, grid, dim3(256), 0, dj, nj);
     } else {
       if (g == 1) allow_large_lds(reinterpret_cast<const void*>(k_grsvd_t<T, 4, 512, true>), kMaxLdsLarge - kStatic);
       launch(st, KC_SVD, 0.0, by[g], KNAME_T(k_grsvd_t<T, 4, 512, true>), k_grsvd_t<T, 4, 512, true>, grid,

@@ -297,3 +297,32 @@ def test_dense_operator_vs_oracle(gpu, prec):
         assert _relerr(x, xd) <= 1e-6
         X0 = gpu.acr_get_block(h, 0, 0, 0)
         assert np.abs(X0 - hodlr.densify(fac.levels[0][0][0])).max() <= 10 * eps * np.abs(X0).max()
+
+
+def test_dense_operator_large_cores_vs_oracle(gpu):
+    """Blocks of 2048 (dense, smooth exponential kernels): the compression of the
+    depth-1 blocks gives rank-revealing SVD cores of 1024 columns, which run in
+    the SVD's global-scratch form for cores beyond 512; the factor and solve
+    match the oracle at 10 eps, and the profiler shows that form ran."""
+    import torch
+    s, ny, eps = 2048, 2, 1e-8
+    x = np.linspace(0.0, 1.0, s)
+    K = np.exp(-np.abs(x[:, None] - x[None, :]) / 0.3)
+    D = [K + 2.0 * np.eye(s), K + 2.5 * np.eye(s)]
+    Fc = 0.3 * np.exp(-np.abs(x[:, None] - x[None, :] - 0.05) / 0.2)
+    E = [np.zeros((s, s)), Fc.T.copy()]
+    F = [Fc, np.zeros((s, s))]
+    op = gpu.DenseOperator.from_blocks(D, E, F)
+    gpu.acr_profile_start(None)
+    h = gpu.acr_factor_dense(op, 128, eps, "fp64")
+    paths = gpu.acr_profile_report().get("paths", {})
+    gpu.acr_profile_start([])
+    f = W.rhs(s * ny, 2, seed=17)
+    xg = gpu.acr_solve(h, torch.from_numpy(f).cuda()).cpu().numpy()
+    fac = OA.factor_blocks(D, E, F, 128, eps)
+    xo = np.concatenate(OA.solve_blocks(fac, [f[i * s:(i + 1) * s] for i in range(ny)]), axis=0)
+    e = _relerr(xg, xo)
+    print(f"dense 2048 blocks: vs oracle {e:.2e}; ranks {gpu.acr_get_info(h)['level_max_rank']}; "
+          f"svd paths {[k for k in paths if k.startswith('svd.')]}")
+    assert e <= 10 * eps
+    assert paths.get("svd.global1024", 0) > 0, paths
