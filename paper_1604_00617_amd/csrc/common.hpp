@@ -2,6 +2,7 @@
 // memory pool, device buffers and the descriptors of batched operands.
 #pragma once
 
+#include <cstdlib>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -470,8 +471,16 @@ class Queue {
     st_ = st;
     last_fill_.reset();
     ops_.push_back(std::move(f));
-    if (ops_.size() >= kMaxPending) flush();
+    if (eager_ > 0) {   // the device is idle: issue at once while the host plans on
+      --eager_;
+      flush();
+    } else if (ops_.size() >= kMaxPending) {
+      flush();
+    }
   }
+  // After a host synchronisation the device has nothing to do: the next few
+  // operations are issued as soon as they are recorded.
+  void device_idle() { eager_ = kEagerAfterSync; }
   // Add a zero fill to the fill launch recorded last, if that is the last
   // pending op (same stream, room left); false otherwise.
   bool append_fill(hipStream_t st, void* p, size_t bytes) {
@@ -516,6 +525,8 @@ class Queue {
   static constexpr size_t kMaxPending = 24;   // keeps the device fed during long host planning
   std::vector<std::function<void()>> ops_;
   std::shared_ptr<ZeroArgs> last_fill_;
+  int eager_ = 0;
+  static constexpr int kEagerAfterSync = 2;
   hipStream_t st_ = nullptr;
   bool flushing_ = false;
   bool dry_ = false;
@@ -635,6 +646,7 @@ inline void read_to_host(void* dst, const void* src, size_t bytes, hipStream_t s
   Queue::get().flush();
   if (bytes) ACR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
   ACR_HIP(hipStreamSynchronize(st));
+  Queue::get().device_idle();
 }
 
 }  // namespace acr
