@@ -725,6 +725,36 @@ def factor_and_pass(acr, torch, op, args, precision, reps):
     return t_factor, t_pass, info, c1 - c0, c3 - c2
 
 
+def pass_modes(acr, torch, op, args, precision, reps):
+    """One-RHS solve-pass time (ms, HIP events over `reps` passes) and launches per pass in
+    each execution mode: grouped launches per step, the levels of few blocks as one
+    persistent launch, the whole pass as one persistent launch (same bits in all three)."""
+    h = acr.acr_factor(op, args.leaf, args.eps, precision)
+    b = torch.randn(op.n, dtype=torch.float64, device="cuda")
+    out = {}
+    try:
+        for mode, name in ((0, "grouped"), (1, "persistent_deep_levels"), (2, "persistent_whole_pass")):
+            acr.acr_set_solve_mode(mode)
+            acr.acr_solve(h, b)   # builds and caches the task list
+            torch.cuda.synchronize()
+            c0 = acr.acr_launch_count()
+            acr.acr_solve(h, b)
+            c1 = acr.acr_launch_count()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                acr.acr_solve(h, b)
+            e1.record()
+            torch.cuda.synchronize()
+            out[name] = {"ms": e0.elapsed_time(e1) / reps, "launches": c1 - c0}
+    finally:
+        acr.acr_set_solve_mode(0)
+        acr.acr_destroy(h)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -847,6 +877,7 @@ def main():
                     "level_mean_rank": [round(v, 2) for v in info["level_mean_rank"]]},
         "kernel_classes_ms": {k: round(v["total_ms"], 3) for k, v in table.items()},
     }
+    out["solve_pass_modes"] = pass_modes(acr, torch, op, args, "mixed", 10)
     if tuned:
         out["tuned"] = tuned
     # the same step with FGMRES (ACR as right preconditioner, FP64 Krylov vectors) in

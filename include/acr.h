@@ -225,7 +225,10 @@ acr_status acr_solve_batched(const acr_handle* hs, const double* const* B, doubl
  * u_{k+1})).  B, X: N x nrhs FP64, column-major, ld = N; X may alias B.
  * In ACR_MIXED_FP32 the pass runs in FP32 (B rounded on entry).  Asynchronous
  * on `stream` (no host synchronisation); its workspace comes from the pool on
- * every call, so the call is not meant for stream capture. */
+ * every call, so the call is not meant for stream capture.  With at most 8
+ * right-hand sides each matvec step of the pass is two grouped launches
+ * (projections, then rows) by default; acr_set_solve_mode selects a
+ * persistent launch for part or all of the pass instead. */
 acr_status acr_solve(acr_handle h, const double* B, double* X, int32_t nrhs, void* stream);
 
 /* acr_solve without any device allocation, for callers that cannot allocate
@@ -240,7 +243,9 @@ acr_status acr_solve(acr_handle h, const double* B, double* X, int32_t nrhs, voi
  * profiler event.  All calls on one GPU share that GPU's scratch and the
  * scratch keeps the last call's contents: calls that overlap in time on one
  * GPU (other threads or other streams) race and are not allowed.  The
- * handle must exist (acr_factor allocates) and its factor is read only. */
+ * handle must exist (acr_factor allocates) and its factor is read only.  It
+ * runs the pass as grouped launches per step (acr_set_solve_mode's mode 1),
+ * whose results equal the persistent pass's bit for bit. */
 acr_status acr_solve_noalloc(acr_handle h, const double* B, double* X, int32_t nrhs, void* stream);
 
 /* Iterative refinement with ACR as the preconditioner (Section 4, closing
@@ -439,6 +444,32 @@ acr_status acr_tune_save(const char* path);
 acr_status acr_tune_load(const char* path);
 /* Drop the table and the noted keys; built-in choices from now on. */
 acr_status acr_tune_clear(void);
+
+/* How solve passes with at most 8 right-hand sides and no early stop run
+ * (process-wide; the levels of the pass are those of Section 3's
+ * back-substitution).
+ *   mode 0 (default): two grouped launches per matvec step (projections,
+ *     then rows), ordered by the stream.
+ *   mode 1: the levels of at most 16 blocks, the last block and their
+ *     back-substitution as one persistent launch; the wider levels as in
+ *     mode 0.
+ *   mode 2: the whole pass as one persistent launch.
+ * In a persistent launch the matvecs are tasks (some projection units, or
+ * 256 output rows, of one block).  Workgroups take them in an order in
+ * which each task follows the tasks it reads from, wait (polling a counter,
+ * bounded) until those are done, run, and count themselves done; the waits
+ * cannot deadlock whatever number of workgroups is resident.  The task list
+ * is built on a handle's first persistent solve with a given nrhs (that call
+ * synchronises `stream` once) and kept with the handle.  Every mode computes
+ * every value with the same device code in the same order, so results are
+ * equal bit for bit across modes.  wait_limit > 0: polls a
+ * task makes on one counter before it gives up; 0: the default, 2^22 polls
+ * (seconds); < 0: every task that reads another task's output gives up (this
+ * forces the failure path).  Once a task gives up, every later wait of the
+ * launch gives up at once, every workgroup still runs to the end of the task
+ * list, and the pass's solution X is set to NaN.  ACR_ERR_INVALID_ARG for
+ * another mode. */
+acr_status acr_set_solve_mode(int32_t mode, int64_t wait_limit);
 
 /* Number of kernel launches (and device fills) the calling thread has
  * issued through the library so far (for launch counts per step). */

@@ -98,6 +98,228 @@ void plan_dense_last(GemmPlan& plan, const Factor<T>& f, const T* F, T* U, int n
   plan.add(s, nrhs, 1, m, 1.0, 0.0, bop(U + blk, s, 0, blk), sg);
 }
 
+// The persistent pass of this factor for nrhs right-hand sides: the same
+// matvec steps as the grouped solve below (forward reduction level by level,
+// the last block, back-substitution), as one task list.  Vector operands are
+// workspace offsets: F_l, G_l, U_l (with one zero pad block at each end) and
+// tmp_l for every level, then the projection buffer.
+template <typename T>
+const PPlan& Factor<T>::plan(int nrhs, int max_blocks, hipStream_t st) const {
+  std::lock_guard<std::mutex> g(plan_mu);
+  const auto key = std::make_pair(nrhs, max_blocks);
+  auto found = plans.find(key);
+  if (found != plans.end()) return *found->second;
+  if (mstop > 1 || !fused_ok(nrhs)) fail(ACR_ERR_INTERNAL, "persistent solve: unsupported factor");
+  auto P = std::make_unique<PPlan>();
+  P->NR = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8;
+  PBuilder pb(P->NR);
+  const int s = nx, nl = (int)lev.size();
+  const size_t blk = (size_t)s * nrhs * sizeof(T);
+  size_t off = 256;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  std::vector<size_t> F(nl + 1), G(nl), U(nl + 1), Tm(nl);
+  F[0] = take((size_t)ny * blk);
+  for (int l = 0; l < nl; ++l) {
+    F[l + 1] = take((size_t)(lev[l].m / 2) * blk);
+    G[l] = take((size_t)lev[l].ne * blk);
+    U[l] = take((size_t)(lev[l].m + 2) * blk);
+    Tm[l] = take((size_t)lev[l].nreal * blk);
+  }
+  U[nl] = take(3 * blk);
+  auto at = [](size_t o) { return reinterpret_cast<T*>(o); };
+  auto job = [&](int nmat, size_t out, int omul, int ooff, int term0, int nterm, const T* C0 = nullptr,
+                 int cmul = 1, int coff = 0) {
+    MVJob J = mv_job<T>(nmat, at(out), omul, ooff, term0, nterm, C0, cmul, coff, 1.0);
+    J.s = s; J.b = b; J.L = L; J.nrhs = nrhs;
+    return J;
+  };
+  // levels with more blocks than kPersistBlocks run as grouped launches
+  // before (forward) and after (backward) the persistent launch
+  int l0 = 0;
+  while (l0 < nl && lev[l0].m > max_blocks) ++l0;
+  P->l0 = l0;
+  int cur = 0;   // level of the steps being added
+  bool fwd = true;
+  auto add = [&](std::vector<MVJob> jb, std::vector<MVTerm> tm) {
+    if (cur >= l0) {
+      pb.step<T>(std::move(jb), tm);
+    } else {
+      (fwd ? P->pre : P->post).push_back(HostStep{cur, std::move(jb), std::move(tm)});
+    }
+  };
+  for (int l = 0; l < nl; ++l) {
+    const Level<T>& Lv = lev[l];
+    cur = l;
+    {  // g_k = X_k f_(2k); the dummy slot (m even) is zero
+      std::vector<MVTerm> tm{mv_hodlr<T>(Lv.X, 1, 0, at(F[l]), 2, 0, 1.0)};
+      add({job(Lv.nreal, G[l], 1, 0, 0, 1), job(Lv.ne - Lv.nreal, G[l], 1, Lv.nreal, 0, 0)}, tm);
+    }
+    const int nodd = Lv.m / 2;
+    if (nodd > 0) {  // f'_j = f_(2j+1) - E_(2j+1) g_j - F_(2j+1) g_(j+1)
+      std::vector<MVTerm> tm;
+      if (Lv.diag) {
+        tm.push_back(mv_diag<T>(Lv.e0.get(), 2, 1, at(G[l]), 1, 0, -1.0));
+        tm.push_back(mv_diag<T>(Lv.f0.get(), 2, 1, at(G[l]), 1, 1, -1.0));
+      } else {
+        tm.push_back(mv_hodlr<T>(Lv.E, 2, 1, at(G[l]), 1, 0, -1.0));
+        tm.push_back(mv_hodlr<T>(Lv.F, 2, 1, at(G[l]), 1, 1, -1.0));
+      }
+      add({job(nodd, F[l + 1], 1, 0, 0, 2, at(F[l]), 2, 1)}, tm);
+    }
+  }
+  cur = nl;
+  {  // u = X f on the last block; zero pads
+    std::vector<MVTerm> tm{mv_hodlr<T>(Xlast, 1, 0, at(F[nl]), 1, 0, 1.0)};
+    add({job(1, U[nl], 1, 1, 0, 1), job(2, U[nl], 2, 0, 0, 0)}, tm);
+  }
+  fwd = false;
+  for (int l = nl - 1; l >= 0; --l) {
+    const Level<T>& Lv = lev[l];
+    const int m = Lv.m, nodd = m / 2;
+    cur = l;
+    {  // tmp_k = E_(2k) u_(2k-1) + F_(2k) u_(2k+1)
+      std::vector<MVTerm> tm;
+      if (Lv.diag) {
+        tm.push_back(mv_diag<T>(Lv.e0.get(), 2, 0, at(U[l + 1]), 1, 0, 1.0));
+        tm.push_back(mv_diag<T>(Lv.f0.get(), 2, 0, at(U[l + 1]), 1, 1, 1.0));
+      } else {
+        tm.push_back(mv_hodlr<T>(Lv.E, 2, 0, at(U[l + 1]), 1, 0, 1.0));
+        tm.push_back(mv_hodlr<T>(Lv.F, 2, 0, at(U[l + 1]), 1, 1, 1.0));
+      }
+      add({job(Lv.nreal, Tm[l], 1, 0, 0, 2)}, tm);
+    }
+    {  // u_(2k) = g_k - X_k tmp_k; odd unknowns from level l+1; zero pads
+      std::vector<MVTerm> tm{mv_hodlr<T>(Lv.X, 1, 0, at(Tm[l]), 1, 0, -1.0)};
+      add({job(Lv.nreal, U[l], 2, 1, 0, 1, at(G[l]), 1, 0), job(nodd, U[l], 2, 2, 0, 0, at(U[l + 1]), 1, 1),
+           job(1, U[l], 1, 0, 0, 0), job(1, U[l], 1, m + 1, 0, 0)},
+          tm);
+    }
+  }
+  pb.check();
+  P->tbuf_off = (long long)take((size_t)pb.tsize * sizeof(T));
+  P->ws_bytes = off;
+  P->f0_off = (long long)F[0];
+  P->u0_off = (long long)U[0];
+  P->w64 = pb.w64;
+  P->ntasks = (int)pb.tasks.size();
+  P->nctr = pb.nctr;
+  P->flops = pb.flops;
+  P->bytes = pb.bytes;
+  const size_t bt = pb.tasks.size() * sizeof(PTask), bj = pb.jobs.size() * sizeof(MVJob),
+               bm = pb.terms.size() * sizeof(MVTerm);
+  const size_t oj = (bt + 255) & ~size_t(255), om = oj + ((bj + 255) & ~size_t(255));
+  std::vector<char> h(om + bm);
+  std::memcpy(h.data(), pb.tasks.data(), bt);
+  std::memcpy(h.data() + oj, pb.jobs.data(), bj);
+  std::memcpy(h.data() + om, pb.terms.data(), bm);
+  P->dev.resize(h.size());
+  // one upload, complete before any stream reads the plan
+  Queue::get().flush();
+  ACR_HIP(hipMemcpyAsync(P->dev.get(), h.data(), h.size(), hipMemcpyHostToDevice, st));
+  ACR_HIP(hipStreamSynchronize(st));
+  Queue::get().device_idle();
+  P->tasks = reinterpret_cast<const PTask*>(P->dev.get());
+  P->jobs = reinterpret_cast<const MVJob*>(P->dev.get() + oj);
+  P->terms = reinterpret_cast<const MVTerm*>(P->dev.get() + om);
+  const PPlan& r = *P;
+  plans[key] = std::move(P);
+  return r;
+}
+
+// X_p = M_p^{-1} B_p as one persistent launch per group of passes with the
+// same projection slots and row form, after one block-layout copy in and
+// before one copy out; the counters of all passes are cleared by one fill.
+template <typename T>
+void solve_persistent_many(const std::vector<const Factor<T>*>& fs, const std::vector<const double*>& Bs,
+                           const std::vector<double*>& Xs, const std::vector<int>& nrs, int max_blocks,
+                           hipStream_t st) {
+  const int P = (int)fs.size();
+  std::vector<const PPlan*> pl(P);
+  size_t nctr = 0;
+  for (int p = 0; p < P; ++p) {
+    pl[p] = &fs[p]->plan(nrs[p], max_blocks, st);
+    nctr += (size_t)pl[p]->nctr;
+  }
+  std::vector<DBuf<char>> ws(P);
+  DBuf<int> ctr(nctr + 2 * 8 + 1);   // pass counters, then (ticket, abort word) per launch group
+  memset_async(ctr.get(), 0, ctr.bytes(), st);
+  std::vector<VJob> tb, fb;
+  std::vector<PInst> in(P);
+  size_t c0 = 0;
+  for (int p = 0; p < P; ++p) {
+    const Factor<T>& f = *fs[p];
+    ws[p].resize(pl[p]->ws_bytes);
+    VJob J;
+    J.s = f.nx; J.nblk = f.ny; J.nrhs = nrs[p]; J.ld = (long long)f.nx * f.ny;
+    J.src = Bs[p]; J.dst = ws[p].get() + pl[p]->f0_off;
+    tb.push_back(J);
+    J.src = ws[p].get() + pl[p]->u0_off + (long long)f.nx * nrs[p] * sizeof(T); J.dst = Xs[p];
+    fb.push_back(J);
+    PInst& I = in[p];
+    I.tasks = pl[p]->tasks; I.jobs = pl[p]->jobs; I.terms = pl[p]->terms; I.ntasks = pl[p]->ntasks;
+    I.ws = ws[p].get(); I.ctr = ctr.get() + c0; I.tbuf_off = pl[p]->tbuf_off;
+    c0 += (size_t)pl[p]->nctr;
+  }
+  gto_blocks<T>(st, tb);
+  // grouped steps of the wide levels, merged over the problems step by step
+  // (every plan lists its steps of one direction in the same level order)
+  auto grouped = [&](bool pre) {
+    size_t most = 0;
+    for (int p = 0; p < P; ++p) most = std::max(most, (pre ? pl[p]->pre : pl[p]->post).size());
+    for (size_t i = 0; i < most; ++i) {
+      std::vector<MVJob> jb;
+      std::vector<MVTerm> tm;
+      for (int p = 0; p < P; ++p) {
+        const auto& list = pre ? pl[p]->pre : pl[p]->post;
+        // backward steps are aligned at level 0 (the last ones of every list)
+        const long long k = pre ? (long long)i : (long long)i - (long long)(most - list.size());
+        if (k < 0 || k >= (long long)list.size()) continue;
+        const HostStep& h = list[(size_t)k];
+        const uintptr_t base = reinterpret_cast<uintptr_t>(ws[p].get());
+        const int t0 = (int)tm.size();
+        for (MVTerm M : h.terms) {
+          M.y = reinterpret_cast<const void*>(base + reinterpret_cast<uintptr_t>(M.y));
+          tm.push_back(M);
+        }
+        for (MVJob J : h.jobs) {
+          J.out = reinterpret_cast<void*>(base + reinterpret_cast<uintptr_t>(J.out));
+          if (J.C0) J.C0 = reinterpret_cast<const void*>(base + reinterpret_cast<uintptr_t>(J.C0));
+          J.term0 += t0;
+          jb.push_back(J);
+        }
+      }
+      PhaseScope ph(pre ? "solve forward" : "solve backward");
+      ghmv<T>(st, jb, tm);
+    }
+  };
+  grouped(true);
+  // one launch per (NR, row form) group
+  int grp = 0;
+  for (int nr : {1, 2, 4, 8})
+    for (int w : {1, 0}) {
+      std::vector<PInst> gi;
+      std::vector<VJob> gf;
+      double fl = 0, by = 0;
+      for (int p = 0; p < P; ++p)
+        if (pl[p]->NR == nr && (int)pl[p]->w64 == w) {
+          gi.push_back(in[p]);
+          gf.push_back(fb[p]);
+          fl += pl[p]->flops;
+          by += pl[p]->bytes;
+        }
+      if (gi.empty()) continue;
+      PhaseScope ph("solve persistent", -1);
+      psolve_run<T>(st, gi, nr, w == 1, ctr.get() + nctr + 2 * grp, gf, fl, by);
+      ++grp;
+    }
+  grouped(false);
+  gfrom_blocks<T>(st, fb);
+}
+
 // Few right-hand sides (<= 8 per problem): every step of a level is one
 // multi-term matvec, for all problems at once (levels counted from the top
 // going down, from each problem's last level going up).  U[l] holds the
@@ -106,6 +328,15 @@ template <typename T>
 void solve_fused_many(const std::vector<const Factor<T>*>& fs, const std::vector<const double*>& Bs,
                       const std::vector<double*>& Xs, const std::vector<int>& nrs, hipStream_t st) {
   const int P = (int)fs.size();
+  {   // the deep levels or the whole pass as one persistent launch, when asked for
+    const int mode = SolveMode::get().mode.load();
+    bool persist = mode != 0 && !Bump::cur() && !Queue::get().dry();
+    for (int p = 0; p < P && persist; ++p) persist = fs[p]->mstop == 1 && fs[p]->fused_ok(nrs[p]);
+    if (persist) {
+      solve_persistent_many<T>(fs, Bs, Xs, nrs, mode == 2 ? INT32_MAX : kPersistBlocks, st);
+      return;
+    }
+  }
   struct PV {
     std::vector<DBuf<T>> F, G, U;
     size_t blk = 0;
@@ -1008,7 +1239,7 @@ void refine_body(acr_handle h, long long n, const double* B, double* X, int nrhs
     rel = 0.0;
     for (int q = 0; q < nrhs; ++q) {
       const double v = hb[q] > 0 ? std::sqrt(hr[q] / hb[q]) : std::sqrt(hr[q]);
-      rel = std::max(rel, v);
+      rel = nan_max(rel, v);
     }
     if (!(rel > tol) || its >= maxit || !std::isfinite(rel)) break;
     h->f->solve(R.get(), D.get(), nrhs, st);
@@ -1105,7 +1336,7 @@ void krylov_body(acr_handle h, long long n, const double* B, double* X, int nrhs
       }
     }
     its_all = std::max(its_all, its);
-    rel_all = std::max(rel_all, rel);
+    rel_all = nan_max(rel_all, rel);
   }
   if (!(rel_all <= tol))
     fail(ACR_ERR_NOT_CONVERGED, "FGMRES stopped at relative residual " + std::to_string(rel_all));
@@ -1555,6 +1786,14 @@ acr_status acr_profile_report(char* buf, int64_t len, int64_t* needed) {
 }
 
 int64_t acr_launch_count(void) { return (int64_t)launch_count(); }
+
+acr_status acr_set_solve_mode(int32_t mode, int64_t wait_limit) {
+  return guard([&] {
+    if (mode < 0 || mode > 2) fail(ACR_ERR_INVALID_ARG, "solve mode must be 0, 1 or 2");
+    SolveMode::get().mode = mode;
+    SolveMode::get().limit = wait_limit == 0 ? (1LL << 22) : wait_limit;
+  });
+}
 
 acr_status acr_tune_record(int32_t on) {
   return guard([&] { Tuner::get().recording = on != 0; });

@@ -2,7 +2,10 @@
 // shared by the library's C ABI files (acr.hip, serve.hip).
 #pragma once
 
+#include <cmath>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <vector>
@@ -28,6 +31,34 @@ struct Level {
   bool diag = false;
   DBuf<T> e0, f0;   // level 0: diagonals of E_i, F_i ([m][s])
   HSet<T> E, F;     // level >= 1: m HODLR blocks each
+};
+
+// The persistent solve pass of one factor for one number of right-hand
+// sides: its task list in device memory (built once, read-only afterwards)
+// and the layout of the workspace every pass allocates (byte offsets; the
+// first 256 bytes are unused, so that no operand offset is zero).
+// A matvec step run as a grouped launch (the levels before the persistent
+// part): jobs and terms as for ghmv, vector operands as workspace offsets.
+struct HostStep {
+  int level = 0;
+  std::vector<MVJob> jobs;
+  std::vector<MVTerm> terms;
+};
+// In the deep-level persistent mode, levels with more blocks than this run
+// as grouped launches and the rest of the pass (deep levels, last block,
+// their back-substitution) as one persistent launch.
+constexpr int kPersistBlocks = 16;
+struct PPlan {
+  int NR = 1, ntasks = 0, nctr = 0, l0 = 0;
+  std::vector<HostStep> pre, post;   // forward steps of levels < l0; backward ones
+  bool w64 = true;
+  size_t ws_bytes = 0;
+  long long f0_off = 0, u0_off = 0, tbuf_off = 0;   // F_0 blocks, U_0 (with its leading pad block)
+  DBuf<char> dev;                                   // tasks | jobs | terms
+  const PTask* tasks = nullptr;
+  const MVJob* jobs = nullptr;
+  const MVTerm* terms = nullptr;
+  double flops = 0, bytes = 0;
 };
 
 template <typename T>
@@ -126,6 +157,11 @@ struct Factor final : FactorBase {
     }
   }
 
+  // persistent solve plans by (right-hand sides, largest grouped-level size)
+  mutable std::mutex plan_mu;
+  mutable std::map<std::pair<int, int>, std::unique_ptr<PPlan>> plans;
+  const PPlan& plan(int nrhs, int max_blocks, hipStream_t st) const;
+
   void solve(const double* B, double* Xout, int nrhs, hipStream_t st) override;
   void solve_fused(const double* B, double* Xout, int nrhs, hipStream_t st);
   void solve_gemm(const double* B, double* Xout, int nrhs, hipStream_t st);
@@ -149,6 +185,14 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
 template <typename T>
 void solve_fused_many(const std::vector<const Factor<T>*>& fs, const std::vector<const double*>& Bs,
                       const std::vector<double*>& Xs, const std::vector<int>& nrs, hipStream_t st);
+
+// max(a, b) that keeps a NaN (a NaN residual norm must stop a solver as
+// not converged, never read as zero).
+inline double nan_max(double a, double b) {
+  if (std::isnan(a)) return a;
+  if (std::isnan(b)) return b;
+  return b > a ? b : a;
+}
 
 // HODLR depth of block size s for a leaf bound (-1 if the halving is not exact).
 int hodlr_depth(int s, int leaf);

@@ -645,28 +645,32 @@ __global__ __launch_bounds__(256) void k_gemm_any(const GJob* __restrict__ jobs,
 
 // ------------------------------------------------------------ HODLR matvec
 // out = beta * C0 + sum_t alpha_t op_t y_t for a batch of blocks, in two
-// launches.  k_hmv_reduce computes, for every HODLR term, matrix, depth d and
-// node tau of that depth, the projections V_d[tau]^T y[tau] (one wave per
-// node and chunk of up to 16 columns, written to a small buffer).
-// k_hmv_apply then gives every output row to one thread: the row of the leaf
-// times y on the leaf's rows, plus U_d[row] times the projection of the
-// sibling of the row's depth-d ancestor, for every depth; no barriers, the
-// leaf and U loads are independent and coalesced over the rows of a wave.
+// steps.  The projection step computes, for every HODLR term, matrix, depth d
+// and node tau of that depth, the projections V_d[tau]^T y[tau] (one wave per
+// node and chunk of up to 16 columns, written to a small buffer).  The row
+// step then gives every output row to one thread: the row of the leaf times y
+// on the leaf's rows, plus U_d[row] times the projection of the sibling of the
+// row's depth-d ancestor, for every depth; no barriers, the leaf and U loads
+// are independent and coalesced over the rows of a wave.  Both steps run as
+// grouped launches (k_hmv_reduce, k_hmv_apply) or as tasks of the persistent
+// solve pass (k_psolve); the arithmetic is the same device code in both.
+//
+// Operand addresses y, C0 and out are taken relative to `ws` (ws = 0: they
+// are device addresses); factor addresses are device addresses.
+template <typename T>
+__device__ __forceinline__ T* wsp(const void* p, const char* ws) {
+  return gmem(reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(ws) + reinterpret_cast<uintptr_t>(p)));
+}
+
+// Projection unit `rem` (depth, node, 16-column chunk) of matrix m of term M,
+// by one whole wave.
 template <typename T, int NR>
-__global__ __launch_bounds__(256) void k_hmv_reduce(const MVRed* __restrict__ reds, int nred,
-                                                    const MVTerm* __restrict__ terms, long long nunits,
-                                                    T* __restrict__ tbuf) {
+__device__ __forceinline__ void hmv_reduce_unit(const MVTerm& M, int m, int rem, const char* ws,
+                                                T* __restrict__ tbuf, int lane) {
   constexpr int CH = 16;                               // columns per unit
   constexpr int RB = NR <= 1 ? 4 : NR <= 2 ? 2 : 1;    // rows per lane per batch
-  const long long u = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  if (u >= nunits) return;   // uniform over the wave; no barriers below
-  const int lane = threadIdx.x % WAVE;
-  const MVRed& R = reds[job_of(reds, nred, u)];
-  const MVTerm& M = terms[R.term];
   const int s = M.s, nrhs = M.nrhs;
-  const long long local = u - R.block0;
-  const int m = (int)(local / R.upm);
-  int rem = (int)(local % R.upm), d = 1;
+  int d = 1;
   for (;; ++d) {
     const int units = (1 << d) * ((M.kc[d] + CH - 1) / CH);
     if (rem < units) break;
@@ -678,7 +682,7 @@ __global__ __launch_bounds__(256) void k_hmv_reduce(const MVRed* __restrict__ re
   const long long vs = (long long)s * nrhs;
   const T* Vb = gmem(static_cast<const T*>(M.V[d])) + (long long)(M.mmul * m + M.moff) * M.k[d] * s +
                 (long long)q0 * s + (long long)node * sd;
-  const T* yb = gmem(static_cast<const T*>(M.y)) + (long long)(M.ymul * m + M.yoff) * vs + (long long)node * sd;
+  const T* yb = wsp<const T>(M.y, ws) + (long long)(M.ymul * m + M.yoff) * vs + (long long)node * sd;
   T pr[CH][NR];
 #pragma unroll
   for (int c = 0; c < CH; ++c)
@@ -724,28 +728,21 @@ __global__ __launch_bounds__(256) void k_hmv_reduce(const MVRed* __restrict__ re
   }
 }
 
-// One thread per output row (rows of all jobs' blocks numbered in order, a
-// job's rows from block0).  W64: every wave lies inside one leaf column block
-// (b and s multiples of 64), so the wave loads y on 64 leaf columns at once
-// and broadcasts each value with a lane read.
+// Output row `row` of matrix m of job J, by one thread.  W64: every wave lies
+// inside one leaf column block (b and s multiples of 64, rows in whole waves),
+// so the wave loads y on 64 leaf columns at once and broadcasts each value
+// with a lane read.
 template <typename T, int NR, bool W64>
-__global__ __launch_bounds__(64) void k_hmv_apply(const MVJob* __restrict__ jobs, int njobs,
-                                                  const MVTerm* __restrict__ terms, long long nrows,
-                                                  const T* __restrict__ tbuf) {
-  const long long g = (long long)blockIdx.x * WAVE + threadIdx.x;
-  if (g >= nrows) return;   // never with W64: the rows fill whole waves
-  const int lane = threadIdx.x;
-  const MVJob& J = jobs[job_of(jobs, njobs, g)];
+__device__ __forceinline__ void hmv_apply_row(const MVJob& J, const MVTerm* __restrict__ terms, int m, int row,
+                                              int lane, const char* ws, const T* __restrict__ tbuf) {
   const int s = J.s, b = J.b, L = J.L, nrhs = J.nrhs;
-  const long long local = g - J.block0;
-  const int m = (int)(local / s), row = (int)(local % s);
   const int l = row / b, r = row % b, nleaf = 1 << L;
   const long long vs = (long long)s * nrhs;
   T acc[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = T(0);
   if (J.C0) {
-    const T* c0 = gmem(static_cast<const T*>(J.C0)) + (long long)(J.cmul * m + J.coff) * vs + row;
+    const T* c0 = wsp<const T>(J.C0, ws) + (long long)(J.cmul * m + J.coff) * vs + row;
 #pragma unroll
     for (int q = 0; q < NR; ++q)
       if (q < nrhs) acc[q] = (T)J.beta * c0[(long long)q * s];
@@ -753,7 +750,7 @@ __global__ __launch_bounds__(64) void k_hmv_apply(const MVJob* __restrict__ jobs
   for (int t = 0; t < J.nterm; ++t) {
     const MVTerm& M = terms[J.term0 + t];
     const int mm = M.mmul * m + M.moff;
-    const T* y = gmem(static_cast<const T*>(M.y)) + (long long)(M.ymul * m + M.yoff) * vs;
+    const T* y = wsp<const T>(M.y, ws) + (long long)(M.ymul * m + M.yoff) * vs;
     T ta[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) ta[q] = T(0);
@@ -805,10 +802,138 @@ __global__ __launch_bounds__(64) void k_hmv_apply(const MVJob* __restrict__ jobs
 #pragma unroll
     for (int q = 0; q < NR; ++q) acc[q] = fma(al, ta[q], acc[q]);
   }
-  T* out = gmem(static_cast<T*>(J.out)) + (long long)(J.omul * m + J.ooff) * vs + row;
+  T* out = wsp<T>(J.out, ws) + (long long)(J.omul * m + J.ooff) * vs + row;
 #pragma unroll
   for (int q = 0; q < NR; ++q)
     if (q < nrhs) out[(long long)q * s] = acc[q];
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_hmv_reduce(const MVRed* __restrict__ reds, int nred,
+                                                    const MVTerm* __restrict__ terms, long long nunits,
+                                                    T* __restrict__ tbuf) {
+  const long long u = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  if (u >= nunits) return;   // uniform over the wave; no barriers below
+  const MVRed& R = reds[job_of(reds, nred, u)];
+  const long long local = u - R.block0;
+  hmv_reduce_unit<T, NR>(terms[R.term], (int)(local / R.upm), (int)(local % R.upm), nullptr, tbuf,
+                         threadIdx.x % WAVE);
+}
+
+// One thread per output row (rows of all jobs' blocks numbered in order, a
+// job's rows from block0).
+template <typename T, int NR, bool W64>
+__global__ __launch_bounds__(64) void k_hmv_apply(const MVJob* __restrict__ jobs, int njobs,
+                                                  const MVTerm* __restrict__ terms, long long nrows,
+                                                  const T* __restrict__ tbuf) {
+  const long long g = (long long)blockIdx.x * WAVE + threadIdx.x;
+  if (g >= nrows) return;   // never with W64: the rows fill whole waves
+  const MVJob& J = jobs[job_of(jobs, njobs, g)];
+  const long long local = g - J.block0;
+  hmv_apply_row<T, NR, W64>(J, terms, (int)(local / J.s), (int)(local % J.s), threadIdx.x, nullptr, tbuf);
+}
+
+// ------------------------------------------------- persistent solve pass
+// One launch runs the whole task list of one or more solve passes (see
+// PTask).  Workgroups take tickets in order from one counter; ticket t is
+// task t - task0 of the instance holding it.  Thread 0 waits until every
+// counter the task depends on has reached its total (polling with a sleep,
+// at most `limit` polls per counter), then the workgroup runs the task and
+// adds one to the task's own counter.
+//   * Visibility: after the workgroup barrier that follows the task, thread
+//     0 increments with release order at device scope; the waiting thread
+//     fences with acquire order at device scope before the barrier that
+//     releases its workgroup to read the inputs.  Each such release and
+//     acquire writes back or invalidates the non-coherent cache lines of the
+//     chip's L2 slices, which is why only the levels with few blocks (few
+//     tasks) run this way.
+//   * Termination: tasks are listed so that each one follows every task it
+//     waits for, and a workgroup holds one task at a time, so the earliest
+//     unfinished task that has been taken has all its inputs done.  A wait
+//     that runs out of polls (or finds the abort word set) gives up: the
+//     workgroup sets the abort word, and every later wait of the launch gives
+//     up at once, so every workgroup reaches the end of the ticket range.
+//     Tasks that gave up leave their outputs unwritten; the pass then writes
+//     NaN to its whole solution (k_pcheck).
+constexpr int kPRows = 256;   // output rows per row task (4 waves)
+constexpr int kPUnits = 8;    // projection units per projection task
+
+__device__ __forceinline__ int pinst_of(const PInst* insts, int n, long long t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (insts[mid].task0 <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, int NR, bool W64>
+__global__ __launch_bounds__(256) void k_psolve(const PInst* __restrict__ insts, int ninst, long long ntask,
+                                                int* __restrict__ ticket, int* __restrict__ abort_word,
+                                                long long limit) {
+  __shared__ long long s_t;
+  __shared__ int s_go;
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  for (;;) {
+    if (tid == 0) s_t = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const long long t = s_t;
+    if (t >= ntask) break;   // uniform over the workgroup
+    const PInst& I = insts[pinst_of(insts, ninst, t)];
+    const PTask& K = I.tasks[t - I.task0];
+    if (tid == 0) {
+      int go = 1;
+      if (limit < 0 && K.ndep > 0) {   // forced give-up (tests of the failure path)
+        __hip_atomic_store(abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        go = 0;
+      }
+      for (int e = 0; e < K.ndep && go; ++e) {
+        const int* c = I.ctr + K.dep[e];
+        long long polls = 0;
+        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < K.need[e]) {
+          if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++polls > limit) {
+            __hip_atomic_store(abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            go = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // inputs written by finished tasks are visible
+      s_go = go;
+    }
+    __syncthreads();
+    if (s_go) {
+      const char* ws = I.ws;
+      T* tbuf = reinterpret_cast<T*>(I.ws + I.tbuf_off);
+      if (K.kind == 0) {
+        const MVTerm& M = I.terms[K.idx];
+        for (int u = K.u0 + wv; u < K.u1; u += 4) hmv_reduce_unit<T, NR>(M, K.m, u, ws, tbuf, lane);
+      } else {
+        const MVJob& J = I.jobs[K.idx];
+        const int row = K.u0 + tid;
+        // W64: u1 - u0 is a multiple of 64, so whole waves take part or none
+        if (row < K.u1) hmv_apply_row<T, NR, W64>(J, I.terms, K.m, row, lane, ws, tbuf);
+      }
+    }
+    __syncthreads();   // the workgroup's stores are done before thread 0 releases them
+    if (tid == 0 && s_go) __hip_atomic_fetch_add(I.ctr + K.done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// After a persistent pass: if a wait gave up, the final unknowns of every
+// instance (the sources of the block-to-vector copy that follows) are set to
+// NaN, since some task outputs were never written.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcheck(const VJob* __restrict__ jobs, int njobs,
+                                                const int* __restrict__ abort_word) {
+  if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+  const VJob& J = jobs[job_of(jobs, njobs, blockIdx.x)];
+  const long long part = blockIdx.x - J.block0;
+  const long long n = (long long)J.s * J.nblk * J.nrhs;
+  T* V = gmem(static_cast<T*>(const_cast<void*>(J.src)));
+  for (long long e = part * 256 + threadIdx.x; e < n; e += (long long)J.per * 256) V[e] = T(NAN);
 }
 
 // ---------------------------------------------------------------- inverse
@@ -3913,6 +4038,168 @@ void ghmv(hipStream_t st, std::vector<MVJob> jobs, const std::vector<MVTerm>& te
 }
 
 template <typename T>
+void PBuilder::step(std::vector<MVJob> js, const std::vector<MVTerm>& tms) {
+  constexpr int CH = 16;
+  auto producer = [&](const void* base, long long blk, long long vs, int* dep, int* need, int& nd) {
+    auto it = prod_.find(reinterpret_cast<long long>(base) + blk * vs);
+    if (it == prod_.end()) return;   // written before the pass
+    for (int e = 0; e < nd; ++e)
+      if (dep[e] == it->second.first) return;
+    if (nd >= kPMaxDep) fail(ACR_ERR_INTERNAL, "persistent solve: too many dependencies");
+    dep[nd] = it->second.first;
+    need[nd] = it->second.second;
+    ++nd;
+  };
+  for (auto J : js) {
+    if (J.nmat <= 0) continue;
+    const int s = J.s, b = J.b, L = J.L, nrhs = J.nrhs;
+    if (nrhs < 1 || nrhs > NR) fail(ACR_ERR_INTERNAL, "persistent solve: right-hand sides above the plan's slots");
+    if (b < 1 || b > 256 || L > kMvMaxDepth || (b << L) != s) fail(ACR_ERR_INTERNAL, "matvec shape");
+    if (b % WAVE != 0) w64 = false;
+    const long long vs = (long long)s * nrhs * (long long)sizeof(T);
+    const int t0 = (int)terms.size();
+    std::vector<int> upm(J.nterm, 0);
+    for (int t = 0; t < J.nterm; ++t) {
+      MVTerm M = tms[J.term0 + t];
+      M.s = s;
+      M.nrhs = nrhs;
+      double e = s;
+      if (M.type == 0) {
+        for (int d = L + 1; d <= kMvMaxDepth; ++d) M.kc[d] = 0;
+        int off = 0;
+        for (int d = 1; d <= L; ++d) {
+          if (M.kc[d] < 0 || M.kc[d] > M.k[d]) fail(ACR_ERR_INTERNAL, "matvec: rank above the allocation");
+          upm[t] += (1 << d) * ((M.kc[d] + CH - 1) / CH);
+          M.toff[d] = off;
+          off += (1 << d) * M.kc[d] * NR;
+          const double ka = M.kmean[d] > 0.0f ? std::min<double>(M.kmean[d], M.kc[d]) : M.kc[d];
+          flops += 2.0 * J.nmat * s * ka * nrhs;
+          bytes += (double)J.nmat * s * (ka + (M.kc[d] ? nrhs : 0)) * sizeof(T);
+          e += (double)s * ka;
+        }
+        for (int d = L + 1; d <= kMvMaxDepth; ++d) M.toff[d] = off;
+        e += (double)s * (b - 1);
+        M.tstride = off;
+        M.tbase = tsize;
+        tsize += (long long)J.nmat * off;
+      }
+      flops += 2.0 * J.nmat * e * nrhs;
+      bytes += (double)J.nmat * (e + (double)s * nrhs) * sizeof(T);
+      terms.push_back(M);
+    }
+    bytes += (double)J.nmat * s * nrhs * sizeof(T) * (J.C0 ? 2 : 1);
+    J.term0 = t0;
+    J.block0 = 0;
+    const int ji = (int)jobs.size();
+    jobs.push_back(J);
+    for (int m = 0; m < J.nmat; ++m) {
+      PTask ap;
+      ap.kind = 1;
+      ap.idx = ji;
+      ap.m = m;
+      for (int t = 0; t < J.nterm; ++t) {
+        const MVTerm& M = terms[t0 + t];
+        const long long yb = (long long)M.ymul * m + M.yoff;
+        if (M.type == 0 && upm[t] > 0) {   // projection tasks of this (term, matrix)
+          const int rc = nctr++;
+          int nrt = 0;
+          for (int u = 0; u < upm[t]; u += kPUnits, ++nrt) {
+            PTask rp;
+            rp.kind = 0;
+            rp.idx = t0 + t;
+            rp.m = m;
+            rp.u0 = u;
+            rp.u1 = std::min(upm[t], u + kPUnits);
+            rp.done = rc;
+            producer(M.y, yb, vs, rp.dep, rp.need, rp.ndep);
+            tasks.push_back(rp);
+          }
+          ap.dep[ap.ndep] = rc;
+          ap.need[ap.ndep] = nrt;
+          ++ap.ndep;
+        }
+        producer(M.y, yb, vs, ap.dep, ap.need, ap.ndep);
+      }
+      if (J.C0) producer(J.C0, (long long)J.cmul * m + J.coff, vs, ap.dep, ap.need, ap.ndep);
+      const int oc = nctr++;
+      int nat = 0;
+      ap.done = oc;
+      for (int r = 0; r < s; r += kPRows, ++nat) {
+        PTask t = ap;
+        t.u0 = r;
+        t.u1 = std::min(s, r + kPRows);
+        tasks.push_back(t);
+      }
+      prod_[reinterpret_cast<long long>(J.out) + ((long long)J.omul * m + J.ooff) * vs] = {oc, nat};
+    }
+  }
+}
+
+void PBuilder::check() const {
+  std::vector<long long> total((size_t)nctr, 0), seen((size_t)nctr, 0);
+  for (const PTask& t : tasks) {
+    if (t.done < 0 || t.done >= nctr) fail(ACR_ERR_INTERNAL, "persistent solve: counter out of range");
+    ++total[(size_t)t.done];
+  }
+  for (const PTask& t : tasks) {
+    if (t.ndep < 0 || t.ndep > kPMaxDep || t.u0 < 0 || t.u1 <= t.u0)
+      fail(ACR_ERR_INTERNAL, "persistent solve: malformed task");
+    for (int e = 0; e < t.ndep; ++e) {
+      const int c = t.dep[e];
+      if (c < 0 || c >= nctr || c == t.done || t.need[e] <= 0 || seen[(size_t)c] != t.need[e] ||
+          total[(size_t)c] != t.need[e])
+        fail(ACR_ERR_INTERNAL, "persistent solve: a task waits for work listed after it");
+    }
+    ++seen[(size_t)t.done];
+  }
+}
+
+template <typename T>
+void psolve_run(hipStream_t st, std::vector<PInst> insts, int NR, bool w64, int* ctl, const std::vector<VJob>& fin,
+                double flops, double bytes) {
+  long long nt = 0;
+  for (auto& I : insts) {
+    I.task0 = nt;
+    nt += I.ntasks;
+  }
+  if (nt <= 0) return;
+  if (nt > 0x7fffffffLL) fail(ACR_ERR_INVALID_ARG, "persistent solve: too many tasks");
+  const PInst* di = upload(insts, st);
+  // one workgroup per CU: the deep levels hold a few hundred tasks at a time
+  const unsigned grid = (unsigned)std::min<long long>(nt, 256);
+  const long long limit = SolveMode::get().limit.load();
+  const int ni = (int)insts.size();
+  auto go = [&](const char* name, auto kern) {
+    launch(st, KC_MATVEC, flops, bytes, name, kern, dim3(grid), dim3(256), 0, di, ni, nt, ctl, ctl + 1, limit);
+  };
+#define ACR_PSOLVE(NRV)                                                         \
+  if (w64) go(KNAME_T(k_psolve<T, NRV, true>), k_psolve<T, NRV, true>);      \
+  else go(KNAME_T(k_psolve<T, NRV, false>), k_psolve<T, NRV, false>);
+  switch (NR) {
+    case 1: ACR_PSOLVE(1) break;
+    case 2: ACR_PSOLVE(2) break;
+    case 4: ACR_PSOLVE(4) break;
+    default: ACR_PSOLVE(8) break;
+  }
+#undef ACR_PSOLVE
+  // NaN for the final unknowns if a wait gave up (nothing happens otherwise)
+  long long b0 = 0;
+  std::vector<VJob> use;
+  for (auto J : fin) {
+    const long long n = (long long)J.s * J.nblk * J.nrhs;
+    if (n <= 0) continue;
+    J.per = (int)std::min<long long>((n + 255) / 256, 1024);
+    J.block0 = b0;
+    b0 += J.per;
+    use.push_back(J);
+  }
+  if (use.empty()) return;
+  const VJob* dj = upload(use, st);
+  launch(st, KC_OTHER, 0.0, 0.0, KNAME_T(k_pcheck<T>), k_pcheck<T>, dim3((unsigned)b0), dim3(256), 0, dj,
+         (int)use.size(), (const int*)(ctl + 1));
+}
+
+template <typename T>
 void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs,
           const std::vector<MVTerm>& terms) {
   for (auto& J : jobs) { J.s = s; J.b = b; J.L = L; J.nrhs = nrhs; }
@@ -4289,6 +4576,9 @@ void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
   template void ghmv<T>(hipStream_t, int, int, int, int, std::vector<MVJob>, const std::vector<MVTerm>&); \
   template void ghmv<T>(hipStream_t, std::vector<MVJob>, const std::vector<MVTerm>&);              \
   template void gto_blocks<T>(hipStream_t, std::vector<VJob>);                                     \
+  template void PBuilder::step<T>(std::vector<MVJob>, const std::vector<MVTerm>&);                \
+  template void psolve_run<T>(hipStream_t, std::vector<PInst>, int, bool, int*, const std::vector<VJob>&, \
+                              double, double);                                                     \
   template void gdense_blocks<T>(hipStream_t, std::vector<DenseJob>);                              \
   template void gdense_to_hodlr<T>(hipStream_t, std::vector<HJob>);                                \
   template void gfrom_blocks<T>(hipStream_t, std::vector<VJob>);                                   \

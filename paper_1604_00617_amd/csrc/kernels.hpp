@@ -3,6 +3,7 @@
 // p = m*ncl + c (matrix m, cluster c) unless stated otherwise.
 #pragma once
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -154,6 +155,80 @@ template <typename T>
 void gto_blocks(hipStream_t st, std::vector<VJob> jobs);     // src double, dst T
 template <typename T>
 void gfrom_blocks(hipStream_t st, std::vector<VJob> jobs);   // src T, dst double
+
+// ------------------------------------------------- persistent solve pass
+// A solve pass as one launch over a task list.  A task is either some
+// projection units of one (term, matrix) of a matvec step (kind 0) or up to
+// 256 output rows of one output block (kind 1).  Workgroups take the tasks
+// in list order; a task first waits until the counters of the tasks whose
+// outputs it reads have reached their totals (ndep pairs counter, total),
+// then runs and adds one to its own counter.  Every task follows the tasks
+// it waits for in the list.  In the jobs and terms of a pass the vector
+// operands (y, C0, out) are byte offsets into the pass's workspace, and the
+// projection buffer lies at tbuf_off in it; factor operands are device
+// addresses.  Counters start at zero.
+constexpr int kPMaxDep = 5;
+struct PTask {
+  int kind = 0;        // 0 projections, 1 output rows
+  int idx = 0;         // term (kind 0) or job (kind 1), indices of the pass
+  int m = 0;           // matrix of the term or job
+  int u0 = 0, u1 = 0;  // units [u0, u1) of the matrix, or rows [u0, u1) of the block
+  int done = 0;        // counter this task adds one to
+  int ndep = 0, pad = 0;
+  int dep[kPMaxDep] = {};
+  int need[kPMaxDep] = {};
+};
+struct PInst {              // one pass of a launch
+  long long task0 = 0;      // ticket of its first task (set by the launcher)
+  const PTask* tasks = nullptr;
+  const MVJob* jobs = nullptr;
+  const MVTerm* terms = nullptr;
+  char* ws = nullptr;       // the pass's workspace
+  int* ctr = nullptr;       // its counters, zero at the start
+  long long tbuf_off = 0;   // projection buffer in the workspace (bytes)
+  int ntasks = 0, pad = 0;
+};
+// Task list of a sequence of matvec steps, each given as to ghmv (vector
+// operands as workspace offsets).  NR: the right-hand-side slots of the
+// projections (1, 2, 4 or 8, at least every job's nrhs).
+struct PBuilder {
+  explicit PBuilder(int nr) : NR(nr) {}
+  int NR = 1;
+  bool w64 = true;      // every job's leaf size is a multiple of 64
+  std::vector<PTask> tasks;
+  std::vector<MVJob> jobs;
+  std::vector<MVTerm> terms;
+  long long tsize = 0;  // projection buffer elements
+  int nctr = 0;
+  double flops = 0, bytes = 0;   // algorithmic counts (numerical ranks)
+  template <typename T>
+  void step(std::vector<MVJob> jobs, const std::vector<MVTerm>& terms);
+  // Checks the list (ACR_ERR_INTERNAL otherwise): counters in range, and
+  // every counter a task waits for reaches the awaited total from tasks
+  // listed before it alone, so no wait depends on a later task.
+  void check() const;
+ private:
+  std::map<long long, std::pair<int, int>> prod_;   // output block offset -> (counter, total)
+};
+// Runs the passes `insts` (built with the same NR and row form) in one launch
+// on st; then, if a wait gave up, sets the final unknowns `fin` (the sources
+// of the block-to-vector copies that follow) to NaN.  ctl: two ints of device
+// memory, zero (ticket, abort word).
+template <typename T>
+void psolve_run(hipStream_t st, std::vector<PInst> insts, int NR, bool w64, int* ctl, const std::vector<VJob>& fin,
+                double flops, double bytes);
+// Process-wide solve-pass settings: mode 0 grouped launches per step, 1 the
+// levels of few blocks as one persistent launch, 2 the whole pass as one
+// persistent launch; wait limit in polls per dependency (< 0: every task
+// with dependencies gives up).
+struct SolveMode {
+  std::atomic<int> mode{0};
+  std::atomic<long long> limit{1LL << 22};
+  static SolveMode& get() {
+    static SolveMode m;
+    return m;
+  }
+};
 
 // Level-0 ingest of the five-point operator, grouped over problems: job j
 // covers matrices m = 0..nmat-1 of one problem, which use block row

@@ -305,7 +305,7 @@ void step(acr_server_s* S) {
     double rel = 0.0;
     for (int q = 0; q < r->nrhs; ++q) {
       const double v = r->hb[q] > 0 ? std::sqrt(hr[o + q] / r->hb[q]) : std::sqrt(hr[o + q]);
-      rel = std::max(rel, v);
+      rel = nan_max(rel, v);
     }
     o += r->nrhs;
     r->relres = rel;
