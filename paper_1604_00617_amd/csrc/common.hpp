@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -641,12 +642,66 @@ inline void copy_d2d_async(void* dst, const void* src, size_t bytes, hipStream_t
   if (!bytes) return;
   Queue::get().op(st, [=]() { ACR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st)); });
 }
+// Pinned staging of the calling thread's host reads, and the event a read
+// waits on.  A copy into pinned memory is queued behind the work that
+// produces the data (a copy into pageable memory would first wait on the
+// host for that work), and polling the event returns as soon as the copy
+// is done, where a blocking stream synchronisation also pays the host
+// thread's wake-up.
+struct HostRead {
+  char* pin = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  static HostRead& get() {
+    static thread_local HostRead h;
+    return h;
+  }
+  ~HostRead() {
+    if (pin) (void)hipHostFree(pin);
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
+// Flush, copy several device ranges to the host and wait for them (one wait).
+struct HostCopy {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+inline void read_many_to_host(const std::vector<HostCopy>& cs, hipStream_t st) {
+  Queue::get().flush();
+  HostRead& H = HostRead::get();
+  if (!H.ev) ACR_HIP(hipEventCreateWithFlags(&H.ev, hipEventDisableTiming));
+  size_t total = 0;
+  for (const auto& c : cs) total += (c.bytes + 15) & ~size_t(15);
+  if (total > H.cap) {
+    if (H.pin) (void)hipHostFree(H.pin);
+    H.pin = nullptr;
+    H.cap = 0;
+    const size_t cap = std::max(total, size_t(1) << 16);
+    ACR_HIP(hipHostMalloc((void**)&H.pin, cap, hipHostMallocDefault));
+    H.cap = cap;
+  }
+  size_t o = 0;
+  for (const auto& c : cs) {
+    if (c.bytes) ACR_HIP(hipMemcpyAsync(H.pin + o, c.src, c.bytes, hipMemcpyDeviceToHost, st));
+    o += (c.bytes + 15) & ~size_t(15);
+  }
+  ACR_HIP(hipEventRecord(H.ev, st));
+  hipError_t e;
+  while ((e = hipEventQuery(H.ev)) == hipErrorNotReady) {
+  }
+  if (e != hipSuccess) ACR_HIP(e);
+  o = 0;
+  for (const auto& c : cs) {
+    if (c.bytes) std::memcpy(c.dst, H.pin + o, c.bytes);
+    o += (c.bytes + 15) & ~size_t(15);
+  }
+  Queue::get().device_idle();
+}
 // Flush, copy device data to the host and wait for it.
 inline void read_to_host(void* dst, const void* src, size_t bytes, hipStream_t st) {
-  Queue::get().flush();
-  if (bytes) ACR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
-  ACR_HIP(hipStreamSynchronize(st));
-  Queue::get().device_idle();
+  read_many_to_host({HostCopy{dst, src, bytes}}, st);
 }
 
 }  // namespace acr

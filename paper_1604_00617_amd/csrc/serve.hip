@@ -285,15 +285,15 @@ void step(acr_server_s* S) {
   size_t tot = 0;
   for (auto& r : S->active) tot += r->nrhs;
   std::vector<double> hr(tot);
-  queue_flush();
   {
+    std::vector<HostCopy> cs;
     size_t o = 0;
     for (auto& r : S->active) {
-      ACR_HIP(hipMemcpyAsync(hr.data() + o, r->nrm.get(), r->nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      cs.push_back(HostCopy{hr.data() + o, r->nrm.get(), r->nrhs * sizeof(double)});
       o += r->nrhs;
     }
+    read_many_to_host(cs, st);
   }
-  ACR_HIP(hipStreamSynchronize(st));
   std::vector<Request*> go32, go64;
   std::vector<std::shared_ptr<Request>> keep;
   size_t o = 0;
