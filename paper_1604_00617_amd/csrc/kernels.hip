@@ -763,15 +763,22 @@ __device__ __forceinline__ void hmv_apply_row(const MVJob& J, const MVTerm* __re
       const T* lf = gmem(static_cast<const T*>(M.lv)) + ((long long)mm * nleaf + l) * b * b + r;
       const T* yl = y + (long long)l * b;
       if (W64) {
+        // all loads of a slice of leaf columns are issued before its products
+        // (64 columns in FP32, 32 in FP64); the products keep column order
+        constexpr int SL = sizeof(T) == 4 ? WAVE : WAVE / 2;
         for (int cb = 0; cb < b; cb += WAVE) {
           T yw[NR];
 #pragma unroll
           for (int q = 0; q < NR; ++q) yw[q] = q < nrhs ? yl[cb + lane + (long long)q * s] : T(0);
-#pragma unroll 16
-          for (int c = 0; c < WAVE; ++c) {
-            const T a = lf[(long long)(cb + c) * b];
 #pragma unroll
-            for (int q = 0; q < NR; ++q) ta[q] = fma(a, lane_read(yw[q], c), ta[q]);
+          for (int c0 = 0; c0 < WAVE; c0 += SL) {
+            T av[SL];
+#pragma unroll
+            for (int c = 0; c < SL; ++c) av[c] = lf[(long long)(cb + c0 + c) * b];
+#pragma unroll
+            for (int c = 0; c < SL; ++c)
+#pragma unroll
+              for (int q = 0; q < NR; ++q) ta[q] = fma(av[c], lane_read(yw[q], c0 + c), ta[q]);
           }
         }
       } else {
@@ -790,11 +797,16 @@ __device__ __forceinline__ void hmv_apply_row(const MVJob& J, const MVTerm* __re
         const int sib = (l >> (L - d)) ^ 1;
         const T* tv = tb + M.toff[d] + (long long)sib * w * NR;
         const T* Ud = gmem(static_cast<const T*>(M.U[d])) + (long long)mm * M.k[d] * s + row;
-#pragma unroll 4
-        for (int q0 = 0; q0 < w; ++q0) {
-          const T uv = Ud[(long long)q0 * s];
+        // eight U columns loaded at once, products in column order
+        for (int q0 = 0; q0 < w; q0 += 8) {
+          T uv[8];
 #pragma unroll
-          for (int q = 0; q < NR; ++q) ta[q] = fma(uv, tv[q0 * NR + q], ta[q]);
+          for (int e = 0; e < 8; ++e) uv[e] = q0 + e < w ? Ud[(long long)(q0 + e) * s] : T(0);
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (q0 + e < w)
+#pragma unroll
+              for (int q = 0; q < NR; ++q) ta[q] = fma(uv[e], tv[(q0 + e) * NR + q], ta[q]);
         }
       }
     }
