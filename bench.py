@@ -727,13 +727,16 @@ def factor_and_pass(acr, torch, op, args, precision, reps):
 
 def pass_modes(acr, torch, op, args, precision, reps):
     """One-RHS solve-pass time (ms, HIP events over `reps` passes) and launches per pass in
-    each execution mode: grouped launches per step, the levels of few blocks as one
-    persistent launch, the whole pass as one persistent launch (same bits in all three)."""
+    each execution mode: grouped launches per step from descriptors kept on the device
+    (default), the same launches planned and uploaded on every call, the levels of few
+    blocks as one persistent launch, the whole pass as one persistent launch (same bits in
+    all four)."""
     h = acr.acr_factor(op, args.leaf, args.eps, precision)
     b = torch.randn(op.n, dtype=torch.float64, device="cuda")
     out = {}
     try:
-        for mode, name in ((0, "grouped"), (1, "persistent_deep_levels"), (2, "persistent_whole_pass")):
+        for mode, name in ((0, "grouped_kept"), (3, "grouped_planned_per_call"), (1, "persistent_deep_levels"),
+                           (2, "persistent_whole_pass")):
             acr.acr_set_solve_mode(mode)
             acr.acr_solve(h, b)   # builds and caches the task list
             torch.cuda.synchronize()

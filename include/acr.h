@@ -227,8 +227,10 @@ acr_status acr_solve_batched(const acr_handle* hs, const double* const* B, doubl
  * on `stream` (no host synchronisation); its workspace comes from the pool on
  * every call, so the call is not meant for stream capture.  With at most 8
  * right-hand sides each matvec step of the pass is two grouped launches
- * (projections, then rows) by default; acr_set_solve_mode selects a
- * persistent launch for part or all of the pass instead. */
+ * (projections, then rows) by default, from descriptors and a workspace the
+ * handle keeps on the device after the first such solve (see
+ * acr_set_solve_mode); acr_set_solve_mode can select a persistent launch for
+ * part or all of the pass instead. */
 acr_status acr_solve(acr_handle h, const double* B, double* X, int32_t nrhs, void* stream);
 
 /* acr_solve without any device allocation, for callers that cannot allocate
@@ -449,11 +451,20 @@ acr_status acr_tune_clear(void);
  * (process-wide; the levels of the pass are those of Section 3's
  * back-substitution).
  *   mode 0 (default): two grouped launches per matvec step (projections,
- *     then rows), ordered by the stream.
+ *     then rows), ordered by the stream.  For a single handle the steps'
+ *     descriptors and the pass's workspace are laid out and copied to the
+ *     device on the first solve with a given nrhs on a given stream and host
+ *     thread (that call synchronises `stream` once) and kept with the handle
+ *     (about 16 N nrhs bytes in FP32) until acr_destroy, so a pass only
+ *     enqueues its launches.  acr_solve_batched and the serving loop, whose
+ *     handles and nrhs change from call to call, plan on every call as in
+ *     mode 3.
  *   mode 1: the levels of at most 16 blocks, the last block and their
  *     back-substitution as one persistent launch; the wider levels as in
  *     mode 0.
  *   mode 2: the whole pass as one persistent launch.
+ *   mode 3: as mode 0, with the steps laid out and their descriptors copied
+ *     on every call (nothing kept).
  * In a persistent launch the matvecs are tasks (some projection units, or
  * 256 output rows, of one block).  Workgroups take them in an order in
  * which each task follows the tasks it reads from, wait (polling a counter,

@@ -386,11 +386,12 @@ def acr_launch_count() -> int:
 
 
 def acr_set_solve_mode(mode: int = 0, wait_limit: int = 0):
-    """Solve passes: 0 = grouped launches per step (default), 1 = the levels
-    of at most 16 blocks as one persistent launch, 2 = the whole pass as one
-    persistent launch (all give the same bits); wait_limit > 0 polls per
-    wait, 0 the default, < 0 every dependent task gives up (the pass then
-    returns NaN)."""
+    """Solve passes: 0 = grouped launches per step from descriptors kept on
+    the device (default), 1 = the levels of at most 16 blocks as one
+    persistent launch, 2 = the whole pass as one persistent launch, 3 =
+    grouped launches planned on every call (all give the same bits);
+    wait_limit > 0 polls per wait, 0 the default, < 0 every dependent task
+    gives up (the pass then returns NaN)."""
     lib = load()
     lib.acr_set_solve_mode.argtypes = [ctypes.c_int32, ctypes.c_int64]
     lib.acr_set_solve_mode.restype = ctypes.c_int

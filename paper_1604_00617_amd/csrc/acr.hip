@@ -10,6 +10,7 @@
 // level are processed together by each batched launch.
 // Solve: forward reduction g_k = X_k f_k, f'_j = f_i - E_i g_{i-1} - F_i g_{i+1};
 // final u = X f; back-substitution u_k = X_k (f_k - E_k u_{k-1} - F_k u_{k+1}).
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -18,6 +19,8 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "factor.hpp"
@@ -106,6 +109,11 @@ void plan_dense_last(GemmPlan& plan, const Factor<T>& f, const T* F, T* U, int n
 template <typename T>
 const PPlan& Factor<T>::plan(int nrhs, int max_blocks, hipStream_t st) const {
   std::lock_guard<std::mutex> g(plan_mu);
+  return plan_locked(nrhs, max_blocks, st);
+}
+
+template <typename T>
+const PPlan& Factor<T>::plan_locked(int nrhs, int max_blocks, hipStream_t st) const {
   const auto key = std::make_pair(nrhs, max_blocks);
   auto found = plans.find(key);
   if (found != plans.end()) return *found->second;
@@ -141,6 +149,7 @@ const PPlan& Factor<T>::plan(int nrhs, int max_blocks, hipStream_t st) const {
   // before (forward) and after (backward) the persistent launch
   int l0 = 0;
   while (l0 < nl && lev[l0].m > max_blocks) ++l0;
+  if (max_blocks < 0) l0 = nl + 1;   // every step grouped, the last block's too
   P->l0 = l0;
   int cur = 0;   // level of the steps being added
   bool fwd = true;
@@ -217,17 +226,95 @@ const PPlan& Factor<T>::plan(int nrhs, int max_blocks, hipStream_t st) const {
   std::memcpy(h.data() + oj, pb.jobs.data(), bj);
   std::memcpy(h.data() + om, pb.terms.data(), bm);
   P->dev.resize(h.size());
-  // one upload, complete before any stream reads the plan
-  Queue::get().flush();
-  ACR_HIP(hipMemcpyAsync(P->dev.get(), h.data(), h.size(), hipMemcpyHostToDevice, st));
-  ACR_HIP(hipStreamSynchronize(st));
-  Queue::get().device_idle();
+  if (!h.empty()) {   // one upload, complete before any stream reads the plan
+    Queue::get().flush();
+    ACR_HIP(hipMemcpyAsync(P->dev.get(), h.data(), h.size(), hipMemcpyHostToDevice, st));
+    ACR_HIP(hipStreamSynchronize(st));
+    Queue::get().device_idle();
+  }
   P->tasks = reinterpret_cast<const PTask*>(P->dev.get());
   P->jobs = reinterpret_cast<const MVJob*>(P->dev.get() + oj);
   P->terms = reinterpret_cast<const MVTerm*>(P->dev.get() + om);
   const PPlan& r = *P;
   plans[key] = std::move(P);
   return r;
+}
+
+// The grouped solve pass of this factor for nrhs right-hand sides on the
+// calling thread and stream, with its workspace and every step's
+// descriptors kept on the device: built on first use from the plan's steps
+// (all grouped), then each pass only enqueues its launches.
+template <typename T>
+const GPass& Factor<T>::gpass(int nrhs, hipStream_t st) const {
+  std::lock_guard<std::mutex> g(plan_mu);
+  const auto key = std::make_tuple(nrhs, st, std::this_thread::get_id());
+  auto found = gpasses.find(key);
+  if (found != gpasses.end()) return *found->second;
+  const PPlan& P = plan_locked(nrhs, -1, st);
+  auto G = std::make_unique<GPass>();
+  G->ws.resize(P.ws_bytes);
+  G->f0_off = P.f0_off;
+  G->u0_off = P.u0_off;
+  const uintptr_t base = reinterpret_cast<uintptr_t>(G->ws.get());
+  std::vector<char> blob;
+  auto put = [&](const void* p, size_t n) {
+    const size_t o = (blob.size() + 255) & ~size_t(255);
+    blob.resize(o + n);
+    if (n) std::memcpy(blob.data() + o, p, n);
+    return o;
+  };
+  std::vector<std::array<size_t, 3>> offs;
+  long long tmax = 1;
+  for (const auto* list : {&P.pre, &P.post})
+    for (const HostStep& hs : *list) {
+      std::vector<MVTerm> tm = hs.terms;
+      std::vector<MVJob> jb = hs.jobs;
+      for (MVTerm& M : tm) M.y = reinterpret_cast<const void*>(base + reinterpret_cast<uintptr_t>(M.y));
+      for (MVJob& J : jb) {
+        J.out = reinterpret_cast<void*>(base + reinterpret_cast<uintptr_t>(J.out));
+        if (J.C0) J.C0 = reinterpret_cast<const void*>(base + reinterpret_cast<uintptr_t>(J.C0));
+      }
+      HmvStep h = hmv_plan<T>(std::move(jb), tm);
+      if (h.rows <= 0) continue;
+      offs.push_back({put(h.reds.data(), h.reds.size() * sizeof(MVRed)), put(h.terms.data(), h.terms.size() * sizeof(MVTerm)),
+                      put(h.jobs.data(), h.jobs.size() * sizeof(MVJob))});
+      tmax = std::max(tmax, h.tsize);
+      G->steps.push_back(std::move(h));
+    }
+  G->tb.resize((size_t)tmax * sizeof(T));
+  G->desc.resize(blob.size());
+  if (!blob.empty()) {   // one upload, complete before the first pass reads it
+    Queue::get().flush();
+    ACR_HIP(hipMemcpyAsync(G->desc.get(), blob.data(), blob.size(), hipMemcpyHostToDevice, st));
+    ACR_HIP(hipStreamSynchronize(st));
+    Queue::get().device_idle();
+  }
+  for (const auto& o : offs) {
+    G->reds.push_back(reinterpret_cast<const MVRed*>(G->desc.get() + o[0]));
+    G->terms.push_back(reinterpret_cast<const MVTerm*>(G->desc.get() + o[1]));
+    G->jobs.push_back(reinterpret_cast<const MVJob*>(G->desc.get() + o[2]));
+  }
+  const GPass& r = *G;
+  gpasses[key] = std::move(G);
+  return r;
+}
+
+// X = M^{-1} B by the kept grouped pass: block layout in, the steps' launches
+// (no planning, no descriptor copies), block layout out.
+template <typename T>
+void solve_kept(const Factor<T>& f, const double* B, double* Xout, int nrhs, hipStream_t st) {
+  const GPass& G = f.gpass(nrhs, st);
+  VJob J;
+  J.s = f.nx; J.nblk = f.ny; J.nrhs = nrhs; J.ld = (long long)f.nx * f.ny;
+  J.src = B; J.dst = G.ws.get() + G.f0_off;
+  gto_blocks<T>(st, {J});
+  {
+    PhaseScope ph("solve pass");
+    T* tb = reinterpret_cast<T*>(G.tb.get());
+    for (size_t i = 0; i < G.steps.size(); ++i) hmv_launch<T>(st, G.steps[i], G.reds[i], G.terms[i], G.jobs[i], tb);
+  }
+  J.src = G.ws.get() + G.u0_off + (long long)f.nx * nrhs * sizeof(T); J.dst = Xout;
+  gfrom_blocks<T>(st, {J});
 }
 
 // X_p = M_p^{-1} B_p as one persistent launch per group of passes with the
@@ -326,14 +413,19 @@ void solve_persistent_many(const std::vector<const Factor<T>*>& fs, const std::v
 // level-l unknowns with one zero pad block at each end.
 template <typename T>
 void solve_fused_many(const std::vector<const Factor<T>*>& fs, const std::vector<const double*>& Bs,
-                      const std::vector<double*>& Xs, const std::vector<int>& nrs, hipStream_t st) {
+                      const std::vector<double*>& Xs, const std::vector<int>& nrs, hipStream_t st, bool keep) {
   const int P = (int)fs.size();
-  {   // the deep levels or the whole pass as one persistent launch, when asked for
+  {   // a kept grouped pass for one problem, or the deep levels or the whole
+      // pass as one persistent launch when asked for
     const int mode = SolveMode::get().mode.load();
-    bool persist = mode != 0 && !Bump::cur() && !Queue::get().dry();
-    for (int p = 0; p < P && persist; ++p) persist = fs[p]->mstop == 1 && fs[p]->fused_ok(nrs[p]);
-    if (persist) {
+    bool ok = !Bump::cur() && !Queue::get().dry();
+    for (int p = 0; p < P && ok; ++p) ok = fs[p]->mstop == 1 && fs[p]->fused_ok(nrs[p]);
+    if (ok && (mode == 1 || mode == 2)) {
       solve_persistent_many<T>(fs, Bs, Xs, nrs, mode == 2 ? INT32_MAX : kPersistBlocks, st);
+      return;
+    }
+    if (ok && mode == 0 && keep && P == 1) {
+      solve_kept<T>(*fs[0], Bs[0], Xs[0], nrs[0], st);
       return;
     }
   }
@@ -489,7 +581,7 @@ void solve_fused_many(const std::vector<const Factor<T>*>& fs, const std::vector
 
 template <typename T>
 void Factor<T>::solve_fused(const double* B, double* Xout, int nrhs, hipStream_t st) {
-  solve_fused_many<T>({this}, {B}, {Xout}, {nrhs}, st);
+  solve_fused_many<T>({this}, {B}, {Xout}, {nrhs}, st, true);
 }
 
 template <typename T>
@@ -1093,7 +1185,7 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
                                                                   const acr_dense_operator*,             \
                                                                   const acr_operator3d*);                \
   template void solve_fused_many<T>(const std::vector<const Factor<T>*>&, const std::vector<const double*>&, \
-                                    const std::vector<double*>&, const std::vector<int>&, hipStream_t);
+                                    const std::vector<double*>&, const std::vector<int>&, hipStream_t, bool);
 ACR_INST(float)
 ACR_INST(double)
 #undef ACR_INST
@@ -1789,7 +1881,7 @@ int64_t acr_launch_count(void) { return (int64_t)launch_count(); }
 
 acr_status acr_set_solve_mode(int32_t mode, int64_t wait_limit) {
   return guard([&] {
-    if (mode < 0 || mode > 2) fail(ACR_ERR_INVALID_ARG, "solve mode must be 0, 1 or 2");
+    if (mode < 0 || mode > 3) fail(ACR_ERR_INVALID_ARG, "solve mode must be 0, 1, 2 or 3");
     SolveMode::get().mode = mode;
     SolveMode::get().limit = wait_limit == 0 ? (1LL << 22) : wait_limit;
   });

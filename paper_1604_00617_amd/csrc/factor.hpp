@@ -8,6 +8,8 @@
 #include <mutex>
 #include <memory>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "hodlr.hpp"
@@ -59,6 +61,19 @@ struct PPlan {
   const MVJob* jobs = nullptr;
   const MVTerm* terms = nullptr;
   double flops = 0, bytes = 0;
+};
+
+// A grouped solve pass kept on the device for one (right-hand-side count,
+// stream, host thread): the workspace of the plan's layout, a projection
+// buffer for the largest step, and every step's descriptors; a pass only
+// enqueues the steps' launches.
+struct GPass {
+  DBuf<char> ws, tb, desc;
+  long long f0_off = 0, u0_off = 0;
+  std::vector<HmvStep> steps;
+  std::vector<const MVRed*> reds;
+  std::vector<const MVTerm*> terms;
+  std::vector<const MVJob*> jobs;
 };
 
 template <typename T>
@@ -160,7 +175,10 @@ struct Factor final : FactorBase {
   // persistent solve plans by (right-hand sides, largest grouped-level size)
   mutable std::mutex plan_mu;
   mutable std::map<std::pair<int, int>, std::unique_ptr<PPlan>> plans;
-  const PPlan& plan(int nrhs, int max_blocks, hipStream_t st) const;
+  mutable std::map<std::tuple<int, hipStream_t, std::thread::id>, std::unique_ptr<GPass>> gpasses;
+  const PPlan& plan(int nrhs, int max_blocks, hipStream_t st) const;   // max_blocks < 0: all grouped
+  const PPlan& plan_locked(int nrhs, int max_blocks, hipStream_t st) const;
+  const GPass& gpass(int nrhs, hipStream_t st) const;
 
   void solve(const double* B, double* Xout, int nrhs, hipStream_t st) override;
   void solve_fused(const double* B, double* Xout, int nrhs, hipStream_t st);
@@ -181,10 +199,13 @@ std::vector<std::unique_ptr<Factor<T>>> factor_many(const std::vector<acr_operat
                                                     const acr_operator3d* op3 = nullptr);
 
 // X_p = M_p^{-1} B_p for several factors with <= 8 right-hand sides each, in
-// shared launches (see acr.hip).
+// shared launches (see acr.hip).  keep: a single factor may use (and build)
+// its kept grouped pass; the batched and serving callers pass false, since
+// their handles and right-hand-side counts change from call to call.
 template <typename T>
 void solve_fused_many(const std::vector<const Factor<T>*>& fs, const std::vector<const double*>& Bs,
-                      const std::vector<double*>& Xs, const std::vector<int>& nrs, hipStream_t st);
+                      const std::vector<double*>& Xs, const std::vector<int>& nrs, hipStream_t st,
+                      bool keep = false);
 
 // max(a, b) that keeps a NaN (a NaN residual norm must stop a solver as
 // not converged, never read as zero).

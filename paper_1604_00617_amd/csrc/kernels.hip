@@ -3934,13 +3934,14 @@ void gcopy(hipStream_t st, std::vector<CJob> jobs) {
 }
 
 template <typename T>
-void ghmv(hipStream_t st, std::vector<MVJob> jobs, const std::vector<MVTerm>& terms) {
+HmvStep hmv_plan(std::vector<MVJob> jobs, const std::vector<MVTerm>& terms) {
   constexpr int CH = 16;
   // every job gets its own copies of its terms, with the places of their
   // projections in the buffer
-  std::vector<MVJob> use;
-  std::vector<MVTerm> tm;
-  std::vector<MVRed> reds;
+  HmvStep h;
+  std::vector<MVJob>& use = h.jobs;
+  std::vector<MVTerm>& tm = h.terms;
+  std::vector<MVRed>& reds = h.reds;
   long long rows = 0, units = 0, tsize = 0;
   double flr = 0, byr = 0, fla = 0, bya = 0;
   int maxnr = 1;
@@ -3990,7 +3991,7 @@ void ghmv(hipStream_t st, std::vector<MVJob> jobs, const std::vector<MVTerm>& te
     bya += (double)J.nmat * s * nrhs * sizeof(T) * (J.C0 ? 2 : 1);
     use.push_back(J);
   }
-  if (use.empty()) return;
+  if (use.empty()) return h;
   const int NR = maxnr <= 1 ? 1 : maxnr <= 2 ? 2 : maxnr <= 4 ? 4 : 8;
   // projection slots: NR per column (the kernels index with the launch's NR)
   for (auto& M : tm) {
@@ -4015,38 +4016,53 @@ void ghmv(hipStream_t st, std::vector<MVJob> jobs, const std::vector<MVTerm>& te
   }
   if ((rows + WAVE - 1) / WAVE > 0x7fffffffLL || (units + 3) / 4 > 0x7fffffffLL)
     fail(ACR_ERR_INVALID_ARG, "matvec grid too large");
-  DBuf<T> tbuf((size_t)std::max<long long>(tsize, 1));
-  const MVTerm* dt = tm.empty() ? nullptr : upload(tm, st);
-  if (units > 0) {
-    const MVRed* dr = upload(reds, st);
-    const dim3 grid((unsigned)((units + 3) / 4));
-    const int nr = (int)reds.size();
+  h.rows = rows; h.units = units; h.tsize = tsize; h.NR = NR; h.w64 = w64;
+  h.flr = flr; h.byr = byr; h.fla = fla; h.bya = bya;
+  return h;
+}
+
+template <typename T>
+void hmv_launch(hipStream_t st, const HmvStep& h, const MVRed* dr, const MVTerm* dt, const MVJob* dj, T* tbuf) {
+  if (h.rows <= 0) return;
+  if (h.units > 0) {
+    const dim3 grid((unsigned)((h.units + 3) / 4));
+    const int nr = (int)h.reds.size();
     auto go = [&](const char* name, auto kern) {
-      launch(st, KC_MATVEC, flr, byr, name, kern, grid, dim3(256), 0, dr, nr, dt, units, tbuf.get());
+      launch(st, KC_MATVEC, h.flr, h.byr, name, kern, grid, dim3(256), 0, dr, nr, dt, h.units, tbuf);
     };
-    switch (NR) {
+    switch (h.NR) {
       case 1: go(KNAME_T(k_hmv_reduce<T, 1>), k_hmv_reduce<T, 1>); break;
       case 2: go(KNAME_T(k_hmv_reduce<T, 2>), k_hmv_reduce<T, 2>); break;
       case 4: go(KNAME_T(k_hmv_reduce<T, 4>), k_hmv_reduce<T, 4>); break;
       default: go(KNAME_T(k_hmv_reduce<T, 8>), k_hmv_reduce<T, 8>); break;
     }
   }
-  const MVJob* dj = upload(use, st);
-  const dim3 grid((unsigned)((rows + WAVE - 1) / WAVE));
-  const int nj = (int)use.size();
+  const dim3 grid((unsigned)((h.rows + WAVE - 1) / WAVE));
+  const int nj = (int)h.jobs.size();
   auto go = [&](const char* name, auto kern) {
-    launch(st, KC_MATVEC, fla, bya, name, kern, grid, dim3(WAVE), 0, dj, nj, dt, rows, (const T*)tbuf.get());
+    launch(st, KC_MATVEC, h.fla, h.bya, name, kern, grid, dim3(WAVE), 0, dj, nj, dt, h.rows, (const T*)tbuf);
   };
 #define ACR_HMV_APPLY(NRV)                                                                   \
-  if (w64) go(KNAME_T(k_hmv_apply<T, NRV, true>), k_hmv_apply<T, NRV, true>);              \
+  if (h.w64) go(KNAME_T(k_hmv_apply<T, NRV, true>), k_hmv_apply<T, NRV, true>);            \
   else go(KNAME_T(k_hmv_apply<T, NRV, false>), k_hmv_apply<T, NRV, false>);
-  switch (NR) {
+  switch (h.NR) {
     case 1: ACR_HMV_APPLY(1) break;
     case 2: ACR_HMV_APPLY(2) break;
     case 4: ACR_HMV_APPLY(4) break;
     default: ACR_HMV_APPLY(8) break;
   }
 #undef ACR_HMV_APPLY
+}
+
+template <typename T>
+void ghmv(hipStream_t st, std::vector<MVJob> jobs, const std::vector<MVTerm>& terms) {
+  const HmvStep h = hmv_plan<T>(std::move(jobs), terms);
+  if (h.rows <= 0) return;
+  DBuf<T> tbuf((size_t)std::max<long long>(h.tsize, 1));
+  const MVTerm* dt = h.terms.empty() ? nullptr : upload(h.terms, st);
+  const MVRed* dr = h.units > 0 ? upload(h.reds, st) : nullptr;
+  const MVJob* dj = upload(h.jobs, st);
+  hmv_launch<T>(st, h, dr, dt, dj, tbuf.get());
 }
 
 template <typename T>
@@ -4587,6 +4603,8 @@ void axpy_d(hipStream_t st, long long n, const double* D, double* X) {
   template void ggemm<T>(hipStream_t, std::vector<GJob>, const std::vector<GSeg>&, int);          \
   template void ghmv<T>(hipStream_t, int, int, int, int, std::vector<MVJob>, const std::vector<MVTerm>&); \
   template void ghmv<T>(hipStream_t, std::vector<MVJob>, const std::vector<MVTerm>&);              \
+  template HmvStep hmv_plan<T>(std::vector<MVJob>, const std::vector<MVTerm>&);                    \
+  template void hmv_launch<T>(hipStream_t, const HmvStep&, const MVRed*, const MVTerm*, const MVJob*, T*); \
   template void gto_blocks<T>(hipStream_t, std::vector<VJob>);                                     \
   template void PBuilder::step<T>(std::vector<MVJob>, const std::vector<MVTerm>&);                \
   template void psolve_run<T>(hipStream_t, std::vector<PInst>, int, bool, int*, const std::vector<VJob>&, \

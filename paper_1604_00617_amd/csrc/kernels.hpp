@@ -137,6 +137,24 @@ struct MVJob {
 // Jobs keep their own s, b, L and nrhs (1..8).
 template <typename T>
 void ghmv(hipStream_t st, std::vector<MVJob> jobs, const std::vector<MVTerm>& terms);
+// ghmv in two halves, for a caller that keeps a step's descriptors in device
+// memory and launches it many times: hmv_plan lays out the step (the
+// descriptors to copy to the device, the grid sizes, the projection buffer
+// size tsize and the algorithmic counts); hmv_launch enqueues its two
+// launches with the device copies of reds, terms and jobs.
+struct HmvStep {
+  std::vector<MVRed> reds;
+  std::vector<MVTerm> terms;
+  std::vector<MVJob> jobs;
+  long long rows = 0, units = 0, tsize = 0;
+  int NR = 1;
+  bool w64 = true;
+  double flr = 0, byr = 0, fla = 0, bya = 0;
+};
+template <typename T>
+HmvStep hmv_plan(std::vector<MVJob> jobs, const std::vector<MVTerm>& terms);
+template <typename T>
+void hmv_launch(hipStream_t st, const HmvStep& h, const MVRed* reds, const MVTerm* terms, const MVJob* jobs, T* tbuf);
 // All jobs with the same shapes.
 template <typename T>
 void ghmv(hipStream_t st, int s, int b, int L, int nrhs, std::vector<MVJob> jobs,

@@ -1,10 +1,11 @@
-"""The persistent solve pass (tasks with bounded dependency waits in one
-launch: the whole pass, or the levels of at most 16 blocks) against the
-grouped per-step launches: all run the same device arithmetic in the same
-order, so every solution must agree bit for bit, alone and batched, in FP64
-and in the mixed form.  The forced failure path (every dependent task gives
-up) must end every kernel normally and return NaN, and the next pass must be
-correct again."""
+"""The execution modes of a solve pass against the default (grouped launches
+from descriptors kept on the device): the persistent pass (tasks with
+bounded dependency waits in one launch: the whole pass, or the levels of at
+most 16 blocks) and the grouped launches planned on every call.  All run the
+same device arithmetic in the same order, so every solution must agree bit
+for bit, alone and batched, in FP64 and in the mixed form.  The forced
+failure path (every dependent task gives up) must end every kernel normally
+and return NaN, and the next pass must be correct again."""
 import numpy as np
 import pytest
 
@@ -41,7 +42,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}{c[1]}x{c[2]}-leaf{c[3]}-rhs{c[5]}")
 def test_persistent_equals_grouped(gpu, case, prec, mode):
@@ -64,7 +65,14 @@ def test_persistent_equals_grouped(gpu, case, prec, mode):
     while mode == 1 and m > 16:
         wide += 1
         m //= 2
-    assert launches <= 6 + 8 * wide, launches
+    if mode in (1, 2):
+        assert launches <= 6 + 8 * wide, launches
+    # the kept pass: the same launches as planning on every call, nothing more
+    c0 = gpu.acr_launch_count()
+    gpu.acr_solve(h, B)
+    kept = gpu.acr_launch_count() - c0
+    if mode == 3:
+        assert kept == launches, (kept, launches)
     gpu.acr_destroy(h)
 
 
@@ -80,7 +88,7 @@ def test_persistent_batched_equals_solo(gpu):
         Bs.append(torch.from_numpy(W.rhs(st.n, nrhs, seed=W.seed_for(2, 800 + i))).cuda())
     xs = [gpu.acr_solve(h, B).cpu().numpy() for h, B in zip(hs, Bs)]
     try:
-        for mode in (1, 2):
+        for mode in (1, 2, 3):
             gpu.acr_set_solve_mode(mode)
             xb = [x.cpu().numpy() for x in gpu.acr_solve_batched(hs, Bs)]
             for i in range(len(hs)):
