@@ -455,7 +455,8 @@ acr_status acr_tune_clear(void);
  *     descriptors and the pass's workspace are laid out and copied to the
  *     device on the first solve with a given nrhs on a given stream and host
  *     thread (that call synchronises `stream` once) and kept with the handle
- *     (about 16 N nrhs bytes in FP32) until acr_destroy, so a pass only
+ *     (about 16 N nrhs bytes in FP32; at most 16 such passes per handle, later
+ *     combinations plan on every call) until acr_destroy, so a pass only
  *     enqueues its launches.  acr_solve_batched and the serving loop, whose
  *     handles and nrhs change from call to call, plan on every call as in
  *     mode 3.

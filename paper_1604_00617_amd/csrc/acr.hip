@@ -299,6 +299,16 @@ const GPass& Factor<T>::gpass(int nrhs, hipStream_t st) const {
   return r;
 }
 
+// A kept pass exists, or may still be added, for (nrhs, stream, thread):
+// a handle keeps at most kMaxKeptPasses (a caller that solves on many
+// streams or threads gets per-call planning beyond that).
+template <typename T>
+bool Factor<T>::may_keep(int nrhs, hipStream_t st) const {
+  std::lock_guard<std::mutex> g(plan_mu);
+  return gpasses.size() < (size_t)kMaxKeptPasses ||
+         gpasses.count(std::make_tuple(nrhs, st, std::this_thread::get_id())) > 0;
+}
+
 // X = M^{-1} B by the kept grouped pass: block layout in, the steps' launches
 // (no planning, no descriptor copies), block layout out.
 template <typename T>
@@ -424,7 +434,7 @@ void solve_fused_many(const std::vector<const Factor<T>*>& fs, const std::vector
       solve_persistent_many<T>(fs, Bs, Xs, nrs, mode == 2 ? INT32_MAX : kPersistBlocks, st);
       return;
     }
-    if (ok && mode == 0 && keep && P == 1) {
+    if (ok && mode == 0 && keep && P == 1 && fs[0]->may_keep(nrs[0], st)) {
       solve_kept<T>(*fs[0], Bs[0], Xs[0], nrs[0], st);
       return;
     }

@@ -76,6 +76,8 @@ struct GPass {
   std::vector<const MVJob*> jobs;
 };
 
+constexpr int kMaxKeptPasses = 16;   // kept solve passes per handle
+
 template <typename T>
 struct Factor final : FactorBase {
   int nx = 0, ny = 0, leaf = 0, b = 0, L = 0, precision = 0;
@@ -179,6 +181,7 @@ struct Factor final : FactorBase {
   const PPlan& plan(int nrhs, int max_blocks, hipStream_t st) const;   // max_blocks < 0: all grouped
   const PPlan& plan_locked(int nrhs, int max_blocks, hipStream_t st) const;
   const GPass& gpass(int nrhs, hipStream_t st) const;
+  bool may_keep(int nrhs, hipStream_t st) const;
 
   void solve(const double* B, double* Xout, int nrhs, hipStream_t st) override;
   void solve_fused(const double* B, double* Xout, int nrhs, hipStream_t st);
