@@ -245,24 +245,52 @@ __device__ __forceinline__ void ggemm_body(const GJob* __restrict__ jobs,
     const T sscale = (T)S.scale;
     const T* Ap = optr<T>(S.A, m, c);
     const T* Bp = optr<T>(S.B, m, c);
-    for (int k0 = 0; k0 < K; k0 += TK) {
-      for (int e = tid; e < TM * TK; e += NT) {
+    // the next K slice is loaded into registers while the current one is
+    // multiplied out of LDS (same values, same product order)
+    constexpr int LA = (TM * TK + NT - 1) / NT, LB = (TK * TN + NT - 1) / NT;
+    T ra[LA], rb[LB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+      for (int u = 0; u < LA; ++u) {
+        const int e = tid + u * NT;
         int i, kk;
         if (!ta) { i = e % TM; kk = e / TM; } else { kk = e % TK; i = e / TK; }
         const int gi = i0 + i, gk = k0 + kk;
         T v = T(0);
-        if (gi < M && gk < K) v = ta ? Ap[gk + (long long)gi * lda] : Ap[gi + (long long)gk * lda];
-        As[kk][i] = v * sscale;
+        if (e < TM * TK && gi < M && gk < K) v = ta ? Ap[gk + (long long)gi * lda] : Ap[gi + (long long)gk * lda];
+        ra[u] = v * sscale;
       }
-      for (int e = tid; e < TK * TN; e += NT) {
+#pragma unroll
+      for (int u = 0; u < LB; ++u) {
+        const int e = tid + u * NT;
         int kk, jj;
         if (!tb) { kk = e % TK; jj = e / TK; } else { jj = e % TN; kk = e / TN; }
         const int gk = k0 + kk, gj = j0 + jj;
         T v = T(0);
-        if (gk < K && gj < N) v = tb ? Bp[gj + (long long)gk * ldb] : Bp[gk + (long long)gj * ldb];
-        Bs[kk][jj] = v;
+        if (e < TK * TN && gk < K && gj < N) v = tb ? Bp[gj + (long long)gk * ldb] : Bp[gk + (long long)gj * ldb];
+        rb[u] = v;
+      }
+    };
+    if (K > 0) fetch(0);
+    for (int k0 = 0; k0 < K; k0 += TK) {
+#pragma unroll
+      for (int u = 0; u < LA; ++u) {
+        const int e = tid + u * NT;
+        if (e >= TM * TK) break;
+        int i, kk;
+        if (!ta) { i = e % TM; kk = e / TM; } else { kk = e % TK; i = e / TK; }
+        As[kk][i] = ra[u];
+      }
+#pragma unroll
+      for (int u = 0; u < LB; ++u) {
+        const int e = tid + u * NT;
+        if (e >= TK * TN) break;
+        int kk, jj;
+        if (!tb) { kk = e % TK; jj = e / TK; } else { jj = e % TN; kk = e / TN; }
+        Bs[kk][jj] = rb[u];
       }
       __syncthreads();
+      if (k0 + TK < K) fetch(k0 + TK);
 #pragma unroll
       for (int kk = 0; kk < TK; ++kk) {
         T a[RM], b[RN];
