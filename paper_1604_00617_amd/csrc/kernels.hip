@@ -1048,16 +1048,29 @@ __global__ __launch_bounds__(256) void k_inverse_wave(const IJob* __restrict__ j
           used = true;
           mystep = j;
           mypiv = f;
+          if constexpr (N != WAVE) {
 #pragma unroll
-          for (int c = 0; c < N; ++c) pr[c] = a[c];
+            for (int c = 0; c < N; ++c) pr[c] = a[c];
+          }
         }
-        // the other lanes of the group read what the pivot lane wrote: a
-        // wavefront-scope fence orders the accesses (LDS is in order per wave)
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const double qq = is_piv ? 0.0 : f / pr[jj];
+        if constexpr (N == WAVE) {
+          // one matrix per wave: every lane reads the pivot row from the pivot
+          // lane's registers (bi is uniform), outside any branch, before any
+          // lane updates its row
+          const double pv = lane_read(a[jj], bi);
+          const double qq = is_piv ? 0.0 : f / pv;
 #pragma unroll
-        for (int c = 0; c < N; ++c) a[c] = fma(-qq, pr[c], a[c]);
-        a[jj] = is_piv ? 1.0 : -qq;
+          for (int c = 0; c < N; ++c) a[c] = fma(-qq, lane_read(a[c], bi), a[c]);
+          a[jj] = is_piv ? 1.0 : -qq;
+        } else {
+          // the other lanes of the group read what the pivot lane wrote: a
+          // wavefront-scope fence orders the accesses (LDS is in order per wave)
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          const double qq = is_piv ? 0.0 : f / pr[jj];
+#pragma unroll
+          for (int c = 0; c < N; ++c) a[c] = fma(-qq, pr[c], a[c]);
+          a[jj] = is_piv ? 1.0 : -qq;
+        }
         if (r == 0) piv_row[wv][g * N + j] = bi;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       }
