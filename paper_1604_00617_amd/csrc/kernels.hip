@@ -2519,6 +2519,38 @@ __global__ __launch_bounds__(256) void k_gcopy(const CJob* __restrict__ jobs, in
                          : nullptr;
   const int rows = Jb.rows, n = rows * Jb.cols, e0 = chunk * kCopyChunk + (int)threadIdx.x;
   const T alpha = (T)Jb.alpha;
+  if (Jb.vec) {
+    // 16-byte accesses (the launcher checked that rows, leading dimensions
+    // and operand offsets are multiples of V elements); the same products
+    // element by element
+    constexpr int V = 16 / sizeof(T);
+    typedef T VT __attribute__((ext_vector_type(V)));
+    constexpr int PV = PER / V;
+    const int rv = rows / V, nv = n / V, v0 = chunk * (kCopyChunk / V) + (int)threadIdx.x;
+    VT w[PV];
+    int r4[PV], q4[PV];
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+      const int e = v0 + u * 256;
+      r4[u] = (e % rv) * V;
+      q4[u] = e / rv;
+      if (e < nv) w[u] = *reinterpret_cast<const VT*>(sp + r4[u] + (long long)q4[u] * src.ld);
+    }
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+      if (v0 + u * 256 >= nv) break;
+      T* d = dp + r4[u] + (long long)q4[u] * dst.ld;
+      VT o;
+#pragma unroll
+      for (int h = 0; h < V; ++h) {
+        T y = alpha * w[u][h];
+        if (sc) y *= sc[Jb.sside ? q4[u] : r4[u] + h];
+        o[h] = Jb.accumulate ? d[h] + y : y;
+      }
+      *reinterpret_cast<VT*>(d) = o;
+    }
+    return;
+  }
   T v[PER];
   int rr[PER], qq[PER];
 #pragma unroll
@@ -3965,6 +3997,14 @@ void gcopy(hipStream_t st, std::vector<CJob> jobs) {
     J.chunks = (int)((n + kCopyChunk - 1) / kCopyChunk);
     J.block0 = b0;
     b0 += (long long)J.nmat * J.ncl * J.chunks;
+    {   // 16-byte accesses when every operand start and column is 16-byte aligned
+      const long long V = 16 / (long long)sizeof(T);
+      auto al = [&](const BOp& o) {
+        return reinterpret_cast<uintptr_t>(o.p) % 16 == 0 && o.ld % V == 0 && o.sm % V == 0 && o.sc_pair % V == 0 &&
+               o.sc_odd % V == 0;
+      };
+      J.vec = J.rows % V == 0 && al(J.src) && al(J.dst);
+    }
     by += (2.0 + J.accumulate) * n * J.nmat * J.ncl * sizeof(T);
     use.push_back(J);
   }

@@ -86,7 +86,8 @@ struct CJob {
   double alpha = 1.0;
   BOp src, dst;
   const void* scale = nullptr;
-  int smul = 1, soff = 0, sside = 0, pad = 0;
+  int smul = 1, soff = 0, sside = 0;
+  int vec = 0;   // set by the launcher: 16-byte accesses
   long long sstride = 0, scl = 0;
 };
 
