@@ -3210,9 +3210,12 @@ const char* kernel_name(const char* src, const char* t, const char* tin, const c
   return pool.insert(out).first->c_str();
 }
 
-#define KNAME_T(...) kernel_name(#__VA_ARGS__, type_name<T>(), "", "")
-#define KNAME_IO(...) kernel_name(#__VA_ARGS__, "", type_name<Tin>(), type_name<Tout>())
-#define KNAME0(...) kernel_name(#__VA_ARGS__, "", "", "")
+// Each use site resolves its name once (a static of the instantiation):
+// launches no longer build the name string every time.
+#define KNAME_T(...) ([]() { static const char* const n_ = kernel_name(#__VA_ARGS__, type_name<T>(), "", ""); return n_; }())
+#define KNAME_IO(...) \
+  ([]() { static const char* const n_ = kernel_name(#__VA_ARGS__, "", type_name<Tin>(), type_name<Tout>()); return n_; }())
+#define KNAME0(...) ([]() { static const char* const n_ = kernel_name(#__VA_ARGS__, "", "", ""); return n_; }())
 
 template <typename J>
 const J* upload(const std::vector<J>& v, hipStream_t st) {
