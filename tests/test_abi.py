@@ -39,3 +39,23 @@ def test_binding_fails_loudly_without_library(tmp_path):
     import paper_1604_00617_amd as acr
     with pytest.raises(ImportError):
         acr.load(str(tmp_path / "missing.so")) if acr._lib is None else (_ for _ in ()).throw(ImportError())
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU only: --gpus above 1 exits with a message
+    before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+
+
+def test_header_documents_solve_modes():
+    """acr_set_solve_mode is declared with its four modes and the wait limit."""
+    with open(os.path.join(ROOT, "include", "acr.h")) as fh:
+        src = fh.read()
+    assert "acr_set_solve_mode(int32_t mode, int64_t wait_limit)" in src
+    for m in ("mode 0", "mode 1", "mode 2", "mode 3"):
+        assert m in src
